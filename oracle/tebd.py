@@ -1,0 +1,256 @@
+"""MPS-TEBD of the vectorised density matrix |rho>> (oracle, FP64, CPU).
+
+State (Eq. mpo_def, App. A): rho is stored as an MPS with local dimension 4,
+site tensors A[k] of shape (chi_left, 4, chi_right); the local index is the
+computational (ket, bra) pair 2*ket + bra of the site.
+
+One Trotter step of size tau (second order):
+    layers  A(tau/2), B(tau), A(tau/2)
+    A = bonds (k, k+1) with k even, B = k odd (chain)
+    global layer l = 3*step + {0, 1, 2}; gates of layer l run in ascending k
+    when l is even, descending when l is odd.
+Per gate (bond k): bring the orthogonality centre onto (k, k+1); form the
+two-site block theta = G (A_k A_{k+1}) as a (4 chi_l) x (4 chi_r) matrix;
+full SVD (LAPACK); keep k' = min(chi_max, k_c) singular triplets, where k_c is
+the smallest k' >= 1 whose discarded squared weight sum_{j > k'} s_j^2 is at
+most cutoff * sum_j s_j^2 (App. B: the more severe of cut_off_rho and
+max_dim_rho).  An ascending gate leaves A_k = U, A_{k+1} = S V^+ (centre moves
+right), a descending one A_k = U S, A_{k+1} = V^+.  Singular values are not
+rescaled.  After each step, when trace forcing is on, rho -> rho / tr(rho)
+with the complex trace (App. B, b_force_rho_trace).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import model as lm
+
+# local covectors: Tr(O rho_site) = sum_{k,b} O[b, k] rho[k, b]
+def covector(O):
+    return np.asarray(O).T.reshape(4)
+
+
+E_ID = covector(lm.I2)
+
+
+def pauli_state_vector(label):
+    """vec of |psi><psi| for a Pauli eigenstate '+z', '-x', ... (Sec. 2.2)."""
+    if len(label) != 2 or label[0] not in "+-" or label[1] not in "xyzXYZ":
+        raise ValueError(f"bad Pauli state label {label!r}")
+    sign = 1.0 if label[0] == "+" else -1.0
+    op = lm.PAULI[label[1].upper()]
+    rho = 0.5 * (lm.I2 + sign * op)
+    return rho.reshape(4).astype(np.complex128)
+
+
+def init_labels(init, N):
+    if isinstance(init, str):
+        return [init] * N
+    init = list(init)
+    if len(init) != N:
+        raise ValueError("init must be one label or N labels")
+    return init
+
+
+def chain_layers(N):
+    A = list(range(0, N - 1, 2))
+    B = list(range(1, N - 1, 2))
+    return A, B
+
+
+def step_schedule(N, step):
+    """[(bond k, fraction of tau, ascending?)] for one chain step."""
+    A, B = chain_layers(N)
+    out = []
+    for j, (bonds, frac) in enumerate(((A, 0.5), (B, 1.0), (A, 0.5))):
+        layer = 3 * step + j
+        asc = layer % 2 == 0
+        for k in (bonds if asc else bonds[::-1]):
+            out.append((k, frac, asc))
+    return out
+
+
+def truncation_rank(s, chi_max, cutoff):
+    """k' = min(chi_max, k_c); s sorted descending (App. B).
+
+    Returns (k', discarded squared weight, total squared weight)."""
+    w = s.astype(np.float64) ** 2
+    W = float(np.sum(w))
+    r = len(s)
+    # tail[k] = sum_{j >= k} w_j  (weight discarded when k values are kept)
+    tail = np.zeros(r + 1)
+    tail[:r] = np.cumsum(w[::-1])[::-1]
+    kc = r
+    for k in range(1, r + 1):
+        if tail[k] <= cutoff * W:
+            kc = k
+            break
+    k = max(1, min(int(chi_max), kc))
+    return k, float(tail[k]), W
+
+
+class MPS:
+    def __init__(self, tensors, centre=0):
+        self.A = [np.array(t, dtype=np.complex128) for t in tensors]
+        self.centre = centre
+        self.discarded = 0.0  # cumulative relative discarded weight
+        self.last_spectra = {}
+
+    @property
+    def N(self):
+        return len(self.A)
+
+    @classmethod
+    def product(cls, init, N):
+        labels = init_labels(init, N)
+        return cls([pauli_state_vector(l).reshape(1, 4, 1) for l in labels], 0)
+
+    def bond_dims(self):
+        return [self.A[k].shape[2] for k in range(self.N - 1)]
+
+    # -- orthogonality centre (exact QR moves; the state is unchanged) --
+    def _shift_right(self, k):
+        a = self.A[k]
+        cl, _, cr = a.shape
+        q, r = np.linalg.qr(a.reshape(cl * 4, cr))
+        self.A[k] = q.reshape(cl, 4, q.shape[1])
+        self.A[k + 1] = np.tensordot(r, self.A[k + 1], axes=(1, 0))
+
+    def _shift_left(self, k):
+        a = self.A[k]
+        cl, _, cr = a.shape
+        q, r = np.linalg.qr(a.reshape(cl, 4 * cr).T)  # a = r^T q^T
+        self.A[k] = q.T.reshape(q.shape[1], 4, cr)
+        self.A[k - 1] = np.tensordot(self.A[k - 1], r.T, axes=(2, 0))
+
+    def move_centre(self, to):
+        while self.centre < to:
+            self._shift_right(self.centre)
+            self.centre += 1
+        while self.centre > to:
+            self._shift_left(self.centre)
+            self.centre -= 1
+
+    # -- two-site gate --
+    def two_site_block(self, k, G):
+        """theta[(l,s'),(t',r)] = sum_{s,t} G[(s't'),(st)] sum_m A_k[l,s,m] A_{k+1}[m,t,r]."""
+        M = np.einsum("lsm,mtr->lstr", self.A[k], self.A[k + 1])
+        th = np.einsum("abst,lstr->labr", G.reshape(4, 4, 4, 4), M)
+        cl, cr = self.A[k].shape[0], self.A[k + 1].shape[2]
+        return th.reshape(cl * 4, 4 * cr)
+
+    def apply_gate(self, k, G, chi_max, cutoff, ascending=True):
+        if self.centre <= k:
+            self.move_centre(k)
+        else:
+            self.move_centre(k + 1)
+        cl, cr = self.A[k].shape[0], self.A[k + 1].shape[2]
+        th = self.two_site_block(k, G)
+        u, s, vh = np.linalg.svd(th, full_matrices=False)
+        kk, disc, W = truncation_rank(s, chi_max, cutoff)
+        self.last_spectra[k] = s.copy()
+        if W > 0:
+            self.discarded += disc / W
+        u, s_k, vh = u[:, :kk], s[:kk], vh[:kk, :]
+        if ascending:
+            self.A[k] = u.reshape(cl, 4, kk)
+            self.A[k + 1] = (s_k[:, None] * vh).reshape(kk, 4, cr)
+            self.centre = k + 1
+        else:
+            self.A[k] = (u * s_k[None, :]).reshape(cl, 4, kk)
+            self.A[k + 1] = vh.reshape(kk, 4, cr)
+            self.centre = k
+        return kk, s
+
+    # -- contractions with product covectors --
+    def contract(self, covectors):
+        """sum over all indices of prod_k covectors[k] . A_k (a scalar)."""
+        v = np.ones(1, dtype=np.complex128)
+        for k, c in enumerate(covectors):
+            v = v @ np.tensordot(self.A[k], c, axes=(1, 0))
+        return complex(v[0])
+
+    def trace(self):
+        return self.contract([E_ID] * self.N)
+
+    def renormalize(self):
+        tr = self.trace()
+        self.A[self.centre] = self.A[self.centre] / tr
+        return tr
+
+    def expect(self, ops):
+        """<prod_i O_i> = Tr(rho prod_i O_i) / Tr(rho); ops = {site: 2x2}."""
+        cov = [covector(ops[k]) if k in ops else E_ID for k in range(self.N)]
+        return self.contract(cov) / self.trace()
+
+
+def gate_tables(model, tau):
+    """{(bond, fraction): G} for fractions 1/2 and 1 of tau."""
+    out = {}
+    for b in range(len(model["bonds"])):
+        for frac in (0.5, 1.0):
+            out[(b, frac)] = lm.bond_gate(model, b, frac * tau)
+    return out
+
+
+def check_chain(model):
+    bonds = np.asarray(model["bonds"])
+    N = model["N"]
+    if len(bonds) != N - 1 or np.any(bonds[:, 0] != np.arange(N - 1)) or np.any(bonds[:, 1] != np.arange(1, N)):
+        raise ValueError("chain schedule needs bonds (k, k+1), k = 0..N-2, in order")
+
+
+def evolve(mps, model, tau, steps, chi_max, cutoff, force_trace=True, gates=None,
+           observer=None, first_step=0):
+    """Run `steps` Trotter steps; observer(step_done, mps) after each step."""
+    check_chain(model)
+    if gates is None:
+        gates = gate_tables(model, tau)
+    for n in range(first_step, first_step + steps):
+        for k, frac, asc in step_schedule(mps.N, n):
+            mps.apply_gate(k, gates[(k, frac)], chi_max, cutoff, asc)
+        if force_trace:
+            mps.renormalize()
+        if observer is not None:
+            observer(n + 1, mps)
+    return mps
+
+
+def zz_observables(mps):
+    """<sz_i> for all i and <sz_i sz_j> for i < j (real parts, complex kept)."""
+    N = mps.N
+    z1 = np.array([mps.expect({i: lm.SZ}) for i in range(N)])
+    z2 = np.array([mps.expect({i: lm.SZ, j: lm.SZ}) for i in range(N) for j in range(i + 1, N)])
+    return z1, z2
+
+
+def connected(mps, i, j, a="Z", b="Z"):
+    """<s^a_i s^b_j> - <s^a_i><s^b_j> (the connected correlator)."""
+    Oa, Ob = lm.PAULI[a], lm.PAULI[b]
+    return mps.expect({i: Oa, j: Ob}) - mps.expect({i: Oa}) * mps.expect({j: Ob})
+
+
+# -- basis conversion to the normalised Pauli basis P_a = sigma^a / sqrt(2),
+#    a in (1, x, y, z) (Eq. mpo_def with orthonormal basis operators) --
+def pauli_basis_matrix():
+    """T[a, 2k+b] with c_a = Tr(P_a rho) = sum_{k,b} T[a, 2k+b] rho[k, b]."""
+    T = np.zeros((4, 4), dtype=np.complex128)
+    for a, key in enumerate("IXYZ"):
+        T[a] = covector(lm.PAULI[key] / np.sqrt(2.0))
+    return T
+
+
+def to_pauli(tensors):
+    T = pauli_basis_matrix()
+    return [np.einsum("as,lsr->lar", T, A) for A in tensors]
+
+
+def from_pauli(tensors):
+    Ti = np.linalg.inv(pauli_basis_matrix())
+    return [np.einsum("as,lsr->lar", Ti, A) for A in tensors]
+
+
+def gate_to_pauli(G):
+    T = pauli_basis_matrix()
+    TT = np.kron(T, T)
+    return TT @ G @ np.linalg.inv(TT)
