@@ -1,0 +1,162 @@
+/*
+ * lmpo.h -- C ABI of an MI355X (gfx950) library that evolves the vectorised
+ * density matrix |rho>> of N qubits, stored as a matrix product state with
+ * local dimension 4, under the Lindblad master equation of
+ *   H. Landa and G. Misguich, "Nonlocal correlations in noisy multiqubit
+ *   systems simulated using matrix product operators", arXiv:2203.05871:
+ *   Eq. (dtrho) with the Hamiltonian Eq. (H0), interactions Eq. (K_def) and
+ *   the dissipators Eqs. (D0), (D1), (D2); state format Eq. (mpo_def), App. A.
+ *
+ * One call of lmpo_evolve_step performs second-order Trotter steps made of
+ * two-site propagators exp(x L_b), each followed by a truncated SVD that keeps
+ * the more severe of a discarded-weight cutoff and a maximal bond dimension
+ * (App. B, parameters cut_off_rho / max_dim_rho of Sec. 6), with the trace
+ * forced to one after every step (b_force_rho_trace, Sec. 6).
+ *
+ * Conventions
+ *  - All functions return 0 (LMPO_OK) or a negative error code; a message is
+ *    then available from lmpo_last_error() (thread-local, valid until the
+ *    next call on the same thread).
+ *  - Host pointers are read during the call only; the library keeps copies.
+ *  - Device memory: the caller owns one device buffer (the "arena") of at
+ *    least lmpo_arena_bytes() bytes, 256-byte aligned, that must outlive the
+ *    state.  The library never allocates or frees device memory.
+ *  - Streams: every device operation of a state is enqueued on the
+ *    hipStream_t given at creation (NULL = the default stream).  Calls that
+ *    return host values (trace, measure, bond dims, weights, sync)
+ *    synchronise that stream.  A state must be used from one host thread at a
+ *    time; distinct states are independent.
+ *  - Storage in the arena: site k holds A_k[l][a][r] (row-major, complex
+ *    double interleaved re/im) in the normalised Pauli basis a = (1, x, y, z),
+ *    P_a = sigma^a / sqrt(2), i.e. rho = sum c_{a_1..a_N} P_{a_1} x ... x P_{a_N}
+ *    (Eq. mpo_def with orthonormal basis operators).
+ */
+#ifndef LMPO_H
+#define LMPO_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  LMPO_OK = 0,
+  LMPO_EINVAL = -1,       /* invalid argument (the paper's "exception if not passed", Sec. 6) */
+  LMPO_ENOMEM = -2,       /* arena too small */
+  LMPO_EHIP = -3,         /* HIP runtime error; the message carries its name */
+  LMPO_ENUMERIC = -4,     /* NaN/Inf in a singular value or observable, or tr(rho) = 0 */
+  LMPO_EUNSUPPORTED = -5  /* valid input this version does not handle */
+};
+
+enum { LMPO_FP64 = 0, LMPO_FP32_CONTRACT = 1 };
+
+/* Model parameters (Sec. 2.1).  bond_ij lists the coupled pairs (i, j), i < j;
+ * each bond contributes J (s+_i s-_j + s-_i s+_j) + (1/2) Jz s^z_i s^z_j
+ * (Eq. K_def read as one term per unordered pair).  Per-site arrays have
+ * length n_qubits: h_x, h_y, h_z of Eq. (H0) and the rates g0, g1, g2 of
+ * Eqs. (D0) (relaxation to s^z = +1), (D1) (to s^z = -1), (D2) (dephasing). */
+typedef struct {
+  int32_t n_qubits;
+  int32_t n_bonds;
+  const int32_t *bond_ij; /* [n_bonds][2] */
+  const double *J;        /* [n_bonds] */
+  const double *Jz;       /* [n_bonds] */
+  const double *hx, *hy, *hz;   /* [n_qubits] */
+  const double *g0, *g1, *g2;   /* [n_qubits], >= 0 */
+} lmpo_model;
+
+/* Numerical controls (Sec. 6, "Numerical simulation control"). */
+typedef struct {
+  double tau;            /* time step, > 0 */
+  int32_t trotter_order; /* 2 (orders 3, 4 of the paper: LMPO_EUNSUPPORTED) */
+  int32_t chi_max;       /* max_dim_rho, >= 1 */
+  double cutoff;         /* cut_off_rho: largest discarded squared Schmidt weight,
+                            relative to the block's total; >= 0 */
+  int32_t precision;     /* LMPO_FP64, or LMPO_FP32_CONTRACT: two-site contractions
+                            in FP32 (FP32 accumulation), SVD/truncation/trace FP64 */
+  int32_t force_trace;   /* 1: rho -> rho / tr(rho) after every step */
+} lmpo_options;
+
+typedef struct lmpo_state lmpo_state;
+
+/* Bytes of device memory a state of this model/options needs (0 on invalid
+ * input; lmpo_last_error() then says why). */
+size_t lmpo_arena_bytes(const lmpo_model *model, const lmpo_options *opt);
+
+/* Create a state in the Pauli product state init_pauli (Sec. 2.2): either one
+ * label such as "+z" for all qubits or n_qubits labels concatenated ("+z-x+y..."),
+ * sign then axis x|y|z.  Builds the gate table exp(x L_b), x in {tau/2, tau},
+ * on the host in FP64 and uploads it.  Requires a chain: bond b = (b, b+1) for
+ * b = 0..N-2 (other geometries: LMPO_EUNSUPPORTED).  hip_stream is a
+ * hipStream_t (NULL for the default stream). */
+int lmpo_create(const lmpo_model *model, const lmpo_options *opt, const char *init_pauli,
+                void *device_arena, size_t arena_bytes, void *hip_stream, lmpo_state **out);
+
+/* Enqueue n_steps >= 0 Trotter steps: layers A(tau/2) B(tau) A(tau/2) over even
+ * bonds (A) and odd bonds (B); each gate moves the orthogonality centre onto its
+ * bond (exact), applies exp(x L_b) to the two-site block, truncates by SVD and
+ * restores canonical form; then rho -> rho / tr(rho) if force_trace. */
+int lmpo_evolve_step(lmpo_state *s, int32_t n_steps);
+
+/* tr(rho) (Sec. 2.4) as (re, im); synchronises. */
+int lmpo_trace(lmpo_state *s, double out_re_im[2]);
+
+/* rho -> rho / tr(rho) (complex division); asynchronous. */
+int lmpo_renormalize(lmpo_state *s);
+
+/* <sigma^a_i> = Tr(rho sigma^a_i) / Tr(rho) (Eq. mu) for n requests:
+ * site[n], pauli[n] in 'X','Y','Z'; out[n][2] = (re, im).  Synchronises. */
+int lmpo_measure_1q(lmpo_state *s, int32_t n, const int32_t *site, const char *pauli, double *out);
+
+/* <sigma^a_i sigma^b_j> / Tr(rho) (Eq. 2Qdef), i != j, paulis[n][2] = (a, b)
+ * for (i[k], j[k]); out[n][2] = (re, im).  Synchronises. */
+int lmpo_measure_2q(lmpo_state *s, int32_t n, const int32_t *i, const int32_t *j,
+                    const char *paulis, double *out);
+
+/* Current bond dimensions chi_0..chi_{N-2}; synchronises. */
+int lmpo_bond_dims(lmpo_state *s, int32_t *out);
+
+/* Sum over all truncations so far of (discarded squared weight / total squared
+ * weight) of the two-site block; synchronises. */
+int lmpo_discarded_weight(lmpo_state *s, double *out);
+
+/* Wait for the state's queued work and report deferred numerical errors. */
+int lmpo_sync(lmpo_state *s);
+
+/* Release host-side resources (the arena stays the caller's). */
+int lmpo_destroy(lmpo_state *s);
+
+const char *lmpo_last_error(void);
+
+/* ---- inspection and kernel-level entry points (used by parity tests) ---- */
+
+/* Site tensor k in the Pauli basis: writes dims[0..1] = (chi_l, chi_r) and, if
+ * out is non-NULL, chi_l*4*chi_r complex values (interleaved, [l][a][r]).
+ * Synchronises.  lmpo_set_site replaces it (shapes must fit the capacity and
+ * match the neighbours' bonds); the caller states where the orthogonality
+ * centre is (the library assumes sites < centre left-orthonormal and
+ * > centre right-orthonormal). */
+int lmpo_get_site(lmpo_state *s, int32_t k, int32_t dims[2], double *out);
+int lmpo_set_site(lmpo_state *s, int32_t k, int32_t chi_l, int32_t chi_r, const double *data);
+int lmpo_set_centre(lmpo_state *s, int32_t centre);
+int lmpo_get_centre(lmpo_state *s, int32_t *centre);
+
+/* Gate table entry exp(x L_b) in the Pauli basis, x = tau/2 (half = 1) or tau
+ * (half = 0): 16x16 complex row-major over (a_i a_j) x (a_i' a_j'). */
+int lmpo_get_gate(lmpo_state *s, int32_t bond, int32_t half, double *out);
+
+/* One gate on bond k (k, k+1) with the chosen propagator, as inside a step:
+ * centre move, contraction, truncated SVD, canonical update (ascending: centre
+ * ends on k+1; descending: on k).  Asynchronous. */
+int lmpo_apply_gate(lmpo_state *s, int32_t k, int32_t half, int32_t ascending);
+
+/* Singular values of the last two-site block, sorted descending (n_out
+ * entries at most), and its kept rank; synchronises. */
+int lmpo_last_spectrum(lmpo_state *s, int32_t n_out, double *sv, int32_t *n_sv, int32_t *kept);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LMPO_H */

@@ -1,0 +1,639 @@
+// C ABI and step executor of the MPO-TEBD Lindblad step (include/lmpo.h).
+//
+// The executor walks the second-order Trotter schedule (layers A(tau/2),
+// B(tau), A(tau/2); A = even bonds, B = odd bonds; global layer l runs its
+// gates in ascending bond order when l is even, descending when odd) and, per
+// gate, launches: centre hops (exact SVD-based QR/LQ), the fused contraction +
+// gate kernel, the block-Jacobi SVD, truncation select and canonical update.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lmpo_internal.h"
+
+using namespace lmpo;
+
+namespace {
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(LMPO_EHIP, std::string(#expr " failed: ") + hipGetErrorString(e_));   \
+  } while (0)
+
+struct Arena {
+  char *base;
+  size_t size, used = 0;
+  template <typename T>
+  T *take(size_t n) {
+    size_t off = (used + 255) & ~size_t(255);
+    used = off + n * sizeof(T);
+    return reinterpret_cast<T *>(base + off);
+  }
+};
+
+constexpr int kMaxReq = 4096;
+constexpr int kMaxSweeps = 40;
+}  // namespace
+
+struct lmpo_state {
+  ModelHost m;
+  lmpo_options opt{};
+  hipStream_t stream = nullptr;
+  int N = 0;
+  std::vector<int> cap;                 // bond capacities
+  std::vector<double2 *> site;          // device site tensors
+  std::vector<size_t> site_elems;       // capacity in complex elements
+  std::vector<int> dims;                // host mirror of bond dims
+  int centre = 0;
+  int cap_max = 1;
+  // device
+  double2 **d_sites = nullptr;
+  int *d_dims = nullptr;
+  double2 *d_gates = nullptr;
+  double2 *X = nullptr, *V = nullptr, *W = nullptr, *Z = nullptr, *T = nullptr;
+  int *active = nullptr, *counter = nullptr, *perm = nullptr, *kept = nullptr, *err = nullptr, *req = nullptr;
+  double *sig = nullptr, *sorted = nullptr, *disc = nullptr;
+  double2 *tr = nullptr, *envL = nullptr, *envR = nullptr, *mout = nullptr;
+  int last_C = 0, last_kept = 0;
+  long long step_index = 0;  // global Trotter step count (fixes the layer order)
+  std::vector<std::complex<double>> gates_host;  // [nb][2][256]
+};
+
+namespace {
+
+struct Sizes {
+  std::vector<int> cap;
+  std::vector<size_t> site_elems;
+  size_t x_elems = 0, v_elems = 0, t_elems = 0, z_elems = 0;
+  int max_cols = 1, max_dim = 1, cap_max = 1;
+};
+
+int validate(const lmpo_model *m, const lmpo_options *o) {
+  if (!m || !o) return fail(LMPO_EINVAL, "null model or options");
+  if (m->n_qubits < 2) return fail(LMPO_EINVAL, "n_qubits must be >= 2");
+  if (m->n_bonds < 1 || !m->bond_ij) return fail(LMPO_EINVAL, "at least one bond is required");
+  if (!m->J || !m->Jz || !m->hx || !m->hy || !m->hz || !m->g0 || !m->g1 || !m->g2)
+    return fail(LMPO_EINVAL, "null parameter array");
+  for (int b = 0; b < m->n_bonds; ++b) {
+    int i = m->bond_ij[2 * b], j = m->bond_ij[2 * b + 1];
+    if (i < 0 || j <= i || j >= m->n_qubits) return fail(LMPO_EINVAL, "bond indices must satisfy 0 <= i < j < N");
+    if (!std::isfinite(m->J[b]) || !std::isfinite(m->Jz[b])) return fail(LMPO_EINVAL, "non-finite coupling");
+  }
+  for (int s = 0; s < m->n_qubits; ++s) {
+    double v[6] = {m->hx[s], m->hy[s], m->hz[s], m->g0[s], m->g1[s], m->g2[s]};
+    for (double x : v)
+      if (!std::isfinite(x)) return fail(LMPO_EINVAL, "non-finite on-site parameter");
+    if (m->g0[s] < 0 || m->g1[s] < 0 || m->g2[s] < 0) return fail(LMPO_EINVAL, "dissipation rates must be >= 0");
+  }
+  if (!(o->tau > 0) || !std::isfinite(o->tau)) return fail(LMPO_EINVAL, "tau must be > 0");
+  if (o->chi_max < 1) return fail(LMPO_EINVAL, "chi_max must be >= 1");
+  if (!(o->cutoff >= 0) || !std::isfinite(o->cutoff)) return fail(LMPO_EINVAL, "cutoff must be >= 0");
+  if (o->precision != LMPO_FP64 && o->precision != LMPO_FP32_CONTRACT)
+    return fail(LMPO_EINVAL, "precision must be LMPO_FP64 or LMPO_FP32_CONTRACT");
+  if (o->trotter_order != 2) return fail(LMPO_EUNSUPPORTED, "only trotter_order = 2 is implemented");
+  if (o->chi_max > kMaxDim / 4) return fail(LMPO_EUNSUPPORTED, "chi_max above 512 is not supported");
+  // chain geometry: bond b = (b, b+1)
+  if (m->n_bonds != m->n_qubits - 1) return fail(LMPO_EUNSUPPORTED, "only open chains (bonds (b, b+1)) are supported");
+  for (int b = 0; b < m->n_bonds; ++b)
+    if (m->bond_ij[2 * b] != b || m->bond_ij[2 * b + 1] != b + 1)
+      return fail(LMPO_EUNSUPPORTED, "only open chains (bonds (b, b+1), in order) are supported");
+  return LMPO_OK;
+}
+
+Sizes compute_sizes(int N, int chi_max) {
+  Sizes z;
+  z.cap.resize(N - 1);
+  for (int b = 0; b < N - 1; ++b) {
+    long long c = chi_max, p = 1;
+    for (int q = 0; q < b + 1 && p < c; ++q) p *= 4;
+    c = std::min(c, p);
+    p = 1;
+    for (int q = 0; q < N - 1 - b && p < c; ++q) p *= 4;
+    c = std::min(c, p);
+    z.cap[b] = (int)c;
+    z.cap_max = std::max(z.cap_max, (int)c);
+  }
+  auto capL = [&](int k) { return k == 0 ? 1 : z.cap[k - 1]; };
+  auto capR = [&](int k) { return k == N - 1 ? 1 : z.cap[k]; };
+  z.site_elems.resize(N);
+  for (int k = 0; k < N; ++k) {
+    z.site_elems[k] = (size_t)capL(k) * 4 * capR(k);
+    z.t_elems = std::max(z.t_elems, z.site_elems[k]);
+  }
+  auto consider = [&](size_t R, size_t C) {  // Jacobi on R x C, R >= C
+    z.x_elems = std::max(z.x_elems, R * C);
+    z.v_elems = std::max(z.v_elems, C * C);
+    z.max_cols = std::max(z.max_cols, (int)C);
+    z.max_dim = std::max(z.max_dim, (int)std::max(R, C));
+  };
+  for (int b = 0; b < N - 1; ++b) {
+    size_t R = 4 * (size_t)capL(b), C = 4 * (size_t)capR(b + 1);
+    consider(std::max(R, C), std::min(R, C));
+    // hops across bond b
+    consider(4 * (size_t)capL(b), z.cap[b]);
+    consider(4 * (size_t)capR(b + 1), z.cap[b]);
+    z.z_elems = std::max(z.z_elems, (size_t)z.cap[b] * z.cap[b]);
+  }
+  return z;
+}
+
+size_t layout(lmpo_state *S, const Sizes &z, int N, int nb, char *base, size_t size) {
+  Arena a{base, size};
+  S->site.resize(N);
+  for (int k = 0; k < N; ++k) S->site[k] = a.take<double2>(z.site_elems[k]);
+  S->d_sites = a.take<double2 *>(N);
+  S->d_dims = a.take<int>(std::max(N - 1, 1));
+  S->d_gates = a.take<double2>((size_t)nb * 2 * 256);
+  S->X = a.take<double2>(z.x_elems);
+  S->V = a.take<double2>(z.v_elems);
+  int nbp = (z.max_cols + JB - 1) / JB;
+  nbp += nbp & 1;
+  if (nbp < 2) nbp = 2;
+  S->W = a.take<double2>((size_t)(nbp / 2) * JP * JP);
+  S->active = a.take<int>(nbp / 2);
+  S->Z = a.take<double2>(z.z_elems);
+  S->T = a.take<double2>(z.t_elems);
+  S->sig = a.take<double>(z.max_cols);
+  S->sorted = a.take<double>(z.max_cols);
+  S->perm = a.take<int>(z.max_cols);
+  S->counter = a.take<int>(1);
+  S->kept = a.take<int>(1);
+  S->err = a.take<int>(1);
+  S->disc = a.take<double>(1);
+  S->tr = a.take<double2>(1);
+  S->envL = a.take<double2>((size_t)(N + 1) * z.cap_max);
+  S->envR = a.take<double2>((size_t)(N + 1) * z.cap_max);
+  S->req = a.take<int>(4 * kMaxReq);
+  S->mout = a.take<double2>(kMaxReq);
+  return a.used;
+}
+
+ModelHost copy_model(const lmpo_model *m) {
+  ModelHost h;
+  h.N = m->n_qubits;
+  h.nb = m->n_bonds;
+  h.bonds.assign(m->bond_ij, m->bond_ij + 2 * m->n_bonds);
+  h.J.assign(m->J, m->J + h.nb);
+  h.Jz.assign(m->Jz, m->Jz + h.nb);
+  h.hx.assign(m->hx, m->hx + h.N);
+  h.hy.assign(m->hy, m->hy + h.N);
+  h.hz.assign(m->hz, m->hz + h.N);
+  h.g0.assign(m->g0, m->g0 + h.N);
+  h.g1.assign(m->g1, m->g1 + h.N);
+  h.g2.assign(m->g2, m->g2 + h.N);
+  h.degree.assign(h.N, 0);
+  for (int b = 0; b < h.nb; ++b) {
+    h.degree[h.bonds[2 * b]]++;
+    h.degree[h.bonds[2 * b + 1]]++;
+  }
+  return h;
+}
+
+int parse_init(const char *init, int N, std::vector<std::pair<int, int>> &out) {
+  if (!init) return fail(LMPO_EINVAL, "init_pauli is null");
+  size_t len = std::strlen(init);
+  if (len != 2 && len != (size_t)2 * N) return fail(LMPO_EINVAL, "init_pauli must hold 1 or N two-character labels");
+  out.resize(N);
+  for (int i = 0; i < N; ++i) {
+    const char *p = (len == 2) ? init : init + 2 * i;
+    int sign = p[0] == '+' ? 1 : (p[0] == '-' ? -1 : 0);
+    int axis = (p[1] == 'x' || p[1] == 'X') ? 1 : (p[1] == 'y' || p[1] == 'Y') ? 2 : (p[1] == 'z' || p[1] == 'Z') ? 3 : 0;
+    if (!sign || !axis) return fail(LMPO_EINVAL, std::string("bad Pauli state label in init_pauli: ") + init);
+    out[i] = {sign, axis};
+  }
+  return LMPO_OK;
+}
+
+int dimL(const lmpo_state *S, int k) { return k == 0 ? 1 : S->dims[k - 1]; }
+int dimR(const lmpo_state *S, int k) { return k == S->N - 1 ? 1 : S->dims[k]; }
+
+int read_int(lmpo_state *S, const int *d, int *h) {
+  HIP_TRY(hipMemcpyAsync(h, d, sizeof(int), hipMemcpyDeviceToHost, S->stream));
+  HIP_TRY(hipStreamSynchronize(S->stream));
+  return LMPO_OK;
+}
+
+// Jacobi SVD of X (R x C, column-major, ld R), R >= C; V <- C x C.
+int svd_block(lmpo_state *S, int R, int C) {
+  launch_identity(S->stream, S->V, C, C);
+  int nbp = (C + JB - 1) / JB;
+  nbp += nbp & 1;
+  if (nbp < 2) nbp = 2;
+  const double tol = 8.0 * std::sqrt((double)R) * 2.220446049250313e-16;
+  for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
+    HIP_TRY(hipMemsetAsync(S->counter, 0, sizeof(int), S->stream));
+    for (int r = 0; r < nbp - 1; ++r)
+      launch_jacobi_round(S->stream, S->X, R, R, S->V, C, C, r, nbp, tol, S->W, S->active, S->counter);
+    int cnt = 0;
+    int rc = read_int(S, S->counter, &cnt);
+    if (rc) return rc;
+    if (cnt == 0) break;
+  }
+  launch_colnorm(S->stream, S->X, R, R, C, S->sig);
+  return LMPO_OK;
+}
+
+int hop_right(lmpo_state *S, int c) {
+  const int chl = dimL(S, c), chm = S->dims[c], chr2 = dimR(S, c + 1);
+  const int R = 4 * chl, C = chm;
+  if (R < C) return fail(LMPO_EUNSUPPORTED, "hop on a bond wider than its left block");
+  launch_hop_load(S->stream, S->site[c], R, C, S->X, 0);
+  int rc = svd_block(S, R, C);
+  if (rc) return rc;
+  launch_select(S->stream, S->sig, C, C, 0.0, 1, S->perm, S->sorted, S->kept, S->d_dims + c, S->disc, S->err);
+  int k = 0;
+  if ((rc = read_int(S, S->kept, &k))) return rc;
+  launch_hop_write(S->stream, S->X, R, S->V, C, S->perm, S->sorted, k, S->site[c], S->Z, R, C, 1);
+  launch_zgemm(S->stream, k, 4 * chr2, chm, S->Z, chm, S->site[c + 1], 4 * chr2, S->T, 4 * chr2);
+  HIP_TRY(hipMemcpyAsync(S->site[c + 1], S->T, (size_t)k * 4 * chr2 * sizeof(double2), hipMemcpyDeviceToDevice,
+                         S->stream));
+  S->dims[c] = k;
+  return LMPO_OK;
+}
+
+int hop_left(lmpo_state *S, int c) {
+  const int chm = S->dims[c - 1], chr = dimR(S, c), chl2 = dimL(S, c - 1);
+  const int R = 4 * chr, C = chm;
+  if (R < C) return fail(LMPO_EUNSUPPORTED, "hop on a bond wider than its right block");
+  launch_hop_load(S->stream, S->site[c], chm, 4 * chr, S->X, 1);
+  int rc = svd_block(S, R, C);
+  if (rc) return rc;
+  launch_select(S->stream, S->sig, C, C, 0.0, 1, S->perm, S->sorted, S->kept, S->d_dims + (c - 1), S->disc,
+                S->err);
+  int k = 0;
+  if ((rc = read_int(S, S->kept, &k))) return rc;
+  launch_hop_write(S->stream, S->X, R, S->V, C, S->perm, S->sorted, k, S->site[c], S->Z, R, C, 0);
+  launch_zgemm(S->stream, 4 * chl2, k, chm, S->site[c - 1], chm, S->Z, k, S->T, k);
+  HIP_TRY(hipMemcpyAsync(S->site[c - 1], S->T, (size_t)4 * chl2 * k * sizeof(double2), hipMemcpyDeviceToDevice,
+                         S->stream));
+  S->dims[c - 1] = k;
+  return LMPO_OK;
+}
+
+int move_centre(lmpo_state *S, int to) {
+  int rc;
+  while (S->centre < to) {
+    if ((rc = hop_right(S, S->centre))) return rc;
+    S->centre++;
+  }
+  while (S->centre > to) {
+    if ((rc = hop_left(S, S->centre))) return rc;
+    S->centre--;
+  }
+  return LMPO_OK;
+}
+
+int apply_gate(lmpo_state *S, int k, int half, int asc) {
+  int rc = move_centre(S, S->centre <= k ? k : k + 1);
+  if (rc) return rc;
+  const int chl = dimL(S, k), chm = S->dims[k], chr = dimR(S, k + 1);
+  const int R = 4 * chl, C = 4 * chr;
+  const int trans = R >= C ? 0 : 1;
+  const int RX = trans ? C : R, CX = trans ? R : C;
+  const double2 *G = S->d_gates + ((size_t)k * 2 + (half ? 1 : 0)) * 256;
+  launch_contract_gate(S->stream, S->opt.precision, S->site[k], S->site[k + 1], G, chl, chm, chr, S->X, trans);
+  if ((rc = svd_block(S, RX, CX))) return rc;
+  launch_select(S->stream, S->sig, CX, S->opt.chi_max, S->opt.cutoff, 0, S->perm, S->sorted, S->kept,
+                S->d_dims + k, S->disc, S->err);
+  const int kmax = std::min(S->opt.chi_max, CX);
+  launch_canon(S->stream, S->X, RX, S->V, CX, S->perm, S->sorted, S->kept, S->site[k], S->site[k + 1], chl, chr,
+               trans, asc, kmax);
+  int kk = 0;
+  if ((rc = read_int(S, S->kept, &kk))) return rc;
+  S->dims[k] = kk;
+  S->last_C = CX;
+  S->last_kept = kk;
+  S->centre = asc ? k + 1 : k;
+  return LMPO_OK;
+}
+
+int check_err(lmpo_state *S) {
+  int e = 0;
+  int rc = read_int(S, S->err, &e);
+  if (rc) return rc;
+  if (e) return fail(LMPO_ENUMERIC, "non-finite or zero singular values / trace encountered");
+  return LMPO_OK;
+}
+
+int renormalize(lmpo_state *S) {
+  launch_trace(S->stream, S->d_sites, S->d_dims, S->N, S->tr);
+  launch_scale_site(S->stream, S->d_sites, S->d_dims, S->N, S->centre, S->tr);
+  return LMPO_OK;
+}
+
+int one_step(lmpo_state *S, long long step) {
+  const int N = S->N;
+  const int layers[3][2] = {{0, 1}, {1, 0}, {0, 1}};  // (first bond parity, half?)
+  for (int j = 0; j < 3; ++j) {
+    const long long layer = 3 * step + j;
+    const bool asc = (layer % 2) == 0;
+    const int par = layers[j][0], half = layers[j][1];
+    std::vector<int> bonds;
+    for (int b = par; b < N - 1; b += 2) bonds.push_back(b);
+    if (!asc) std::reverse(bonds.begin(), bonds.end());
+    for (int b : bonds) {
+      int rc = apply_gate(S, b, half, asc ? 1 : 0);
+      if (rc) return rc;
+    }
+  }
+  if (S->opt.force_trace) return renormalize(S);
+  return LMPO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *lmpo_last_error(void) { return g_err.c_str(); }
+
+size_t lmpo_arena_bytes(const lmpo_model *model, const lmpo_options *opt) {
+  if (validate(model, opt) != LMPO_OK) return 0;
+  Sizes z = compute_sizes(model->n_qubits, opt->chi_max);
+  lmpo_state tmp;
+  return layout(&tmp, z, model->n_qubits, model->n_bonds, nullptr, 0) + 256;
+}
+
+int lmpo_create(const lmpo_model *model, const lmpo_options *opt, const char *init_pauli, void *device_arena,
+                size_t arena_bytes, void *hip_stream, lmpo_state **out) {
+  if (!out) return fail(LMPO_EINVAL, "out is null");
+  *out = nullptr;
+  int rc = validate(model, opt);
+  if (rc) return rc;
+  std::vector<std::pair<int, int>> init;
+  if ((rc = parse_init(init_pauli, model->n_qubits, init))) return rc;
+  if (!device_arena) return fail(LMPO_EINVAL, "device_arena is null");
+  if (reinterpret_cast<uintptr_t>(device_arena) % 256) return fail(LMPO_EINVAL, "device_arena must be 256-byte aligned");
+  Sizes z = compute_sizes(model->n_qubits, opt->chi_max);
+  if (z.max_dim > kMaxDim) return fail(LMPO_EUNSUPPORTED, "block dimension above 2048");
+  lmpo_state *S = new lmpo_state();
+  S->m = copy_model(model);
+  S->opt = *opt;
+  S->N = model->n_qubits;
+  S->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  size_t need = layout(S, z, S->N, S->m.nb, reinterpret_cast<char *>(device_arena), arena_bytes);
+  if (need > arena_bytes) {
+    delete S;
+    return fail(LMPO_ENOMEM, "arena too small: need " + std::to_string(need) + " bytes");
+  }
+  S->cap = z.cap;
+  S->site_elems = z.site_elems;
+  S->cap_max = z.cap_max;
+  S->dims.assign(S->N - 1, 1);
+  S->centre = 0;
+  // gate table: exp(x L_b), x in {tau, tau/2}, index [b][half]
+  const int nb = S->m.nb;
+  S->gates_host.assign((size_t)nb * 2 * 256, 0.0);
+  std::vector<std::complex<double>> L(256), A(256);
+  for (int b = 0; b < nb; ++b) {
+    bond_generator_pauli(S->m, b, L.data());
+    for (int half = 0; half < 2; ++half) {
+      double x = half ? 0.5 * opt->tau : opt->tau;
+      for (int e = 0; e < 256; ++e) A[e] = x * L[e];
+      if (!expm_pade13(16, A.data(), &S->gates_host[((size_t)b * 2 + half) * 256])) {
+        delete S;
+        return fail(LMPO_ENUMERIC, "matrix exponential failed");
+      }
+    }
+  }
+  auto cleanup = [&](int code) {
+    delete S;
+    return code;
+  };
+  hipError_t e;
+  e = hipMemcpyAsync(S->d_gates, S->gates_host.data(), S->gates_host.size() * sizeof(double2), hipMemcpyHostToDevice,
+                     S->stream);
+  if (e != hipSuccess) return cleanup(fail(LMPO_EHIP, std::string("gate upload: ") + hipGetErrorString(e)));
+  e = hipMemcpyAsync(S->d_sites, S->site.data(), S->N * sizeof(double2 *), hipMemcpyHostToDevice, S->stream);
+  if (e != hipSuccess) return cleanup(fail(LMPO_EHIP, std::string("site table upload: ") + hipGetErrorString(e)));
+  std::vector<int> ones(std::max(S->N - 1, 1), 1);
+  e = hipMemcpyAsync(S->d_dims, ones.data(), ones.size() * sizeof(int), hipMemcpyHostToDevice, S->stream);
+  if (e != hipSuccess) return cleanup(fail(LMPO_EHIP, std::string("dims upload: ") + hipGetErrorString(e)));
+  // product state: per site (1, 0, 0, 0) / sqrt(2) with +-1/sqrt(2) on the axis
+  const double r2 = 1.0 / std::sqrt(2.0);
+  std::vector<double2> sitev(4 * S->N);
+  for (int i = 0; i < S->N; ++i) {
+    for (int a = 0; a < 4; ++a) sitev[4 * i + a] = make_double2(0, 0);
+    sitev[4 * i] = make_double2(r2, 0);
+    sitev[4 * i + init[i].second] = make_double2(init[i].first * r2, 0);
+  }
+  for (int i = 0; i < S->N; ++i) {
+    e = hipMemcpyAsync(S->site[i], &sitev[4 * i], 4 * sizeof(double2), hipMemcpyHostToDevice, S->stream);
+    if (e != hipSuccess) return cleanup(fail(LMPO_EHIP, std::string("site upload: ") + hipGetErrorString(e)));
+  }
+  int zero = 0;
+  double zd = 0.0;
+  e = hipMemcpyAsync(S->err, &zero, sizeof(int), hipMemcpyHostToDevice, S->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(S->disc, &zd, sizeof(double), hipMemcpyHostToDevice, S->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(S->stream);
+  if (e != hipSuccess) return cleanup(fail(LMPO_EHIP, std::string("init: ") + hipGetErrorString(e)));
+  *out = S;
+  return LMPO_OK;
+}
+
+int lmpo_evolve_step(lmpo_state *S, int32_t n_steps) {
+  if (!S) return fail(LMPO_EINVAL, "state is null");
+  if (n_steps < 0) return fail(LMPO_EINVAL, "n_steps must be >= 0");
+  for (int n = 0; n < n_steps; ++n) {
+    int rc = one_step(S, S->step_index);
+    if (rc) return rc;
+    S->step_index++;
+  }
+  return LMPO_OK;
+}
+
+int lmpo_sync(lmpo_state *S) {
+  if (!S) return fail(LMPO_EINVAL, "state is null");
+  HIP_TRY(hipStreamSynchronize(S->stream));
+  return check_err(S);
+}
+
+int lmpo_trace(lmpo_state *S, double out[2]) {
+  if (!S || !out) return fail(LMPO_EINVAL, "null argument");
+  launch_trace(S->stream, S->d_sites, S->d_dims, S->N, S->tr);
+  double2 t;
+  HIP_TRY(hipMemcpyAsync(&t, S->tr, sizeof(double2), hipMemcpyDeviceToHost, S->stream));
+  HIP_TRY(hipStreamSynchronize(S->stream));
+  out[0] = t.x;
+  out[1] = t.y;
+  int rc = check_err(S);
+  if (rc) return rc;
+  if (!std::isfinite(t.x) || !std::isfinite(t.y)) return fail(LMPO_ENUMERIC, "non-finite trace");
+  return LMPO_OK;
+}
+
+int lmpo_renormalize(lmpo_state *S) {
+  if (!S) return fail(LMPO_EINVAL, "state is null");
+  return renormalize(S);
+}
+
+namespace {
+int pauli_index(char c) {
+  switch (c) {
+    case 'X': case 'x': return 1;
+    case 'Y': case 'y': return 2;
+    case 'Z': case 'z': return 3;
+    case 'I': case 'i': return 0;
+  }
+  return -1;
+}
+
+// req rows (i, a, j, b); j < 0 for 1Q.  out[n][2] = numerator / trace.
+int run_measure(lmpo_state *S, const std::vector<int> &req, double *out) {
+  const int n = (int)req.size() / 4;
+  launch_env_all(S->stream, S->d_sites, S->d_dims, S->N, S->cap_max, S->envL, S->envR);
+  launch_trace(S->stream, S->d_sites, S->d_dims, S->N, S->tr);
+  double2 tr;
+  HIP_TRY(hipMemcpyAsync(&tr, S->tr, sizeof(double2), hipMemcpyDeviceToHost, S->stream));
+  std::vector<double2> buf(kMaxReq);
+  for (int q0 = 0; q0 < n; q0 += kMaxReq) {
+    const int m = std::min(kMaxReq, n - q0);
+    HIP_TRY(hipMemcpyAsync(S->req, req.data() + 4 * (size_t)q0, 4 * (size_t)m * sizeof(int), hipMemcpyHostToDevice,
+                           S->stream));
+    launch_measure(S->stream, S->d_sites, S->d_dims, S->N, S->cap_max, S->envL, S->envR, m, S->req, S->mout);
+    HIP_TRY(hipMemcpyAsync(buf.data(), S->mout, (size_t)m * sizeof(double2), hipMemcpyDeviceToHost, S->stream));
+    HIP_TRY(hipStreamSynchronize(S->stream));
+    const double d = tr.x * tr.x + tr.y * tr.y;
+    if (!(d > 0) || !std::isfinite(d)) return fail(LMPO_ENUMERIC, "trace is zero or non-finite");
+    for (int q = 0; q < m; ++q) {
+      double2 v = buf[q];
+      out[2 * (q0 + q)] = (v.x * tr.x + v.y * tr.y) / d;
+      out[2 * (q0 + q) + 1] = (v.y * tr.x - v.x * tr.y) / d;
+    }
+  }
+  return check_err(S);
+}
+}  // namespace
+
+int lmpo_measure_1q(lmpo_state *S, int32_t n, const int32_t *site, const char *pauli, double *out) {
+  if (!S || n < 0 || (n > 0 && (!site || !pauli || !out))) return fail(LMPO_EINVAL, "null argument or n < 0");
+  std::vector<int> req;
+  for (int q = 0; q < n; ++q) {
+    int a = pauli_index(pauli[q]);
+    if (site[q] < 0 || site[q] >= S->N) return fail(LMPO_EINVAL, "site index out of range");
+    if (a <= 0) return fail(LMPO_EINVAL, "pauli must be one of X, Y, Z");
+    req.insert(req.end(), {site[q], a, -1, 0});
+  }
+  if (n == 0) return LMPO_OK;
+  return run_measure(S, req, out);
+}
+
+int lmpo_measure_2q(lmpo_state *S, int32_t n, const int32_t *i, const int32_t *j, const char *paulis, double *out) {
+  if (!S || n < 0 || (n > 0 && (!i || !j || !paulis || !out))) return fail(LMPO_EINVAL, "null argument or n < 0");
+  std::vector<int> req;
+  for (int q = 0; q < n; ++q) {
+    int a = pauli_index(paulis[2 * q]), b = pauli_index(paulis[2 * q + 1]);
+    int ii = i[q], jj = j[q];
+    if (ii < 0 || ii >= S->N || jj < 0 || jj >= S->N) return fail(LMPO_EINVAL, "site index out of range");
+    if (ii == jj) return fail(LMPO_EINVAL, "2Q observable needs i != j");
+    if (a <= 0 || b <= 0) return fail(LMPO_EINVAL, "paulis must be X, Y or Z");
+    if (ii > jj) {
+      std::swap(ii, jj);
+      std::swap(a, b);
+    }
+    req.insert(req.end(), {ii, a, jj, b});
+  }
+  if (n == 0) return LMPO_OK;
+  return run_measure(S, req, out);
+}
+
+int lmpo_bond_dims(lmpo_state *S, int32_t *out) {
+  if (!S || !out) return fail(LMPO_EINVAL, "null argument");
+  HIP_TRY(hipMemcpyAsync(out, S->d_dims, (S->N - 1) * sizeof(int), hipMemcpyDeviceToHost, S->stream));
+  HIP_TRY(hipStreamSynchronize(S->stream));
+  return check_err(S);
+}
+
+int lmpo_discarded_weight(lmpo_state *S, double *out) {
+  if (!S || !out) return fail(LMPO_EINVAL, "null argument");
+  HIP_TRY(hipMemcpyAsync(out, S->disc, sizeof(double), hipMemcpyDeviceToHost, S->stream));
+  HIP_TRY(hipStreamSynchronize(S->stream));
+  return check_err(S);
+}
+
+int lmpo_destroy(lmpo_state *S) {
+  if (!S) return LMPO_OK;
+  hipError_t e = hipStreamSynchronize(S->stream);
+  delete S;
+  if (e != hipSuccess) return fail(LMPO_EHIP, std::string("destroy: ") + hipGetErrorString(e));
+  return LMPO_OK;
+}
+
+int lmpo_get_site(lmpo_state *S, int32_t k, int32_t dims[2], double *out) {
+  if (!S || !dims) return fail(LMPO_EINVAL, "null argument");
+  if (k < 0 || k >= S->N) return fail(LMPO_EINVAL, "site index out of range");
+  HIP_TRY(hipStreamSynchronize(S->stream));
+  dims[0] = dimL(S, k);
+  dims[1] = dimR(S, k);
+  if (out)
+    HIP_TRY(hipMemcpyAsync(out, S->site[k], (size_t)dims[0] * 4 * dims[1] * sizeof(double2), hipMemcpyDeviceToHost,
+                           S->stream));
+  HIP_TRY(hipStreamSynchronize(S->stream));
+  return LMPO_OK;
+}
+
+int lmpo_set_site(lmpo_state *S, int32_t k, int32_t chl, int32_t chr, const double *data) {
+  if (!S || !data) return fail(LMPO_EINVAL, "null argument");
+  if (k < 0 || k >= S->N) return fail(LMPO_EINVAL, "site index out of range");
+  const int capl = k == 0 ? 1 : S->cap[k - 1], capr = k == S->N - 1 ? 1 : S->cap[k];
+  if (chl < 1 || chr < 1 || chl > capl || chr > capr) return fail(LMPO_EINVAL, "site shape exceeds the bond capacity");
+  if (k > 0) S->dims[k - 1] = chl;
+  if (k < S->N - 1) S->dims[k] = chr;
+  HIP_TRY(hipMemcpyAsync(S->site[k], data, (size_t)chl * 4 * chr * sizeof(double2), hipMemcpyHostToDevice, S->stream));
+  HIP_TRY(hipMemcpyAsync(S->d_dims, S->dims.data(), (S->N - 1) * sizeof(int), hipMemcpyHostToDevice, S->stream));
+  HIP_TRY(hipStreamSynchronize(S->stream));
+  return LMPO_OK;
+}
+
+int lmpo_set_centre(lmpo_state *S, int32_t c) {
+  if (!S) return fail(LMPO_EINVAL, "state is null");
+  if (c < 0 || c >= S->N) return fail(LMPO_EINVAL, "centre out of range");
+  S->centre = c;
+  return LMPO_OK;
+}
+
+int lmpo_get_centre(lmpo_state *S, int32_t *c) {
+  if (!S || !c) return fail(LMPO_EINVAL, "null argument");
+  *c = S->centre;
+  return LMPO_OK;
+}
+
+int lmpo_get_gate(lmpo_state *S, int32_t bond, int32_t half, double *out) {
+  if (!S || !out) return fail(LMPO_EINVAL, "null argument");
+  if (bond < 0 || bond >= S->m.nb) return fail(LMPO_EINVAL, "bond out of range");
+  std::memcpy(out, &S->gates_host[((size_t)bond * 2 + (half ? 1 : 0)) * 256], 256 * sizeof(double2));
+  return LMPO_OK;
+}
+
+int lmpo_apply_gate(lmpo_state *S, int32_t k, int32_t half, int32_t ascending) {
+  if (!S) return fail(LMPO_EINVAL, "state is null");
+  if (k < 0 || k >= S->N - 1) return fail(LMPO_EINVAL, "bond out of range");
+  return apply_gate(S, k, half, ascending);
+}
+
+int lmpo_last_spectrum(lmpo_state *S, int32_t n_out, double *sv, int32_t *n_sv, int32_t *kept) {
+  if (!S || !n_sv || !kept) return fail(LMPO_EINVAL, "null argument");
+  HIP_TRY(hipStreamSynchronize(S->stream));
+  *n_sv = S->last_C;
+  *kept = S->last_kept;
+  int n = std::min<int>(n_out, S->last_C);
+  if (sv && n > 0) {
+    HIP_TRY(hipMemcpyAsync(sv, S->sorted, n * sizeof(double), hipMemcpyDeviceToHost, S->stream));
+    HIP_TRY(hipStreamSynchronize(S->stream));
+  }
+  return LMPO_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,282 @@
+"""Thin Python binding of the lmpo C ABI (include/lmpo.h).
+
+Argument marshalling only: every step of the evolution runs in the HIP
+library.  PyTorch supplies the device arena (a uint8 tensor on the GPU) and
+the stream; the library never allocates device memory.  If the compiled
+library is missing, importing this module raises: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liblmpo.so")
+
+LMPO_FP64 = 0
+LMPO_FP32_CONTRACT = 1
+
+_ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENUMERIC", -5: "EUNSUPPORTED"}
+
+
+class LmpoError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"lmpo error {code} ({_ERRORS.get(code, '?')}): {msg}")
+        self.code = code
+
+
+class _Model(ctypes.Structure):
+    _fields_ = [
+        ("n_qubits", ctypes.c_int32),
+        ("n_bonds", ctypes.c_int32),
+        ("bond_ij", ctypes.POINTER(ctypes.c_int32)),
+        ("J", ctypes.POINTER(ctypes.c_double)),
+        ("Jz", ctypes.POINTER(ctypes.c_double)),
+        ("hx", ctypes.POINTER(ctypes.c_double)),
+        ("hy", ctypes.POINTER(ctypes.c_double)),
+        ("hz", ctypes.POINTER(ctypes.c_double)),
+        ("g0", ctypes.POINTER(ctypes.c_double)),
+        ("g1", ctypes.POINTER(ctypes.c_double)),
+        ("g2", ctypes.POINTER(ctypes.c_double)),
+    ]
+
+
+class _Options(ctypes.Structure):
+    _fields_ = [
+        ("tau", ctypes.c_double),
+        ("trotter_order", ctypes.c_int32),
+        ("chi_max", ctypes.c_int32),
+        ("cutoff", ctypes.c_double),
+        ("precision", ctypes.c_int32),
+        ("force_trace", ctypes.c_int32),
+    ]
+
+
+_lib = None
+
+EXPORTS = [
+    "lmpo_arena_bytes", "lmpo_create", "lmpo_evolve_step", "lmpo_trace", "lmpo_renormalize",
+    "lmpo_measure_1q", "lmpo_measure_2q", "lmpo_bond_dims", "lmpo_discarded_weight", "lmpo_sync",
+    "lmpo_destroy", "lmpo_last_error", "lmpo_get_site", "lmpo_set_site", "lmpo_set_centre",
+    "lmpo_get_centre", "lmpo_get_gate", "lmpo_apply_gate", "lmpo_last_spectrum",
+]
+
+
+def load_library(path: str = LIB_PATH):
+    """Load the compiled library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"HIP library {path} is missing: build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    P = ctypes.c_void_p
+    i32, dbl = ctypes.c_int32, ctypes.c_double
+    pi32 = ctypes.POINTER(ctypes.c_int32)
+    pdbl = ctypes.POINTER(ctypes.c_double)
+    sig = {
+        "lmpo_arena_bytes": (ctypes.c_size_t, [ctypes.POINTER(_Model), ctypes.POINTER(_Options)]),
+        "lmpo_create": (ctypes.c_int, [ctypes.POINTER(_Model), ctypes.POINTER(_Options), ctypes.c_char_p, P,
+                                       ctypes.c_size_t, P, ctypes.POINTER(P)]),
+        "lmpo_evolve_step": (ctypes.c_int, [P, i32]),
+        "lmpo_trace": (ctypes.c_int, [P, pdbl]),
+        "lmpo_renormalize": (ctypes.c_int, [P]),
+        "lmpo_measure_1q": (ctypes.c_int, [P, i32, pi32, ctypes.c_char_p, pdbl]),
+        "lmpo_measure_2q": (ctypes.c_int, [P, i32, pi32, pi32, ctypes.c_char_p, pdbl]),
+        "lmpo_bond_dims": (ctypes.c_int, [P, pi32]),
+        "lmpo_discarded_weight": (ctypes.c_int, [P, pdbl]),
+        "lmpo_sync": (ctypes.c_int, [P]),
+        "lmpo_destroy": (ctypes.c_int, [P]),
+        "lmpo_last_error": (ctypes.c_char_p, []),
+        "lmpo_get_site": (ctypes.c_int, [P, i32, pi32, pdbl]),
+        "lmpo_set_site": (ctypes.c_int, [P, i32, i32, i32, pdbl]),
+        "lmpo_set_centre": (ctypes.c_int, [P, i32]),
+        "lmpo_get_centre": (ctypes.c_int, [P, pi32]),
+        "lmpo_get_gate": (ctypes.c_int, [P, i32, i32, pdbl]),
+        "lmpo_apply_gate": (ctypes.c_int, [P, i32, i32, i32]),
+        "lmpo_last_spectrum": (ctypes.c_int, [P, i32, pdbl, pi32, pi32]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise LmpoError(rc, _lib.lmpo_last_error().decode())
+
+
+def _dptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _iptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+
+
+class _ModelArrays:
+    """Keeps the contiguous host arrays alive while the C struct points at them."""
+
+    def __init__(self, model):
+        N = int(model["N"])
+        self.bonds = np.ascontiguousarray(np.asarray(model["bonds"], dtype=np.int32).reshape(-1, 2))
+        nb = len(self.bonds)
+        f = lambda k, n: np.ascontiguousarray(np.broadcast_to(np.asarray(model.get(k, 0.0), dtype=np.float64), (n,)))
+        self.arrs = {k: f(k, nb) for k in ("J", "Jz")}
+        self.arrs.update({k: f(k, N) for k in ("hx", "hy", "hz", "g0", "g1", "g2")})
+        self.struct = _Model(N, nb, _iptr(self.bonds), *[_dptr(self.arrs[k]) for k in
+                                                          ("J", "Jz", "hx", "hy", "hz", "g0", "g1", "g2")])
+
+
+def _options(tau, chi_max, cutoff, precision, force_trace, order=2):
+    prec = {"fp64": LMPO_FP64, "fp32": LMPO_FP32_CONTRACT}.get(precision, precision)
+    return _Options(float(tau), int(order), int(chi_max), float(cutoff), int(prec), int(bool(force_trace)))
+
+
+def arena_bytes(model, tau, chi_max, cutoff=0.0, precision="fp64", force_trace=True, order=2):
+    lib = load_library()
+    m = _ModelArrays(model)
+    o = _options(tau, chi_max, cutoff, precision, force_trace, order)
+    n = lib.lmpo_arena_bytes(ctypes.byref(m.struct), ctypes.byref(o))
+    if n == 0:
+        raise LmpoError(-1, lib.lmpo_last_error().decode())
+    return int(n)
+
+
+def _init_string(init, N):
+    if isinstance(init, str):
+        return init.encode()
+    labels = list(init)
+    if len(labels) != N:
+        raise ValueError("init must be one label or N labels")
+    return "".join(labels).encode()
+
+
+class Chain:
+    """One qubit chain's vectorised density matrix on the GPU."""
+
+    def __init__(self, model, tau, chi_max, cutoff=0.0, precision="fp64", init="+z", force_trace=True,
+                 order=2, device="cuda:0", stream=None):
+        import torch
+
+        lib = load_library()
+        self.N = int(model["N"])
+        self._m = _ModelArrays(model)
+        self._o = _options(tau, chi_max, cutoff, precision, force_trace, order)
+        n = lib.lmpo_arena_bytes(ctypes.byref(self._m.struct), ctypes.byref(self._o))
+        if n == 0:
+            raise LmpoError(-1, lib.lmpo_last_error().decode())
+        self.arena = torch.empty(n + 256, dtype=torch.uint8, device=device)
+        base = self.arena.data_ptr()
+        off = (-base) % 256
+        self._stream = stream if stream is not None else torch.cuda.current_stream(device)
+        h = ctypes.c_void_p()
+        _check(lib.lmpo_create(ctypes.byref(self._m.struct), ctypes.byref(self._o), _init_string(init, self.N),
+                               ctypes.c_void_p(base + off), ctypes.c_size_t(n), ctypes.c_void_p(self._stream.cuda_stream),
+                               ctypes.byref(h)))
+        self._h = h
+        self._lib = lib
+
+    # -- evolution --
+    def evolve(self, n_steps=1):
+        _check(self._lib.lmpo_evolve_step(self._h, int(n_steps)))
+
+    def renormalize(self):
+        _check(self._lib.lmpo_renormalize(self._h))
+
+    def sync(self):
+        _check(self._lib.lmpo_sync(self._h))
+
+    def apply_gate(self, k, half, ascending):
+        _check(self._lib.lmpo_apply_gate(self._h, int(k), int(bool(half)), int(bool(ascending))))
+
+    # -- readouts --
+    def trace(self):
+        out = np.zeros(2)
+        _check(self._lib.lmpo_trace(self._h, _dptr(out)))
+        return complex(out[0], out[1])
+
+    def measure_1q(self, sites, paulis):
+        sites = np.ascontiguousarray(sites, dtype=np.int32)
+        if isinstance(paulis, str) and len(paulis) == 1:
+            paulis = paulis * len(sites)
+        p = "".join(paulis).encode()
+        out = np.zeros((len(sites), 2))
+        _check(self._lib.lmpo_measure_1q(self._h, len(sites), _iptr(sites), p, _dptr(out)))
+        return out[:, 0] + 1j * out[:, 1]
+
+    def measure_2q(self, i, j, paulis):
+        i = np.ascontiguousarray(i, dtype=np.int32)
+        j = np.ascontiguousarray(j, dtype=np.int32)
+        if isinstance(paulis, str) and len(paulis) == 2:
+            paulis = [paulis] * len(i)
+        p = "".join(paulis).encode()
+        out = np.zeros((len(i), 2))
+        _check(self._lib.lmpo_measure_2q(self._h, len(i), _iptr(i), _iptr(j), p, _dptr(out)))
+        return out[:, 0] + 1j * out[:, 1]
+
+    def zz_observables(self):
+        """<sz_i> (all i) and <sz_i sz_j> (all i < j), as complex arrays."""
+        N = self.N
+        z1 = self.measure_1q(np.arange(N), "Z")
+        ii, jj = np.triu_indices(N, 1)
+        z2 = self.measure_2q(ii, jj, "ZZ")
+        return z1, z2
+
+    def bond_dims(self):
+        out = np.zeros(self.N - 1, dtype=np.int32)
+        _check(self._lib.lmpo_bond_dims(self._h, _iptr(out)))
+        return out.tolist()
+
+    def discarded_weight(self):
+        out = np.zeros(1)
+        _check(self._lib.lmpo_discarded_weight(self._h, _dptr(out)))
+        return float(out[0])
+
+    def get_site(self, k):
+        dims = np.zeros(2, dtype=np.int32)
+        _check(self._lib.lmpo_get_site(self._h, int(k), _iptr(dims), None))
+        buf = np.zeros(int(dims[0]) * 4 * int(dims[1]) * 2)
+        _check(self._lib.lmpo_get_site(self._h, int(k), _iptr(dims), _dptr(buf)))
+        return (buf[0::2] + 1j * buf[1::2]).reshape(int(dims[0]), 4, int(dims[1]))
+
+    def set_site(self, k, A):
+        A = np.asarray(A, dtype=np.complex128)
+        buf = np.ascontiguousarray(np.stack([A.real, A.imag], axis=-1).reshape(-1))
+        _check(self._lib.lmpo_set_site(self._h, int(k), A.shape[0], A.shape[2], _dptr(buf)))
+
+    def set_centre(self, c):
+        _check(self._lib.lmpo_set_centre(self._h, int(c)))
+
+    def centre(self):
+        out = np.zeros(1, dtype=np.int32)
+        _check(self._lib.lmpo_get_centre(self._h, _iptr(out)))
+        return int(out[0])
+
+    def gate(self, bond, half):
+        buf = np.zeros(512)
+        _check(self._lib.lmpo_get_gate(self._h, int(bond), int(bool(half)), _dptr(buf)))
+        return (buf[0::2] + 1j * buf[1::2]).reshape(16, 16)
+
+    def last_spectrum(self, n=4096):
+        sv = np.zeros(n)
+        nsv = np.zeros(1, dtype=np.int32)
+        kept = np.zeros(1, dtype=np.int32)
+        _check(self._lib.lmpo_last_spectrum(self._h, n, _dptr(sv), _iptr(nsv), _iptr(kept)))
+        return sv[: int(nsv[0])], int(kept[0])
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(self._lib.lmpo_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,56 @@
+"""CPU checks of the C ABI: the library loads and exports every declared symbol."""
+import ctypes
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_symbols():
+    text = open(os.path.join(ROOT, "include", "lmpo.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(lmpo_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_core_entry_points():
+    syms = declared_symbols()
+    for s in ("lmpo_create", "lmpo_evolve_step", "lmpo_trace", "lmpo_renormalize", "lmpo_measure_1q",
+              "lmpo_measure_2q", "lmpo_destroy", "lmpo_last_error"):
+        assert s in syms
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2203_05871_amd import lmpo
+
+    lib = ctypes.CDLL(lmpo.LIB_PATH)
+    missing = [s for s in declared_symbols() if not hasattr(lib, s)]
+    assert not missing, missing
+    assert sorted(lmpo.EXPORTS) == declared_symbols()
+
+
+def test_arena_size_and_argument_errors_on_host():
+    """lmpo_arena_bytes validates on the host without touching a GPU."""
+    import workloads
+    from paper_2203_05871_amd import lmpo
+
+    m, run = workloads.c3()
+    n = lmpo.arena_bytes(m, run["tau"], run["chi_max"], run["cutoff"])
+    # 30 sites at chi=256 dominate: at least 28 * 256*4*256 complex doubles
+    assert n > 28 * 256 * 4 * 256 * 16
+    assert n < 2 << 30
+    import pytest
+    with pytest.raises(lmpo.LmpoError, match="tau"):
+        lmpo.arena_bytes(m, -1.0, 16)
+    with pytest.raises(lmpo.LmpoError, match="chi_max"):
+        lmpo.arena_bytes(m, 0.1, 0)
+    with pytest.raises(lmpo.LmpoError, match="cutoff"):
+        lmpo.arena_bytes(m, 0.1, 8, cutoff=-1)
+    with pytest.raises(lmpo.LmpoError, match="trotter_order"):
+        lmpo.arena_bytes(m, 0.1, 8, order=4)
+    bad = dict(m)
+    bad["g0"] = -m["g0"]
+    with pytest.raises(lmpo.LmpoError, match="rates"):
+        lmpo.arena_bytes(bad, 0.1, 8)
+    lad = workloads.ladder_model(3)
+    with pytest.raises(lmpo.LmpoError, match="chains"):
+        lmpo.arena_bytes(lad, 0.1, 8)
