@@ -45,7 +45,8 @@ struct Arena {
 };
 
 constexpr int kMaxReq = 4096;
-constexpr int kMaxSweeps = 40;
+constexpr int kMaxSweeps = 80;
+constexpr int kStats = 8;  // [last sweeps, last C, last R, -, total sweeps, total SVDs, -, -]
 }  // namespace
 
 struct lmpo_state {
@@ -64,10 +65,20 @@ struct lmpo_state {
   int *d_dims = nullptr;
   double2 *d_gates = nullptr;
   double2 *X = nullptr, *V = nullptr, *W = nullptr, *Z = nullptr, *T = nullptr;
-  int *active = nullptr, *counter = nullptr, *perm = nullptr, *kept = nullptr, *err = nullptr, *req = nullptr;
+  int *act = nullptr;
+  int *sweep_cnt = nullptr, *stats = nullptr, *perm = nullptr, *kept = nullptr, *err = nullptr, *req = nullptr;
+  unsigned *bar = nullptr;
+  unsigned long long *tprof = nullptr;
+  int grid = 1;                 // largest co-resident grid of the persistent SVD
+  int *dims_pinned = nullptr;   // asynchronous copy of the bond dims (grid sizing only)
+  hipEvent_t dims_ready = nullptr;
+  std::vector<int> dims_est;    // bond dims as of the last completed step
+  ~lmpo_state() {
+    if (dims_ready) (void)hipEventDestroy(dims_ready);
+    if (dims_pinned) (void)hipHostFree(dims_pinned);
+  }
   double *sig = nullptr, *sorted = nullptr, *disc = nullptr;
   double2 *tr = nullptr, *envL = nullptr, *envR = nullptr, *mout = nullptr;
-  int last_C = 0, last_kept = 0;
   long long step_index = 0;  // global Trotter step count (fixes the layer order)
   std::vector<std::complex<double>> gates_host;  // [nb][2][256]
 };
@@ -162,14 +173,19 @@ size_t layout(lmpo_state *S, const Sizes &z, int N, int nb, char *base, size_t s
   int nbp = (z.max_cols + JB - 1) / JB;
   nbp += nbp & 1;
   if (nbp < 2) nbp = 2;
-  S->W = a.take<double2>((size_t)(nbp / 2) * JP * JP);
-  S->active = a.take<int>(nbp / 2);
+  // rotations of two consecutive sweeps: [2][rounds][pairs][JP][JP]
+  const size_t slots = (size_t)(nbp - 1) * (nbp / 2);
+  S->W = a.take<double2>(2 * slots * JP * JP);
+  S->act = a.take<int>(2 * slots);
   S->Z = a.take<double2>(z.z_elems);
   S->T = a.take<double2>(z.t_elems);
   S->sig = a.take<double>(z.max_cols);
   S->sorted = a.take<double>(z.max_cols);
   S->perm = a.take<int>(z.max_cols);
-  S->counter = a.take<int>(1);
+  S->sweep_cnt = a.take<int>(kMaxSweeps);
+  S->stats = a.take<int>(kStats);
+  S->bar = a.take<unsigned>(8 * 32 + 64);
+  S->tprof = a.take<unsigned long long>(16);
   S->kept = a.take<int>(1);
   S->err = a.take<int>(1);
   S->disc = a.take<double>(1);
@@ -219,6 +235,8 @@ int parse_init(const char *init, int N, std::vector<std::pair<int, int>> &out) {
 
 int dimL(const lmpo_state *S, int k) { return k == 0 ? 1 : S->dims[k - 1]; }
 int dimR(const lmpo_state *S, int k) { return k == S->N - 1 ? 1 : S->dims[k]; }
+int capL(const lmpo_state *S, int k) { return k == 0 ? 1 : S->cap[k - 1]; }
+int capR(const lmpo_state *S, int k) { return k == S->N - 1 ? 1 : S->cap[k]; }
 
 int read_int(lmpo_state *S, const int *d, int *h) {
   HIP_TRY(hipMemcpyAsync(h, d, sizeof(int), hipMemcpyDeviceToHost, S->stream));
@@ -226,71 +244,86 @@ int read_int(lmpo_state *S, const int *d, int *h) {
   return LMPO_OK;
 }
 
-// Jacobi SVD of X (R x C, column-major, ld R), R >= C; V <- C x C.
-int svd_block(lmpo_state *S, int R, int C) {
-  launch_identity(S->stream, S->V, C, C);
+int sync_dims(lmpo_state *S) {
+  HIP_TRY(hipMemcpyAsync(S->dims.data(), S->d_dims, (S->N - 1) * sizeof(int), hipMemcpyDeviceToHost, S->stream));
+  HIP_TRY(hipStreamSynchronize(S->stream));
+  return LMPO_OK;
+}
+
+SvdLaunch svd_args(lmpo_state *S, int mode, int k, int asc) {
+  SvdLaunch L;
+  L.mode = mode;
+  L.k = k;
+  L.N = S->N;
+  L.asc = asc;
+  L.chi_max = S->opt.chi_max;
+  L.max_sweeps = kMaxSweeps;
+  L.cutoff = S->opt.cutoff;
+  L.tol_factor = 32.0;
+  L.sites = S->d_sites;
+  L.dims = S->d_dims;
+  L.X = S->X;
+  L.V = S->V;
+  L.W = S->W;
+  L.act = S->act;
+  L.Z = S->Z;
+  L.T = S->T;
+  L.sweep_cnt = S->sweep_cnt;
+  L.sig = S->sig;
+  L.sorted = S->sorted;
+  L.perm = S->perm;
+  L.kept = S->kept;
+  L.err = S->err;
+  L.stats = S->stats;
+  L.disc = S->disc;
+  L.bar = S->bar;
+  L.tprof = S->tprof;
+  return L;
+}
+
+// Workgroups for one persistent SVD of an R x C block: one per Jacobi pair of
+// a round, no more (grid barriers get slower with every extra workgroup).  Sizes are estimates
+// (bond dims of the last completed step, plus growth margin); they only affect
+// speed, never results.
+int grid_for(const lmpo_state *S, int R, int C) {
+  (void)R;
   int nbp = (C + JB - 1) / JB;
   nbp += nbp & 1;
-  if (nbp < 2) nbp = 2;
-  const double tol = 8.0 * std::sqrt((double)R) * 2.220446049250313e-16;
-  for (int sweep = 0; sweep < kMaxSweeps; ++sweep) {
-    HIP_TRY(hipMemsetAsync(S->counter, 0, sizeof(int), S->stream));
-    for (int r = 0; r < nbp - 1; ++r)
-      launch_jacobi_round(S->stream, S->X, R, R, S->V, C, C, r, nbp, tol, S->W, S->active, S->counter);
-    int cnt = 0;
-    int rc = read_int(S, S->counter, &cnt);
-    if (rc) return rc;
-    if (cnt == 0) break;
+  const int npairs = std::max(1, nbp / 2);
+  return std::max(1, std::min(npairs, S->grid));
+}
+int est(const lmpo_state *S, int bond) {
+  if (bond < 0 || bond >= S->N - 1) return 1;
+  return std::min(S->cap[bond], S->dims_est[bond] + 8);
+}
+
+void refresh_estimates(lmpo_state *S) {
+  if (S->dims_ready && hipEventQuery(S->dims_ready) == hipSuccess)
+    std::copy(S->dims_pinned, S->dims_pinned + (S->N - 1), S->dims_est.begin());
+}
+
+// Exact move of the orthogonality centre by one site (SVD-based QR / LQ).
+int hop(lmpo_state *S, int c, bool right) {
+  int R, C;
+  if (right) {
+    R = 4 * (c == 0 ? 1 : est(S, c - 1));
+    C = est(S, c);
+  } else {
+    R = 4 * (c == S->N - 1 ? 1 : est(S, c));
+    C = est(S, c - 1);
   }
-  launch_colnorm(S->stream, S->X, R, R, C, S->sig);
-  return LMPO_OK;
-}
-
-int hop_right(lmpo_state *S, int c) {
-  const int chl = dimL(S, c), chm = S->dims[c], chr2 = dimR(S, c + 1);
-  const int R = 4 * chl, C = chm;
-  if (R < C) return fail(LMPO_EUNSUPPORTED, "hop on a bond wider than its left block");
-  launch_hop_load(S->stream, S->site[c], R, C, S->X, 0);
-  int rc = svd_block(S, R, C);
-  if (rc) return rc;
-  launch_select(S->stream, S->sig, C, C, 0.0, 1, S->perm, S->sorted, S->kept, S->d_dims + c, S->disc, S->err);
-  int k = 0;
-  if ((rc = read_int(S, S->kept, &k))) return rc;
-  launch_hop_write(S->stream, S->X, R, S->V, C, S->perm, S->sorted, k, S->site[c], S->Z, R, C, 1);
-  launch_zgemm(S->stream, k, 4 * chr2, chm, S->Z, chm, S->site[c + 1], 4 * chr2, S->T, 4 * chr2);
-  HIP_TRY(hipMemcpyAsync(S->site[c + 1], S->T, (size_t)k * 4 * chr2 * sizeof(double2), hipMemcpyDeviceToDevice,
-                         S->stream));
-  S->dims[c] = k;
-  return LMPO_OK;
-}
-
-int hop_left(lmpo_state *S, int c) {
-  const int chm = S->dims[c - 1], chr = dimR(S, c), chl2 = dimL(S, c - 1);
-  const int R = 4 * chr, C = chm;
-  if (R < C) return fail(LMPO_EUNSUPPORTED, "hop on a bond wider than its right block");
-  launch_hop_load(S->stream, S->site[c], chm, 4 * chr, S->X, 1);
-  int rc = svd_block(S, R, C);
-  if (rc) return rc;
-  launch_select(S->stream, S->sig, C, C, 0.0, 1, S->perm, S->sorted, S->kept, S->d_dims + (c - 1), S->disc,
-                S->err);
-  int k = 0;
-  if ((rc = read_int(S, S->kept, &k))) return rc;
-  launch_hop_write(S->stream, S->X, R, S->V, C, S->perm, S->sorted, k, S->site[c], S->Z, R, C, 0);
-  launch_zgemm(S->stream, 4 * chl2, k, chm, S->site[c - 1], chm, S->Z, k, S->T, k);
-  HIP_TRY(hipMemcpyAsync(S->site[c - 1], S->T, (size_t)4 * chl2 * k * sizeof(double2), hipMemcpyDeviceToDevice,
-                         S->stream));
-  S->dims[c - 1] = k;
+  HIP_TRY(launch_svd_persistent(S->stream, svd_args(S, right ? 1 : 2, c, 0), grid_for(S, R, C)));
   return LMPO_OK;
 }
 
 int move_centre(lmpo_state *S, int to) {
   int rc;
   while (S->centre < to) {
-    if ((rc = hop_right(S, S->centre))) return rc;
+    if ((rc = hop(S, S->centre, true))) return rc;
     S->centre++;
   }
   while (S->centre > to) {
-    if ((rc = hop_left(S, S->centre))) return rc;
+    if ((rc = hop(S, S->centre, false))) return rc;
     S->centre--;
   }
   return LMPO_OK;
@@ -299,23 +332,12 @@ int move_centre(lmpo_state *S, int to) {
 int apply_gate(lmpo_state *S, int k, int half, int asc) {
   int rc = move_centre(S, S->centre <= k ? k : k + 1);
   if (rc) return rc;
-  const int chl = dimL(S, k), chm = S->dims[k], chr = dimR(S, k + 1);
-  const int R = 4 * chl, C = 4 * chr;
-  const int trans = R >= C ? 0 : 1;
-  const int RX = trans ? C : R, CX = trans ? R : C;
   const double2 *G = S->d_gates + ((size_t)k * 2 + (half ? 1 : 0)) * 256;
-  launch_contract_gate(S->stream, S->opt.precision, S->site[k], S->site[k + 1], G, chl, chm, chr, S->X, trans);
-  if ((rc = svd_block(S, RX, CX))) return rc;
-  launch_select(S->stream, S->sig, CX, S->opt.chi_max, S->opt.cutoff, 0, S->perm, S->sorted, S->kept,
-                S->d_dims + k, S->disc, S->err);
-  const int kmax = std::min(S->opt.chi_max, CX);
-  launch_canon(S->stream, S->X, RX, S->V, CX, S->perm, S->sorted, S->kept, S->site[k], S->site[k + 1], chl, chr,
-               trans, asc, kmax);
-  int kk = 0;
-  if ((rc = read_int(S, S->kept, &kk))) return rc;
-  S->dims[k] = kk;
-  S->last_C = CX;
-  S->last_kept = kk;
+  launch_contract_gate(S->stream, S->opt.precision, S->d_sites, S->d_dims, S->N, k, capL(S, k), capR(S, k + 1), G,
+                       S->X);
+  HIP_TRY(hipGetLastError());
+  const int r = 4 * (k == 0 ? 1 : est(S, k - 1)), c = 4 * (k + 1 == S->N - 1 ? 1 : est(S, k + 1));
+  HIP_TRY(launch_svd_persistent(S->stream, svd_args(S, 0, k, asc), grid_for(S, std::max(r, c), std::min(r, c))));
   S->centre = asc ? k + 1 : k;
   return LMPO_OK;
 }
@@ -324,6 +346,7 @@ int check_err(lmpo_state *S) {
   int e = 0;
   int rc = read_int(S, S->err, &e);
   if (rc) return rc;
+  if (e & 2) return fail(LMPO_EHIP, "a grid barrier wait exceeded its spin limit (workgroups not co-resident)");
   if (e) return fail(LMPO_ENUMERIC, "non-finite or zero singular values / trace encountered");
   return LMPO_OK;
 }
@@ -433,9 +456,17 @@ int lmpo_create(const lmpo_model *model, const lmpo_options *opt, const char *in
     e = hipMemcpyAsync(S->site[i], &sitev[4 * i], 4 * sizeof(double2), hipMemcpyHostToDevice, S->stream);
     if (e != hipSuccess) return cleanup(fail(LMPO_EHIP, std::string("site upload: ") + hipGetErrorString(e)));
   }
+  S->grid = svd_grid_size();
+  S->dims_est.assign(std::max(S->N - 1, 1), 1);
+  e = hipHostMalloc((void **)&S->dims_pinned, std::max(S->N - 1, 1) * sizeof(int), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&S->dims_ready, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(S->dims_ready, S->stream);
+  if (e != hipSuccess) return cleanup(fail(LMPO_EHIP, std::string("pinned dims: ") + hipGetErrorString(e)));
   int zero = 0;
   double zd = 0.0;
-  e = hipMemcpyAsync(S->err, &zero, sizeof(int), hipMemcpyHostToDevice, S->stream);
+  e = hipMemsetAsync(S->stats, 0, kStats * sizeof(int), S->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(S->tprof, 0, 16 * sizeof(unsigned long long), S->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(S->err, &zero, sizeof(int), hipMemcpyHostToDevice, S->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(S->disc, &zd, sizeof(double), hipMemcpyHostToDevice, S->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(S->stream);
   if (e != hipSuccess) return cleanup(fail(LMPO_EHIP, std::string("init: ") + hipGetErrorString(e)));
@@ -447,9 +478,14 @@ int lmpo_evolve_step(lmpo_state *S, int32_t n_steps) {
   if (!S) return fail(LMPO_EINVAL, "state is null");
   if (n_steps < 0) return fail(LMPO_EINVAL, "n_steps must be >= 0");
   for (int n = 0; n < n_steps; ++n) {
+    refresh_estimates(S);
     int rc = one_step(S, S->step_index);
     if (rc) return rc;
     S->step_index++;
+    if (S->dims_ready && hipEventQuery(S->dims_ready) != hipErrorNotReady) {
+      HIP_TRY(hipMemcpyAsync(S->dims_pinned, S->d_dims, (S->N - 1) * sizeof(int), hipMemcpyDeviceToHost, S->stream));
+      HIP_TRY(hipEventRecord(S->dims_ready, S->stream));
+    }
   }
   return LMPO_OK;
 }
@@ -574,7 +610,8 @@ int lmpo_destroy(lmpo_state *S) {
 int lmpo_get_site(lmpo_state *S, int32_t k, int32_t dims[2], double *out) {
   if (!S || !dims) return fail(LMPO_EINVAL, "null argument");
   if (k < 0 || k >= S->N) return fail(LMPO_EINVAL, "site index out of range");
-  HIP_TRY(hipStreamSynchronize(S->stream));
+  int rc = sync_dims(S);
+  if (rc) return rc;
   dims[0] = dimL(S, k);
   dims[1] = dimR(S, k);
   if (out)
@@ -587,8 +624,10 @@ int lmpo_get_site(lmpo_state *S, int32_t k, int32_t dims[2], double *out) {
 int lmpo_set_site(lmpo_state *S, int32_t k, int32_t chl, int32_t chr, const double *data) {
   if (!S || !data) return fail(LMPO_EINVAL, "null argument");
   if (k < 0 || k >= S->N) return fail(LMPO_EINVAL, "site index out of range");
-  const int capl = k == 0 ? 1 : S->cap[k - 1], capr = k == S->N - 1 ? 1 : S->cap[k];
+  const int capl = capL(S, k), capr = capR(S, k);
   if (chl < 1 || chr < 1 || chl > capl || chr > capr) return fail(LMPO_EINVAL, "site shape exceeds the bond capacity");
+  int rc = sync_dims(S);
+  if (rc) return rc;
   if (k > 0) S->dims[k - 1] = chl;
   if (k < S->N - 1) S->dims[k] = chr;
   HIP_TRY(hipMemcpyAsync(S->site[k], data, (size_t)chl * 4 * chr * sizeof(double2), hipMemcpyHostToDevice, S->stream));
@@ -625,14 +664,42 @@ int lmpo_apply_gate(lmpo_state *S, int32_t k, int32_t half, int32_t ascending) {
 
 int lmpo_last_spectrum(lmpo_state *S, int32_t n_out, double *sv, int32_t *n_sv, int32_t *kept) {
   if (!S || !n_sv || !kept) return fail(LMPO_EINVAL, "null argument");
+  int st[kStats];
+  HIP_TRY(hipMemcpyAsync(st, S->stats, sizeof(st), hipMemcpyDeviceToHost, S->stream));
+  HIP_TRY(hipMemcpyAsync(kept, S->kept, sizeof(int), hipMemcpyDeviceToHost, S->stream));
   HIP_TRY(hipStreamSynchronize(S->stream));
-  *n_sv = S->last_C;
-  *kept = S->last_kept;
-  int n = std::min<int>(n_out, S->last_C);
+  *n_sv = st[1];
+  int n = std::min<int>(n_out, st[1]);
   if (sv && n > 0) {
     HIP_TRY(hipMemcpyAsync(sv, S->sorted, n * sizeof(double), hipMemcpyDeviceToHost, S->stream));
     HIP_TRY(hipStreamSynchronize(S->stream));
   }
+  return LMPO_OK;
+}
+
+int lmpo_svd_profile(lmpo_state *S, double out_us[12]) {
+  if (!S || !out_us) return fail(LMPO_EINVAL, "null argument");
+  unsigned long long t[16];
+  HIP_TRY(hipMemcpyAsync(t, S->tprof, sizeof(t), hipMemcpyDeviceToHost, S->stream));
+  HIP_TRY(hipStreamSynchronize(S->stream));
+  int dev = 0, khz = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+  for (int i = 0; i < 12; ++i) out_us[i] = khz > 0 ? (double)t[i] * 1e3 / khz : 0.0;
+  out_us[7] = (double)t[7];
+  out_us[3] = (double)t[12];  // shader clock cycles of the first workgroup (whole kernels)
+  return LMPO_OK;
+}
+
+int lmpo_svd_stats(lmpo_state *S, int32_t out[4]) {
+  if (!S || !out) return fail(LMPO_EINVAL, "null argument");
+  int st[kStats];
+  HIP_TRY(hipMemcpyAsync(st, S->stats, sizeof(st), hipMemcpyDeviceToHost, S->stream));
+  HIP_TRY(hipStreamSynchronize(S->stream));
+  out[0] = st[0];
+  out[1] = st[1];
+  out[2] = st[4];
+  out[3] = st[5];
   return LMPO_OK;
 }
 

@@ -28,24 +28,30 @@ constexpr int JB = 8;
 constexpr int JP = 2 * JB;
 constexpr int kMaxDim = 2048;  // largest block side (4 chi) the sort handles
 
-// ---- kernel launchers (kernels.hip) ----
-void launch_contract_gate(hipStream_t s, int precision, const double2 *Ak, const double2 *Ak1,
-                          const double2 *G, int chl, int chm, int chr, double2 *X, int trans);
-void launch_jacobi_round(hipStream_t s, double2 *X, int ldx, int R, double2 *V, int ldv, int C,
-                         int round, int nbp, double tol, double2 *W, int *active, int *counter);
-void launch_identity(hipStream_t s, double2 *V, int ldv, int C);
-void launch_colnorm(hipStream_t s, const double2 *X, int ldx, int R, int C, double *sig);
-void launch_select(hipStream_t s, const double *sig, int C, int chi_max, double cutoff, int hop,
-                   int *perm, double *sorted, int *kept, int *dims_slot, double *disc, int *err);
-void launch_canon(hipStream_t s, const double2 *X, int ldx, const double2 *V, int ldv,
-                  const int *perm, const double *sorted, const int *kept, double2 *Ak,
-                  double2 *Ak1, int chl, int chr, int trans, int asc, int kmax);
-void launch_hop_load(hipStream_t s, const double2 *A, int rows, int cols, double2 *X, int ct);
-void launch_hop_write(hipStream_t s, const double2 *X, int ldx, const double2 *V, int ldv,
-                      const int *perm, const double *sorted, int k, double2 *Ac, double2 *Z,
-                      int R, int C, int right);
-void launch_zgemm(hipStream_t s, int M, int N, int K, const double2 *A, int lda, const double2 *B,
-                  int ldb, double2 *Cm, int ldc);
+// ---- kernel launchers (kernels.hip, svd.hip) ----
+void launch_contract_gate(hipStream_t s, int precision, double2 *const *sites, const int *dims, int N, int k,
+                          int cap_l, int cap_r, const double2 *G, double2 *X);
+
+// One persistent cooperative launch: mode 0 = truncated SVD + canonical update
+// of the two-site block on bond k (X filled by the contraction); mode 1/2 =
+// exact centre hop right/left from site k.
+struct SvdLaunch {
+  int mode, k, N, asc, chi_max, max_sweeps;
+  double cutoff, tol_factor;
+  double2 *const *sites;
+  int *dims;
+  double2 *X, *V, *W, *Z, *T;
+  int *act;
+  int *sweep_cnt;
+  double *sig, *sorted;
+  int *perm, *kept, *err, *stats;
+  double *disc;
+  unsigned *bar;
+  unsigned long long *tprof;
+};
+int svd_grid_size();
+hipError_t launch_svd_persistent(hipStream_t s, const SvdLaunch &L, int grid);
+
 void launch_trace(hipStream_t s, double2 *const *sites, const int *dims, int N, double2 *out);
 void launch_env_all(hipStream_t s, double2 *const *sites, const int *dims, int N, int cap,
                     double2 *envL, double2 *envR);

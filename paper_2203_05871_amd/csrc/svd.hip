@@ -1,0 +1,828 @@
+// Persistent, device-driven truncated SVD for one two-site block or one
+// orthogonality-centre hop (gfx950).
+//
+// One cooperative launch performs, with grid barriers between phases:
+//   (hop only) load X from the site tensor
+//   V <- I
+//   sweeps of block one-sided Jacobi until a sweep applies no rotation
+//   column norms sigma_j = ||x_j||
+//   sort + truncation select (workgroup 0)
+//   gate: canonical update of A_k, A_{k+1};  hop: A_c <- Q, neighbour <- R * neighbour
+// All problem sizes come from the bond-dimension array in device memory, so a
+// whole Trotter step is enqueued without any host synchronisation.
+//
+// Jacobi (Hestenes) on X (R x C, column-major, R >= C): X V = U diag(sigma).
+// Columns form blocks of JB; each round pairs the blocks by a round-robin
+// tournament.  Per pair, the JP x JP Gram matrix G = X_p^H X_p is diagonalised
+// by cyclic two-sided Jacobi in LDS (W unitary, G W = W diag), then X_p <- X_p W
+// and V_p <- V_p W.  A pair is skipped when every off-diagonal entry satisfies
+// |g_pq| <= tol sqrt(g_pp g_qq): the columns are then orthogonal to working
+// accuracy relative to their own norms, which gives small singular values
+// to high relative accuracy.
+#include "lmpo_internal.h"
+
+namespace lmpo {
+
+namespace {
+
+__device__ __forceinline__ double2 zmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 zconj(double2 a) { return make_double2(a.x, -a.y); }
+__device__ __forceinline__ double2 zadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ void zfma(double2 &acc, double2 a, double2 b) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+}
+__device__ __forceinline__ void zfma_cj(double2 &acc, double2 a, double2 b) {  // acc += conj(a) b
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(-a.y, b.x, acc.y);
+}
+
+constexpr int NT = 256;  // threads per workgroup
+constexpr int kInnerSweeps = 1;
+
+// Hierarchical grid barrier: 8 group counters (one per workgroup residue mod 8,
+// i.e. per XCD under the default round-robin dispatch) and a top counter; all
+// counters are monotonic (barrier n waits for n * members arrivals).
+struct Barrier {
+  unsigned *grp;  // [8 * 32] (one 128-byte line per group)
+  unsigned *top;
+  unsigned *flag;
+  int *err;       // set to 2 if a wait ever exceeds its spin limit
+  unsigned G;
+  unsigned phase;
+  // Every thread's global writes before the barrier are visible to every
+  // workgroup after it: the workgroup barrier orders this block's stores,
+  // thread 0 publishes them device-wide (agent-scope fence) and, after the
+  // wait, acquires the other blocks' stores for the whole workgroup.
+  __device__ void sync() {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      __threadfence();
+      const unsigned target = ++phase;
+      const unsigned g = blockIdx.x & 7u;
+      const unsigned ngrp = G < 8u ? G : 8u;
+      const unsigned members = (G - g + 7u) / 8u;
+      unsigned old = atomicAdd(&grp[g * 32], 1u);
+      if (old == target * members - 1u) {
+        unsigned t = atomicAdd(top, 1u);
+        if (t == target * ngrp - 1u) __hip_atomic_store(flag, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      // bounded wait: a co-resident grid always completes; the limit (seconds)
+      // only guarantees that every wave exits if residency were ever violated
+      unsigned spins = 0;
+      while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > (1u << 25)) {
+          atomicOr(err, 2);
+          break;
+        }
+      }
+      __threadfence();
+    } else {
+      ++phase;
+    }
+    __syncthreads();
+  }
+};
+
+// LDS ordering among the lanes of one wavefront: its LDS operations execute in
+// order, so a compiler fence plus a wait for outstanding LDS traffic suffices.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0)
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ void pair_blocks(int round, int p, int nbp, int &bi, int &bj) {
+  const int m = nbp - 1;
+  if (p == 0) {
+    bi = m;
+    bj = round;
+  } else {
+    bi = (round + p) % m;
+    bj = (round - p + m) % m;
+  }
+}
+
+// Partner of index i in step `step` of the round-robin over JP indices.
+__device__ __forceinline__ int inner_partner(int i, int step) {
+  const int m = JP - 1;
+  if (i == m) return step;
+  if (i == step) return m;
+  // i = (step + t) % m  <->  partner = (step - t) % m
+  int t = (i - step + m) % m;
+  return (step - t + m) % m;
+}
+
+constexpr int kChunk = 512;  // rows of a column pair staged in LDS at once
+struct SharedPair {
+  double2 xs[kChunk][JP + 1];
+  double2 G[2][JP][JP + 1];
+  double2 W[2][JP][JP + 1];
+  int col[JP];
+};
+struct SharedSelect {
+  double key[kMaxDim];
+  int idx[kMaxDim];
+  double tail[kMaxDim + 1];
+  int cnt_above, cnt_nz, bad;
+};
+struct SharedGemm {
+  double2 As[16][64];
+  double2 Bs[16][64];
+};
+union SharedAll {
+  SharedPair pair;
+  SharedSelect sel;
+  SharedGemm gemm;
+  double red[NT];
+};
+
+// Stage rows [r0, r0 + n) of the pair's columns of M into LDS (xs[i][c]).
+// All global loads of a thread are issued before any LDS store, so their
+// latencies overlap instead of adding up.
+__device__ __forceinline__ void stage_rows(SharedPair &s, const double2 *__restrict__ M, int ld, int r0, int n) {
+  constexpr int kRows = kChunk / NT;  // rows per thread and column
+  double2 buf[JP][kRows];
+#pragma unroll
+  for (int c = 0; c < JP; ++c)
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+      const int i = threadIdx.x + k * NT;
+      buf[c][k] = (i < n && s.col[c] >= 0) ? M[(size_t)(r0 + i) + (size_t)s.col[c] * ld] : make_double2(0, 0);
+    }
+#pragma unroll
+  for (int c = 0; c < JP; ++c)
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+      const int i = threadIdx.x + k * NT;
+      if (i < n) s.xs[i][c] = buf[c][k];
+    }
+}
+
+// MFMA helpers: v_mfma_f64_16x16x4f64 computes D(16x16) += A(16x4) B(4x16).
+// Lane l supplies A[l % 16][l / 16] and B[l / 16][l % 16]; it holds
+// D[l / 16 + 4 r][l % 16] in register r (rows interleaved by 4, unlike the
+// f32 16x16x4 form; checked on gfx950).  Complex products are split into four
+// real MFMAs.
+typedef double d4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+
+// M[r0 + i][col[c]] <- sum_q xs[i][q] W[q][c] for the staged rows (n rows),
+// one 16-row block per wave and step.
+__device__ __forceinline__ void rotate_staged(SharedPair &s, const double2 (*W)[JP + 1], double2 *__restrict__ M,
+                                              int ld, int r0, int n) {
+  static_assert(JP == 16, "MFMA tiling assumes 16 columns per pair");
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  double2 w[4];
+#pragma unroll
+  for (int kk = 0; kk < 4; ++kk) w[kk] = W[4 * kk + lk][lr];
+  const int cj = s.col[lr];
+  for (int i0 = wave * 16; i0 < n; i0 += 64) {
+    d4 yr = {0, 0, 0, 0}, yi = {0, 0, 0, 0};
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+      const int row = i0 + lr;
+      const double2 x = (row < n) ? s.xs[row][4 * kk + lk] : make_double2(0, 0);
+      yr = mfma64(x.x, w[kk].x, yr);
+      yr = mfma64(-x.y, w[kk].y, yr);
+      yi = mfma64(x.x, w[kk].y, yi);
+      yi = mfma64(x.y, w[kk].x, yi);
+    }
+    if (cj >= 0) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = i0 + lk + 4 * r;
+        if (row < n) M[(size_t)(r0 + row) + (size_t)cj * ld] = make_double2(yr[r], yi[r]);
+      }
+    }
+  }
+}
+
+// One Jacobi pair: Gram of the JP columns, one cyclic sweep of two-sided
+// Jacobi on it (W), then X_p <- X_p W and V_p <- V_p W.  The same workgroup
+// does all of it, so a round needs a single grid barrier.  Returns whether the
+// pair was rotated (some off-diagonal above threshold).
+__device__ bool pair_work(SharedPair &s, double2 *__restrict__ X, int ldx, int R, double2 *__restrict__ Wout,
+                          int C, int bi, int bj, double tol, unsigned long long *tp) {
+  const int t = threadIdx.x;
+  unsigned long long tm = wall_clock64();
+  auto mark = [&](int slot) {
+    if (tp && t == 0) {
+      unsigned long long now = wall_clock64();
+      tp[slot] += now - tm;
+      tm = now;
+    }
+  };
+  if (t < JP) {
+    int c = (t < JB) ? bi * JB + t : bj * JB + (t - JB);
+    s.col[t] = (c < C) ? c : -1;
+  }
+  __syncthreads();
+  const int a = t / JP, b = t % JP;
+  // G = X_p^H X_p with MFMA: A[i][k] = conj(X[k][i]) and B[k][j] = X[k][j] take
+  // the same element per lane; each wave covers every fourth 4-row step.
+  {
+    const int lane = t & 63, wave = t >> 6;
+    const int lr = lane & 15, lk = lane >> 4;
+    d4 gr = {0, 0, 0, 0}, gi = {0, 0, 0, 0};
+    for (int r0 = 0; r0 < R; r0 += kChunk) {
+      const int n = min(kChunk, R - r0);
+      stage_rows(s, X, ldx, r0, n);
+      __syncthreads();
+      for (int k0 = wave * 4; k0 < n; k0 += 16) {
+        const int row = k0 + lk;
+        const double2 x = (row < n) ? s.xs[row][lr] : make_double2(0, 0);
+        gr = mfma64(x.x, x.x, gr);
+        gr = mfma64(x.y, x.y, gr);
+        gi = mfma64(x.x, x.y, gi);
+        gi = mfma64(-x.y, x.x, gi);
+      }
+      if (r0 + kChunk < R) __syncthreads();
+    }
+    // reduce the four waves' partial Grams through LDS: wave w writes its
+    // partial to scratch slot w (G[0], G[1], W[0], W[1]), one barrier, sum
+    double2 (*part)[JP + 1] = (wave == 0) ? s.G[0] : (wave == 1) ? s.G[1] : (wave == 2) ? s.W[0] : s.W[1];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) part[lk + 4 * r][lr] = make_double2(gr[r], gi[r]);
+    __syncthreads();
+  }
+  double2 acc = zadd(zadd(s.G[0][a][b], s.G[1][a][b]), zadd(s.W[0][a][b], s.W[1][a][b]));
+  __syncthreads();
+  if (a == b) acc.y = 0.0;
+  s.G[0][a][b] = acc;
+  s.W[0][a][b] = make_double2(a == b ? 1.0 : 0.0, 0.0);
+  __syncthreads();
+  int need = 0;
+  if (a < b) {
+    double d = sqrt(s.G[0][a][a].x * s.G[0][b][b].x);
+    double m = sqrt(acc.x * acc.x + acc.y * acc.y);
+    need = m > tol * d;
+  }
+  need = __syncthreads_or(need);
+  mark(8);
+  if (!need) return false;
+  // One cyclic sweep over the JP x JP Gram per round: the pair need not be
+  // diagonalised exactly, later rounds recompute its Gram from the columns
+  // (the outer sweep count is the same as with a fully converged inner solve).
+  __shared__ double2 s_al[JP], s_be[JP];
+  __shared__ int s_pt[JP], s_rot[JP];
+  int cur = 0;
+  const double tol2 = tol * tol;
+  for (int sweep = 0; sweep < kInnerSweeps; ++sweep) {
+    for (int step = 0; step < JP - 1; ++step) {
+      if (t < JP / 2) {
+        int p, q;
+        if (t == 0) {
+          p = step;
+          q = JP - 1;
+        } else {
+          const int m = JP - 1;
+          p = (step + t) % m;
+          q = (step - t + m) % m;
+          if (p > q) {
+            int x = p;
+            p = q;
+            q = x;
+          }
+        }
+        const double app = s.G[cur][p][p].x, aqq = s.G[cur][q][q].x;
+        const double2 c = s.G[cur][p][q];
+        const double mc2 = c.x * c.x + c.y * c.y;
+        s_pt[p] = q;
+        s_pt[q] = p;
+        if (mc2 > tol2 * (app * aqq) && mc2 > 0.0) {
+          // zero g_pq: x_p' = cs x_p - sn e^{-i phi} x_q, x_q' = sn x_p + cs e^{-i phi} x_q
+          // (an FP32 tangent here costs ~2.6x more sweeps: keep FP64)
+          const double inv = rsqrt(mc2);
+          const double zeta = 0.5 * (aqq - app) * inv;
+          const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+          const double cs = rsqrt(1.0 + tt * tt), sn = tt * cs;
+          const double2 ph = make_double2(c.x * inv, -c.y * inv);
+          s_al[p] = make_double2(cs, 0.0);
+          s_be[p] = make_double2(-sn * ph.x, -sn * ph.y);
+          s_al[q] = make_double2(cs * ph.x, cs * ph.y);
+          s_be[q] = make_double2(sn, 0.0);
+          s_rot[p] = s_rot[q] = 1;
+        } else {
+          s_al[p] = s_al[q] = make_double2(1.0, 0.0);
+          s_be[p] = s_be[q] = make_double2(0.0, 0.0);
+          s_rot[p] = s_rot[q] = 0;
+        }
+      }
+      __syncthreads();
+      const int pa = s_pt[a], pb = s_pt[b];
+      const double2 al_a = s_al[a], be_a = s_be[a], al_b = s_al[b], be_b = s_be[b];
+      const int nxt = cur ^ 1;
+      const double2 gj_a = zadd(zmul(s.G[cur][a][b], al_b), zmul(s.G[cur][a][pb], be_b));
+      const double2 gj_pa = zadd(zmul(s.G[cur][pa][b], al_b), zmul(s.G[cur][pa][pb], be_b));
+      double2 g = zadd(zmul(zconj(al_a), gj_a), zmul(zconj(be_a), gj_pa));
+      if (a == b) g.y = 0.0;
+      if (pa == b && s_rot[a]) g = make_double2(0.0, 0.0);
+      s.G[nxt][a][b] = g;
+      s.W[nxt][a][b] = zadd(zmul(s.W[cur][a][b], al_b), zmul(s.W[cur][a][pb], be_b));
+      __syncthreads();
+      cur = nxt;
+    }
+  }
+  mark(9);
+  const double2(*W)[JP + 1] = s.W[cur];
+  // X_p <- X_p W (rows still staged when R fits one chunk)
+  if (R <= kChunk) {
+    rotate_staged(s, W, X, ldx, 0, R);
+  } else {
+    for (int r0 = 0; r0 < R; r0 += kChunk) {
+      const int n = min(kChunk, R - r0);
+      __syncthreads();
+      stage_rows(s, X, ldx, r0, n);
+      __syncthreads();
+      rotate_staged(s, W, X, ldx, r0, n);
+    }
+  }
+  // record W for the row-parallel update of V after the sweep
+  Wout[t] = W[t / JP][t % JP];
+  __syncthreads();
+  mark(10);
+  return true;
+}
+
+// V <- V W_1 W_2 ... over one sweep's rounds.  The rows of V transform
+// independently, so workgroups take row blocks of V into LDS and apply every
+// recorded pair rotation of the sweep in round order; no grid barrier needed.
+__device__ void sweep_update_v(SharedPair &s, double2 *__restrict__ V, int ldv, int C, int nbp,
+                               const double2 *__restrict__ Wsw, const int *__restrict__ act, int G) {
+  const int npairs = nbp / 2;
+  double2 *vs = &s.xs[0][0];  // h rows x C columns, row-major, h * C <= kChunk * (JP + 1)
+  int h = (kChunk * (JP + 1)) / C;
+  h = h >= 16 ? 16 : (h >= 8 ? 8 : 4);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int r0 = blockIdx.x * h; r0 < C; r0 += G * h) {
+    const int nr = min(h, C - r0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < h * C; e += NT) {
+      const int i = e / C, c = e - i * C;
+      vs[e] = (i < nr) ? V[(size_t)(r0 + i) + (size_t)c * ldv] : make_double2(0, 0);
+    }
+    __syncthreads();
+    for (int round = 0; round < nbp - 1; ++round) {
+      for (int p = wave; p < npairs; p += 4) {
+        if (!act[round * npairs + p]) continue;
+        int bi, bj;
+        pair_blocks(round, p, nbp, bi, bj);
+        const double2 *W = Wsw + (size_t)(round * npairs + p) * JP * JP;
+        int cq[4];
+        double2 w[4];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const int q = 4 * kk + lk;
+          const int c = (q < JB) ? bi * JB + q : bj * JB + (q - JB);
+          cq[kk] = c < C ? c : -1;
+          w[kk] = W[q * JP + lr];
+        }
+        const int cj0 = (lr < JB) ? bi * JB + lr : bj * JB + (lr - JB);
+        const int cj = cj0 < C ? cj0 : -1;
+        d4 yr = {0, 0, 0, 0}, yi = {0, 0, 0, 0};
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) {
+          const double2 x = (lr < h && cq[kk] >= 0) ? vs[lr * C + cq[kk]] : make_double2(0, 0);
+          yr = mfma64(x.x, w[kk].x, yr);
+          yr = mfma64(-x.y, w[kk].y, yr);
+          yi = mfma64(x.x, w[kk].y, yi);
+          yi = mfma64(x.y, w[kk].x, yi);
+        }
+        if (cj >= 0) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int row = lk + 4 * r;
+            if (row < h) vs[row * C + cj] = make_double2(yr[r], yi[r]);
+          }
+        }
+      }
+      __syncthreads();
+    }
+    for (int e = threadIdx.x; e < nr * C; e += NT) {
+      const int i = e / C, c = e - i * C;
+      V[(size_t)(r0 + i) + (size_t)c * ldv] = vs[e];
+    }
+  }
+}
+
+__device__ void block_select(SharedSelect &s, const double *__restrict__ sig, int C, int chi_max, double cutoff,
+                             int hop, int *__restrict__ perm, double *__restrict__ sorted, int *__restrict__ kept,
+                             int *__restrict__ dims_slot, double *__restrict__ disc, int *__restrict__ err) {
+  const int t = threadIdx.x;
+  int n2 = 2;
+  while (n2 < C) n2 <<= 1;
+  if (t == 0) {
+    s.cnt_above = 0;
+    s.cnt_nz = 0;
+    s.bad = 0;
+  }
+  __syncthreads();
+  for (int e = t; e < n2; e += NT) {
+    double v = (e < C) ? sig[e] : -1.0;
+    if (e < C && !(v >= 0.0 && v < INFINITY)) atomicOr(&s.bad, 1);
+    s.key[e] = v;
+    s.idx[e] = e;
+  }
+  __syncthreads();
+  for (int size = 2; size <= n2; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int e = t; e < n2; e += NT) {
+        int partner = e ^ stride;
+        if (partner > e) {
+          bool desc = ((e & size) == 0);
+          double ka = s.key[e], kb = s.key[partner];
+          int ia = s.idx[e], ib = s.idx[partner];
+          bool a_first = (ka > kb) || (ka == kb && ia < ib);
+          if (desc ? !a_first : a_first) {
+            s.key[e] = kb;
+            s.key[partner] = ka;
+            s.idx[e] = ib;
+            s.idx[partner] = ia;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int e = t; e < n2; e += NT) s.tail[e] = (e < C) ? s.key[e] * s.key[e] : 0.0;
+  if (t == 0) s.tail[n2] = 0.0;
+  __syncthreads();
+  for (int off = 1; off < n2; off <<= 1) {
+    double v[kMaxDim / NT];
+    int q = 0;
+    for (int e = t; e < n2; e += NT, ++q) v[q] = (e + off < n2) ? s.tail[e + off] : 0.0;
+    __syncthreads();
+    q = 0;
+    for (int e = t; e < n2; e += NT, ++q) s.tail[e] += v[q];
+    __syncthreads();
+  }
+  const double W = s.tail[0];
+  for (int e = t; e < C; e += NT) {
+    if (e >= 1 && s.tail[e] > cutoff * W) atomicAdd(&s.cnt_above, 1);
+    if (s.key[e] > 0.0) atomicAdd(&s.cnt_nz, 1);
+    perm[e] = s.idx[e];
+    sorted[e] = s.key[e];
+  }
+  __syncthreads();
+  if (t == 0) {
+    int k;
+    if (hop) {
+      k = s.cnt_nz;
+    } else {
+      int kc = 1 + s.cnt_above;
+      k = kc < chi_max ? kc : chi_max;
+      if (k > s.cnt_nz) k = s.cnt_nz;
+    }
+    if (k < 1) k = 1;
+    if (s.bad || !(W > 0.0)) *err = 1;
+    *kept = k;
+    *dims_slot = k;
+    if (!hop && W > 0.0) *disc += s.tail[k] / W;
+  }
+  __syncthreads();
+}
+
+}  // namespace
+
+struct SvdArgs {
+  int mode;  // 0: gate on bond k; 1: hop right from site k; 2: hop left from site k
+  int k, N, asc, chi_max, max_sweeps;
+  double cutoff, tol_factor;
+  double2 *const *sites;
+  int *dims;
+  double2 *X, *V, *W, *Z, *T;  // W: [2][rounds][pairs][JP][JP] rotations of the last two sweeps
+  int *act;        // [2][rounds][pairs] pair rotated?
+  int *sweep_cnt;  // [max_sweeps]
+  double *sig, *sorted;
+  int *perm, *kept, *err, *stats;
+  double *disc;
+  unsigned *bar;  // [8 * 32 + 64]
+  unsigned long long *tprof;  // [8] accumulated wall-clock ticks per phase (workgroup 0)
+};
+
+__global__ __launch_bounds__(NT) void svd_persistent_kernel(SvdArgs a) {
+  __shared__ SharedAll sh;
+  // phase timers (workgroup 0, thread 0): 0 setup, 1 pair Gram+eig, 2 wait after A,
+  // 3 update, 4 wait after B, 5 norms+select, 6 epilogue, 7 launches
+  unsigned long long tmark = wall_clock64();
+  const unsigned long long cyc0 = clock64();
+  const bool prof = a.tprof && blockIdx.x == 0 && threadIdx.x == 0;
+  auto lap = [&](int slot) {
+    if (prof) {
+      unsigned long long now = wall_clock64();
+      a.tprof[slot] += now - tmark;
+      tmark = now;
+    }
+  };
+  if (prof) a.tprof[7] += 1;
+  Barrier bar{a.bar, a.bar + 8 * 32, a.bar + 8 * 32 + 32, a.err, gridDim.x, 0u};
+  const int G = gridDim.x;
+  const size_t gtid = (size_t)blockIdx.x * NT + threadIdx.x, gstride = (size_t)G * NT;
+  const int N = a.N;
+  auto dimL = [&](int s) { return s == 0 ? 1 : a.dims[s - 1]; };
+  auto dimR = [&](int s) { return s == N - 1 ? 1 : a.dims[s]; };
+  // ---- problem shape (read before any bond dimension is rewritten) ----
+  int R, C, trans = 0, chl = 1, chm = 1, chr = 1, site = a.k;
+  if (a.mode == 0) {
+    chl = dimL(a.k);
+    chr = dimR(a.k + 1);
+    const int r = 4 * chl, c = 4 * chr;
+    trans = r >= c ? 0 : 1;
+    R = trans ? c : r;
+    C = trans ? r : c;
+  } else if (a.mode == 1) {
+    chl = dimL(site);
+    chm = a.dims[site];
+    chr = dimR(site + 1);  // right dim of the neighbour
+    R = 4 * chl;
+    C = chm;
+  } else {
+    chm = a.dims[site - 1];
+    chr = dimR(site);
+    chl = dimL(site - 1);  // left dim of the neighbour
+    R = 4 * chr;
+    C = chm;
+  }
+  const int ldx = R, ldv = C;
+  // ---- hop: load X from the site tensor ----
+  if (a.mode == 1) {
+    const double2 *A = a.sites[site];
+    for (size_t e = gtid; e < (size_t)R * C; e += gstride) {
+      int i = e / C, j = e % C;
+      a.X[(size_t)i + (size_t)j * ldx] = A[e];
+    }
+  } else if (a.mode == 2) {
+    const double2 *A = a.sites[site];  // chm x (4 chr)
+    for (size_t e = gtid; e < (size_t)R * C; e += gstride) {
+      int i = e / R, j = e % R;  // A[i][j], i < chm, j < 4 chr
+      a.X[(size_t)j + (size_t)i * ldx] = zconj(A[e]);
+    }
+  }
+  for (size_t e = gtid; e < (size_t)C * C; e += gstride) {
+    int i = e % C, j = e / C;
+    a.V[(size_t)i + (size_t)j * ldv] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+  }
+  if (gtid < (size_t)a.max_sweeps) a.sweep_cnt[gtid] = 0;
+  bar.sync();
+  lap(0);
+  // ---- block Jacobi sweeps ----
+  int nbp = (C + JB - 1) / JB;
+  nbp += nbp & 1;
+  if (nbp < 2) nbp = 2;
+  const int npairs = nbp / 2;
+  const double tol = a.tol_factor * sqrt((double)R) * 2.220446049250313e-16;
+  int sweeps = 0;
+  const size_t wsw_stride = (size_t)(nbp - 1) * npairs;  // pair slots per sweep
+  for (int sweep = 0; sweep < a.max_sweeps; ++sweep) {
+    double2 *Wsw = a.W + (size_t)(sweep & 1) * wsw_stride * JP * JP;
+    int *act = a.act + (size_t)(sweep & 1) * wsw_stride;
+    for (int round = 0; round < nbp - 1; ++round) {
+      for (int p = blockIdx.x; p < npairs; p += G) {
+        int bi, bj;
+        pair_blocks(round, p, nbp, bi, bj);
+        const size_t slot = (size_t)round * npairs + p;
+        bool active = pair_work(sh.pair, a.X, ldx, R, Wsw + slot * JP * JP, C, bi, bj, tol,
+                                (a.tprof && blockIdx.x == 0) ? a.tprof : nullptr);
+        if (threadIdx.x == 0) {
+          act[slot] = active ? 1 : 0;
+          if (active) atomicAdd(&a.sweep_cnt[sweep], 1);
+        }
+        __syncthreads();
+      }
+      lap(1);
+      bar.sync();
+      lap(2);
+    }
+    sweeps = sweep + 1;
+    if (__hip_atomic_load(&a.sweep_cnt[sweep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) break;
+    sweep_update_v(sh.pair, a.V, ldv, C, nbp, Wsw, act, G);
+    lap(11);
+  }
+  bar.sync();
+  // ---- column norms ----
+  for (int j = blockIdx.x; j < C; j += G) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < R; i += NT) {
+      double2 v = a.X[(size_t)i + (size_t)j * ldx];
+      acc = fma(v.x, v.x, fma(v.y, v.y, acc));
+    }
+    sh.red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = NT / 2; off > 0; off >>= 1) {
+      if (threadIdx.x < off) sh.red[threadIdx.x] += sh.red[threadIdx.x + off];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) a.sig[j] = sqrt(sh.red[0]);
+    __syncthreads();
+  }
+  bar.sync();
+  int *dslot = (a.mode == 2) ? a.dims + (site - 1) : a.dims + site;
+  if (blockIdx.x == 0) {
+    if (threadIdx.x == 0 && a.stats) {
+      a.stats[0] = sweeps;
+      a.stats[1] = C;
+      a.stats[2] = R;
+      a.stats[4] += sweeps;
+      a.stats[5] += 1;
+    }
+    block_select(sh.sel, a.sig, C, a.chi_max, a.cutoff, a.mode != 0, a.perm, a.sorted, a.kept, dslot, a.disc, a.err);
+  }
+  bar.sync();
+  lap(5);
+  const int k = __hip_atomic_load(a.kept, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (a.mode == 0) {
+    // theta = U S V^H: ascending A_k <- U, A_{k+1} <- S V^H; descending A_k <- U S, A_{k+1} <- V^H.
+    // trans: X = theta^H, so theta's left vectors are V's columns, its right vectors X / sigma.
+    double2 *Ak = a.sites[a.k], *Ak1 = a.sites[a.k + 1];
+    const size_t na = (size_t)4 * chl * k, nb = (size_t)k * 4 * chr;
+    const size_t n = na > nb ? na : nb;
+    for (size_t e = gtid; e < n; e += gstride) {
+      if (e < na) {
+        const int i = e / k, al = e % k;
+        const int pc = a.perm[al];
+        const double sg = a.sorted[al];
+        double2 u;
+        if (trans == 0) {
+          double2 x = a.X[(size_t)i + (size_t)pc * ldx];
+          u = make_double2(x.x / sg, x.y / sg);
+        } else {
+          u = a.V[(size_t)i + (size_t)pc * ldv];
+        }
+        if (!a.asc) u = make_double2(u.x * sg, u.y * sg);
+        Ak[e] = u;
+      }
+      if (e < nb) {
+        const int al = e / (4 * chr), j = e % (4 * chr);
+        const int pc = a.perm[al];
+        const double sg = a.sorted[al];
+        double2 v;
+        if (trans == 0) {
+          v = a.V[(size_t)j + (size_t)pc * ldv];
+        } else {
+          double2 x = a.X[(size_t)j + (size_t)pc * ldx];
+          v = make_double2(x.x / sg, x.y / sg);
+        }
+        if (a.asc) v = make_double2(v.x * sg, v.y * sg);
+        Ak1[e] = zconj(v);
+      }
+    }
+    lap(6);
+    if (prof) a.tprof[12] += clock64() - cyc0;
+    return;
+  }
+  // ---- hop epilogue ----
+  const bool right = a.mode == 1;
+  double2 *Ac = a.sites[site];
+  {
+    const size_t na = (size_t)R * k, nz = (size_t)k * C;
+    const size_t n = na > nz ? na : nz;
+    for (size_t e = gtid; e < n; e += gstride) {
+      if (e < na) {
+        int i, al;
+        if (right) {
+          i = e / k;
+          al = e % k;
+        } else {
+          al = e / R;
+          i = e % R;
+        }
+        const double sg = a.sorted[al];
+        double2 x = a.X[(size_t)i + (size_t)a.perm[al] * ldx];
+        x = make_double2(x.x / sg, x.y / sg);
+        Ac[e] = right ? x : zconj(x);
+      }
+      if (e < nz) {
+        int al, m;
+        if (right) {
+          al = e / C;
+          m = e % C;
+        } else {
+          m = e / k;
+          al = e % k;
+        }
+        const double sg = a.sorted[al];
+        double2 v = a.V[(size_t)m + (size_t)a.perm[al] * ldv];
+        v = make_double2(v.x * sg, v.y * sg);
+        a.Z[e] = right ? zconj(v) : v;
+      }
+    }
+  }
+  bar.sync();
+  // neighbour update: right: T = Z (k x C) * A_{c+1} (C x 4 chr);  left: T = A_{c-1} (4 chl x C) * Z (C x k)
+  const double2 *Am = right ? a.Z : a.sites[site - 1];
+  const double2 *Bm = right ? a.sites[site + 1] : a.Z;
+  const int M = right ? k : 4 * chl, Nn = right ? 4 * chr : k, K = C;
+  const int lda = K, ldb = Nn;
+  const int tiles_m = (M + 63) / 64, tiles_n = (Nn + 63) / 64;
+  for (int tile = blockIdx.x; tile < tiles_m * tiles_n; tile += G) {
+    const int i0 = (tile / tiles_n) * 64, j0 = (tile % tiles_n) * 64;
+    const int t = threadIdx.x, ty = t / 16, tx = t % 16;
+    double2 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0, 0);
+    for (int k0 = 0; k0 < K; k0 += 16) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        int e = t + NT * q;
+        int row = e / 16, kk = e % 16;
+        sh.gemm.As[kk][row] =
+            (i0 + row < M && k0 + kk < K) ? Am[(size_t)(i0 + row) * lda + k0 + kk] : make_double2(0, 0);
+        int kb = e / 64, j = e % 64;
+        sh.gemm.Bs[kb][j] = (k0 + kb < K && j0 + j < Nn) ? Bm[(size_t)(k0 + kb) * ldb + j0 + j] : make_double2(0, 0);
+      }
+      __syncthreads();
+#pragma unroll 4
+      for (int kk = 0; kk < 16; ++kk) {
+        double2 av[4], bv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) av[i] = sh.gemm.As[kk][ty * 4 + i];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) bv[j] = sh.gemm.Bs[kk][tx + 16 * j];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 4; ++j) zfma(acc[i][j], av[i], bv[j]);
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        int r = i0 + ty * 4 + i, c = j0 + tx + 16 * j;
+        if (r < M && c < Nn) a.T[(size_t)r * Nn + c] = acc[i][j];
+      }
+  }
+  bar.sync();
+  double2 *dst = right ? a.sites[site + 1] : a.sites[site - 1];
+  for (size_t e = gtid; e < (size_t)M * Nn; e += gstride) dst[e] = a.T[e];
+  lap(6);
+  if (prof) a.tprof[12] += clock64() - cyc0;
+}
+
+static int g_grid = 0;
+
+int svd_grid_size() {
+  if (g_grid) return g_grid;
+  int dev = 0, cus = 0, occ = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, svd_persistent_kernel, NT, 0);
+  if (cus <= 0) cus = 1;
+  if (occ <= 0) occ = 1;
+  g_grid = cus;  // one workgroup per compute unit
+  if (g_grid > cus * occ) g_grid = cus * occ;
+  return g_grid;
+}
+
+hipError_t launch_svd_persistent(hipStream_t s, const SvdLaunch &L, int grid) {
+  SvdArgs a;
+  a.mode = L.mode;
+  a.k = L.k;
+  a.N = L.N;
+  a.asc = L.asc;
+  a.chi_max = L.chi_max;
+  a.max_sweeps = L.max_sweeps;
+  a.cutoff = L.cutoff;
+  a.tol_factor = L.tol_factor;
+  a.sites = L.sites;
+  a.dims = L.dims;
+  a.X = L.X;
+  a.V = L.V;
+  a.W = L.W;
+  a.act = L.act;
+  a.Z = L.Z;
+  a.T = L.T;
+  a.sweep_cnt = L.sweep_cnt;
+  a.sig = L.sig;
+  a.sorted = L.sorted;
+  a.perm = L.perm;
+  a.kept = L.kept;
+  a.err = L.err;
+  a.stats = L.stats;
+  a.disc = L.disc;
+  a.bar = L.bar;
+  a.tprof = L.tprof;
+  hipError_t e = hipMemsetAsync(L.bar, 0, (8 * 32 + 64) * sizeof(unsigned), s);
+  if (e != hipSuccess) return e;
+  void *args[] = {&a};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(svd_persistent_kernel), dim3(grid), dim3(NT), args,
+                                    0, s);
+}
+
+}  // namespace lmpo

@@ -60,7 +60,8 @@ EXPORTS = [
     "lmpo_arena_bytes", "lmpo_create", "lmpo_evolve_step", "lmpo_trace", "lmpo_renormalize",
     "lmpo_measure_1q", "lmpo_measure_2q", "lmpo_bond_dims", "lmpo_discarded_weight", "lmpo_sync",
     "lmpo_destroy", "lmpo_last_error", "lmpo_get_site", "lmpo_set_site", "lmpo_set_centre",
-    "lmpo_get_centre", "lmpo_get_gate", "lmpo_apply_gate", "lmpo_last_spectrum",
+    "lmpo_get_centre", "lmpo_get_gate", "lmpo_apply_gate", "lmpo_last_spectrum", "lmpo_svd_stats",
+    "lmpo_svd_profile",
 ]
 
 
@@ -97,6 +98,8 @@ def load_library(path: str = LIB_PATH):
         "lmpo_get_gate": (ctypes.c_int, [P, i32, i32, pdbl]),
         "lmpo_apply_gate": (ctypes.c_int, [P, i32, i32, i32]),
         "lmpo_last_spectrum": (ctypes.c_int, [P, i32, pdbl, pi32, pi32]),
+        "lmpo_svd_stats": (ctypes.c_int, [P, pi32]),
+        "lmpo_svd_profile": (ctypes.c_int, [P, pdbl]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -269,6 +272,20 @@ class Chain:
         kept = np.zeros(1, dtype=np.int32)
         _check(self._lib.lmpo_last_spectrum(self._h, n, _dptr(sv), _iptr(nsv), _iptr(kept)))
         return sv[: int(nsv[0])], int(kept[0])
+
+    def svd_stats(self):
+        """(last sweeps, last column count, total sweeps, total SVDs incl. hops)."""
+        out = np.zeros(4, dtype=np.int32)
+        _check(self._lib.lmpo_svd_stats(self._h, _iptr(out)))
+        return tuple(int(x) for x in out)
+
+    def svd_profile(self):
+        """Accumulated microseconds per persistent-SVD phase (first workgroup)."""
+        out = np.zeros(12)
+        _check(self._lib.lmpo_svd_profile(self._h, _dptr(out)))
+        names = ["setup", "pairs", "wait", "cycles", "-", "select", "epilogue", "launches", "gram", "eig",
+                 "upd_x", "upd_v"]
+        return dict(zip(names, out.tolist()))
 
     def close(self):
         if getattr(self, "_h", None):
