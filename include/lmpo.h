@@ -166,6 +166,15 @@ int lmpo_svd_stats(lmpo_state *s, int32_t out[4]);
  * [9] eigen sweep, [10] X update, [11] V update.  Synchronises. */
 int lmpo_svd_profile(lmpo_state *s, double out_us[12]);
 
+/* Profiling window for the persistent SVD kernel (one launch per truncated
+ * SVD or centre hop).  Between begin and end, HIP events bracket every such
+ * launch on the state's stream (at most max_launches; more is an error at
+ * end) and each launch adds its declared flop count 4 (14 R C^2 + 8 C^3)
+ * for its R x C block (R >= C) to a device counter.  end synchronises and
+ * returns out = (launches, summed kernel milliseconds, summed declared flops). */
+int lmpo_profile_begin(lmpo_state *s, int32_t max_launches);
+int lmpo_profile_end(lmpo_state *s, double out[3]);
+
 #ifdef __cplusplus
 }
 #endif

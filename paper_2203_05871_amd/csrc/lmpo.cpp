@@ -65,15 +65,23 @@ struct lmpo_state {
   int *d_dims = nullptr;
   double2 *d_gates = nullptr;
   double2 *X = nullptr, *V = nullptr, *W = nullptr, *Z = nullptr, *T = nullptr;
-  int *act = nullptr;
+  int *act = nullptr, *cmap = nullptr;
+  double *cnorm = nullptr;
   int *sweep_cnt = nullptr, *stats = nullptr, *perm = nullptr, *kept = nullptr, *err = nullptr, *req = nullptr;
   unsigned *bar = nullptr;
   unsigned long long *tprof = nullptr;
+  double *alg_flops = nullptr;
+  // optional profiling window: HIP events around every persistent SVD launch
+  bool profiling = false;
+  std::vector<hipEvent_t> ev;  // pairs (start, stop)
+  size_t ev_used = 0;
+  bool ev_overflow = false;
   int grid = 1;                 // largest co-resident grid of the persistent SVD
   int *dims_pinned = nullptr;   // asynchronous copy of the bond dims (grid sizing only)
   hipEvent_t dims_ready = nullptr;
   std::vector<int> dims_est;    // bond dims as of the last completed step
   ~lmpo_state() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
     if (dims_ready) (void)hipEventDestroy(dims_ready);
     if (dims_pinned) (void)hipHostFree(dims_pinned);
   }
@@ -177,6 +185,8 @@ size_t layout(lmpo_state *S, const Sizes &z, int N, int nb, char *base, size_t s
   const size_t slots = (size_t)(nbp - 1) * (nbp / 2);
   S->W = a.take<double2>(2 * slots * JP * JP);
   S->act = a.take<int>(2 * slots);
+  S->cmap = a.take<int>((size_t)nbp * JB);
+  S->cnorm = a.take<double>(z.max_cols);
   S->Z = a.take<double2>(z.z_elems);
   S->T = a.take<double2>(z.t_elems);
   S->sig = a.take<double>(z.max_cols);
@@ -186,6 +196,7 @@ size_t layout(lmpo_state *S, const Sizes &z, int N, int nb, char *base, size_t s
   S->stats = a.take<int>(kStats);
   S->bar = a.take<unsigned>(8 * 32 + 64);
   S->tprof = a.take<unsigned long long>(16);
+  S->alg_flops = a.take<double>(1);
   S->kept = a.take<int>(1);
   S->err = a.take<int>(1);
   S->disc = a.take<double>(1);
@@ -266,6 +277,8 @@ SvdLaunch svd_args(lmpo_state *S, int mode, int k, int asc) {
   L.V = S->V;
   L.W = S->W;
   L.act = S->act;
+  L.cmap = S->cmap;
+  L.cnorm = S->cnorm;
   L.Z = S->Z;
   L.T = S->T;
   L.sweep_cnt = S->sweep_cnt;
@@ -278,6 +291,7 @@ SvdLaunch svd_args(lmpo_state *S, int mode, int k, int asc) {
   L.disc = S->disc;
   L.bar = S->bar;
   L.tprof = S->tprof;
+  L.alg_flops = S->alg_flops;
   return L;
 }
 
@@ -302,6 +316,22 @@ void refresh_estimates(lmpo_state *S) {
     std::copy(S->dims_pinned, S->dims_pinned + (S->N - 1), S->dims_est.begin());
 }
 
+int launch_svd(lmpo_state *S, const SvdLaunch &L, int grid) {
+  hipEvent_t *pair = nullptr;
+  if (S->profiling) {
+    if (S->ev_used + 2 <= S->ev.size()) {
+      pair = &S->ev[S->ev_used];
+      S->ev_used += 2;
+    } else {
+      S->ev_overflow = true;
+    }
+  }
+  if (pair) HIP_TRY(hipEventRecord(pair[0], S->stream));
+  HIP_TRY(launch_svd_persistent(S->stream, L, grid));
+  if (pair) HIP_TRY(hipEventRecord(pair[1], S->stream));
+  return LMPO_OK;
+}
+
 // Exact move of the orthogonality centre by one site (SVD-based QR / LQ).
 int hop(lmpo_state *S, int c, bool right) {
   int R, C;
@@ -312,8 +342,7 @@ int hop(lmpo_state *S, int c, bool right) {
     R = 4 * (c == S->N - 1 ? 1 : est(S, c));
     C = est(S, c - 1);
   }
-  HIP_TRY(launch_svd_persistent(S->stream, svd_args(S, right ? 1 : 2, c, 0), grid_for(S, R, C)));
-  return LMPO_OK;
+  return launch_svd(S, svd_args(S, right ? 1 : 2, c, 0), grid_for(S, R, C));
 }
 
 int move_centre(lmpo_state *S, int to) {
@@ -337,7 +366,8 @@ int apply_gate(lmpo_state *S, int k, int half, int asc) {
                        S->X);
   HIP_TRY(hipGetLastError());
   const int r = 4 * (k == 0 ? 1 : est(S, k - 1)), c = 4 * (k + 1 == S->N - 1 ? 1 : est(S, k + 1));
-  HIP_TRY(launch_svd_persistent(S->stream, svd_args(S, 0, k, asc), grid_for(S, std::max(r, c), std::min(r, c))));
+  rc = launch_svd(S, svd_args(S, 0, k, asc), grid_for(S, std::max(r, c), std::min(r, c)));
+  if (rc) return rc;
   S->centre = asc ? k + 1 : k;
   return LMPO_OK;
 }
@@ -688,6 +718,39 @@ int lmpo_svd_profile(lmpo_state *S, double out_us[12]) {
   for (int i = 0; i < 12; ++i) out_us[i] = khz > 0 ? (double)t[i] * 1e3 / khz : 0.0;
   out_us[7] = (double)t[7];
   out_us[3] = (double)t[12];  // shader clock cycles of the first workgroup (whole kernels)
+  return LMPO_OK;
+}
+
+int lmpo_profile_begin(lmpo_state *S, int32_t max_launches) {
+  if (!S || max_launches < 1) return fail(LMPO_EINVAL, "null state or max_launches < 1");
+  while (S->ev.size() < 2 * (size_t)max_launches) {
+    hipEvent_t e;
+    HIP_TRY(hipEventCreate(&e));
+    S->ev.push_back(e);
+  }
+  HIP_TRY(hipMemsetAsync(S->alg_flops, 0, sizeof(double), S->stream));
+  S->ev_used = 0;
+  S->ev_overflow = false;
+  S->profiling = true;
+  return LMPO_OK;
+}
+
+int lmpo_profile_end(lmpo_state *S, double out[3]) {
+  if (!S || !out) return fail(LMPO_EINVAL, "null argument");
+  S->profiling = false;
+  HIP_TRY(hipStreamSynchronize(S->stream));
+  double ms = 0.0;
+  for (size_t i = 0; i + 1 < S->ev_used; i += 2) {
+    float t = 0.f;
+    HIP_TRY(hipEventElapsedTime(&t, S->ev[i], S->ev[i + 1]));
+    ms += t;
+  }
+  double flops = 0.0;
+  HIP_TRY(hipMemcpy(&flops, S->alg_flops, sizeof(double), hipMemcpyDeviceToHost));
+  out[0] = (double)(S->ev_used / 2);
+  out[1] = ms;
+  out[2] = flops;
+  if (S->ev_overflow) return fail(LMPO_EINVAL, "more SVD launches than max_launches in the profiling window");
   return LMPO_OK;
 }
 

@@ -42,12 +42,15 @@ struct SvdLaunch {
   int *dims;
   double2 *X, *V, *W, *Z, *T;
   int *act;
+  int *cmap;
+  double *cnorm;
   int *sweep_cnt;
   double *sig, *sorted;
   int *perm, *kept, *err, *stats;
   double *disc;
   unsigned *bar;
   unsigned long long *tprof;
+  double *alg_flops;
 };
 int svd_grid_size();
 hipError_t launch_svd_persistent(hipStream_t s, const SvdLaunch &L, int grid);

@@ -91,6 +91,19 @@ struct Barrier {
   }
 };
 
+// 1/sqrt(x) and 1/x from the hardware estimates plus Newton steps (to ~1 ulp;
+// x > 0 normal).
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * fma(-0.5 * x * y, y, 1.5);
+  return y * fma(-0.5 * x * y, y, 1.5);
+}
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = y * fma(-x, y, 2.0);
+  return y * fma(-x, y, 2.0);
+}
+
 // LDS ordering among the lanes of one wavefront: its LDS operations execute in
 // order, so a compiler fence plus a wait for outstanding LDS traffic suffices.
 __device__ __forceinline__ void wave_sync() {
@@ -214,7 +227,7 @@ __device__ __forceinline__ void rotate_staged(SharedPair &s, const double2 (*W)[
 // does all of it, so a round needs a single grid barrier.  Returns whether the
 // pair was rotated (some off-diagonal above threshold).
 __device__ bool pair_work(SharedPair &s, double2 *__restrict__ X, int ldx, int R, double2 *__restrict__ Wout,
-                          int C, int bi, int bj, double tol, unsigned long long *tp) {
+                          int C, int bi, int bj, double tol, const int *__restrict__ cmap, unsigned long long *tp) {
   const int t = threadIdx.x;
   unsigned long long tm = wall_clock64();
   auto mark = [&](int slot) {
@@ -226,7 +239,7 @@ __device__ bool pair_work(SharedPair &s, double2 *__restrict__ X, int ldx, int R
   };
   if (t < JP) {
     int c = (t < JB) ? bi * JB + t : bj * JB + (t - JB);
-    s.col[t] = (c < C) ? c : -1;
+    s.col[t] = (c < C) ? cmap[c] : -1;
   }
   __syncthreads();
   const int a = t / JP, b = t % JP;
@@ -301,13 +314,14 @@ __device__ bool pair_work(SharedPair &s, double2 *__restrict__ X, int ldx, int R
         const double mc2 = c.x * c.x + c.y * c.y;
         s_pt[p] = q;
         s_pt[q] = p;
-        if (mc2 > tol2 * (app * aqq) && mc2 > 0.0) {
+        if (mc2 > tol2 * (app * aqq) && mc2 > 1e-290) {  // (normal range for the rsq estimates)
           // zero g_pq: x_p' = cs x_p - sn e^{-i phi} x_q, x_q' = sn x_p + cs e^{-i phi} x_q
           // (an FP32 tangent here costs ~2.6x more sweeps: keep FP64)
-          const double inv = rsqrt(mc2);
+          const double inv = rsq_nr(mc2);
           const double zeta = 0.5 * (aqq - app) * inv;
-          const double tt = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-          const double cs = rsqrt(1.0 + tt * tt), sn = tt * cs;
+          const double r2 = fma(zeta, zeta, 1.0);
+          const double tt = copysign(rcp_nr(fabs(zeta) + r2 * rsq_nr(r2)), zeta);
+          const double cs = rsq_nr(fma(tt, tt, 1.0)), sn = tt * cs;
           const double2 ph = make_double2(c.x * inv, -c.y * inv);
           s_al[p] = make_double2(cs, 0.0);
           s_be[p] = make_double2(-sn * ph.x, -sn * ph.y);
@@ -360,7 +374,8 @@ __device__ bool pair_work(SharedPair &s, double2 *__restrict__ X, int ldx, int R
 // independently, so workgroups take row blocks of V into LDS and apply every
 // recorded pair rotation of the sweep in round order; no grid barrier needed.
 __device__ void sweep_update_v(SharedPair &s, double2 *__restrict__ V, int ldv, int C, int nbp,
-                               const double2 *__restrict__ Wsw, const int *__restrict__ act, int G) {
+                               const double2 *__restrict__ Wsw, const int *__restrict__ act, int G,
+                               const int *__restrict__ cmap) {
   const int npairs = nbp / 2;
   double2 *vs = &s.xs[0][0];  // h rows x C columns, row-major, h * C <= kChunk * (JP + 1)
   int h = (kChunk * (JP + 1)) / C;
@@ -387,11 +402,11 @@ __device__ void sweep_update_v(SharedPair &s, double2 *__restrict__ V, int ldv, 
         for (int kk = 0; kk < 4; ++kk) {
           const int q = 4 * kk + lk;
           const int c = (q < JB) ? bi * JB + q : bj * JB + (q - JB);
-          cq[kk] = c < C ? c : -1;
+          cq[kk] = c < C ? cmap[c] : -1;
           w[kk] = W[q * JP + lr];
         }
         const int cj0 = (lr < JB) ? bi * JB + lr : bj * JB + (lr - JB);
-        const int cj = cj0 < C ? cj0 : -1;
+        const int cj = cj0 < C ? cmap[cj0] : -1;
         d4 yr = {0, 0, 0, 0}, yi = {0, 0, 0, 0};
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk) {
@@ -416,6 +431,41 @@ __device__ void sweep_update_v(SharedPair &s, double2 *__restrict__ V, int ldv, 
       V[(size_t)(r0 + i) + (size_t)c * ldv] = vs[e];
     }
   }
+}
+
+// cmap[0..C) = physical columns sorted by decreasing squared norm (ties by
+// index); cmap[C..n) = identity (padding columns).
+__device__ void order_columns(SharedSelect &s, const double *__restrict__ nrm, int C, int n, int *__restrict__ cmap) {
+  const int t = threadIdx.x;
+  int n2 = 2;
+  while (n2 < C) n2 <<= 1;
+  for (int e = t; e < n2; e += NT) {
+    s.key[e] = (e < C) ? nrm[e] : -1.0;
+    s.idx[e] = e;
+  }
+  __syncthreads();
+  for (int size = 2; size <= n2; size <<= 1) {
+    for (int stride = size >> 1; stride > 0; stride >>= 1) {
+      for (int e = t; e < n2; e += NT) {
+        int partner = e ^ stride;
+        if (partner > e) {
+          bool desc = ((e & size) == 0);
+          double ka = s.key[e], kb = s.key[partner];
+          int ia = s.idx[e], ib = s.idx[partner];
+          bool a_first = (ka > kb) || (ka == kb && ia < ib);
+          if (desc ? !a_first : a_first) {
+            s.key[e] = kb;
+            s.key[partner] = ka;
+            s.idx[e] = ib;
+            s.idx[partner] = ia;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  for (int e = t; e < n; e += NT) cmap[e] = (e < C) ? s.idx[e] : e;
+  __syncthreads();
 }
 
 __device__ void block_select(SharedSelect &s, const double *__restrict__ sig, int C, int chi_max, double cutoff,
@@ -505,12 +555,15 @@ struct SvdArgs {
   int *dims;
   double2 *X, *V, *W, *Z, *T;  // W: [2][rounds][pairs][JP][JP] rotations of the last two sweeps
   int *act;        // [2][rounds][pairs] pair rotated?
+  int *cmap;       // [nbp * JB] sweep order of the physical columns (sorted by norm)
+  double *cnorm;   // [C] squared column norms at the start of a sweep
   int *sweep_cnt;  // [max_sweeps]
   double *sig, *sorted;
   int *perm, *kept, *err, *stats;
   double *disc;
   unsigned *bar;  // [8 * 32 + 64]
   unsigned long long *tprof;  // [8] accumulated wall-clock ticks per phase (workgroup 0)
+  double *alg_flops;          // accumulated declared SVD flops (Golub-Van Loan count)
 };
 
 __global__ __launch_bounds__(NT) void svd_persistent_kernel(SvdArgs a) {
@@ -589,12 +642,32 @@ __global__ __launch_bounds__(NT) void svd_persistent_kernel(SvdArgs a) {
   for (int sweep = 0; sweep < a.max_sweeps; ++sweep) {
     double2 *Wsw = a.W + (size_t)(sweep & 1) * wsw_stride * JP * JP;
     int *act = a.act + (size_t)(sweep & 1) * wsw_stride;
+    // order the columns by decreasing norm for this sweep (blocks then hold
+    // columns of similar size, which speeds up convergence on graded spectra)
+    for (int j = blockIdx.x; j < C; j += G) {
+      double acc = 0.0;
+      for (int i = threadIdx.x; i < R; i += NT) {
+        double2 v = a.X[(size_t)i + (size_t)j * ldx];
+        acc = fma(v.x, v.x, fma(v.y, v.y, acc));
+      }
+      sh.red[threadIdx.x] = acc;
+      __syncthreads();
+      for (int off = NT / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh.red[threadIdx.x] += sh.red[threadIdx.x + off];
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) a.cnorm[j] = sh.red[0];
+      __syncthreads();
+    }
+    bar.sync();
+    if (blockIdx.x == 0) order_columns(sh.sel, a.cnorm, C, nbp * JB, a.cmap);
+    bar.sync();
     for (int round = 0; round < nbp - 1; ++round) {
       for (int p = blockIdx.x; p < npairs; p += G) {
         int bi, bj;
         pair_blocks(round, p, nbp, bi, bj);
         const size_t slot = (size_t)round * npairs + p;
-        bool active = pair_work(sh.pair, a.X, ldx, R, Wsw + slot * JP * JP, C, bi, bj, tol,
+        bool active = pair_work(sh.pair, a.X, ldx, R, Wsw + slot * JP * JP, C, bi, bj, tol, a.cmap,
                                 (a.tprof && blockIdx.x == 0) ? a.tprof : nullptr);
         if (threadIdx.x == 0) {
           act[slot] = active ? 1 : 0;
@@ -608,7 +681,7 @@ __global__ __launch_bounds__(NT) void svd_persistent_kernel(SvdArgs a) {
     }
     sweeps = sweep + 1;
     if (__hip_atomic_load(&a.sweep_cnt[sweep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) break;
-    sweep_update_v(sh.pair, a.V, ldv, C, nbp, Wsw, act, G);
+    sweep_update_v(sh.pair, a.V, ldv, C, nbp, Wsw, act, G, a.cmap);
     lap(11);
   }
   bar.sync();
@@ -631,6 +704,12 @@ __global__ __launch_bounds__(NT) void svd_persistent_kernel(SvdArgs a) {
   bar.sync();
   int *dslot = (a.mode == 2) ? a.dims + (site - 1) : a.dims + site;
   if (blockIdx.x == 0) {
+    if (threadIdx.x == 0 && a.alg_flops) {
+      // declared cost of a thin complex SVD of an R x C block (R >= C):
+      // 4 (14 R C^2 + 8 C^3) real flops (Golub & Van Loan, Golub-Reinsch count)
+      const double rr = R, cc = C;
+      *a.alg_flops += 4.0 * (14.0 * rr * cc * cc + 8.0 * cc * cc * cc);
+    }
     if (threadIdx.x == 0 && a.stats) {
       a.stats[0] = sweeps;
       a.stats[1] = C;
@@ -806,6 +885,8 @@ hipError_t launch_svd_persistent(hipStream_t s, const SvdLaunch &L, int grid) {
   a.V = L.V;
   a.W = L.W;
   a.act = L.act;
+  a.cmap = L.cmap;
+  a.cnorm = L.cnorm;
   a.Z = L.Z;
   a.T = L.T;
   a.sweep_cnt = L.sweep_cnt;
@@ -818,6 +899,7 @@ hipError_t launch_svd_persistent(hipStream_t s, const SvdLaunch &L, int grid) {
   a.disc = L.disc;
   a.bar = L.bar;
   a.tprof = L.tprof;
+  a.alg_flops = L.alg_flops;
   hipError_t e = hipMemsetAsync(L.bar, 0, (8 * 32 + 64) * sizeof(unsigned), s);
   if (e != hipSuccess) return e;
   void *args[] = {&a};

@@ -61,7 +61,7 @@ EXPORTS = [
     "lmpo_measure_1q", "lmpo_measure_2q", "lmpo_bond_dims", "lmpo_discarded_weight", "lmpo_sync",
     "lmpo_destroy", "lmpo_last_error", "lmpo_get_site", "lmpo_set_site", "lmpo_set_centre",
     "lmpo_get_centre", "lmpo_get_gate", "lmpo_apply_gate", "lmpo_last_spectrum", "lmpo_svd_stats",
-    "lmpo_svd_profile",
+    "lmpo_svd_profile", "lmpo_profile_begin", "lmpo_profile_end",
 ]
 
 
@@ -100,6 +100,8 @@ def load_library(path: str = LIB_PATH):
         "lmpo_last_spectrum": (ctypes.c_int, [P, i32, pdbl, pi32, pi32]),
         "lmpo_svd_stats": (ctypes.c_int, [P, pi32]),
         "lmpo_svd_profile": (ctypes.c_int, [P, pdbl]),
+        "lmpo_profile_begin": (ctypes.c_int, [P, i32]),
+        "lmpo_profile_end": (ctypes.c_int, [P, pdbl]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -286,6 +288,15 @@ class Chain:
         names = ["setup", "pairs", "wait", "cycles", "-", "select", "epilogue", "launches", "gram", "eig",
                  "upd_x", "upd_v"]
         return dict(zip(names, out.tolist()))
+
+    def profile_begin(self, max_launches=20000):
+        _check(self._lib.lmpo_profile_begin(self._h, int(max_launches)))
+
+    def profile_end(self):
+        """(SVD launches, summed kernel ms from HIP events, summed declared flops)."""
+        out = np.zeros(3)
+        _check(self._lib.lmpo_profile_end(self._h, _dptr(out)))
+        return int(out[0]), float(out[1]), float(out[2])
 
     def close(self):
         if getattr(self, "_h", None):
