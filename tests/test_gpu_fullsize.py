@@ -1,0 +1,191 @@
+"""GPU parity at full size and on edge cases, through the C ABI.
+
+Full size: a random canonical MPS at chi = 256 is injected (N = 10, so the
+middle gate sees a 1024 x 1024 two-site block, as in the chi = 256 chain);
+one gate is applied on the GPU and by the oracle; the singular values, the
+kept rank and the observables after the gate must agree.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import model as lm
+from oracle import tebd
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def Chain():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2203_05871_amd import Chain, load_library
+
+    load_library()
+    return Chain
+
+
+def random_canonical_mps(dims, centre, seed, centre_decay=0.0):
+    """Pauli-basis site tensors with bond dims `dims`: sites < centre left-,
+    sites > centre right-orthonormal, the centre Gaussian (singular values
+    reshaped to decay as exp(-decay j) when decay > 0)."""
+    rng = np.random.default_rng(seed)
+    N = len(dims) + 1
+    A = []
+    for k in range(N):
+        cl = 1 if k == 0 else dims[k - 1]
+        cr = 1 if k == N - 1 else dims[k]
+        t = rng.standard_normal((cl, 4, cr)) + 1j * rng.standard_normal((cl, 4, cr))
+        if k < centre:
+            q, _ = np.linalg.qr(t.reshape(cl * 4, cr))
+            t = q.reshape(cl, 4, cr)
+        elif k > centre:
+            q, _ = np.linalg.qr(t.reshape(cl, 4 * cr).T)
+            t = q.T.reshape(cl, 4, cr)
+        elif centre_decay > 0:
+            u, s, vh = np.linalg.svd(t.reshape(cl * 4, cr), full_matrices=False)
+            s = np.exp(-centre_decay * np.arange(len(s)))
+            t = ((u * s) @ vh).reshape(cl, 4, cr)
+        A.append(t)
+    return A
+
+
+def inject(ch, A, centre):
+    for k, t in enumerate(A):
+        ch.set_site(k, t)
+    ch.set_centre(centre)
+
+
+def one_gate_parity(Chain, dims, bond, chi_max, cutoff, seed, decay=0.0, asc=True, half=True, tau=0.05):
+    N = len(dims) + 1
+    m = workloads.jittered_chain(N, seed)
+    A = random_canonical_mps(dims, bond, seed, decay)
+    ch = Chain(m, tau, chi_max, cutoff, "fp64", "+z")
+    inject(ch, A, bond)
+    ch.apply_gate(bond, half, asc)
+    sv, kept = ch.last_spectrum()
+    ref = tebd.MPS(tebd.from_pauli(A), centre=bond)
+    G = lm.bond_gate(m, bond, (0.5 if half else 1.0) * tau)
+    kk, s = ref.apply_gate(bond, G, chi_max, cutoff, asc)
+    return ch, ref, sv, kept, kk, s
+
+
+@pytest.mark.parametrize("decay", [0.0, 0.02])
+def test_full_size_gate_1024(Chain, decay):
+    dims = [4, 16, 64, 256, 256, 256, 64, 16, 4]  # N = 10; bond 4 joins two chi = 256 bonds
+    ch, ref, sv, kept, kk, s = one_gate_parity(Chain, dims, 4, 256, 1e-10, 3, decay)
+    assert len(sv) == 1024 and len(s) == 1024
+    assert kept == kk
+    # singular values: relative agreement where they carry weight
+    big = s > 1e-12 * s[0]
+    np.testing.assert_allclose(sv[big], s[big], rtol=1e-10, atol=1e-13 * s[0])
+    assert ch.bond_dims() == ref.bond_dims()
+    for i in (0, 3, 4, 5, 9):
+        g = ch.measure_1q([i], "Z")[0]
+        r = ref.expect({i: lm.SZ})
+        assert abs(g - r) < 1e-10, (i, g, r)
+    g = ch.measure_2q([2], [7], ["XY"])[0]
+    assert abs(g - ref.expect({2: lm.SX, 7: lm.SY})) < 1e-10
+    ch.close()
+
+
+@pytest.mark.parametrize("asc", [True, False])
+def test_ragged_gate_both_directions(Chain, asc):
+    """Bond dims that are not multiples of any tile: 37, 53, 29."""
+    dims = [4, 16, 37, 53, 29, 16, 4]  # N = 8
+    ch, ref, sv, kept, kk, s = one_gate_parity(Chain, dims, 3, 64, 1e-12, 5, 0.05, asc=asc)
+    assert kept == kk
+    big = s > 1e-12 * s[0]
+    np.testing.assert_allclose(sv[big], s[big], rtol=1e-10, atol=1e-13 * s[0])
+    for i in range(8):
+        assert abs(ch.measure_1q([i], "Z")[0] - ref.expect({i: lm.SZ})) < 1e-10
+    # the next gate needs a centre hop (and it is exact)
+    nb = 5 if asc else 1
+    G = lm.bond_gate(ch_model(8, 5), nb, 0.05)
+    ref.apply_gate(nb, G, 64, 1e-12, asc)
+    ch.apply_gate(nb, 0, asc)
+    for i in range(8):
+        assert abs(ch.measure_1q([i], "X")[0] - ref.expect({i: lm.SX})) < 1e-10
+    ch.close()
+
+
+def ch_model(N, seed):
+    return workloads.jittered_chain(N, seed)
+
+
+def test_c2_parity_sampled(Chain):
+    """N=20, chi_max=128, cutoff 1e-12, tau=0.05: first 20 steps, every 5."""
+    m, run = workloads.c2()
+    ch = Chain(m, run["tau"], run["chi_max"], run["cutoff"], "fp64", run["init"])
+    ref = tebd.MPS.product(run["init"], m["N"])
+    gates = tebd.gate_tables(m, run["tau"])
+    worst = 0.0
+    for n in range(0, 20, 5):
+        ch.evolve(5)
+        tebd.evolve(ref, m, run["tau"], 5, run["chi_max"], run["cutoff"], gates=gates, first_step=n)
+        sites = [0, 1, 5, 10, 19]
+        z = ch.measure_1q(sites, "Z")
+        y = ch.measure_1q(sites, "Y")
+        zr = [ref.expect({i: lm.SZ}) for i in sites]
+        yr = [ref.expect({i: lm.SY}) for i in sites]
+        worst = max(worst, np.abs(z - zr).max(), np.abs(y - yr).max())
+        zz = ch.measure_2q([0, 1, 3], [1, 5, 17], "ZZ")
+        zzr = [ref.expect({i: lm.SZ, j: lm.SZ}) for i, j in ((0, 1), (1, 5), (3, 17))]
+        worst = max(worst, np.abs(zz - zzr).max())
+    assert worst < 1e-10
+    assert ch.bond_dims() == ref.bond_dims()
+    ch.close()
+
+
+def test_determinism(Chain):
+    """Two identical runs are bitwise equal (no races in LDS / grid phases)."""
+    m = workloads.jittered_chain(10, 2)
+    outs = []
+    for _ in range(2):
+        ch = Chain(m, 0.05, 24, 1e-12, "fp64", "+x")
+        ch.evolve(8)
+        outs.append(np.concatenate([ch.measure_1q(np.arange(10), "X"), ch.measure_1q(np.arange(10), "Z")]))
+        dims = ch.bond_dims()
+        ch.close()
+    assert np.array_equal(outs[0], outs[1])
+    assert max(dims) == 24
+
+
+def test_two_site_chain_and_chi_one(Chain):
+    """N = 2 (a single bond) and chi_max = 1 (product-state truncation)."""
+    m = workloads.random_model(2, 4)
+    ch = Chain(m, 0.1, 4, 0.0, "fp64", "-y")
+    ref = tebd.MPS.product("-y", 2)
+    ch.evolve(5)
+    tebd.evolve(ref, m, 0.1, 5, 4, 0.0)
+    for i in range(2):
+        for P, O in (("X", lm.SX), ("Y", lm.SY), ("Z", lm.SZ)):
+            assert abs(ch.measure_1q([i], P)[0] - ref.expect({i: O})) < 1e-12
+    ch.close()
+    m = workloads.jittered_chain(6, 1)
+    ch = Chain(m, 0.05, 1, 0.0, "fp64", "+x")
+    ref = tebd.MPS.product("+x", 6)
+    ch.evolve(3)
+    tebd.evolve(ref, m, 0.05, 3, 1, 0.0)
+    assert ch.bond_dims() == [1] * 5
+    z = ch.measure_1q(np.arange(6), "Z")
+    assert np.abs(z - [ref.expect({i: lm.SZ}) for i in range(6)]).max() < 1e-12
+    ch.close()
+
+
+def test_error_paths(Chain):
+    from paper_2203_05871_amd import LmpoError
+
+    m = workloads.jittered_chain(5, 0)
+    with pytest.raises(LmpoError, match="Pauli"):
+        Chain(m, 0.05, 8, 0.0, "fp64", "+q")
+    ch = Chain(m, 0.05, 8, 0.0, "fp64", "+z")
+    with pytest.raises(LmpoError, match="i != j"):
+        ch.measure_2q([1], [1], ["ZZ"])
+    with pytest.raises(LmpoError, match="range"):
+        ch.measure_1q([7], "Z")
+    with pytest.raises(LmpoError, match="X, Y, Z"):
+        ch.measure_1q([0], "Q")
+    ch.close()
