@@ -61,13 +61,13 @@ inline void check_launch() { (void)hipGetLastError(); }
 //         trans = 1 -> X = theta^H, column-major, ld = 4 chr.
 // ---------------------------------------------------------------------------
 template <typename T>
-__global__ __launch_bounds__(256) void contract_gate_kernel(double2 *const *sites, const int *dims, int N, int k,
-                                                            const double2 *__restrict__ G,
-                                                            double2 *__restrict__ X) {
+__device__ __forceinline__ void contract_body(double2 *const *sites, const int *dims, int N, int k,
+                                              const double2 *__restrict__ G, double2 *__restrict__ X,
+                                              const int bx, const int by) {
   using C2 = cplx<T>;
   const int chl = (k == 0) ? 1 : dims[k - 1], chm = dims[k], chr = (k + 1 == N - 1) ? 1 : dims[k + 1];
   const int trans = (4 * chl >= 4 * chr) ? 0 : 1;
-  if ((int)blockIdx.y * 16 >= chl || (int)blockIdx.x * 16 >= chr) return;
+  if (by * 16 >= chl || bx * 16 >= chr) return;
   const double2 *__restrict__ Ak = sites[k];
   const double2 *__restrict__ Ak1 = sites[k + 1];
   __shared__ C2 As[16][64];
@@ -75,7 +75,7 @@ __global__ __launch_bounds__(256) void contract_gate_kernel(double2 *const *site
   __shared__ C2 Ms[64][65];
   __shared__ C2 Gs[16][16];
   const int t = threadIdx.x;
-  const int l0 = blockIdx.y * 16, r0 = blockIdx.x * 16;
+  const int l0 = by * 16, r0 = bx * 16;
   const int ty = t / 16, tx = t % 16;
   const int R = 4 * chl;
   {
@@ -145,6 +145,20 @@ __global__ __launch_bounds__(256) void contract_gate_kernel(double2 *const *site
   }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void contract_gate_kernel(double2 *const *sites, const int *dims, int N, int k,
+                                                            const double2 *__restrict__ G,
+                                                            double2 *__restrict__ X) {
+  contract_body<T>(sites, dims, N, k, G, X, blockIdx.x, blockIdx.y);
+}
+
+// Batched form: job blockIdx.z of a device array of independent contractions.
+template <typename T>
+__global__ __launch_bounds__(256) void contract_gate_batched_kernel(const ContractJob *__restrict__ jobs) {
+  const ContractJob j = jobs[blockIdx.z];
+  contract_body<T>(j.sites, j.dims, j.N, j.k, j.G, j.X, blockIdx.x, blockIdx.y);
+}
+
 void launch_contract_gate(hipStream_t s, int precision, double2 *const *sites, const int *dims, int N, int k,
                           int cap_l, int cap_r, const double2 *G, double2 *X) {
   dim3 grid((cap_r + 15) / 16, (cap_l + 15) / 16);
@@ -152,6 +166,17 @@ void launch_contract_gate(hipStream_t s, int precision, double2 *const *sites, c
     hipLaunchKernelGGL(contract_gate_kernel<float>, grid, dim3(256), 0, s, sites, dims, N, k, G, X);
   else
     hipLaunchKernelGGL(contract_gate_kernel<double>, grid, dim3(256), 0, s, sites, dims, N, k, G, X);
+  check_launch();
+}
+
+void launch_contract_batched(hipStream_t s, int precision, const ContractJob *d_jobs, int n_jobs, int cap_l,
+                             int cap_r) {
+  if (n_jobs <= 0) return;
+  dim3 grid((cap_r + 15) / 16, (cap_l + 15) / 16, n_jobs);
+  if (precision == LMPO_FP32_CONTRACT)
+    hipLaunchKernelGGL(contract_gate_batched_kernel<float>, grid, dim3(256), 0, s, d_jobs);
+  else
+    hipLaunchKernelGGL(contract_gate_batched_kernel<double>, grid, dim3(256), 0, s, d_jobs);
   check_launch();
 }
 

@@ -29,6 +29,16 @@ constexpr int JP = 2 * JB;
 constexpr int kMaxDim = 2048;  // largest block side (4 chi) the sort handles
 
 // ---- kernel launchers (kernels.hip, svd.hip) ----
+// One two-site contraction (for the batched launch).
+struct ContractJob {
+  double2 *const *sites;
+  const int *dims;
+  int N, k;
+  const double2 *G;
+  double2 *X;
+};
+void launch_contract_batched(hipStream_t s, int precision, const ContractJob *d_jobs, int n_jobs, int cap_l,
+                             int cap_r);
 void launch_contract_gate(hipStream_t s, int precision, double2 *const *sites, const int *dims, int N, int k,
                           int cap_l, int cap_r, const double2 *G, double2 *X);
 
@@ -54,6 +64,11 @@ struct SvdLaunch {
 };
 int svd_grid_size();
 hipError_t launch_svd_persistent(hipStream_t s, const SvdLaunch &L, int grid);
+// One cooperative launch over many independent SvdLaunch problems (device
+// array d_args); workgroup b serves problem d_block_group[b].  The callers
+// zero every participating problem's barrier block beforehand.
+hipError_t launch_svd_batched(hipStream_t s, const SvdLaunch *d_args, const int *d_block_group,
+                              const int *d_group_first, int total_blocks);
 
 void launch_trace(hipStream_t s, double2 *const *sites, const int *dims, int N, double2 *out);
 void launch_env_all(hipStream_t s, double2 *const *sites, const int *dims, int N, int cap,

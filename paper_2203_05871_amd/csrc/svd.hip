@@ -54,7 +54,8 @@ struct Barrier {
   unsigned *top;
   unsigned *flag;
   int *err;       // set to 2 if a wait ever exceeds its spin limit
-  unsigned G;
+  unsigned G;     // workgroups taking part
+  unsigned rank;  // this workgroup's index among them
   unsigned phase;
   // Every thread's global writes before the barrier are visible to every
   // workgroup after it: the workgroup barrier orders this block's stores,
@@ -65,7 +66,7 @@ struct Barrier {
     if (threadIdx.x == 0) {
       __threadfence();
       const unsigned target = ++phase;
-      const unsigned g = blockIdx.x & 7u;
+      const unsigned g = rank & 7u;
       const unsigned ngrp = G < 8u ? G : 8u;
       const unsigned members = (G - g + 7u) / 8u;
       unsigned old = atomicAdd(&grp[g * 32], 1u);
@@ -375,14 +376,14 @@ __device__ bool pair_work(SharedPair &s, double2 *__restrict__ X, int ldx, int R
 // recorded pair rotation of the sweep in round order; no grid barrier needed.
 __device__ void sweep_update_v(SharedPair &s, double2 *__restrict__ V, int ldv, int C, int nbp,
                                const double2 *__restrict__ Wsw, const int *__restrict__ act, int G,
-                               const int *__restrict__ cmap) {
+                               const int *__restrict__ cmap, int rank) {
   const int npairs = nbp / 2;
   double2 *vs = &s.xs[0][0];  // h rows x C columns, row-major, h * C <= kChunk * (JP + 1)
   int h = (kChunk * (JP + 1)) / C;
   h = h >= 16 ? 16 : (h >= 8 ? 8 : 4);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  for (int r0 = blockIdx.x * h; r0 < C; r0 += G * h) {
+  for (int r0 = rank * h; r0 < C; r0 += G * h) {
     const int nr = min(h, C - r0);
     __syncthreads();
     for (int e = threadIdx.x; e < h * C; e += NT) {
@@ -547,32 +548,17 @@ __device__ void block_select(SharedSelect &s, const double *__restrict__ sig, in
 
 }  // namespace
 
-struct SvdArgs {
-  int mode;  // 0: gate on bond k; 1: hop right from site k; 2: hop left from site k
-  int k, N, asc, chi_max, max_sweeps;
-  double cutoff, tol_factor;
-  double2 *const *sites;
-  int *dims;
-  double2 *X, *V, *W, *Z, *T;  // W: [2][rounds][pairs][JP][JP] rotations of the last two sweeps
-  int *act;        // [2][rounds][pairs] pair rotated?
-  int *cmap;       // [nbp * JB] sweep order of the physical columns (sorted by norm)
-  double *cnorm;   // [C] squared column norms at the start of a sweep
-  int *sweep_cnt;  // [max_sweeps]
-  double *sig, *sorted;
-  int *perm, *kept, *err, *stats;
-  double *disc;
-  unsigned *bar;  // [8 * 32 + 64]
-  unsigned long long *tprof;  // [8] accumulated wall-clock ticks per phase (workgroup 0)
-  double *alg_flops;          // accumulated declared SVD flops (Golub-Van Loan count)
-};
 
-__global__ __launch_bounds__(NT) void svd_persistent_kernel(SvdArgs a) {
-  __shared__ SharedAll sh;
+
+// The whole truncated SVD / centre hop, run by G cooperating workgroups (this
+// one has index `rank`); group-local barriers only, so independent problems
+// can share one launch.
+__device__ void svd_body(const SvdLaunch &a, const unsigned rank, const unsigned G_, SharedAll &sh) {
   // phase timers (workgroup 0, thread 0): 0 setup, 1 pair Gram+eig, 2 wait after A,
   // 3 update, 4 wait after B, 5 norms+select, 6 epilogue, 7 launches
   unsigned long long tmark = wall_clock64();
   const unsigned long long cyc0 = clock64();
-  const bool prof = a.tprof && blockIdx.x == 0 && threadIdx.x == 0;
+  const bool prof = a.tprof && rank == 0 && threadIdx.x == 0;
   auto lap = [&](int slot) {
     if (prof) {
       unsigned long long now = wall_clock64();
@@ -581,9 +567,9 @@ __global__ __launch_bounds__(NT) void svd_persistent_kernel(SvdArgs a) {
     }
   };
   if (prof) a.tprof[7] += 1;
-  Barrier bar{a.bar, a.bar + 8 * 32, a.bar + 8 * 32 + 32, a.err, gridDim.x, 0u};
-  const int G = gridDim.x;
-  const size_t gtid = (size_t)blockIdx.x * NT + threadIdx.x, gstride = (size_t)G * NT;
+  Barrier bar{a.bar, a.bar + 8 * 32, a.bar + 8 * 32 + 32, a.err, G_, rank, 0u};
+  const int G = (int)G_;
+  const size_t gtid = (size_t)rank * NT + threadIdx.x, gstride = (size_t)G * NT;
   const int N = a.N;
   auto dimL = [&](int s) { return s == 0 ? 1 : a.dims[s - 1]; };
   auto dimR = [&](int s) { return s == N - 1 ? 1 : a.dims[s]; };
@@ -644,7 +630,7 @@ __global__ __launch_bounds__(NT) void svd_persistent_kernel(SvdArgs a) {
     int *act = a.act + (size_t)(sweep & 1) * wsw_stride;
     // order the columns by decreasing norm for this sweep (blocks then hold
     // columns of similar size, which speeds up convergence on graded spectra)
-    for (int j = blockIdx.x; j < C; j += G) {
+    for (int j = rank; j < C; j += G) {
       double acc = 0.0;
       for (int i = threadIdx.x; i < R; i += NT) {
         double2 v = a.X[(size_t)i + (size_t)j * ldx];
@@ -660,15 +646,15 @@ __global__ __launch_bounds__(NT) void svd_persistent_kernel(SvdArgs a) {
       __syncthreads();
     }
     bar.sync();
-    if (blockIdx.x == 0) order_columns(sh.sel, a.cnorm, C, nbp * JB, a.cmap);
+    if (rank == 0) order_columns(sh.sel, a.cnorm, C, nbp * JB, a.cmap);
     bar.sync();
     for (int round = 0; round < nbp - 1; ++round) {
-      for (int p = blockIdx.x; p < npairs; p += G) {
+      for (int p = rank; p < npairs; p += G) {
         int bi, bj;
         pair_blocks(round, p, nbp, bi, bj);
         const size_t slot = (size_t)round * npairs + p;
         bool active = pair_work(sh.pair, a.X, ldx, R, Wsw + slot * JP * JP, C, bi, bj, tol, a.cmap,
-                                (a.tprof && blockIdx.x == 0) ? a.tprof : nullptr);
+                                (a.tprof && rank == 0) ? a.tprof : nullptr);
         if (threadIdx.x == 0) {
           act[slot] = active ? 1 : 0;
           if (active) atomicAdd(&a.sweep_cnt[sweep], 1);
@@ -681,12 +667,12 @@ __global__ __launch_bounds__(NT) void svd_persistent_kernel(SvdArgs a) {
     }
     sweeps = sweep + 1;
     if (__hip_atomic_load(&a.sweep_cnt[sweep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) break;
-    sweep_update_v(sh.pair, a.V, ldv, C, nbp, Wsw, act, G, a.cmap);
+    sweep_update_v(sh.pair, a.V, ldv, C, nbp, Wsw, act, G, a.cmap, rank);
     lap(11);
   }
   bar.sync();
   // ---- column norms ----
-  for (int j = blockIdx.x; j < C; j += G) {
+  for (int j = rank; j < C; j += G) {
     double acc = 0.0;
     for (int i = threadIdx.x; i < R; i += NT) {
       double2 v = a.X[(size_t)i + (size_t)j * ldx];
@@ -703,7 +689,7 @@ __global__ __launch_bounds__(NT) void svd_persistent_kernel(SvdArgs a) {
   }
   bar.sync();
   int *dslot = (a.mode == 2) ? a.dims + (site - 1) : a.dims + site;
-  if (blockIdx.x == 0) {
+  if (rank == 0) {
     if (threadIdx.x == 0 && a.alg_flops) {
       // declared cost of a thin complex SVD of an R x C block (R >= C):
       // 4 (14 R C^2 + 8 C^3) real flops (Golub & Van Loan, Golub-Reinsch count)
@@ -806,7 +792,7 @@ __global__ __launch_bounds__(NT) void svd_persistent_kernel(SvdArgs a) {
   const int M = right ? k : 4 * chl, Nn = right ? 4 * chr : k, K = C;
   const int lda = K, ldb = Nn;
   const int tiles_m = (M + 63) / 64, tiles_n = (Nn + 63) / 64;
-  for (int tile = blockIdx.x; tile < tiles_m * tiles_n; tile += G) {
+  for (int tile = rank; tile < tiles_m * tiles_n; tile += G) {
     const int i0 = (tile / tiles_n) * 64, j0 = (tile % tiles_n) * 64;
     const int t = threadIdx.x, ty = t / 16, tx = t % 16;
     double2 acc[4][4];
@@ -854,6 +840,25 @@ __global__ __launch_bounds__(NT) void svd_persistent_kernel(SvdArgs a) {
   if (prof) a.tprof[12] += clock64() - cyc0;
 }
 
+__global__ __launch_bounds__(NT) void svd_persistent_kernel(SvdLaunch a) {
+  __shared__ SharedAll sh;
+  svd_body(a, blockIdx.x, gridDim.x, sh);
+}
+
+// Many independent problems in one cooperative launch: workgroup b belongs to
+// group block_group[b], whose workgroups are group_first[g] .. group_first[g+1]-1.
+// Groups with mode < 0 have nothing to do in this launch.
+__global__ __launch_bounds__(NT) void svd_batched_kernel(const SvdLaunch *__restrict__ args,
+                                                         const int *__restrict__ block_group,
+                                                         const int *__restrict__ group_first) {
+  __shared__ SharedAll sh;
+  const int g = block_group[blockIdx.x];
+  const SvdLaunch a = args[g];
+  if (a.mode < 0) return;
+  const int first = group_first[g];
+  svd_body(a, blockIdx.x - first, group_first[g + 1] - first, sh);
+}
+
 static int g_grid = 0;
 
 int svd_grid_size() {
@@ -870,41 +875,19 @@ int svd_grid_size() {
 }
 
 hipError_t launch_svd_persistent(hipStream_t s, const SvdLaunch &L, int grid) {
-  SvdArgs a;
-  a.mode = L.mode;
-  a.k = L.k;
-  a.N = L.N;
-  a.asc = L.asc;
-  a.chi_max = L.chi_max;
-  a.max_sweeps = L.max_sweeps;
-  a.cutoff = L.cutoff;
-  a.tol_factor = L.tol_factor;
-  a.sites = L.sites;
-  a.dims = L.dims;
-  a.X = L.X;
-  a.V = L.V;
-  a.W = L.W;
-  a.act = L.act;
-  a.cmap = L.cmap;
-  a.cnorm = L.cnorm;
-  a.Z = L.Z;
-  a.T = L.T;
-  a.sweep_cnt = L.sweep_cnt;
-  a.sig = L.sig;
-  a.sorted = L.sorted;
-  a.perm = L.perm;
-  a.kept = L.kept;
-  a.err = L.err;
-  a.stats = L.stats;
-  a.disc = L.disc;
-  a.bar = L.bar;
-  a.tprof = L.tprof;
-  a.alg_flops = L.alg_flops;
   hipError_t e = hipMemsetAsync(L.bar, 0, (8 * 32 + 64) * sizeof(unsigned), s);
   if (e != hipSuccess) return e;
+  SvdLaunch a = L;
   void *args[] = {&a};
   return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(svd_persistent_kernel), dim3(grid), dim3(NT), args,
                                     0, s);
+}
+
+hipError_t launch_svd_batched(hipStream_t s, const SvdLaunch *d_args, const int *d_block_group,
+                              const int *d_group_first, int total_blocks) {
+  void *args[] = {(void *)&d_args, (void *)&d_block_group, (void *)&d_group_first};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(svd_batched_kernel), dim3(total_blocks), dim3(NT),
+                                    args, 0, s);
 }
 
 }  // namespace lmpo
