@@ -175,6 +175,49 @@ int lmpo_svd_profile(lmpo_state *s, double out_us[12]);
 int lmpo_profile_begin(lmpo_state *s, int32_t max_launches);
 int lmpo_profile_end(lmpo_state *s, double out[3]);
 
+/* ---- batched form: many independent chains in one launch per layer ----
+ *
+ * A batch groups existing states (each from lmpo_create, all on the same
+ * stream, possibly of different N, models, chi_max, cutoff and precision) and
+ * advances them together: every Trotter layer of every chain runs in one
+ * cooperative launch in which each chain is served by its own group of
+ * workgroups that walks the chain's gates (and centre hops) in the same order
+ * and with the same arithmetic as lmpo_evolve_step, so each chain's result is
+ * the one lmpo_evolve_step gives.  The co-resident grid is split between the
+ * chains by a cost model of the Jacobi SVD (more workgroups to chains with
+ * larger bond dimensions), and a chain's workgroups are placed on one XCD
+ * where they fit.
+ *
+ * The chains stay owned by the caller and usable through the single-chain
+ * calls (measure, trace, bond dims, ...) after lmpo_batch_sync; they must not
+ * be destroyed before the batch.  The batch needs a second device arena of
+ * lmpo_batch_arena_bytes() bytes (256-byte aligned, caller-owned).  At most
+ * one workgroup per compute unit per chain is available: n_chains above the
+ * co-resident grid gives LMPO_EUNSUPPORTED. */
+typedef struct lmpo_batch lmpo_batch;
+
+size_t lmpo_batch_arena_bytes(lmpo_state *const *chains, int32_t n_chains);
+int lmpo_batch_create(lmpo_state *const *chains, int32_t n_chains, void *device_arena, size_t arena_bytes,
+                      lmpo_batch **out);
+
+/* Enqueue n_steps Trotter steps of every chain (asynchronous).  Each chain
+ * continues from its own step count and centre, as lmpo_evolve_step would. */
+int lmpo_batch_evolve_step(lmpo_batch *b, int32_t n_steps);
+
+/* Wait for the batch's work; reports the first chain with a deferred error. */
+int lmpo_batch_sync(lmpo_batch *b);
+
+/* Workgroups per chain in the current plan (n_chains entries). */
+int lmpo_batch_plan(lmpo_batch *b, int32_t *workgroups);
+
+/* Profiling window over the per-layer launches, as lmpo_profile_begin/_end:
+ * out = (launches, summed kernel milliseconds, summed declared SVD flops of
+ * all chains). */
+int lmpo_batch_profile_begin(lmpo_batch *b, int32_t max_launches);
+int lmpo_batch_profile_end(lmpo_batch *b, double out[3]);
+
+int lmpo_batch_destroy(lmpo_batch *b);
+
 #ifdef __cplusplus
 }
 #endif

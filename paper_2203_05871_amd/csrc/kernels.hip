@@ -3,28 +3,13 @@
 // Complex numbers are double2 (x = re, y = im), interleaved in memory.
 // Site tensors A[l][a][r] are row-major; the two-site block theta and the
 // SVD work matrix X are column-major.
+#include "contract_tile.h"
 #include "lmpo_internal.h"
 
 namespace lmpo {
 
 namespace {
 
-template <typename T>
-struct cplx {
-  T x, y;
-};
-
-template <typename T>
-__device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
-  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
-}
-template <typename T>
-__device__ __forceinline__ void cfma(cplx<T> &acc, cplx<T> a, cplx<T> b) {
-  acc.x = fma(a.x, b.x, acc.x);
-  acc.x = fma(-a.y, b.y, acc.x);
-  acc.y = fma(a.x, b.y, acc.y);
-  acc.y = fma(a.y, b.x, acc.y);
-}
 __device__ __forceinline__ double2 dmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
@@ -48,115 +33,12 @@ inline void check_launch() { (void)hipGetLastError(); }
 
 }  // namespace
 
-// ---------------------------------------------------------------------------
-// Two-site contraction with the gate (north_star steps "contract the two-site
-// block" and "apply the propagator"):
-//   M[(l,s),(t,r)] = sum_m A_k[l][s][m] A_{k+1}[m][t][r]
-//   theta[(l,s'),(t',r)] = sum_{s,t} G[(s' t'),(s t)] M[(l,s),(t,r)]
-// A workgroup owns 16 values of l and 16 of r, i.e. a 64 x 64 tile of M with
-// all four s and all four t, so the 16x16 gate is applied in the epilogue
-// from LDS.  T is the arithmetic type (double, or float for the FP32
-// contraction form: operands rounded to FP32, FP32 accumulation).
-// Output: trans = 0 -> X = theta, column-major, ld = 4 chl;
-//         trans = 1 -> X = theta^H, column-major, ld = 4 chr.
-// ---------------------------------------------------------------------------
-template <typename T>
-__device__ __forceinline__ void contract_body(double2 *const *sites, const int *dims, int N, int k,
-                                              const double2 *__restrict__ G, double2 *__restrict__ X,
-                                              const int bx, const int by) {
-  using C2 = cplx<T>;
-  const int chl = (k == 0) ? 1 : dims[k - 1], chm = dims[k], chr = (k + 1 == N - 1) ? 1 : dims[k + 1];
-  const int trans = (4 * chl >= 4 * chr) ? 0 : 1;
-  if (by * 16 >= chl || bx * 16 >= chr) return;
-  const double2 *__restrict__ Ak = sites[k];
-  const double2 *__restrict__ Ak1 = sites[k + 1];
-  __shared__ C2 As[16][64];
-  __shared__ C2 Bs[16][64];
-  __shared__ C2 Ms[64][65];
-  __shared__ C2 Gs[16][16];
-  const int t = threadIdx.x;
-  const int l0 = by * 16, r0 = bx * 16;
-  const int ty = t / 16, tx = t % 16;
-  const int R = 4 * chl;
-  {
-    double2 g = G[t];
-    Gs[t / 16][t % 16] = C2{(T)g.x, (T)g.y};
-  }
-  C2 acc[4][4];
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = C2{0, 0};
-  for (int m0 = 0; m0 < chm; m0 += 16) {
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      int e = t + 256 * q;
-      int row = e / 16, kk = e % 16;
-      int gr = l0 * 4 + row, gm = m0 + kk;
-      double2 v = make_double2(0, 0);
-      if (gr < R && gm < chm) v = Ak[(size_t)gr * chm + gm];
-      As[kk][row] = C2{(T)v.x, (T)v.y};
-      int kb = e / 64, j = e % 64;
-      int gmb = m0 + kb, r = r0 + (j % 16);
-      double2 w = make_double2(0, 0);
-      if (gmb < chm && r < chr) w = Ak1[(size_t)gmb * 4 * chr + (j / 16) * chr + r];
-      Bs[kb][j] = C2{(T)w.x, (T)w.y};
-    }
-    __syncthreads();
-#pragma unroll 4
-    for (int kk = 0; kk < 16; ++kk) {
-      C2 a[4], b[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty * 4 + i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx * 4 + j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) cfma(acc[i][j], a[i], b[j]);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) Ms[ty * 4 + i][tx * 4 + j] = acc[i][j];
-  __syncthreads();
-  // epilogue: thread -> (l, r); 16 outputs (s', t')
-  const int li = t / 16, ri = t % 16;
-  const int l = l0 + li, r = r0 + ri;
-  if (l >= chl || r >= chr) return;
-  C2 m[16];
-#pragma unroll
-  for (int s = 0; s < 4; ++s)
-#pragma unroll
-    for (int tt = 0; tt < 4; ++tt) m[4 * s + tt] = Ms[li * 4 + s][tt * 16 + ri];
-#pragma unroll
-  for (int o = 0; o < 16; ++o) {
-    C2 out{0, 0};
-#pragma unroll
-    for (int q = 0; q < 16; ++q) cfma(out, Gs[o][q], m[q]);
-    const int sp = o / 4, tp = o % 4;
-    const size_t row = (size_t)l * 4 + sp, col = (size_t)tp * chr + r;
-    if (trans == 0)
-      X[row + col * (size_t)(4 * chl)] = make_double2((double)out.x, (double)out.y);
-    else
-      X[col + row * (size_t)(4 * chr)] = make_double2((double)out.x, -(double)out.y);
-  }
-}
-
 template <typename T>
 __global__ __launch_bounds__(256) void contract_gate_kernel(double2 *const *sites, const int *dims, int N, int k,
                                                             const double2 *__restrict__ G,
                                                             double2 *__restrict__ X) {
-  contract_body<T>(sites, dims, N, k, G, X, blockIdx.x, blockIdx.y);
-}
-
-// Batched form: job blockIdx.z of a device array of independent contractions.
-template <typename T>
-__global__ __launch_bounds__(256) void contract_gate_batched_kernel(const ContractJob *__restrict__ jobs) {
-  const ContractJob j = jobs[blockIdx.z];
-  contract_body<T>(j.sites, j.dims, j.N, j.k, j.G, j.X, blockIdx.x, blockIdx.y);
+  __shared__ ContractLds<T> lds;
+  contract_tile<T>(lds, sites, dims, N, k, G, X, blockIdx.x, blockIdx.y);
 }
 
 void launch_contract_gate(hipStream_t s, int precision, double2 *const *sites, const int *dims, int N, int k,
@@ -166,17 +48,6 @@ void launch_contract_gate(hipStream_t s, int precision, double2 *const *sites, c
     hipLaunchKernelGGL(contract_gate_kernel<float>, grid, dim3(256), 0, s, sites, dims, N, k, G, X);
   else
     hipLaunchKernelGGL(contract_gate_kernel<double>, grid, dim3(256), 0, s, sites, dims, N, k, G, X);
-  check_launch();
-}
-
-void launch_contract_batched(hipStream_t s, int precision, const ContractJob *d_jobs, int n_jobs, int cap_l,
-                             int cap_r) {
-  if (n_jobs <= 0) return;
-  dim3 grid((cap_r + 15) / 16, (cap_l + 15) / 16, n_jobs);
-  if (precision == LMPO_FP32_CONTRACT)
-    hipLaunchKernelGGL(contract_gate_batched_kernel<float>, grid, dim3(256), 0, s, d_jobs);
-  else
-    hipLaunchKernelGGL(contract_gate_batched_kernel<double>, grid, dim3(256), 0, s, d_jobs);
   check_launch();
 }
 

@@ -767,3 +767,420 @@ int lmpo_svd_stats(lmpo_state *S, int32_t out[4]) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Batched form: many independent chains advance together, one cooperative
+// launch per Trotter layer.  Each chain keeps its own state (arena, gates,
+// buffers); the batch adds the per-layer tables, one barrier block per chain
+// and a plan that splits the co-resident grid between the chains.
+// ---------------------------------------------------------------------------
+namespace {
+constexpr int kMaxBatchBlocks = 4096;
+
+// Planning model of one persistent SVD of an R x C block on G workgroups,
+// in microseconds: sweeps x rounds x (pair tasks per workgroup x pair time +
+// barrier).  Only the split of the grid between chains depends on it.
+struct CostModel {
+  double pair_fixed = 6.0, pair_per_row = 0.03, bar_fixed = 2.0, bar_per_wg = 0.05;
+};
+
+int jacobi_pairs(int C) {
+  int nbp = (C + JB - 1) / JB;
+  nbp += nbp & 1;
+  if (nbp < 2) nbp = 2;
+  return nbp / 2;
+}
+
+double svd_cost(int R, int C, int G, const CostModel &m) {
+  if (R < C) std::swap(R, C);
+  const int npairs = jacobi_pairs(C), rounds = 2 * npairs - 1;
+  const double sweeps = 3.0 + 0.9 * std::log2((double)std::max(C, 2));
+  const double tb = G == 1 ? 0.2 : m.bar_fixed + m.bar_per_wg * G;
+  const int per_wg = (npairs + G - 1) / G;
+  return sweeps * rounds * (per_wg * (m.pair_fixed + m.pair_per_row * R) + tb);
+}
+}  // namespace
+
+struct lmpo_batch {
+  std::vector<lmpo_state *> ch;
+  hipStream_t stream = nullptr;
+  int n = 0, grid_max = 1;
+  CostModel model;
+  // device tables (caller's arena)
+  BatchChain *d_chains = nullptr;
+  int *d_block_group = nullptr, *d_block_rank = nullptr, *d_group_size = nullptr;
+  unsigned *d_bar = nullptr;
+  int *d_centre = nullptr, *d_dims = nullptr;
+  double2 *d_tr = nullptr;
+  double *d_flops = nullptr;
+  std::vector<int> dims_off;
+  int dims_total = 0;
+  // current plan
+  std::vector<int> gsize, block_group, block_rank;
+  int total_blocks = 0;
+  // pinned staging for table uploads and the bond-dim readback
+  char *stage = nullptr;
+  size_t stage_bytes = 0;
+  hipEvent_t stage_done = nullptr;
+  int *dims_pinned = nullptr;
+  hipEvent_t dims_ready = nullptr;
+  std::vector<int> dims_est;
+  // profiling window
+  bool profiling = false;
+  std::vector<hipEvent_t> ev;
+  size_t ev_used = 0;
+  bool ev_overflow = false;
+  ~lmpo_batch() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    if (stage_done) (void)hipEventDestroy(stage_done);
+    if (dims_ready) (void)hipEventDestroy(dims_ready);
+    if (stage) (void)hipHostFree(stage);
+    if (dims_pinned) (void)hipHostFree(dims_pinned);
+  }
+};
+
+namespace {
+
+size_t batch_layout(lmpo_batch *B, char *base, size_t size) {
+  Arena a{base, size};
+  B->d_chains = a.take<BatchChain>(B->n);
+  B->d_block_group = a.take<int>(kMaxBatchBlocks);
+  B->d_block_rank = a.take<int>(kMaxBatchBlocks);
+  B->d_group_size = a.take<int>(B->n);
+  B->d_bar = a.take<unsigned>((size_t)B->n * kBarWords);
+  B->d_centre = a.take<int>(B->n);
+  B->d_tr = a.take<double2>(B->n);
+  B->d_dims = a.take<int>(std::max(B->dims_total, 1));
+  B->d_flops = a.take<double>(B->n);
+  return a.used;
+}
+
+int batch_check_chains(lmpo_state *const *chains, int n) {
+  if (!chains || n < 1) return fail(LMPO_EINVAL, "need at least one chain");
+  if (n > kMaxBatchBlocks) return fail(LMPO_EUNSUPPORTED, "too many chains for one batch");
+  for (int c = 0; c < n; ++c) {
+    if (!chains[c]) return fail(LMPO_EINVAL, "null chain in batch");
+    if (chains[c]->stream != chains[0]->stream) return fail(LMPO_EINVAL, "all chains of a batch must share one stream");
+    for (int d = 0; d < c; ++d)
+      if (chains[d] == chains[c]) return fail(LMPO_EINVAL, "a chain appears twice in the batch");
+  }
+  return LMPO_OK;
+}
+
+// Bond dims used for planning: last known value plus a growth margin.
+int batch_est(const lmpo_batch *B, int c, int bond) {
+  const lmpo_state *S = B->ch[c];
+  if (bond < 0 || bond >= S->N - 1) return 1;
+  return std::min(S->cap[bond], B->dims_est[B->dims_off[c] + bond] + 8);
+}
+
+// Modelled time of one Trotter step of chain c on G workgroups: every gate
+// (even bonds twice) and about one centre hop per gate.
+double chain_cost(const lmpo_batch *B, int c, int G) {
+  const int N = B->ch[c]->N;
+  double t = 0.0;
+  for (int b = 0; b < N - 1; ++b) {
+    const int mult = (b % 2 == 0) ? 2 : 1;
+    const int l = b == 0 ? 1 : batch_est(B, c, b - 1), r = b + 1 == N - 1 ? 1 : batch_est(B, c, b + 1);
+    t += mult * (svd_cost(4 * l, 4 * r, G, B->model) + svd_cost(4 * l, batch_est(B, c, b), G, B->model));
+  }
+  return t;
+}
+
+int chain_max_pairs(const lmpo_batch *B, int c) {
+  const int N = B->ch[c]->N;
+  int p = 1;
+  for (int b = 0; b < N - 1; ++b) {
+    const int l = b == 0 ? 1 : batch_est(B, c, b - 1), r = b + 1 == N - 1 ? 1 : batch_est(B, c, b + 1);
+    p = std::max(p, jacobi_pairs(std::min(4 * l, 4 * r)));
+  }
+  return p;
+}
+
+// Split the co-resident grid: start from one workgroup per chain and give
+// the next workgroup to the chain with the longest modelled step while that
+// shortens it.  Then place each chain's workgroups on one XCD where they fit
+// (workgroup b runs on XCD b mod 8), so a chain's barrier and data traffic
+// stay within one L2.
+void batch_plan(lmpo_batch *B, std::vector<int> &gsize, std::vector<int> &bgroup, std::vector<int> &brank) {
+  const int n = B->n, budget = std::min(B->grid_max, kMaxBatchBlocks);
+  gsize.assign(n, 1);
+  std::vector<double> cost(n);
+  std::vector<int> maxg(n);
+  for (int c = 0; c < n; ++c) {
+    cost[c] = chain_cost(B, c, 1);
+    maxg[c] = chain_max_pairs(B, c);
+  }
+  int total = n;
+  while (total < budget) {
+    int worst = 0;
+    for (int c = 1; c < n; ++c)
+      if (cost[c] > cost[worst]) worst = c;
+    if (gsize[worst] >= maxg[worst]) break;
+    const double next = chain_cost(B, worst, gsize[worst] + 1);
+    if (next >= cost[worst]) break;
+    gsize[worst]++;
+    cost[worst] = next;
+    total++;
+  }
+  // XCD-aware placement
+  constexpr int kXcd = 8;
+  std::vector<std::vector<int>> slots(kXcd);
+  for (int b = total - 1; b >= 0; --b) slots[b % kXcd].push_back(b);  // popped in increasing order
+  std::vector<int> order(n);
+  for (int c = 0; c < n; ++c) order[c] = c;
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return gsize[x] > gsize[y]; });
+  bgroup.assign(total, -1);
+  brank.assign(total, 0);
+  for (int c : order) {
+    int need = gsize[c], rank = 0;
+    while (need > 0) {
+      int best = 0;
+      for (int x = 1; x < kXcd; ++x)
+        if (slots[x].size() > slots[best].size()) best = x;
+      // prefer an XCD that holds the whole group
+      for (int x = 0; x < kXcd; ++x)
+        if ((int)slots[x].size() >= need && slots[x].size() < slots[best].size()) best = x;
+      while (need > 0 && !slots[best].empty()) {
+        const int b = slots[best].back();
+        slots[best].pop_back();
+        bgroup[b] = c;
+        brank[b] = rank++;
+        --need;
+      }
+    }
+  }
+}
+
+// Upload through the pinned staging buffer (waits for its previous use).
+struct StageCopy {
+  void *dst;
+  const void *src;
+  size_t bytes;
+};
+int batch_upload(lmpo_batch *B, const std::vector<StageCopy> &copies) {
+  size_t need = 0;
+  for (const auto &c : copies) need += (c.bytes + 255) & ~size_t(255);
+  HIP_TRY(hipEventSynchronize(B->stage_done));
+  if (need > B->stage_bytes) {
+    if (B->stage) HIP_TRY(hipHostFree(B->stage));
+    B->stage = nullptr;
+    HIP_TRY(hipHostMalloc((void **)&B->stage, need, hipHostMallocDefault));
+    B->stage_bytes = need;
+  }
+  size_t off = 0;
+  for (const auto &c : copies) {
+    std::memcpy(B->stage + off, c.src, c.bytes);
+    HIP_TRY(hipMemcpyAsync(c.dst, B->stage + off, c.bytes, hipMemcpyHostToDevice, B->stream));
+    off += (c.bytes + 255) & ~size_t(255);
+  }
+  HIP_TRY(hipEventRecord(B->stage_done, B->stream));
+  return LMPO_OK;
+}
+
+void batch_refresh_estimates(lmpo_batch *B) {
+  if (B->dims_ready && hipEventQuery(B->dims_ready) == hipSuccess)
+    std::copy(B->dims_pinned, B->dims_pinned + B->dims_total, B->dims_est.begin());
+}
+
+// Re-plan from the current estimates; upload the tables if the plan changed.
+int batch_replan(lmpo_batch *B) {
+  std::vector<int> gs, bg, br;
+  batch_plan(B, gs, bg, br);
+  if (gs == B->gsize && bg == B->block_group && br == B->block_rank) return LMPO_OK;
+  B->gsize = gs;
+  B->block_group = bg;
+  B->block_rank = br;
+  B->total_blocks = (int)bg.size();
+  return batch_upload(B, {{B->d_group_size, gs.data(), gs.size() * sizeof(int)},
+                          {B->d_block_group, bg.data(), bg.size() * sizeof(int)},
+                          {B->d_block_rank, br.data(), br.size() * sizeof(int)}});
+}
+
+int batch_launch(lmpo_batch *B, int local_step, int j) {
+  hipEvent_t *pair = nullptr;
+  if (B->profiling) {
+    if (B->ev_used + 2 <= B->ev.size()) {
+      pair = &B->ev[B->ev_used];
+      B->ev_used += 2;
+    } else {
+      B->ev_overflow = true;
+    }
+  }
+  const int parity = j == 1 ? 1 : 0, half = j == 1 ? 0 : 1;
+  if (pair) HIP_TRY(hipEventRecord(pair[0], B->stream));
+  HIP_TRY(launch_batch_layer(B->stream, B->d_chains, B->d_block_group, B->d_block_rank, B->d_group_size,
+                             B->total_blocks, B->d_bar, (size_t)B->n * kBarWords, local_step, j, parity, half,
+                             j == 2 ? 1 : 0));
+  if (pair) HIP_TRY(hipEventRecord(pair[1], B->stream));
+  return LMPO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lmpo_batch_arena_bytes(lmpo_state *const *chains, int32_t n_chains) {
+  if (batch_check_chains(chains, n_chains) != LMPO_OK) return 0;
+  lmpo_batch tmp;
+  tmp.n = n_chains;
+  for (int c = 0; c < n_chains; ++c) tmp.dims_total += chains[c]->N - 1;
+  return batch_layout(&tmp, nullptr, 0) + 256;
+}
+
+int lmpo_batch_create(lmpo_state *const *chains, int32_t n_chains, void *device_arena, size_t arena_bytes,
+                      lmpo_batch **out) {
+  if (!out) return fail(LMPO_EINVAL, "out is null");
+  *out = nullptr;
+  int rc = batch_check_chains(chains, n_chains);
+  if (rc) return rc;
+  if (!device_arena) return fail(LMPO_EINVAL, "device_arena is null");
+  if (reinterpret_cast<uintptr_t>(device_arena) % 256) return fail(LMPO_EINVAL, "device_arena must be 256-byte aligned");
+  lmpo_batch *B = new lmpo_batch();
+  auto cleanup = [&](int code) {
+    delete B;
+    return code;
+  };
+  B->n = n_chains;
+  B->ch.assign(chains, chains + n_chains);
+  B->stream = chains[0]->stream;
+  B->dims_off.resize(n_chains);
+  for (int c = 0; c < n_chains; ++c) {
+    B->dims_off[c] = B->dims_total;
+    B->dims_total += chains[c]->N - 1;
+  }
+  const size_t need = batch_layout(B, reinterpret_cast<char *>(device_arena), arena_bytes);
+  if (need > arena_bytes) return cleanup(fail(LMPO_ENOMEM, "batch arena too small: need " + std::to_string(need) + " bytes"));
+  B->grid_max = batch_grid_size();
+  if (n_chains > B->grid_max)
+    return cleanup(fail(LMPO_EUNSUPPORTED, "more chains than co-resident workgroups (" + std::to_string(B->grid_max) + ")"));
+  hipError_t e = hipEventCreateWithFlags(&B->stage_done, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventRecord(B->stage_done, B->stream);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&B->dims_ready, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipHostMalloc((void **)&B->dims_pinned, std::max(B->dims_total, 1) * sizeof(int), hipHostMallocDefault);
+  if (e == hipSuccess) e = hipMemsetAsync(B->d_flops, 0, n_chains * sizeof(double), B->stream);
+  if (e != hipSuccess) return cleanup(fail(LMPO_EHIP, std::string("batch init: ") + hipGetErrorString(e)));
+  // estimates from the chains' current bond dims
+  B->dims_est.assign(std::max(B->dims_total, 1), 1);
+  for (int c = 0; c < n_chains; ++c) {
+    lmpo_state *S = chains[c];
+    if ((rc = sync_dims(S))) return cleanup(rc);
+    std::copy(S->dims.begin(), S->dims.end(), B->dims_est.begin() + B->dims_off[c]);
+  }
+  std::copy(B->dims_est.begin(), B->dims_est.begin() + B->dims_total, B->dims_pinned);
+  e = hipEventRecord(B->dims_ready, B->stream);
+  if (e != hipSuccess) return cleanup(fail(LMPO_EHIP, std::string("batch init: ") + hipGetErrorString(e)));
+  if ((rc = batch_replan(B))) return cleanup(rc);
+  *out = B;
+  return LMPO_OK;
+}
+
+int lmpo_batch_evolve_step(lmpo_batch *B, int32_t n_steps) {
+  if (!B) return fail(LMPO_EINVAL, "batch is null");
+  if (n_steps < 0) return fail(LMPO_EINVAL, "n_steps must be >= 0");
+  if (n_steps == 0) return LMPO_OK;
+  // per-call chain records: the chains may have been advanced on their own
+  // since the last call, so centre and step parity come from their states
+  std::vector<BatchChain> recs(B->n);
+  std::vector<int> centres(B->n);
+  for (int c = 0; c < B->n; ++c) {
+    lmpo_state *S = B->ch[c];
+    BatchChain &r = recs[c];
+    r.L = svd_args(S, 0, 0, 0);
+    r.L.bar = B->d_bar + (size_t)c * kBarWords;
+    r.L.alg_flops = B->d_flops + c;
+    r.gates = S->d_gates;
+    r.centre = B->d_centre + c;
+    r.tr = B->d_tr + c;
+    r.dims_out = B->d_dims + B->dims_off[c];
+    r.precision = S->opt.precision;
+    r.force_trace = S->opt.force_trace ? 1 : 0;
+    r.step_parity = (int)(S->step_index & 1);
+    centres[c] = S->centre;
+  }
+  int rc = batch_upload(B, {{B->d_chains, recs.data(), recs.size() * sizeof(BatchChain)},
+                            {B->d_centre, centres.data(), centres.size() * sizeof(int)}});
+  if (rc) return rc;
+  for (int s = 0; s < n_steps; ++s) {
+    batch_refresh_estimates(B);
+    if ((rc = batch_replan(B))) return rc;
+    for (int j = 0; j < 3; ++j)
+      if ((rc = batch_launch(B, s, j))) return rc;
+    if (hipEventQuery(B->dims_ready) != hipErrorNotReady) {
+      HIP_TRY(hipMemcpyAsync(B->dims_pinned, B->d_dims, B->dims_total * sizeof(int), hipMemcpyDeviceToHost, B->stream));
+      HIP_TRY(hipEventRecord(B->dims_ready, B->stream));
+    }
+  }
+  // host mirrors: the last layer (even bonds) ends ascending on the last even
+  // bond or descending on bond 0
+  for (int c = 0; c < B->n; ++c) {
+    lmpo_state *S = B->ch[c];
+    const long long last = S->step_index + n_steps - 1;
+    const bool asc = ((last + 2) & 1) == 0;
+    const int last_even = ((S->N - 2) / 2) * 2;
+    S->centre = asc ? last_even + 1 : 0;
+    S->step_index += n_steps;
+  }
+  return LMPO_OK;
+}
+
+int lmpo_batch_sync(lmpo_batch *B) {
+  if (!B) return fail(LMPO_EINVAL, "batch is null");
+  HIP_TRY(hipStreamSynchronize(B->stream));
+  for (int c = 0; c < B->n; ++c) {
+    int rc = check_err(B->ch[c]);
+    if (rc) return fail(rc, "chain " + std::to_string(c) + ": " + g_err);
+  }
+  return LMPO_OK;
+}
+
+int lmpo_batch_plan(lmpo_batch *B, int32_t *workgroups) {
+  if (!B || !workgroups) return fail(LMPO_EINVAL, "null argument");
+  for (int c = 0; c < B->n; ++c) workgroups[c] = B->gsize[c];
+  return LMPO_OK;
+}
+
+int lmpo_batch_profile_begin(lmpo_batch *B, int32_t max_launches) {
+  if (!B || max_launches < 1) return fail(LMPO_EINVAL, "null batch or max_launches < 1");
+  while (B->ev.size() < 2 * (size_t)max_launches) {
+    hipEvent_t e;
+    HIP_TRY(hipEventCreate(&e));
+    B->ev.push_back(e);
+  }
+  HIP_TRY(hipMemsetAsync(B->d_flops, 0, B->n * sizeof(double), B->stream));
+  B->ev_used = 0;
+  B->ev_overflow = false;
+  B->profiling = true;
+  return LMPO_OK;
+}
+
+int lmpo_batch_profile_end(lmpo_batch *B, double out[3]) {
+  if (!B || !out) return fail(LMPO_EINVAL, "null argument");
+  B->profiling = false;
+  HIP_TRY(hipStreamSynchronize(B->stream));
+  double ms = 0.0;
+  for (size_t i = 0; i + 1 < B->ev_used; i += 2) {
+    float t = 0.f;
+    HIP_TRY(hipEventElapsedTime(&t, B->ev[i], B->ev[i + 1]));
+    ms += t;
+  }
+  std::vector<double> f(B->n);
+  HIP_TRY(hipMemcpy(f.data(), B->d_flops, B->n * sizeof(double), hipMemcpyDeviceToHost));
+  double flops = 0.0;
+  for (double x : f) flops += x;
+  out[0] = (double)(B->ev_used / 2);
+  out[1] = ms;
+  out[2] = flops;
+  if (B->ev_overflow) return fail(LMPO_EINVAL, "more layer launches than max_launches in the profiling window");
+  return LMPO_OK;
+}
+
+int lmpo_batch_destroy(lmpo_batch *B) {
+  if (!B) return LMPO_OK;
+  hipError_t e = hipStreamSynchronize(B->stream);
+  delete B;
+  if (e != hipSuccess) return fail(LMPO_EHIP, std::string("batch destroy: ") + hipGetErrorString(e));
+  return LMPO_OK;
+}
+
+}  // extern "C"

@@ -29,16 +29,6 @@ constexpr int JP = 2 * JB;
 constexpr int kMaxDim = 2048;  // largest block side (4 chi) the sort handles
 
 // ---- kernel launchers (kernels.hip, svd.hip) ----
-// One two-site contraction (for the batched launch).
-struct ContractJob {
-  double2 *const *sites;
-  const int *dims;
-  int N, k;
-  const double2 *G;
-  double2 *X;
-};
-void launch_contract_batched(hipStream_t s, int precision, const ContractJob *d_jobs, int n_jobs, int cap_l,
-                             int cap_r);
 void launch_contract_gate(hipStream_t s, int precision, double2 *const *sites, const int *dims, int N, int k,
                           int cap_l, int cap_r, const double2 *G, double2 *X);
 
@@ -64,11 +54,26 @@ struct SvdLaunch {
 };
 int svd_grid_size();
 hipError_t launch_svd_persistent(hipStream_t s, const SvdLaunch &L, int grid);
-// One cooperative launch over many independent SvdLaunch problems (device
-// array d_args); workgroup b serves problem d_block_group[b].  The callers
-// zero every participating problem's barrier block beforehand.
-hipError_t launch_svd_batched(hipStream_t s, const SvdLaunch *d_args, const int *d_block_group,
-                              const int *d_group_first, int total_blocks);
+// Batched form: one chain of a batch as seen by the per-layer kernel.
+struct BatchChain {
+  SvdLaunch L;           // the chain's buffers (mode, k, asc set per op); L.bar is its barrier block
+  const double2 *gates;  // [nb][2][256]
+  int *centre;           // orthogonality centre, kept on the device between layers
+  double2 *tr;           // trace scratch
+  int *dims_out;         // copy of the bond dims after each layer (or null)
+  int precision;
+  int force_trace;       // renormalise after the step's last layer
+  int step_parity;       // parity of the chain's step count at local step 0
+};
+int batch_grid_size();
+// One cooperative launch running layer j of local step `local_step` of every
+// chain: workgroup b serves chain block_group[b] as its member block_rank[b]
+// of group_size[chain].  bar_base[0 .. bar_words) (all barrier blocks) is
+// zeroed first.
+hipError_t launch_batch_layer(hipStream_t s, const BatchChain *d_chains, const int *d_block_group,
+                              const int *d_block_rank, const int *d_group_size, int total_blocks, unsigned *bar_base,
+                              size_t bar_words, int local_step, int j, int parity, int half, int last_layer);
+constexpr size_t kBarWords = 8 * 32 + 64;  // one grid-barrier block
 
 void launch_trace(hipStream_t s, double2 *const *sites, const int *dims, int N, double2 *out);
 void launch_env_all(hipStream_t s, double2 *const *sites, const int *dims, int N, int cap,

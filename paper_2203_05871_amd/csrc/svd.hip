@@ -19,6 +19,7 @@
 // |g_pq| <= tol sqrt(g_pp g_qq): the columns are then orthogonal to working
 // accuracy relative to their own norms, which gives small singular values
 // to high relative accuracy.
+#include "contract_tile.h"
 #include "lmpo_internal.h"
 
 namespace lmpo {
@@ -62,6 +63,11 @@ struct Barrier {
   // thread 0 publishes them device-wide (agent-scope fence) and, after the
   // wait, acquires the other blocks' stores for the whole workgroup.
   __device__ void sync() {
+    if (G == 1u) {  // one workgroup: its own barrier orders its global traffic
+      __syncthreads();
+      ++phase;
+      return;
+    }
     __syncthreads();
     if (threadIdx.x == 0) {
       __threadfence();
@@ -553,7 +559,8 @@ __device__ void block_select(SharedSelect &s, const double *__restrict__ sig, in
 // The whole truncated SVD / centre hop, run by G cooperating workgroups (this
 // one has index `rank`); group-local barriers only, so independent problems
 // can share one launch.
-__device__ void svd_body(const SvdLaunch &a, const unsigned rank, const unsigned G_, SharedAll &sh) {
+__device__ void svd_body(const SvdLaunch &a, Barrier &bar, SharedAll &sh) {
+  const unsigned rank = bar.rank, G_ = bar.G;
   // phase timers (workgroup 0, thread 0): 0 setup, 1 pair Gram+eig, 2 wait after A,
   // 3 update, 4 wait after B, 5 norms+select, 6 epilogue, 7 launches
   unsigned long long tmark = wall_clock64();
@@ -567,12 +574,11 @@ __device__ void svd_body(const SvdLaunch &a, const unsigned rank, const unsigned
     }
   };
   if (prof) a.tprof[7] += 1;
-  Barrier bar{a.bar, a.bar + 8 * 32, a.bar + 8 * 32 + 32, a.err, G_, rank, 0u};
   const int G = (int)G_;
   const size_t gtid = (size_t)rank * NT + threadIdx.x, gstride = (size_t)G * NT;
   const int N = a.N;
-  auto dimL = [&](int s) { return s == 0 ? 1 : a.dims[s - 1]; };
-  auto dimR = [&](int s) { return s == N - 1 ? 1 : a.dims[s]; };
+  auto dimL = [&](int s) { return s == 0 ? 1 : ld_dim(a.dims + s - 1); };
+  auto dimR = [&](int s) { return s == N - 1 ? 1 : ld_dim(a.dims + s); };
   // ---- problem shape (read before any bond dimension is rewritten) ----
   int R, C, trans = 0, chl = 1, chm = 1, chr = 1, site = a.k;
   if (a.mode == 0) {
@@ -584,12 +590,12 @@ __device__ void svd_body(const SvdLaunch &a, const unsigned rank, const unsigned
     C = trans ? r : c;
   } else if (a.mode == 1) {
     chl = dimL(site);
-    chm = a.dims[site];
+    chm = ld_dim(a.dims + site);
     chr = dimR(site + 1);  // right dim of the neighbour
     R = 4 * chl;
     C = chm;
   } else {
-    chm = a.dims[site - 1];
+    chm = ld_dim(a.dims + site - 1);
     chr = dimR(site);
     chl = dimL(site - 1);  // left dim of the neighbour
     R = 4 * chr;
@@ -842,21 +848,125 @@ __device__ void svd_body(const SvdLaunch &a, const unsigned rank, const unsigned
 
 __global__ __launch_bounds__(NT) void svd_persistent_kernel(SvdLaunch a) {
   __shared__ SharedAll sh;
-  svd_body(a, blockIdx.x, gridDim.x, sh);
+  Barrier bar{a.bar, a.bar + 8 * 32, a.bar + 8 * 32 + 32, a.err, gridDim.x, blockIdx.x, 0u};
+  svd_body(a, bar, sh);
 }
 
-// Many independent problems in one cooperative launch: workgroup b belongs to
-// group block_group[b], whose workgroups are group_first[g] .. group_first[g+1]-1.
-// Groups with mode < 0 have nothing to do in this launch.
-__global__ __launch_bounds__(NT) void svd_batched_kernel(const SvdLaunch *__restrict__ args,
+// ---------------------------------------------------------------------------
+// Batched form: one cooperative launch runs one Trotter layer of many chains.
+// Workgroup b serves chain block_group[b] as member block_rank[b] of its
+// group_size[g] workgroups; the group walks the layer's gates in order, each
+// preceded by the centre hops that bring the orthogonality centre onto the
+// bond, as the single-chain executor does (the same device code per op).
+// The layer of chain g is the global layer 3 n_g + j with n_g = its step
+// count; it runs ascending when that index is even, i.e. when
+// step_parity[g] + local_step + j is even.  Bonds b = parity, parity + 2, ...
+// < N - 1 get exp(x L_b) with x = tau/2 (half) or tau.
+// ---------------------------------------------------------------------------
+union SharedBatch {
+  SharedAll all;
+  ContractLds<double> cd;
+  ContractLds<float> cf;
+  double2 env[2][kMaxDim / 4];
+};
+
+// tr(rho) by one workgroup: v <- sqrt(2) v A_i[:, 0, :] over the sites
+// (Tr P_a = sqrt(2) delta_{a0} in the normalised Pauli basis).
+__device__ double2 chain_trace(double2 *const *sites, const int *dims, int N, double2 (*env)[kMaxDim / 4]) {
+  const double s2 = 1.4142135623730951;
+  double2 *v0 = env[0], *v1 = env[1];
+  if (threadIdx.x == 0) v0[0] = make_double2(1.0, 0.0);
+  __syncthreads();
+  for (int i = 0; i < N; ++i) {
+    const int cl = i == 0 ? 1 : ld_dim(dims + i - 1), cr = i == N - 1 ? 1 : ld_dim(dims + i);
+    const double2 *A = sites[i];
+    for (int r = threadIdx.x; r < cr; r += NT) {
+      double2 acc = make_double2(0, 0);
+      for (int l = 0; l < cl; ++l) zfma(acc, v0[l], A[(size_t)l * 4 * cr + r]);
+      v1[r] = make_double2(acc.x * s2, acc.y * s2);
+    }
+    __syncthreads();
+    double2 *t = v0;
+    v0 = v1;
+    v1 = t;
+  }
+  return v0[0];
+}
+
+__global__ __launch_bounds__(NT) void batch_layer_kernel(const BatchChain *__restrict__ chains,
                                                          const int *__restrict__ block_group,
-                                                         const int *__restrict__ group_first) {
-  __shared__ SharedAll sh;
+                                                         const int *__restrict__ block_rank,
+                                                         const int *__restrict__ group_size, int local_step,
+                                                         int j, int parity, int half, int last_layer) {
+  __shared__ SharedBatch sh;
   const int g = block_group[blockIdx.x];
-  const SvdLaunch a = args[g];
-  if (a.mode < 0) return;
-  const int first = group_first[g];
-  svd_body(a, blockIdx.x - first, group_first[g + 1] - first, sh);
+  const unsigned rank = block_rank[blockIdx.x], G = group_size[g];
+  // the chain's launch record lives in LDS (mode, k, asc change per op)
+  __shared__ SvdLaunch L;
+  if (threadIdx.x == 0) L = chains[g].L;
+  __syncthreads();
+  const double2 *gates = chains[g].gates;
+  int *centre_p = chains[g].centre;
+  const int precision = chains[g].precision;
+  Barrier bar{L.bar, L.bar + 8 * 32, L.bar + 8 * 32 + 32, L.err, G, rank, 0u};
+  const int N = L.N;
+  const int asc = ((chains[g].step_parity + local_step + j) & 1) == 0;
+  int centre = ld_dim(centre_p);
+  const int nbonds = parity > N - 2 ? 0 : (N - 2 - parity) / 2 + 1;
+  // ops in order: for each bond of the layer, the hops that bring the centre
+  // onto it, then the gate; one svd_body call site serves both kinds
+  int q = 0;
+  while (q < nbonds) {
+    const int b = asc ? parity + 2 * q : parity + 2 * (nbonds - 1 - q);
+    const int target = centre <= b ? b : b + 1;
+    const bool gate = centre == target;
+    if (gate) {
+      const double2 *Gt = gates + ((size_t)b * 2 + (half ? 1 : 0)) * 256;
+      const int chl = b == 0 ? 1 : ld_dim(L.dims + b - 1), chr = b + 1 == N - 1 ? 1 : ld_dim(L.dims + b + 1);
+      const int tx = (chr + 15) / 16, ntiles = tx * ((chl + 15) / 16);
+      for (int t = rank; t < ntiles; t += G) {
+        if (precision == LMPO_FP32_CONTRACT)
+          contract_tile<float>(sh.cf, L.sites, L.dims, N, b, Gt, L.X, t % tx, t / tx);
+        else
+          contract_tile<double>(sh.cd, L.sites, L.dims, N, b, Gt, L.X, t % tx, t / tx);
+      }
+    }
+    if (threadIdx.x == 0) {
+      L.mode = gate ? 0 : (centre < target ? 1 : 2);
+      L.k = gate ? b : centre;
+      L.asc = gate ? asc : 0;
+    }
+    bar.sync();
+    svd_body(L, bar, sh.all);
+    bar.sync();
+    if (gate) {
+      centre = asc ? b + 1 : b;
+      ++q;
+    } else {
+      centre += centre < target ? 1 : -1;
+    }
+  }
+  if (last_layer && chains[g].force_trace) {
+    // rho <- rho / tr(rho): trace by the first workgroup, scaling of the
+    // centre site by all, with the single-chain kernels' arithmetic
+    if (rank == 0) {
+      const double2 tr = chain_trace(L.sites, L.dims, N, sh.env);
+      if (threadIdx.x == 0) *chains[g].tr = tr;
+    }
+    bar.sync();
+    const double2 z = chains[g].tr[0];
+    const double d = z.x * z.x + z.y * z.y;
+    const double2 inv = make_double2(z.x / d, -z.y / d);
+    const int cl = centre == 0 ? 1 : ld_dim(L.dims + centre - 1), cr = centre == N - 1 ? 1 : ld_dim(L.dims + centre);
+    double2 *A = L.sites[centre];
+    const size_t n = (size_t)cl * 4 * cr;
+    for (size_t e = (size_t)rank * NT + threadIdx.x; e < n; e += (size_t)G * NT) A[e] = zmul(A[e], inv);
+  }
+  if (rank == 0) {
+    if (threadIdx.x == 0) *centre_p = centre;
+    if (chains[g].dims_out)
+      for (int i = threadIdx.x; i < N - 1; i += NT) chains[g].dims_out[i] = ld_dim(L.dims + i);
+  }
 }
 
 static int g_grid = 0;
@@ -883,10 +993,24 @@ hipError_t launch_svd_persistent(hipStream_t s, const SvdLaunch &L, int grid) {
                                     0, s);
 }
 
-hipError_t launch_svd_batched(hipStream_t s, const SvdLaunch *d_args, const int *d_block_group,
-                              const int *d_group_first, int total_blocks) {
-  void *args[] = {(void *)&d_args, (void *)&d_block_group, (void *)&d_group_first};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(svd_batched_kernel), dim3(total_blocks), dim3(NT),
+int batch_grid_size() {
+  int dev = 0, cus = 0, occ = 0;
+  (void)hipGetDevice(&dev);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batch_layer_kernel, NT, 0);
+  if (cus <= 0) cus = 1;
+  if (occ <= 0) occ = 1;
+  return cus * occ;
+}
+
+hipError_t launch_batch_layer(hipStream_t s, const BatchChain *d_chains, const int *d_block_group,
+                              const int *d_block_rank, const int *d_group_size, int total_blocks, unsigned *bar_base,
+                              size_t bar_words, int local_step, int j, int parity, int half, int last_layer) {
+  hipError_t e = hipMemsetAsync(bar_base, 0, bar_words * sizeof(unsigned), s);
+  if (e != hipSuccess) return e;
+  void *args[] = {(void *)&d_chains, (void *)&d_block_group, (void *)&d_block_rank, (void *)&d_group_size,
+                  &local_step, &j, &parity, &half, &last_layer};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(batch_layer_kernel), dim3(total_blocks), dim3(NT),
                                     args, 0, s);
 }
 

@@ -62,6 +62,8 @@ EXPORTS = [
     "lmpo_destroy", "lmpo_last_error", "lmpo_get_site", "lmpo_set_site", "lmpo_set_centre",
     "lmpo_get_centre", "lmpo_get_gate", "lmpo_apply_gate", "lmpo_last_spectrum", "lmpo_svd_stats",
     "lmpo_svd_profile", "lmpo_profile_begin", "lmpo_profile_end",
+    "lmpo_batch_arena_bytes", "lmpo_batch_create", "lmpo_batch_evolve_step", "lmpo_batch_sync",
+    "lmpo_batch_plan", "lmpo_batch_profile_begin", "lmpo_batch_profile_end", "lmpo_batch_destroy",
 ]
 
 
@@ -102,6 +104,14 @@ def load_library(path: str = LIB_PATH):
         "lmpo_svd_profile": (ctypes.c_int, [P, pdbl]),
         "lmpo_profile_begin": (ctypes.c_int, [P, i32]),
         "lmpo_profile_end": (ctypes.c_int, [P, pdbl]),
+        "lmpo_batch_arena_bytes": (ctypes.c_size_t, [ctypes.POINTER(P), i32]),
+        "lmpo_batch_create": (ctypes.c_int, [ctypes.POINTER(P), i32, P, ctypes.c_size_t, ctypes.POINTER(P)]),
+        "lmpo_batch_evolve_step": (ctypes.c_int, [P, i32]),
+        "lmpo_batch_sync": (ctypes.c_int, [P]),
+        "lmpo_batch_plan": (ctypes.c_int, [P, pi32]),
+        "lmpo_batch_profile_begin": (ctypes.c_int, [P, i32]),
+        "lmpo_batch_profile_end": (ctypes.c_int, [P, pdbl]),
+        "lmpo_batch_destroy": (ctypes.c_int, [P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -301,6 +311,63 @@ class Chain:
     def close(self):
         if getattr(self, "_h", None):
             _check(self._lib.lmpo_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Many chains advanced together, one cooperative launch per Trotter layer
+    (lmpo_batch_*).  The chains stay usable for readouts after sync(); they
+    must share one stream and outlive the batch."""
+
+    def __init__(self, chains, device="cuda:0"):
+        import torch
+
+        lib = load_library()
+        self.chains = list(chains)
+        arr = (ctypes.c_void_p * len(self.chains))(*[c._h.value for c in self.chains])
+        self._arr = arr
+        n = lib.lmpo_batch_arena_bytes(arr, len(self.chains))
+        if n == 0:
+            raise LmpoError(-1, lib.lmpo_last_error().decode())
+        self.arena = torch.empty(n + 256, dtype=torch.uint8, device=device)
+        base = self.arena.data_ptr()
+        off = (-base) % 256
+        h = ctypes.c_void_p()
+        _check(lib.lmpo_batch_create(arr, len(self.chains), ctypes.c_void_p(base + off), ctypes.c_size_t(n),
+                                     ctypes.byref(h)))
+        self._h = h
+        self._lib = lib
+
+    def evolve(self, n_steps=1):
+        _check(self._lib.lmpo_batch_evolve_step(self._h, int(n_steps)))
+
+    def sync(self):
+        _check(self._lib.lmpo_batch_sync(self._h))
+
+    def plan(self):
+        """Workgroups per chain in the current launch plan."""
+        out = np.zeros(len(self.chains), dtype=np.int32)
+        _check(self._lib.lmpo_batch_plan(self._h, _iptr(out)))
+        return out
+
+    def profile_begin(self, max_launches=20000):
+        _check(self._lib.lmpo_batch_profile_begin(self._h, int(max_launches)))
+
+    def profile_end(self):
+        """(layer launches, summed kernel ms from HIP events, summed declared SVD flops)."""
+        out = np.zeros(3)
+        _check(self._lib.lmpo_batch_profile_end(self._h, _dptr(out)))
+        return int(out[0]), float(out[1]), float(out[2])
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(self._lib.lmpo_batch_destroy(self._h))
             self._h = None
 
     def __del__(self):
