@@ -65,6 +65,114 @@ def timed_run(model, run, precision, steps, warmup):
             "dims": dims, "sweeps": stats[2], "svds": stats[3], "trace": tr}
 
 
+def timed_batch(models, run, steps, warmup, sequential):
+    """C4: the batched form (one launch per Trotter layer over all chains), and
+    optionally the same chains run one after another through the single-chain
+    path (the plain FP64 GPU path) for comparison."""
+    import torch
+
+    from paper_2203_05871_amd import Batch, Chain
+
+    def make():
+        return [Chain(m, run["tau"], run["chi_max"], run["cutoff"], "fp64", run["init"]) for m in models]
+
+    if warmup > 0:
+        w = make()
+        wb = Batch(w)
+        wb.evolve(warmup)
+        wb.sync()
+        wb.close()
+        for c in w:
+            c.close()
+    chains = make()
+    b = Batch(chains)
+    torch.cuda.synchronize()
+    b.profile_begin(3 * steps + 3)
+    t0 = time.perf_counter()
+    b.evolve(steps)
+    b.sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    launches, ms, flops = b.profile_end()
+    plan = b.plan()
+    out = {"seconds": dt, "launches": launches, "kernel_ms": ms, "flops": flops, "plan": plan,
+           "obs": [zz(c) for c in chains], "max_chi": max(max(c.bond_dims()) for c in chains)}
+    b.close()
+    for c in chains:
+        c.close()
+    if sequential:
+        chains = make()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for c in chains:
+            c.evolve(steps)
+        for c in chains:
+            c.sync()
+        torch.cuda.synchronize()
+        out["sequential_seconds"] = time.perf_counter() - t0
+        out["sequential_obs"] = [zz(c) for c in chains]
+        for c in chains:
+            c.close()
+    return out
+
+
+def bench_c4(args):
+    """Batched form on the 64-chain workload (a separate line from the
+    headline; not the driver's default)."""
+    import numpy as np
+
+    import workloads
+
+    models, run = workloads.c4()
+    K, W = args.steps, args.warmup
+    r = timed_batch(models, run, K, W, sequential=not args.no_sequential)
+    value = K / r["seconds"]
+    achieved = r["flops"] / (r["kernel_ms"] * 1e-3) / 1e12
+    line = {
+        "metric": "Trotter steps/s of the whole 64-chain batch (batched form, FP64)", "value": value,
+        "unit": "steps/s", "n_gpus": 1, "steps": K, "warmup": W, "ms_per_step": 1e3 * r["seconds"] / K,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic (seeded uneven chains, no dataset)",
+        "config": {"workload": f"64 chains, N~U{{8..24}}, Omega~U[0.5,2], Delta~U[2,8], chi_max=64, cutoff=1e-12, "
+                               f"tau=0.05, {K} steps from {run['init']}", "chains": len(models),
+                   "max_chi_reached": int(r["max_chi"]), "workgroups": int(r["plan"].sum())},
+        "roofline": {"bound": "mfma", "kernel": "batch_layer_kernel", "achieved": achieved,
+                     "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
+                     "traffic": None, "launches": r["launches"],
+                     "avg_launch_ms": r["kernel_ms"] / max(1, r["launches"]),
+                     "flops_per_launch": r["flops"] / max(1, r["launches"])},
+    }
+    if "sequential_seconds" in r:
+        line["sequential_single_chain_steps_per_s"] = K / r["sequential_seconds"]
+        line["speedup_vs_sequential"] = r["sequential_seconds"] / r["seconds"]
+        line["batch_vs_sequential_max_obs_diff"] = float(max(np.abs(a - b).max() for a, b in
+                                                             zip(r["obs"], r["sequential_obs"])))
+    if not args.no_cpu:
+        # oracle on a bounded sample: the first chains, all K steps each, until the budget is spent
+        from oracle import tebd
+
+        t0 = time.perf_counter()
+        done_chains = 0
+        worst = 0.0
+        for c, m in enumerate(models):
+            mps = tebd.MPS.product(run["init"], m["N"])
+            gates = tebd.gate_tables(m, run["tau"])
+            tebd.evolve(mps, m, run["tau"], K, run["chi_max"], run["cutoff"], gates=gates)
+            z1, z2 = tebd.zz_observables(mps)
+            worst = max(worst, float(np.abs(np.concatenate([z1, z2]) - r["obs"][c]).max()))
+            done_chains += 1
+            if time.perf_counter() - t0 > args.cpu_budget:
+                break
+        dt = time.perf_counter() - t0
+        # steps/s of the whole batch, extrapolated from the sampled chains' share of the sites
+        frac = sum(m["N"] for m in models[:done_chains]) / sum(m["N"] for m in models)
+        line["cpu_baseline"] = {"value": K * frac / dt, "unit": "steps/s", "cores": blas_threads(), "kind": "oracle",
+                                "sample": f"first {done_chains} of {len(models)} chains, all {K} steps; "
+                                          f"batch rate scaled by their share of the sites"}
+        line["obs_err_vs_oracle_sampled"] = worst
+    print(json.dumps(line), flush=True)
+
+
 def cpu_baseline(model, run, steps, budget_s):
     """The FP64 oracle on the host cores: as many of the same steps as fit in
     the time budget (a bounded sample of the same trajectory)."""
@@ -104,12 +212,15 @@ def blas_threads():
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--steps", type=int, default=None, help="timed steps (default: the workload's run, 50 or 40)")
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", choices=["both", "fp32", "fp64"], default="both")
     ap.add_argument("--cpu-budget", type=float, default=25.0, help="seconds of oracle time for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--init", default="+x")
+    ap.add_argument("--workload", choices=["c3", "c4"], default="c3",
+                    help="c3: N=30 chain at chi=256 (headline); c4: 64-chain batched form")
+    ap.add_argument("--no-sequential", action="store_true", help="c4: skip the sequential single-chain run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}): a single chain's Trotter step is a "
@@ -123,6 +234,12 @@ def main():
     import workloads
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.workload == "c4":
+        if args.steps is None:
+            args.steps = 40
+        return bench_c4(args)
+    if args.steps is None:
+        args.steps = 50
     model, run = workloads.c3(args.init)
     K, W = args.steps, args.warmup
     res = {}

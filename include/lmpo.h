@@ -156,15 +156,22 @@ int lmpo_apply_gate(lmpo_state *s, int32_t k, int32_t half, int32_t ascending);
  * entries at most), and its kept rank; synchronises. */
 int lmpo_last_spectrum(lmpo_state *s, int32_t n_out, double *sv, int32_t *n_sv, int32_t *kept);
 
+/* Cap on the workgroups that serve one SVD or centre hop of this state (0:
+ * automatic, one per Jacobi pair of the block, at most the co-resident grid).
+ * Results do not depend on it; it exists for tuning and for tests of that. */
+int lmpo_set_workgroups(lmpo_state *s, int32_t max_workgroups);
+
 /* Jacobi statistics: out = (sweeps of the last SVD, its column count,
  * total sweeps so far, total SVDs so far, hops included); synchronises. */
 int lmpo_svd_stats(lmpo_state *s, int32_t out[4]);
 
 /* Accumulated time of the persistent SVD phases seen by its first workgroup,
  * microseconds: [0] setup, [1] Jacobi pair work, [2] barrier wait, [5] norms +
- * select, [6] epilogue, [7] number of launches; inside the pair work [8] Gram,
- * [9] eigen sweep, [10] X update, [11] V update.  Synchronises. */
-int lmpo_svd_profile(lmpo_state *s, double out_us[12]);
+ * select, [6] epilogue; inside the pair work [8] Gram, [9] eigen sweep, [10] X
+ * update, [11] V update.  Counts: [3] shader clock cycles, [4] pair tasks,
+ * [7] launches, [12] pair tasks that rotated.  out_us has 16 entries.
+ * Synchronises. */
+int lmpo_svd_profile(lmpo_state *s, double out_us[16]);
 
 /* Profiling window for the persistent SVD kernel (one launch per truncated
  * SVD or centre hop).  Between begin and end, HIP events bracket every such

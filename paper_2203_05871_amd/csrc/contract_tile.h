@@ -134,4 +134,53 @@ __device__ __forceinline__ void contract_tile(ContractLds<T> &lds, double2 *cons
   }
 }
 
+// ---------------------------------------------------------------------------
+// Trace and rescaling shared by the single-chain kernels and the batched
+// layer kernel (explicit fma, so both give the same bits).
+// In the basis P_a = sigma^a / sqrt(2), Tr P_a = sqrt(2) delta_{a0}.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double2 zmul_exact(double2 a, double2 b) {
+  return make_double2(fma(a.x, b.x, -(a.y * b.y)), fma(a.x, b.y, a.y * b.x));
+}
+__device__ __forceinline__ void zfma_exact(double2 &acc, double2 a, double2 b) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+}
+
+// v_out[r] = sqrt(2) sum_l v_in[l] A[l][a][r], by one workgroup (v in LDS).
+__device__ __forceinline__ void env_step_right(const double2 *__restrict__ A, int cl, int cr, int a,
+                                               const double2 *vin, double2 *vout) {
+  const double s2 = 1.4142135623730951;
+  for (int r = threadIdx.x; r < cr; r += blockDim.x) {
+    double2 acc = make_double2(0, 0);
+    const double2 *col = A + (size_t)a * cr + r;
+    for (int l = 0; l < cl; ++l) zfma_exact(acc, vin[l], col[(size_t)l * 4 * cr]);
+    vout[r] = make_double2(acc.x * s2, acc.y * s2);
+  }
+}
+
+// tr(rho) by one workgroup; v0, v1 hold at least max bond dim entries.
+__device__ __forceinline__ double2 chain_trace(double2 *const *sites, const int *dims, int N, double2 *v0,
+                                               double2 *v1) {
+  if (threadIdx.x == 0) v0[0] = make_double2(1.0, 0.0);
+  __syncthreads();
+  for (int i = 0; i < N; ++i) {
+    const int cl = i == 0 ? 1 : ld_dim(dims + i - 1), cr = i == N - 1 ? 1 : ld_dim(dims + i);
+    env_step_right(sites[i], cl, cr, 0, v0, v1);
+    __syncthreads();
+    double2 *t = v0;
+    v0 = v1;
+    v1 = t;
+  }
+  return v0[0];
+}
+
+// 1 / z for the rescaling rho -> rho / tr(rho).
+__device__ __forceinline__ double2 zinv_exact(double2 z) {
+  const double d = fma(z.x, z.x, z.y * z.y);
+  return make_double2(z.x / d, -z.y / d);
+}
+
 }  // namespace lmpo

@@ -1,0 +1,273 @@
+// Blocked Householder QR for the persistent SVD kernel (gfx950).
+//
+// A = Q R for a complex R x C matrix held column-major in global memory,
+// logical column j at physical column qmap[j] (the caller's pivoting order).
+// Each reflector is Hermitian and unitary, H = I - tau v v^H with real tau and
+// v(leading) = 1: for a column x with leading entry alpha = |alpha| e^{i phi},
+// H x = -e^{i phi} ||x|| e_1 (the sign choice that avoids cancellation; the
+// diagonal of R is therefore complex).  Reflectors are grouped in panels of nb
+// and kept in compact WY form, H_1 ... H_nb = I - V T V^H with T upper
+// triangular (Schreiber & Van Loan, 1989).  A panel is factored by one
+// workgroup with the panel in LDS; the trailing columns are updated with
+// A <- (I - V T^H V^H) A by all workgroups, 16 columns per task.  The same
+// panel update with T (not T^H), applied panel by panel in reverse order,
+// forms Q Y.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace lmpo {
+
+constexpr int NT_QR = 256;            // threads per workgroup
+constexpr int kQrNbMax = 8;           // reflectors per panel (4 when the panel has more than kQrRows rows)
+constexpr int kQrRows = 1024;         // panel rows that fit in LDS at width 8
+constexpr int kQrPanelElems = kQrRows * kQrNbMax;
+
+struct SharedQR {
+  double2 P[kQrPanelElems];           // panel (factor) or reflectors (update), column-major, ld = m
+  double2 T[kQrNbMax][kQrNbMax];      // the panel's T
+  double2 Wt[kQrNbMax][17];           // T^H (V^H Y) or T (V^H Y) of one 16-column task
+  double2 red[4][kQrNbMax];           // per-wave partial sums
+  double sred[4];
+};
+
+namespace qr {
+
+__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+__device__ __forceinline__ double2 cmulc(double2 a, double2 b) {  // conj(a) b
+  return make_double2(a.x * b.x + a.y * b.y, a.x * b.y - a.y * b.x);
+}
+__device__ __forceinline__ void cfma(double2 &acc, double2 a, double2 b) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+}
+__device__ __forceinline__ void cfmac(double2 &acc, double2 a, double2 b) {  // acc += conj(a) b
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(-a.y, b.x, acc.y);
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// Sum of one double over the workgroup; every thread gets the same value
+// (waves summed in a fixed order).
+__device__ __forceinline__ double block_sum(SharedQR &s, double v) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) s.sred[wave] = v;
+  __syncthreads();
+  return (s.sred[0] + s.sred[1]) + (s.sred[2] + s.sred[3]);
+}
+
+// Sums of n <= kQrNbMax complex values over the workgroup, result in s.red[0][q].
+__device__ __forceinline__ void block_sum_n(SharedQR &s, double2 *acc, int n) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kQrNbMax; ++q) {
+    if (q < n) {
+      const double re = wave_sum(acc[q].x), im = wave_sum(acc[q].y);
+      if (lane == 0) s.red[wave][q] = make_double2(re, im);
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < n) {
+    const int q = threadIdx.x;
+    double2 a = s.red[0][q], b = s.red[1][q], c = s.red[2][q], d = s.red[3][q];
+    s.red[0][q] = make_double2((a.x + b.x) + (c.x + d.x), (a.y + b.y) + (c.y + d.y));
+  }
+  __syncthreads();
+}
+
+}  // namespace qr
+
+// Panel width for an R-row matrix.
+__device__ __host__ inline int qr_panel_width(int R) { return R <= kQrRows ? kQrNbMax : kQrNbMax / 2; }
+
+// Factor logical columns [j0, j0 + nb) of A (rows j0 .. R-1) with this
+// workgroup: on return those columns of X hold R's entries on and above the
+// diagonal and the reflectors below it; Tg (nb x nb, row-major) holds T.
+__device__ __noinline__ void qr_panel(SharedQR &s, double2 *__restrict__ X, int ldx, const int *__restrict__ qmap, int R, int j0,
+                         int nb, double2 *__restrict__ Tg) {
+  using namespace qr;
+  const int m = R - j0, t = threadIdx.x;
+  for (int c = 0; c < nb; ++c) {
+    const double2 *col = X + (size_t)qmap[j0 + c] * ldx + j0;
+    for (int i = t; i < m; i += NT_QR) s.P[c * m + i] = col[i];
+  }
+  if (t < kQrNbMax * kQrNbMax) s.T[t / kQrNbMax][t % kQrNbMax] = make_double2(0, 0);
+  __syncthreads();
+  for (int c = 0; c < nb; ++c) {
+    double2 *pc = s.P + c * m;
+    double ss = 0.0;
+    for (int i = c + 1 + t; i < m; i += NT_QR) ss = fma(pc[i].x, pc[i].x, fma(pc[i].y, pc[i].y, ss));
+    ss = block_sum(s, ss);
+    const double2 al = pc[c];
+    double tau = 0.0;
+    double2 beta = al, rinv = make_double2(0, 0);
+    if (ss > 0.0) {
+      const double aa = sqrt(al.x * al.x + al.y * al.y);
+      const double nrm = sqrt(fma(aa, aa, ss));
+      const double2 ph = aa > 0.0 ? make_double2(al.x / aa, al.y / aa) : make_double2(1.0, 0.0);
+      const double d = aa + nrm;
+      tau = d / nrm;
+      beta = make_double2(-ph.x * nrm, -ph.y * nrm);
+      rinv = make_double2(ph.x / d, -ph.y / d);  // 1 / (e^{i phi} (|alpha| + ||x||))
+    }
+    __syncthreads();
+    if (tau != 0.0)
+      for (int i = c + 1 + t; i < m; i += NT_QR) pc[i] = cmul(pc[i], rinv);
+    if (t == 0) pc[c] = beta;
+    __syncthreads();
+    // w_q = v^H a_q for the panel columns q > c; z_j = v_j^H v for j < c
+    double2 acc[kQrNbMax];
+#pragma unroll
+    for (int q = 0; q < kQrNbMax; ++q) acc[q] = make_double2(0, 0);
+    const int nd = nb - 1;
+    for (int i = c + 1 + t; i < m; i += NT_QR) {
+      const double2 v = pc[i];
+#pragma unroll
+      for (int q = 0; q < kQrNbMax; ++q) {
+        if (q < nd) {
+          const int cq = q < c ? q : q + 1;  // j < c first, then columns after c
+          cfmac(acc[q], cq < c ? s.P[cq * m + i] : v, cq < c ? v : s.P[cq * m + i]);
+        }
+      }
+    }
+    if (t == 0) {  // row c, where v = 1
+#pragma unroll
+      for (int q = 0; q < kQrNbMax; ++q) {
+        if (q < nd) {
+          const int cq = q < c ? q : q + 1;
+          const double2 e = s.P[cq * m + c];
+          if (cq < c) {
+            acc[q].x += e.x;
+            acc[q].y -= e.y;  // conj(v_j[c]) * 1
+          } else {
+            acc[q].x += e.x;
+            acc[q].y += e.y;  // conj(1) * a_q[c]
+          }
+        }
+      }
+    }
+    block_sum_n(s, acc, nd);
+    if (tau != 0.0) {
+      for (int q = c + 1; q < nb; ++q) {
+        const double2 w = s.red[0][q - 1];
+        const double2 tw = make_double2(tau * w.x, tau * w.y);
+        double2 *pq = s.P + q * m;
+        for (int i = c + t; i < m; i += NT_QR) {
+          const double2 v = i == c ? make_double2(1.0, 0.0) : pc[i];
+          const double2 u = cmul(v, tw);
+          pq[i] = make_double2(pq[i].x - u.x, pq[i].y - u.y);
+        }
+      }
+    }
+    if (t == 0) {
+      // T(0:c, c) = -tau T(0:c, 0:c) z, T(c, c) = tau
+      double2 col[kQrNbMax];
+      for (int r = 0; r < c; ++r) {
+        double2 a = make_double2(0, 0);
+        for (int j = r; j < c; ++j) cfma(a, s.T[r][j], s.red[0][j]);
+        col[r] = make_double2(-tau * a.x, -tau * a.y);
+      }
+      for (int r = 0; r < c; ++r) s.T[r][c] = col[r];
+      s.T[c][c] = make_double2(tau, 0.0);
+    }
+    __syncthreads();
+  }
+  for (int c = 0; c < nb; ++c) {
+    double2 *col = X + (size_t)qmap[j0 + c] * ldx + j0;
+    for (int i = t; i < m; i += NT_QR) col[i] = s.P[c * m + i];
+  }
+  if (t < nb * nb) Tg[t] = s.T[t / nb][t % nb];
+  __syncthreads();
+}
+
+// Load the reflectors of the panel at logical columns [j0, j0 + nb) (rows
+// j0 .. R-1, unit diagonal, zeros above) and its T into LDS.
+__device__ __noinline__ void qr_load_panel(SharedQR &s, const double2 *__restrict__ X, int ldx, const int *__restrict__ qmap, int R,
+                              int j0, int nb, const double2 *__restrict__ Tg) {
+  const int m = R - j0, t = threadIdx.x;
+  __syncthreads();
+  for (int c = 0; c < nb; ++c) {
+    const double2 *col = X + (size_t)qmap[j0 + c] * ldx + j0;
+    for (int i = t; i < m; i += NT_QR)
+      s.P[c * m + i] = i < c ? make_double2(0, 0) : (i == c ? make_double2(1.0, 0.0) : col[i]);
+  }
+  if (t < nb * nb) s.T[t / nb][t % nb] = Tg[t];
+  __syncthreads();
+}
+
+// Y[row0 + i][cols] <- (I - V M V^H) Y for the 16 (or fewer) columns
+// cols[0 .. ncols) of Y (col0 + 0 .. ncols when cols is null), rows i < m, with M = T^H (adjoint = true, the
+// factorisation) or T (forming Q).  V and T from qr_load_panel.  Column c of
+// Y is at Y + ycol(c) * ldy.  Thread (j = t / 16, g = t % 16) works on column
+// j, rows g, g + 16, ... (coalesced); the reduction over g stays in the wave.
+__device__ __noinline__ void qr_apply_panel(SharedQR &s, int m, int nb, bool adjoint, double2 *__restrict__ Y, int ldy, int row0,
+                               const int *cols, int col0, int ncols) {
+  using namespace qr;
+  const int t = threadIdx.x, j = t >> 4, g = t & 15;
+  double2 *ycol = (j < ncols) ? Y + (size_t)(cols ? cols[j] : col0 + j) * ldy + row0 : nullptr;
+  double2 acc[kQrNbMax];
+#pragma unroll
+  for (int q = 0; q < kQrNbMax; ++q) acc[q] = make_double2(0, 0);
+  if (ycol) {
+    for (int i = g; i < m; i += 16) {
+      const double2 y = ycol[i];
+#pragma unroll
+      for (int q = 0; q < kQrNbMax; ++q)
+        if (q < nb) cfmac(acc[q], s.P[q * m + i], y);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kQrNbMax; ++q) {
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) {
+      acc[q].x += __shfl_xor(acc[q].x, off);
+      acc[q].y += __shfl_xor(acc[q].y, off);
+    }
+  }
+  __syncthreads();
+  if (g == 0 && j < 16) {
+    // Wt[:, j] = M (V^H y_j)
+    for (int r = 0; r < nb; ++r) {
+      double2 a = make_double2(0, 0);
+      for (int q = 0; q < nb; ++q) {
+        if (adjoint) {
+          if (q <= r) cfmac(a, s.T[q][r], acc[q]);  // (T^H)[r][q] = conj(T[q][r]), upper T
+        } else {
+          if (q >= r) cfma(a, s.T[r][q], acc[q]);
+        }
+      }
+      s.Wt[r][j] = a;
+    }
+  }
+  __syncthreads();
+  if (ycol) {
+    for (int i = g; i < m; i += 16) {
+      double2 y = ycol[i];
+#pragma unroll
+      for (int q = 0; q < kQrNbMax; ++q) {
+        if (q < nb) {
+          const double2 u = cmul(s.P[q * m + i], s.Wt[q][j]);
+          y.x -= u.x;
+          y.y -= u.y;
+        }
+      }
+      ycol[i] = y;
+    }
+  }
+}
+
+}  // namespace lmpo

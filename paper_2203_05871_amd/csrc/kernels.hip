@@ -63,17 +63,6 @@ __device__ __forceinline__ void site_dims(const int *dims, int N, int i, int &cl
   cr = (i == N - 1) ? 1 : dims[i];
 }
 
-// v_out[r] = sqrt(2) sum_l v_in[l] A[l][a][r]  (block-wide, v in LDS)
-__device__ void env_step_right(const double2 *__restrict__ A, int cl, int cr, int a, const double2 *vin,
-                               double2 *vout) {
-  const double s2 = 1.4142135623730951;
-  for (int r = threadIdx.x; r < cr; r += blockDim.x) {
-    double2 acc = make_double2(0, 0);
-    const double2 *col = A + (size_t)a * cr + r;
-    for (int l = 0; l < cl; ++l) dfma(acc, vin[l], col[(size_t)l * 4 * cr]);
-    vout[r] = make_double2(acc.x * s2, acc.y * s2);
-  }
-}
 // v_out[l] = sqrt(2) sum_r A[l][a][r] v_in[r]
 __device__ void env_step_left(const double2 *__restrict__ A, int cl, int cr, int a, const double2 *vin,
                               double2 *vout) {
@@ -89,25 +78,12 @@ __device__ void env_step_left(const double2 *__restrict__ A, int cl, int cr, int
 __global__ __launch_bounds__(256) void trace_kernel(double2 *const *sites, const int *dims, int N,
                                                     double2 *out) {
   extern __shared__ double2 buf[];
-  int cap = 1;
-  for (int i = 0; i < N - 1; ++i) cap = dims[i] > cap ? dims[i] : cap;
-  double2 *v0 = buf, *v1 = buf + cap;
-  if (threadIdx.x == 0) v0[0] = make_double2(1.0, 0.0);
-  __syncthreads();
-  for (int i = 0; i < N; ++i) {
-    int cl, cr;
-    site_dims(dims, N, i, cl, cr);
-    env_step_right(sites[i], cl, cr, 0, v0, v1);
-    __syncthreads();
-    double2 *tmp = v0;
-    v0 = v1;
-    v1 = tmp;
-  }
-  if (threadIdx.x == 0) out[0] = v0[0];
+  const double2 tr = chain_trace(sites, dims, N, buf, buf + kMaxDim / 4);
+  if (threadIdx.x == 0) out[0] = tr;
 }
 
 void launch_trace(hipStream_t s, double2 *const *sites, const int *dims, int N, double2 *out) {
-  hipLaunchKernelGGL(trace_kernel, dim3(1), dim3(256), 2 * kMaxDim * sizeof(double2), s, sites, dims, N, out);
+  hipLaunchKernelGGL(trace_kernel, dim3(1), dim3(256), 2 * (kMaxDim / 4) * sizeof(double2), s, sites, dims, N, out);
   check_launch();
 }
 
@@ -198,12 +174,10 @@ __global__ void scale_site_kernel(double2 *const *sites, const int *dims, int N,
   int cl, cr;
   site_dims(dims, N, site, cl, cr);
   const size_t n = (size_t)cl * 4 * cr;
-  const double2 z = tr[0];
-  const double d = z.x * z.x + z.y * z.y;
-  const double2 inv = make_double2(z.x / d, -z.y / d);
+  const double2 inv = zinv_exact(tr[0]);
   double2 *A = sites[site];
   for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
-    A[e] = dmul(A[e], inv);
+    A[e] = zmul_exact(A[e], inv);
 }
 
 void launch_scale_site(hipStream_t s, double2 *const *sites, const int *dims, int N, int site, const double2 *tr) {

@@ -65,6 +65,8 @@ struct lmpo_state {
   int *d_dims = nullptr;
   double2 *d_gates = nullptr;
   double2 *X = nullptr, *V = nullptr, *W = nullptr, *Z = nullptr, *T = nullptr;
+  double2 *Y = nullptr, *Lb = nullptr, *Tq = nullptr;
+  int *qmap = nullptr, *qinv = nullptr;
   int *act = nullptr, *cmap = nullptr;
   double *cnorm = nullptr;
   int *sweep_cnt = nullptr, *stats = nullptr, *perm = nullptr, *kept = nullptr, *err = nullptr, *req = nullptr;
@@ -77,6 +79,7 @@ struct lmpo_state {
   size_t ev_used = 0;
   bool ev_overflow = false;
   int grid = 1;                 // largest co-resident grid of the persistent SVD
+  int wg_cap = 0;               // caller's cap on workgroups per SVD launch (0: none)
   int *dims_pinned = nullptr;   // asynchronous copy of the bond dims (grid sizing only)
   hipEvent_t dims_ready = nullptr;
   std::vector<int> dims_est;    // bond dims as of the last completed step
@@ -187,6 +190,11 @@ size_t layout(lmpo_state *S, const Sizes &z, int N, int nb, char *base, size_t s
   S->act = a.take<int>(2 * slots);
   S->cmap = a.take<int>((size_t)nbp * JB);
   S->cnorm = a.take<double>(z.max_cols);
+  S->Y = a.take<double2>(z.v_elems);
+  S->Lb = a.take<double2>(z.x_elems);
+  S->Tq = a.take<double2>((size_t)(z.max_cols / 4 + 2) * 64);
+  S->qmap = a.take<int>(z.max_cols);
+  S->qinv = a.take<int>(z.max_cols);
   S->Z = a.take<double2>(z.z_elems);
   S->T = a.take<double2>(z.t_elems);
   S->sig = a.take<double>(z.max_cols);
@@ -275,6 +283,11 @@ SvdLaunch svd_args(lmpo_state *S, int mode, int k, int asc) {
   L.dims = S->d_dims;
   L.X = S->X;
   L.V = S->V;
+  L.Y = S->Y;
+  L.Lb = S->Lb;
+  L.Tq = S->Tq;
+  L.qmap = S->qmap;
+  L.qinv = S->qinv;
   L.W = S->W;
   L.act = S->act;
   L.cmap = S->cmap;
@@ -304,7 +317,8 @@ int grid_for(const lmpo_state *S, int R, int C) {
   int nbp = (C + JB - 1) / JB;
   nbp += nbp & 1;
   const int npairs = std::max(1, nbp / 2);
-  return std::max(1, std::min(npairs, S->grid));
+  const int cap = S->wg_cap > 0 ? std::min(S->wg_cap, S->grid) : S->grid;
+  return std::max(1, std::min(npairs, cap));
 }
 int est(const lmpo_state *S, int bond) {
   if (bond < 0 || bond >= S->N - 1) return 1;
@@ -707,7 +721,7 @@ int lmpo_last_spectrum(lmpo_state *S, int32_t n_out, double *sv, int32_t *n_sv, 
   return LMPO_OK;
 }
 
-int lmpo_svd_profile(lmpo_state *S, double out_us[12]) {
+int lmpo_svd_profile(lmpo_state *S, double out_us[16]) {
   if (!S || !out_us) return fail(LMPO_EINVAL, "null argument");
   unsigned long long t[16];
   HIP_TRY(hipMemcpyAsync(t, S->tprof, sizeof(t), hipMemcpyDeviceToHost, S->stream));
@@ -718,6 +732,9 @@ int lmpo_svd_profile(lmpo_state *S, double out_us[12]) {
   for (int i = 0; i < 12; ++i) out_us[i] = khz > 0 ? (double)t[i] * 1e3 / khz : 0.0;
   out_us[7] = (double)t[7];
   out_us[3] = (double)t[12];  // shader clock cycles of the first workgroup (whole kernels)
+  out_us[4] = (double)t[13];   // pair tasks of the first workgroup
+  out_us[12] = (double)t[14];  // of which rotated
+  out_us[13] = out_us[14] = out_us[15] = 0.0;
   return LMPO_OK;
 }
 
@@ -751,6 +768,13 @@ int lmpo_profile_end(lmpo_state *S, double out[3]) {
   out[1] = ms;
   out[2] = flops;
   if (S->ev_overflow) return fail(LMPO_EINVAL, "more SVD launches than max_launches in the profiling window");
+  return LMPO_OK;
+}
+
+int lmpo_set_workgroups(lmpo_state *S, int32_t max_workgroups) {
+  if (!S) return fail(LMPO_EINVAL, "state is null");
+  if (max_workgroups < 0) return fail(LMPO_EINVAL, "max_workgroups must be >= 0");
+  S->wg_cap = max_workgroups;
   return LMPO_OK;
 }
 

@@ -41,6 +41,11 @@ struct SvdLaunch {
   double2 *const *sites;
   int *dims;
   double2 *X, *V, *W, *Z, *T;
+  double2 *Y;   // C x C Jacobi matrix (R^H of the QR)
+  double2 *Lb;  // left vectors of X, or the hop's explicit Q (R x k)
+  double2 *Tq;  // T factors of the QR panels, kQrNbMax^2 each
+  int *qmap;    // QR column order (logical -> physical column of X)
+  int *qinv;    // its inverse
   int *act;
   int *cmap;
   double *cnorm;

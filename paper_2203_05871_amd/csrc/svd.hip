@@ -20,6 +20,7 @@
 // accuracy relative to their own norms, which gives small singular values
 // to high relative accuracy.
 #include "contract_tile.h"
+#include "householder.h"
 #include "lmpo_internal.h"
 
 namespace lmpo {
@@ -162,8 +163,10 @@ union SharedAll {
   SharedPair pair;
   SharedSelect sel;
   SharedGemm gemm;
+  SharedQR qr;
   double red[NT];
 };
+static_assert(NT == NT_QR, "the Householder helpers assume the SVD workgroup size");
 
 // Stage rows [r0, r0 + n) of the pair's columns of M into LDS (xs[i][c]).
 // All global loads of a thread are issued before any LDS store, so their
@@ -291,6 +294,10 @@ __device__ bool pair_work(SharedPair &s, double2 *__restrict__ X, int ldx, int R
   }
   need = __syncthreads_or(need);
   mark(8);
+  if (tp && t == 0) {
+    tp[13] += 1;
+    tp[14] += need ? 1 : 0;
+  }
   if (!need) return false;
   // One cyclic sweep over the JP x JP Gram per round: the pair need not be
   // diagonalised exactly, later rounds recompute its Gram from the columns
@@ -556,13 +563,22 @@ __device__ void block_select(SharedSelect &s, const double *__restrict__ sig, in
 
 
 
-// The whole truncated SVD / centre hop, run by G cooperating workgroups (this
-// one has index `rank`); group-local barriers only, so independent problems
-// can share one launch.
+// The whole truncated SVD / centre hop, run by G cooperating workgroups
+// (group-local barriers only, so independent problems can share one launch).
+//
+// Gate (mode 0), on the R x C block X (R >= C; X = theta, or theta^H when
+// that is taller): the columns are ordered by decreasing norm (P), X P = Q R
+// by blocked Householder QR, and one-sided block Jacobi runs on Y = R^H
+// (C x C): Y W = U_Y diag(sigma).  Then X = (Q W) diag(sigma) (P U_Y)^H, so
+// the left vectors of X are Q W and the right ones P U_Y.  Jacobi on the
+// triangular factor of a norm-ordered QR needs far fewer sweeps than on X
+// itself for graded spectra (Drmac & Veselic, 2008).
+// Hop (modes 1, 2): A_c = Q R (right) or A_c^H = Q R (left) by the same QR;
+// the centre site takes Q (or Q^H) and the neighbour absorbs R (or R^H).
 __device__ void svd_body(const SvdLaunch &a, Barrier &bar, SharedAll &sh) {
   const unsigned rank = bar.rank, G_ = bar.G;
-  // phase timers (workgroup 0, thread 0): 0 setup, 1 pair Gram+eig, 2 wait after A,
-  // 3 update, 4 wait after B, 5 norms+select, 6 epilogue, 7 launches
+  // phase timers (workgroup 0, thread 0): 0 setup + QR, 1 pair Gram+eig, 2 wait
+  // after a round, 5 norms+select, 6 epilogue, 7 launches, 11 V update
   unsigned long long tmark = wall_clock64();
   const unsigned long long cyc0 = clock64();
   const bool prof = a.tprof && rank == 0 && threadIdx.x == 0;
@@ -601,8 +617,25 @@ __device__ void svd_body(const SvdLaunch &a, Barrier &bar, SharedAll &sh) {
     R = 4 * chr;
     C = chm;
   }
-  const int ldx = R, ldv = C;
-  // ---- hop: load X from the site tensor ----
+  const int ldx = R;
+  auto colnorms = [&](const double2 *M, int ld, int rows, double *out, bool root) {
+    for (int j = rank; j < C; j += G) {
+      double acc = 0.0;
+      for (int i = threadIdx.x; i < rows; i += NT) {
+        double2 v = M[(size_t)i + (size_t)j * ld];
+        acc = fma(v.x, v.x, fma(v.y, v.y, acc));
+      }
+      sh.red[threadIdx.x] = acc;
+      __syncthreads();
+      for (int off = NT / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh.red[threadIdx.x] += sh.red[threadIdx.x + off];
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) out[j] = root ? sqrt(sh.red[0]) : sh.red[0];
+      __syncthreads();
+    }
+  };
+  // ---- hop: load X from the site tensor; gate: order the columns ----
   if (a.mode == 1) {
     const double2 *A = a.sites[site];
     for (size_t e = gtid; e < (size_t)R * C; e += gstride) {
@@ -616,19 +649,174 @@ __device__ void svd_body(const SvdLaunch &a, Barrier &bar, SharedAll &sh) {
       a.X[(size_t)j + (size_t)i * ldx] = zconj(A[e]);
     }
   }
+  if (a.mode == 0) {
+    colnorms(a.X, ldx, R, a.cnorm, false);
+    bar.sync();
+    if (rank == 0) order_columns(sh.sel, a.cnorm, C, C, a.qmap);
+  } else {
+    for (size_t e = gtid; e < (size_t)C; e += gstride) a.qmap[e] = (int)e;
+  }
+  bar.sync();
+  // ---- blocked Householder QR of X P ----
+  const int nq = R < C ? R : C, nbw = qr_panel_width(R);
+  for (int j0 = 0, p = 0; j0 < nq; j0 += nbw, ++p) {
+    const int nb = min(nbw, nq - j0);
+    double2 *Tp = a.Tq + (size_t)p * kQrNbMax * kQrNbMax;
+    if (rank == 0) qr_panel(sh.qr, a.X, ldx, a.qmap, R, j0, nb, Tp);
+    bar.sync();
+    const int c0 = j0 + nb, ntail = C - c0, ntask = (ntail + 15) / 16;
+    if (ntail > 0) {
+      if ((int)rank < ntask) {
+        qr_load_panel(sh.qr, a.X, ldx, a.qmap, R, j0, nb, Tp);
+        for (int task = rank; task < ntask; task += G)
+          qr_apply_panel(sh.qr, R - j0, nb, true, a.X, ldx, j0, a.qmap + c0 + task * 16, 0,
+                         min(16, ntail - task * 16));
+      }
+      bar.sync();
+    }
+  }
+  // Q Y for the columns of Lb (R rows, ncol columns): panels in reverse
+  // order, each workgroup on its own 16-column tasks (no barrier needed).
+  auto apply_q = [&](int ncol) {
+    const int ntask = (ncol + 15) / 16;
+    for (int task = rank; task < ntask; task += G) {
+      for (int j0 = ((nq - 1) / nbw) * nbw, p = (nq - 1) / nbw; j0 >= 0; j0 -= nbw, --p) {
+        const int nb = min(nbw, nq - j0);
+        qr_load_panel(sh.qr, a.X, ldx, a.qmap, R, j0, nb, a.Tq + (size_t)p * kQrNbMax * kQrNbMax);
+        qr_apply_panel(sh.qr, R - j0, nb, false, a.Lb, R, j0, nullptr, task * 16, min(16, ncol - task * 16));
+      }
+    }
+  };
+  lap(0);
+  if (a.mode != 0) {
+    // ---- hop: explicit thin Q, then A_c <- Q (or Q^H), neighbour <- R A (or A R^H) ----
+    const int k = nq;
+    for (size_t e = gtid; e < (size_t)R * k; e += gstride) {
+      const int i = e % R, jj = e / R;
+      a.Lb[e] = make_double2(i == jj ? 1.0 : 0.0, 0.0);
+    }
+    bar.sync();
+    apply_q(k);
+    int *dslot = (a.mode == 2) ? a.dims + (site - 1) : a.dims + site;
+    if (rank == 0 && threadIdx.x == 0) {
+      if (a.alg_flops) {
+        // declared cost of a thin complex QR with Q formed: 4 (4 R n^2 - 4 n^3 / 3), n = min(R, C)
+        const double rr = R, cc = k;
+        *a.alg_flops += 4.0 * (4.0 * rr * cc * cc - 4.0 / 3.0 * cc * cc * cc);
+      }
+      if (a.stats) {
+        a.stats[0] = 0;
+        a.stats[1] = C;
+        a.stats[2] = R;
+        a.stats[5] += 1;
+      }
+      *a.kept = k;
+    }
+    bar.sync();
+    if (rank == 0 && threadIdx.x == 0) *dslot = k;
+    const bool right = a.mode == 1;
+    double2 *Ac = a.sites[site];
+    {
+      const size_t na = (size_t)R * k, nz = (size_t)k * C;
+      const size_t n = na > nz ? na : nz;
+      for (size_t e = gtid; e < n; e += gstride) {
+        if (e < na) {
+          int i, al;
+          if (right) {
+            i = e / k;
+            al = e % k;
+          } else {
+            al = e / R;
+            i = e % R;
+          }
+          const double2 q = a.Lb[(size_t)i + (size_t)al * R];
+          Ac[e] = right ? q : zconj(q);
+        }
+        if (e < nz) {
+          int al, m;
+          if (right) {
+            al = e / C;
+            m = e % C;
+          } else {
+            m = e / k;
+            al = e % k;
+          }
+          const double2 r = m >= al ? a.X[(size_t)al + (size_t)m * ldx] : make_double2(0, 0);  // R[al][m]
+          a.Z[e] = right ? r : zconj(r);
+        }
+      }
+    }
+    bar.sync();
+    // neighbour update: right: T = Z (k x C) * A_{c+1} (C x 4 chr);  left: T = A_{c-1} (4 chl x C) * Z (C x k)
+    const double2 *Am = right ? a.Z : a.sites[site - 1];
+    const double2 *Bm = right ? a.sites[site + 1] : a.Z;
+    const int M = right ? k : 4 * chl, Nn = right ? 4 * chr : k, K = C;
+    const int lda = K, ldb = Nn;
+    const int tiles_m = (M + 63) / 64, tiles_n = (Nn + 63) / 64;
+    for (int tile = rank; tile < tiles_m * tiles_n; tile += G) {
+      const int i0 = (tile / tiles_n) * 64, j0 = (tile % tiles_n) * 64;
+      const int t = threadIdx.x, ty = t / 16, tx = t % 16;
+      double2 acc[4][4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0, 0);
+      for (int k0 = 0; k0 < K; k0 += 16) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          int e = t + NT * q;
+          int row = e / 16, kk = e % 16;
+          sh.gemm.As[kk][row] =
+              (i0 + row < M && k0 + kk < K) ? Am[(size_t)(i0 + row) * lda + k0 + kk] : make_double2(0, 0);
+          int kb = e / 64, j = e % 64;
+          sh.gemm.Bs[kb][j] = (k0 + kb < K && j0 + j < Nn) ? Bm[(size_t)(k0 + kb) * ldb + j0 + j] : make_double2(0, 0);
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int kk = 0; kk < 16; ++kk) {
+          double2 av[4], bv[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i) av[i] = sh.gemm.As[kk][ty * 4 + i];
+#pragma unroll
+          for (int j = 0; j < 4; ++j) bv[j] = sh.gemm.Bs[kk][tx + 16 * j];
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) zfma(acc[i][j], av[i], bv[j]);
+        }
+        __syncthreads();
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          int r = i0 + ty * 4 + i, c = j0 + tx + 16 * j;
+          if (r < M && c < Nn) a.T[(size_t)r * Nn + c] = acc[i][j];
+        }
+    }
+    bar.sync();
+    double2 *dst = right ? a.sites[site + 1] : a.sites[site - 1];
+    for (size_t e = gtid; e < (size_t)M * Nn; e += gstride) dst[e] = a.T[e];
+    lap(6);
+    if (prof) a.tprof[12] += clock64() - cyc0;
+    return;
+  }
+  // ---- gate: Y = R^H (C x C, lower triangular), V = I ----
+  double2 *Y = a.Y;
+  const int ldy = C, ldv = C;
   for (size_t e = gtid; e < (size_t)C * C; e += gstride) {
-    int i = e % C, j = e / C;
-    a.V[(size_t)i + (size_t)j * ldv] = make_double2(i == j ? 1.0 : 0.0, 0.0);
+    const int i = e % C, j = e / C;
+    Y[e] = i >= j ? zconj(a.X[(size_t)j + (size_t)a.qmap[i] * ldx]) : make_double2(0, 0);
+    a.V[e] = make_double2(i == j ? 1.0 : 0.0, 0.0);
   }
   if (gtid < (size_t)a.max_sweeps) a.sweep_cnt[gtid] = 0;
   bar.sync();
-  lap(0);
-  // ---- block Jacobi sweeps ----
+  // ---- block Jacobi sweeps on Y ----
   int nbp = (C + JB - 1) / JB;
   nbp += nbp & 1;
   if (nbp < 2) nbp = 2;
   const int npairs = nbp / 2;
-  const double tol = a.tol_factor * sqrt((double)R) * 2.220446049250313e-16;
+  const double tol = a.tol_factor * sqrt((double)C) * 2.220446049250313e-16;
   int sweeps = 0;
   const size_t wsw_stride = (size_t)(nbp - 1) * npairs;  // pair slots per sweep
   for (int sweep = 0; sweep < a.max_sweeps; ++sweep) {
@@ -636,21 +824,7 @@ __device__ void svd_body(const SvdLaunch &a, Barrier &bar, SharedAll &sh) {
     int *act = a.act + (size_t)(sweep & 1) * wsw_stride;
     // order the columns by decreasing norm for this sweep (blocks then hold
     // columns of similar size, which speeds up convergence on graded spectra)
-    for (int j = rank; j < C; j += G) {
-      double acc = 0.0;
-      for (int i = threadIdx.x; i < R; i += NT) {
-        double2 v = a.X[(size_t)i + (size_t)j * ldx];
-        acc = fma(v.x, v.x, fma(v.y, v.y, acc));
-      }
-      sh.red[threadIdx.x] = acc;
-      __syncthreads();
-      for (int off = NT / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) sh.red[threadIdx.x] += sh.red[threadIdx.x + off];
-        __syncthreads();
-      }
-      if (threadIdx.x == 0) a.cnorm[j] = sh.red[0];
-      __syncthreads();
-    }
+    colnorms(Y, ldy, C, a.cnorm, false);
     bar.sync();
     if (rank == 0) order_columns(sh.sel, a.cnorm, C, nbp * JB, a.cmap);
     bar.sync();
@@ -659,7 +833,7 @@ __device__ void svd_body(const SvdLaunch &a, Barrier &bar, SharedAll &sh) {
         int bi, bj;
         pair_blocks(round, p, nbp, bi, bj);
         const size_t slot = (size_t)round * npairs + p;
-        bool active = pair_work(sh.pair, a.X, ldx, R, Wsw + slot * JP * JP, C, bi, bj, tol, a.cmap,
+        bool active = pair_work(sh.pair, Y, ldy, C, Wsw + slot * JP * JP, C, bi, bj, tol, a.cmap,
                                 (a.tprof && rank == 0) ? a.tprof : nullptr);
         if (threadIdx.x == 0) {
           act[slot] = active ? 1 : 0;
@@ -677,24 +851,11 @@ __device__ void svd_body(const SvdLaunch &a, Barrier &bar, SharedAll &sh) {
     lap(11);
   }
   bar.sync();
-  // ---- column norms ----
-  for (int j = rank; j < C; j += G) {
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < R; i += NT) {
-      double2 v = a.X[(size_t)i + (size_t)j * ldx];
-      acc = fma(v.x, v.x, fma(v.y, v.y, acc));
-    }
-    sh.red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int off = NT / 2; off > 0; off >>= 1) {
-      if (threadIdx.x < off) sh.red[threadIdx.x] += sh.red[threadIdx.x + off];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) a.sig[j] = sqrt(sh.red[0]);
-    __syncthreads();
-  }
+  // ---- singular values, truncation select; inverse of the QR column order ----
+  colnorms(Y, ldy, C, a.sig, true);
+  for (size_t e = gtid; e < (size_t)C; e += gstride) a.qinv[a.qmap[e]] = (int)e;
   bar.sync();
-  int *dslot = (a.mode == 2) ? a.dims + (site - 1) : a.dims + site;
+  int *dslot = a.dims + site;
   if (rank == 0) {
     if (threadIdx.x == 0 && a.alg_flops) {
       // declared cost of a thin complex SVD of an R x C block (R >= C):
@@ -709,139 +870,53 @@ __device__ void svd_body(const SvdLaunch &a, Barrier &bar, SharedAll &sh) {
       a.stats[4] += sweeps;
       a.stats[5] += 1;
     }
-    block_select(sh.sel, a.sig, C, a.chi_max, a.cutoff, a.mode != 0, a.perm, a.sorted, a.kept, dslot, a.disc, a.err);
+    block_select(sh.sel, a.sig, C, a.chi_max, a.cutoff, 0, a.perm, a.sorted, a.kept, dslot, a.disc, a.err);
   }
   bar.sync();
   lap(5);
   const int k = __hip_atomic_load(a.kept, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  if (a.mode == 0) {
-    // theta = U S V^H: ascending A_k <- U, A_{k+1} <- S V^H; descending A_k <- U S, A_{k+1} <- V^H.
-    // trans: X = theta^H, so theta's left vectors are V's columns, its right vectors X / sigma.
-    double2 *Ak = a.sites[a.k], *Ak1 = a.sites[a.k + 1];
-    const size_t na = (size_t)4 * chl * k, nb = (size_t)k * 4 * chr;
-    const size_t n = na > nb ? na : nb;
-    for (size_t e = gtid; e < n; e += gstride) {
-      if (e < na) {
-        const int i = e / k, al = e % k;
-        const int pc = a.perm[al];
-        const double sg = a.sorted[al];
-        double2 u;
-        if (trans == 0) {
-          double2 x = a.X[(size_t)i + (size_t)pc * ldx];
-          u = make_double2(x.x / sg, x.y / sg);
-        } else {
-          u = a.V[(size_t)i + (size_t)pc * ldv];
-        }
-        if (!a.asc) u = make_double2(u.x * sg, u.y * sg);
-        Ak[e] = u;
-      }
-      if (e < nb) {
-        const int al = e / (4 * chr), j = e % (4 * chr);
-        const int pc = a.perm[al];
-        const double sg = a.sorted[al];
-        double2 v;
-        if (trans == 0) {
-          v = a.V[(size_t)j + (size_t)pc * ldv];
-        } else {
-          double2 x = a.X[(size_t)j + (size_t)pc * ldx];
-          v = make_double2(x.x / sg, x.y / sg);
-        }
-        if (a.asc) v = make_double2(v.x * sg, v.y * sg);
-        Ak1[e] = zconj(v);
-      }
-    }
-    lap(6);
-    if (prof) a.tprof[12] += clock64() - cyc0;
-    return;
-  }
-  // ---- hop epilogue ----
-  const bool right = a.mode == 1;
-  double2 *Ac = a.sites[site];
-  {
-    const size_t na = (size_t)R * k, nz = (size_t)k * C;
-    const size_t n = na > nz ? na : nz;
-    for (size_t e = gtid; e < n; e += gstride) {
-      if (e < na) {
-        int i, al;
-        if (right) {
-          i = e / k;
-          al = e % k;
-        } else {
-          al = e / R;
-          i = e % R;
-        }
-        const double sg = a.sorted[al];
-        double2 x = a.X[(size_t)i + (size_t)a.perm[al] * ldx];
-        x = make_double2(x.x / sg, x.y / sg);
-        Ac[e] = right ? x : zconj(x);
-      }
-      if (e < nz) {
-        int al, m;
-        if (right) {
-          al = e / C;
-          m = e % C;
-        } else {
-          m = e / k;
-          al = e % k;
-        }
-        const double sg = a.sorted[al];
-        double2 v = a.V[(size_t)m + (size_t)a.perm[al] * ldv];
-        v = make_double2(v.x * sg, v.y * sg);
-        a.Z[e] = right ? zconj(v) : v;
-      }
-    }
+  // ---- left vectors of X: Lb = Q [W(:, perm(0:k)); 0] ----
+  for (size_t e = gtid; e < (size_t)R * k; e += gstride) {
+    const int i = e % R, al = e / R;
+    a.Lb[e] = i < C ? a.V[(size_t)i + (size_t)a.perm[al] * ldv] : make_double2(0, 0);
   }
   bar.sync();
-  // neighbour update: right: T = Z (k x C) * A_{c+1} (C x 4 chr);  left: T = A_{c-1} (4 chl x C) * Z (C x k)
-  const double2 *Am = right ? a.Z : a.sites[site - 1];
-  const double2 *Bm = right ? a.sites[site + 1] : a.Z;
-  const int M = right ? k : 4 * chl, Nn = right ? 4 * chr : k, K = C;
-  const int lda = K, ldb = Nn;
-  const int tiles_m = (M + 63) / 64, tiles_n = (Nn + 63) / 64;
-  for (int tile = rank; tile < tiles_m * tiles_n; tile += G) {
-    const int i0 = (tile / tiles_n) * 64, j0 = (tile % tiles_n) * 64;
-    const int t = threadIdx.x, ty = t / 16, tx = t % 16;
-    double2 acc[4][4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) acc[i][j] = make_double2(0, 0);
-    for (int k0 = 0; k0 < K; k0 += 16) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        int e = t + NT * q;
-        int row = e / 16, kk = e % 16;
-        sh.gemm.As[kk][row] =
-            (i0 + row < M && k0 + kk < K) ? Am[(size_t)(i0 + row) * lda + k0 + kk] : make_double2(0, 0);
-        int kb = e / 64, j = e % 64;
-        sh.gemm.Bs[kb][j] = (k0 + kb < K && j0 + j < Nn) ? Bm[(size_t)(k0 + kb) * ldb + j0 + j] : make_double2(0, 0);
-      }
-      __syncthreads();
-#pragma unroll 4
-      for (int kk = 0; kk < 16; ++kk) {
-        double2 av[4], bv[4];
-#pragma unroll
-        for (int i = 0; i < 4; ++i) av[i] = sh.gemm.As[kk][ty * 4 + i];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) bv[j] = sh.gemm.Bs[kk][tx + 16 * j];
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-#pragma unroll
-          for (int j = 0; j < 4; ++j) zfma(acc[i][j], av[i], bv[j]);
-      }
-      __syncthreads();
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i)
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        int r = i0 + ty * 4 + i, c = j0 + tx + 16 * j;
-        if (r < M && c < Nn) a.T[(size_t)r * Nn + c] = acc[i][j];
-      }
-  }
+  apply_q(k);
   bar.sync();
-  double2 *dst = right ? a.sites[site + 1] : a.sites[site - 1];
-  for (size_t e = gtid; e < (size_t)M * Nn; e += gstride) dst[e] = a.T[e];
+  // ---- canonical update: theta = U S V^H; ascending A_k <- U, A_{k+1} <- S V^H;
+  // descending A_k <- U S, A_{k+1} <- V^H.  Left vectors of X: Lb; right
+  // vectors of X: row r is row qinv[r] of Y W / sigma.  X = theta^H swaps them.
+  double2 *Ak = a.sites[a.k], *Ak1 = a.sites[a.k + 1];
+  const size_t na = (size_t)4 * chl * k, nb2 = (size_t)k * 4 * chr;
+  const size_t n = na > nb2 ? na : nb2;
+  for (size_t e = gtid; e < n; e += gstride) {
+    if (e < na) {
+      const int i = e / k, al = e % k;
+      const double sg = a.sorted[al];
+      double2 u;
+      if (trans == 0) {
+        u = a.Lb[(size_t)i + (size_t)al * R];
+      } else {
+        const double2 y = Y[(size_t)a.qinv[i] + (size_t)a.perm[al] * ldy];
+        u = make_double2(y.x / sg, y.y / sg);
+      }
+      if (!a.asc) u = make_double2(u.x * sg, u.y * sg);
+      Ak[e] = u;
+    }
+    if (e < nb2) {
+      const int al = e / (4 * chr), j = e % (4 * chr);
+      const double sg = a.sorted[al];
+      double2 v;
+      if (trans == 0) {
+        const double2 y = Y[(size_t)a.qinv[j] + (size_t)a.perm[al] * ldy];
+        v = make_double2(y.x / sg, y.y / sg);
+      } else {
+        v = a.Lb[(size_t)j + (size_t)al * R];
+      }
+      if (a.asc) v = make_double2(v.x * sg, v.y * sg);
+      Ak1[e] = zconj(v);
+    }
+  }
   lap(6);
   if (prof) a.tprof[12] += clock64() - cyc0;
 }
@@ -869,29 +944,6 @@ union SharedBatch {
   ContractLds<float> cf;
   double2 env[2][kMaxDim / 4];
 };
-
-// tr(rho) by one workgroup: v <- sqrt(2) v A_i[:, 0, :] over the sites
-// (Tr P_a = sqrt(2) delta_{a0} in the normalised Pauli basis).
-__device__ double2 chain_trace(double2 *const *sites, const int *dims, int N, double2 (*env)[kMaxDim / 4]) {
-  const double s2 = 1.4142135623730951;
-  double2 *v0 = env[0], *v1 = env[1];
-  if (threadIdx.x == 0) v0[0] = make_double2(1.0, 0.0);
-  __syncthreads();
-  for (int i = 0; i < N; ++i) {
-    const int cl = i == 0 ? 1 : ld_dim(dims + i - 1), cr = i == N - 1 ? 1 : ld_dim(dims + i);
-    const double2 *A = sites[i];
-    for (int r = threadIdx.x; r < cr; r += NT) {
-      double2 acc = make_double2(0, 0);
-      for (int l = 0; l < cl; ++l) zfma(acc, v0[l], A[(size_t)l * 4 * cr + r]);
-      v1[r] = make_double2(acc.x * s2, acc.y * s2);
-    }
-    __syncthreads();
-    double2 *t = v0;
-    v0 = v1;
-    v1 = t;
-  }
-  return v0[0];
-}
 
 __global__ __launch_bounds__(NT) void batch_layer_kernel(const BatchChain *__restrict__ chains,
                                                          const int *__restrict__ block_group,
@@ -950,17 +1002,15 @@ __global__ __launch_bounds__(NT) void batch_layer_kernel(const BatchChain *__res
     // rho <- rho / tr(rho): trace by the first workgroup, scaling of the
     // centre site by all, with the single-chain kernels' arithmetic
     if (rank == 0) {
-      const double2 tr = chain_trace(L.sites, L.dims, N, sh.env);
+      const double2 tr = chain_trace(L.sites, L.dims, N, sh.env[0], sh.env[1]);
       if (threadIdx.x == 0) *chains[g].tr = tr;
     }
     bar.sync();
-    const double2 z = chains[g].tr[0];
-    const double d = z.x * z.x + z.y * z.y;
-    const double2 inv = make_double2(z.x / d, -z.y / d);
+    const double2 inv = zinv_exact(chains[g].tr[0]);
     const int cl = centre == 0 ? 1 : ld_dim(L.dims + centre - 1), cr = centre == N - 1 ? 1 : ld_dim(L.dims + centre);
     double2 *A = L.sites[centre];
     const size_t n = (size_t)cl * 4 * cr;
-    for (size_t e = (size_t)rank * NT + threadIdx.x; e < n; e += (size_t)G * NT) A[e] = zmul(A[e], inv);
+    for (size_t e = (size_t)rank * NT + threadIdx.x; e < n; e += (size_t)G * NT) A[e] = zmul_exact(A[e], inv);
   }
   if (rank == 0) {
     if (threadIdx.x == 0) *centre_p = centre;

@@ -61,7 +61,7 @@ EXPORTS = [
     "lmpo_measure_1q", "lmpo_measure_2q", "lmpo_bond_dims", "lmpo_discarded_weight", "lmpo_sync",
     "lmpo_destroy", "lmpo_last_error", "lmpo_get_site", "lmpo_set_site", "lmpo_set_centre",
     "lmpo_get_centre", "lmpo_get_gate", "lmpo_apply_gate", "lmpo_last_spectrum", "lmpo_svd_stats",
-    "lmpo_svd_profile", "lmpo_profile_begin", "lmpo_profile_end",
+    "lmpo_svd_profile", "lmpo_profile_begin", "lmpo_profile_end", "lmpo_set_workgroups",
     "lmpo_batch_arena_bytes", "lmpo_batch_create", "lmpo_batch_evolve_step", "lmpo_batch_sync",
     "lmpo_batch_plan", "lmpo_batch_profile_begin", "lmpo_batch_profile_end", "lmpo_batch_destroy",
 ]
@@ -104,6 +104,7 @@ def load_library(path: str = LIB_PATH):
         "lmpo_svd_profile": (ctypes.c_int, [P, pdbl]),
         "lmpo_profile_begin": (ctypes.c_int, [P, i32]),
         "lmpo_profile_end": (ctypes.c_int, [P, pdbl]),
+        "lmpo_set_workgroups": (ctypes.c_int, [P, i32]),
         "lmpo_batch_arena_bytes": (ctypes.c_size_t, [ctypes.POINTER(P), i32]),
         "lmpo_batch_create": (ctypes.c_int, [ctypes.POINTER(P), i32, P, ctypes.c_size_t, ctypes.POINTER(P)]),
         "lmpo_batch_evolve_step": (ctypes.c_int, [P, i32]),
@@ -293,14 +294,18 @@ class Chain:
 
     def svd_profile(self):
         """Accumulated microseconds per persistent-SVD phase (first workgroup)."""
-        out = np.zeros(12)
+        out = np.zeros(16)
         _check(self._lib.lmpo_svd_profile(self._h, _dptr(out)))
-        names = ["setup", "pairs", "wait", "cycles", "-", "select", "epilogue", "launches", "gram", "eig",
-                 "upd_x", "upd_v"]
+        names = ["setup", "pairs", "wait", "cycles", "tasks", "select", "epilogue", "launches", "gram", "eig",
+                 "upd_x", "upd_v", "rotated"]
         return dict(zip(names, out.tolist()))
 
     def profile_begin(self, max_launches=20000):
         _check(self._lib.lmpo_profile_begin(self._h, int(max_launches)))
+
+    def set_workgroups(self, max_workgroups):
+        """Cap the workgroups per SVD launch (0: automatic); results do not depend on it."""
+        _check(self._lib.lmpo_set_workgroups(self._h, int(max_workgroups)))
 
     def profile_end(self):
         """(SVD launches, summed kernel ms from HIP events, summed declared flops)."""

@@ -53,6 +53,7 @@ def random_canonical_mps(dims, centre, seed, centre_decay=0.0):
 
 
 def inject(ch, A, centre):
+    """Write the site tensors and declare the centre."""
     for k, t in enumerate(A):
         ch.set_site(k, t)
     ch.set_centre(centre)
@@ -151,6 +152,28 @@ def test_determinism(Chain):
         ch.close()
     assert np.array_equal(outs[0], outs[1])
     assert max(dims) == 24
+
+
+def test_result_independent_of_workgroups(Chain):
+    """The same gate (a 212 x 164 block: 11 Jacobi pairs per round, 11 QR
+    update tasks) and the same steps with 1, 2, 5 and automatic workgroups per
+    SVD give the same bits."""
+    dims = [4, 16, 53, 64, 41, 16, 4]  # N = 8; bond 3 joins 53 and 41 (block 212 x 164)
+    m = workloads.jittered_chain(8, 11)
+    A = random_canonical_mps(dims, 3, 11, 0.05)
+    outs = []
+    for wg in (1, 2, 5, 0):
+        ch = Chain(m, 0.05, 64, 1e-12, "fp64", "+z")
+        inject(ch, A, 3)
+        ch.set_workgroups(wg)
+        ch.apply_gate(3, True, True)
+        ch.apply_gate(5, False, True)
+        ch.evolve(2)
+        outs.append([ch.get_site(k) for k in range(8)] + [np.array(ch.bond_dims())])
+        ch.close()
+    for o in outs[1:]:
+        for x, y in zip(outs[0], o):
+            assert np.array_equal(x, y), np.abs(x - y).max()
 
 
 def test_two_site_chain_and_chi_one(Chain):
