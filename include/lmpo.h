@@ -168,17 +168,20 @@ int lmpo_svd_stats(lmpo_state *s, int32_t out[4]);
 /* Accumulated time of the persistent SVD phases seen by its first workgroup,
  * microseconds: [0] setup, [1] Jacobi pair work, [2] barrier wait, [5] norms +
  * select, [6] epilogue; inside the pair work [8] Gram, [9] eigen sweep, [10] X
- * update, [11] V update.  Counts: [3] shader clock cycles, [4] pair tasks,
- * [7] launches, [12] pair tasks that rotated.  out_us has 16 entries.
+ * update, [11] V update; [16] column order, [17] QR panels, [18] QR trailing
+ * updates, [19] forming Q Y.  Counts: [3] shader clock cycles, [4] pair
+ * tasks, [7] launches, [12] pair tasks that rotated.  out_us has 24 entries.
  * Synchronises. */
-int lmpo_svd_profile(lmpo_state *s, double out_us[16]);
+int lmpo_svd_profile(lmpo_state *s, double out_us[24]);
 
 /* Profiling window for the persistent SVD kernel (one launch per truncated
  * SVD or centre hop).  Between begin and end, HIP events bracket every such
  * launch on the state's stream (at most max_launches; more is an error at
- * end) and each launch adds its declared flop count 4 (14 R C^2 + 8 C^3)
- * for its R x C block (R >= C) to a device counter.  end synchronises and
- * returns out = (launches, summed kernel milliseconds, summed declared flops). */
+ * end) and each launch adds its declared flop count to a device counter:
+ * 4 (14 R C^2 + 8 C^3) for the thin SVD of a gate's R x C block (R >= C;
+ * Golub & Van Loan), 4 (4 R n^2 - 4 n^3 / 3) for a hop's thin QR with Q formed
+ * (n = min(R, C)).  end synchronises and returns out = (launches, summed
+ * kernel milliseconds, summed declared flops). */
 int lmpo_profile_begin(lmpo_state *s, int32_t max_launches);
 int lmpo_profile_end(lmpo_state *s, double out[3]);
 

@@ -52,10 +52,37 @@ __device__ __forceinline__ void cfmac(double2 &acc, double2 a, double2 b) {  // 
   acc.y = fma(-a.y, b.x, acc.y);
 }
 
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+// Lane exchange within rows of 16 lanes through DPP (no LDS round trip).
+template <int kCtrl>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(b & 0xffffffffLL), kCtrl, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), kCtrl, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over each row of 16 lanes, the same bits in every lane of the row:
+// pairs (quad_perm 1,0,3,2), quads (2,3,0,1), half rows (row_half_mirror),
+// rows (row_mirror).
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_mov<0xB1>(v);
+  v += dpp_mov<0x4E>(v);
+  v += dpp_mov<0x141>(v);
+  v += dpp_mov<0x140>(v);
   return v;
+}
+
+__device__ __forceinline__ double lane_read(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 64 lanes of the wave, the same bits in every lane.
+__device__ __forceinline__ double wave_sum(double v) {
+  v = row16_sum(v);
+  return (lane_read(v, 0) + lane_read(v, 16)) + (lane_read(v, 32) + lane_read(v, 48));
 }
 
 // Sum of one double over the workgroup; every thread gets the same value
@@ -232,11 +259,8 @@ __device__ __noinline__ void qr_apply_panel(SharedQR &s, int m, int nb, bool adj
   }
 #pragma unroll
   for (int q = 0; q < kQrNbMax; ++q) {
-#pragma unroll
-    for (int off = 8; off > 0; off >>= 1) {
-      acc[q].x += __shfl_xor(acc[q].x, off);
-      acc[q].y += __shfl_xor(acc[q].y, off);
-    }
+    acc[q].x = row16_sum(acc[q].x);  // the 16 lanes of column j form one DPP row
+    acc[q].y = row16_sum(acc[q].y);
   }
   __syncthreads();
   if (g == 0 && j < 16) {

@@ -203,7 +203,7 @@ size_t layout(lmpo_state *S, const Sizes &z, int N, int nb, char *base, size_t s
   S->sweep_cnt = a.take<int>(kMaxSweeps);
   S->stats = a.take<int>(kStats);
   S->bar = a.take<unsigned>(8 * 32 + 64);
-  S->tprof = a.take<unsigned long long>(16);
+  S->tprof = a.take<unsigned long long>(32);
   S->alg_flops = a.take<double>(1);
   S->kept = a.take<int>(1);
   S->err = a.take<int>(1);
@@ -509,7 +509,7 @@ int lmpo_create(const lmpo_model *model, const lmpo_options *opt, const char *in
   int zero = 0;
   double zd = 0.0;
   e = hipMemsetAsync(S->stats, 0, kStats * sizeof(int), S->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(S->tprof, 0, 16 * sizeof(unsigned long long), S->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(S->tprof, 0, 32 * sizeof(unsigned long long), S->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(S->err, &zero, sizeof(int), hipMemcpyHostToDevice, S->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(S->disc, &zd, sizeof(double), hipMemcpyHostToDevice, S->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(S->stream);
@@ -721,18 +721,19 @@ int lmpo_last_spectrum(lmpo_state *S, int32_t n_out, double *sv, int32_t *n_sv, 
   return LMPO_OK;
 }
 
-int lmpo_svd_profile(lmpo_state *S, double out_us[16]) {
+int lmpo_svd_profile(lmpo_state *S, double out_us[24]) {
   if (!S || !out_us) return fail(LMPO_EINVAL, "null argument");
-  unsigned long long t[16];
+  unsigned long long t[32];
   HIP_TRY(hipMemcpyAsync(t, S->tprof, sizeof(t), hipMemcpyDeviceToHost, S->stream));
   HIP_TRY(hipStreamSynchronize(S->stream));
   int dev = 0, khz = 0;
   HIP_TRY(hipGetDevice(&dev));
   HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
-  for (int i = 0; i < 12; ++i) out_us[i] = khz > 0 ? (double)t[i] * 1e3 / khz : 0.0;
-  out_us[7] = (double)t[7];
-  out_us[3] = (double)t[12];  // shader clock cycles of the first workgroup (whole kernels)
+  auto us = [&](unsigned long long v) { return khz > 0 ? (double)v * 1e3 / khz : 0.0; };
+  for (int i = 0; i < 24; ++i) out_us[i] = us(t[i]);
+  out_us[3] = (double)t[12];   // shader clock cycles of the first workgroup (whole kernels)
   out_us[4] = (double)t[13];   // pair tasks of the first workgroup
+  out_us[7] = (double)t[7];    // launches
   out_us[12] = (double)t[14];  // of which rotated
   out_us[13] = out_us[14] = out_us[15] = 0.0;
   return LMPO_OK;

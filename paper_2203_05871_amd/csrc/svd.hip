@@ -302,61 +302,51 @@ __device__ bool pair_work(SharedPair &s, double2 *__restrict__ X, int ldx, int R
   // One cyclic sweep over the JP x JP Gram per round: the pair need not be
   // diagonalised exactly, later rounds recompute its Gram from the columns
   // (the outer sweep count is the same as with a fully converged inner solve).
-  __shared__ double2 s_al[JP], s_be[JP];
-  __shared__ int s_pt[JP], s_rot[JP];
+  // Each thread (a, b) computes the two rotations it needs (those of a's and
+  // b's pairs) itself, so a step costs one workgroup barrier.
   int cur = 0;
   const double tol2 = tol * tol;
+  // rotation of pair (p, q), p < q, that zeroes g_pq: columns
+  // x_p' = cs x_p + s x_q, x_q' = cs x_q - conj(s) x_p with cs real,
+  // s = tau cs, cs = 1 / sqrt(1 + |tau|^2) and the small root
+  // tau = 2 conj(g_pq) / (d + sgn(d) sqrt(d^2 + 4 |g_pq|^2)), d = g_pp - g_qq.
+  // Returns false (identity) when g_pq is below the threshold.
+  auto rotation = [&](int p, int q, double &cs, double2 &sc) {
+    const double app = s.G[cur][p][p].x, aqq = s.G[cur][q][q].x;
+    const double2 c = s.G[cur][p][q];
+    const double mc2 = fma(c.x, c.x, c.y * c.y);
+    if (!(mc2 > tol2 * (app * aqq) && mc2 > 1e-290)) {  // (normal range for the rsq estimates)
+      cs = 1.0;
+      sc = make_double2(0.0, 0.0);
+      return false;
+    }
+    const double d = app - aqq;
+    const double r2 = fma(d, d, 4.0 * mc2);
+    const double r = r2 * rsq_nr(r2);
+    const double den = d + copysign(r, d);
+    const double f = 2.0 * rcp_nr(den);
+    const double2 tau = make_double2(f * c.x, -f * c.y);
+    cs = rsq_nr(fma(tau.x, tau.x, fma(tau.y, tau.y, 1.0)));
+    sc = make_double2(tau.x * cs, tau.y * cs);
+    return true;
+  };
   for (int sweep = 0; sweep < kInnerSweeps; ++sweep) {
     for (int step = 0; step < JP - 1; ++step) {
-      if (t < JP / 2) {
-        int p, q;
-        if (t == 0) {
-          p = step;
-          q = JP - 1;
-        } else {
-          const int m = JP - 1;
-          p = (step + t) % m;
-          q = (step - t + m) % m;
-          if (p > q) {
-            int x = p;
-            p = q;
-            q = x;
-          }
-        }
-        const double app = s.G[cur][p][p].x, aqq = s.G[cur][q][q].x;
-        const double2 c = s.G[cur][p][q];
-        const double mc2 = c.x * c.x + c.y * c.y;
-        s_pt[p] = q;
-        s_pt[q] = p;
-        if (mc2 > tol2 * (app * aqq) && mc2 > 1e-290) {  // (normal range for the rsq estimates)
-          // zero g_pq: x_p' = cs x_p - sn e^{-i phi} x_q, x_q' = sn x_p + cs e^{-i phi} x_q
-          // (an FP32 tangent here costs ~2.6x more sweeps: keep FP64)
-          const double inv = rsq_nr(mc2);
-          const double zeta = 0.5 * (aqq - app) * inv;
-          const double r2 = fma(zeta, zeta, 1.0);
-          const double tt = copysign(rcp_nr(fabs(zeta) + r2 * rsq_nr(r2)), zeta);
-          const double cs = rsq_nr(fma(tt, tt, 1.0)), sn = tt * cs;
-          const double2 ph = make_double2(c.x * inv, -c.y * inv);
-          s_al[p] = make_double2(cs, 0.0);
-          s_be[p] = make_double2(-sn * ph.x, -sn * ph.y);
-          s_al[q] = make_double2(cs * ph.x, cs * ph.y);
-          s_be[q] = make_double2(sn, 0.0);
-          s_rot[p] = s_rot[q] = 1;
-        } else {
-          s_al[p] = s_al[q] = make_double2(1.0, 0.0);
-          s_be[p] = s_be[q] = make_double2(0.0, 0.0);
-          s_rot[p] = s_rot[q] = 0;
-        }
-      }
-      __syncthreads();
-      const int pa = s_pt[a], pb = s_pt[b];
-      const double2 al_a = s_al[a], be_a = s_be[a], al_b = s_al[b], be_b = s_be[b];
+      const int pa = inner_partner(a, step), pb = inner_partner(b, step);
+      double cs_a, cs_b;
+      double2 s_a, s_b;
+      const bool rot_a = rotation(min(a, pa), max(a, pa), cs_a, s_a);
+      rotation(min(b, pb), max(b, pb), cs_b, s_b);
+      // column b of J: J[b][b] = cs, J[pb][b] = s (b the lower index) or -conj(s)
+      const double2 al_a = make_double2(cs_a, 0.0), al_b = make_double2(cs_b, 0.0);
+      const double2 be_a = a < pa ? s_a : make_double2(-s_a.x, s_a.y);
+      const double2 be_b = b < pb ? s_b : make_double2(-s_b.x, s_b.y);
       const int nxt = cur ^ 1;
       const double2 gj_a = zadd(zmul(s.G[cur][a][b], al_b), zmul(s.G[cur][a][pb], be_b));
       const double2 gj_pa = zadd(zmul(s.G[cur][pa][b], al_b), zmul(s.G[cur][pa][pb], be_b));
       double2 g = zadd(zmul(zconj(al_a), gj_a), zmul(zconj(be_a), gj_pa));
       if (a == b) g.y = 0.0;
-      if (pa == b && s_rot[a]) g = make_double2(0.0, 0.0);
+      if (pa == b && rot_a) g = make_double2(0.0, 0.0);
       s.G[nxt][a][b] = g;
       s.W[nxt][a][b] = zadd(zmul(s.W[cur][a][b], al_b), zmul(s.W[cur][a][pb], be_b));
       __syncthreads();
@@ -657,13 +647,16 @@ __device__ void svd_body(const SvdLaunch &a, Barrier &bar, SharedAll &sh) {
     for (size_t e = gtid; e < (size_t)C; e += gstride) a.qmap[e] = (int)e;
   }
   bar.sync();
+  lap(16);
   // ---- blocked Householder QR of X P ----
   const int nq = R < C ? R : C, nbw = qr_panel_width(R);
   for (int j0 = 0, p = 0; j0 < nq; j0 += nbw, ++p) {
     const int nb = min(nbw, nq - j0);
     double2 *Tp = a.Tq + (size_t)p * kQrNbMax * kQrNbMax;
     if (rank == 0) qr_panel(sh.qr, a.X, ldx, a.qmap, R, j0, nb, Tp);
+    lap(17);
     bar.sync();
+    lap(2);
     const int c0 = j0 + nb, ntail = C - c0, ntask = (ntail + 15) / 16;
     if (ntail > 0) {
       if ((int)rank < ntask) {
@@ -672,7 +665,9 @@ __device__ void svd_body(const SvdLaunch &a, Barrier &bar, SharedAll &sh) {
           qr_apply_panel(sh.qr, R - j0, nb, true, a.X, ldx, j0, a.qmap + c0 + task * 16, 0,
                          min(16, ntail - task * 16));
       }
+      lap(18);
       bar.sync();
+      lap(2);
     }
   }
   // Q Y for the columns of Lb (R rows, ncol columns): panels in reverse
@@ -686,6 +681,7 @@ __device__ void svd_body(const SvdLaunch &a, Barrier &bar, SharedAll &sh) {
         qr_apply_panel(sh.qr, R - j0, nb, false, a.Lb, R, j0, nullptr, task * 16, min(16, ncol - task * 16));
       }
     }
+    lap(19);
   };
   lap(0);
   if (a.mode != 0) {

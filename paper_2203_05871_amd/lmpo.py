@@ -294,10 +294,10 @@ class Chain:
 
     def svd_profile(self):
         """Accumulated microseconds per persistent-SVD phase (first workgroup)."""
-        out = np.zeros(16)
+        out = np.zeros(24)
         _check(self._lib.lmpo_svd_profile(self._h, _dptr(out)))
         names = ["setup", "pairs", "wait", "cycles", "tasks", "select", "epilogue", "launches", "gram", "eig",
-                 "upd_x", "upd_v", "rotated"]
+                 "upd_x", "upd_v", "rotated", "-", "-", "-", "order", "qr_panel", "qr_update", "form_q"]
         return dict(zip(names, out.tolist()))
 
     def profile_begin(self, max_launches=20000):
