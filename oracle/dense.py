@@ -34,13 +34,13 @@ def apply_two_site(v, G, i, j, N):
 
 
 def trotter_evolve(v, model, tau, steps, gates=None, first_step=0, observer=None,
-                   force_trace=True):
+                   force_trace=True, order=2):
     tebd.check_chain(model)
     N = model["N"]
     if gates is None:
-        gates = tebd.gate_tables(model, tau)
+        gates = tebd.gate_tables(model, tau, order)
     for n in range(first_step, first_step + steps):
-        for k, frac, _ in tebd.step_schedule(N, n):
+        for k, frac, _ in tebd.step_schedule(N, n, order):
             v = apply_two_site(v, gates[(k, frac)], k, k + 1, N)
         if force_trace:
             v = v / trace(v, N)
@@ -114,3 +114,20 @@ def mps_to_vector(tensors):
     for A in tensors:
         v = np.tensordot(v, A, axes=(1, 0)).reshape(-1, A.shape[2])
     return v.reshape(-1)
+
+
+def renyi2(v, N):
+    """S_2 = -ln tr(rho^2) from the dense matrix (Eq. S_2), unit-trace normalised."""
+    rho = to_matrix(v, N)
+    rho = rho / np.trace(rho)
+    return float(-np.log(np.trace(rho @ rho).real))
+
+
+def osee(v, N, bond):
+    """OSEE of |rho>> across bond (bond, bond + 1) (Eq. OSEE): entropy of the
+    normalised squared singular values of the coefficient vector reshaped as
+    (sites 0..bond) x (sites bond+1..N-1)."""
+    s = np.linalg.svd(v.reshape(4 ** (bond + 1), 4 ** (N - bond - 1)), compute_uv=False)
+    p = s ** 2 / np.sum(s ** 2)
+    p = p[p > 0]
+    return float(-np.sum(p * np.log(p)))

@@ -4,11 +4,17 @@ State (Eq. mpo_def, App. A): rho is stored as an MPS with local dimension 4,
 site tensors A[k] of shape (chi_left, 4, chi_right); the local index is the
 computational (ket, bra) pair 2*ket + bra of the site.
 
-One Trotter step of size tau (second order):
+One Trotter step of size tau, second order (the default):
     layers  A(tau/2), B(tau), A(tau/2)
     A = bonds (k, k+1) with k even, B = k odd (chain)
-    global layer l = 3*step + {0, 1, 2}; gates of layer l run in ascending k
-    when l is even, descending when l is odd.
+Fourth order (the paper's trotter_order = 4, Sec. 6; the composition is not
+printed there, the symmetric triple product of second-order steps is used):
+    S4(tau) = S2(w1 tau) S2(w0 tau) S2(w1 tau),
+    w1 = 1 / (2 - 2^(1/3)), w0 = 1 - 2 w1,
+with the two adjacent A half-layers merged (A layers commute), i.e. seven
+layers A(w1/2) B(w1) A((w1+w0)/2) B(w0) A((w0+w1)/2) B(w1) A(w1/2) (times tau).
+Global layer l = L*step + j (L layers per step); gates of layer l run in
+ascending k when l is even, descending when l is odd.
 Per gate (bond k): bring the orthogonality centre onto (k, k+1); form the
 two-site block theta = G (A_k A_{k+1}) as a (4 chi_l) x (4 chi_r) matrix;
 full SVD (LAPACK); keep k' = min(chi_max, k_c) singular triplets, where k_c is
@@ -58,13 +64,26 @@ def chain_layers(N):
     return A, B
 
 
-def step_schedule(N, step):
+def trotter_layers(order=2):
+    """[(bond parity, fraction of tau)] of one step (see the module header)."""
+    if order == 2:
+        return [(0, 0.5), (1, 1.0), (0, 0.5)]
+    if order == 4:
+        w1 = 1.0 / (2.0 - 2.0 ** (1.0 / 3.0))
+        w0 = 1.0 - 2.0 * w1
+        return [(0, 0.5 * w1), (1, w1), (0, 0.5 * (w1 + w0)), (1, w0), (0, 0.5 * (w1 + w0)), (1, w1),
+                (0, 0.5 * w1)]
+    raise ValueError("trotter order must be 2 or 4")
+
+
+def step_schedule(N, step, order=2):
     """[(bond k, fraction of tau, ascending?)] for one chain step."""
-    A, B = chain_layers(N)
+    layers = chain_layers(N)
+    lay = trotter_layers(order)
     out = []
-    for j, (bonds, frac) in enumerate(((A, 0.5), (B, 1.0), (A, 0.5))):
-        layer = 3 * step + j
-        asc = layer % 2 == 0
+    for j, (parity, frac) in enumerate(lay):
+        asc = (len(lay) * step + j) % 2 == 0
+        bonds = layers[parity]
         for k in (bonds if asc else bonds[::-1]):
             out.append((k, frac, asc))
     return out
@@ -183,12 +202,40 @@ class MPS:
         cov = [covector(ops[k]) if k in ops else E_ID for k in range(self.N)]
         return self.contract(cov) / self.trace()
 
+    # -- global characteristics (Sec. 2.4) --
+    def tr_rho2(self):
+        """tr(rho^2) = sum rho[k, b] rho[b, k]: each site's (ket, bra) index
+        of one copy meets the swapped index of the other."""
+        swap = np.array([0, 2, 1, 3])  # 2*ket + bra -> 2*bra + ket
+        env = np.ones((1, 1), dtype=np.complex128)
+        for A in self.A:
+            # env'[r, r'] = sum_{l, l', s} env[l, l'] A[l, s, r] A[l', swap(s), r']
+            t = np.tensordot(env, A, axes=(0, 0))              # (l', s, r)
+            env = np.tensordot(t, A[:, swap, :], axes=((0, 1), (0, 1)))  # (r, r')
+        return complex(env[0, 0])
 
-def gate_tables(model, tau):
-    """{(bond, fraction): G} for fractions 1/2 and 1 of tau."""
+    def renyi2(self):
+        """S_2 = -ln tr(rho^2) (Eq. S_2), for rho normalised to unit trace."""
+        return float(-np.log((self.tr_rho2() / self.trace() ** 2).real))
+
+    def osee(self, bond):
+        """OSEE of |rho>> across bond (bond, bond + 1) (Eq. OSEE): von Neumann
+        entropy of the normalised Schmidt weights s^2 / sum s^2, obtained from
+        the SVD of the orthogonality centre placed on site `bond`."""
+        self.move_centre(bond)
+        A = self.A[bond]
+        s = np.linalg.svd(A.reshape(A.shape[0] * 4, A.shape[2]), compute_uv=False)
+        p = s ** 2 / np.sum(s ** 2)
+        p = p[p > 0]
+        return float(-np.sum(p * np.log(p)))
+
+
+def gate_tables(model, tau, order=2):
+    """{(bond, fraction): G} for every fraction of tau the scheme uses."""
     out = {}
+    fracs = sorted({f for _, f in trotter_layers(order)})
     for b in range(len(model["bonds"])):
-        for frac in (0.5, 1.0):
+        for frac in fracs:
             out[(b, frac)] = lm.bond_gate(model, b, frac * tau)
     return out
 
@@ -201,13 +248,13 @@ def check_chain(model):
 
 
 def evolve(mps, model, tau, steps, chi_max, cutoff, force_trace=True, gates=None,
-           observer=None, first_step=0):
+           observer=None, first_step=0, order=2):
     """Run `steps` Trotter steps; observer(step_done, mps) after each step."""
     check_chain(model)
     if gates is None:
-        gates = gate_tables(model, tau)
+        gates = gate_tables(model, tau, order)
     for n in range(first_step, first_step + steps):
-        for k, frac, asc in step_schedule(mps.N, n):
+        for k, frac, asc in step_schedule(mps.N, n, order):
             mps.apply_gate(k, gates[(k, frac)], chi_max, cutoff, asc)
         if force_trace:
             mps.renormalize()
