@@ -70,7 +70,8 @@ typedef struct {
 /* Numerical controls (Sec. 6, "Numerical simulation control"). */
 typedef struct {
   double tau;            /* time step, > 0 */
-  int32_t trotter_order; /* 2 (orders 3, 4 of the paper: LMPO_EUNSUPPORTED) */
+  int32_t trotter_order; /* 2, or 4: the symmetric triple product S2(w1 t) S2(w0 t) S2(w1 t),
+                            w1 = 1/(2 - 2^(1/3)), w0 = 1 - 2 w1 (7 layers); 3: LMPO_EUNSUPPORTED */
   int32_t chi_max;       /* max_dim_rho, >= 1 */
   double cutoff;         /* cut_off_rho: largest discarded squared Schmidt weight,
                             relative to the block's total; >= 0 */
@@ -95,7 +96,7 @@ int lmpo_create(const lmpo_model *model, const lmpo_options *opt, const char *in
                 void *device_arena, size_t arena_bytes, void *hip_stream, lmpo_state **out);
 
 /* Enqueue n_steps >= 0 Trotter steps: layers A(tau/2) B(tau) A(tau/2) over even
- * bonds (A) and odd bonds (B); each gate moves the orthogonality centre onto its
+ * bonds (A) and odd bonds (B) (order 4: the seven layers of the composition); each gate moves the orthogonality centre onto its
  * bond (exact), applies exp(x L_b) to the two-site block, truncates by SVD and
  * restores canonical form; then rho -> rho / tr(rho) if force_trace. */
 int lmpo_evolve_step(lmpo_state *s, int32_t n_steps);
@@ -114,6 +115,19 @@ int lmpo_measure_1q(lmpo_state *s, int32_t n, const int32_t *site, const char *p
  * for (i[k], j[k]); out[n][2] = (re, im).  Synchronises. */
 int lmpo_measure_2q(lmpo_state *s, int32_t n, const int32_t *i, const int32_t *j,
                     const char *paulis, double *out);
+
+/* Second Renyi entropy S_2 = -ln tr(rho^2) (Eq. S_2, Sec. 2.4), evaluated as
+ * -ln( <<rho|rho>> / |tr rho|^2 ): <<rho|rho>> = tr(rho^dagger rho) is the squared
+ * norm of the orthogonality centre (the state is kept in mixed-canonical form)
+ * and equals tr(rho^2) for Hermitian rho.  Synchronises. */
+int lmpo_renyi2(lmpo_state *s, double *out);
+
+/* Operator-space entanglement entropy across bond (bond, bond+1) (Eq. OSEE,
+ * Sec. 2.4): the von Neumann entropy of the normalised Schmidt weights
+ * s_j^2 / sum s^2 of |rho>>.  Moves the orthogonality centre onto site `bond`
+ * (exact hops; the state is unchanged) and takes the singular values of that
+ * site on the GPU.  Synchronises. */
+int lmpo_osee(lmpo_state *s, int32_t bond, double *out);
 
 /* Current bond dimensions chi_0..chi_{N-2}; synchronises. */
 int lmpo_bond_dims(lmpo_state *s, int32_t *out);
@@ -216,6 +230,22 @@ int lmpo_batch_evolve_step(lmpo_batch *b, int32_t n_steps);
 
 /* Wait for the batch's work; reports the first chain with a deferred error. */
 int lmpo_batch_sync(lmpo_batch *b);
+
+/* Online autotuner (off by default).  Results do not depend on how the grid
+ * is split between chains, so with autotuning on, the batch tries one step
+ * under each candidate cap on the workgroups per chain (1, 2, 4, 8, 16, none)
+ * for every (largest block size bucket, precision) it meets, timed with HIP
+ * events (those steps synchronise), and then keeps the fastest.  The table is
+ * process-wide per device, so later batches reuse it; a batch with tuning off
+ * still uses entries that exist. */
+int lmpo_batch_set_autotune(lmpo_batch *b, int32_t enable);
+
+/* The tuned entries of the current device: log2 of the block column bucket,
+ * precision bit mask (1 << LMPO_FP64 | 1 << LMPO_FP32_CONTRACT), chosen cap
+ * (0 = none) and its step time in ms; at most max_entries written, the count
+ * in *n_entries. */
+int lmpo_autotune_table(int32_t max_entries, int32_t *log2_bucket, int32_t *precisions, int32_t *cap,
+                        double *best_ms, int32_t *n_entries);
 
 /* Workgroups per chain in the current plan (n_chains entries). */
 int lmpo_batch_plan(lmpo_batch *b, int32_t *workgroups);

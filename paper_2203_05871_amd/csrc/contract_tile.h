@@ -30,12 +30,39 @@ __device__ __forceinline__ int ld_dim(const int *p) {
 //   M[(l,s),(t,r)] = sum_m A_k[l][s][m] A_{k+1}[m][t][r]
 //   theta[(l,s'),(t',r)] = sum_{s,t} G[(s' t'),(s t)] M[(l,s),(t,r)]
 // A workgroup owns 16 values of l and 16 of r, i.e. a 64 x 64 tile of M with
-// all four s and all four t, so the 16x16 gate is applied in the epilogue
-// from LDS.  T is the arithmetic type (double, or float for the FP32
+// all four s and all four t (a complex GEMM on the matrix cores, real-split),
+// so the 16x16 gate is applied in the epilogue from LDS.  T is the arithmetic type (double, or float for the FP32
 // contraction form: operands rounded to FP32, FP32 accumulation).
 // Output: trans = 0 -> X = theta, column-major, ld = 4 chl;
 //         trans = 1 -> X = theta^H, column-major, ld = 4 chr.
 // ---------------------------------------------------------------------------
+// Matrix-core step D += A B on 16 x 16 x 4 tiles: lane l supplies A[l % 16][l / 16]
+// and B[l / 16][l % 16].  The accumulator rows a lane holds differ by type:
+// FP64 (v_mfma_f64_16x16x4f64) D[l / 16 + 4 r][l % 16], FP32
+// (v_mfma_f32_16x16x4f32) D[4 (l / 16) + r][l % 16], r = 0..3.
+template <typename T>
+struct MfmaAcc;
+template <>
+struct MfmaAcc<double> {
+  typedef double type __attribute__((ext_vector_type(4)));
+  __device__ static int row(int lk, int r) { return lk + 4 * r; }
+};
+template <>
+struct MfmaAcc<float> {
+  typedef float type __attribute__((ext_vector_type(4)));
+  __device__ static int row(int lk, int r) { return 4 * lk + r; }
+};
+template <typename T>
+__device__ __forceinline__ typename MfmaAcc<T>::type mfma_step(T a, T b, typename MfmaAcc<T>::type c);
+template <>
+__device__ __forceinline__ MfmaAcc<double>::type mfma_step<double>(double a, double b, MfmaAcc<double>::type c) {
+  return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+template <>
+__device__ __forceinline__ MfmaAcc<float>::type mfma_step<float>(float a, float b, MfmaAcc<float>::type c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
 template <typename T>
 struct ContractLds {
   cplx<T> As[16][64];
@@ -65,17 +92,18 @@ __device__ __forceinline__ void contract_tile(ContractLds<T> &lds, double2 *cons
   __syncthreads();  // the previous tile of this workgroup may still read Gs / Ms
   const int t = threadIdx.x;
   const int l0 = by * 16, r0 = bx * 16;
-  const int ty = t / 16, tx = t % 16;
   const int R = 4 * chl;
   {
     double2 g = G[t];
     Gs[t / 16][t % 16] = C2{(T)g.x, (T)g.y};
   }
-  C2 acc[4][4];
+  // M tile (64 x 64) on the matrix cores: wave w owns rows [16 w, 16 w + 16)
+  // as four 16 x 16 sub-tiles; complex products as four real MFMAs.
+  const int lane = t & 63, wave = t >> 6, lr = lane & 15, lk = lane >> 4;
+  using V4 = typename MfmaAcc<T>::type;
+  V4 re[4], im[4];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
-#pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = C2{0, 0};
+  for (int st = 0; st < 4; ++st) re[st] = im[st] = V4{0, 0, 0, 0};
   for (int m0 = 0; m0 < chm; m0 += 16) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -92,24 +120,24 @@ __device__ __forceinline__ void contract_tile(ContractLds<T> &lds, double2 *cons
       Bs[kb][j] = C2{(T)w.x, (T)w.y};
     }
     __syncthreads();
-#pragma unroll 4
-    for (int kk = 0; kk < 16; ++kk) {
-      C2 a[4], b[4];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][ty * 4 + i];
+    for (int k0 = 0; k0 < 16; k0 += 4) {
+      const C2 a = As[k0 + lk][16 * wave + lr];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tx * 4 + j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) cfma(acc[i][j], a[i], b[j]);
+      for (int st = 0; st < 4; ++st) {
+        const C2 b = Bs[k0 + lk][16 * st + lr];
+        re[st] = mfma_step<T>(a.x, b.x, re[st]);
+        re[st] = mfma_step<T>(-a.y, b.y, re[st]);
+        im[st] = mfma_step<T>(a.x, b.y, im[st]);
+        im[st] = mfma_step<T>(a.y, b.x, im[st]);
+      }
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int st = 0; st < 4; ++st)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) Ms[ty * 4 + i][tx * 4 + j] = acc[i][j];
+    for (int r = 0; r < 4; ++r) Ms[16 * wave + MfmaAcc<T>::row(lk, r)][16 * st + lr] = C2{re[st][r], im[st][r]};
   __syncthreads();
   // epilogue: thread -> (l, r); 16 outputs (s', t')
   const int li = t / 16, ri = t % 16;

@@ -180,6 +180,30 @@ __global__ void scale_site_kernel(double2 *const *sites, const int *dims, int N,
     A[e] = zmul_exact(A[e], inv);
 }
 
+// out[0] = sum |A_site|^2 by one workgroup (fixed summation order).
+__global__ __launch_bounds__(256) void norm2_site_kernel(double2 *const *sites, const int *dims, int N, int site,
+                                                         double *out) {
+  __shared__ double red[256];
+  int cl, cr;
+  site_dims(dims, N, site, cl, cr);
+  const size_t n = (size_t)cl * 4 * cr;
+  const double2 *A = sites[site];
+  double acc = 0.0;
+  for (size_t e = threadIdx.x; e < n; e += 256) acc = fma(A[e].x, A[e].x, fma(A[e].y, A[e].y, acc));
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
+void launch_norm2_site(hipStream_t s, double2 *const *sites, const int *dims, int N, int site, double *out) {
+  hipLaunchKernelGGL(norm2_site_kernel, dim3(1), dim3(256), 0, s, sites, dims, N, site, out);
+  check_launch();
+}
+
 void launch_scale_site(hipStream_t s, double2 *const *sites, const int *dims, int N, int site, const double2 *tr) {
   hipLaunchKernelGGL(scale_site_kernel, dim3(256), dim3(256), 0, s, sites, dims, N, site, tr);
   check_launch();

@@ -11,7 +11,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "lmpo_internal.h"
@@ -47,6 +50,34 @@ struct Arena {
 constexpr int kMaxReq = 4096;
 constexpr int kMaxSweeps = 80;
 constexpr int kStats = 8;  // [last sweeps, last C, last R, -, total sweeps, total SVDs, -, -]
+
+// Gate table slots: exp(x L_b) with x = fraction * tau.  Slots 0, 1 serve the
+// second-order step A(tau/2) B(tau) A(tau/2); slots 2..5 the fourth-order
+// composition S2(w1 tau) S2(w0 tau) S2(w1 tau), w1 = 1 / (2 - 2^(1/3)),
+// w0 = 1 - 2 w1, with adjacent A half-layers merged: seven layers
+// A(w1/2) B(w1) A((w1+w0)/2) B(w0) A((w0+w1)/2) B(w1) A(w1/2).
+double gate_fraction(int slot) {
+  const double w1 = 1.0 / (2.0 - std::cbrt(2.0)), w0 = 1.0 - 2.0 * w1;
+  switch (slot) {
+    case 0: return 1.0;
+    case 1: return 0.5;
+    case 2: return 0.5 * w1;
+    case 3: return w1;
+    case 4: return 0.5 * (w1 + w0);
+    default: return w0;
+  }
+}
+
+struct TrotterLayer {
+  int parity;  // bonds b = parity, parity + 2, ...
+  int slot;    // gate table slot
+};
+
+const std::vector<TrotterLayer> &trotter_layers(int order) {
+  static const std::vector<TrotterLayer> o2 = {{0, 1}, {1, 0}, {0, 1}};
+  static const std::vector<TrotterLayer> o4 = {{0, 2}, {1, 3}, {0, 4}, {1, 5}, {0, 4}, {1, 3}, {0, 2}};
+  return order == 4 ? o4 : o2;
+}
 }  // namespace
 
 struct lmpo_state {
@@ -88,10 +119,10 @@ struct lmpo_state {
     if (dims_ready) (void)hipEventDestroy(dims_ready);
     if (dims_pinned) (void)hipHostFree(dims_pinned);
   }
-  double *sig = nullptr, *sorted = nullptr, *disc = nullptr;
+  double *sig = nullptr, *sorted = nullptr, *disc = nullptr, *aux = nullptr;
   double2 *tr = nullptr, *envL = nullptr, *envR = nullptr, *mout = nullptr;
   long long step_index = 0;  // global Trotter step count (fixes the layer order)
-  std::vector<std::complex<double>> gates_host;  // [nb][2][256]
+  std::vector<std::complex<double>> gates_host;  // [nb][kGateSlots][256]
 };
 
 namespace {
@@ -125,7 +156,8 @@ int validate(const lmpo_model *m, const lmpo_options *o) {
   if (!(o->cutoff >= 0) || !std::isfinite(o->cutoff)) return fail(LMPO_EINVAL, "cutoff must be >= 0");
   if (o->precision != LMPO_FP64 && o->precision != LMPO_FP32_CONTRACT)
     return fail(LMPO_EINVAL, "precision must be LMPO_FP64 or LMPO_FP32_CONTRACT");
-  if (o->trotter_order != 2) return fail(LMPO_EUNSUPPORTED, "only trotter_order = 2 is implemented");
+  if (o->trotter_order != 2 && o->trotter_order != 4)
+    return fail(LMPO_EUNSUPPORTED, "trotter_order must be 2 or 4 (order 3 is not implemented)");
   if (o->chi_max > kMaxDim / 4) return fail(LMPO_EUNSUPPORTED, "chi_max above 512 is not supported");
   // chain geometry: bond b = (b, b+1)
   if (m->n_bonds != m->n_qubits - 1) return fail(LMPO_EUNSUPPORTED, "only open chains (bonds (b, b+1)) are supported");
@@ -178,7 +210,7 @@ size_t layout(lmpo_state *S, const Sizes &z, int N, int nb, char *base, size_t s
   for (int k = 0; k < N; ++k) S->site[k] = a.take<double2>(z.site_elems[k]);
   S->d_sites = a.take<double2 *>(N);
   S->d_dims = a.take<int>(std::max(N - 1, 1));
-  S->d_gates = a.take<double2>((size_t)nb * 2 * 256);
+  S->d_gates = a.take<double2>((size_t)nb * kGateSlots * 256);
   S->X = a.take<double2>(z.x_elems);
   S->V = a.take<double2>(z.v_elems);
   int nbp = (z.max_cols + JB - 1) / JB;
@@ -188,7 +220,7 @@ size_t layout(lmpo_state *S, const Sizes &z, int N, int nb, char *base, size_t s
   const size_t slots = (size_t)(nbp - 1) * (nbp / 2);
   S->W = a.take<double2>(2 * slots * JP * JP);
   S->act = a.take<int>(2 * slots);
-  S->cmap = a.take<int>((size_t)nbp * JB);
+  S->cmap = a.take<int>((size_t)2 * nbp * JB);  // two sweeps' column orders
   S->cnorm = a.take<double>(z.max_cols);
   S->Y = a.take<double2>(z.v_elems);
   S->Lb = a.take<double2>(z.x_elems);
@@ -202,12 +234,13 @@ size_t layout(lmpo_state *S, const Sizes &z, int N, int nb, char *base, size_t s
   S->perm = a.take<int>(z.max_cols);
   S->sweep_cnt = a.take<int>(kMaxSweeps);
   S->stats = a.take<int>(kStats);
-  S->bar = a.take<unsigned>(8 * 32 + 64);
+  S->bar = a.take<unsigned>(kBarWords);
   S->tprof = a.take<unsigned long long>(32);
   S->alg_flops = a.take<double>(1);
   S->kept = a.take<int>(1);
   S->err = a.take<int>(1);
   S->disc = a.take<double>(1);
+  S->aux = a.take<double>(4);
   S->tr = a.take<double2>(1);
   S->envL = a.take<double2>((size_t)(N + 1) * z.cap_max);
   S->envR = a.take<double2>((size_t)(N + 1) * z.cap_max);
@@ -288,6 +321,7 @@ SvdLaunch svd_args(lmpo_state *S, int mode, int k, int asc) {
   L.Tq = S->Tq;
   L.qmap = S->qmap;
   L.qinv = S->qinv;
+  L.aux = S->aux;
   L.W = S->W;
   L.act = S->act;
   L.cmap = S->cmap;
@@ -318,7 +352,9 @@ int grid_for(const lmpo_state *S, int R, int C) {
   nbp += nbp & 1;
   const int npairs = std::max(1, nbp / 2);
   const int cap = S->wg_cap > 0 ? std::min(S->wg_cap, S->grid) : S->grid;
-  return std::max(1, std::min(npairs, cap));
+  // from 4 pairs up, as many workgroups again update V behind the rounds
+  const int want = npairs >= 4 ? 2 * npairs : npairs;
+  return std::max(1, std::min(want, cap));
 }
 int est(const lmpo_state *S, int bond) {
   if (bond < 0 || bond >= S->N - 1) return 1;
@@ -372,10 +408,10 @@ int move_centre(lmpo_state *S, int to) {
   return LMPO_OK;
 }
 
-int apply_gate(lmpo_state *S, int k, int half, int asc) {
+int apply_gate(lmpo_state *S, int k, int slot, int asc) {
   int rc = move_centre(S, S->centre <= k ? k : k + 1);
   if (rc) return rc;
-  const double2 *G = S->d_gates + ((size_t)k * 2 + (half ? 1 : 0)) * 256;
+  const double2 *G = S->d_gates + ((size_t)k * kGateSlots + slot) * 256;
   launch_contract_gate(S->stream, S->opt.precision, S->d_sites, S->d_dims, S->N, k, capL(S, k), capR(S, k + 1), G,
                        S->X);
   HIP_TRY(hipGetLastError());
@@ -403,16 +439,16 @@ int renormalize(lmpo_state *S) {
 
 int one_step(lmpo_state *S, long long step) {
   const int N = S->N;
-  const int layers[3][2] = {{0, 1}, {1, 0}, {0, 1}};  // (first bond parity, half?)
-  for (int j = 0; j < 3; ++j) {
-    const long long layer = 3 * step + j;
+  const std::vector<TrotterLayer> &layers = trotter_layers(S->opt.trotter_order);
+  for (int j = 0; j < (int)layers.size(); ++j) {
+    const long long layer = (long long)layers.size() * step + j;
     const bool asc = (layer % 2) == 0;
-    const int par = layers[j][0], half = layers[j][1];
+    const int par = layers[j].parity, slot = layers[j].slot;
     std::vector<int> bonds;
     for (int b = par; b < N - 1; b += 2) bonds.push_back(b);
     if (!asc) std::reverse(bonds.begin(), bonds.end());
     for (int b : bonds) {
-      int rc = apply_gate(S, b, half, asc ? 1 : 0);
+      int rc = apply_gate(S, b, slot, asc ? 1 : 0);
       if (rc) return rc;
     }
   }
@@ -460,16 +496,16 @@ int lmpo_create(const lmpo_model *model, const lmpo_options *opt, const char *in
   S->cap_max = z.cap_max;
   S->dims.assign(S->N - 1, 1);
   S->centre = 0;
-  // gate table: exp(x L_b), x in {tau, tau/2}, index [b][half]
+  // gate table: exp(x L_b) for every time fraction x / tau of the scheme, index [b][slot]
   const int nb = S->m.nb;
-  S->gates_host.assign((size_t)nb * 2 * 256, 0.0);
+  S->gates_host.assign((size_t)nb * kGateSlots * 256, 0.0);
   std::vector<std::complex<double>> L(256), A(256);
   for (int b = 0; b < nb; ++b) {
     bond_generator_pauli(S->m, b, L.data());
-    for (int half = 0; half < 2; ++half) {
-      double x = half ? 0.5 * opt->tau : opt->tau;
+    for (int slot = 0; slot < kGateSlots; ++slot) {
+      const double x = gate_fraction(slot) * opt->tau;
       for (int e = 0; e < 256; ++e) A[e] = x * L[e];
-      if (!expm_pade13(16, A.data(), &S->gates_host[((size_t)b * 2 + half) * 256])) {
+      if (!expm_pade13(16, A.data(), &S->gates_host[((size_t)b * kGateSlots + slot) * 256])) {
         delete S;
         return fail(LMPO_ENUMERIC, "matrix exponential failed");
       }
@@ -696,14 +732,14 @@ int lmpo_get_centre(lmpo_state *S, int32_t *c) {
 int lmpo_get_gate(lmpo_state *S, int32_t bond, int32_t half, double *out) {
   if (!S || !out) return fail(LMPO_EINVAL, "null argument");
   if (bond < 0 || bond >= S->m.nb) return fail(LMPO_EINVAL, "bond out of range");
-  std::memcpy(out, &S->gates_host[((size_t)bond * 2 + (half ? 1 : 0)) * 256], 256 * sizeof(double2));
+  std::memcpy(out, &S->gates_host[((size_t)bond * kGateSlots + (half ? 1 : 0)) * 256], 256 * sizeof(double2));
   return LMPO_OK;
 }
 
 int lmpo_apply_gate(lmpo_state *S, int32_t k, int32_t half, int32_t ascending) {
   if (!S) return fail(LMPO_EINVAL, "state is null");
   if (k < 0 || k >= S->N - 1) return fail(LMPO_EINVAL, "bond out of range");
-  return apply_gate(S, k, half, ascending);
+  return apply_gate(S, k, half ? 1 : 0, ascending);
 }
 
 int lmpo_last_spectrum(lmpo_state *S, int32_t n_out, double *sv, int32_t *n_sv, int32_t *kept) {
@@ -772,6 +808,40 @@ int lmpo_profile_end(lmpo_state *S, double out[3]) {
   return LMPO_OK;
 }
 
+int lmpo_renyi2(lmpo_state *S, double *out) {
+  if (!S || !out) return fail(LMPO_EINVAL, "null argument");
+  // tr(rho^dagger rho) = sum |c|^2 in the orthonormal Pauli basis = the squared
+  // norm of the orthogonality centre (every other site is an isometry)
+  launch_trace(S->stream, S->d_sites, S->d_dims, S->N, S->tr);
+  launch_norm2_site(S->stream, S->d_sites, S->d_dims, S->N, S->centre, S->aux + 2);
+  double2 tr;
+  double n2 = 0.0;
+  HIP_TRY(hipMemcpyAsync(&tr, S->tr, sizeof(double2), hipMemcpyDeviceToHost, S->stream));
+  HIP_TRY(hipMemcpyAsync(&n2, S->aux + 2, sizeof(double), hipMemcpyDeviceToHost, S->stream));
+  HIP_TRY(hipStreamSynchronize(S->stream));
+  int rc = check_err(S);
+  if (rc) return rc;
+  const double t2 = tr.x * tr.x + tr.y * tr.y;
+  if (!(t2 > 0) || !(n2 > 0) || !std::isfinite(n2)) return fail(LMPO_ENUMERIC, "trace or purity is zero or non-finite");
+  *out = -std::log(n2 / t2);
+  return LMPO_OK;
+}
+
+int lmpo_osee(lmpo_state *S, int32_t bond, double *out) {
+  if (!S || !out) return fail(LMPO_EINVAL, "null argument");
+  if (bond < 0 || bond >= S->N - 1) return fail(LMPO_EINVAL, "bond out of range");
+  int rc = move_centre(S, bond);
+  if (rc) return rc;
+  const int R = 4 * (bond == 0 ? 1 : est(S, bond - 1)), C = est(S, bond);
+  if ((rc = launch_svd(S, svd_args(S, 3, bond, 0), grid_for(S, std::max(R, C), std::min(R, C))))) return rc;
+  double h[2];
+  HIP_TRY(hipMemcpyAsync(h, S->aux, 2 * sizeof(double), hipMemcpyDeviceToHost, S->stream));
+  HIP_TRY(hipStreamSynchronize(S->stream));
+  if ((rc = check_err(S))) return rc;
+  *out = h[0];
+  return LMPO_OK;
+}
+
 int lmpo_set_workgroups(lmpo_state *S, int32_t max_workgroups) {
   if (!S) return fail(LMPO_EINVAL, "state is null");
   if (max_workgroups < 0) return fail(LMPO_EINVAL, "max_workgroups must be >= 0");
@@ -826,11 +896,31 @@ double svd_cost(int R, int C, int G, const CostModel &m) {
 }
 }  // namespace
 
+namespace {
+// Online autotuner of the batched form.  Results do not depend on how the
+// grid is split, so the batch can try plans during real steps: for each
+// (largest block bucket, precision) it runs one step under each candidate cap
+// on the workgroups per chain, times it with HIP events and keeps the fastest.
+// The table lives for the process (one per device), so later batches reuse it.
+constexpr int kTuneCaps[] = {1, 2, 4, 8, 16, 0};  // 0: the cost model's choice, uncapped
+constexpr int kTuneN = sizeof(kTuneCaps) / sizeof(kTuneCaps[0]);
+struct TuneEntry {
+  double ms[kTuneN] = {};
+  int next = 0;   // next candidate to time
+  int best = -1;  // index into kTuneCaps once all are timed
+};
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, TuneEntry> g_tune;  // (device, log2 bucket, precision)
+}  // namespace
+
 struct lmpo_batch {
   std::vector<lmpo_state *> ch;
   hipStream_t stream = nullptr;
   int n = 0, grid_max = 1;
   CostModel model;
+  bool autotune = false;
+  int wg_cap = 0;  // cap on workgroups per chain in force (0: none)
+  hipEvent_t tune_ev[2] = {nullptr, nullptr};
   // device tables (caller's arena)
   BatchChain *d_chains = nullptr;
   int *d_block_group = nullptr, *d_block_rank = nullptr, *d_group_size = nullptr;
@@ -857,6 +947,8 @@ struct lmpo_batch {
   bool ev_overflow = false;
   ~lmpo_batch() {
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+    for (hipEvent_t e : tune_ev)
+      if (e) (void)hipEventDestroy(e);
     if (stage_done) (void)hipEventDestroy(stage_done);
     if (dims_ready) (void)hipEventDestroy(dims_ready);
     if (stage) (void)hipHostFree(stage);
@@ -886,6 +978,8 @@ int batch_check_chains(lmpo_state *const *chains, int n) {
   for (int c = 0; c < n; ++c) {
     if (!chains[c]) return fail(LMPO_EINVAL, "null chain in batch");
     if (chains[c]->stream != chains[0]->stream) return fail(LMPO_EINVAL, "all chains of a batch must share one stream");
+    if (chains[c]->opt.trotter_order != chains[0]->opt.trotter_order)
+      return fail(LMPO_EINVAL, "all chains of a batch must use the same Trotter order");
     for (int d = 0; d < c; ++d)
       if (chains[d] == chains[c]) return fail(LMPO_EINVAL, "a chain appears twice in the batch");
   }
@@ -935,6 +1029,7 @@ void batch_plan(lmpo_batch *B, std::vector<int> &gsize, std::vector<int> &bgroup
   for (int c = 0; c < n; ++c) {
     cost[c] = chain_cost(B, c, 1);
     maxg[c] = chain_max_pairs(B, c);
+    if (B->wg_cap > 0) maxg[c] = std::min(maxg[c], B->wg_cap);
   }
   int total = n;
   while (total < budget) {
@@ -1022,7 +1117,26 @@ int batch_replan(lmpo_batch *B) {
                           {B->d_block_rank, br.data(), br.size() * sizeof(int)}});
 }
 
-int batch_launch(lmpo_batch *B, int local_step, int j) {
+// Tuning key: device, log2 of the largest (estimated) gate block column count
+// over the batch, and the precisions present (bit mask).
+std::tuple<int, int, int> tune_key(const lmpo_batch *B) {
+  int cmax = 1, prec = 0;
+  for (int c = 0; c < B->n; ++c) {
+    const int N = B->ch[c]->N;
+    prec |= 1 << B->ch[c]->opt.precision;
+    for (int b = 0; b < N - 1; ++b) {
+      const int l = b == 0 ? 1 : batch_est(B, c, b - 1), r = b + 1 == N - 1 ? 1 : batch_est(B, c, b + 1);
+      cmax = std::max(cmax, std::min(4 * l, 4 * r));
+    }
+  }
+  int lg = 0;
+  while ((1 << lg) < cmax) ++lg;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  return std::make_tuple(dev, lg, prec);
+}
+
+int batch_launch(lmpo_batch *B, int local_step, int j, const TrotterLayer &lay, bool last) {
   hipEvent_t *pair = nullptr;
   if (B->profiling) {
     if (B->ev_used + 2 <= B->ev.size()) {
@@ -1032,11 +1146,11 @@ int batch_launch(lmpo_batch *B, int local_step, int j) {
       B->ev_overflow = true;
     }
   }
-  const int parity = j == 1 ? 1 : 0, half = j == 1 ? 0 : 1;
+  const int parity = lay.parity, slot = lay.slot;
   if (pair) HIP_TRY(hipEventRecord(pair[0], B->stream));
   HIP_TRY(launch_batch_layer(B->stream, B->d_chains, B->d_block_group, B->d_block_rank, B->d_group_size,
-                             B->total_blocks, B->d_bar, (size_t)B->n * kBarWords, local_step, j, parity, half,
-                             j == 2 ? 1 : 0));
+                             B->total_blocks, B->d_bar, (size_t)B->n * kBarWords, local_step, j, parity, slot,
+                             last ? 1 : 0));
   if (pair) HIP_TRY(hipEventRecord(pair[1], B->stream));
   return LMPO_OK;
 }
@@ -1082,6 +1196,8 @@ int lmpo_batch_create(lmpo_state *const *chains, int32_t n_chains, void *device_
   hipError_t e = hipEventCreateWithFlags(&B->stage_done, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventRecord(B->stage_done, B->stream);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&B->dims_ready, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreate(&B->tune_ev[0]);
+  if (e == hipSuccess) e = hipEventCreate(&B->tune_ev[1]);
   if (e == hipSuccess) e = hipHostMalloc((void **)&B->dims_pinned, std::max(B->dims_total, 1) * sizeof(int), hipHostMallocDefault);
   if (e == hipSuccess) e = hipMemsetAsync(B->d_flops, 0, n_chains * sizeof(double), B->stream);
   if (e != hipSuccess) return cleanup(fail(LMPO_EHIP, std::string("batch init: ") + hipGetErrorString(e)));
@@ -1128,9 +1244,40 @@ int lmpo_batch_evolve_step(lmpo_batch *B, int32_t n_steps) {
   if (rc) return rc;
   for (int s = 0; s < n_steps; ++s) {
     batch_refresh_estimates(B);
+    // autotuner: the cap of this step (a candidate under trial, or the best known)
+    int trial = -1;
+    std::tuple<int, int, int> key;
+    {
+      key = tune_key(B);
+      std::lock_guard<std::mutex> lock(g_tune_mu);
+      auto it = g_tune.find(key);
+      if (it != g_tune.end() && it->second.best >= 0) {
+        B->wg_cap = kTuneCaps[it->second.best];
+      } else if (B->autotune) {
+        trial = g_tune[key].next;
+        B->wg_cap = kTuneCaps[trial];
+      } else {
+        B->wg_cap = 0;
+      }
+    }
     if ((rc = batch_replan(B))) return rc;
-    for (int j = 0; j < 3; ++j)
-      if ((rc = batch_launch(B, s, j))) return rc;
+    if (trial >= 0) HIP_TRY(hipEventRecord(B->tune_ev[0], B->stream));
+    const std::vector<TrotterLayer> &layers = trotter_layers(B->ch[0]->opt.trotter_order);
+    for (int j = 0; j < (int)layers.size(); ++j)
+      if ((rc = batch_launch(B, s, j, layers[j], j + 1 == (int)layers.size()))) return rc;
+    if (trial >= 0) {
+      HIP_TRY(hipEventRecord(B->tune_ev[1], B->stream));
+      HIP_TRY(hipEventSynchronize(B->tune_ev[1]));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, B->tune_ev[0], B->tune_ev[1]));
+      std::lock_guard<std::mutex> lock(g_tune_mu);
+      TuneEntry &te = g_tune[key];
+      if (te.best < 0 && te.next == trial) {
+        te.ms[trial] = ms;
+        te.next = trial + 1;
+        if (te.next == kTuneN) te.best = (int)(std::min_element(te.ms, te.ms + kTuneN) - te.ms);
+      }
+    }
     if (hipEventQuery(B->dims_ready) != hipErrorNotReady) {
       HIP_TRY(hipMemcpyAsync(B->dims_pinned, B->d_dims, B->dims_total * sizeof(int), hipMemcpyDeviceToHost, B->stream));
       HIP_TRY(hipEventRecord(B->dims_ready, B->stream));
@@ -1156,6 +1303,33 @@ int lmpo_batch_sync(lmpo_batch *B) {
     int rc = check_err(B->ch[c]);
     if (rc) return fail(rc, "chain " + std::to_string(c) + ": " + g_err);
   }
+  return LMPO_OK;
+}
+
+int lmpo_batch_set_autotune(lmpo_batch *B, int32_t enable) {
+  if (!B) return fail(LMPO_EINVAL, "batch is null");
+  B->autotune = enable != 0;
+  return LMPO_OK;
+}
+
+int lmpo_autotune_table(int32_t max_entries, int32_t *log2_bucket, int32_t *precisions, int32_t *cap,
+                        double *best_ms, int32_t *n_entries) {
+  if (!n_entries || max_entries < 0 || (max_entries > 0 && (!log2_bucket || !precisions || !cap || !best_ms)))
+    return fail(LMPO_EINVAL, "null argument");
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  int n = 0, dev = 0;
+  (void)hipGetDevice(&dev);
+  for (const auto &kv : g_tune) {
+    if (std::get<0>(kv.first) != dev || kv.second.best < 0) continue;
+    if (n < max_entries) {
+      log2_bucket[n] = std::get<1>(kv.first);
+      precisions[n] = std::get<2>(kv.first);
+      cap[n] = kTuneCaps[kv.second.best];
+      best_ms[n] = kv.second.ms[kv.second.best];
+    }
+    ++n;
+  }
+  *n_entries = n;
   return LMPO_OK;
 }
 

@@ -27,6 +27,7 @@ void bond_generator_pauli(const ModelHost &m, int bond, std::complex<double> *L)
 constexpr int JB = 8;
 constexpr int JP = 2 * JB;
 constexpr int kMaxDim = 2048;  // largest block side (4 chi) the sort handles
+constexpr int kGateSlots = 6;  // gates per bond: second- and fourth-order time fractions
 
 // ---- kernel launchers (kernels.hip, svd.hip) ----
 void launch_contract_gate(hipStream_t s, int precision, double2 *const *sites, const int *dims, int N, int k,
@@ -34,7 +35,8 @@ void launch_contract_gate(hipStream_t s, int precision, double2 *const *sites, c
 
 // One persistent cooperative launch: mode 0 = truncated SVD + canonical update
 // of the two-site block on bond k (X filled by the contraction); mode 1/2 =
-// exact centre hop right/left from site k.
+// exact centre hop right/left from site k; mode 3 = singular values of site k
+// as a (4 chi_l) x chi_r matrix and their entropy (no change of the state).
 struct SvdLaunch {
   int mode, k, N, asc, chi_max, max_sweeps;
   double cutoff, tol_factor;
@@ -46,6 +48,7 @@ struct SvdLaunch {
   double2 *Tq;  // T factors of the QR panels, kQrNbMax^2 each
   int *qmap;    // QR column order (logical -> physical column of X)
   int *qinv;    // its inverse
+  double *aux;  // mode 3 results: (entropy, total squared weight)
   int *act;
   int *cmap;
   double *cnorm;
@@ -62,7 +65,7 @@ hipError_t launch_svd_persistent(hipStream_t s, const SvdLaunch &L, int grid);
 // Batched form: one chain of a batch as seen by the per-layer kernel.
 struct BatchChain {
   SvdLaunch L;           // the chain's buffers (mode, k, asc set per op); L.bar is its barrier block
-  const double2 *gates;  // [nb][2][256]
+  const double2 *gates;  // [nb][kGateSlots][256]
   int *centre;           // orthogonality centre, kept on the device between layers
   double2 *tr;           // trace scratch
   int *dims_out;         // copy of the bond dims after each layer (or null)
@@ -77,14 +80,16 @@ int batch_grid_size();
 // zeroed first.
 hipError_t launch_batch_layer(hipStream_t s, const BatchChain *d_chains, const int *d_block_group,
                               const int *d_block_rank, const int *d_group_size, int total_blocks, unsigned *bar_base,
-                              size_t bar_words, int local_step, int j, int parity, int half, int last_layer);
-constexpr size_t kBarWords = 8 * 32 + 64;  // one grid-barrier block
+                              size_t bar_words, int local_step, int j, int parity, int slot, int last_layer);
+constexpr size_t kBarBlock = 8 * 32 + 64;   // one grid barrier: 8 group counters, top, flag
+constexpr size_t kBarWords = 2 * kBarBlock;  // a problem's full-group and pair-group barriers
 
 void launch_trace(hipStream_t s, double2 *const *sites, const int *dims, int N, double2 *out);
 void launch_env_all(hipStream_t s, double2 *const *sites, const int *dims, int N, int cap,
                     double2 *envL, double2 *envR);
 void launch_measure(hipStream_t s, double2 *const *sites, const int *dims, int N, int cap,
                     const double2 *envL, const double2 *envR, int n, const int *req, double2 *out);
+void launch_norm2_site(hipStream_t s, double2 *const *sites, const int *dims, int N, int site, double *out);
 void launch_scale_site(hipStream_t s, double2 *const *sites, const int *dims, int N, int site,
                        const double2 *tr);
 

@@ -135,11 +135,13 @@ __device__ __forceinline__ void pair_blocks(int round, int p, int nbp, int &bi, 
 // Partner of index i in step `step` of the round-robin over JP indices.
 __device__ __forceinline__ int inner_partner(int i, int step) {
   const int m = JP - 1;
-  if (i == m) return step;
-  if (i == step) return m;
-  // i = (step + t) % m  <->  partner = (step - t) % m
-  int t = (i - step + m) % m;
-  return (step - t + m) % m;
+  // i = (step + t) % m  <->  partner = (step - t) % m, i.e. (2 step - i) mod m;
+  // index m pairs with index step
+  int p = 2 * step - i;
+  p += p < 0 ? m : 0;
+  p += p < 0 ? m : 0;
+  p -= p >= m ? m : 0;
+  return i == m ? step : (i == step ? m : p);
 }
 
 constexpr int kChunk = 512;  // rows of a column pair staged in LDS at once
@@ -311,24 +313,23 @@ __device__ bool pair_work(SharedPair &s, double2 *__restrict__ X, int ldx, int R
   // s = tau cs, cs = 1 / sqrt(1 + |tau|^2) and the small root
   // tau = 2 conj(g_pq) / (d + sgn(d) sqrt(d^2 + 4 |g_pq|^2)), d = g_pp - g_qq.
   // Returns false (identity) when g_pq is below the threshold.
+  // Branch-free, so that the two rotations a thread needs run interleaved:
+  // the arithmetic is always done and the identity selected below threshold.
   auto rotation = [&](int p, int q, double &cs, double2 &sc) {
     const double app = s.G[cur][p][p].x, aqq = s.G[cur][q][q].x;
     const double2 c = s.G[cur][p][q];
     const double mc2 = fma(c.x, c.x, c.y * c.y);
-    if (!(mc2 > tol2 * (app * aqq) && mc2 > 1e-290)) {  // (normal range for the rsq estimates)
-      cs = 1.0;
-      sc = make_double2(0.0, 0.0);
-      return false;
-    }
+    const bool on = mc2 > tol2 * (app * aqq) && mc2 > 1e-290;  // (normal range for the rsq estimates)
     const double d = app - aqq;
-    const double r2 = fma(d, d, 4.0 * mc2);
+    const double r2 = on ? fma(d, d, 4.0 * mc2) : 1.0;
     const double r = r2 * rsq_nr(r2);
-    const double den = d + copysign(r, d);
+    const double den = on ? d + copysign(r, d) : 1.0;
     const double f = 2.0 * rcp_nr(den);
     const double2 tau = make_double2(f * c.x, -f * c.y);
-    cs = rsq_nr(fma(tau.x, tau.x, fma(tau.y, tau.y, 1.0)));
-    sc = make_double2(tau.x * cs, tau.y * cs);
-    return true;
+    const double cz = rsq_nr(fma(tau.x, tau.x, fma(tau.y, tau.y, 1.0)));
+    cs = on ? cz : 1.0;
+    sc = on ? make_double2(tau.x * cz, tau.y * cz) : make_double2(0.0, 0.0);
+    return on;
   };
   for (int sweep = 0; sweep < kInnerSweeps; ++sweep) {
     for (int step = 0; step < JP - 1; ++step) {
@@ -600,6 +601,14 @@ __device__ void svd_body(const SvdLaunch &a, Barrier &bar, SharedAll &sh) {
     chr = dimR(site + 1);  // right dim of the neighbour
     R = 4 * chl;
     C = chm;
+  } else if (a.mode == 3) {
+    // spectrum of site k as a (4 chl) x chr matrix (or its adjoint when wider)
+    chl = dimL(site);
+    chr = dimR(site);
+    const int r = 4 * chl, c = chr;
+    trans = r >= c ? 0 : 1;
+    R = trans ? c : r;
+    C = trans ? r : c;
   } else {
     chm = ld_dim(a.dims + site - 1);
     chr = dimR(site);
@@ -638,8 +647,17 @@ __device__ void svd_body(const SvdLaunch &a, Barrier &bar, SharedAll &sh) {
       int i = e / R, j = e % R;  // A[i][j], i < chm, j < 4 chr
       a.X[(size_t)j + (size_t)i * ldx] = zconj(A[e]);
     }
+  } else if (a.mode == 3) {
+    const double2 *A = a.sites[site];  // (4 chl) x chr, row-major
+    for (size_t e = gtid; e < (size_t)R * C; e += gstride) {
+      const int i = e / chr, j = e % chr;
+      if (trans == 0)
+        a.X[(size_t)i + (size_t)j * ldx] = A[e];
+      else
+        a.X[(size_t)j + (size_t)i * ldx] = zconj(A[e]);
+    }
   }
-  if (a.mode == 0) {
+  if (a.mode == 0 || a.mode == 3) {
     colnorms(a.X, ldx, R, a.cnorm, false);
     bar.sync();
     if (rank == 0) order_columns(sh.sel, a.cnorm, C, C, a.qmap);
@@ -684,7 +702,7 @@ __device__ void svd_body(const SvdLaunch &a, Barrier &bar, SharedAll &sh) {
     lap(19);
   };
   lap(0);
-  if (a.mode != 0) {
+  if (a.mode == 1 || a.mode == 2) {
     // ---- hop: explicit thin Q, then A_c <- Q (or Q^H), neighbour <- R A (or A R^H) ----
     const int k = nq;
     for (size_t e = gtid; e < (size_t)R * k; e += gstride) {
@@ -806,47 +824,113 @@ __device__ void svd_body(const SvdLaunch &a, Barrier &bar, SharedAll &sh) {
     a.V[e] = make_double2(i == j ? 1.0 : 0.0, 0.0);
   }
   if (gtid < (size_t)a.max_sweeps) a.sweep_cnt[gtid] = 0;
-  bar.sync();
   // ---- block Jacobi sweeps on Y ----
   int nbp = (C + JB - 1) / JB;
   nbp += nbp & 1;
   if (nbp < 2) nbp = 2;
   const int npairs = nbp / 2;
+  // Workgroups [0, np) do the pair rounds under their own barrier; the others
+  // (nv of them) apply the previous sweep's rotations to V meanwhile, so the V
+  // update leaves the critical path.  The pair barrier's counters are cleared
+  // here (every workgroup has left its previous use behind a full barrier).
+  const int np = G < npairs ? G : npairs, nv = G - np;
+  if (rank == 0 && threadIdx.x < 10) {
+    unsigned *pb = a.bar + kBarBlock;
+    pb[threadIdx.x < 8 ? threadIdx.x * 32 : 8 * 32 + (threadIdx.x - 8) * 32] = 0u;
+  }
+  bar.sync();
+  Barrier pbar{a.bar + kBarBlock, a.bar + kBarBlock + 8 * 32, a.bar + kBarBlock + 8 * 32 + 32, a.err,
+               (unsigned)np, rank < (unsigned)np ? rank : 0u, 0u};
   const double tol = a.tol_factor * sqrt((double)C) * 2.220446049250313e-16;
-  int sweeps = 0;
+  int sweeps = 0, pending = -1;  // pending: active sweep whose V update is outstanding
   const size_t wsw_stride = (size_t)(nbp - 1) * npairs;  // pair slots per sweep
+  const size_t cmap_stride = (size_t)nbp * JB;
+  auto update_v = [&](int sw, int workers, int me) {
+    sweep_update_v(sh.pair, a.V, ldv, C, nbp, a.W + (size_t)(sw & 1) * wsw_stride * JP * JP,
+                   a.act + (size_t)(sw & 1) * wsw_stride, workers, a.cmap + (sw & 1) * cmap_stride, me);
+  };
   for (int sweep = 0; sweep < a.max_sweeps; ++sweep) {
     double2 *Wsw = a.W + (size_t)(sweep & 1) * wsw_stride * JP * JP;
     int *act = a.act + (size_t)(sweep & 1) * wsw_stride;
+    int *cmap = a.cmap + (sweep & 1) * cmap_stride;
     // order the columns by decreasing norm for this sweep (blocks then hold
     // columns of similar size, which speeds up convergence on graded spectra)
     colnorms(Y, ldy, C, a.cnorm, false);
     bar.sync();
-    if (rank == 0) order_columns(sh.sel, a.cnorm, C, nbp * JB, a.cmap);
+    if (rank == 0) order_columns(sh.sel, a.cnorm, C, nbp * JB, cmap);
     bar.sync();
-    for (int round = 0; round < nbp - 1; ++round) {
-      for (int p = rank; p < npairs; p += G) {
-        int bi, bj;
-        pair_blocks(round, p, nbp, bi, bj);
-        const size_t slot = (size_t)round * npairs + p;
-        bool active = pair_work(sh.pair, Y, ldy, C, Wsw + slot * JP * JP, C, bi, bj, tol, a.cmap,
-                                (a.tprof && rank == 0) ? a.tprof : nullptr);
-        if (threadIdx.x == 0) {
-          act[slot] = active ? 1 : 0;
-          if (active) atomicAdd(&a.sweep_cnt[sweep], 1);
+    if ((int)rank < np) {
+      for (int round = 0; round < nbp - 1; ++round) {
+        for (int p = rank; p < npairs; p += np) {
+          int bi, bj;
+          pair_blocks(round, p, nbp, bi, bj);
+          const size_t slot = (size_t)round * npairs + p;
+          bool active = pair_work(sh.pair, Y, ldy, C, Wsw + slot * JP * JP, C, bi, bj, tol, cmap,
+                                  (a.tprof && rank == 0) ? a.tprof : nullptr);
+          if (threadIdx.x == 0) {
+            act[slot] = active ? 1 : 0;
+            if (active) atomicAdd(&a.sweep_cnt[sweep], 1);
+          }
+          __syncthreads();
         }
+        lap(1);
+        pbar.sync();
+        lap(2);
+      }
+    } else if (pending >= 0) {
+      update_v(pending, nv, rank - np);
+    }
+    bar.sync();
+    sweeps = sweep + 1;
+    const bool converged =
+        __hip_atomic_load(&a.sweep_cnt[sweep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+    if (nv == 0) {
+      if (converged) break;
+      update_v(sweep, G, rank);
+      lap(11);
+    } else {
+      pending = converged ? -1 : sweep;
+      if (converged) break;
+    }
+  }
+  if (pending >= 0) update_v(pending, G, rank);  // the sweep limit was reached while rotating
+  bar.sync();
+  if (a.mode == 3) {
+    // ---- spectrum only: OSEE = -sum p ln p, p = sigma^2 / sum sigma^2 (no state change) ----
+    colnorms(Y, ldy, C, a.sig, false);
+    bar.sync();
+    if (rank == 0) {
+      double w = 0.0;
+      for (int j = threadIdx.x; j < C; j += NT) w += a.sig[j];
+      sh.red[threadIdx.x] = w;
+      __syncthreads();
+      for (int off = NT / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh.red[threadIdx.x] += sh.red[threadIdx.x + off];
         __syncthreads();
       }
-      lap(1);
-      bar.sync();
-      lap(2);
+      const double W = sh.red[0];
+      __syncthreads();
+      double h = 0.0;
+      for (int j = threadIdx.x; j < C; j += NT) {
+        const double p = a.sig[j] / W;
+        if (p > 0.0) h -= p * log(p);
+      }
+      sh.red[threadIdx.x] = h;
+      __syncthreads();
+      for (int off = NT / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh.red[threadIdx.x] += sh.red[threadIdx.x + off];
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) {
+        a.aux[0] = sh.red[0];
+        a.aux[1] = W;
+        if (!(W > 0.0) || !(sh.red[0] >= 0.0)) atomicOr(a.err, 1);
+      }
     }
-    sweeps = sweep + 1;
-    if (__hip_atomic_load(&a.sweep_cnt[sweep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) break;
-    sweep_update_v(sh.pair, a.V, ldv, C, nbp, Wsw, act, G, a.cmap, rank);
-    lap(11);
+    lap(5);
+    if (prof) a.tprof[12] += clock64() - cyc0;
+    return;
   }
-  bar.sync();
   // ---- singular values, truncation select; inverse of the QR column order ----
   colnorms(Y, ldy, C, a.sig, true);
   for (size_t e = gtid; e < (size_t)C; e += gstride) a.qinv[a.qmap[e]] = (int)e;
@@ -929,10 +1013,10 @@ __global__ __launch_bounds__(NT) void svd_persistent_kernel(SvdLaunch a) {
 // group_size[g] workgroups; the group walks the layer's gates in order, each
 // preceded by the centre hops that bring the orthogonality centre onto the
 // bond, as the single-chain executor does (the same device code per op).
-// The layer of chain g is the global layer 3 n_g + j with n_g = its step
-// count; it runs ascending when that index is even, i.e. when
-// step_parity[g] + local_step + j is even.  Bonds b = parity, parity + 2, ...
-// < N - 1 get exp(x L_b) with x = tau/2 (half) or tau.
+// The layer of chain g is the global layer L n_g + j (L = 3 or 7 layers per
+// step, n_g = its step count); it runs ascending when that index is even,
+// i.e. (L odd) when step_parity[g] + local_step + j is even.  Bonds b =
+// parity, parity + 2, ... < N - 1 get the gate in table slot `slot`.
 // ---------------------------------------------------------------------------
 union SharedBatch {
   SharedAll all;
@@ -945,7 +1029,7 @@ __global__ __launch_bounds__(NT) void batch_layer_kernel(const BatchChain *__res
                                                          const int *__restrict__ block_group,
                                                          const int *__restrict__ block_rank,
                                                          const int *__restrict__ group_size, int local_step,
-                                                         int j, int parity, int half, int last_layer) {
+                                                         int j, int parity, int slot, int last_layer) {
   __shared__ SharedBatch sh;
   const int g = block_group[blockIdx.x];
   const unsigned rank = block_rank[blockIdx.x], G = group_size[g];
@@ -969,7 +1053,7 @@ __global__ __launch_bounds__(NT) void batch_layer_kernel(const BatchChain *__res
     const int target = centre <= b ? b : b + 1;
     const bool gate = centre == target;
     if (gate) {
-      const double2 *Gt = gates + ((size_t)b * 2 + (half ? 1 : 0)) * 256;
+      const double2 *Gt = gates + ((size_t)b * kGateSlots + slot) * 256;
       const int chl = b == 0 ? 1 : ld_dim(L.dims + b - 1), chr = b + 1 == N - 1 ? 1 : ld_dim(L.dims + b + 1);
       const int tx = (chr + 15) / 16, ntiles = tx * ((chl + 15) / 16);
       for (int t = rank; t < ntiles; t += G) {
@@ -1031,7 +1115,7 @@ int svd_grid_size() {
 }
 
 hipError_t launch_svd_persistent(hipStream_t s, const SvdLaunch &L, int grid) {
-  hipError_t e = hipMemsetAsync(L.bar, 0, (8 * 32 + 64) * sizeof(unsigned), s);
+  hipError_t e = hipMemsetAsync(L.bar, 0, kBarWords * sizeof(unsigned), s);
   if (e != hipSuccess) return e;
   SvdLaunch a = L;
   void *args[] = {&a};
@@ -1051,11 +1135,11 @@ int batch_grid_size() {
 
 hipError_t launch_batch_layer(hipStream_t s, const BatchChain *d_chains, const int *d_block_group,
                               const int *d_block_rank, const int *d_group_size, int total_blocks, unsigned *bar_base,
-                              size_t bar_words, int local_step, int j, int parity, int half, int last_layer) {
+                              size_t bar_words, int local_step, int j, int parity, int slot, int last_layer) {
   hipError_t e = hipMemsetAsync(bar_base, 0, bar_words * sizeof(unsigned), s);
   if (e != hipSuccess) return e;
   void *args[] = {(void *)&d_chains, (void *)&d_block_group, (void *)&d_block_rank, (void *)&d_group_size,
-                  &local_step, &j, &parity, &half, &last_layer};
+                  &local_step, &j, &parity, &slot, &last_layer};
   return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(batch_layer_kernel), dim3(total_blocks), dim3(NT),
                                     args, 0, s);
 }

@@ -62,8 +62,10 @@ EXPORTS = [
     "lmpo_destroy", "lmpo_last_error", "lmpo_get_site", "lmpo_set_site", "lmpo_set_centre",
     "lmpo_get_centre", "lmpo_get_gate", "lmpo_apply_gate", "lmpo_last_spectrum", "lmpo_svd_stats",
     "lmpo_svd_profile", "lmpo_profile_begin", "lmpo_profile_end", "lmpo_set_workgroups",
+    "lmpo_renyi2", "lmpo_osee",
     "lmpo_batch_arena_bytes", "lmpo_batch_create", "lmpo_batch_evolve_step", "lmpo_batch_sync",
     "lmpo_batch_plan", "lmpo_batch_profile_begin", "lmpo_batch_profile_end", "lmpo_batch_destroy",
+    "lmpo_batch_set_autotune", "lmpo_autotune_table",
 ]
 
 
@@ -105,6 +107,8 @@ def load_library(path: str = LIB_PATH):
         "lmpo_profile_begin": (ctypes.c_int, [P, i32]),
         "lmpo_profile_end": (ctypes.c_int, [P, pdbl]),
         "lmpo_set_workgroups": (ctypes.c_int, [P, i32]),
+        "lmpo_renyi2": (ctypes.c_int, [P, pdbl]),
+        "lmpo_osee": (ctypes.c_int, [P, i32, pdbl]),
         "lmpo_batch_arena_bytes": (ctypes.c_size_t, [ctypes.POINTER(P), i32]),
         "lmpo_batch_create": (ctypes.c_int, [ctypes.POINTER(P), i32, P, ctypes.c_size_t, ctypes.POINTER(P)]),
         "lmpo_batch_evolve_step": (ctypes.c_int, [P, i32]),
@@ -113,6 +117,8 @@ def load_library(path: str = LIB_PATH):
         "lmpo_batch_profile_begin": (ctypes.c_int, [P, i32]),
         "lmpo_batch_profile_end": (ctypes.c_int, [P, pdbl]),
         "lmpo_batch_destroy": (ctypes.c_int, [P]),
+        "lmpo_batch_set_autotune": (ctypes.c_int, [P, i32]),
+        "lmpo_autotune_table": (ctypes.c_int, [i32, pi32, pi32, pi32, pdbl, pi32]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -244,6 +250,18 @@ class Chain:
         z2 = self.measure_2q(ii, jj, "ZZ")
         return z1, z2
 
+    def renyi2(self):
+        """S_2 = -ln tr(rho^2) (Eq. S_2)."""
+        out = np.zeros(1)
+        _check(self._lib.lmpo_renyi2(self._h, _dptr(out)))
+        return float(out[0])
+
+    def osee(self, bond):
+        """Operator-space entanglement entropy across bond (bond, bond+1) (Eq. OSEE)."""
+        out = np.zeros(1)
+        _check(self._lib.lmpo_osee(self._h, int(bond), _dptr(out)))
+        return float(out[0])
+
     def bond_dims(self):
         out = np.zeros(self.N - 1, dtype=np.int32)
         _check(self._lib.lmpo_bond_dims(self._h, _iptr(out)))
@@ -354,6 +372,23 @@ class Batch:
 
     def sync(self):
         _check(self._lib.lmpo_batch_sync(self._h))
+
+    def set_autotune(self, enable=True):
+        _check(self._lib.lmpo_batch_set_autotune(self._h, int(bool(enable))))
+
+    @staticmethod
+    def tuning_table():
+        """[(log2 block bucket, precision mask, cap, best ms)] tuned so far on this device."""
+        lib = load_library()
+        n = np.zeros(1, dtype=np.int32)
+        _check(lib.lmpo_autotune_table(0, None, None, None, None, _iptr(n)))
+        m = int(n[0])
+        if m == 0:
+            return []
+        b, p, c = (np.zeros(m, dtype=np.int32) for _ in range(3))
+        ms = np.zeros(m)
+        _check(lib.lmpo_autotune_table(m, _iptr(b), _iptr(p), _iptr(c), _dptr(ms), _iptr(n)))
+        return [(int(b[i]), int(p[i]), int(c[i]), float(ms[i])) for i in range(m)]
 
     def plan(self):
         """Workgroups per chain in the current launch plan."""

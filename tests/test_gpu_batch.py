@@ -195,3 +195,28 @@ def test_batch_errors(lib):
         lib.Batch([])
     a.close()
     c.close()
+
+
+def test_batch_autotune_keeps_results(lib):
+    """Autotuning tries several workgroup caps during real steps: the state is
+    the same bits as without tuning, and the tuned entries are recorded."""
+    models = uneven_models()
+    # chi_max = 8 saturates within a few steps, so the block-size bucket settles
+    # and its six candidate steps complete within the run
+    a = [lib.Chain(m, 0.05, 8, 1e-12, "fp64", "+x") for m in models]
+    r = [lib.Chain(m, 0.05, 8, 1e-12, "fp64", "+x") for m in models]
+    ba = lib.Batch(a)
+    ba.set_autotune(True)
+    ba.evolve(20)
+    ba.sync()
+    for ch in r:
+        ch.evolve(20)
+        ch.sync()
+    for x, y in zip(a, r):
+        assert_same_state(x, y)
+    table = lib.Batch.tuning_table()
+    assert len(table) >= 1
+    assert all(cap in (0, 1, 2, 4, 8, 16) and ms > 0 for _, _, cap, ms in table)
+    ba.close()
+    for ch in a + r:
+        ch.close()

@@ -1,0 +1,124 @@
+"""GPU parity of the paper features next to the step: the fourth-order Trotter
+scheme (Sec. 6, trotter_order), the second Renyi entropy (Eq. S_2) and the
+operator-space entanglement entropy (Eq. OSEE), against the FP64 oracle."""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import model as lm
+from oracle import tebd
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def lib():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2203_05871_amd as p
+
+    p.load_library()
+    return p
+
+
+def obs(ch, N):
+    return np.concatenate([ch.measure_1q(np.arange(N), "Z"), ch.measure_1q(np.arange(N), "X"),
+                           ch.measure_2q(np.arange(N - 1), np.arange(1, N), "ZZ")])
+
+
+def oracle_obs(mps, N):
+    z = [mps.expect({i: lm.SZ}) for i in range(N)]
+    x = [mps.expect({i: lm.SX}) for i in range(N)]
+    zz = [mps.expect({i: lm.SZ, i + 1: lm.SZ}) for i in range(N - 1)]
+    return np.array(z + x + zz)
+
+
+def test_fourth_order_exact_chain(lib):
+    """N = 6 at chi = 64 = 4^3 (no truncation), every model term on, 12 steps."""
+    m = workloads.random_model(6, 9)
+    ch = lib.Chain(m, 0.05, 64, 0.0, "fp64", "+x", order=4)
+    ref = tebd.MPS.product("+x", 6)
+    for n in range(0, 12, 4):
+        ch.evolve(4)
+        tebd.evolve(ref, m, 0.05, 4, 64, 0.0, first_step=n, order=4)
+        assert np.abs(obs(ch, 6) - oracle_obs(ref, 6)).max() < 1e-10
+    assert ch.bond_dims() == ref.bond_dims()
+    ch.close()
+
+
+def test_fourth_order_truncated(lib):
+    """Jittered chain N = 10, chi_max = 12 binding, cutoff 1e-12, 8 steps."""
+    m = workloads.jittered_chain(10, 4)
+    ch = lib.Chain(m, 0.05, 12, 1e-12, "fp64", "+x", order=4)
+    ref = tebd.MPS.product("+x", 10)
+    ch.evolve(8)
+    tebd.evolve(ref, m, 0.05, 8, 12, 1e-12, order=4)
+    assert ch.bond_dims() == ref.bond_dims()
+    assert max(ch.bond_dims()) == 12
+    assert np.abs(obs(ch, 10) - oracle_obs(ref, 10)).max() < 1e-10
+    ch.close()
+
+
+def test_fourth_order_batch_equals_single(lib):
+    ms = [workloads.jittered_chain(7, 1), workloads.random_model(5, 2)]
+    b_chains = [lib.Chain(m, 0.05, 16, 1e-12, "fp64", "+x", order=4) for m in ms]
+    singles = [lib.Chain(m, 0.05, 16, 1e-12, "fp64", "+x", order=4) for m in ms]
+    b = lib.Batch(b_chains)
+    b.evolve(3)
+    b.sync()
+    for x, y in zip(b_chains, singles):
+        y.evolve(3)
+        assert x.bond_dims() == y.bond_dims()
+        for k in range(x.N):
+            assert np.array_equal(x.get_site(k), y.get_site(k))
+    b.close()
+    with pytest.raises(lib.LmpoError, match="Trotter order"):
+        lib.Batch([b_chains[0], lib.Chain(ms[0], 0.05, 16, 1e-12, "fp64", "+x", order=2)])
+    for c in b_chains + singles:
+        c.close()
+
+
+def test_renyi2_and_osee_parity(lib):
+    """S_2 and the OSEE of every bond after truncated evolution; evolution
+    continues to agree after the OSEE has moved the orthogonality centre."""
+    m = workloads.jittered_chain(9, 6)
+    ch = lib.Chain(m, 0.05, 20, 1e-12, "fp64", "+x")
+    ref = tebd.MPS.product("+x", 9)
+    assert abs(ch.renyi2() - ref.renyi2()) < 1e-12
+    assert abs(ch.osee(4)) < 1e-12  # product state
+    ch.evolve(6)
+    tebd.evolve(ref, m, 0.05, 6, 20, 1e-12)
+    assert abs(ch.renyi2() - ref.renyi2()) < 1e-10
+    for bond in (4, 0, 7, 2):
+        g, r = ch.osee(bond), ref.osee(bond)
+        assert abs(g - r) < 1e-10, (bond, g, r)
+        assert g > 0
+    ch.evolve(3)
+    tebd.evolve(ref, m, 0.05, 3, 20, 1e-12, first_step=6)
+    assert ch.bond_dims() == ref.bond_dims()
+    assert np.abs(obs(ch, 9) - oracle_obs(ref, 9)).max() < 1e-10
+    assert abs(ch.renyi2() - ref.renyi2()) < 1e-10
+    ch.close()
+
+
+def test_osee_wide_centre_site(lib):
+    """A centre site wider than tall (chi_r > 4 chi_l: an injected state with a
+    non-minimal bond) takes the adjoint branch; the hop away from it compresses
+    the bond to its rank exactly as the oracle's QR does."""
+    from test_gpu_fullsize import random_canonical_mps
+
+    dims = [2, 16, 16, 16, 4]  # N = 6; site 1 is 2 x 4 x 16, an 8 x 16 matrix
+    m = workloads.jittered_chain(6, 3)
+    A = random_canonical_mps(dims, 1, 8)
+    ch = lib.Chain(m, 0.05, 64, 0.0, "fp64", "+z")
+    for k, t in enumerate(A):
+        ch.set_site(k, t)
+    ch.set_centre(1)
+    ref = tebd.MPS(tebd.from_pauli(A), centre=1)
+    for bond in (1, 2, 4, 0):
+        g, r = ch.osee(bond), ref.osee(bond)
+        assert abs(g - r) < 1e-10, (bond, g, r)
+    assert ch.bond_dims() == ref.bond_dims()
+    ch.close()
