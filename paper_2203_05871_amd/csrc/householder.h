@@ -19,9 +19,8 @@
 namespace lmpo {
 
 constexpr int NT_QR = 256;            // threads per workgroup
-constexpr int kQrNbMax = 8;           // reflectors per panel (4 when the panel has more than kQrRows rows)
-constexpr int kQrRows = 1024;         // panel rows that fit in LDS at width 8
-constexpr int kQrPanelElems = kQrRows * kQrNbMax;
+constexpr int kQrNbMax = 8;           // reflectors per panel: 8 up to 1024 rows, 4 beyond
+constexpr int kQrPanelElems = 8192;   // panel elements held in LDS (rows x width)
 
 struct SharedQR {
   double2 P[kQrPanelElems];           // panel (factor) or reflectors (update), column-major, ld = m
@@ -118,8 +117,21 @@ __device__ __forceinline__ void block_sum_n(SharedQR &s, double2 *acc, int n) {
 
 }  // namespace qr
 
-// Panel width for an R-row matrix.
-__device__ __host__ inline int qr_panel_width(int R) { return R <= kQrRows ? kQrNbMax : kQrNbMax / 2; }
+// Panel width for an R-row matrix (the panel of R x width elements fits in LDS).
+__device__ __host__ inline int qr_panel_width(int R) { return R <= 1024 ? 8 : 4; }
+
+// 1/x and sqrt(x) from the hardware estimates plus Newton steps (x > 0 normal).
+__device__ __forceinline__ double qr_rcp(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = y * fma(-x, y, 2.0);
+  return y * fma(-x, y, 2.0);
+}
+__device__ __forceinline__ double qr_sqrt(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * fma(-0.5 * x * y, y, 1.5);
+  y = y * fma(-0.5 * x * y, y, 1.5);
+  return x * y;
+}
 
 // Factor logical columns [j0, j0 + nb) of A (rows j0 .. R-1) with this
 // workgroup: on return those columns of X hold R's entries on and above the
@@ -128,6 +140,7 @@ __device__ __noinline__ void qr_panel(SharedQR &s, double2 *__restrict__ X, int 
                          int nb, double2 *__restrict__ Tg) {
   using namespace qr;
   const int m = R - j0, t = threadIdx.x;
+  __syncthreads();  // the panel's columns may just have been written by other threads of this workgroup
   for (int c = 0; c < nb; ++c) {
     const double2 *col = X + (size_t)qmap[j0 + c] * ldx + j0;
     for (int i = t; i < m; i += NT_QR) s.P[c * m + i] = col[i];
@@ -142,14 +155,17 @@ __device__ __noinline__ void qr_panel(SharedQR &s, double2 *__restrict__ X, int 
     const double2 al = pc[c];
     double tau = 0.0;
     double2 beta = al, rinv = make_double2(0, 0);
-    if (ss > 0.0) {
-      const double aa = sqrt(al.x * al.x + al.y * al.y);
-      const double nrm = sqrt(fma(aa, aa, ss));
-      const double2 ph = aa > 0.0 ? make_double2(al.x / aa, al.y / aa) : make_double2(1.0, 0.0);
+    if (ss > 1e-290) {  // (normal range for the estimates; smaller columns are left as they are)
+      const double a2 = fma(al.x, al.x, al.y * al.y);
+      const double nrm = qr_sqrt(a2 + ss);
+      const double aa = a2 > 1e-290 ? qr_sqrt(a2) : 0.0;
+      const double iaa = aa > 0.0 ? qr_rcp(aa) : 0.0;
+      const double2 ph = aa > 0.0 ? make_double2(al.x * iaa, al.y * iaa) : make_double2(1.0, 0.0);
       const double d = aa + nrm;
-      tau = d / nrm;
+      tau = d * qr_rcp(nrm);
       beta = make_double2(-ph.x * nrm, -ph.y * nrm);
-      rinv = make_double2(ph.x / d, -ph.y / d);  // 1 / (e^{i phi} (|alpha| + ||x||))
+      const double id = qr_rcp(d);
+      rinv = make_double2(ph.x * id, -ph.y * id);  // 1 / (e^{i phi} (|alpha| + ||x||))
     }
     __syncthreads();
     if (tau != 0.0)
@@ -200,15 +216,12 @@ __device__ __noinline__ void qr_panel(SharedQR &s, double2 *__restrict__ X, int 
         }
       }
     }
-    if (t == 0) {
-      // T(0:c, c) = -tau T(0:c, 0:c) z, T(c, c) = tau
-      double2 col[kQrNbMax];
-      for (int r = 0; r < c; ++r) {
-        double2 a = make_double2(0, 0);
-        for (int j = r; j < c; ++j) cfma(a, s.T[r][j], s.red[0][j]);
-        col[r] = make_double2(-tau * a.x, -tau * a.y);
-      }
-      for (int r = 0; r < c; ++r) s.T[r][c] = col[r];
+    // T(0:c, c) = -tau T(0:c, 0:c) z (row r by thread r), T(c, c) = tau
+    if (t < c) {
+      double2 a = make_double2(0, 0);
+      for (int j = t; j < c; ++j) cfma(a, s.T[t][j], s.red[0][j]);
+      s.T[t][c] = make_double2(-tau * a.x, -tau * a.y);
+    } else if (t == c) {
       s.T[c][c] = make_double2(tau, 0.0);
     }
     __syncthreads();
@@ -264,14 +277,17 @@ __device__ __noinline__ void qr_apply_panel(SharedQR &s, int m, int nb, bool adj
   }
   __syncthreads();
   if (g == 0 && j < 16) {
-    // Wt[:, j] = M (V^H y_j)
+    // Wt[:, j] = M (V^H y_j); q unrolled so that acc stays in registers
     for (int r = 0; r < nb; ++r) {
       double2 a = make_double2(0, 0);
-      for (int q = 0; q < nb; ++q) {
-        if (adjoint) {
-          if (q <= r) cfmac(a, s.T[q][r], acc[q]);  // (T^H)[r][q] = conj(T[q][r]), upper T
-        } else {
-          if (q >= r) cfma(a, s.T[r][q], acc[q]);
+#pragma unroll
+      for (int q = 0; q < kQrNbMax; ++q) {
+        if (q < nb) {
+          if (adjoint) {
+            if (q <= r) cfmac(a, s.T[q][r], acc[q]);  // (T^H)[r][q] = conj(T[q][r]), upper T
+          } else {
+            if (q >= r) cfma(a, s.T[r][q], acc[q]);
+          }
         }
       }
       s.Wt[r][j] = a;

@@ -224,7 +224,7 @@ size_t layout(lmpo_state *S, const Sizes &z, int N, int nb, char *base, size_t s
   S->cnorm = a.take<double>(z.max_cols);
   S->Y = a.take<double2>(z.v_elems);
   S->Lb = a.take<double2>(z.x_elems);
-  S->Tq = a.take<double2>((size_t)(z.max_cols / 4 + 2) * 64);
+  S->Tq = a.take<double2>((size_t)(z.max_cols / 4 + 2) * 256);  // one 16 x 16 T per QR panel
   S->qmap = a.take<int>(z.max_cols);
   S->qinv = a.take<int>(z.max_cols);
   S->Z = a.take<double2>(z.z_elems);

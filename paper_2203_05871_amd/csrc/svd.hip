@@ -135,13 +135,11 @@ __device__ __forceinline__ void pair_blocks(int round, int p, int nbp, int &bi, 
 // Partner of index i in step `step` of the round-robin over JP indices.
 __device__ __forceinline__ int inner_partner(int i, int step) {
   const int m = JP - 1;
-  // i = (step + t) % m  <->  partner = (step - t) % m, i.e. (2 step - i) mod m;
-  // index m pairs with index step
-  int p = 2 * step - i;
-  p += p < 0 ? m : 0;
-  p += p < 0 ? m : 0;
-  p -= p >= m ? m : 0;
-  return i == m ? step : (i == step ? m : p);
+  if (i == m) return step;
+  if (i == step) return m;
+  // i = (step + t) % m  <->  partner = (step - t) % m
+  int t = (i - step + m) % m;
+  return (step - t + m) % m;
 }
 
 constexpr int kChunk = 512;  // rows of a column pair staged in LDS at once
@@ -313,23 +311,24 @@ __device__ bool pair_work(SharedPair &s, double2 *__restrict__ X, int ldx, int R
   // s = tau cs, cs = 1 / sqrt(1 + |tau|^2) and the small root
   // tau = 2 conj(g_pq) / (d + sgn(d) sqrt(d^2 + 4 |g_pq|^2)), d = g_pp - g_qq.
   // Returns false (identity) when g_pq is below the threshold.
-  // Branch-free, so that the two rotations a thread needs run interleaved:
-  // the arithmetic is always done and the identity selected below threshold.
   auto rotation = [&](int p, int q, double &cs, double2 &sc) {
     const double app = s.G[cur][p][p].x, aqq = s.G[cur][q][q].x;
     const double2 c = s.G[cur][p][q];
     const double mc2 = fma(c.x, c.x, c.y * c.y);
-    const bool on = mc2 > tol2 * (app * aqq) && mc2 > 1e-290;  // (normal range for the rsq estimates)
+    if (!(mc2 > tol2 * (app * aqq) && mc2 > 1e-290)) {  // (normal range for the rsq estimates)
+      cs = 1.0;
+      sc = make_double2(0.0, 0.0);
+      return false;
+    }
     const double d = app - aqq;
-    const double r2 = on ? fma(d, d, 4.0 * mc2) : 1.0;
+    const double r2 = fma(d, d, 4.0 * mc2);
     const double r = r2 * rsq_nr(r2);
-    const double den = on ? d + copysign(r, d) : 1.0;
+    const double den = d + copysign(r, d);
     const double f = 2.0 * rcp_nr(den);
     const double2 tau = make_double2(f * c.x, -f * c.y);
-    const double cz = rsq_nr(fma(tau.x, tau.x, fma(tau.y, tau.y, 1.0)));
-    cs = on ? cz : 1.0;
-    sc = on ? make_double2(tau.x * cz, tau.y * cz) : make_double2(0.0, 0.0);
-    return on;
+    cs = rsq_nr(fma(tau.x, tau.x, fma(tau.y, tau.y, 1.0)));
+    sc = make_double2(tau.x * cs, tau.y * cs);
+    return true;
   };
   for (int sweep = 0; sweep < kInnerSweeps; ++sweep) {
     for (int step = 0; step < JP - 1; ++step) {
@@ -666,27 +665,46 @@ __device__ void svd_body(const SvdLaunch &a, Barrier &bar, SharedAll &sh) {
   }
   bar.sync();
   lap(16);
-  // ---- blocked Householder QR of X P ----
+  // ---- blocked Householder QR of X P, with look-ahead: workgroup 0 applies
+  // panel p to the first 16-column task (which holds panel p + 1) and factors
+  // panel p + 1 at once, while the others apply panel p to the remaining tasks;
+  // one barrier per panel ----
   const int nq = R < C ? R : C, nbw = qr_panel_width(R);
-  for (int j0 = 0, p = 0; j0 < nq; j0 += nbw, ++p) {
-    const int nb = min(nbw, nq - j0);
-    double2 *Tp = a.Tq + (size_t)p * kQrNbMax * kQrNbMax;
-    if (rank == 0) qr_panel(sh.qr, a.X, ldx, a.qmap, R, j0, nb, Tp);
+  auto Tpan = [&](int p) { return a.Tq + (size_t)p * kQrNbMax * kQrNbMax; };
+  if (nq > 0) {
+    if (rank == 0) qr_panel(sh.qr, a.X, ldx, a.qmap, R, 0, min(nbw, nq), Tpan(0));
     lap(17);
     bar.sync();
     lap(2);
+  }
+  for (int j0 = 0, p = 0; j0 < nq; j0 += nbw, ++p) {
+    const int nb = min(nbw, nq - j0);
     const int c0 = j0 + nb, ntail = C - c0, ntask = (ntail + 15) / 16;
-    if (ntail > 0) {
-      if ((int)rank < ntask) {
-        qr_load_panel(sh.qr, a.X, ldx, a.qmap, R, j0, nb, Tp);
-        for (int task = rank; task < ntask; task += G)
-          qr_apply_panel(sh.qr, R - j0, nb, true, a.X, ldx, j0, a.qmap + c0 + task * 16, 0,
-                         min(16, ntail - task * 16));
-      }
+    if (ntail <= 0) break;
+    auto apply_tasks = [&](int first, int stride) {
+      for (int task = first; task < ntask; task += stride)
+        qr_apply_panel(sh.qr, R - j0, nb, true, a.X, ldx, j0, a.qmap + c0 + task * 16, 0,
+                       min(16, ntail - task * 16));
+    };
+    if (rank == 0) {
+      qr_load_panel(sh.qr, a.X, ldx, a.qmap, R, j0, nb, Tpan(p));
+      apply_tasks(0, ntask);  // task 0 only
       lap(18);
-      bar.sync();
-      lap(2);
+      if (c0 < nq) {
+        qr_panel(sh.qr, a.X, ldx, a.qmap, R, c0, min(nbw, nq - c0), Tpan(p + 1));
+        lap(17);
+      }
+      if (G == 1 && ntask > 1) {
+        qr_load_panel(sh.qr, a.X, ldx, a.qmap, R, j0, nb, Tpan(p));
+        apply_tasks(1, 1);
+        lap(18);
+      }
+    } else if ((int)rank < ntask) {
+      qr_load_panel(sh.qr, a.X, ldx, a.qmap, R, j0, nb, Tpan(p));
+      apply_tasks((int)rank, G - 1);
     }
+    bar.sync();
+    lap(2);
   }
   // Q Y for the columns of Lb (R rows, ncol columns): panels in reverse
   // order, each workgroup on its own 16-column tasks (no barrier needed).
