@@ -80,6 +80,49 @@ const std::vector<TrotterLayer> &trotter_layers(int order) {
 }
 }  // namespace
 
+// Bond-dimension mirror for sizing launches.  After each step the device bond
+// dims are copied into one of kRing pinned slots; before enqueuing step s the
+// host waits for the copy of step s - kLag, so the sizes it plans with are at
+// most kLag steps old while the GPU still has kLag steps of work queued.
+// (Without the wait the host would run far ahead and plan every step with the
+// dims of the first one.)  Sizes only affect speed, never results.
+struct DimsRing {
+  static constexpr int kRing = 3, kLag = 2;
+  int n = 0;
+  int *pinned = nullptr;  // [kRing][n]
+  hipEvent_t ev[kRing] = {nullptr, nullptr, nullptr};
+  long long issued[kRing] = {-1, -1, -1};  // step whose dims each slot holds
+  hipError_t init(int count) {
+    n = count > 0 ? count : 1;
+    hipError_t e = hipHostMalloc((void **)&pinned, (size_t)kRing * n * sizeof(int), hipHostMallocDefault);
+    for (int i = 0; i < kRing && e == hipSuccess; ++i) e = hipEventCreateWithFlags(&ev[i], hipEventDisableTiming);
+    return e;
+  }
+  ~DimsRing() {
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+    if (pinned) (void)hipHostFree(pinned);
+  }
+  // before step s: wait for the copy taken after step s - kLag and load it
+  hipError_t before(long long s, int *est) {
+    const long long want = s - kLag;
+    if (want < 0) return hipSuccess;
+    const int slot = (int)(want % kRing);
+    if (issued[slot] != want) return hipSuccess;
+    hipError_t e = hipEventSynchronize(ev[slot]);
+    if (e == hipSuccess) std::copy(pinned + (size_t)slot * n, pinned + (size_t)(slot + 1) * n, est);
+    return e;
+  }
+  // after step s: copy the device dims into slot s mod kRing
+  hipError_t after(long long s, const int *d_dims, hipStream_t st) {
+    const int slot = (int)(s % kRing);
+    hipError_t e = hipMemcpyAsync(pinned + (size_t)slot * n, d_dims, n * sizeof(int), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipEventRecord(ev[slot], st);
+    if (e == hipSuccess) issued[slot] = s;
+    return e;
+  }
+};
+
 struct lmpo_state {
   ModelHost m;
   lmpo_options opt{};
@@ -111,13 +154,10 @@ struct lmpo_state {
   bool ev_overflow = false;
   int grid = 1;                 // largest co-resident grid of the persistent SVD
   int wg_cap = 0;               // caller's cap on workgroups per SVD launch (0: none)
-  int *dims_pinned = nullptr;   // asynchronous copy of the bond dims (grid sizing only)
-  hipEvent_t dims_ready = nullptr;
-  std::vector<int> dims_est;    // bond dims as of the last completed step
+  DimsRing ring;                // asynchronous copies of the bond dims (launch sizing only)
+  std::vector<int> dims_est;    // bond dims as of a step at most two steps back
   ~lmpo_state() {
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
-    if (dims_ready) (void)hipEventDestroy(dims_ready);
-    if (dims_pinned) (void)hipHostFree(dims_pinned);
   }
   double *sig = nullptr, *sorted = nullptr, *disc = nullptr, *aux = nullptr;
   double2 *tr = nullptr, *envL = nullptr, *envR = nullptr, *mout = nullptr;
@@ -361,9 +401,9 @@ int est(const lmpo_state *S, int bond) {
   return std::min(S->cap[bond], S->dims_est[bond] + 8);
 }
 
-void refresh_estimates(lmpo_state *S) {
-  if (S->dims_ready && hipEventQuery(S->dims_ready) == hipSuccess)
-    std::copy(S->dims_pinned, S->dims_pinned + (S->N - 1), S->dims_est.begin());
+int refresh_estimates(lmpo_state *S) {
+  HIP_TRY(S->ring.before(S->step_index, S->dims_est.data()));
+  return LMPO_OK;
 }
 
 int launch_svd(lmpo_state *S, const SvdLaunch &L, int grid) {
@@ -538,9 +578,7 @@ int lmpo_create(const lmpo_model *model, const lmpo_options *opt, const char *in
   }
   S->grid = svd_grid_size();
   S->dims_est.assign(std::max(S->N - 1, 1), 1);
-  e = hipHostMalloc((void **)&S->dims_pinned, std::max(S->N - 1, 1) * sizeof(int), hipHostMallocDefault);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&S->dims_ready, hipEventDisableTiming);
-  if (e == hipSuccess) e = hipEventRecord(S->dims_ready, S->stream);
+  e = S->ring.init(S->N - 1);
   if (e != hipSuccess) return cleanup(fail(LMPO_EHIP, std::string("pinned dims: ") + hipGetErrorString(e)));
   int zero = 0;
   double zd = 0.0;
@@ -558,14 +596,11 @@ int lmpo_evolve_step(lmpo_state *S, int32_t n_steps) {
   if (!S) return fail(LMPO_EINVAL, "state is null");
   if (n_steps < 0) return fail(LMPO_EINVAL, "n_steps must be >= 0");
   for (int n = 0; n < n_steps; ++n) {
-    refresh_estimates(S);
-    int rc = one_step(S, S->step_index);
+    int rc = refresh_estimates(S);
     if (rc) return rc;
+    if ((rc = one_step(S, S->step_index))) return rc;
+    HIP_TRY(S->ring.after(S->step_index, S->d_dims, S->stream));
     S->step_index++;
-    if (S->dims_ready && hipEventQuery(S->dims_ready) != hipErrorNotReady) {
-      HIP_TRY(hipMemcpyAsync(S->dims_pinned, S->d_dims, (S->N - 1) * sizeof(int), hipMemcpyDeviceToHost, S->stream));
-      HIP_TRY(hipEventRecord(S->dims_ready, S->stream));
-    }
   }
   return LMPO_OK;
 }
@@ -937,8 +972,8 @@ struct lmpo_batch {
   char *stage = nullptr;
   size_t stage_bytes = 0;
   hipEvent_t stage_done = nullptr;
-  int *dims_pinned = nullptr;
-  hipEvent_t dims_ready = nullptr;
+  DimsRing ring;
+  long long steps_done = 0;
   std::vector<int> dims_est;
   // profiling window
   bool profiling = false;
@@ -950,9 +985,7 @@ struct lmpo_batch {
     for (hipEvent_t e : tune_ev)
       if (e) (void)hipEventDestroy(e);
     if (stage_done) (void)hipEventDestroy(stage_done);
-    if (dims_ready) (void)hipEventDestroy(dims_ready);
     if (stage) (void)hipHostFree(stage);
-    if (dims_pinned) (void)hipHostFree(dims_pinned);
   }
 };
 
@@ -1098,9 +1131,9 @@ int batch_upload(lmpo_batch *B, const std::vector<StageCopy> &copies) {
   return LMPO_OK;
 }
 
-void batch_refresh_estimates(lmpo_batch *B) {
-  if (B->dims_ready && hipEventQuery(B->dims_ready) == hipSuccess)
-    std::copy(B->dims_pinned, B->dims_pinned + B->dims_total, B->dims_est.begin());
+int batch_refresh_estimates(lmpo_batch *B) {
+  HIP_TRY(B->ring.before(B->steps_done, B->dims_est.data()));
+  return LMPO_OK;
 }
 
 // Re-plan from the current estimates; upload the tables if the plan changed.
@@ -1195,10 +1228,9 @@ int lmpo_batch_create(lmpo_state *const *chains, int32_t n_chains, void *device_
     return cleanup(fail(LMPO_EUNSUPPORTED, "more chains than co-resident workgroups (" + std::to_string(B->grid_max) + ")"));
   hipError_t e = hipEventCreateWithFlags(&B->stage_done, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventRecord(B->stage_done, B->stream);
-  if (e == hipSuccess) e = hipEventCreateWithFlags(&B->dims_ready, hipEventDisableTiming);
+  if (e == hipSuccess) e = B->ring.init(B->dims_total);
   if (e == hipSuccess) e = hipEventCreate(&B->tune_ev[0]);
   if (e == hipSuccess) e = hipEventCreate(&B->tune_ev[1]);
-  if (e == hipSuccess) e = hipHostMalloc((void **)&B->dims_pinned, std::max(B->dims_total, 1) * sizeof(int), hipHostMallocDefault);
   if (e == hipSuccess) e = hipMemsetAsync(B->d_flops, 0, n_chains * sizeof(double), B->stream);
   if (e != hipSuccess) return cleanup(fail(LMPO_EHIP, std::string("batch init: ") + hipGetErrorString(e)));
   // estimates from the chains' current bond dims
@@ -1208,9 +1240,6 @@ int lmpo_batch_create(lmpo_state *const *chains, int32_t n_chains, void *device_
     if ((rc = sync_dims(S))) return cleanup(rc);
     std::copy(S->dims.begin(), S->dims.end(), B->dims_est.begin() + B->dims_off[c]);
   }
-  std::copy(B->dims_est.begin(), B->dims_est.begin() + B->dims_total, B->dims_pinned);
-  e = hipEventRecord(B->dims_ready, B->stream);
-  if (e != hipSuccess) return cleanup(fail(LMPO_EHIP, std::string("batch init: ") + hipGetErrorString(e)));
   if ((rc = batch_replan(B))) return cleanup(rc);
   *out = B;
   return LMPO_OK;
@@ -1243,7 +1272,7 @@ int lmpo_batch_evolve_step(lmpo_batch *B, int32_t n_steps) {
                             {B->d_centre, centres.data(), centres.size() * sizeof(int)}});
   if (rc) return rc;
   for (int s = 0; s < n_steps; ++s) {
-    batch_refresh_estimates(B);
+    if ((rc = batch_refresh_estimates(B))) return rc;
     // autotuner: the cap of this step (a candidate under trial, or the best known)
     int trial = -1;
     std::tuple<int, int, int> key;
@@ -1278,10 +1307,8 @@ int lmpo_batch_evolve_step(lmpo_batch *B, int32_t n_steps) {
         if (te.next == kTuneN) te.best = (int)(std::min_element(te.ms, te.ms + kTuneN) - te.ms);
       }
     }
-    if (hipEventQuery(B->dims_ready) != hipErrorNotReady) {
-      HIP_TRY(hipMemcpyAsync(B->dims_pinned, B->d_dims, B->dims_total * sizeof(int), hipMemcpyDeviceToHost, B->stream));
-      HIP_TRY(hipEventRecord(B->dims_ready, B->stream));
-    }
+    HIP_TRY(B->ring.after(B->steps_done, B->d_dims, B->stream));
+    B->steps_done++;
   }
   // host mirrors: the last layer (even bonds) ends ascending on the last even
   // bond or descending on bond 0
