@@ -35,13 +35,20 @@ def apply_two_site(v, G, i, j, N):
 
 def trotter_evolve(v, model, tau, steps, gates=None, first_step=0, observer=None,
                    force_trace=True, order=2):
-    tebd.check_chain(model)
+    """The MPS schedule on the full vector; a bond (i, j) apart along the path
+    acts on sites i and j directly (no SWAP network)."""
     N = model["N"]
+    chain = tebd.is_chain(model)
+    bonds = np.asarray(model["bonds"])
     if gates is None:
         gates = tebd.gate_tables(model, tau, order)
     for n in range(first_step, first_step + steps):
-        for k, frac, _ in tebd.step_schedule(N, n, order):
-            v = apply_two_site(v, gates[(k, frac)], k, k + 1, N)
+        if chain:
+            for k, frac, _ in tebd.step_schedule(N, n, order):
+                v = apply_two_site(v, gates[(k, frac)], k, k + 1, N)
+        else:
+            for b, frac, _ in tebd.sweep_schedule(model, order):
+                v = apply_two_site(v, gates[(b, frac)], int(bonds[b, 0]), int(bonds[b, 1]), N)
         if force_trace:
             v = v / trace(v, N)
         if observer is not None:
@@ -131,3 +138,18 @@ def osee(v, N, bond):
     p = s ** 2 / np.sum(s ** 2)
     p = p[p > 0]
     return float(-np.sum(p * np.log(p)))
+
+
+def graph_state_vector(N, pairs):
+    """|psi><psi| for the graph state of Eq. (graph_state), from its closed
+    form psi(x) = 2^(-N/2) (-1)^(sum over pairs of x_j x_k), x_i in {0, 1}."""
+    x = (np.arange(2 ** N)[:, None] >> (N - 1 - np.arange(N))[None, :]) & 1
+    phase = np.zeros(2 ** N, dtype=np.int64)
+    for a, b in pairs:
+        phase += x[:, a] * x[:, b]
+    psi = (1.0 - 2.0 * (phase % 2)) / np.sqrt(2.0 ** N)
+    rho = np.outer(psi, psi.conj()).astype(np.complex128)
+    # rows k_0..k_{N-1}, columns b_0..b_{N-1} -> site-major (k_0 b_0)(k_1 b_1)...
+    t = rho.reshape((2,) * (2 * N))
+    perm = [q for s in range(N) for q in (s, N + s)]
+    return t.transpose(perm).reshape(-1)

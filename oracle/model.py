@@ -98,6 +98,13 @@ def bond_gate(model, b, x):
     return scipy.linalg.expm(x * bond_generator(model, b))
 
 
+def unitary_channel(U):
+    """Superoperator of rho -> U rho U^+ for a two-qubit unitary U (basis
+    |k_i k_j>, index 2 k_i + k_j), in site-major order (k_i b_i, k_j b_j)."""
+    U = np.asarray(U, dtype=np.complex128)
+    return _two_site_to_site_major(superop(U, U.conj().T))
+
+
 def swap_gate():
     """Superoperator that exchanges two sites' (ket, bra) pairs."""
     P = np.zeros((16, 16))

@@ -24,6 +24,17 @@ max_dim_rho).  An ascending gate leaves A_k = U, A_{k+1} = S V^+ (centre moves
 right), a descending one A_k = U S, A_{k+1} = V^+.  Singular values are not
 rescaled.  After each step, when trace forcing is on, rho -> rho / tr(rho)
 with the complex trace (App. B, b_force_rho_trace).
+
+Other geometries (Sec. 2.3: the MPS follows a path through the qubits, so a
+coupled pair may sit several sites apart along it, e.g. the zigzag ladder of
+the plaquette appendix).  When the bond list is not the open chain in order,
+a step is the symmetric sweep over the bond list
+    S2(tau) = F(tau/2) R(tau/2),
+F applying exp(tau/2 L_b) for b = 0, 1, ..., R the same factors in reverse
+order; fourth order composes S2(w1 tau) S2(w0 tau) S2(w1 tau) without merging.
+A bond (i, j) with j > i + 1 is applied by carrying site j down to i + 1 with
+SWAP gates on (j-1, j), ..., (i+1, i+2) (each a two-site gate with the same
+truncation rule), applying G on (i, i+1) and carrying it back up.
 """
 from __future__ import annotations
 
@@ -86,6 +97,36 @@ def step_schedule(N, step, order=2):
         bonds = layers[parity]
         for k in (bonds if asc else bonds[::-1]):
             out.append((k, frac, asc))
+    return out
+
+
+def is_chain(model):
+    """True when the bond list is the open chain (k, k+1), k = 0..N-2, in order."""
+    bonds = np.asarray(model["bonds"])
+    N = model["N"]
+    return (len(bonds) == N - 1 and bool(np.all(bonds[:, 0] == np.arange(N - 1)))
+            and bool(np.all(bonds[:, 1] == np.arange(1, N))))
+
+
+def sweep_fractions(order=2):
+    """Fractions x of tau of the symmetric sweeps F(x) R(x) of one step on a
+    general bond list (see the module header)."""
+    if order == 2:
+        return [0.5]
+    if order == 4:
+        w1 = 1.0 / (2.0 - 2.0 ** (1.0 / 3.0))
+        w0 = 1.0 - 2.0 * w1
+        return [0.5 * w1, 0.5 * w0, 0.5 * w1]
+    raise ValueError("trotter order must be 2 or 4")
+
+
+def sweep_schedule(model, order=2):
+    """[(bond b, fraction of tau, forward?)] of one step on a general bond list."""
+    nb = len(model["bonds"])
+    out = []
+    for x in sweep_fractions(order):
+        out += [(b, x, True) for b in range(nb)]
+        out += [(b, x, False) for b in reversed(range(nb))]
     return out
 
 
@@ -181,6 +222,21 @@ class MPS:
             self.centre = k
         return kk, s
 
+    def apply_pair_gate(self, i, j, G, chi_max, cutoff, forward=True):
+        """G (16 x 16, acting on (site i, site j)) on a pair i < j.  Adjacent:
+        one gate, the centre ends right of the pair on forward sweeps and left
+        of it otherwise.  Apart: SWAPs carry site j to i + 1 (centre moving
+        left), G on (i, i + 1), SWAPs carry it back (centre moving right)."""
+        if j == i + 1:
+            self.apply_gate(i, G, chi_max, cutoff, forward)
+            return
+        P = lm.swap_gate()
+        for k in range(j - 1, i, -1):
+            self.apply_gate(k, P, chi_max, cutoff, False)
+        self.apply_gate(i, G, chi_max, cutoff, True)
+        for k in range(i + 1, j):
+            self.apply_gate(k, P, chi_max, cutoff, True)
+
     # -- contractions with product covectors --
     def contract(self, covectors):
         """sum over all indices of prod_k covectors[k] . A_k (a scalar)."""
@@ -233,29 +289,33 @@ class MPS:
 def gate_tables(model, tau, order=2):
     """{(bond, fraction): G} for every fraction of tau the scheme uses."""
     out = {}
-    fracs = sorted({f for _, f in trotter_layers(order)})
+    if is_chain(model):
+        fracs = sorted({f for _, f in trotter_layers(order)})
+    else:
+        fracs = sorted(set(sweep_fractions(order)))
     for b in range(len(model["bonds"])):
         for frac in fracs:
             out[(b, frac)] = lm.bond_gate(model, b, frac * tau)
     return out
 
 
-def check_chain(model):
-    bonds = np.asarray(model["bonds"])
-    N = model["N"]
-    if len(bonds) != N - 1 or np.any(bonds[:, 0] != np.arange(N - 1)) or np.any(bonds[:, 1] != np.arange(1, N)):
-        raise ValueError("chain schedule needs bonds (k, k+1), k = 0..N-2, in order")
-
-
 def evolve(mps, model, tau, steps, chi_max, cutoff, force_trace=True, gates=None,
            observer=None, first_step=0, order=2):
-    """Run `steps` Trotter steps; observer(step_done, mps) after each step."""
-    check_chain(model)
+    """Run `steps` Trotter steps; observer(step_done, mps) after each step.
+    The open chain in order takes the layered schedule, any other bond list
+    the symmetric bond-list sweep (module header)."""
+    chain = is_chain(model)
     if gates is None:
         gates = gate_tables(model, tau, order)
+    bonds = np.asarray(model["bonds"])
     for n in range(first_step, first_step + steps):
-        for k, frac, asc in step_schedule(mps.N, n, order):
-            mps.apply_gate(k, gates[(k, frac)], chi_max, cutoff, asc)
+        if chain:
+            for k, frac, asc in step_schedule(mps.N, n, order):
+                mps.apply_gate(k, gates[(k, frac)], chi_max, cutoff, asc)
+        else:
+            for b, frac, fwd in sweep_schedule(model, order):
+                i, j = int(bonds[b, 0]), int(bonds[b, 1])
+                mps.apply_pair_gate(i, j, gates[(b, frac)], chi_max, cutoff, fwd)
         if force_trace:
             mps.renormalize()
         if observer is not None:
@@ -301,3 +361,23 @@ def gate_to_pauli(G):
     T = pauli_basis_matrix()
     TT = np.kron(T, T)
     return TT @ G @ np.linalg.inv(TT)
+
+
+# -- graph-state initial condition (Eq. graph_state) --
+def cz_channel():
+    """Superoperator of rho -> CZ rho CZ on two sites (site-major order)."""
+    return lm.unitary_channel(np.diag([1.0, 1.0, 1.0, -1.0]).astype(np.complex128))
+
+
+def graph_state(N, pairs, chi_max, cutoff):
+    """|psi0><psi0| with psi0 = prod_{(j,k) in V} CZ[j,k] prod_i |+x_i>: the
+    product of +x states, then the CZ channel on every listed pair in order
+    (a pair apart along the path goes through the SWAP network)."""
+    mps = MPS.product("+x", N)
+    G = cz_channel()
+    for a, b in pairs:
+        i, j = (int(a), int(b)) if a < b else (int(b), int(a))
+        if not (0 <= i < j < N):
+            raise ValueError("graph pairs need two distinct sites in range")
+        mps.apply_pair_gate(i, j, G, chi_max, cutoff, True)
+    return mps
