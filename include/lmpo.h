@@ -54,7 +54,11 @@ enum { LMPO_FP64 = 0, LMPO_FP32_CONTRACT = 1 };
 
 /* Model parameters (Sec. 2.1).  bond_ij lists the coupled pairs (i, j), i < j;
  * each bond contributes J (s+_i s-_j + s-_i s+_j) + (1/2) Jz s^z_i s^z_j
- * (Eq. K_def read as one term per unordered pair).  Per-site arrays have
+ * (Eq. K_def read as one term per unordered pair).  Qubit indices are
+ * positions along the MPS path (Sec. 2.3), so a pair may be several sites
+ * apart (a ladder or plaquette folded onto the path); every qubit must belong
+ * to at least one bond, whose generators carry its on-site terms (shared
+ * equally among its bonds).  Per-site arrays have
  * length n_qubits: h_x, h_y, h_z of Eq. (H0) and the rates g0, g1, g2 of
  * Eqs. (D0) (relaxation to s^z = +1), (D1) (to s^z = -1), (D2) (dephasing). */
 typedef struct {
@@ -88,17 +92,23 @@ size_t lmpo_arena_bytes(const lmpo_model *model, const lmpo_options *opt);
 
 /* Create a state in the Pauli product state init_pauli (Sec. 2.2): either one
  * label such as "+z" for all qubits or n_qubits labels concatenated ("+z-x+y..."),
- * sign then axis x|y|z.  Builds the gate table exp(x L_b), x in {tau/2, tau},
- * on the host in FP64 and uploads it.  Requires a chain: bond b = (b, b+1) for
- * b = 0..N-2 (other geometries: LMPO_EUNSUPPORTED).  hip_stream is a
- * hipStream_t (NULL for the default stream). */
+ * sign then axis x|y|z.  Builds the gate table exp(x L_b) for every time
+ * fraction x/tau the schedule uses, on the host in FP64, and uploads it.
+ * hip_stream is a hipStream_t (NULL for the default stream). */
 int lmpo_create(const lmpo_model *model, const lmpo_options *opt, const char *init_pauli,
                 void *device_arena, size_t arena_bytes, void *hip_stream, lmpo_state **out);
 
-/* Enqueue n_steps >= 0 Trotter steps: layers A(tau/2) B(tau) A(tau/2) over even
- * bonds (A) and odd bonds (B) (order 4: the seven layers of the composition); each gate moves the orthogonality centre onto its
- * bond (exact), applies exp(x L_b) to the two-site block, truncates by SVD and
- * restores canonical form; then rho -> rho / tr(rho) if force_trace. */
+/* Enqueue n_steps >= 0 Trotter steps.  Open chain (bond b = (b, b+1) for
+ * b = 0..N-2, in that order): layers A(tau/2) B(tau) A(tau/2) over even bonds
+ * (A) and odd bonds (B) (order 4: the seven layers of the composition).  Any
+ * other bond list: the symmetric sweep F(tau/2) R(tau/2), F applying
+ * exp(tau/2 L_b) for b = 0, 1, ..., R the same factors in reverse order (order
+ * 4: S2(w1 tau) S2(w0 tau) S2(w1 tau) of such sweeps); a pair (i, j) with
+ * j > i + 1 is applied by SWAP gates carrying site j to i + 1, the propagator
+ * on (i, i + 1), and SWAP gates carrying it back.  Each gate (SWAPs included)
+ * moves the orthogonality centre onto its two sites (exact), applies the
+ * 16 x 16 superoperator to the two-site block, truncates by SVD and restores
+ * canonical form; then rho -> rho / tr(rho) if force_trace. */
 int lmpo_evolve_step(lmpo_state *s, int32_t n_steps);
 
 /* tr(rho) (Sec. 2.4) as (re, im); synchronises. */
@@ -165,6 +175,28 @@ int lmpo_get_gate(lmpo_state *s, int32_t bond, int32_t half, double *out);
  * centre move, contraction, truncated SVD, canonical update (ascending: centre
  * ends on k+1; descending: on k).  Asynchronous. */
 int lmpo_apply_gate(lmpo_state *s, int32_t k, int32_t half, int32_t ascending);
+
+/* A caller's two-site superoperator G on qubits i != j, applied like one gate
+ * of a step (SWAP network when |i - j| > 1, truncation by the state's chi_max
+ * and cutoff).  G: 16x16 complex (interleaved re/im, row-major) in the Pauli
+ * basis P_{a_i} (x) P_{a_j}, index 4 a_i + a_j, acting on (qubit i, qubit j) in
+ * that order.  Non-finite entries: LMPO_EINVAL.  Drains the stream before
+ * copying G to the device, then enqueues the gate asynchronously. */
+int lmpo_apply_superop(lmpo_state *s, int32_t i, int32_t j, const double *G);
+
+/* The channel rho -> U rho U^+ of a two-qubit unitary U on qubits (i, j), as
+ * lmpo_apply_superop.  U: 4x4 complex (interleaved, row-major) in the basis
+ * |k_i k_j>, index 2 k_i + k_j, with |0> the s^z = +1 state.  Unitarity is
+ * not checked. */
+int lmpo_apply_unitary(lmpo_state *s, int32_t i, int32_t j, const double *U);
+
+/* Restart from the graph state of Eq. (graph_state): every qubit in |+x>,
+ * then CZ applied to each of the n_pairs pairs (pairs[2p], pairs[2p+1]) in
+ * order, through the SWAP network when apart.  The bond dims grow as the CZ
+ * gates require (truncated by chi_max / cutoff like any gate; cutoff 0 keeps
+ * round-off singular values).  Resets the step count (time 0) and the
+ * discarded weight.  Synchronises at entry; the gates run asynchronously. */
+int lmpo_init_graph_state(lmpo_state *s, int32_t n_pairs, const int32_t *pairs);
 
 /* Singular values of the last two-site block, sorted descending (n_out
  * entries at most), and its kept rank; synchronises. */

@@ -56,6 +56,9 @@ constexpr int kStats = 8;  // [last sweeps, last C, last R, -, total sweeps, tot
 // composition S2(w1 tau) S2(w0 tau) S2(w1 tau), w1 = 1 / (2 - 2^(1/3)),
 // w0 = 1 - 2 w1, with adjacent A half-layers merged: seven layers
 // A(w1/2) B(w1) A((w1+w0)/2) B(w0) A((w0+w1)/2) B(w1) A(w1/2).
+// On other bond lists a second-order step is the symmetric sweep
+// F(tau/2) R(tau/2) over the bonds (slot 1); fourth order composes such
+// sweeps with w1/2 (slot 2) and w0/2 (slot 6).
 double gate_fraction(int slot) {
   const double w1 = 1.0 / (2.0 - std::cbrt(2.0)), w0 = 1.0 - 2.0 * w1;
   switch (slot) {
@@ -64,8 +67,16 @@ double gate_fraction(int slot) {
     case 2: return 0.5 * w1;
     case 3: return w1;
     case 4: return 0.5 * (w1 + w0);
-    default: return w0;
+    case 5: return w0;
+    default: return 0.5 * w0;
   }
+}
+
+// Slots of the symmetric sweeps of one step on a general bond list.
+const std::vector<int> &sweep_slots(int order) {
+  static const std::vector<int> o2 = {1};
+  static const std::vector<int> o4 = {2, 6, 2};
+  return order == 4 ? o4 : o2;
 }
 
 struct TrotterLayer {
@@ -163,6 +174,9 @@ struct lmpo_state {
   double2 *tr = nullptr, *envL = nullptr, *envR = nullptr, *mout = nullptr;
   long long step_index = 0;  // global Trotter step count (fixes the layer order)
   std::vector<std::complex<double>> gates_host;  // [nb][kGateSlots][256]
+  bool chain = true;            // bond list is the open chain (b, b+1) in order
+  double2 *d_swap = nullptr;    // exchange of two sites (Pauli basis)
+  double2 *d_user = nullptr;    // caller-supplied two-site superoperator
 };
 
 namespace {
@@ -199,12 +213,21 @@ int validate(const lmpo_model *m, const lmpo_options *o) {
   if (o->trotter_order != 2 && o->trotter_order != 4)
     return fail(LMPO_EUNSUPPORTED, "trotter_order must be 2 or 4 (order 3 is not implemented)");
   if (o->chi_max > kMaxDim / 4) return fail(LMPO_EUNSUPPORTED, "chi_max above 512 is not supported");
-  // chain geometry: bond b = (b, b+1)
-  if (m->n_bonds != m->n_qubits - 1) return fail(LMPO_EUNSUPPORTED, "only open chains (bonds (b, b+1)) are supported");
-  for (int b = 0; b < m->n_bonds; ++b)
-    if (m->bond_ij[2 * b] != b || m->bond_ij[2 * b + 1] != b + 1)
-      return fail(LMPO_EUNSUPPORTED, "only open chains (bonds (b, b+1), in order) are supported");
+  std::vector<int> deg(m->n_qubits, 0);
+  for (int b = 0; b < m->n_bonds; ++b) {
+    deg[m->bond_ij[2 * b]]++;
+    deg[m->bond_ij[2 * b + 1]]++;
+  }
+  for (int s = 0; s < m->n_qubits; ++s)
+    if (deg[s] == 0) return fail(LMPO_EINVAL, "every qubit must belong to a bond (its on-site terms ride on them)");
   return LMPO_OK;
+}
+
+bool is_chain(const lmpo_model *m) {
+  if (m->n_bonds != m->n_qubits - 1) return false;
+  for (int b = 0; b < m->n_bonds; ++b)
+    if (m->bond_ij[2 * b] != b || m->bond_ij[2 * b + 1] != b + 1) return false;
+  return true;
 }
 
 Sizes compute_sizes(int N, int chi_max) {
@@ -251,6 +274,8 @@ size_t layout(lmpo_state *S, const Sizes &z, int N, int nb, char *base, size_t s
   S->d_sites = a.take<double2 *>(N);
   S->d_dims = a.take<int>(std::max(N - 1, 1));
   S->d_gates = a.take<double2>((size_t)nb * kGateSlots * 256);
+  S->d_swap = a.take<double2>(256);
+  S->d_user = a.take<double2>(256);
   S->X = a.take<double2>(z.x_elems);
   S->V = a.take<double2>(z.v_elems);
   int nbp = (z.max_cols + JB - 1) / JB;
@@ -448,10 +473,10 @@ int move_centre(lmpo_state *S, int to) {
   return LMPO_OK;
 }
 
-int apply_gate(lmpo_state *S, int k, int slot, int asc) {
+// Two-site gate G (device, 16x16 Pauli basis) on sites (k, k+1).
+int apply_gate_dev(lmpo_state *S, int k, const double2 *G, int asc) {
   int rc = move_centre(S, S->centre <= k ? k : k + 1);
   if (rc) return rc;
-  const double2 *G = S->d_gates + ((size_t)k * kGateSlots + slot) * 256;
   launch_contract_gate(S->stream, S->opt.precision, S->d_sites, S->d_dims, S->N, k, capL(S, k), capR(S, k + 1), G,
                        S->X);
   HIP_TRY(hipGetLastError());
@@ -459,6 +484,73 @@ int apply_gate(lmpo_state *S, int k, int slot, int asc) {
   rc = launch_svd(S, svd_args(S, 0, k, asc), grid_for(S, std::max(r, c), std::min(r, c)));
   if (rc) return rc;
   S->centre = asc ? k + 1 : k;
+  return LMPO_OK;
+}
+
+const double2 *gate_ptr(const lmpo_state *S, int bond, int slot) {
+  return S->d_gates + ((size_t)bond * kGateSlots + slot) * 256;
+}
+
+int apply_gate(lmpo_state *S, int k, int slot, int asc) { return apply_gate_dev(S, k, gate_ptr(S, k, slot), asc); }
+
+// G on qubits i < j.  Neighbours on the path: one gate (the centre ends right
+// of the pair on forward sweeps, left of it otherwise).  Apart: SWAP gates
+// carry site j down to i + 1 (centre moving left), G acts on (i, i + 1), SWAP
+// gates carry it back (centre moving right).  Every SWAP is an ordinary
+// truncated two-site gate.
+int apply_pair(lmpo_state *S, int i, int j, const double2 *G, bool forward) {
+  int rc;
+  if (j == i + 1) return apply_gate_dev(S, i, G, forward ? 1 : 0);
+  for (int k = j - 1; k > i; --k)
+    if ((rc = apply_gate_dev(S, k, S->d_swap, 0))) return rc;
+  if ((rc = apply_gate_dev(S, i, G, 1))) return rc;
+  for (int k = i + 1; k < j; ++k)
+    if ((rc = apply_gate_dev(S, k, S->d_swap, 1))) return rc;
+  return LMPO_OK;
+}
+
+// Product of Pauli eigenstates: per site (1, 0, 0, 0) / sqrt(2) with
+// +-1/sqrt(2) on the axis; bond dims 1, centre 0.  Synchronises.
+int upload_product(lmpo_state *S, const std::vector<std::pair<int, int>> &init) {
+  const double r2 = 1.0 / std::sqrt(2.0);
+  std::vector<double2> sitev(4 * S->N);
+  for (int i = 0; i < S->N; ++i) {
+    for (int a = 0; a < 4; ++a) sitev[4 * i + a] = make_double2(0, 0);
+    sitev[4 * i] = make_double2(r2, 0);
+    sitev[4 * i + init[i].second] = make_double2(init[i].first * r2, 0);
+  }
+  for (int i = 0; i < S->N; ++i)
+    HIP_TRY(hipMemcpyAsync(S->site[i], &sitev[4 * i], 4 * sizeof(double2), hipMemcpyHostToDevice, S->stream));
+  std::fill(S->dims.begin(), S->dims.end(), 1);
+  std::vector<int> ones(std::max(S->N - 1, 1), 1);
+  HIP_TRY(hipMemcpyAsync(S->d_dims, ones.data(), ones.size() * sizeof(int), hipMemcpyHostToDevice, S->stream));
+  HIP_TRY(hipStreamSynchronize(S->stream));
+  S->centre = 0;
+  return LMPO_OK;
+}
+
+// Copies a caller's 16x16 Pauli-basis superoperator for qubits (i, j) into the
+// device slot, re-indexed to act on (min, max) when i > j.  The stream is
+// drained first, so no queued gate still reads the slot.  Synchronises.
+int upload_user_gate(lmpo_state *S, int i, int j, const double *G) {
+  std::vector<double2> g(256);
+  auto flip = [](int x) { return (x % 4) * 4 + x / 4; };
+  for (int r = 0; r < 16; ++r)
+    for (int c = 0; c < 16; ++c) {
+      const int rr = i > j ? flip(r) : r, cc = i > j ? flip(c) : c;
+      g[rr * 16 + cc] = make_double2(G[2 * (r * 16 + c)], G[2 * (r * 16 + c) + 1]);
+    }
+  for (const double2 &v : g)
+    if (!std::isfinite(v.x) || !std::isfinite(v.y)) return fail(LMPO_EINVAL, "non-finite gate entry");
+  HIP_TRY(hipStreamSynchronize(S->stream));
+  HIP_TRY(hipMemcpyAsync(S->d_user, g.data(), 256 * sizeof(double2), hipMemcpyHostToDevice, S->stream));
+  HIP_TRY(hipStreamSynchronize(S->stream));
+  return LMPO_OK;
+}
+
+int pair_args(const lmpo_state *S, int i, int j) {
+  if (i < 0 || j < 0 || i >= S->N || j >= S->N || i == j)
+    return fail(LMPO_EINVAL, "a two-site gate needs two distinct qubits in range");
   return LMPO_OK;
 }
 
@@ -479,6 +571,21 @@ int renormalize(lmpo_state *S) {
 
 int one_step(lmpo_state *S, long long step) {
   const int N = S->N;
+  if (!S->chain) {  // symmetric sweeps F(x) R(x) over the bond list
+    const int nb = S->m.nb;
+    for (int slot : sweep_slots(S->opt.trotter_order)) {
+      for (int b = 0; b < nb; ++b) {
+        int rc = apply_pair(S, S->m.bonds[2 * b], S->m.bonds[2 * b + 1], gate_ptr(S, b, slot), true);
+        if (rc) return rc;
+      }
+      for (int b = nb - 1; b >= 0; --b) {
+        int rc = apply_pair(S, S->m.bonds[2 * b], S->m.bonds[2 * b + 1], gate_ptr(S, b, slot), false);
+        if (rc) return rc;
+      }
+    }
+    if (S->opt.force_trace) return renormalize(S);
+    return LMPO_OK;
+  }
   const std::vector<TrotterLayer> &layers = trotter_layers(S->opt.trotter_order);
   for (int j = 0; j < (int)layers.size(); ++j) {
     const long long layer = (long long)layers.size() * step + j;
@@ -524,6 +631,7 @@ int lmpo_create(const lmpo_model *model, const lmpo_options *opt, const char *in
   lmpo_state *S = new lmpo_state();
   S->m = copy_model(model);
   S->opt = *opt;
+  S->chain = is_chain(model);
   S->N = model->n_qubits;
   S->stream = reinterpret_cast<hipStream_t>(hip_stream);
   size_t need = layout(S, z, S->N, S->m.nb, reinterpret_cast<char *>(device_arena), arena_bytes);
@@ -559,23 +667,16 @@ int lmpo_create(const lmpo_model *model, const lmpo_options *opt, const char *in
   e = hipMemcpyAsync(S->d_gates, S->gates_host.data(), S->gates_host.size() * sizeof(double2), hipMemcpyHostToDevice,
                      S->stream);
   if (e != hipSuccess) return cleanup(fail(LMPO_EHIP, std::string("gate upload: ") + hipGetErrorString(e)));
+  std::vector<std::complex<double>> swap(256);
+  swap_pauli(swap.data());
+  e = hipMemcpyAsync(S->d_swap, swap.data(), 256 * sizeof(double2), hipMemcpyHostToDevice, S->stream);
+  if (e != hipSuccess) return cleanup(fail(LMPO_EHIP, std::string("swap upload: ") + hipGetErrorString(e)));
   e = hipMemcpyAsync(S->d_sites, S->site.data(), S->N * sizeof(double2 *), hipMemcpyHostToDevice, S->stream);
   if (e != hipSuccess) return cleanup(fail(LMPO_EHIP, std::string("site table upload: ") + hipGetErrorString(e)));
   std::vector<int> ones(std::max(S->N - 1, 1), 1);
   e = hipMemcpyAsync(S->d_dims, ones.data(), ones.size() * sizeof(int), hipMemcpyHostToDevice, S->stream);
   if (e != hipSuccess) return cleanup(fail(LMPO_EHIP, std::string("dims upload: ") + hipGetErrorString(e)));
-  // product state: per site (1, 0, 0, 0) / sqrt(2) with +-1/sqrt(2) on the axis
-  const double r2 = 1.0 / std::sqrt(2.0);
-  std::vector<double2> sitev(4 * S->N);
-  for (int i = 0; i < S->N; ++i) {
-    for (int a = 0; a < 4; ++a) sitev[4 * i + a] = make_double2(0, 0);
-    sitev[4 * i] = make_double2(r2, 0);
-    sitev[4 * i + init[i].second] = make_double2(init[i].first * r2, 0);
-  }
-  for (int i = 0; i < S->N; ++i) {
-    e = hipMemcpyAsync(S->site[i], &sitev[4 * i], 4 * sizeof(double2), hipMemcpyHostToDevice, S->stream);
-    if (e != hipSuccess) return cleanup(fail(LMPO_EHIP, std::string("site upload: ") + hipGetErrorString(e)));
-  }
+  if ((rc = upload_product(S, init))) return cleanup(rc);
   S->grid = svd_grid_size();
   S->dims_est.assign(std::max(S->N - 1, 1), 1);
   e = S->ring.init(S->N - 1);
@@ -775,6 +876,60 @@ int lmpo_apply_gate(lmpo_state *S, int32_t k, int32_t half, int32_t ascending) {
   if (!S) return fail(LMPO_EINVAL, "state is null");
   if (k < 0 || k >= S->N - 1) return fail(LMPO_EINVAL, "bond out of range");
   return apply_gate(S, k, half ? 1 : 0, ascending);
+}
+
+int lmpo_apply_superop(lmpo_state *S, int32_t i, int32_t j, const double *G) {
+  if (!S || !G) return fail(LMPO_EINVAL, "null argument");
+  int rc = pair_args(S, i, j);
+  if (rc || (rc = upload_user_gate(S, i, j, G))) return rc;
+  return apply_pair(S, std::min(i, j), std::max(i, j), S->d_user, true);
+}
+
+int lmpo_apply_unitary(lmpo_state *S, int32_t i, int32_t j, const double *U) {
+  if (!S || !U) return fail(LMPO_EINVAL, "null argument");
+  int rc = pair_args(S, i, j);
+  if (rc) return rc;
+  std::vector<std::complex<double>> u(16), G(256);
+  for (int e = 0; e < 16; ++e) u[e] = {U[2 * e], U[2 * e + 1]};
+  for (const auto &v : u)
+    if (!std::isfinite(v.real()) || !std::isfinite(v.imag())) return fail(LMPO_EINVAL, "non-finite unitary entry");
+  unitary_channel_pauli(u.data(), G.data());
+  if ((rc = upload_user_gate(S, i, j, reinterpret_cast<const double *>(G.data())))) return rc;
+  return apply_pair(S, std::min(i, j), std::max(i, j), S->d_user, true);
+}
+
+int lmpo_init_graph_state(lmpo_state *S, int32_t n_pairs, const int32_t *pairs) {
+  if (!S) return fail(LMPO_EINVAL, "state is null");
+  if (n_pairs < 0 || (n_pairs > 0 && !pairs)) return fail(LMPO_EINVAL, "bad pair list");
+  for (int p = 0; p < n_pairs; ++p) {
+    int rc = pair_args(S, pairs[2 * p], pairs[2 * p + 1]);
+    if (rc) return rc;
+  }
+  HIP_TRY(hipStreamSynchronize(S->stream));
+  std::vector<std::pair<int, int>> plus_x(S->N, {1, 1});
+  int rc = upload_product(S, plus_x);
+  if (rc) return rc;
+  // a fresh initial condition: time 0, nothing discarded yet
+  S->step_index = 0;
+  for (long long &v : S->ring.issued) v = -1;
+  std::fill(S->dims_est.begin(), S->dims_est.end(), 1);
+  const double zd = 0.0;
+  HIP_TRY(hipMemcpyAsync(S->disc, &zd, sizeof(double), hipMemcpyHostToDevice, S->stream));
+  if (n_pairs == 0) {
+    HIP_TRY(hipStreamSynchronize(S->stream));
+    return LMPO_OK;
+  }
+  // CZ = diag(1, 1, 1, -1): rho -> CZ rho CZ on every listed pair
+  std::vector<std::complex<double>> cz(16, 0.0), G(256);
+  cz[0] = cz[5] = cz[10] = 1.0;
+  cz[15] = -1.0;
+  unitary_channel_pauli(cz.data(), G.data());
+  if ((rc = upload_user_gate(S, 0, 1, reinterpret_cast<const double *>(G.data())))) return rc;
+  for (int p = 0; p < n_pairs; ++p) {
+    const int a = pairs[2 * p], b = pairs[2 * p + 1];
+    if ((rc = apply_pair(S, std::min(a, b), std::max(a, b), S->d_user, true))) return rc;
+  }
+  return LMPO_OK;
 }
 
 int lmpo_last_spectrum(lmpo_state *S, int32_t n_out, double *sv, int32_t *n_sv, int32_t *kept) {
@@ -1013,6 +1168,8 @@ int batch_check_chains(lmpo_state *const *chains, int n) {
     if (chains[c]->stream != chains[0]->stream) return fail(LMPO_EINVAL, "all chains of a batch must share one stream");
     if (chains[c]->opt.trotter_order != chains[0]->opt.trotter_order)
       return fail(LMPO_EINVAL, "all chains of a batch must use the same Trotter order");
+    if (!chains[c]->chain)
+      return fail(LMPO_EUNSUPPORTED, "the batched form runs open chains only (bonds (b, b+1) in order)");
     for (int d = 0; d < c; ++d)
       if (chains[d] == chains[c]) return fail(LMPO_EINVAL, "a chain appears twice in the batch");
   }

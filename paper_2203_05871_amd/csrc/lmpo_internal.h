@@ -21,13 +21,18 @@ struct ModelHost {
 
 bool expm_pade13(int n, const std::complex<double> *A, std::complex<double> *out);
 void bond_generator_pauli(const ModelHost &m, int bond, std::complex<double> *L);
+// 16x16 superoperators in the Pauli-product basis B_ab = P_a (x) P_b (index 4a + b):
+// rho -> U rho U^+ for a two-qubit unitary U (row-major 4x4, basis |k_i k_j>,
+// index 2 k_i + k_j), and the exchange of the two sites.
+void unitary_channel_pauli(const std::complex<double> *U, std::complex<double> *G);
+void swap_pauli(std::complex<double> *G);
 
 // Block one-sided Jacobi: columns are processed in blocks of JB, two blocks
 // (JP columns) per workgroup and round.
 constexpr int JB = 8;
 constexpr int JP = 2 * JB;
 constexpr int kMaxDim = 2048;  // largest block side (4 chi) the sort handles
-constexpr int kGateSlots = 6;  // gates per bond: second- and fourth-order time fractions
+constexpr int kGateSlots = 7;  // gates per bond: second- and fourth-order time fractions
 
 // ---- kernel launchers (kernels.hip, svd.hip) ----
 void launch_contract_gate(hipStream_t s, int precision, double2 *const *sites, const int *dims, int N, int k,

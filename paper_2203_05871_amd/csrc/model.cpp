@@ -250,4 +250,26 @@ void bond_generator_pauli(const ModelHost &m, int bond, std::complex<double> *Lo
   }
 }
 
+void unitary_channel_pauli(const std::complex<double> *U, std::complex<double> *G) {
+  M4 u;
+  for (int r = 0; r < 4; ++r)
+    for (int c = 0; c < 4; ++c) u.a[r][c] = U[4 * r + c];
+  const M4 ud = dagger4(u);
+  const double inv_sqrt2 = 1.0 / std::sqrt(2.0);
+  M4 basis[16];
+  for (int a = 0; a < 4; ++a)
+    for (int c = 0; c < 4; ++c)
+      basis[4 * a + c] = kron(scale(pauli2(a), inv_sqrt2), scale(pauli2(c), inv_sqrt2));
+  for (int col = 0; col < 16; ++col) {
+    const M4 image = mul4(mul4(u, basis[col]), ud);
+    for (int row = 0; row < 16; ++row) G[row * 16 + col] = trace4(mul4(basis[row], image));
+  }
+}
+
+void swap_pauli(std::complex<double> *G) {
+  for (int e = 0; e < 256; ++e) G[e] = 0.0;
+  for (int a = 0; a < 4; ++a)
+    for (int c = 0; c < 4; ++c) G[(4 * c + a) * 16 + (4 * a + c)] = 1.0;
+}
+
 }  // namespace lmpo

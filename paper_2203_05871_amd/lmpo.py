@@ -62,7 +62,7 @@ EXPORTS = [
     "lmpo_destroy", "lmpo_last_error", "lmpo_get_site", "lmpo_set_site", "lmpo_set_centre",
     "lmpo_get_centre", "lmpo_get_gate", "lmpo_apply_gate", "lmpo_last_spectrum", "lmpo_svd_stats",
     "lmpo_svd_profile", "lmpo_profile_begin", "lmpo_profile_end", "lmpo_set_workgroups",
-    "lmpo_renyi2", "lmpo_osee",
+    "lmpo_renyi2", "lmpo_osee", "lmpo_apply_superop", "lmpo_apply_unitary", "lmpo_init_graph_state",
     "lmpo_batch_arena_bytes", "lmpo_batch_create", "lmpo_batch_evolve_step", "lmpo_batch_sync",
     "lmpo_batch_plan", "lmpo_batch_profile_begin", "lmpo_batch_profile_end", "lmpo_batch_destroy",
     "lmpo_batch_set_autotune", "lmpo_autotune_table",
@@ -109,6 +109,9 @@ def load_library(path: str = LIB_PATH):
         "lmpo_set_workgroups": (ctypes.c_int, [P, i32]),
         "lmpo_renyi2": (ctypes.c_int, [P, pdbl]),
         "lmpo_osee": (ctypes.c_int, [P, i32, pdbl]),
+        "lmpo_apply_superop": (ctypes.c_int, [P, i32, i32, pdbl]),
+        "lmpo_apply_unitary": (ctypes.c_int, [P, i32, i32, pdbl]),
+        "lmpo_init_graph_state": (ctypes.c_int, [P, i32, pi32]),
         "lmpo_batch_arena_bytes": (ctypes.c_size_t, [ctypes.POINTER(P), i32]),
         "lmpo_batch_create": (ctypes.c_int, [ctypes.POINTER(P), i32, P, ctypes.c_size_t, ctypes.POINTER(P)]),
         "lmpo_batch_evolve_step": (ctypes.c_int, [P, i32]),
@@ -216,6 +219,23 @@ class Chain:
 
     def apply_gate(self, k, half, ascending):
         _check(self._lib.lmpo_apply_gate(self._h, int(k), int(bool(half)), int(bool(ascending))))
+
+    def apply_superop(self, i, j, G):
+        """16x16 superoperator (Pauli basis, index 4 a_i + a_j) on qubits (i, j)."""
+        G = np.asarray(G, dtype=np.complex128).reshape(16, 16)
+        buf = np.ascontiguousarray(np.stack([G.real, G.imag], axis=-1).reshape(-1))
+        _check(self._lib.lmpo_apply_superop(self._h, int(i), int(j), _dptr(buf)))
+
+    def apply_unitary(self, i, j, U):
+        """rho -> U rho U^+ for a 4x4 unitary on qubits (i, j), basis |k_i k_j>."""
+        U = np.asarray(U, dtype=np.complex128).reshape(4, 4)
+        buf = np.ascontiguousarray(np.stack([U.real, U.imag], axis=-1).reshape(-1))
+        _check(self._lib.lmpo_apply_unitary(self._h, int(i), int(j), _dptr(buf)))
+
+    def init_graph_state(self, pairs):
+        """Restart from the graph state of Eq. (graph_state) on the given pairs."""
+        p = np.ascontiguousarray(np.asarray(pairs, dtype=np.int32).reshape(-1, 2))
+        _check(self._lib.lmpo_init_graph_state(self._h, len(p), _iptr(p)))
 
     # -- readouts --
     def trace(self):

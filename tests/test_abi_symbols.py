@@ -52,5 +52,9 @@ def test_arena_size_and_argument_errors_on_host():
     with pytest.raises(lmpo.LmpoError, match="rates"):
         lmpo.arena_bytes(bad, 0.1, 8)
     lad = workloads.ladder_model(3)
-    with pytest.raises(lmpo.LmpoError, match="chains"):
-        lmpo.arena_bytes(lad, 0.1, 8)
+    assert lmpo.arena_bytes(lad, 0.1, 8) > 0  # bonds apart along the path are accepted
+    lone = dict(lad)
+    lone["bonds"] = lad["bonds"][lad["bonds"].max(axis=1) < 5]  # qubit 5 in no bond
+    lone["J"], lone["Jz"] = lad["J"][: len(lone["bonds"])], lad["Jz"][: len(lone["bonds"])]
+    with pytest.raises(lmpo.LmpoError, match="belong to a bond"):
+        lmpo.arena_bytes(lone, 0.1, 8)

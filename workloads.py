@@ -123,6 +123,14 @@ def ladder_model(n_rungs=8, J=1.0, delta=5.0, omega=1.0, g0=0.1, g2=0.05):
     }
 
 
+def c5():
+    """2 x 8 ladder (N = 16, 8 rungs, 14 legs two sites apart on the path),
+    chi_max = 128, cutoff 1e-12, tau = 0.05, 40 steps, init +z."""
+    m = ladder_model(8)
+    run = {"tau": 0.05, "steps": 40, "chi_max": 128, "cutoff": 1e-12, "init": "+z"}
+    return m, run
+
+
 def random_model(N, seed, bonds=None, zz=True, all_fields=True):
     """A generic model with every term switched on (for coverage tests)."""
     rng = np.random.default_rng(seed)
