@@ -74,8 +74,11 @@ typedef struct {
 /* Numerical controls (Sec. 6, "Numerical simulation control"). */
 typedef struct {
   double tau;            /* time step, > 0 */
-  int32_t trotter_order; /* 2, or 4: the symmetric triple product S2(w1 t) S2(w0 t) S2(w1 t),
-                            w1 = 1/(2 - 2^(1/3)), w0 = 1 - 2 w1 (7 layers); 3: LMPO_EUNSUPPORTED */
+  int32_t trotter_order; /* 2; 3 (open chain only): the product A(7/24) B(2/3) A(3/4) B(-2/3)
+                            A(-1/24) B(1) of the even (A) and odd (B) bond layers (R. D. Ruth,
+                            1983); or 4: the symmetric triple product S2(w1 t) S2(w0 t) S2(w1 t),
+                            w1 = 1/(2 - 2^(1/3)), w0 = 1 - 2 w1 (7 layers).  Others:
+                            LMPO_EUNSUPPORTED */
   int32_t chi_max;       /* max_dim_rho, >= 1 */
   double cutoff;         /* cut_off_rho: largest discarded squared Schmidt weight,
                             relative to the block's total; >= 0 */
@@ -100,7 +103,8 @@ int lmpo_create(const lmpo_model *model, const lmpo_options *opt, const char *in
 
 /* Enqueue n_steps >= 0 Trotter steps.  Open chain (bond b = (b, b+1) for
  * b = 0..N-2, in that order): layers A(tau/2) B(tau) A(tau/2) over even bonds
- * (A) and odd bonds (B) (order 4: the seven layers of the composition).  Any
+ * (A) and odd bonds (B) (orders 3 and 4: the six or seven layers of the
+ * composition; layer L n + j of step n runs ascending in k iff even).  Any
  * other bond list: the symmetric sweep F(tau/2) R(tau/2), F applying
  * exp(tau/2 L_b) for b = 0, 1, ..., R the same factors in reverse order (order
  * 4: S2(w1 tau) S2(w0 tau) S2(w1 tau) of such sweeps); a pair (i, j) with

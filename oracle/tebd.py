@@ -13,6 +13,10 @@ printed there, the symmetric triple product of second-order steps is used):
     w1 = 1 / (2 - 2^(1/3)), w0 = 1 - 2 w1,
 with the two adjacent A half-layers merged (A layers commute), i.e. seven
 layers A(w1/2) B(w1) A((w1+w0)/2) B(w0) A((w0+w1)/2) B(w1) A(w1/2) (times tau).
+Third order (trotter_order = 3, chain only): the non-symmetric product of the
+two layer operators A(7/24) B(2/3) A(3/4) B(-2/3) A(-1/24) B(1) (R. D. Ruth,
+IEEE Trans. Nucl. Sci. 30 (1983) 2669); negative fractions run the dissipators
+backwards for that sub-step.
 Global layer l = L*step + j (L layers per step); gates of layer l run in
 ascending k when l is even, descending when l is odd.
 Per gate (bond k): bring the orthogonality centre onto (k, k+1); form the
@@ -79,12 +83,14 @@ def trotter_layers(order=2):
     """[(bond parity, fraction of tau)] of one step (see the module header)."""
     if order == 2:
         return [(0, 0.5), (1, 1.0), (0, 0.5)]
+    if order == 3:
+        return [(0, 7.0 / 24.0), (1, 2.0 / 3.0), (0, 0.75), (1, -2.0 / 3.0), (0, -1.0 / 24.0), (1, 1.0)]
     if order == 4:
         w1 = 1.0 / (2.0 - 2.0 ** (1.0 / 3.0))
         w0 = 1.0 - 2.0 * w1
         return [(0, 0.5 * w1), (1, w1), (0, 0.5 * (w1 + w0)), (1, w0), (0, 0.5 * (w1 + w0)), (1, w1),
                 (0, 0.5 * w1)]
-    raise ValueError("trotter order must be 2 or 4")
+    raise ValueError("trotter order must be 2, 3 or 4")
 
 
 def step_schedule(N, step, order=2):
@@ -117,7 +123,7 @@ def sweep_fractions(order=2):
         w1 = 1.0 / (2.0 - 2.0 ** (1.0 / 3.0))
         w0 = 1.0 - 2.0 * w1
         return [0.5 * w1, 0.5 * w0, 0.5 * w1]
-    raise ValueError("trotter order must be 2 or 4")
+    raise ValueError("on a general bond list the trotter order must be 2 or 4")
 
 
 def sweep_schedule(model, order=2):

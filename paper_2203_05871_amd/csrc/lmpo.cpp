@@ -56,6 +56,10 @@ constexpr int kStats = 8;  // [last sweeps, last C, last R, -, total sweeps, tot
 // composition S2(w1 tau) S2(w0 tau) S2(w1 tau), w1 = 1 / (2 - 2^(1/3)),
 // w0 = 1 - 2 w1, with adjacent A half-layers merged: seven layers
 // A(w1/2) B(w1) A((w1+w0)/2) B(w0) A((w0+w1)/2) B(w1) A(w1/2).
+// Slots 7..11 (with slot 0) serve the third-order product (R. D. Ruth,
+// IEEE Trans. Nucl. Sci. 30 (1983) 2669) of the two layer operators,
+// A(7/24) B(2/3) A(3/4) B(-2/3) A(-1/24) B(1), whose negative fractions run
+// the dissipators backwards for that sub-step.
 // On other bond lists a second-order step is the symmetric sweep
 // F(tau/2) R(tau/2) over the bonds (slot 1); fourth order composes such
 // sweeps with w1/2 (slot 2) and w0/2 (slot 6).
@@ -68,7 +72,12 @@ double gate_fraction(int slot) {
     case 3: return w1;
     case 4: return 0.5 * (w1 + w0);
     case 5: return w0;
-    default: return 0.5 * w0;
+    case 6: return 0.5 * w0;
+    case 7: return 7.0 / 24.0;
+    case 8: return 2.0 / 3.0;
+    case 9: return 0.75;
+    case 10: return -2.0 / 3.0;
+    default: return -1.0 / 24.0;
   }
 }
 
@@ -86,8 +95,9 @@ struct TrotterLayer {
 
 const std::vector<TrotterLayer> &trotter_layers(int order) {
   static const std::vector<TrotterLayer> o2 = {{0, 1}, {1, 0}, {0, 1}};
+  static const std::vector<TrotterLayer> o3 = {{0, 7}, {1, 8}, {0, 9}, {1, 10}, {0, 11}, {1, 0}};
   static const std::vector<TrotterLayer> o4 = {{0, 2}, {1, 3}, {0, 4}, {1, 5}, {0, 4}, {1, 3}, {0, 2}};
-  return order == 4 ? o4 : o2;
+  return order == 4 ? o4 : order == 3 ? o3 : o2;
 }
 }  // namespace
 
@@ -188,6 +198,13 @@ struct Sizes {
   int max_cols = 1, max_dim = 1, cap_max = 1;
 };
 
+bool is_chain(const lmpo_model *m) {
+  if (m->n_bonds != m->n_qubits - 1) return false;
+  for (int b = 0; b < m->n_bonds; ++b)
+    if (m->bond_ij[2 * b] != b || m->bond_ij[2 * b + 1] != b + 1) return false;
+  return true;
+}
+
 int validate(const lmpo_model *m, const lmpo_options *o) {
   if (!m || !o) return fail(LMPO_EINVAL, "null model or options");
   if (m->n_qubits < 2) return fail(LMPO_EINVAL, "n_qubits must be >= 2");
@@ -210,8 +227,7 @@ int validate(const lmpo_model *m, const lmpo_options *o) {
   if (!(o->cutoff >= 0) || !std::isfinite(o->cutoff)) return fail(LMPO_EINVAL, "cutoff must be >= 0");
   if (o->precision != LMPO_FP64 && o->precision != LMPO_FP32_CONTRACT)
     return fail(LMPO_EINVAL, "precision must be LMPO_FP64 or LMPO_FP32_CONTRACT");
-  if (o->trotter_order != 2 && o->trotter_order != 4)
-    return fail(LMPO_EUNSUPPORTED, "trotter_order must be 2 or 4 (order 3 is not implemented)");
+  if (o->trotter_order < 2 || o->trotter_order > 4) return fail(LMPO_EUNSUPPORTED, "trotter_order must be 2, 3 or 4");
   if (o->chi_max > kMaxDim / 4) return fail(LMPO_EUNSUPPORTED, "chi_max above 512 is not supported");
   std::vector<int> deg(m->n_qubits, 0);
   for (int b = 0; b < m->n_bonds; ++b) {
@@ -220,14 +236,9 @@ int validate(const lmpo_model *m, const lmpo_options *o) {
   }
   for (int s = 0; s < m->n_qubits; ++s)
     if (deg[s] == 0) return fail(LMPO_EINVAL, "every qubit must belong to a bond (its on-site terms ride on them)");
+  if (o->trotter_order == 3 && !is_chain(m))
+    return fail(LMPO_EUNSUPPORTED, "trotter_order 3 needs the open chain (two commuting layer operators)");
   return LMPO_OK;
-}
-
-bool is_chain(const lmpo_model *m) {
-  if (m->n_bonds != m->n_qubits - 1) return false;
-  for (int b = 0; b < m->n_bonds; ++b)
-    if (m->bond_ij[2 * b] != b || m->bond_ij[2 * b + 1] != b + 1) return false;
-  return true;
 }
 
 Sizes compute_sizes(int N, int chi_max) {
@@ -1422,7 +1433,8 @@ int lmpo_batch_evolve_step(lmpo_batch *B, int32_t n_steps) {
     r.dims_out = B->d_dims + B->dims_off[c];
     r.precision = S->opt.precision;
     r.force_trace = S->opt.force_trace ? 1 : 0;
-    r.step_parity = (int)(S->step_index & 1);
+    // layer L n + j runs ascending iff even: with L even only j decides
+    r.step_parity = trotter_layers(S->opt.trotter_order).size() % 2 ? (int)(S->step_index & 1) : 0;
     centres[c] = S->centre;
   }
   int rc = batch_upload(B, {{B->d_chains, recs.data(), recs.size() * sizeof(BatchChain)},
@@ -1449,8 +1461,9 @@ int lmpo_batch_evolve_step(lmpo_batch *B, int32_t n_steps) {
     if ((rc = batch_replan(B))) return rc;
     if (trial >= 0) HIP_TRY(hipEventRecord(B->tune_ev[0], B->stream));
     const std::vector<TrotterLayer> &layers = trotter_layers(B->ch[0]->opt.trotter_order);
+    const int ls = layers.size() % 2 ? s : 0;  // see step_parity
     for (int j = 0; j < (int)layers.size(); ++j)
-      if ((rc = batch_launch(B, s, j, layers[j], j + 1 == (int)layers.size()))) return rc;
+      if ((rc = batch_launch(B, ls, j, layers[j], j + 1 == (int)layers.size()))) return rc;
     if (trial >= 0) {
       HIP_TRY(hipEventRecord(B->tune_ev[1], B->stream));
       HIP_TRY(hipEventSynchronize(B->tune_ev[1]));

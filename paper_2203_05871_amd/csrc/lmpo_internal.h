@@ -32,7 +32,7 @@ void swap_pauli(std::complex<double> *G);
 constexpr int JB = 8;
 constexpr int JP = 2 * JB;
 constexpr int kMaxDim = 2048;  // largest block side (4 chi) the sort handles
-constexpr int kGateSlots = 7;  // gates per bond: second- and fourth-order time fractions
+constexpr int kGateSlots = 12;  // gates per bond: the time fractions of orders 2, 3 and 4
 
 // ---- kernel launchers (kernels.hip, svd.hip) ----
 void launch_contract_gate(hipStream_t s, int precision, double2 *const *sites, const int *dims, int N, int k,

@@ -1031,9 +1031,10 @@ __global__ __launch_bounds__(NT) void svd_persistent_kernel(SvdLaunch a) {
 // group_size[g] workgroups; the group walks the layer's gates in order, each
 // preceded by the centre hops that bring the orthogonality centre onto the
 // bond, as the single-chain executor does (the same device code per op).
-// The layer of chain g is the global layer L n_g + j (L = 3 or 7 layers per
-// step, n_g = its step count); it runs ascending when that index is even,
-// i.e. (L odd) when step_parity[g] + local_step + j is even.  Bonds b =
+// The layer of chain g is the global layer L n_g + j (L = 3, 6 or 7 layers
+// per step, n_g = its step count); it runs ascending when that index is even,
+// i.e. when step_parity[g] + local_step + j is even (the host passes zeros
+// for both when L is even).  Bonds b =
 // parity, parity + 2, ... < N - 1 get the gate in table slot `slot`.
 // ---------------------------------------------------------------------------
 union SharedBatch {

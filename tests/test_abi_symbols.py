@@ -46,7 +46,10 @@ def test_arena_size_and_argument_errors_on_host():
     with pytest.raises(lmpo.LmpoError, match="cutoff"):
         lmpo.arena_bytes(m, 0.1, 8, cutoff=-1)
     with pytest.raises(lmpo.LmpoError, match="trotter_order"):
-        lmpo.arena_bytes(m, 0.1, 8, order=3)
+        lmpo.arena_bytes(m, 0.1, 8, order=5)
+    assert lmpo.arena_bytes(m, 0.1, 8, order=3) > 0
+    with pytest.raises(lmpo.LmpoError, match="trotter_order 3"):
+        lmpo.arena_bytes(workloads.ladder_model(3), 0.1, 8, order=3)
     bad = dict(m)
     bad["g0"] = -m["g0"]
     with pytest.raises(lmpo.LmpoError, match="rates"):

@@ -1,6 +1,7 @@
-"""GPU parity of the paper features next to the step: the fourth-order Trotter
-scheme (Sec. 6, trotter_order), the second Renyi entropy (Eq. S_2) and the
-operator-space entanglement entropy (Eq. OSEE), against the FP64 oracle."""
+"""GPU parity of the paper features next to the step: the third- and
+fourth-order Trotter schemes (Sec. 6, trotter_order), the second Renyi entropy
+(Eq. S_2) and the operator-space entanglement entropy (Eq. OSEE), against the
+FP64 oracle."""
 import numpy as np
 import pytest
 
@@ -35,36 +36,43 @@ def oracle_obs(mps, N):
     return np.array(z + x + zz)
 
 
-def test_fourth_order_exact_chain(lib):
+@pytest.mark.parametrize("order", [3, 4])
+def test_higher_order_exact_chain(lib, order):
     """N = 6 at chi = 64 = 4^3 (no truncation), every model term on, 12 steps."""
     m = workloads.random_model(6, 9)
-    ch = lib.Chain(m, 0.05, 64, 0.0, "fp64", "+x", order=4)
+    ch = lib.Chain(m, 0.05, 64, 0.0, "fp64", "+x", order=order)
     ref = tebd.MPS.product("+x", 6)
     for n in range(0, 12, 4):
         ch.evolve(4)
-        tebd.evolve(ref, m, 0.05, 4, 64, 0.0, first_step=n, order=4)
+        tebd.evolve(ref, m, 0.05, 4, 64, 0.0, first_step=n, order=order)
         assert np.abs(obs(ch, 6) - oracle_obs(ref, 6)).max() < 1e-10
     assert ch.bond_dims() == ref.bond_dims()
     ch.close()
 
 
-def test_fourth_order_truncated(lib):
+@pytest.mark.parametrize("order", [3, 4])
+def test_higher_order_truncated(lib, order):
     """Jittered chain N = 10, chi_max = 12 binding, cutoff 1e-12, 8 steps."""
     m = workloads.jittered_chain(10, 4)
-    ch = lib.Chain(m, 0.05, 12, 1e-12, "fp64", "+x", order=4)
+    ch = lib.Chain(m, 0.05, 12, 1e-12, "fp64", "+x", order=order)
     ref = tebd.MPS.product("+x", 10)
     ch.evolve(8)
-    tebd.evolve(ref, m, 0.05, 8, 12, 1e-12, order=4)
+    tebd.evolve(ref, m, 0.05, 8, 12, 1e-12, order=order)
     assert ch.bond_dims() == ref.bond_dims()
     assert max(ch.bond_dims()) == 12
     assert np.abs(obs(ch, 10) - oracle_obs(ref, 10)).max() < 1e-10
     ch.close()
 
 
-def test_fourth_order_batch_equals_single(lib):
+@pytest.mark.parametrize("order", [3, 4])
+def test_higher_order_batch_equals_single(lib, order):
+    """A batch continues chains already stepped alone (odd step count), so the
+    per-chain layer directions must follow each chain's own step count."""
     ms = [workloads.jittered_chain(7, 1), workloads.random_model(5, 2)]
-    b_chains = [lib.Chain(m, 0.05, 16, 1e-12, "fp64", "+x", order=4) for m in ms]
-    singles = [lib.Chain(m, 0.05, 16, 1e-12, "fp64", "+x", order=4) for m in ms]
+    b_chains = [lib.Chain(m, 0.05, 16, 1e-12, "fp64", "+x", order=order) for m in ms]
+    singles = [lib.Chain(m, 0.05, 16, 1e-12, "fp64", "+x", order=order) for m in ms]
+    b_chains[0].evolve(1)
+    singles[0].evolve(1)
     b = lib.Batch(b_chains)
     b.evolve(3)
     b.sync()
