@@ -153,3 +153,10 @@ def graph_state_vector(N, pairs):
     t = rho.reshape((2,) * (2 * N))
     perm = [q for s in range(N) for q in (s, N + s)]
     return t.transpose(perm).reshape(-1)
+
+
+def adjoint(v, N):
+    """|rho^+>> from |rho>> (rho^+[k, b] = conj(rho[b, k]) on every site)."""
+    t = np.conj(v).reshape((2, 2) * N)
+    perm = [q for s in range(N) for q in (2 * s + 1, 2 * s)]
+    return t.transpose(perm).reshape(-1)

@@ -243,6 +243,38 @@ class MPS:
         for k in range(i + 1, j):
             self.apply_gate(k, P, chi_max, cutoff, True)
 
+    # -- Hermitian part (Sec. 6, force_rho_hermitian_step) --
+    def hermitize(self, chi_max, cutoff):
+        """rho -> (rho + rho^+)/2.  rho^+ has site tensors conj(A_k) with the
+        site's ket and bra exchanged; the sum is the MPS of the direct sums of
+        the two (bonds doubled, 1/2 on the first site), made left-orthonormal
+        by QR from the left, then compressed from the right by the truncated
+        two-site SVD of every bond (the identity gate, usual rule).  The
+        centre ends on site 0."""
+        N = self.N
+        swap = np.array([0, 2, 1, 3])  # local (ket, bra) -> (bra, ket)
+        B = []
+        for k, A in enumerate(self.A):
+            D = np.conj(A[:, swap, :])
+            cl, _, cr = A.shape
+            if N == 1:
+                T = A + D
+            elif k == 0:
+                T = np.concatenate([A, D], axis=2)
+            elif k == N - 1:
+                T = np.concatenate([A, D], axis=0)
+            else:
+                T = np.zeros((2 * cl, 4, 2 * cr), dtype=np.complex128)
+                T[:cl, :, :cr] = A
+                T[cl:, :, cr:] = D
+            B.append(0.5 * T if k == 0 else T)
+        self.A = B
+        self.centre = 0
+        self.move_centre(N - 1)
+        ident = np.eye(16, dtype=np.complex128)
+        for k in range(N - 2, -1, -1):
+            self.apply_gate(k, ident, chi_max, cutoff, False)
+
     # -- contractions with product covectors --
     def contract(self, covectors):
         """sum over all indices of prod_k covectors[k] . A_k (a scalar)."""
@@ -306,10 +338,12 @@ def gate_tables(model, tau, order=2):
 
 
 def evolve(mps, model, tau, steps, chi_max, cutoff, force_trace=True, gates=None,
-           observer=None, first_step=0, order=2):
+           observer=None, first_step=0, order=2, hermitian_every=0):
     """Run `steps` Trotter steps; observer(step_done, mps) after each step.
     The open chain in order takes the layered schedule, any other bond list
-    the symmetric bond-list sweep (module header)."""
+    the symmetric bond-list sweep (module header).  With hermitian_every = k
+    >= 1, rho -> (rho + rho^+)/2 ends every k-th step (global count), before
+    the trace is forced."""
     chain = is_chain(model)
     if gates is None:
         gates = gate_tables(model, tau, order)
@@ -322,6 +356,8 @@ def evolve(mps, model, tau, steps, chi_max, cutoff, force_trace=True, gates=None
             for b, frac, fwd in sweep_schedule(model, order):
                 i, j = int(bonds[b, 0]), int(bonds[b, 1])
                 mps.apply_pair_gate(i, j, gates[(b, frac)], chi_max, cutoff, fwd)
+        if hermitian_every and (n + 1) % hermitian_every == 0:
+            mps.hermitize(chi_max, cutoff)
         if force_trace:
             mps.renormalize()
         if observer is not None:

@@ -138,3 +138,70 @@ def test_third_order_schedule_and_tebd_equals_dense():
     v = dense.trotter_evolve(dense.product_vector("+x", 5), m, 0.07, 3, order=3)
     for ops in ({0: lm.SZ}, {2: lm.SX, 4: lm.SY}, {1: lm.SZ, 3: lm.SZ}):
         assert abs(mps.expect(ops) - dense.expect(v, 5, ops)) < 1e-13
+
+
+def nonhermitian_mps(N, seed, chi=4):
+    """A generic MPS (not Hermitian), in canonical form with centre N-1."""
+    rng = np.random.default_rng(seed)
+    dims = [1] + [min(chi, 4 ** (k + 1), 4 ** (N - k - 1)) for k in range(N - 1)] + [1]
+    A = [rng.standard_normal((dims[k], 4, dims[k + 1])) + 1j * rng.standard_normal((dims[k], 4, dims[k + 1]))
+         for k in range(N)]
+    mps = tebd.MPS(A, centre=0)
+    mps.move_centre(N - 1)
+    return mps
+
+
+def test_adjoint_vector_is_the_matrix_adjoint():
+    rng = np.random.default_rng(3)
+    v = rng.standard_normal(4 ** 3) + 1j * rng.standard_normal(4 ** 3)
+    M = dense.to_matrix(v, 3)
+    assert np.abs(dense.to_matrix(dense.adjoint(v, 3), 3) - M.conj().T).max() == 0
+
+
+def test_hermitize_equals_dense_hermitian_part():
+    """Without truncation the MPS result is (rho + rho^+)/2 of the full vector,
+    whose matrix is Hermitian; the trace becomes Re tr(rho)."""
+    N = 5
+    mps = nonhermitian_mps(N, 1)
+    v = dense.mps_to_vector(mps.A)
+    tr = mps.trace()
+    mps.hermitize(4 ** 3, 1e-14)  # the cutoff drops the round-off tail of the rank-8 sum
+    h = dense.mps_to_vector(mps.A)
+    ref = 0.5 * (v + dense.adjoint(v, N))
+    assert np.abs(h - ref).max() < 1e-12 * np.abs(ref).max()
+    M = dense.to_matrix(h, N)
+    assert np.abs(M - M.conj().T).max() < 1e-12 * np.abs(M).max()
+    assert abs(mps.trace() - tr.real) < 1e-12 * abs(tr)
+    assert mps.centre == 0
+    assert max(mps.bond_dims()) <= 2 * 4
+
+
+def test_hermitize_keeps_a_hermitian_state():
+    """An evolved (Hermitian) state is unchanged, and the compression returns
+    the bond dims to their exact ranks (the doubled copies are dependent)."""
+    m = workloads.random_model(5, 3)
+    mps = tebd.MPS.product("+x", 5)
+    tebd.evolve(mps, m, 0.05, 3, 1024, 1e-13)
+    v = dense.mps_to_vector(mps.A)
+    dims = mps.bond_dims()
+    mps.hermitize(1024, 1e-13)
+    assert np.abs(dense.mps_to_vector(mps.A) - v).max() < 1e-12
+    assert mps.bond_dims() == dims
+
+
+def test_evolve_with_hermitian_every_matches_dense():
+    """Second-order steps with the Hermitian part taken every 2nd step, no
+    truncation, against the same sequence on the full vector."""
+    m = workloads.random_model(4, 8)
+    N = 4
+    mps = nonhermitian_mps(N, 2)
+    v = dense.mps_to_vector(mps.A)
+    v = v / dense.trace(v, N)
+    tebd.evolve(mps, m, 0.05, 4, 1024, 0.0, hermitian_every=2)
+    gates = tebd.gate_tables(m, 0.05)
+    for n in range(4):
+        v = dense.trotter_evolve(v, m, 0.05, 1, gates=gates, first_step=n, force_trace=False)
+        if (n + 1) % 2 == 0:
+            v = 0.5 * (v + dense.adjoint(v, N))
+        v = v / dense.trace(v, N)
+    assert np.abs(dense.mps_to_vector(mps.A) - v).max() < 1e-12
