@@ -85,6 +85,10 @@ typedef struct {
   int32_t precision;     /* LMPO_FP64, or LMPO_FP32_CONTRACT: two-site contractions
                             in FP32 (FP32 accumulation), SVD/truncation/trace FP64 */
   int32_t force_trace;   /* 1: rho -> rho / tr(rho) after every step */
+  int32_t force_hermitian_every; /* force_rho_hermitian_step: k >= 1 replaces rho by
+                            (rho + rho^+)/2 after every k-th step (before the trace is
+                            forced), 0 never.  k >= 1 doubles the bond capacities (arena
+                            about 4x) and needs chi_max <= 256 */
 } lmpo_options;
 
 typedef struct lmpo_state lmpo_state;
@@ -162,7 +166,8 @@ const char *lmpo_last_error(void);
 
 /* Site tensor k in the Pauli basis: writes dims[0..1] = (chi_l, chi_r) and, if
  * out is non-NULL, chi_l*4*chi_r complex values (interleaved, [l][a][r]).
- * Synchronises.  lmpo_set_site replaces it (shapes must fit the capacity and
+ * Synchronises.  lmpo_set_site replaces it (shapes must fit the capacity, half
+ * of it when force_hermitian_every > 0, and
  * match the neighbours' bonds); the caller states where the orthogonality
  * centre is (the library assumes sites < centre left-orthonormal and
  * > centre right-orthonormal). */
@@ -201,6 +206,16 @@ int lmpo_apply_unitary(lmpo_state *s, int32_t i, int32_t j, const double *U);
  * round-off singular values).  Resets the step count (time 0) and the
  * discarded weight.  Synchronises at entry; the gates run asynchronously. */
 int lmpo_init_graph_state(lmpo_state *s, int32_t n_pairs, const int32_t *pairs);
+
+/* rho -> (rho + rho^+)/2 now (Sec. 6, force_rho_hermitian_step).  In the
+ * Hermitian Pauli basis rho^+ has the conjugate coefficients, so the sum is
+ * the direct sum of the MPS and its complex conjugate (bond dims doubled,
+ * factor 1/2 on site 0); it is made left-orthonormal by exact QR from the
+ * left and compressed by the truncated two-site SVD of every bond from the
+ * right (chi_max, cutoff; the discarded weight counts).  The centre ends on
+ * site 0; the trace is not renormalised.  Requires a state created with
+ * force_hermitian_every > 0 (LMPO_EUNSUPPORTED otherwise).  Asynchronous. */
+int lmpo_hermitize(lmpo_state *s);
 
 /* Singular values of the last two-site block, sorted descending (n_out
  * entries at most), and its kept rank; synchronises. */

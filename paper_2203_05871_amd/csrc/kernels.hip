@@ -209,4 +209,48 @@ void launch_scale_site(hipStream_t s, double2 *const *sites, const int *dims, in
   check_launch();
 }
 
+// ---------------------------------------------------------------------------
+// Hermitian part rho -> (rho + rho^+) / 2 (the solver's force_rho_hermitian_step,
+// Sec. 6).  The basis operators P_a are Hermitian, so rho^+ has the complex
+// conjugate coefficients; the sum is the MPS whose site k is the direct sum of
+// A_k and conj(A_k) (bond dims doubled: block diagonal inside the chain, a row
+// of two blocks on the first site, a column on the last), the first site
+// carrying the factor 1/2.  src is a copy of site k taken before the call;
+// dims are the bond dims before doubling.
+// ---------------------------------------------------------------------------
+__global__ void hermitian_sum_site_kernel(const double2 *__restrict__ src, double2 *__restrict__ dst,
+                                          const int *dims, int N, int k) {
+  int cl, cr;
+  site_dims(dims, N, k, cl, cr);
+  const bool first = (k == 0), last = (k == N - 1);
+  const int nl = first ? 1 : 2 * cl, nr = last ? 1 : 2 * cr;
+  const double f = first ? 0.5 : 1.0;
+  const size_t n = (size_t)nl * 4 * nr;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e % nr), a = (int)((e / nr) % 4), l = (int)(e / ((size_t)4 * nr));
+    const int hl = first ? 0 : l / cl, hr = last ? 0 : r / cr;  // copy (0: rho, 1: rho^+) of each index
+    double2 out = make_double2(0.0, 0.0);
+    if (first || last || hl == hr) {
+      const int copy = first ? hr : hl;
+      const double2 v = src[(size_t)(l - hl * cl) * 4 * cr + (size_t)a * cr + (r - hr * cr)];
+      out = make_double2(f * v.x, copy ? -f * v.y : f * v.y);
+    }
+    dst[e] = out;
+  }
+}
+
+__global__ void double_dims_kernel(int *dims, int n) {
+  for (int b = threadIdx.x; b < n; b += blockDim.x) dims[b] *= 2;
+}
+
+void launch_hermitian_sum_site(hipStream_t s, const double2 *src, double2 *dst, const int *dims, int N, int k) {
+  hipLaunchKernelGGL(hermitian_sum_site_kernel, dim3(256), dim3(256), 0, s, src, dst, dims, N, k);
+  check_launch();
+}
+
+void launch_double_dims(hipStream_t s, int *dims, int n) {
+  hipLaunchKernelGGL(double_dims_kernel, dim3(1), dim3(64), 0, s, dims, n);
+  check_launch();
+}
+
 }  // namespace lmpo

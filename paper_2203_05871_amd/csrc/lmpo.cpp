@@ -187,6 +187,8 @@ struct lmpo_state {
   bool chain = true;            // bond list is the open chain (b, b+1) in order
   double2 *d_swap = nullptr;    // exchange of two sites (Pauli basis)
   double2 *d_user = nullptr;    // caller-supplied two-site superoperator
+  double2 *d_ident = nullptr;   // identity (compression sweep of the Hermitian part)
+  bool herm_room = false;       // bond capacities doubled for the Hermitian part
 };
 
 namespace {
@@ -236,12 +238,18 @@ int validate(const lmpo_model *m, const lmpo_options *o) {
   }
   for (int s = 0; s < m->n_qubits; ++s)
     if (deg[s] == 0) return fail(LMPO_EINVAL, "every qubit must belong to a bond (its on-site terms ride on them)");
+  if (o->force_hermitian_every < 0) return fail(LMPO_EINVAL, "force_hermitian_every must be >= 0");
+  if (o->force_hermitian_every > 0 && o->chi_max > kMaxDim / 8)
+    return fail(LMPO_EUNSUPPORTED, "force_hermitian_every needs chi_max <= 256 (the doubled bonds reach 512)");
   if (o->trotter_order == 3 && !is_chain(m))
     return fail(LMPO_EUNSUPPORTED, "trotter_order 3 needs the open chain (two commuting layer operators)");
   return LMPO_OK;
 }
 
-Sizes compute_sizes(int N, int chi_max) {
+// Bond capacities min(chi_max, 4^(b+1), 4^(N-1-b)), times `mult` (2 when the
+// Hermitian part is taken: the direct sum of rho and rho^+ doubles every bond
+// until it is compressed again).
+Sizes compute_sizes(int N, int chi_max, int mult) {
   Sizes z;
   z.cap.resize(N - 1);
   for (int b = 0; b < N - 1; ++b) {
@@ -250,7 +258,7 @@ Sizes compute_sizes(int N, int chi_max) {
     c = std::min(c, p);
     p = 1;
     for (int q = 0; q < N - 1 - b && p < c; ++q) p *= 4;
-    c = std::min(c, p);
+    c = std::min(c, p) * mult;
     z.cap[b] = (int)c;
     z.cap_max = std::max(z.cap_max, (int)c);
   }
@@ -287,6 +295,7 @@ size_t layout(lmpo_state *S, const Sizes &z, int N, int nb, char *base, size_t s
   S->d_gates = a.take<double2>((size_t)nb * kGateSlots * 256);
   S->d_swap = a.take<double2>(256);
   S->d_user = a.take<double2>(256);
+  S->d_ident = a.take<double2>(256);
   S->X = a.take<double2>(z.x_elems);
   S->V = a.take<double2>(z.v_elems);
   int nbp = (z.max_cols + JB - 1) / JB;
@@ -565,18 +574,53 @@ int pair_args(const lmpo_state *S, int i, int j) {
   return LMPO_OK;
 }
 
+int renormalize(lmpo_state *S) {
+  launch_trace(S->stream, S->d_sites, S->d_dims, S->N, S->tr);
+  launch_scale_site(S->stream, S->d_sites, S->d_dims, S->N, S->centre, S->tr);
+  return LMPO_OK;
+}
+
+// rho -> (rho + rho^+) / 2 (force_rho_hermitian_step, Sec. 6): the direct
+// sum of the MPS and its conjugate (bonds doubled, first site halved), an
+// exact QR sweep from the left (bonds fall to their exact rank bound), then a
+// right-to-left sweep of identity gates, i.e. the truncated two-site SVD of
+// every bond with the state's chi_max and cutoff.  The centre ends on site 0.
+int hermitize(lmpo_state *S) {
+  const int N = S->N;
+  for (int k = 0; k < N; ++k) {
+    HIP_TRY(hipMemcpyAsync(S->T, S->site[k], S->site_elems[k] * sizeof(double2), hipMemcpyDeviceToDevice,
+                           S->stream));
+    launch_hermitian_sum_site(S->stream, S->T, S->site[k], S->d_dims, N, k);
+    HIP_TRY(hipGetLastError());
+  }
+  launch_double_dims(S->stream, S->d_dims, N - 1);
+  HIP_TRY(hipGetLastError());
+  for (int b = 0; b < N - 1; ++b) S->dims_est[b] = std::min(S->cap[b], 2 * S->dims_est[b]);  // launch sizing
+  S->centre = 0;
+  int rc = move_centre(S, N - 1);
+  for (int k = N - 2; k >= 0 && !rc; --k) rc = apply_gate_dev(S, k, S->d_ident, 0);
+  for (int b = 0; b < N - 1; ++b) S->dims_est[b] = std::min(S->dims_est[b], S->opt.chi_max);
+  return rc;
+}
+
+// End of step `step`: the Hermitian part every force_hermitian_every steps,
+// then the trace forced to one.
+int finish_step(lmpo_state *S, long long step) {
+  const int every = S->opt.force_hermitian_every;
+  if (every > 0 && (step + 1) % every == 0) {
+    int rc = hermitize(S);
+    if (rc) return rc;
+  }
+  if (S->opt.force_trace) return renormalize(S);
+  return LMPO_OK;
+}
+
 int check_err(lmpo_state *S) {
   int e = 0;
   int rc = read_int(S, S->err, &e);
   if (rc) return rc;
   if (e & 2) return fail(LMPO_EHIP, "a grid barrier wait exceeded its spin limit (workgroups not co-resident)");
   if (e) return fail(LMPO_ENUMERIC, "non-finite or zero singular values / trace encountered");
-  return LMPO_OK;
-}
-
-int renormalize(lmpo_state *S) {
-  launch_trace(S->stream, S->d_sites, S->d_dims, S->N, S->tr);
-  launch_scale_site(S->stream, S->d_sites, S->d_dims, S->N, S->centre, S->tr);
   return LMPO_OK;
 }
 
@@ -594,8 +638,7 @@ int one_step(lmpo_state *S, long long step) {
         if (rc) return rc;
       }
     }
-    if (S->opt.force_trace) return renormalize(S);
-    return LMPO_OK;
+    return finish_step(S, step);
   }
   const std::vector<TrotterLayer> &layers = trotter_layers(S->opt.trotter_order);
   for (int j = 0; j < (int)layers.size(); ++j) {
@@ -610,8 +653,7 @@ int one_step(lmpo_state *S, long long step) {
       if (rc) return rc;
     }
   }
-  if (S->opt.force_trace) return renormalize(S);
-  return LMPO_OK;
+  return finish_step(S, step);
 }
 
 }  // namespace
@@ -622,7 +664,7 @@ const char *lmpo_last_error(void) { return g_err.c_str(); }
 
 size_t lmpo_arena_bytes(const lmpo_model *model, const lmpo_options *opt) {
   if (validate(model, opt) != LMPO_OK) return 0;
-  Sizes z = compute_sizes(model->n_qubits, opt->chi_max);
+  Sizes z = compute_sizes(model->n_qubits, opt->chi_max, opt->force_hermitian_every > 0 ? 2 : 1);
   lmpo_state tmp;
   return layout(&tmp, z, model->n_qubits, model->n_bonds, nullptr, 0) + 256;
 }
@@ -637,12 +679,13 @@ int lmpo_create(const lmpo_model *model, const lmpo_options *opt, const char *in
   if ((rc = parse_init(init_pauli, model->n_qubits, init))) return rc;
   if (!device_arena) return fail(LMPO_EINVAL, "device_arena is null");
   if (reinterpret_cast<uintptr_t>(device_arena) % 256) return fail(LMPO_EINVAL, "device_arena must be 256-byte aligned");
-  Sizes z = compute_sizes(model->n_qubits, opt->chi_max);
+  Sizes z = compute_sizes(model->n_qubits, opt->chi_max, opt->force_hermitian_every > 0 ? 2 : 1);
   if (z.max_dim > kMaxDim) return fail(LMPO_EUNSUPPORTED, "block dimension above 2048");
   lmpo_state *S = new lmpo_state();
   S->m = copy_model(model);
   S->opt = *opt;
   S->chain = is_chain(model);
+  S->herm_room = opt->force_hermitian_every > 0;
   S->N = model->n_qubits;
   S->stream = reinterpret_cast<hipStream_t>(hip_stream);
   size_t need = layout(S, z, S->N, S->m.nb, reinterpret_cast<char *>(device_arena), arena_bytes);
@@ -678,9 +721,12 @@ int lmpo_create(const lmpo_model *model, const lmpo_options *opt, const char *in
   e = hipMemcpyAsync(S->d_gates, S->gates_host.data(), S->gates_host.size() * sizeof(double2), hipMemcpyHostToDevice,
                      S->stream);
   if (e != hipSuccess) return cleanup(fail(LMPO_EHIP, std::string("gate upload: ") + hipGetErrorString(e)));
-  std::vector<std::complex<double>> swap(256);
+  std::vector<std::complex<double>> swap(256), ident(256, 0.0);
   swap_pauli(swap.data());
+  for (int q = 0; q < 16; ++q) ident[17 * q] = 1.0;
   e = hipMemcpyAsync(S->d_swap, swap.data(), 256 * sizeof(double2), hipMemcpyHostToDevice, S->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(S->d_ident, ident.data(), 256 * sizeof(double2), hipMemcpyHostToDevice, S->stream);
   if (e != hipSuccess) return cleanup(fail(LMPO_EHIP, std::string("swap upload: ") + hipGetErrorString(e)));
   e = hipMemcpyAsync(S->d_sites, S->site.data(), S->N * sizeof(double2 *), hipMemcpyHostToDevice, S->stream);
   if (e != hipSuccess) return cleanup(fail(LMPO_EHIP, std::string("site table upload: ") + hipGetErrorString(e)));
@@ -851,7 +897,9 @@ int lmpo_get_site(lmpo_state *S, int32_t k, int32_t dims[2], double *out) {
 int lmpo_set_site(lmpo_state *S, int32_t k, int32_t chl, int32_t chr, const double *data) {
   if (!S || !data) return fail(LMPO_EINVAL, "null argument");
   if (k < 0 || k >= S->N) return fail(LMPO_EINVAL, "site index out of range");
-  const int capl = capL(S, k), capr = capR(S, k);
+  // with room reserved for the Hermitian part, half the capacity is usable
+  const int div = S->herm_room ? 2 : 1;
+  const int capl = k == 0 ? 1 : capL(S, k) / div, capr = k == S->N - 1 ? 1 : capR(S, k) / div;
   if (chl < 1 || chr < 1 || chl > capl || chr > capr) return fail(LMPO_EINVAL, "site shape exceeds the bond capacity");
   int rc = sync_dims(S);
   if (rc) return rc;
@@ -941,6 +989,13 @@ int lmpo_init_graph_state(lmpo_state *S, int32_t n_pairs, const int32_t *pairs) 
     if ((rc = apply_pair(S, std::min(a, b), std::max(a, b), S->d_user, true))) return rc;
   }
   return LMPO_OK;
+}
+
+int lmpo_hermitize(lmpo_state *S) {
+  if (!S) return fail(LMPO_EINVAL, "state is null");
+  if (!S->herm_room)
+    return fail(LMPO_EUNSUPPORTED, "create the state with force_hermitian_every > 0 to reserve the doubled bonds");
+  return hermitize(S);
 }
 
 int lmpo_last_spectrum(lmpo_state *S, int32_t n_out, double *sv, int32_t *n_sv, int32_t *kept) {
@@ -1181,6 +1236,8 @@ int batch_check_chains(lmpo_state *const *chains, int n) {
       return fail(LMPO_EINVAL, "all chains of a batch must use the same Trotter order");
     if (!chains[c]->chain)
       return fail(LMPO_EUNSUPPORTED, "the batched form runs open chains only (bonds (b, b+1) in order)");
+    if (chains[c]->opt.force_hermitian_every > 0)
+      return fail(LMPO_EUNSUPPORTED, "the batched form does not take the Hermitian part (force_hermitian_every)");
     for (int d = 0; d < c; ++d)
       if (chains[d] == chains[c]) return fail(LMPO_EINVAL, "a chain appears twice in the batch");
   }

@@ -97,5 +97,7 @@ void launch_measure(hipStream_t s, double2 *const *sites, const int *dims, int N
 void launch_norm2_site(hipStream_t s, double2 *const *sites, const int *dims, int N, int site, double *out);
 void launch_scale_site(hipStream_t s, double2 *const *sites, const int *dims, int N, int site,
                        const double2 *tr);
+void launch_hermitian_sum_site(hipStream_t s, const double2 *src, double2 *dst, const int *dims, int N, int k);
+void launch_double_dims(hipStream_t s, int *dims, int n);
 
 }  // namespace lmpo

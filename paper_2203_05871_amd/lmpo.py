@@ -51,6 +51,7 @@ class _Options(ctypes.Structure):
         ("cutoff", ctypes.c_double),
         ("precision", ctypes.c_int32),
         ("force_trace", ctypes.c_int32),
+        ("force_hermitian_every", ctypes.c_int32),
     ]
 
 
@@ -63,6 +64,7 @@ EXPORTS = [
     "lmpo_get_centre", "lmpo_get_gate", "lmpo_apply_gate", "lmpo_last_spectrum", "lmpo_svd_stats",
     "lmpo_svd_profile", "lmpo_profile_begin", "lmpo_profile_end", "lmpo_set_workgroups",
     "lmpo_renyi2", "lmpo_osee", "lmpo_apply_superop", "lmpo_apply_unitary", "lmpo_init_graph_state",
+    "lmpo_hermitize",
     "lmpo_batch_arena_bytes", "lmpo_batch_create", "lmpo_batch_evolve_step", "lmpo_batch_sync",
     "lmpo_batch_plan", "lmpo_batch_profile_begin", "lmpo_batch_profile_end", "lmpo_batch_destroy",
     "lmpo_batch_set_autotune", "lmpo_autotune_table",
@@ -112,6 +114,7 @@ def load_library(path: str = LIB_PATH):
         "lmpo_apply_superop": (ctypes.c_int, [P, i32, i32, pdbl]),
         "lmpo_apply_unitary": (ctypes.c_int, [P, i32, i32, pdbl]),
         "lmpo_init_graph_state": (ctypes.c_int, [P, i32, pi32]),
+        "lmpo_hermitize": (ctypes.c_int, [P]),
         "lmpo_batch_arena_bytes": (ctypes.c_size_t, [ctypes.POINTER(P), i32]),
         "lmpo_batch_create": (ctypes.c_int, [ctypes.POINTER(P), i32, P, ctypes.c_size_t, ctypes.POINTER(P)]),
         "lmpo_batch_evolve_step": (ctypes.c_int, [P, i32]),
@@ -158,15 +161,16 @@ class _ModelArrays:
                                                           ("J", "Jz", "hx", "hy", "hz", "g0", "g1", "g2")])
 
 
-def _options(tau, chi_max, cutoff, precision, force_trace, order=2):
+def _options(tau, chi_max, cutoff, precision, force_trace, order=2, hermitian_every=0):
     prec = {"fp64": LMPO_FP64, "fp32": LMPO_FP32_CONTRACT}.get(precision, precision)
-    return _Options(float(tau), int(order), int(chi_max), float(cutoff), int(prec), int(bool(force_trace)))
+    return _Options(float(tau), int(order), int(chi_max), float(cutoff), int(prec), int(bool(force_trace)),
+                    int(hermitian_every))
 
 
-def arena_bytes(model, tau, chi_max, cutoff=0.0, precision="fp64", force_trace=True, order=2):
+def arena_bytes(model, tau, chi_max, cutoff=0.0, precision="fp64", force_trace=True, order=2, hermitian_every=0):
     lib = load_library()
     m = _ModelArrays(model)
-    o = _options(tau, chi_max, cutoff, precision, force_trace, order)
+    o = _options(tau, chi_max, cutoff, precision, force_trace, order, hermitian_every)
     n = lib.lmpo_arena_bytes(ctypes.byref(m.struct), ctypes.byref(o))
     if n == 0:
         raise LmpoError(-1, lib.lmpo_last_error().decode())
@@ -186,13 +190,13 @@ class Chain:
     """One qubit chain's vectorised density matrix on the GPU."""
 
     def __init__(self, model, tau, chi_max, cutoff=0.0, precision="fp64", init="+z", force_trace=True,
-                 order=2, device="cuda:0", stream=None):
+                 order=2, device="cuda:0", stream=None, hermitian_every=0):
         import torch
 
         lib = load_library()
         self.N = int(model["N"])
         self._m = _ModelArrays(model)
-        self._o = _options(tau, chi_max, cutoff, precision, force_trace, order)
+        self._o = _options(tau, chi_max, cutoff, precision, force_trace, order, hermitian_every)
         n = lib.lmpo_arena_bytes(ctypes.byref(self._m.struct), ctypes.byref(self._o))
         if n == 0:
             raise LmpoError(-1, lib.lmpo_last_error().decode())
@@ -231,6 +235,10 @@ class Chain:
         U = np.asarray(U, dtype=np.complex128).reshape(4, 4)
         buf = np.ascontiguousarray(np.stack([U.real, U.imag], axis=-1).reshape(-1))
         _check(self._lib.lmpo_apply_unitary(self._h, int(i), int(j), _dptr(buf)))
+
+    def hermitize(self):
+        """rho -> (rho + rho^+)/2 now (needs hermitian_every > 0 at creation)."""
+        _check(self._lib.lmpo_hermitize(self._h))
 
     def init_graph_state(self, pairs):
         """Restart from the graph state of Eq. (graph_state) on the given pairs."""

@@ -130,3 +130,65 @@ def test_osee_wide_centre_site(lib):
         assert abs(g - r) < 1e-10, (bond, g, r)
     assert ch.bond_dims() == ref.bond_dims()
     ch.close()
+
+
+def test_hermitize_non_hermitian_state(lib):
+    """A non-Hermitian-preserving superoperator makes rho non-Hermitian; the
+    Hermitian part then matches the oracle's, and observables become real."""
+    m = workloads.jittered_chain(7, 3)
+    ch = lib.Chain(m, 0.05, 32, 1e-12, "fp64", "+x", hermitian_every=1000)
+    ref = tebd.MPS.product("+x", 7)
+    ch.evolve(3)
+    tebd.evolve(ref, m, 0.05, 3, 32, 1e-12)
+    rng = np.random.default_rng(4)
+    Gc = np.eye(16) + 0.2 * (rng.standard_normal((16, 16)) + 1j * rng.standard_normal((16, 16)))
+    ch.apply_superop(1, 3, tebd.gate_to_pauli(Gc))
+    ref.apply_pair_gate(1, 3, Gc, 32, 1e-12, True)
+    assert np.abs(obs(ch, 7).imag).max() > 1e-3  # no longer Hermitian
+    ch.hermitize()
+    ref.hermitize(32, 1e-12)
+    assert ch.bond_dims() == ref.bond_dims()
+    assert ch.centre() == 0
+    o = obs(ch, 7)
+    assert np.abs(o - oracle_obs(ref, 7)).max() < 1e-10
+    assert np.abs(o.imag).max() < 1e-12
+    tr = ref.trace()
+    assert abs(ch.trace() - tr) < 1e-12 * abs(tr) and abs(tr.imag) < 1e-14
+    ch.close()
+
+
+@pytest.mark.parametrize("ladder", [False, True])
+def test_evolution_with_hermitian_every(lib, ladder):
+    """The Hermitian part every 2nd step inside the evolution (chain and
+    ladder, truncating), FP64 against the oracle, FP32 form within 1e-5."""
+    m = workloads.ladder_model(4) if ladder else workloads.jittered_chain(9, 1)
+    N = m["N"]
+    ch = lib.Chain(m, 0.05, 16, 1e-12, "fp64", "+x", hermitian_every=2)
+    c32 = lib.Chain(m, 0.05, 16, 1e-12, "fp32", "+x", hermitian_every=2)
+    ref = tebd.MPS.product("+x", N)
+    ch.evolve(5)
+    c32.evolve(5)
+    tebd.evolve(ref, m, 0.05, 5, 16, 1e-12, hermitian_every=2)
+    assert ch.bond_dims() == ref.bond_dims()
+    assert max(ch.bond_dims()) == 16
+    o = obs(ch, N)
+    assert np.abs(o - oracle_obs(ref, N)).max() < 1e-10
+    assert np.abs(obs(c32, N) - o).max() < 1e-5
+    ch.close()
+    c32.close()
+
+
+def test_hermitize_errors(lib):
+    m = workloads.jittered_chain(5, 0)
+    plain = lib.Chain(m, 0.05, 8, 0.0, "fp64", "+z")
+    with pytest.raises(lib.LmpoError, match="force_hermitian_every"):
+        plain.hermitize()
+    roomy = lib.Chain(m, 0.05, 8, 0.0, "fp64", "+z", hermitian_every=3)
+    with pytest.raises(lib.LmpoError, match="Hermitian"):
+        lib.Batch([roomy])
+    with pytest.raises(lib.LmpoError, match="capacity"):
+        roomy.set_site(2, np.zeros((16, 4, 8)))  # bond capacity 16 reserved, 8 usable
+    with pytest.raises(lib.LmpoError, match="chi_max <= 256"):
+        lib.Chain(m, 0.05, 300, 0.0, "fp64", "+z", hermitian_every=1)
+    plain.close()
+    roomy.close()
