@@ -99,17 +99,12 @@ struct Barrier {
   }
 };
 
-// 1/sqrt(x) and 1/x from the hardware estimates plus Newton steps (to ~1 ulp;
-// x > 0 normal).
+// 1/sqrt(x) from the hardware estimate plus Newton steps (to ~1 ulp; x > 0
+// normal).
 __device__ __forceinline__ double rsq_nr(double x) {
   double y = __builtin_amdgcn_rsq(x);
   y = y * fma(-0.5 * x * y, y, 1.5);
   return y * fma(-0.5 * x * y, y, 1.5);
-}
-__device__ __forceinline__ double rcp_nr(double x) {
-  double y = __builtin_amdgcn_rcp(x);
-  y = y * fma(-x, y, 2.0);
-  return y * fma(-x, y, 2.0);
 }
 
 // LDS ordering among the lanes of one wavefront: its LDS operations execute in
@@ -309,7 +304,9 @@ __device__ bool pair_work(SharedPair &s, double2 *__restrict__ X, int ldx, int R
   // rotation of pair (p, q), p < q, that zeroes g_pq: columns
   // x_p' = cs x_p + s x_q, x_q' = cs x_q - conj(s) x_p with cs real,
   // s = tau cs, cs = 1 / sqrt(1 + |tau|^2) and the small root
-  // tau = 2 conj(g_pq) / (d + sgn(d) sqrt(d^2 + 4 |g_pq|^2)), d = g_pp - g_qq.
+  // tau = 2 conj(g_pq) / D, D = d + sgn(d) sqrt(d^2 + 4 |g_pq|^2), d = g_pp - g_qq;
+  // with q = 1 / sqrt(D^2 + 4 |g_pq|^2) that is cs = |D| q, s = 2 sgn(d) conj(g_pq) q
+  // (two reciprocal square roots, no division).
   // Returns false (identity) when g_pq is below the threshold.
   auto rotation = [&](int p, int q, double &cs, double2 &sc) {
     const double app = s.G[cur][p][p].x, aqq = s.G[cur][q][q].x;
@@ -323,11 +320,11 @@ __device__ bool pair_work(SharedPair &s, double2 *__restrict__ X, int ldx, int R
     const double d = app - aqq;
     const double r2 = fma(d, d, 4.0 * mc2);
     const double r = r2 * rsq_nr(r2);
-    const double den = d + copysign(r, d);
-    const double f = 2.0 * rcp_nr(den);
-    const double2 tau = make_double2(f * c.x, -f * c.y);
-    cs = rsq_nr(fma(tau.x, tau.x, fma(tau.y, tau.y, 1.0)));
-    sc = make_double2(tau.x * cs, tau.y * cs);
+    const double D = d + copysign(r, d);
+    const double iq = rsq_nr(fma(D, D, 4.0 * mc2));
+    cs = fabs(D) * iq;
+    const double f = copysign(2.0 * iq, d);
+    sc = make_double2(f * c.x, -f * c.y);
     return true;
   };
   for (int sweep = 0; sweep < kInnerSweeps; ++sweep) {

@@ -212,3 +212,30 @@ def test_error_paths(Chain):
     with pytest.raises(LmpoError, match="X, Y, Z"):
         ch.measure_1q([0], "Q")
     ch.close()
+
+
+@pytest.mark.timeout(400)
+def test_c3_full_run_parity(Chain):
+    """The 30-site benchmark chain (chi_max = 256, cutoff 1e-10, tau = 0.05,
+    +x, 50 steps) in the launch configuration the benchmark times: after every
+    step of the run the bond dims, and at the end every <sz_i> and
+    <sz_i sz_j> (i < j), FP64 against the oracle; the FP32-contraction form
+    within 1e-5 of FP64."""
+    m, run = workloads.c3()
+    N = m["N"]
+    ch = Chain(m, run["tau"], run["chi_max"], run["cutoff"], "fp64", run["init"])
+    c32 = Chain(m, run["tau"], run["chi_max"], run["cutoff"], "fp32", run["init"])
+    ref = tebd.MPS.product(run["init"], N)
+    for n in range(run["steps"]):
+        ch.evolve(1)
+        tebd.evolve(ref, m, run["tau"], 1, run["chi_max"], run["cutoff"], first_step=n)
+        assert ch.bond_dims() == ref.bond_dims(), n
+    c32.evolve(run["steps"])
+    z1, z2 = ch.zz_observables()
+    r1, r2 = tebd.zz_observables(ref)
+    assert max(np.abs(z1 - r1).max(), np.abs(z2 - r2).max()) < 1e-10
+    f1, f2 = c32.zz_observables()
+    assert max(np.abs(f1 - z1).max(), np.abs(f2 - z2).max()) < 1e-5
+    assert abs(ch.trace() - 1.0) < 1e-12
+    ch.close()
+    c32.close()
