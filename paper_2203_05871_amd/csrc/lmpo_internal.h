@@ -87,7 +87,7 @@ hipError_t launch_batch_layer(hipStream_t s, const BatchChain *d_chains, const i
                               const int *d_block_rank, const int *d_group_size, int total_blocks, unsigned *bar_base,
                               size_t bar_words, int local_step, int j, int parity, int slot, int last_layer);
 constexpr size_t kBarBlock = 8 * 32 + 64;   // one grid barrier: 8 group counters, top, flag
-constexpr size_t kBarWords = 2 * kBarBlock;  // a problem's full-group and pair-group barriers
+constexpr size_t kBarWords = 2 * kBarBlock;  // a problem's grid barrier and its Jacobi block versions
 
 void launch_trace(hipStream_t s, double2 *const *sites, const int *dims, int N, double2 *out);
 void launch_env_all(hipStream_t s, double2 *const *sites, const int *dims, int N, int cap,

@@ -116,6 +116,39 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Dataflow order between Jacobi rounds: every column block belongs to exactly
+// one pair per round, so a pair of round r needs only its two blocks as the
+// pairs of round r - 1 left them.  ver[b] counts the rounds that have
+// finished with block b (monotonic within a launch); a pair waits until both
+// of its blocks reach `need`, works, and publishes need + 1 for both.  The
+// fences are those of the grid barrier (agent-scope release before the
+// publishing store, acquire after the wait); the wait is bounded like the
+// barrier's and skipped once an error has been flagged.
+__device__ __forceinline__ void wait_blocks(unsigned *va, unsigned *vb, unsigned need, int *err) {
+  if (threadIdx.x == 0) {
+    unsigned spins = 0;
+    while (__hip_atomic_load(va, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need ||
+           __hip_atomic_load(vb, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+      if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 2) break;
+      __builtin_amdgcn_s_sleep(1);
+      if (++spins > (1u << 22)) {
+        atomicOr(err, 2);
+        break;
+      }
+    }
+    __threadfence();
+  }
+  __syncthreads();
+}
+// Call after a __syncthreads() that follows the block's writes.
+__device__ __forceinline__ void publish_blocks(unsigned *va, unsigned *vb, unsigned v) {
+  if (threadIdx.x == 0) {
+    __threadfence();
+    __hip_atomic_store(va, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(vb, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
 __device__ __forceinline__ void pair_blocks(int round, int p, int nbp, int &bi, int &bj) {
   const int m = nbp - 1;
   if (p == 0) {
@@ -844,18 +877,17 @@ __device__ void svd_body(const SvdLaunch &a, Barrier &bar, SharedAll &sh) {
   nbp += nbp & 1;
   if (nbp < 2) nbp = 2;
   const int npairs = nbp / 2;
-  // Workgroups [0, np) do the pair rounds under their own barrier; the others
-  // (nv of them) apply the previous sweep's rotations to V meanwhile, so the V
-  // update leaves the critical path.  The pair barrier's counters are cleared
-  // here (every workgroup has left its previous use behind a full barrier).
+  // Workgroups [0, np) do the pair rounds, ordered block by block (see
+  // wait_blocks); the others (nv of them) apply the previous sweep's rotations
+  // to V meanwhile, so the V update leaves the critical path.  The block
+  // versions live in the second barrier block and are cleared here (every
+  // workgroup has left its previous use behind a full barrier).
   const int np = G < npairs ? G : npairs, nv = G - np;
-  if (rank == 0 && threadIdx.x < 10) {
-    unsigned *pb = a.bar + kBarBlock;
-    pb[threadIdx.x < 8 ? threadIdx.x * 32 : 8 * 32 + (threadIdx.x - 8) * 32] = 0u;
-  }
+  static_assert(kMaxDim / JB + 2 <= (int)kBarBlock, "block versions must fit the barrier block");
+  unsigned *ver = a.bar + kBarBlock;
+  if (rank == 0)
+    for (int b = threadIdx.x; b < nbp; b += NT) ver[b] = 0u;
   bar.sync();
-  Barrier pbar{a.bar + kBarBlock, a.bar + kBarBlock + 8 * 32, a.bar + kBarBlock + 8 * 32 + 32, a.err,
-               (unsigned)np, rank < (unsigned)np ? rank : 0u, 0u};
   const double tol = a.tol_factor * sqrt((double)C) * 2.220446049250313e-16;
   int sweeps = 0, pending = -1;  // pending: active sweep whose V update is outstanding
   const size_t wsw_stride = (size_t)(nbp - 1) * npairs;  // pair slots per sweep
@@ -875,10 +907,13 @@ __device__ void svd_body(const SvdLaunch &a, Barrier &bar, SharedAll &sh) {
     if (rank == 0) order_columns(sh.sel, a.cnorm, C, nbp * JB, cmap);
     bar.sync();
     if ((int)rank < np) {
+      const unsigned base = (unsigned)sweep * (unsigned)(nbp - 1);  // every block's version at the sweep's start
       for (int round = 0; round < nbp - 1; ++round) {
         for (int p = rank; p < npairs; p += np) {
           int bi, bj;
           pair_blocks(round, p, nbp, bi, bj);
+          if (np > 1) wait_blocks(ver + bi, ver + bj, base + round, a.err);
+          lap(2);
           const size_t slot = (size_t)round * npairs + p;
           bool active = pair_work(sh.pair, Y, ldy, C, Wsw + slot * JP * JP, C, bi, bj, tol, cmap,
                                   (a.tprof && rank == 0) ? a.tprof : nullptr);
@@ -887,10 +922,9 @@ __device__ void svd_body(const SvdLaunch &a, Barrier &bar, SharedAll &sh) {
             if (active) atomicAdd(&a.sweep_cnt[sweep], 1);
           }
           __syncthreads();
+          if (np > 1) publish_blocks(ver + bi, ver + bj, base + round + 1);
+          lap(1);
         }
-        lap(1);
-        pbar.sync();
-        lap(2);
       }
     } else if (pending >= 0) {
       update_v(pending, nv, rank - np);
