@@ -283,17 +283,18 @@ int lmpo_batch_evolve_step(lmpo_batch *b, int32_t n_steps);
 int lmpo_batch_sync(lmpo_batch *b);
 
 /* Online autotuner (off by default).  Results do not depend on how the grid
- * is split between chains, so with autotuning on, the batch tries one step
- * under each candidate cap on the workgroups per chain (1, 2, 4, 8, 16, none)
- * for every (largest block size bucket, precision) it meets, timed with HIP
- * events (those steps synchronise), and then keeps the fastest.  The table is
+ * is split between chains, so with autotuning on, the batch times two steps
+ * under each candidate cap on the workgroups per chain (1, 2, 4, 8, 16, none),
+ * in palindromic order so that the growth of the steps' cost cancels, for
+ * every (largest block size bucket, precision) it meets, with HIP events
+ * (those steps synchronise), and then keeps the fastest.  The table is
  * process-wide per device, so later batches reuse it; a batch with tuning off
  * still uses entries that exist. */
 int lmpo_batch_set_autotune(lmpo_batch *b, int32_t enable);
 
 /* The tuned entries of the current device: log2 of the block column bucket,
  * precision bit mask (1 << LMPO_FP64 | 1 << LMPO_FP32_CONTRACT), chosen cap
- * (0 = none) and its step time in ms; at most max_entries written, the count
+ * (0 = none) and its mean step time in ms; at most max_entries written, the count
  * in *n_entries. */
 int lmpo_autotune_table(int32_t max_entries, int32_t *log2_bucket, int32_t *precisions, int32_t *cap,
                         double *best_ms, int32_t *n_entries);

@@ -1155,15 +1155,20 @@ double svd_cost(int R, int C, int G, const CostModel &m) {
 namespace {
 // Online autotuner of the batched form.  Results do not depend on how the
 // grid is split, so the batch can try plans during real steps: for each
-// (largest block bucket, precision) it runs one step under each candidate cap
-// on the workgroups per chain, times it with HIP events and keeps the fastest.
-// The table lives for the process (one per device), so later batches reuse it.
+// (largest block bucket, precision) it runs real steps under each candidate
+// cap on the workgroups per chain, times them with HIP events and keeps the
+// fastest.  Each candidate is timed twice, in palindromic order (1, 2, ..., 0,
+// 0, ..., 2, 1), and ranked by the sum: steps get dearer as the bond dims
+// grow, and the mirrored order cancels that drift to first order.  The table
+// lives for the process (one per device), so later batches reuse it.
 constexpr int kTuneCaps[] = {1, 2, 4, 8, 16, 0};  // 0: the cost model's choice, uncapped
 constexpr int kTuneN = sizeof(kTuneCaps) / sizeof(kTuneCaps[0]);
+constexpr int kTuneTrials = 2 * kTuneN;
+int tune_candidate(int trial) { return trial < kTuneN ? trial : kTuneTrials - 1 - trial; }
 struct TuneEntry {
-  double ms[kTuneN] = {};
-  int next = 0;   // next candidate to time
-  int best = -1;  // index into kTuneCaps once all are timed
+  double ms[kTuneN] = {};  // summed over the candidate's two trials
+  int next = 0;            // next trial (0 .. kTuneTrials - 1)
+  int best = -1;           // index into kTuneCaps once all are timed
 };
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int>, TuneEntry> g_tune;  // (device, log2 bucket, precision)
@@ -1510,7 +1515,7 @@ int lmpo_batch_evolve_step(lmpo_batch *B, int32_t n_steps) {
         B->wg_cap = kTuneCaps[it->second.best];
       } else if (B->autotune) {
         trial = g_tune[key].next;
-        B->wg_cap = kTuneCaps[trial];
+        B->wg_cap = kTuneCaps[tune_candidate(trial)];
       } else {
         B->wg_cap = 0;
       }
@@ -1529,9 +1534,9 @@ int lmpo_batch_evolve_step(lmpo_batch *B, int32_t n_steps) {
       std::lock_guard<std::mutex> lock(g_tune_mu);
       TuneEntry &te = g_tune[key];
       if (te.best < 0 && te.next == trial) {
-        te.ms[trial] = ms;
+        te.ms[tune_candidate(trial)] += ms;
         te.next = trial + 1;
-        if (te.next == kTuneN) te.best = (int)(std::min_element(te.ms, te.ms + kTuneN) - te.ms);
+        if (te.next == kTuneTrials) te.best = (int)(std::min_element(te.ms, te.ms + kTuneN) - te.ms);
       }
     }
     HIP_TRY(B->ring.after(B->steps_done, B->d_dims, B->stream));
@@ -1579,7 +1584,7 @@ int lmpo_autotune_table(int32_t max_entries, int32_t *log2_bucket, int32_t *prec
       log2_bucket[n] = std::get<1>(kv.first);
       precisions[n] = std::get<2>(kv.first);
       cap[n] = kTuneCaps[kv.second.best];
-      best_ms[n] = kv.second.ms[kv.second.best];
+      best_ms[n] = 0.5 * kv.second.ms[kv.second.best];
     }
     ++n;
   }

@@ -202,7 +202,7 @@ def test_batch_autotune_keeps_results(lib):
     the same bits as without tuning, and the tuned entries are recorded."""
     models = uneven_models()
     # chi_max = 8 saturates within a few steps, so the block-size bucket settles
-    # and its six candidate steps complete within the run
+    # and its twelve trial steps (two per candidate) complete within the run
     a = [lib.Chain(m, 0.05, 8, 1e-12, "fp64", "+x") for m in models]
     r = [lib.Chain(m, 0.05, 8, 1e-12, "fp64", "+x") for m in models]
     ba = lib.Batch(a)
