@@ -101,12 +101,12 @@ const std::vector<TrotterLayer> &trotter_layers(int order) {
 }
 }  // namespace
 
-// Bond-dimension mirror for sizing launches.  After each step the device bond
-// dims are copied into one of kRing pinned slots; before enqueuing step s the
-// host waits for the copy of step s - kLag, so the sizes it plans with are at
-// most kLag steps old while the GPU still has kLag steps of work queued.
-// (Without the wait the host would run far ahead and plan every step with the
-// dims of the first one.)  Sizes only affect speed, never results.
+// Bond-dimension mirror for the batched form's planner.  After each step the
+// device bond dims are copied into one of kRing pinned slots; before enqueuing
+// step s the host waits for the copy of step s - kLag, so the plan (how many
+// workgroups each chain gets) is made with dims at most kLag steps old while
+// the GPU still has kLag steps of work queued.  Plans only affect speed, never
+// results.
 struct DimsRing {
   static constexpr int kRing = 3, kLag = 2;
   int n = 0;
@@ -175,8 +175,6 @@ struct lmpo_state {
   bool ev_overflow = false;
   int grid = 1;                 // largest co-resident grid of the persistent SVD
   int wg_cap = 0;               // caller's cap on workgroups per SVD launch (0: none)
-  DimsRing ring;                // asynchronous copies of the bond dims (launch sizing only)
-  std::vector<int> dims_est;    // bond dims as of a step at most two steps back
   ~lmpo_state() {
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
   }
@@ -427,28 +425,20 @@ SvdLaunch svd_args(lmpo_state *S, int mode, int k, int asc) {
   return L;
 }
 
-// Workgroups for one persistent SVD of an R x C block: one per Jacobi pair of
-// a round, no more (grid barriers get slower with every extra workgroup).  Sizes are estimates
-// (bond dims of the last completed step, plus growth margin); they only affect
-// speed, never results.
+// Workgroups launched for one persistent SVD whose problem has at most C
+// columns (from the bond capacities, so nothing waits for the device's dims):
+// svd_workgroups(C), capped by the caller's limit and the co-resident grid.
+// The kernel trims the grid to what the actual dims need (grid barriers get
+// slower with every extra workgroup); the count only affects speed, never
+// results.
 int grid_for(const lmpo_state *S, int R, int C) {
   (void)R;
-  int nbp = (C + JB - 1) / JB;
-  nbp += nbp & 1;
-  const int npairs = std::max(1, nbp / 2);
   const int cap = S->wg_cap > 0 ? std::min(S->wg_cap, S->grid) : S->grid;
-  // from 4 pairs up, as many workgroups again update V behind the rounds
-  const int want = npairs >= 4 ? 2 * npairs : npairs;
-  return std::max(1, std::min(want, cap));
+  return std::max(1, std::min(svd_workgroups(C), cap));
 }
 int est(const lmpo_state *S, int bond) {
   if (bond < 0 || bond >= S->N - 1) return 1;
-  return std::min(S->cap[bond], S->dims_est[bond] + 8);
-}
-
-int refresh_estimates(lmpo_state *S) {
-  HIP_TRY(S->ring.before(S->step_index, S->dims_est.data()));
-  return LMPO_OK;
+  return S->cap[bond];
 }
 
 int launch_svd(lmpo_state *S, const SvdLaunch &L, int grid) {
@@ -595,11 +585,9 @@ int hermitize(lmpo_state *S) {
   }
   launch_double_dims(S->stream, S->d_dims, N - 1);
   HIP_TRY(hipGetLastError());
-  for (int b = 0; b < N - 1; ++b) S->dims_est[b] = std::min(S->cap[b], 2 * S->dims_est[b]);  // launch sizing
   S->centre = 0;
   int rc = move_centre(S, N - 1);
   for (int k = N - 2; k >= 0 && !rc; --k) rc = apply_gate_dev(S, k, S->d_ident, 0);
-  for (int b = 0; b < N - 1; ++b) S->dims_est[b] = std::min(S->dims_est[b], S->opt.chi_max);
   return rc;
 }
 
@@ -735,9 +723,6 @@ int lmpo_create(const lmpo_model *model, const lmpo_options *opt, const char *in
   if (e != hipSuccess) return cleanup(fail(LMPO_EHIP, std::string("dims upload: ") + hipGetErrorString(e)));
   if ((rc = upload_product(S, init))) return cleanup(rc);
   S->grid = svd_grid_size();
-  S->dims_est.assign(std::max(S->N - 1, 1), 1);
-  e = S->ring.init(S->N - 1);
-  if (e != hipSuccess) return cleanup(fail(LMPO_EHIP, std::string("pinned dims: ") + hipGetErrorString(e)));
   int zero = 0;
   double zd = 0.0;
   e = hipMemsetAsync(S->stats, 0, kStats * sizeof(int), S->stream);
@@ -754,10 +739,8 @@ int lmpo_evolve_step(lmpo_state *S, int32_t n_steps) {
   if (!S) return fail(LMPO_EINVAL, "state is null");
   if (n_steps < 0) return fail(LMPO_EINVAL, "n_steps must be >= 0");
   for (int n = 0; n < n_steps; ++n) {
-    int rc = refresh_estimates(S);
+    int rc = one_step(S, S->step_index);
     if (rc) return rc;
-    if ((rc = one_step(S, S->step_index))) return rc;
-    HIP_TRY(S->ring.after(S->step_index, S->d_dims, S->stream));
     S->step_index++;
   }
   return LMPO_OK;
@@ -970,8 +953,6 @@ int lmpo_init_graph_state(lmpo_state *S, int32_t n_pairs, const int32_t *pairs) 
   if (rc) return rc;
   // a fresh initial condition: time 0, nothing discarded yet
   S->step_index = 0;
-  for (long long &v : S->ring.issued) v = -1;
-  std::fill(S->dims_est.begin(), S->dims_est.end(), 1);
   const double zd = 0.0;
   HIP_TRY(hipMemcpyAsync(S->disc, &zd, sizeof(double), hipMemcpyHostToDevice, S->stream));
   if (n_pairs == 0) {

@@ -34,6 +34,17 @@ constexpr int JP = 2 * JB;
 constexpr int kMaxDim = 2048;  // largest block side (4 chi) the sort handles
 constexpr int kGateSlots = 12;  // gates per bond: the time fractions of orders 2, 3 and 4
 
+// Workgroups that serve one persistent SVD or hop whose Jacobi/QR works on C
+// columns: one per Jacobi pair of a round, and from 4 pairs up as many again
+// to update V behind the rounds.  The host sizes launches from the bond
+// capacities; the kernel trims itself to this count from the actual dims.
+__host__ __device__ inline int svd_workgroups(int C) {
+  int nbp = (C + JB - 1) / JB;
+  nbp += nbp & 1;
+  const int npairs = nbp / 2 > 1 ? nbp / 2 : 1;
+  return npairs >= 4 ? 2 * npairs : npairs;
+}
+
 // ---- kernel launchers (kernels.hip, svd.hip) ----
 void launch_contract_gate(hipStream_t s, int precision, double2 *const *sites, const int *dims, int N, int k,
                           int cap_l, int cap_r, const double2 *G, double2 *X);

@@ -1050,9 +1050,29 @@ __device__ void svd_body(const SvdLaunch &a, Barrier &bar, SharedAll &sh) {
   if (prof) a.tprof[12] += clock64() - cyc0;
 }
 
+// Columns of the launch's QR / Jacobi problem, from the current bond dims (the
+// shape svd_body derives).
+__device__ int svd_cols(const SvdLaunch &a) {
+  const int N = a.N, k = a.k;
+  auto dimL = [&](int s) { return s == 0 ? 1 : ld_dim(a.dims + s - 1); };
+  auto dimR = [&](int s) { return s == N - 1 ? 1 : ld_dim(a.dims + s); };
+  switch (a.mode) {
+    case 0: return min(4 * dimL(k), 4 * dimR(k + 1));
+    case 1: return ld_dim(a.dims + k);
+    case 3: return min(4 * dimL(k), dimR(k));
+    default: return ld_dim(a.dims + k - 1);
+  }
+}
+
+// The host launches the grid its bond capacities could need; every workgroup
+// computes the same effective count from the actual dims, and the surplus
+// leaves before touching the barrier (whose member count is the effective one).
 __global__ __launch_bounds__(NT) void svd_persistent_kernel(SvdLaunch a) {
   __shared__ SharedAll sh;
-  Barrier bar{a.bar, a.bar + 8 * 32, a.bar + 8 * 32 + 32, a.err, gridDim.x, blockIdx.x, 0u};
+  const unsigned want = (unsigned)svd_workgroups(svd_cols(a));
+  const unsigned G = gridDim.x < want ? gridDim.x : want;
+  if (blockIdx.x >= G) return;
+  Barrier bar{a.bar, a.bar + 8 * 32, a.bar + 8 * 32 + 32, a.err, G, blockIdx.x, 0u};
   svd_body(a, bar, sh);
 }
 
