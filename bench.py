@@ -13,6 +13,10 @@ two is reported.
 
 Warm-up runs W steps on a separate chain; the timed run starts a fresh chain
 at t=0 and times exactly K steps (default 50 = the whole configured run).
+Under the 1e-10 cutoff chi stays well below 256 on this trajectory, so the
+line also carries `saturated`: the same chain with cutoff 0, whose interior
+bonds sit at chi_max = 256 after two steps, timed over two steps once settled
+(FP32-contraction form), with the SVD kernel's roofline at that shape.
 """
 from __future__ import annotations
 
@@ -63,6 +67,29 @@ def timed_run(model, run, precision, steps, warmup):
     ch.close()
     return {"seconds": dt, "launches": launches, "svd_ms": svd_ms, "svd_flops": svd_flops, "obs": obs,
             "dims": dims, "sweeps": stats[2], "svds": stats[3], "trace": tr}
+
+
+def saturated_run(model, run, precision, settle, steps):
+    """The chain with cutoff 0 (chi_max binds in the bulk): `settle` untimed
+    steps, then `steps` timed ones."""
+    import torch
+
+    from paper_2203_05871_amd import Chain
+
+    ch = Chain(model, run["tau"], run["chi_max"], 0.0, precision, run["init"])
+    ch.evolve(settle)
+    ch.sync()
+    torch.cuda.synchronize()
+    ch.profile_begin(200 * steps)
+    t0 = time.perf_counter()
+    ch.evolve(steps)
+    ch.sync()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    launches, svd_ms, svd_flops = ch.profile_end()
+    dims = ch.bond_dims()
+    ch.close()
+    return {"seconds": dt, "launches": launches, "svd_ms": svd_ms, "svd_flops": svd_flops, "dims": dims}
 
 
 def timed_batch(models, run, steps, warmup, sequential):
@@ -249,6 +276,7 @@ def main():
     ap.add_argument("--workload", choices=["c3", "c4"], default="c3",
                     help="c3: N=30 chain at chi=256 (headline); c4: 64-chain batched form")
     ap.add_argument("--no-sequential", action="store_true", help="c4: skip the sequential single-chain run")
+    ap.add_argument("--no-saturated", action="store_true", help="c3: skip the cutoff-0 run at chi = 256")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also run one plain device-to-device copy of MIB MiB (the calibration kernel of "
                          "the FETCH_SIZE / WRITE_SIZE counters)")
@@ -310,12 +338,27 @@ def main():
         "data": "synthetic (seeded driven-dissipative chain, no dataset)",
         "config": {"workload": f"N=30 jittered XY chain, chi_max=256, cutoff=1e-10, tau=0.05, "
                                f"{K} steps from {args.init}", "N": 30, "chi_max": 256, "cutoff": 1e-10,
-                   "tau": 0.05, "init": args.init, "max_chi_reached": int(max(h["dims"]))},
+                   "tau": 0.05, "init": args.init, "max_chi_reached": int(max(h["dims"])),
+                   "bond_dims_final": [int(d) for d in h["dims"]]},
         "roofline": roofline,
     }
     if "fp32" in res and "fp64" in res:
         line["fp64_steps_per_s"] = K / res["fp64"]["seconds"]
         line["obs_err_fp32_vs_fp64"] = float(np.abs(res["fp32"]["obs"] - res["fp64"]["obs"]).max())
+    if not args.no_saturated:
+        settle, ks = 4, 2
+        sat = saturated_run(model, run, head, settle, ks)
+        sa = sat["svd_flops"] / (sat["svd_ms"] * 1e-3) / 1e12
+        line["saturated"] = {
+            "workload": f"the same chain and run with cutoff 0: interior bonds at chi_max=256; steps {settle + 1}-"
+                        f"{settle + ks} timed after {settle} untimed", "steps_per_s": ks / sat["seconds"],
+            "ms_per_step": 1e3 * sat["seconds"] / ks, "bond_dims": [int(d) for d in sat["dims"]],
+            "roofline": {"bound": "mfma", "kernel": "svd_persistent_kernel", "achieved": sa,
+                         "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": sa / FP64_PEAK_TFLOPS,
+                         "launches": sat["launches"], "avg_launch_ms": sat["svd_ms"] / max(1, sat["launches"]),
+                         "flops_per_launch": sat["svd_flops"] / max(1, sat["launches"])}}
+        print(f"# saturated ({head}): {ks} steps in {sat['seconds']:.2f} s, max chi {max(sat['dims'])}",
+              file=sys.stderr, flush=True)
     if not args.no_cpu:
         done, dt, obs = cpu_baseline(model, run, K, args.cpu_budget)
         line["cpu_baseline"] = {"value": done / dt, "unit": "steps/s", "cores": blas_threads(), "kind": "oracle",
