@@ -50,7 +50,13 @@ enum {
   LMPO_EUNSUPPORTED = -5  /* valid input this version does not handle */
 };
 
-enum { LMPO_FP64 = 0, LMPO_FP32_CONTRACT = 1 };
+/* LMPO_FP64_REAL: the real-arithmetic form.  In the Hermitian Pauli basis every
+ * Lindblad propagator, SWAP, unitary channel and Pauli / graph initial state is
+ * real, so the coefficients stay real: contractions, Gram matrices, Jacobi
+ * rotations and V updates run in real FP64 (one product per complex four),
+ * the storage keeps its complex layout with zero imaginary parts, and rho is
+ * Hermitian by construction (Hermitisation is a no-op). */
+enum { LMPO_FP64 = 0, LMPO_FP32_CONTRACT = 1, LMPO_FP64_REAL = 2 };
 
 /* Model parameters (Sec. 2.1).  bond_ij lists the coupled pairs (i, j), i < j;
  * each bond contributes J (s+_i s-_j + s-_i s+_j) + (1/2) Jz s^z_i s^z_j
@@ -82,8 +88,9 @@ typedef struct {
   int32_t chi_max;       /* max_dim_rho, >= 1 */
   double cutoff;         /* cut_off_rho: largest discarded squared Schmidt weight,
                             relative to the block's total; >= 0 */
-  int32_t precision;     /* LMPO_FP64, or LMPO_FP32_CONTRACT: two-site contractions
-                            in FP32 (FP32 accumulation), SVD/truncation/trace FP64 */
+  int32_t precision;     /* LMPO_FP64, LMPO_FP32_CONTRACT (two-site contractions
+                            in FP32 with FP32 accumulation, SVD/truncation/trace FP64),
+                            or LMPO_FP64_REAL (real arithmetic, see above) */
   int32_t force_trace;   /* 1: rho -> rho / tr(rho) after every step */
   int32_t force_hermitian_every; /* force_rho_hermitian_step: k >= 1 replaces rho by
                             (rho + rho^+)/2 after every k-th step (before the trace is
@@ -189,7 +196,9 @@ int lmpo_apply_gate(lmpo_state *s, int32_t k, int32_t half, int32_t ascending);
  * of a step (SWAP network when |i - j| > 1, truncation by the state's chi_max
  * and cutoff).  G: 16x16 complex (interleaved re/im, row-major) in the Pauli
  * basis P_{a_i} (x) P_{a_j}, index 4 a_i + a_j, acting on (qubit i, qubit j) in
- * that order.  Non-finite entries: LMPO_EINVAL.  Drains the stream before
+ * that order.  Non-finite entries: LMPO_EINVAL; in the real-arithmetic form an
+ * entry with an imaginary part above 1e-12 of the largest entry is
+ * LMPO_EINVAL too (smaller ones are dropped).  Drains the stream before
  * copying G to the device, then enqueues the gate asynchronously. */
 int lmpo_apply_superop(lmpo_state *s, int32_t i, int32_t j, const double *G);
 

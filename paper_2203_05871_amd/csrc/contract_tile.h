@@ -32,7 +32,9 @@ __device__ __forceinline__ int ld_dim(const int *p) {
 // A workgroup owns 16 values of l and 16 of r, i.e. a 64 x 64 tile of M with
 // all four s and all four t (a complex GEMM on the matrix cores, real-split),
 // so the 16x16 gate is applied in the epilogue from LDS.  T is the arithmetic type (double, or float for the FP32
-// contraction form: operands rounded to FP32, FP32 accumulation).
+// contraction form: operands rounded to FP32, FP32 accumulation).  kReal: the
+// real-arithmetic form (every operand has zero imaginary part in the Pauli
+// basis), one real product instead of four and a zero imaginary output.
 // Output: trans = 0 -> X = theta, column-major, ld = 4 chl;
 //         trans = 1 -> X = theta^H, column-major, ld = 4 chr.
 // ---------------------------------------------------------------------------
@@ -74,7 +76,7 @@ struct ContractLds {
 // One 16 (l) x 16 (r) output tile (bx, by) of the contraction on bond k, run by
 // one workgroup of 256 threads; tiles outside the current dims return at once.
 // dims may change between launches, so they are read with device-scope loads.
-template <typename T>
+template <typename T, bool kReal = false>
 __device__ __forceinline__ void contract_tile(ContractLds<T> &lds, double2 *const *sites, const int *dims, int N,
                                               int k, const double2 *__restrict__ G, double2 *__restrict__ X,
                                               const int bx, const int by) {
@@ -127,9 +129,11 @@ __device__ __forceinline__ void contract_tile(ContractLds<T> &lds, double2 *cons
       for (int st = 0; st < 4; ++st) {
         const C2 b = Bs[k0 + lk][16 * st + lr];
         re[st] = mfma_step<T>(a.x, b.x, re[st]);
-        re[st] = mfma_step<T>(-a.y, b.y, re[st]);
-        im[st] = mfma_step<T>(a.x, b.y, im[st]);
-        im[st] = mfma_step<T>(a.y, b.x, im[st]);
+        if (!kReal) {
+          re[st] = mfma_step<T>(-a.y, b.y, re[st]);
+          im[st] = mfma_step<T>(a.x, b.y, im[st]);
+          im[st] = mfma_step<T>(a.y, b.x, im[st]);
+        }
       }
     }
     __syncthreads();
@@ -152,7 +156,12 @@ __device__ __forceinline__ void contract_tile(ContractLds<T> &lds, double2 *cons
   for (int o = 0; o < 16; ++o) {
     C2 out{0, 0};
 #pragma unroll
-    for (int q = 0; q < 16; ++q) cfma(out, Gs[o][q], m[q]);
+    for (int q = 0; q < 16; ++q) {
+      if (kReal)
+        out.x = fma(Gs[o][q].x, m[q].x, out.x);
+      else
+        cfma(out, Gs[o][q], m[q]);
+    }
     const int sp = o / 4, tp = o % 4;
     const size_t row = (size_t)l * 4 + sp, col = (size_t)tp * chr + r;
     if (trans == 0)

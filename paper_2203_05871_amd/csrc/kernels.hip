@@ -33,21 +33,23 @@ inline void check_launch() { (void)hipGetLastError(); }
 
 }  // namespace
 
-template <typename T>
+template <typename T, bool kReal>
 __global__ __launch_bounds__(256) void contract_gate_kernel(double2 *const *sites, const int *dims, int N, int k,
                                                             const double2 *__restrict__ G,
                                                             double2 *__restrict__ X) {
   __shared__ ContractLds<T> lds;
-  contract_tile<T>(lds, sites, dims, N, k, G, X, blockIdx.x, blockIdx.y);
+  contract_tile<T, kReal>(lds, sites, dims, N, k, G, X, blockIdx.x, blockIdx.y);
 }
 
 void launch_contract_gate(hipStream_t s, int precision, double2 *const *sites, const int *dims, int N, int k,
                           int cap_l, int cap_r, const double2 *G, double2 *X) {
   dim3 grid((cap_r + 15) / 16, (cap_l + 15) / 16);
   if (precision == LMPO_FP32_CONTRACT)
-    hipLaunchKernelGGL(contract_gate_kernel<float>, grid, dim3(256), 0, s, sites, dims, N, k, G, X);
+    hipLaunchKernelGGL((contract_gate_kernel<float, false>), grid, dim3(256), 0, s, sites, dims, N, k, G, X);
+  else if (precision == LMPO_FP64_REAL)
+    hipLaunchKernelGGL((contract_gate_kernel<double, true>), grid, dim3(256), 0, s, sites, dims, N, k, G, X);
   else
-    hipLaunchKernelGGL(contract_gate_kernel<double>, grid, dim3(256), 0, s, sites, dims, N, k, G, X);
+    hipLaunchKernelGGL((contract_gate_kernel<double, false>), grid, dim3(256), 0, s, sites, dims, N, k, G, X);
   check_launch();
 }
 

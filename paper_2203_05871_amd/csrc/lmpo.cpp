@@ -225,8 +225,8 @@ int validate(const lmpo_model *m, const lmpo_options *o) {
   if (!(o->tau > 0) || !std::isfinite(o->tau)) return fail(LMPO_EINVAL, "tau must be > 0");
   if (o->chi_max < 1) return fail(LMPO_EINVAL, "chi_max must be >= 1");
   if (!(o->cutoff >= 0) || !std::isfinite(o->cutoff)) return fail(LMPO_EINVAL, "cutoff must be >= 0");
-  if (o->precision != LMPO_FP64 && o->precision != LMPO_FP32_CONTRACT)
-    return fail(LMPO_EINVAL, "precision must be LMPO_FP64 or LMPO_FP32_CONTRACT");
+  if (o->precision != LMPO_FP64 && o->precision != LMPO_FP32_CONTRACT && o->precision != LMPO_FP64_REAL)
+    return fail(LMPO_EINVAL, "precision must be LMPO_FP64, LMPO_FP32_CONTRACT or LMPO_FP64_REAL");
   if (o->trotter_order < 2 || o->trotter_order > 4) return fail(LMPO_EUNSUPPORTED, "trotter_order must be 2, 3 or 4");
   if (o->chi_max > kMaxDim / 4) return fail(LMPO_EUNSUPPORTED, "chi_max above 512 is not supported");
   std::vector<int> deg(m->n_qubits, 0);
@@ -393,6 +393,7 @@ SvdLaunch svd_args(lmpo_state *S, int mode, int k, int asc) {
   L.asc = asc;
   L.chi_max = S->opt.chi_max;
   L.max_sweeps = kMaxSweeps;
+  L.real = S->opt.precision == LMPO_FP64_REAL ? 1 : 0;
   L.cutoff = S->opt.cutoff;
   L.tol_factor = 32.0;
   L.sites = S->d_sites;
@@ -550,8 +551,17 @@ int upload_user_gate(lmpo_state *S, int i, int j, const double *G) {
       const int rr = i > j ? flip(r) : r, cc = i > j ? flip(c) : c;
       g[rr * 16 + cc] = make_double2(G[2 * (r * 16 + c)], G[2 * (r * 16 + c) + 1]);
     }
-  for (const double2 &v : g)
+  double big = 0.0, im = 0.0;
+  for (const double2 &v : g) {
     if (!std::isfinite(v.x) || !std::isfinite(v.y)) return fail(LMPO_EINVAL, "non-finite gate entry");
+    big = std::max(big, std::hypot(v.x, v.y));
+    im = std::max(im, std::abs(v.y));
+  }
+  if (S->opt.precision == LMPO_FP64_REAL) {
+    if (im > 1e-12 * big)
+      return fail(LMPO_EINVAL, "the real-arithmetic form needs a superoperator that is real in the Pauli basis");
+    for (double2 &v : g) v.y = 0.0;
+  }
   HIP_TRY(hipStreamSynchronize(S->stream));
   HIP_TRY(hipMemcpyAsync(S->d_user, g.data(), 256 * sizeof(double2), hipMemcpyHostToDevice, S->stream));
   HIP_TRY(hipStreamSynchronize(S->stream));
@@ -576,6 +586,7 @@ int renormalize(lmpo_state *S) {
 // right-to-left sweep of identity gates, i.e. the truncated two-site SVD of
 // every bond with the state's chi_max and cutoff.  The centre ends on site 0.
 int hermitize(lmpo_state *S) {
+  if (S->opt.precision == LMPO_FP64_REAL) return LMPO_OK;  // real coefficients: rho^+ = rho exactly
   const int N = S->N;
   for (int k = 0; k < N; ++k) {
     HIP_TRY(hipMemcpyAsync(S->T, S->site[k], S->site_elems[k] * sizeof(double2), hipMemcpyDeviceToDevice,
@@ -700,6 +711,20 @@ int lmpo_create(const lmpo_model *model, const lmpo_options *opt, const char *in
         return fail(LMPO_ENUMERIC, "matrix exponential failed");
       }
     }
+  }
+  if (opt->precision == LMPO_FP64_REAL) {
+    // a Lindblad propagator maps Hermitian operators to Hermitian ones, so in
+    // the Hermitian basis B_ab it is real; drop the round-off imaginary parts
+    double big = 0.0, im = 0.0;
+    for (const auto &v : S->gates_host) {
+      big = std::max(big, std::abs(v));
+      im = std::max(im, std::abs(v.imag()));
+    }
+    if (im > 1e-12 * big) {
+      delete S;
+      return fail(LMPO_ENUMERIC, "gate table not real in the Pauli basis");
+    }
+    for (auto &v : S->gates_host) v = v.real();
   }
   auto cleanup = [&](int code) {
     delete S;

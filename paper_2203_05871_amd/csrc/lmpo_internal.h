@@ -55,6 +55,7 @@ void launch_contract_gate(hipStream_t s, int precision, double2 *const *sites, c
 // as a (4 chi_l) x chi_r matrix and their entropy (no change of the state).
 struct SvdLaunch {
   int mode, k, N, asc, chi_max, max_sweeps;
+  int real;  // real-arithmetic form: every operand has zero imaginary part
   double cutoff, tol_factor;
   double2 *const *sites;
   int *dims;

@@ -229,7 +229,9 @@ __device__ __forceinline__ d4 mfma64(double a, double b, d4 c) {
 }
 
 // M[r0 + i][col[c]] <- sum_q xs[i][q] W[q][c] for the staged rows (n rows),
-// one 16-row block per wave and step.
+// one 16-row block per wave and step.  kReal: every operand is real (the
+// real-arithmetic form), one real MFMA per step and a zero imaginary part.
+template <bool kReal>
 __device__ __forceinline__ void rotate_staged(SharedPair &s, const double2 (*W)[JP + 1], double2 *__restrict__ M,
                                               int ld, int r0, int n) {
   static_assert(JP == 16, "MFMA tiling assumes 16 columns per pair");
@@ -246,9 +248,11 @@ __device__ __forceinline__ void rotate_staged(SharedPair &s, const double2 (*W)[
       const int row = i0 + lr;
       const double2 x = (row < n) ? s.xs[row][4 * kk + lk] : make_double2(0, 0);
       yr = mfma64(x.x, w[kk].x, yr);
-      yr = mfma64(-x.y, w[kk].y, yr);
-      yi = mfma64(x.x, w[kk].y, yi);
-      yi = mfma64(x.y, w[kk].x, yi);
+      if (!kReal) {
+        yr = mfma64(-x.y, w[kk].y, yr);
+        yi = mfma64(x.x, w[kk].y, yi);
+        yi = mfma64(x.y, w[kk].x, yi);
+      }
     }
     if (cj >= 0) {
 #pragma unroll
@@ -263,8 +267,10 @@ __device__ __forceinline__ void rotate_staged(SharedPair &s, const double2 (*W)[
 // One Jacobi pair: Gram of the JP columns, one cyclic sweep of two-sided
 // Jacobi on it (W), then X_p <- X_p W and V_p <- V_p W.  The same workgroup
 // does all of it, so a round needs a single grid barrier.  Returns whether the
-// pair was rotated (some off-diagonal above threshold).
-__device__ bool pair_work(SharedPair &s, double2 *__restrict__ X, int ldx, int R, double2 *__restrict__ Wout,
+// pair was rotated (some off-diagonal above threshold).  kReal: the columns are
+// real (real-arithmetic form): real Gram, real rotations, real products.
+template <bool kReal>
+__device__ __forceinline__ bool pair_work(SharedPair &s, double2 *__restrict__ X, int ldx, int R, double2 *__restrict__ Wout,
                           int C, int bi, int bj, double tol, const int *__restrict__ cmap, unsigned long long *tp) {
   const int t = threadIdx.x;
   unsigned long long tm = wall_clock64();
@@ -295,9 +301,11 @@ __device__ bool pair_work(SharedPair &s, double2 *__restrict__ X, int ldx, int R
         const int row = k0 + lk;
         const double2 x = (row < n) ? s.xs[row][lr] : make_double2(0, 0);
         gr = mfma64(x.x, x.x, gr);
-        gr = mfma64(x.y, x.y, gr);
-        gi = mfma64(x.x, x.y, gi);
-        gi = mfma64(-x.y, x.x, gi);
+        if (!kReal) {
+          gr = mfma64(x.y, x.y, gr);
+          gi = mfma64(x.x, x.y, gi);
+          gi = mfma64(-x.y, x.x, gi);
+        }
       }
       if (r0 + kChunk < R) __syncthreads();
     }
@@ -360,6 +368,11 @@ __device__ bool pair_work(SharedPair &s, double2 *__restrict__ X, int ldx, int R
     sc = make_double2(f * c.x, -f * c.y);
     return true;
   };
+  // complex products, or real ones in the real-arithmetic form
+  auto mul = [](double2 x, double2 y) { return kReal ? make_double2(x.x * y.x, 0.0) : zmul(x, y); };
+  auto cmul_conj = [](double2 x, double2 y) {  // conj(x) y
+    return kReal ? make_double2(x.x * y.x, 0.0) : zmul(zconj(x), y);
+  };
   for (int sweep = 0; sweep < kInnerSweeps; ++sweep) {
     for (int step = 0; step < JP - 1; ++step) {
       const int pa = inner_partner(a, step), pb = inner_partner(b, step);
@@ -372,13 +385,13 @@ __device__ bool pair_work(SharedPair &s, double2 *__restrict__ X, int ldx, int R
       const double2 be_a = a < pa ? s_a : make_double2(-s_a.x, s_a.y);
       const double2 be_b = b < pb ? s_b : make_double2(-s_b.x, s_b.y);
       const int nxt = cur ^ 1;
-      const double2 gj_a = zadd(zmul(s.G[cur][a][b], al_b), zmul(s.G[cur][a][pb], be_b));
-      const double2 gj_pa = zadd(zmul(s.G[cur][pa][b], al_b), zmul(s.G[cur][pa][pb], be_b));
-      double2 g = zadd(zmul(zconj(al_a), gj_a), zmul(zconj(be_a), gj_pa));
+      const double2 gj_a = zadd(mul(s.G[cur][a][b], al_b), mul(s.G[cur][a][pb], be_b));
+      const double2 gj_pa = zadd(mul(s.G[cur][pa][b], al_b), mul(s.G[cur][pa][pb], be_b));
+      double2 g = zadd(cmul_conj(al_a, gj_a), cmul_conj(be_a, gj_pa));
       if (a == b) g.y = 0.0;
       if (pa == b && rot_a) g = make_double2(0.0, 0.0);
       s.G[nxt][a][b] = g;
-      s.W[nxt][a][b] = zadd(zmul(s.W[cur][a][b], al_b), zmul(s.W[cur][a][pb], be_b));
+      s.W[nxt][a][b] = zadd(mul(s.W[cur][a][b], al_b), mul(s.W[cur][a][pb], be_b));
       __syncthreads();
       cur = nxt;
     }
@@ -387,14 +400,14 @@ __device__ bool pair_work(SharedPair &s, double2 *__restrict__ X, int ldx, int R
   const double2(*W)[JP + 1] = s.W[cur];
   // X_p <- X_p W (rows still staged when R fits one chunk)
   if (R <= kChunk) {
-    rotate_staged(s, W, X, ldx, 0, R);
+    rotate_staged<kReal>(s, W, X, ldx, 0, R);
   } else {
     for (int r0 = 0; r0 < R; r0 += kChunk) {
       const int n = min(kChunk, R - r0);
       __syncthreads();
       stage_rows(s, X, ldx, r0, n);
       __syncthreads();
-      rotate_staged(s, W, X, ldx, r0, n);
+      rotate_staged<kReal>(s, W, X, ldx, r0, n);
     }
   }
   // record W for the row-parallel update of V after the sweep
@@ -404,10 +417,11 @@ __device__ bool pair_work(SharedPair &s, double2 *__restrict__ X, int ldx, int R
   return true;
 }
 
-// V <- V W_1 W_2 ... over one sweep's rounds.  The rows of V transform
+// V <- V W_1 W_2 ... over one sweep's rounds (kReal: real V and W).  The rows of V transform
 // independently, so workgroups take row blocks of V into LDS and apply every
 // recorded pair rotation of the sweep in round order; no grid barrier needed.
-__device__ void sweep_update_v(SharedPair &s, double2 *__restrict__ V, int ldv, int C, int nbp,
+template <bool kReal>
+__device__ __forceinline__ void sweep_update_v(SharedPair &s, double2 *__restrict__ V, int ldv, int C, int nbp,
                                const double2 *__restrict__ Wsw, const int *__restrict__ act, int G,
                                const int *__restrict__ cmap, int rank) {
   const int npairs = nbp / 2;
@@ -446,9 +460,11 @@ __device__ void sweep_update_v(SharedPair &s, double2 *__restrict__ V, int ldv, 
         for (int kk = 0; kk < 4; ++kk) {
           const double2 x = (lr < h && cq[kk] >= 0) ? vs[lr * C + cq[kk]] : make_double2(0, 0);
           yr = mfma64(x.x, w[kk].x, yr);
-          yr = mfma64(-x.y, w[kk].y, yr);
-          yi = mfma64(x.x, w[kk].y, yi);
-          yi = mfma64(x.y, w[kk].x, yi);
+          if (!kReal) {
+            yr = mfma64(-x.y, w[kk].y, yr);
+            yi = mfma64(x.x, w[kk].y, yi);
+            yi = mfma64(x.y, w[kk].x, yi);
+          }
         }
         if (cj >= 0) {
 #pragma unroll
@@ -595,7 +611,8 @@ __device__ void block_select(SharedSelect &s, const double *__restrict__ sig, in
 // itself for graded spectra (Drmac & Veselic, 2008).
 // Hop (modes 1, 2): A_c = Q R (right) or A_c^H = Q R (left) by the same QR;
 // the centre site takes Q (or Q^H) and the neighbour absorbs R (or R^H).
-__device__ void svd_body(const SvdLaunch &a, Barrier &bar, SharedAll &sh) {
+template <bool kReal>
+__device__ __forceinline__ void svd_body(const SvdLaunch &a, Barrier &bar, SharedAll &sh) {
   const unsigned rank = bar.rank, G_ = bar.G;
   // phase timers (workgroup 0, thread 0): 0 setup + QR, 1 pair Gram+eig, 2 wait
   // after a round, 5 norms+select, 6 epilogue, 7 launches, 11 V update
@@ -893,8 +910,8 @@ __device__ void svd_body(const SvdLaunch &a, Barrier &bar, SharedAll &sh) {
   const size_t wsw_stride = (size_t)(nbp - 1) * npairs;  // pair slots per sweep
   const size_t cmap_stride = (size_t)nbp * JB;
   auto update_v = [&](int sw, int workers, int me) {
-    sweep_update_v(sh.pair, a.V, ldv, C, nbp, a.W + (size_t)(sw & 1) * wsw_stride * JP * JP,
-                   a.act + (size_t)(sw & 1) * wsw_stride, workers, a.cmap + (sw & 1) * cmap_stride, me);
+    sweep_update_v<kReal>(sh.pair, a.V, ldv, C, nbp, a.W + (size_t)(sw & 1) * wsw_stride * JP * JP,
+                          a.act + (size_t)(sw & 1) * wsw_stride, workers, a.cmap + (sw & 1) * cmap_stride, me);
   };
   for (int sweep = 0; sweep < a.max_sweeps; ++sweep) {
     double2 *Wsw = a.W + (size_t)(sweep & 1) * wsw_stride * JP * JP;
@@ -915,8 +932,8 @@ __device__ void svd_body(const SvdLaunch &a, Barrier &bar, SharedAll &sh) {
           if (np > 1) wait_blocks(ver + bi, ver + bj, base + round, a.err);
           lap(2);
           const size_t slot = (size_t)round * npairs + p;
-          bool active = pair_work(sh.pair, Y, ldy, C, Wsw + slot * JP * JP, C, bi, bj, tol, cmap,
-                                  (a.tprof && rank == 0) ? a.tprof : nullptr);
+          unsigned long long *tp = (a.tprof && rank == 0) ? a.tprof : nullptr;
+          const bool active = pair_work<kReal>(sh.pair, Y, ldy, C, Wsw + slot * JP * JP, C, bi, bj, tol, cmap, tp);
           if (threadIdx.x == 0) {
             act[slot] = active ? 1 : 0;
             if (active) atomicAdd(&a.sweep_cnt[sweep], 1);
@@ -1067,13 +1084,25 @@ __device__ int svd_cols(const SvdLaunch &a) {
 // The host launches the grid its bond capacities could need; every workgroup
 // computes the same effective count from the actual dims, and the surplus
 // leaves before touching the barrier (whose member count is the effective one).
+// kReal selects the real-arithmetic form (a separate instantiation, so the
+// complex kernel carries none of it).
+template <bool kReal>
 __global__ __launch_bounds__(NT) void svd_persistent_kernel(SvdLaunch a) {
   __shared__ SharedAll sh;
   const unsigned want = (unsigned)svd_workgroups(svd_cols(a));
   const unsigned G = gridDim.x < want ? gridDim.x : want;
   if (blockIdx.x >= G) return;
   Barrier bar{a.bar, a.bar + 8 * 32, a.bar + 8 * 32 + 32, a.err, G, blockIdx.x, 0u};
-  svd_body(a, bar, sh);
+  svd_body<kReal>(a, bar, sh);
+}
+
+// A batch may mix real-form and complex chains: one out-of-line call site
+// serves both instantiations.
+__device__ __noinline__ void svd_body_any(const SvdLaunch &a, Barrier &bar, SharedAll &sh) {
+  if (a.real)
+    svd_body<true>(a, bar, sh);
+  else
+    svd_body<false>(a, bar, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -1129,6 +1158,8 @@ __global__ __launch_bounds__(NT) void batch_layer_kernel(const BatchChain *__res
       for (int t = rank; t < ntiles; t += G) {
         if (precision == LMPO_FP32_CONTRACT)
           contract_tile<float>(sh.cf, L.sites, L.dims, N, b, Gt, L.X, t % tx, t / tx);
+        else if (precision == LMPO_FP64_REAL)
+          contract_tile<double, true>(sh.cd, L.sites, L.dims, N, b, Gt, L.X, t % tx, t / tx);
         else
           contract_tile<double>(sh.cd, L.sites, L.dims, N, b, Gt, L.X, t % tx, t / tx);
       }
@@ -1139,7 +1170,7 @@ __global__ __launch_bounds__(NT) void batch_layer_kernel(const BatchChain *__res
       L.asc = gate ? asc : 0;
     }
     bar.sync();
-    svd_body(L, bar, sh.all);
+    svd_body_any(L, bar, sh.all);
     bar.sync();
     if (gate) {
       centre = asc ? b + 1 : b;
@@ -1176,7 +1207,7 @@ int svd_grid_size() {
   int dev = 0, cus = 0, occ = 0;
   (void)hipGetDevice(&dev);
   (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, svd_persistent_kernel, NT, 0);
+  (void)hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, svd_persistent_kernel<false>, NT, 0);
   if (cus <= 0) cus = 1;
   if (occ <= 0) occ = 1;
   g_grid = cus;  // one workgroup per compute unit
@@ -1189,8 +1220,9 @@ hipError_t launch_svd_persistent(hipStream_t s, const SvdLaunch &L, int grid) {
   if (e != hipSuccess) return e;
   SvdLaunch a = L;
   void *args[] = {&a};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(svd_persistent_kernel), dim3(grid), dim3(NT), args,
-                                    0, s);
+  const void *fn = L.real ? reinterpret_cast<const void *>(svd_persistent_kernel<true>)
+                         : reinterpret_cast<const void *>(svd_persistent_kernel<false>);
+  return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(NT), args, 0, s);
 }
 
 int batch_grid_size() {

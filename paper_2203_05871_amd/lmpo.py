@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "liblmpo.so")
 
 LMPO_FP64 = 0
 LMPO_FP32_CONTRACT = 1
+LMPO_FP64_REAL = 2
 
 _ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EHIP", -4: "ENUMERIC", -5: "EUNSUPPORTED"}
 
@@ -162,7 +163,7 @@ class _ModelArrays:
 
 
 def _options(tau, chi_max, cutoff, precision, force_trace, order=2, hermitian_every=0):
-    prec = {"fp64": LMPO_FP64, "fp32": LMPO_FP32_CONTRACT}.get(precision, precision)
+    prec = {"fp64": LMPO_FP64, "fp32": LMPO_FP32_CONTRACT, "real": LMPO_FP64_REAL}.get(precision, precision)
     return _Options(float(tau), int(order), int(chi_max), float(cutoff), int(prec), int(bool(force_trace)),
                     int(hermitian_every))
 
