@@ -16,7 +16,10 @@ at t=0 and times exactly K steps (default 50 = the whole configured run).
 Under the 1e-10 cutoff chi stays well below 256 on this trajectory, so the
 line also carries `saturated`: the same chain with cutoff 0, whose interior
 bonds sit at chi_max = 256 after two steps, timed over two steps once settled
-(FP32-contraction form), with the SVD kernel's roofline at that shape.
+(FP32-contraction form), with the SVD kernel's roofline at that shape.  The
+real-arithmetic Pauli-basis form (opt-in, exact because every propagator is
+real in that basis) is timed the same way and reported on its own
+(`real_steps_per_s`, with its observable difference to the complex FP64 run).
 """
 from __future__ import annotations
 
@@ -277,6 +280,7 @@ def main():
                     help="c3: N=30 chain at chi=256 (headline); c4: 64-chain batched form")
     ap.add_argument("--no-sequential", action="store_true", help="c4: skip the sequential single-chain run")
     ap.add_argument("--no-saturated", action="store_true", help="c3: skip the cutoff-0 run at chi = 256")
+    ap.add_argument("--no-real", action="store_true", help="c3: skip the real-arithmetic form")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also run one plain device-to-device copy of MIB MiB (the calibration kernel of "
                          "the FETCH_SIZE / WRITE_SIZE counters)")
@@ -345,6 +349,11 @@ def main():
     if "fp32" in res and "fp64" in res:
         line["fp64_steps_per_s"] = K / res["fp64"]["seconds"]
         line["obs_err_fp32_vs_fp64"] = float(np.abs(res["fp32"]["obs"] - res["fp64"]["obs"]).max())
+    if not args.no_real and "fp64" in res:
+        rr = timed_run(model, run, "real", K, W)
+        line["real_steps_per_s"] = K / rr["seconds"]
+        line["obs_err_real_vs_fp64"] = float(np.abs(rr["obs"] - res["fp64"]["obs"]).max())
+        print(f"# real: {K} steps in {rr['seconds']:.2f} s", file=sys.stderr, flush=True)
     if not args.no_saturated:
         settle, ks = 4, 2
         sat = saturated_run(model, run, head, settle, ks)
