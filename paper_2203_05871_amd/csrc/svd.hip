@@ -754,14 +754,41 @@ __device__ __forceinline__ void svd_body(const SvdLaunch &a, Barrier &bar, Share
     lap(2);
   }
   // Q Y for the columns of Lb (R rows, ncol columns): panels in reverse
-  // order, each workgroup on its own 16-column tasks (no barrier needed).
+  // order, each workgroup on its own column tasks (no barrier needed).  Up to
+  // 512 rows a task of 8 columns stays in the upper half of the panel buffer
+  // for all panels (only the reflectors stream in); beyond, 16-column tasks
+  // are read and written per panel.
   auto apply_q = [&](int ncol) {
-    const int ntask = (ncol + 15) / 16;
-    for (int task = rank; task < ntask; task += G) {
-      for (int j0 = ((nq - 1) / nbw) * nbw, p = (nq - 1) / nbw; j0 >= 0; j0 -= nbw, --p) {
-        const int nb = min(nbw, nq - j0);
-        qr_load_panel(sh.qr, a.X, ldx, a.qmap, R, j0, nb, a.Tq + (size_t)p * kQrNbMax * kQrNbMax);
-        qr_apply_panel(sh.qr, R - j0, nb, false, a.Lb, R, j0, nullptr, task * 16, min(16, ncol - task * 16));
+    constexpr int kTileCols = 8;
+    if (R * kQrNbMax <= kQrPanelElems / 2) {
+      double2 *tile = sh.qr.P + kQrPanelElems / 2;  // R x kTileCols, column-major
+      const int ntask = (ncol + kTileCols - 1) / kTileCols;
+      for (int task = rank; task < ntask; task += G) {
+        const int c0 = task * kTileCols, nc = min(kTileCols, ncol - c0);
+        __syncthreads();
+        for (int e = threadIdx.x; e < R * kTileCols; e += NT) {
+          const int i = e % R, j = e / R;
+          tile[e] = j < nc ? a.Lb[(size_t)i + (size_t)(c0 + j) * R] : make_double2(0, 0);
+        }
+        for (int j0 = ((nq - 1) / nbw) * nbw, p = (nq - 1) / nbw; j0 >= 0; j0 -= nbw, --p) {
+          const int nb = min(nbw, nq - j0);
+          qr_load_panel(sh.qr, a.X, ldx, a.qmap, R, j0, nb, a.Tq + (size_t)p * kQrNbMax * kQrNbMax);
+          qr_apply_panel(sh.qr, R - j0, nb, false, tile, R, j0, nullptr, 0, nc);
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < R * nc; e += NT) {
+          const int i = e % R, j = e / R;
+          a.Lb[(size_t)i + (size_t)(c0 + j) * R] = tile[e];
+        }
+      }
+    } else {
+      const int ntask = (ncol + 15) / 16;
+      for (int task = rank; task < ntask; task += G) {
+        for (int j0 = ((nq - 1) / nbw) * nbw, p = (nq - 1) / nbw; j0 >= 0; j0 -= nbw, --p) {
+          const int nb = min(nbw, nq - j0);
+          qr_load_panel(sh.qr, a.X, ldx, a.qmap, R, j0, nb, a.Tq + (size_t)p * kQrNbMax * kQrNbMax);
+          qr_apply_panel(sh.qr, R - j0, nb, false, a.Lb, R, j0, nullptr, task * 16, min(16, ncol - task * 16));
+        }
       }
     }
     lap(19);
