@@ -84,37 +84,6 @@ __device__ __forceinline__ double wave_sum(double v) {
   return (lane_read(v, 0) + lane_read(v, 16)) + (lane_read(v, 32) + lane_read(v, 48));
 }
 
-// Sum of one double over the workgroup; every thread gets the same value
-// (waves summed in a fixed order).
-__device__ __forceinline__ double block_sum(SharedQR &s, double v) {
-  v = wave_sum(v);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  __syncthreads();
-  if (lane == 0) s.sred[wave] = v;
-  __syncthreads();
-  return (s.sred[0] + s.sred[1]) + (s.sred[2] + s.sred[3]);
-}
-
-// Sums of n <= kQrNbMax complex values over the workgroup, result in s.red[0][q].
-__device__ __forceinline__ void block_sum_n(SharedQR &s, double2 *acc, int n) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < kQrNbMax; ++q) {
-    if (q < n) {
-      const double re = wave_sum(acc[q].x), im = wave_sum(acc[q].y);
-      if (lane == 0) s.red[wave][q] = make_double2(re, im);
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x < n) {
-    const int q = threadIdx.x;
-    double2 a = s.red[0][q], b = s.red[1][q], c = s.red[2][q], d = s.red[3][q];
-    s.red[0][q] = make_double2((a.x + b.x) + (c.x + d.x), (a.y + b.y) + (c.y + d.y));
-  }
-  __syncthreads();
-}
-
 }  // namespace qr
 
 // Panel width for an R-row matrix (the panel of R x width elements fits in LDS).
@@ -136,10 +105,17 @@ __device__ __forceinline__ double qr_sqrt(double x) {
 // Factor logical columns [j0, j0 + nb) of A (rows j0 .. R-1) with this
 // workgroup: on return those columns of X hold R's entries on and above the
 // diagonal and the reflectors below it; Tg (nb x nb, row-major) holds T.
+// Per column c, with x = a_c below the diagonal and v = (1, x r), r the
+// reflector's scale: every quantity the column needs comes from one
+// workgroup reduction over the unscaled x, ||x||^2, d_q = x^H a_q (later
+// columns q) and e_j = v_j^H x (earlier reflectors j), since
+// w_q = v^H a_q = conj(r) d_q + a_q[c] and z_j = v_j^H v = r e_j + conj(v_j[c]);
+// then one pass scales x and updates the later columns.  Two workgroup
+// barriers per column.
 __device__ __noinline__ void qr_panel(SharedQR &s, double2 *__restrict__ X, int ldx, const int *__restrict__ qmap, int R, int j0,
                          int nb, double2 *__restrict__ Tg) {
   using namespace qr;
-  const int m = R - j0, t = threadIdx.x;
+  const int m = R - j0, t = threadIdx.x, lane = t & 63, wave = t >> 6;
   __syncthreads();  // the panel's columns may just have been written by other threads of this workgroup
   for (int c = 0; c < nb; ++c) {
     const double2 *col = X + (size_t)qmap[j0 + c] * ldx + j0;
@@ -147,12 +123,58 @@ __device__ __noinline__ void qr_panel(SharedQR &s, double2 *__restrict__ X, int 
   }
   if (t < kQrNbMax * kQrNbMax) s.T[t / kQrNbMax][t % kQrNbMax] = make_double2(0, 0);
   __syncthreads();
+  const int nd = nb - 1;
   for (int c = 0; c < nb; ++c) {
     double2 *pc = s.P + c * m;
-    double ss = 0.0;
-    for (int i = c + 1 + t; i < m; i += NT_QR) ss = fma(pc[i].x, pc[i].x, fma(pc[i].y, pc[i].y, ss));
-    ss = block_sum(s, ss);
+    // row c of the panel: written before the last barrier, rewritten after the next one
     const double2 al = pc[c];
+    double2 rowc[kQrNbMax];
+#pragma unroll
+    for (int q = 0; q < kQrNbMax; ++q)
+      if (q < nd) rowc[q] = s.P[(q < c ? q : q + 1) * m + c];
+    double ss = 0.0;
+    double2 acc[kQrNbMax];
+#pragma unroll
+    for (int q = 0; q < kQrNbMax; ++q) acc[q] = make_double2(0, 0);
+    for (int i = c + 1 + t; i < m; i += NT_QR) {
+      const double2 x = pc[i];
+      ss = fma(x.x, x.x, fma(x.y, x.y, ss));
+#pragma unroll
+      for (int q = 0; q < kQrNbMax; ++q) {
+        if (q < nd) {
+          const int cq = q < c ? q : q + 1;
+          const double2 e = s.P[cq * m + i];
+          if (cq < c)
+            cfmac(acc[q], e, x);  // e_j: conj(v_j[i]) x_i
+          else
+            cfmac(acc[q], x, e);  // d_q: conj(x_i) a_q[i]
+        }
+      }
+    }
+    // workgroup sums: DPP inside the waves, then the four waves in a fixed order
+    ss = wave_sum(ss);
+#pragma unroll
+    for (int q = 0; q < kQrNbMax; ++q) {
+      if (q < nd) {
+        acc[q].x = wave_sum(acc[q].x);
+        acc[q].y = wave_sum(acc[q].y);
+      }
+    }
+    if (lane == 0) {
+      s.sred[wave] = ss;
+#pragma unroll
+      for (int q = 0; q < kQrNbMax; ++q)
+        if (q < nd) s.red[wave][q] = acc[q];
+    }
+    __syncthreads();
+    ss = (s.sred[0] + s.sred[1]) + (s.sred[2] + s.sred[3]);
+#pragma unroll
+    for (int q = 0; q < kQrNbMax; ++q) {
+      if (q < nd) {
+        const double2 a = s.red[0][q], b = s.red[1][q], cc = s.red[2][q], d = s.red[3][q];
+        acc[q] = make_double2((a.x + b.x) + (cc.x + d.x), (a.y + b.y) + (cc.y + d.y));
+      }
+    }
     double tau = 0.0;
     double2 beta = al, rinv = make_double2(0, 0);
     if (ss > 1e-290) {  // (normal range for the estimates; smaller columns are left as they are)
@@ -167,59 +189,43 @@ __device__ __noinline__ void qr_panel(SharedQR &s, double2 *__restrict__ X, int 
       const double id = qr_rcp(d);
       rinv = make_double2(ph.x * id, -ph.y * id);  // 1 / (e^{i phi} (|alpha| + ||x||))
     }
-    __syncthreads();
-    if (tau != 0.0)
-      for (int i = c + 1 + t; i < m; i += NT_QR) pc[i] = cmul(pc[i], rinv);
-    if (t == 0) pc[c] = beta;
-    __syncthreads();
-    // w_q = v^H a_q for the panel columns q > c; z_j = v_j^H v for j < c
-    double2 acc[kQrNbMax];
+    // w_q (later columns) and z_j (earlier reflectors), uniform over the workgroup
 #pragma unroll
-    for (int q = 0; q < kQrNbMax; ++q) acc[q] = make_double2(0, 0);
-    const int nd = nb - 1;
-    for (int i = c + 1 + t; i < m; i += NT_QR) {
-      const double2 v = pc[i];
-#pragma unroll
-      for (int q = 0; q < kQrNbMax; ++q) {
-        if (q < nd) {
-          const int cq = q < c ? q : q + 1;  // j < c first, then columns after c
-          cfmac(acc[q], cq < c ? s.P[cq * m + i] : v, cq < c ? v : s.P[cq * m + i]);
+    for (int q = 0; q < kQrNbMax; ++q) {
+      if (q < nd) {
+        if (q < c) {
+          const double2 u = cmul(rinv, acc[q]);
+          acc[q] = make_double2(u.x + rowc[q].x, u.y - rowc[q].y);  // r e_j + conj(v_j[c])
+        } else {
+          const double2 u = cmulc(rinv, acc[q]);
+          acc[q] = make_double2(u.x + rowc[q].x, u.y + rowc[q].y);  // conj(r) d_q + a_q[c]
         }
       }
     }
-    if (t == 0) {  // row c, where v = 1
+    if (tau != 0.0) {
+      for (int i = c + t; i < m; i += NT_QR) {
+        double2 v = make_double2(1.0, 0.0);
+        if (i > c) {
+          v = cmul(pc[i], rinv);
+          pc[i] = v;
+        }
 #pragma unroll
-      for (int q = 0; q < kQrNbMax; ++q) {
-        if (q < nd) {
-          const int cq = q < c ? q : q + 1;
-          const double2 e = s.P[cq * m + c];
-          if (cq < c) {
-            acc[q].x += e.x;
-            acc[q].y -= e.y;  // conj(v_j[c]) * 1
-          } else {
-            acc[q].x += e.x;
-            acc[q].y += e.y;  // conj(1) * a_q[c]
+        for (int q = 0; q < kQrNbMax; ++q) {
+          if (q < nd && q >= c) {  // column q + 1
+            const double2 u = cmul(v, make_double2(tau * acc[q].x, tau * acc[q].y));
+            double2 *pq = s.P + (q + 1) * m;
+            pq[i] = make_double2(pq[i].x - u.x, pq[i].y - u.y);
           }
         }
       }
     }
-    block_sum_n(s, acc, nd);
-    if (tau != 0.0) {
-      for (int q = c + 1; q < nb; ++q) {
-        const double2 w = s.red[0][q - 1];
-        const double2 tw = make_double2(tau * w.x, tau * w.y);
-        double2 *pq = s.P + q * m;
-        for (int i = c + t; i < m; i += NT_QR) {
-          const double2 v = i == c ? make_double2(1.0, 0.0) : pc[i];
-          const double2 u = cmul(v, tw);
-          pq[i] = make_double2(pq[i].x - u.x, pq[i].y - u.y);
-        }
-      }
-    }
+    if (t == 0) pc[c] = beta;
     // T(0:c, c) = -tau T(0:c, 0:c) z (row r by thread r), T(c, c) = tau
     if (t < c) {
       double2 a = make_double2(0, 0);
-      for (int j = t; j < c; ++j) cfma(a, s.T[t][j], s.red[0][j]);
+#pragma unroll
+      for (int j = 0; j < kQrNbMax; ++j)
+        if (j >= t && j < c) cfma(a, s.T[t][j], acc[j]);
       s.T[t][c] = make_double2(-tau * a.x, -tau * a.y);
     } else if (t == c) {
       s.T[c][c] = make_double2(tau, 0.0);
