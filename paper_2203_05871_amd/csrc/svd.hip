@@ -399,16 +399,15 @@ __device__ __forceinline__ bool pair_work(SharedPair &s, double2 *__restrict__ X
   mark(9);
   const double2(*W)[JP + 1] = s.W[cur];
   // X_p <- X_p W (rows still staged when R fits one chunk)
-  if (R <= kChunk) {
-    rotate_staged<kReal>(s, W, X, ldx, 0, R);
-  } else {
-    for (int r0 = 0; r0 < R; r0 += kChunk) {
-      const int n = min(kChunk, R - r0);
-      __syncthreads();
-      stage_rows(s, X, ldx, r0, n);
-      __syncthreads();
-      rotate_staged<kReal>(s, W, X, ldx, r0, n);
-    }
+  // (the Gram pass left the last chunk of rows staged: rotate it first, then
+  // stage the others again)
+  const int rlast = ((R - 1) / kChunk) * kChunk;
+  rotate_staged<kReal>(s, W, X, ldx, rlast, R - rlast);
+  for (int r0 = 0; r0 < rlast; r0 += kChunk) {
+    __syncthreads();
+    stage_rows(s, X, ldx, r0, kChunk);
+    __syncthreads();
+    rotate_staged<kReal>(s, W, X, ldx, r0, kChunk);
   }
   // record W for the row-parallel update of V after the sweep
   Wout[t] = W[t / JP][t % JP];
