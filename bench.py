@@ -72,6 +72,20 @@ def timed_run(model, run, precision, steps, warmup):
             "dims": dims, "sweeps": stats[2], "svds": stats[3], "trace": tr}
 
 
+def chi_per_step(model, run, precision, steps):
+    """Largest bond dimension after every step (an untimed pass: it reads the
+    bond dims after each step)."""
+    from paper_2203_05871_amd import Chain
+
+    ch = Chain(model, run["tau"], run["chi_max"], run["cutoff"], precision, run["init"])
+    out = []
+    for _ in range(steps):
+        ch.evolve(1)
+        out.append(int(max(ch.bond_dims())))
+    ch.close()
+    return out
+
+
 def saturated_run(model, run, precision, settle, steps):
     """The chain with cutoff 0 (chi_max binds in the bulk): `settle` untimed
     steps, then `steps` timed ones."""
@@ -281,6 +295,8 @@ def main():
     ap.add_argument("--no-sequential", action="store_true", help="c4: skip the sequential single-chain run")
     ap.add_argument("--no-saturated", action="store_true", help="c3: skip the cutoff-0 run at chi = 256")
     ap.add_argument("--no-real", action="store_true", help="c3: skip the real-arithmetic form")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="c3: skip the +z variant and the per-step chi profiles")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also run one plain device-to-device copy of MIB MiB (the calibration kernel of "
                          "the FETCH_SIZE / WRITE_SIZE counters)")
@@ -354,6 +370,15 @@ def main():
         line["real_steps_per_s"] = K / rr["seconds"]
         line["obs_err_real_vs_fp64"] = float(np.abs(rr["obs"] - res["fp64"]["obs"]).max())
         print(f"# real: {K} steps in {rr['seconds']:.2f} s", file=sys.stderr, flush=True)
+    if not args.no_variants:
+        # the edge-driven variant (+z) beside the global quench (+x), and the
+        # largest bond dimension after every step of both
+        _, run_z = workloads.c3("+z")
+        rz = timed_run(model, run_z, head, K, 0)
+        line["plus_z"] = {"steps_per_s": K / rz["seconds"], "max_chi_reached": int(max(rz["dims"])),
+                          "bond_dims_final": [int(d) for d in rz["dims"]]}
+        line["max_chi_per_step"] = {args.init: chi_per_step(model, run, head, K),
+                                    "+z": chi_per_step(model, run_z, head, K)}
     if not args.no_saturated:
         settle, ks = 4, 2
         sat = saturated_run(model, run, head, settle, ks)
