@@ -131,7 +131,7 @@ __device__ __forceinline__ void wait_blocks(unsigned *va, unsigned *vb, unsigned
            __hip_atomic_load(vb, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
       if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 2) break;
       __builtin_amdgcn_s_sleep(1);
-      if (++spins > (1u << 22)) {
+      if (++spins > (1u << 25)) {  // the grid barrier's bound
         atomicOr(err, 2);
         break;
       }
