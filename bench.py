@@ -110,7 +110,7 @@ def saturated_run(model, run, precision, settle, steps):
 
 
 def timed_batch(models, run, steps, warmup, sequential):
-    """C4: the batched form (one launch per Trotter layer over all chains), and
+    """The 64-chain workload in the batched form (one launch per Trotter layer over all chains), and
     optionally the same chains run one after another through the single-chain
     path (the plain FP64 GPU path) for comparison."""
     import torch
@@ -164,14 +164,14 @@ def timed_batch(models, run, steps, warmup, sequential):
     return out
 
 
-def bench_c4(args):
+def bench_batch(args):
     """Batched form on the 64-chain workload (a separate line from the
     headline; not the driver's default)."""
     import numpy as np
 
     import workloads
 
-    models, run = workloads.c4()
+    models, run = workloads.chains64_uneven()
     K, W = args.steps, args.warmup
     r = timed_batch(models, run, K, W, sequential=not args.no_sequential)
     value = K / r["seconds"]
@@ -246,7 +246,7 @@ def cpu_baseline(model, run, steps, budget_s):
     return done, dt, obs
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "svd_persistent_c3_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "svd_persistent_chain30_traffic.json")
 
 
 def measured_traffic():
@@ -290,20 +290,20 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=25.0, help="seconds of oracle time for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--init", default="+x")
-    ap.add_argument("--workload", choices=["c3", "c4"], default="c3",
-                    help="c3: N=30 chain at chi=256 (headline); c4: 64-chain batched form")
-    ap.add_argument("--no-sequential", action="store_true", help="c4: skip the sequential single-chain run")
-    ap.add_argument("--no-saturated", action="store_true", help="c3: skip the cutoff-0 run at chi = 256")
-    ap.add_argument("--no-real", action="store_true", help="c3: skip the real-arithmetic form")
+    ap.add_argument("--workload", choices=["chain30", "chains64"], default="chain30",
+                    help="chain30: N=30 chain at chi_max=256 (headline); chains64: 64 uneven chains, batched form")
+    ap.add_argument("--no-sequential", action="store_true", help="chains64: skip the sequential single-chain run")
+    ap.add_argument("--no-saturated", action="store_true", help="chain30: skip the cutoff-0 run at chi = 256")
+    ap.add_argument("--no-real", action="store_true", help="chain30: skip the real-arithmetic form")
     ap.add_argument("--no-variants", action="store_true",
-                    help="c3: skip the +z variant and the per-step chi profiles")
+                    help="chain30: skip the +z variant and the per-step chi profiles")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also run one plain device-to-device copy of MIB MiB (the calibration kernel of "
                          "the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for {args.gpus}): a single chain's Trotter step is a "
-              "strictly sequential chain of gates; multi-GPU sharding is described in DESIGN.md, not run.",
+              "strictly sequential chain of gates; sharding over several GPUs is not run.",
               file=sys.stderr)
         sys.exit(2)
 
@@ -321,13 +321,13 @@ def main():
         torch.cuda.synchronize()
         print(f"# copy probe: {args.copy_probe} MiB read + written", file=sys.stderr, flush=True)
         del src, dst
-    if args.workload == "c4":
+    if args.workload == "chains64":
         if args.steps is None:
             args.steps = 40
-        return bench_c4(args)
+        return bench_batch(args)
     if args.steps is None:
         args.steps = 50
-    model, run = workloads.c3(args.init)
+    model, run = workloads.chain30_jittered(args.init)
     K, W = args.steps, args.warmup
     res = {}
     for prec in (["fp32", "fp64"] if args.precision == "both" else [args.precision]):
@@ -373,7 +373,7 @@ def main():
     if not args.no_variants:
         # the edge-driven variant (+z) beside the global quench (+x), and the
         # largest bond dimension after every step of both
-        _, run_z = workloads.c3("+z")
+        _, run_z = workloads.chain30_jittered("+z")
         rz = timed_run(model, run_z, head, K, 0)
         line["plus_z"] = {"steps_per_s": K / rz["seconds"], "max_chi_reached": int(max(rz["dims"])),
                           "bond_dims_final": [int(d) for d in rz["dims"]]}

@@ -25,8 +25,8 @@ __device__ __forceinline__ int ld_dim(const int *p) {
 }
 
 // ---------------------------------------------------------------------------
-// Two-site contraction with the gate (north_star steps "contract the two-site
-// block" and "apply the propagator"):
+// Two-site contraction with the gate (forming the two-site block and applying
+// the propagator to it):
 //   M[(l,s),(t,r)] = sum_m A_k[l][s][m] A_{k+1}[m][t][r]
 //   theta[(l,s'),(t',r)] = sum_{s,t} G[(s' t'),(s t)] M[(l,s),(t,r)]
 // A workgroup owns 16 values of l and 16 of r, i.e. a 64 x 64 tile of M with

@@ -33,7 +33,7 @@ def test_arena_size_and_argument_errors_on_host():
     import workloads
     from paper_2203_05871_amd import lmpo
 
-    m, run = workloads.c3()
+    m, run = workloads.chain30_jittered()
     n = lmpo.arena_bytes(m, run["tau"], run["chi_max"], run["cutoff"])
     # 30 sites at chi=256 dominate: at least 28 * 256*4*256 complex doubles
     assert n > 28 * 256 * 4 * 256 * 16

@@ -149,12 +149,12 @@ def test_batch_mixed_precision(lib):
         ch.close()
 
 
-def test_batch_c4_full_size_sampled(lib):
+def test_batch_64_chains_full_size_sampled(lib):
     """The 64-chain batching workload (N in [8, 24], chi_max = 64, cutoff
     1e-12) for 10 steps in the launch configuration the benchmark times;
     sampled chains equal their single-chain runs bit for bit, the smallest
     one also matches the oracle."""
-    models, run = workloads.c4()
+    models, run = workloads.chains64_uneven()
     chains = [lib.Chain(m, run["tau"], run["chi_max"], run["cutoff"], "fp64", run["init"]) for m in models]
     b = lib.Batch(chains)
     steps = 10

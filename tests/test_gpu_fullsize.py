@@ -116,11 +116,11 @@ def ch_model(N, seed):
     return workloads.jittered_chain(N, seed)
 
 
-def test_c2_full_run(Chain):
+def test_chain20_full_run(Chain):
     """The 20-site chain workload in full (chi_max = 128, cutoff 1e-12, tau =
     0.05, 100 steps from +z): every 10 steps all <sz_i> and <sz_i sz_j> (i < j)
     and the bond dims against the oracle."""
-    m, run = workloads.c2()
+    m, run = workloads.chain20_jittered()
     ch = Chain(m, run["tau"], run["chi_max"], run["cutoff"], "fp64", run["init"])
     ref = tebd.MPS.product(run["init"], m["N"])
     gates = tebd.gate_tables(m, run["tau"])
@@ -209,13 +209,13 @@ def test_error_paths(Chain):
 
 
 @pytest.mark.timeout(400)
-def test_c3_full_run_parity(Chain):
+def test_chain30_full_run_parity(Chain):
     """The 30-site benchmark chain (chi_max = 256, cutoff 1e-10, tau = 0.05,
     +x, 50 steps) in the launch configuration the benchmark times: after every
     step of the run the bond dims, and at the end every <sz_i> and
     <sz_i sz_j> (i < j), FP64 against the oracle; the FP32-contraction form
     within 1e-5 of FP64."""
-    m, run = workloads.c3()
+    m, run = workloads.chain30_jittered()
     N = m["N"]
     ch = Chain(m, run["tau"], run["chi_max"], run["cutoff"], "fp64", run["init"])
     c32 = Chain(m, run["tau"], run["chi_max"], run["cutoff"], "fp32", run["init"])

@@ -74,10 +74,10 @@ def test_graph_with_cycle_and_long_bonds(lib):
     ch.close()
 
 
-def test_c5_ladder_full_run(lib):
+def test_ladder2x8_full_run(lib):
     """The 2 x 8 ladder workload in full (N = 16, chi_max = 128, cutoff 1e-12,
     40 steps from +z), in the FP64 and FP32-contraction forms."""
-    m, run = workloads.c5()
+    m, run = workloads.ladder2x8()
     N = m["N"]
     ch = lib.Chain(m, run["tau"], run["chi_max"], run["cutoff"], "fp64", run["init"])
     c32 = lib.Chain(m, run["tau"], run["chi_max"], run["cutoff"], "fp32", run["init"])
@@ -93,10 +93,10 @@ def test_c5_ladder_full_run(lib):
     c32.close()
 
 
-def test_c5_ladder_truncating_sampled(lib):
+def test_ladder2x8_truncating_sampled(lib):
     """The same ladder from +x with chi_max = 32, which binds from the second
     step: three steps against the oracle."""
-    m, run = workloads.c5()
+    m, run = workloads.ladder2x8()
     N = m["N"]
     ch = lib.Chain(m, run["tau"], 32, run["cutoff"], "fp64", "+x")
     ref = tebd.MPS.product("+x", N)

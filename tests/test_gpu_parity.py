@@ -65,9 +65,9 @@ def test_initial_state_observables(lib):
     ch.close()
 
 
-def test_c1_parity_fp64(lib):
+def test_chain6_exact_parity_fp64(lib):
     """N=6, chi=64 (exact), tau=0.01, 100 steps, all <sz_i> and <sz_i sz_j>."""
-    m, run = workloads.c1()
+    m, run = workloads.chain6_exact()
     worst, ch, ref = run_both(lib, m, run, run["steps"], every=10)
     assert worst < 1e-10
     assert ch.bond_dims() == ref.bond_dims()

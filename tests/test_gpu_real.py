@@ -67,8 +67,8 @@ def test_real_form_against_oracle(lib, order):
     ch.close()
 
 
-def test_real_form_c1(lib):
-    m, run = workloads.c1()
+def test_real_form_chain6_exact(lib):
+    m, run = workloads.chain6_exact()
     ch = lib.Chain(m, run["tau"], run["chi_max"], run["cutoff"], "real", run["init"])
     ref = tebd.MPS.product(run["init"], m["N"])
     ch.evolve(run["steps"])

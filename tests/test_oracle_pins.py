@@ -43,9 +43,9 @@ def test_single_site_generator_matches_bloch_equations():
 def test_bloch_steady_state_golden_and_tebd():
     """J = 0: each site follows its own Bloch equations; the driven edge
     relaxes to the optical-Bloch steady state (golden file)."""
-    data = np.loadtxt(os.path.join(GOLDEN, "bloch_steady_c1_site0.txt"))
+    data = np.loadtxt(os.path.join(GOLDEN, "bloch_steady_driven_qubit.txt"))
     np.testing.assert_allclose(cf.bloch_steady_state(1.0, 0.0, 0.1, 0.05), data, atol=1e-15)
-    m, _ = workloads.c1()
+    m, _ = workloads.chain6_exact()
     m["J"][:] = 0.0
     m["N"] = 3
     m["bonds"] = m["bonds"][:2]
@@ -143,7 +143,7 @@ def test_tebd_equals_dense_trotter_without_truncation():
 
 
 def test_trotter_second_order_against_exact():
-    m, run = workloads.c1()
+    m, run = workloads.chain6_exact()
     N = m["N"]
     v0 = dense.product_vector("+z", N)
     T = 1.0
@@ -158,10 +158,10 @@ def test_trotter_second_order_against_exact():
     assert errs[2] < 3e-5
 
 
-def test_c1_oracle_close_to_exact():
-    """C1 (tau = 0.01, T = 1, chi = 64 = 4^3 exact): MPS-TEBD is within the
+def test_chain6_oracle_close_to_exact():
+    """The exact 6-site chain (tau = 0.01, T = 1, chi = 64 = 4^3): MPS-TEBD is within the
     O(tau^2) Trotter error of the exact Lindblad evolution."""
-    m, run = workloads.c1()
+    m, run = workloads.chain6_exact()
     N = m["N"]
     mps = tebd.MPS.product("+z", N)
     tebd.evolve(mps, m, run["tau"], 100, run["chi_max"], run["cutoff"])
@@ -244,7 +244,7 @@ def test_delta_zero_symmetry_survives_truncation():
 
 
 def test_trace_and_hermiticity_invariants():
-    m, run = workloads.c1()
+    m, run = workloads.chain6_exact()
     N = 6
     v = dense.product_vector("+z", N)
     v = dense.trotter_evolve(v, m, 0.05, 20, force_trace=False)
@@ -361,7 +361,7 @@ def _plant(monkeypatch, what):
 def test_planted_mistakes_are_caught(monkeypatch, what):
     _plant(monkeypatch, what)
     caught = []
-    data = np.loadtxt(os.path.join(GOLDEN, "bloch_steady_c1_site0.txt"))
+    data = np.loadtxt(os.path.join(GOLDEN, "bloch_steady_driven_qubit.txt"))
     m = workloads.chain_model(3, 0.0, 0.0, 1.0, 0.1, 0.05)
     mps = tebd.MPS.product("+z", 3)
     tebd.evolve(mps, m, 0.25, 400, 4, 0.0)

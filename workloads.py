@@ -49,7 +49,7 @@ def alternating(N, delta):
     return float(delta) * (np.arange(N) % 2)
 
 
-def c1():
+def chain6_exact():
     """N=6 chain, chi_max=64 = 4^3 (exact, no truncation), tau=0.01, 100 steps."""
     m = chain_model(6, 1.0, alternating(6, 5.0), 1.0, 0.1, 0.05)
     run = {"tau": 0.01, "steps": 100, "chi_max": 64, "cutoff": 0.0, "init": "+z"}
@@ -66,14 +66,14 @@ def jittered_chain(N, seed=0):
     return chain_model(N, J, hz, 1.0, 0.1, 0.05)
 
 
-def c2():
+def chain20_jittered():
     """N=20 jittered chain, chi_max=128, cutoff 1e-12, tau=0.05, 100 steps."""
     m = jittered_chain(20, 0)
     run = {"tau": 0.05, "steps": 100, "chi_max": 128, "cutoff": 1e-12, "init": "+z"}
     return m, run
 
 
-def c3(init="+x"):
+def chain30_jittered(init="+x"):
     """N=30 jittered chain, chi_max=256, cutoff 1e-10, tau=0.05, 50 steps.
 
     init "+x" (a global quench) makes chi=256 bind in the bulk; "+z" is the
@@ -83,7 +83,7 @@ def c3(init="+x"):
     return m, run
 
 
-def c4(n_chains=64, seed=0):
+def chains64_uneven(n_chains=64, seed=0):
     """Independent chains: per chain, in order, N ~ U{8..24}, Omega ~ U[0.5, 2],
     Delta ~ U[2, 8]; J=1, g0=0.1, g2=0.05; chi_max=64, cutoff 1e-12."""
     rng = np.random.default_rng(seed)
@@ -123,7 +123,7 @@ def ladder_model(n_rungs=8, J=1.0, delta=5.0, omega=1.0, g0=0.1, g2=0.05):
     }
 
 
-def c5():
+def ladder2x8():
     """2 x 8 ladder (N = 16, 8 rungs, 14 legs two sites apart on the path),
     chi_max = 128, cutoff 1e-12, tau = 0.05, 40 steps, init +z."""
     m = ladder_model(8)
