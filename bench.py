@@ -222,9 +222,15 @@ def bench_batch(args):
     print(json.dumps(line), flush=True)
 
 
-def cpu_baseline(model, run, steps, budget_s):
+def cpu_baseline(model, run, steps, budget_s, threads=None):
     """The FP64 oracle on the host cores: as many of the same steps as fit in
-    the time budget (a bounded sample of the same trajectory)."""
+    the time budget (a bounded sample of the same trajectory); `threads`
+    limits the BLAS threads."""
+    if threads is not None:
+        from threadpoolctl import threadpool_limits
+
+        with threadpool_limits(limits=threads):
+            return cpu_baseline(model, run, steps, budget_s)
     import numpy as np
 
     from oracle import tebd
@@ -321,6 +327,20 @@ def main():
         torch.cuda.synchronize()
         print(f"# copy probe: {args.copy_probe} MiB read + written", file=sys.stderr, flush=True)
         del src, dst
+    # context for the HBM roofline: a plain 1 GiB device copy (read + write);
+    # skipped in counter runs, whose calibration is the probe copy above
+    copy_gbps = None
+    if args.copy_probe == 0:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        copy_gbps = 5 * 2 * (1 << 30) / (time.perf_counter() - t0) / 1e9
+        del src, dst
     if args.workload == "chains64":
         if args.steps is None:
             args.steps = 40
@@ -349,7 +369,8 @@ def main():
                 "launches": h["launches"],
                 "avg_launch_ms": h["svd_ms"] / max(1, h["launches"]),
                 "flops_per_launch": h["svd_flops"] / max(1, h["launches"]),
-                "kernel_share_of_step": h["svd_ms"] * 1e-3 / h["seconds"]}
+                "kernel_share_of_step": h["svd_ms"] * 1e-3 / h["seconds"],
+                "measured_copy_GBps": copy_gbps}
     line = {
         "metric": METRIC, "value": value, "unit": "steps/s", "n_gpus": 1, "steps": K, "warmup": W,
         "ms_per_step": 1e3 * h["seconds"] / K, "higher_is_better": True, "scaling": "weak",
@@ -397,6 +418,9 @@ def main():
         done, dt, obs = cpu_baseline(model, run, K, args.cpu_budget)
         line["cpu_baseline"] = {"value": done / dt, "unit": "steps/s", "cores": blas_threads(), "kind": "oracle",
                                 "sample": f"first {done} of the {K} timed steps (FP64 NumPy/LAPACK oracle)"}
+        d1, t1, _ = cpu_baseline(model, run, K, args.cpu_budget / 2, threads=1)
+        line["cpu_baseline_1thread"] = {"value": d1 / t1, "unit": "steps/s", "cores": 1, "kind": "oracle",
+                                        "sample": f"first {d1} of the {K} timed steps, one BLAS thread"}
         if obs is not None:
             ref = res["fp64"]["obs"] if "fp64" in res else h["obs"]
             line["obs_err_fp64_vs_oracle"] = float(np.abs(ref - obs).max())
