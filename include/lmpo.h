@@ -43,7 +43,7 @@ extern "C" {
 
 enum {
   LMPO_OK = 0,
-  LMPO_EINVAL = -1,       /* invalid argument (the paper's "exception if not passed", Sec. 6) */
+  LMPO_EINVAL = -1,       /* invalid or missing argument (the paper's solver stops with an error there, Sec. 6) */
   LMPO_ENOMEM = -2,       /* arena too small */
   LMPO_EHIP = -3,         /* HIP runtime error; the message carries its name */
   LMPO_ENUMERIC = -4,     /* NaN/Inf in a singular value or observable, or tr(rho) = 0 */
@@ -77,7 +77,7 @@ typedef struct {
   const double *g0, *g1, *g2;   /* [n_qubits], >= 0 */
 } lmpo_model;
 
-/* Numerical controls (Sec. 6, "Numerical simulation control"). */
+/* Numerical controls of the solver (Sec. 6). */
 typedef struct {
   double tau;            /* time step, > 0 */
   int32_t trotter_order; /* 2; 3 (open chain only): the product A(7/24) B(2/3) A(3/4) B(-2/3)
