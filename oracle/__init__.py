@@ -17,6 +17,11 @@ Sources (Landa & Misguich, arXiv:2203.05871):
   dense.py         brute-force 4^N references: the same Trotter product
                    without truncation, and exact exponentiation of the full
                    Liouvillian (the paper's brute-force comparison, Sec. 3.2)
+  adjoint.py       parameter gradients of a final-time expectation value by
+                   the adjoint (co-state) method on the MPS: transposed gates
+                   carry the co-state back, every gate contributes the trace
+                   of its Frechet-derivative factor with the two-site
+                   transition density of state and co-state
   closed_forms.py  textbook closed forms used as pins: single-qubit Bloch
                    equations and their steady state, the one-excitation
                    sector of the XY chain (Sec. 3.2, free-fermion picture)

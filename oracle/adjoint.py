@@ -1,0 +1,195 @@
+"""Parameter gradients of a final-time expectation value by the adjoint
+(co-state) method on the MPS (oracle, FP64, CPU).
+
+TEST INFRASTRUCTURE ONLY (see the package header).
+
+Objective: F = Tr(O rho_T) / Tr(rho_T) with O = sigma^a on one qubit
+(Eq. mu), after T Trotter steps from a fixed initial state.  Parameters: every
+entry of hx, hy, hz, g0, g1, g2 (per qubit) and J, Jz (per bond) of the model
+of Sec. 2.1.  Each bond generator L_b is linear in every one of them (the
+Hamiltonian enters through a commutator, each rate multiplies its dissipator),
+so dL_b/dtheta is the generator of the same bond with theta = 1 and all other
+parameters 0, with the same sharing of the on-site terms among the bonds.
+
+Derivative of the Trotter product (gates G_g = exp(x_g L_b(g)), the step's
+division by the trace at its end): F does not change when rho_T is scaled, and
+each gate's derivative is dG/dtheta = K G with K = (dG/dtheta) G^{-1}, so
+
+    dF/dtheta = sum_g  s_g  < mu_g , K_g rho_g >
+
+  rho_g  the state right after gate g (as computed: divided by the traces of
+         the steps before),
+  mu_g   the co-state right after gate g: mu_T = (o - F 1) / Tr(rho_T), with o
+         and 1 the covectors of O and of the trace, carried backwards by
+         mu <- G^T mu through every later gate (SWAP gates included); <., .>
+         is the bilinear pairing sum_x mu_x rho_x of coefficient vectors, so
+         the transpose (not the adjoint) is the backward map,
+  s_g    1 / (product of the traces t_m divided out at the ends of steps m
+         from the gate's own step to the last; 1 without trace forcing),
+  K_g    the Frechet derivative of the exponential at x L in the direction
+         x dL/dtheta (SciPy), times exp(-x L), on the gate's two sites.
+
+< mu, K rho > only involves the two sites the gate acted on: it is
+tr(K Gamma) with the transition density Gamma[(c d), (a b)] = the sum over
+every other index of rho[..c d..] mu[..a b..].
+
+On the MPS, rho_g is the forward TEBD state after gate g (every snapshot kept)
+and mu_g the co-state MPS (bond dimension 2 at time T, brought to canonical
+form by an exact QR sweep) after the truncated two-site gates G^T, with the
+state's chi_max and cutoff, applied in reverse order.  Without truncation this
+is exactly the derivative of the Trotter product (pinned against central
+differences of the dense Trotter evolution).  With truncation it approximates
+that derivative to the truncation error of both passes; it is not the
+derivative of the truncated map itself (no differentiation of the truncated
+SVD).
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.linalg
+
+from . import model as lm
+from . import tebd
+
+SITE_KEYS = ("hx", "hy", "hz", "g0", "g1", "g2")
+BOND_KEYS = ("J", "Jz")
+
+
+def parameter_list(model):
+    """[(key, index)] in the order hx[0..N-1], hy, hz, g0, g1, g2, J[0..nb-1], Jz."""
+    N, nb = model["N"], len(model["bonds"])
+    return [(k, s) for k in SITE_KEYS for s in range(N)] + [(k, b) for k in BOND_KEYS for b in range(nb)]
+
+
+def unit_model(model, key, index):
+    """The model with parameter (key, index) = 1 and every other parameter 0."""
+    out = dict(model)
+    for k in SITE_KEYS + BOND_KEYS:
+        out[k] = np.zeros(len(model[k]))
+    out[key][index] = 1.0
+    return out
+
+
+def generator_derivative(model, b, key, index):
+    """dL_b / dtheta (16 x 16, site-major computational basis)."""
+    return lm.bond_generator(unit_model(model, key, index), b)
+
+
+def bond_parameters(model, b):
+    """Parameters that bond b's generator depends on."""
+    i, j = (int(x) for x in model["bonds"][b])
+    return [(k, s) for s in (i, j) for k in SITE_KEYS] + [("J", b), ("Jz", b)]
+
+
+def k_matrix(L, dL, x):
+    """(d/dtheta exp(x L)) exp(-x L) for dL/dtheta = dL."""
+    _, D = scipy.linalg.expm_frechet(x * L, x * dL)
+    return D @ scipy.linalg.expm(-x * L)
+
+
+def transition_density(mu, rho, k):
+    """Gamma[(c d), (a b)] on sites (k, k + 1): rho's local indices (c, d)
+    and mu's (a, b), every other index of the two MPS contracted pairwise."""
+    N = len(mu)
+    L = np.ones((1, 1), dtype=np.complex128)
+    for s in range(k):
+        L = np.einsum("pq,pam,qan->mn", L, mu[s], rho[s], optimize=True)
+    R = np.ones((1, 1), dtype=np.complex128)
+    for s in range(N - 1, k + 1, -1):
+        R = np.einsum("map,naq,pq->mn", mu[s], rho[s], R, optimize=True)
+    g = np.einsum("pq,pam,mbr,qcn,nds,rs->cdab", L, mu[k], mu[k + 1], rho[k], rho[k + 1], R, optimize=True)
+    return g.reshape(16, 16)
+
+
+def forward_record(model, tau, steps, chi_max, cutoff, init, order=2, force_trace=True):
+    """The TEBD run of tebd.evolve, keeping after every two-site gate the
+    record (site k, bond or None for a SWAP, fraction of tau, ascending?,
+    copy of all site tensors), and the trace divided out at each step's end.
+    Returns (final MPS, [records of step n], [trace of step n])."""
+    N = model["N"]
+    mps = tebd.MPS.product(init, N)
+    gates = tebd.gate_tables(model, tau, order)
+    P = lm.swap_gate()
+    bonds = np.asarray(model["bonds"])
+    chain = tebd.is_chain(model)
+    records, traces = [], []
+    for n in range(steps):
+        ops = []
+
+        def gate(k, G, asc, b, frac):
+            mps.apply_gate(k, G, chi_max, cutoff, asc)
+            ops.append((k, b, frac, asc, [a.copy() for a in mps.A]))
+
+        if chain:
+            for k, frac, asc in tebd.step_schedule(N, n, order):
+                gate(k, gates[(k, frac)], asc, k, frac)
+        else:
+            for b, frac, fwd in tebd.sweep_schedule(model, order):
+                i, j = int(bonds[b, 0]), int(bonds[b, 1])
+                if j == i + 1:
+                    gate(i, gates[(b, frac)], fwd, b, frac)
+                    continue
+                for k in range(j - 1, i, -1):
+                    gate(k, P, False, None, None)
+                gate(i, gates[(b, frac)], True, b, frac)
+                for k in range(i + 1, j):
+                    gate(k, P, True, None, None)
+        traces.append(mps.renormalize() if force_trace else 1.0)
+        records.append(ops)
+    return mps, records, traces
+
+
+def costate(N, site, pauli, F, tr):
+    """MPS of mu_T = (o - F 1) / tr, bond dimension 2 (1 for N = 1 is not
+    needed: N >= 2), left-orthonormal with the centre on the last site."""
+    o = [tebd.covector(lm.PAULI[pauli]) if s == site else tebd.E_ID for s in range(N)]
+    w = [tebd.E_ID] * N
+    A = []
+    for s in range(N):
+        if s == 0:
+            t = np.zeros((1, 4, 2), dtype=np.complex128)
+            t[0, :, 0], t[0, :, 1] = o[s], w[s]
+        elif s == N - 1:
+            t = np.zeros((2, 4, 1), dtype=np.complex128)
+            t[0, :, 0], t[1, :, 0] = o[s] / tr, -F * w[s] / tr
+        else:
+            t = np.zeros((2, 4, 2), dtype=np.complex128)
+            t[0, :, 0], t[1, :, 1] = o[s], w[s]
+        A.append(t)
+    mu = tebd.MPS(A, 0)
+    mu.move_centre(N - 1)
+    return mu
+
+
+def gradient(model, tau, steps, chi_max, cutoff, init, site, pauli, order=2, force_trace=True):
+    """(F, {key: complex array of dF/dtheta}, final MPS) for O = sigma^pauli
+    on `site` (module header)."""
+    N = model["N"]
+    mps, records, traces = forward_record(model, tau, steps, chi_max, cutoff, init, order, force_trace)
+    F = mps.expect({site: lm.PAULI[pauli.upper()]})
+    mu = costate(N, site, pauli.upper(), F, mps.trace())
+    gates = tebd.gate_tables(model, tau, order)
+    P = lm.swap_gate()
+    grads = {k: np.zeros(len(model[k]), dtype=np.complex128) for k in SITE_KEYS + BOND_KEYS}
+    kcache = {}
+    scale = 1.0
+    for n in reversed(range(steps)):
+        scale = scale / traces[n]
+        for k, b, frac, asc, snap in reversed(records[n]):
+            if b is None:
+                mu.apply_gate(k, P.T, chi_max, cutoff, not asc)
+                continue
+            Gam = transition_density(mu.A, snap, k)
+            for key, idx in bond_parameters(model, b):
+                ck = (b, frac, key, idx)
+                if ck not in kcache:
+                    kcache[ck] = k_matrix(lm.bond_generator(model, b), generator_derivative(model, b, key, idx),
+                                          frac * tau)
+                grads[key][idx] += scale * np.sum(kcache[ck] * Gam.T)
+            mu.apply_gate(k, gates[(b, frac)].T, chi_max, cutoff, not asc)
+    return F, grads, mps
+
+
+def flatten(model, grads):
+    """Gradient dict -> array in parameter_list order."""
+    return np.array([grads[k][i] for k, i in parameter_list(model)])

@@ -1,0 +1,178 @@
+"""Pins of the oracle's adjoint gradient (oracle/adjoint.py) against what does
+not depend on it: central differences of the dense Trotter evolution (the same
+product of gates on the full 4^N vector, no MPS), brute-force contractions of
+the full vectors, and central differences of the matrix exponential."""
+import numpy as np
+import pytest
+import scipy.linalg
+
+from oracle import adjoint, dense, tebd
+from oracle import model as lm
+
+
+def rich_chain(N, seed):
+    """Every parameter nonzero, so that a dropped term shows."""
+    rng = np.random.default_rng(seed)
+    nb = N - 1
+    return {
+        "N": N,
+        "bonds": np.array([[b, b + 1] for b in range(nb)]),
+        "J": rng.uniform(0.5, 1.5, nb), "Jz": rng.uniform(-0.8, 0.8, nb),
+        "hx": rng.uniform(-1, 1, N), "hy": rng.uniform(-1, 1, N), "hz": rng.uniform(-2, 2, N),
+        "g0": rng.uniform(0.05, 0.3, N), "g1": rng.uniform(0.02, 0.2, N), "g2": rng.uniform(0.02, 0.2, N),
+    }
+
+
+def rich_graph(N, bonds, seed):
+    m = rich_chain(N, seed)
+    rng = np.random.default_rng(seed + 1)
+    nb = len(bonds)
+    m["bonds"] = np.asarray(bonds)
+    m["J"], m["Jz"] = rng.uniform(0.5, 1.5, nb), rng.uniform(-0.8, 0.8, nb)
+    return m
+
+
+def dense_expectation(model, tau, steps, init, site, pauli, order=2, force_trace=True):
+    N = model["N"]
+    v = dense.product_vector(init, N)
+    v = dense.trotter_evolve(v, model, tau, steps, order=order, force_trace=force_trace)
+    return dense.expect(v, N, {site: lm.PAULI[pauli]})
+
+
+def dense_fd_gradient(model, tau, steps, init, site, pauli, order=2, force_trace=True, h=1e-6):
+    out = []
+    for key, idx in adjoint.parameter_list(model):
+        vals = []
+        for sgn in (1.0, -1.0):
+            m = {k: (np.array(v, dtype=float) if k in adjoint.SITE_KEYS + adjoint.BOND_KEYS else v)
+                 for k, v in model.items()}
+            m[key][idx] += sgn * h
+            vals.append(dense_expectation(m, tau, steps, init, site, pauli, order, force_trace))
+        out.append((vals[0] - vals[1]) / (2 * h))
+    return np.array(out)
+
+
+def test_forward_record_is_the_tebd_run():
+    """The recording forward pass performs exactly tebd.evolve's gates."""
+    m = rich_chain(5, 1)
+    mps, records, traces = adjoint.forward_record(m, 0.1, 3, 6, 1e-8, "+x")
+    ref = tebd.MPS.product("+x", 5)
+    tebd.evolve(ref, m, 0.1, 3, 6, 1e-8)
+    for a, b in zip(mps.A, ref.A):
+        assert np.array_equal(a, b)
+    assert len(records) == 3 and all(len(r) == 6 for r in records)  # A, B, A: 2 + 2 + 2 gates on 5 sites
+    assert np.allclose(traces, 1.0, atol=1e-2)  # truncation alone moves the trace
+
+
+def test_forward_record_swap_network_is_the_tebd_run():
+    m = rich_graph(4, [[0, 1], [0, 2], [1, 3], [2, 3]], 2)
+    mps, records, _ = adjoint.forward_record(m, 0.1, 2, 16, 0.0, "+x")
+    ref = tebd.MPS.product("+x", 4)
+    tebd.evolve(ref, m, 0.1, 2, 16, 0.0)
+    for a, b in zip(mps.A, ref.A):
+        assert np.array_equal(a, b)
+    # per step: F and R sweeps over 4 bonds, the two bonds apart taking 2 SWAPs each
+    assert len(records[0]) == 2 * (4 + 2 * 2)
+    assert sum(r[1] is None for r in records[0]) == 8
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 3])
+def test_transition_density_brute_force(k):
+    """tr(K Gamma) equals <mu, K rho> on the full vectors, for random MPS and K."""
+    rng = np.random.default_rng(k)
+    N = 5
+    dims = [1, 3, 4, 5, 2, 1]
+    mk = lambda d: [rng.standard_normal((d[s], 4, d[s + 1])) + 1j * rng.standard_normal((d[s], 4, d[s + 1]))
+                    for s in range(N)]
+    mu, rho = mk(dims), mk([1, 2, 6, 3, 4, 1])
+    K = rng.standard_normal((16, 16)) + 1j * rng.standard_normal((16, 16))
+    Gam = adjoint.transition_density(mu, rho, k)
+    got = np.sum(K * Gam.T)
+    ref = np.dot(dense.mps_to_vector(mu), dense.apply_two_site(dense.mps_to_vector(rho), K, k, k + 1, N))
+    assert abs(got - ref) <= 1e-12 * abs(ref)
+
+
+def test_k_matrix_against_central_differences_of_expm():
+    m = rich_chain(3, 4)
+    L = lm.bond_generator(m, 0)
+    for key, idx in [("hz", 0), ("g0", 1), ("J", 0), ("hy", 1)]:
+        dL = adjoint.generator_derivative(m, 0, key, idx)
+        x, h = 0.07, 1e-5
+        fd = (scipy.linalg.expm(x * (L + h * dL)) - scipy.linalg.expm(x * (L - h * dL))) / (2 * h)
+        K = adjoint.k_matrix(L, dL, x)
+        assert np.abs(K @ scipy.linalg.expm(x * L) - fd).max() < 1e-9
+
+
+def test_generator_is_linear_in_every_parameter():
+    """The unit-model derivative reproduces L_b exactly as sum theta dL/dtheta."""
+    m = rich_graph(4, [[0, 1], [0, 2], [1, 3], [2, 3]], 5)
+    for b in range(4):
+        acc = sum(m[k][i] * adjoint.generator_derivative(m, b, k, i) for k, i in adjoint.bond_parameters(m, b))
+        assert np.abs(acc - lm.bond_generator(m, b)).max() < 1e-12
+
+
+@pytest.mark.parametrize("site,pauli,force", [(1, "Z", True), (2, "X", True), (0, "Y", False)])
+def test_exact_chain_gradient_equals_dense_trotter_derivative(site, pauli, force):
+    """No truncation (chi = 4^2 on 4 sites, cutoff 0): every one of the 30
+    derivatives equals central differences of the dense Trotter product."""
+    m = rich_chain(4, 7)
+    tau, steps = 0.1, 3
+    F, g, _ = adjoint.gradient(m, tau, steps, 16, 0.0, "+x", site, pauli, force_trace=force)
+    assert abs(F - dense_expectation(m, tau, steps, "+x", site, pauli, force_trace=force)) < 1e-12
+    got = adjoint.flatten(m, g)
+    ref = dense_fd_gradient(m, tau, steps, "+x", site, pauli, force_trace=force)
+    assert np.abs(got.imag).max() < 1e-12
+    assert np.abs(got - ref).max() < 1e-8, np.abs(got - ref).max()
+
+
+def test_exact_plaquette_gradient_equals_dense_trotter_derivative():
+    """A 2 x 2 plaquette on the zigzag path: two of the four bonds go through
+    the SWAP network, whose transposes the co-state passes back through."""
+    m = rich_graph(4, [[0, 1], [0, 2], [1, 3], [2, 3]], 8)
+    tau, steps = 0.1, 2
+    F, g, _ = adjoint.gradient(m, tau, steps, 16, 0.0, "+z", 3, "X")
+    got = adjoint.flatten(m, g)
+    ref = dense_fd_gradient(m, tau, steps, "+z", 3, "X")
+    assert np.abs(got - ref).max() < 1e-8, np.abs(got - ref).max()
+
+
+def test_exact_fourth_order_gradient_equals_dense_trotter_derivative():
+    m = rich_chain(3, 9)
+    F, g, _ = adjoint.gradient(m, 0.15, 2, 16, 0.0, "+y", 0, "Z", order=4)
+    got = adjoint.flatten(m, g)
+    ref = dense_fd_gradient(m, 0.15, 2, "+y", 0, "Z", order=4)
+    assert np.abs(got - ref).max() < 1e-8, np.abs(got - ref).max()
+
+
+def test_truncated_gradient_approaches_the_dense_derivative():
+    """With truncation the co-state gradient approximates the Trotter
+    derivative; the error falls as chi grows and vanishes at the exact chi."""
+    m = rich_chain(6, 11)
+    tau, steps = 0.1, 4
+    ref = dense_fd_gradient(m, tau, steps, "+x", 2, "Z")
+    errs = []
+    for chi in (4, 8, 16, 64):
+        _, g, _ = adjoint.gradient(m, tau, steps, chi, 0.0, "+x", 2, "Z")
+        errs.append(np.abs(adjoint.flatten(m, g) - ref).max())
+    assert errs[-1] < 1e-8
+    assert errs[0] > errs[1] > errs[2] > errs[3]
+    assert errs[1] < 0.05 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("N,site,pauli", [(2, 0, "X"), (4, 2, "Z"), (5, 4, "Y")])
+def test_costate_brute_force(N, site, pauli):
+    """<mu_T, v> = (Tr(O v) - F Tr(v)) / tr for any vector v (the F 1 term
+    contributes nothing to exact trace-preserving dynamics, so it is pinned
+    here on its own), and the QR sweep leaves sites 0..N-2 left-orthonormal."""
+    rng = np.random.default_rng(N)
+    F, tr = 0.3 - 0.2j, 0.9 + 0.1j
+    mu = adjoint.costate(N, site, pauli, F, tr)
+    v = rng.standard_normal(4 ** N) + 1j * rng.standard_normal(4 ** N)
+    ops = {site: lm.PAULI[pauli]}
+    cov_o = [tebd.covector(ops[k]) if k in ops else tebd.E_ID for k in range(N)]
+    ref = (dense.contract(v, cov_o) - F * dense.contract(v, [tebd.E_ID] * N)) / tr
+    got = np.dot(dense.mps_to_vector(mu.A), v)
+    assert abs(got - ref) <= 1e-12 * abs(ref)
+    for A in mu.A[:-1]:
+        M = A.reshape(-1, A.shape[2])
+        assert np.abs(M.conj().T @ M - np.eye(M.shape[1])).max() < 1e-12
