@@ -319,6 +319,62 @@ int lmpo_batch_profile_end(lmpo_batch *b, double out[3]);
 
 int lmpo_batch_destroy(lmpo_batch *b);
 
+/* ---- Parameter gradients (adjoint form) ----------------------------------
+ * Derivatives of a final-time expectation value F = Tr(sigma^a_i rho_T) /
+ * Tr(rho_T) (Eq. mu) with respect to every model parameter, by the adjoint
+ * (co-state) method.  Every bond generator L_b is linear in each parameter
+ * theta, and the derivative of the gate exp(x L_b) is K exp(x L_b) with K =
+ * (d/dtheta exp(x L_b)) exp(-x L_b), so the derivative of the Trotter product
+ * is sum over gates g of s_g <mu_g, K_g rho_g>: rho_g the state after gate g,
+ * mu_g the co-state after it (mu_T = (o - F 1)/Tr(rho_T), o and 1 the
+ * covectors of sigma^a_i and of the trace, carried back by the transposed
+ * gates, SWAP gates included), s_g the inverse product of the traces divided
+ * out at the ends of the steps from g's own step on, and <mu, K rho> the trace
+ * of K with the two-site transition density of the two MPS.  The co-state is
+ * an MPS truncated by the same rule as the state, with the state's chi_max and
+ * cutoff unless the caller gives its own (a backward-evolved local observable
+ * spreads faster than a weakly driven state, so its bonds can be the larger
+ * cost).  Without truncation the result is the exact derivative of the
+ * Trotter product; with it, an approximation to the truncation error of the
+ * two passes (this is not a derivative of the truncated SVD).
+ *
+ * A workspace serves one state and a fixed number of steps.  It holds the
+ * co-state (a state of the same model and controls, its gate table
+ * transposed), a snapshot of the state at the start of every step, the gate
+ * outputs of one step (the step is replayed from its snapshot during the
+ * backward pass) and the environments; lmpo_grad_arena_bytes gives its size
+ * (device memory, 256-byte aligned, caller-owned, bounded by (n_steps + 1 +
+ * gates per step) site blocks at capacity).  Not supported (LMPO_EUNSUPPORTED):
+ * force_hermitian_every > 0, chi_max < 2. */
+typedef struct lmpo_grad lmpo_grad;
+
+/* Device bytes of the workspace for n_steps >= 1 steps of s (0 on invalid
+ * input).  costate_chi_max <= 0 and costate_cutoff < 0 take the state's
+ * values; the co-state's chi_max must be 2..512. */
+size_t lmpo_grad_arena_bytes(lmpo_state *s, int32_t n_steps, int32_t costate_chi_max, double costate_cutoff);
+
+/* Builds the workspace: creates the co-state in it, transposes its gate table,
+ * and tabulates K for every bond, used time fraction and parameter on the host
+ * (the Frechet derivative of the exponential as the upper-right block of the
+ * exponential of [[x L, x dL], [0, x L]]).  Synchronises.  The state must
+ * outlive the workspace. */
+int lmpo_grad_create(lmpo_state *s, int32_t n_steps, int32_t costate_chi_max, double costate_cutoff,
+                     void *device_arena, size_t arena_bytes, lmpo_grad **out);
+
+/* Advances the state by the workspace's n_steps exactly as lmpo_evolve_step
+ * would (same results; the discarded weight and the statistics count the
+ * forward run only) and returns F = <sigma^pauli_site>(T) as (re, im) and
+ * grad_out[p] = d Re F / d theta_p for the 6 n_qubits + 2 n_bonds parameters
+ * in the order hx[0..N-1], hy, hz, g0, g1, g2, J[0..n_bonds-1], Jz.
+ * pauli is 'X', 'Y' or 'Z'.  Synchronises (once per co-state gate). */
+int lmpo_grad_run(lmpo_grad *g, int32_t site, char pauli, double F[2], double *grad_out);
+
+/* Bond dims of the co-state (n_qubits - 1 entries): after a run, those of
+ * mu at time 0, the end of the backward pass.  Synchronises. */
+int lmpo_grad_costate_dims(lmpo_grad *g, int32_t *out);
+
+int lmpo_grad_destroy(lmpo_grad *g);
+
 #ifdef __cplusplus
 }
 #endif

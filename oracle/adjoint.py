@@ -35,8 +35,8 @@ every other index of rho[..c d..] mu[..a b..].
 
 On the MPS, rho_g is the forward TEBD state after gate g (every snapshot kept)
 and mu_g the co-state MPS (bond dimension 2 at time T, brought to canonical
-form by an exact QR sweep) after the truncated two-site gates G^T, with the
-state's chi_max and cutoff, applied in reverse order.  Without truncation this
+form by an exact QR sweep) after the truncated two-site gates G^T, applied
+in reverse order with the state's chi_max and cutoff or the co-state's own.  Without truncation this
 is exactly the derivative of the Trotter product (pinned against central
 differences of the dense Trotter evolution).  With truncation it approximates
 that derivative to the truncation error of both passes; it is not the
@@ -161,9 +161,13 @@ def costate(N, site, pauli, F, tr):
     return mu
 
 
-def gradient(model, tau, steps, chi_max, cutoff, init, site, pauli, order=2, force_trace=True):
+def gradient(model, tau, steps, chi_max, cutoff, init, site, pauli, order=2, force_trace=True,
+             costate_chi_max=None, costate_cutoff=None):
     """(F, {key: complex array of dF/dtheta}, final MPS) for O = sigma^pauli
-    on `site` (module header)."""
+    on `site` (module header).  The co-state is truncated with chi_max and
+    cutoff unless costate_chi_max / costate_cutoff are given."""
+    chi_mu = chi_max if costate_chi_max is None else costate_chi_max
+    cut_mu = cutoff if costate_cutoff is None else costate_cutoff
     N = model["N"]
     mps, records, traces = forward_record(model, tau, steps, chi_max, cutoff, init, order, force_trace)
     F = mps.expect({site: lm.PAULI[pauli.upper()]})
@@ -177,7 +181,7 @@ def gradient(model, tau, steps, chi_max, cutoff, init, site, pauli, order=2, for
         scale = scale / traces[n]
         for k, b, frac, asc, snap in reversed(records[n]):
             if b is None:
-                mu.apply_gate(k, P.T, chi_max, cutoff, not asc)
+                mu.apply_gate(k, P.T, chi_mu, cut_mu, not asc)
                 continue
             Gam = transition_density(mu.A, snap, k)
             for key, idx in bond_parameters(model, b):
@@ -186,7 +190,7 @@ def gradient(model, tau, steps, chi_max, cutoff, init, site, pauli, order=2, for
                     kcache[ck] = k_matrix(lm.bond_generator(model, b), generator_derivative(model, b, key, idx),
                                           frac * tau)
                 grads[key][idx] += scale * np.sum(kcache[ck] * Gam.T)
-            mu.apply_gate(k, gates[(b, frac)].T, chi_max, cutoff, not asc)
+            mu.apply_gate(k, gates[(b, frac)].T, chi_mu, cut_mu, not asc)
     return F, grads, mps
 
 

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblmpo.so")
-SOURCES = ["model.cpp", "kernels.hip", "svd.hip", "lmpo.cpp"]
+SOURCES = ["model.cpp", "kernels.hip", "svd.hip", "grad.hip", "lmpo.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-shared", "--offload-arch=gfx950",

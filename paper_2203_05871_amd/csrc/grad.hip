@@ -1,0 +1,143 @@
+// HIP kernels (gfx950) of the adjoint gradient: contractions of the state MPS
+// with the co-state MPS (bilinear: coefficients are paired without complex
+// conjugation), the two-site transition density, and the accumulation of
+// each gate's contribution tr(K Gamma) into the parameter gradient.
+//
+// Complex numbers are double2 (x = re, y = im).
+#include "lmpo_internal.h"
+
+namespace lmpo {
+
+namespace {
+
+__device__ __forceinline__ void zfma(double2 &acc, double2 a, double2 b) {
+  acc.x = fma(a.x, b.x, acc.x);
+  acc.x = fma(-a.y, b.y, acc.x);
+  acc.y = fma(a.x, b.y, acc.y);
+  acc.y = fma(a.y, b.x, acc.y);
+}
+__device__ __forceinline__ double2 zadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+
+constexpr int kBM = 32, kBN = 32, kBK = 16;
+
+}  // namespace
+
+// C(m, n) = sum_k A(m, k) B(k, n) for batch z, every operand addressed by its
+// own element strides (any transposition or slice of a row-major tensor).
+// 256 threads own a 32 x 32 tile of C, 2 x 2 elements each; A and B pass
+// through LDS in k-chunks of 16.  Reads outside [0, M) x [0, K) and
+// [0, K) x [0, N) are replaced by zeros, so the grid may cover more than C.
+__global__ __launch_bounds__(256) void zgemm_kernel(ZgemmArgs g) {
+  __shared__ double2 As[kBK][kBM + 1];
+  __shared__ double2 Bs[kBK][kBN + 1];
+  const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
+  const int m0 = blockIdx.y * kBM, n0 = blockIdx.x * kBN, z = blockIdx.z;
+  const double2 *A = g.A + (long long)z * g.sab;
+  const double2 *B = g.B + (long long)z * g.sbb;
+  double2 acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = make_double2(0.0, 0.0);
+  for (int k0 = 0; k0 < g.K; k0 += kBK) {
+    for (int e = tid; e < kBK * kBM; e += 256) {
+      const int kk = e / kBM, mm = e % kBM;
+      const int m = m0 + mm, k = k0 + kk;
+      As[kk][mm] = (m < g.M && k < g.K) ? A[(long long)m * g.sam + (long long)k * g.sak] : make_double2(0.0, 0.0);
+    }
+    for (int e = tid; e < kBK * kBN; e += 256) {
+      const int kk = e / kBN, nn = e % kBN;
+      const int n = n0 + nn, k = k0 + kk;
+      Bs[kk][nn] = (n < g.N && k < g.K) ? B[(long long)k * g.sbk + (long long)n * g.sbn] : make_double2(0.0, 0.0);
+    }
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = 0; kk < kBK; ++kk) {
+      const double2 a0 = As[kk][ty], a1 = As[kk][ty + 16];
+      const double2 b0 = Bs[kk][tx], b1 = Bs[kk][tx + 16];
+      zfma(acc[0][0], a0, b0);
+      zfma(acc[0][1], a0, b1);
+      zfma(acc[1][0], a1, b0);
+      zfma(acc[1][1], a1, b1);
+    }
+    __syncthreads();
+  }
+  double2 *C = g.C + (long long)z * g.scb;
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) {
+      const int m = m0 + ty + 16 * i, n = n0 + tx + 16 * j;
+      if (m < g.M && n < g.N) C[(long long)m * g.scm + (long long)n * g.scn] = acc[i][j];
+    }
+}
+
+void launch_zgemm(hipStream_t s, const ZgemmArgs &g, int batch) {
+  if (g.M <= 0 || g.N <= 0 || batch <= 0) return;
+  dim3 grid((g.N + kBN - 1) / kBN, (g.M + kBM - 1) / kBM, batch);
+  hipLaunchKernelGGL(zgemm_kernel, grid, dim3(256), 0, s, g);
+  (void)hipGetLastError();
+}
+
+// gam[(c d) * 16 + (a b)] = sum_{p, q} E[a][p][c][q] Fr[d][p][b][q] with p <
+// pm (co-state bond) and q < qm (state bond): one workgroup per output, a
+// fixed-order reduction (results do not depend on timing).
+__global__ __launch_bounds__(256) void transition_reduce_kernel(const double2 *__restrict__ E,
+                                                                const double2 *__restrict__ Fr, int pm, int qm,
+                                                                double2 *__restrict__ gam) {
+  __shared__ double2 red[256];
+  const int out = blockIdx.x;
+  const int x = out / 16, y = out % 16;
+  const int c = x / 4, d = x % 4, a = y / 4, b = y % 4;
+  const long long n = (long long)pm * qm;
+  double2 acc = make_double2(0.0, 0.0);
+  for (long long e = threadIdx.x; e < n; e += 256) {
+    const int p = (int)(e / qm), q = (int)(e % qm);
+    const double2 u = E[(((long long)a * pm + p) * 4 + c) * qm + q];
+    const double2 v = Fr[(((long long)d * pm + p) * 4 + b) * qm + q];
+    zfma(acc, u, v);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] = zadd(red[threadIdx.x], red[threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) gam[out] = red[0];
+}
+
+void launch_transition_reduce(hipStream_t s, const double2 *E, const double2 *Fr, int pm, int qm, double2 *gam) {
+  hipLaunchKernelGGL(transition_reduce_kernel, dim3(256), dim3(256), 0, s, E, Fr, pm, qm, gam);
+  (void)hipGetLastError();
+}
+
+// grad[pidx[j]] += scale * sum_{y, x} K[j][y][x] gam[x][y] for the nk
+// parameters j of one gate (K: [nk][16][16], row = output index).  One
+// workgroup per parameter; workgroups write distinct entries.
+__global__ __launch_bounds__(256) void grad_accumulate_kernel(const double2 *__restrict__ K, const int *pidx,
+                                                              const double2 *__restrict__ gam, double2 scale,
+                                                              double2 *grad) {
+  __shared__ double2 red[256];
+  const int j = blockIdx.x, e = threadIdx.x;
+  const int y = e / 16, x = e % 16;
+  double2 acc = make_double2(0.0, 0.0);
+  zfma(acc, K[(size_t)j * 256 + e], gam[x * 16 + y]);
+  red[e] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (e < off) red[e] = zadd(red[e], red[e + off]);
+    __syncthreads();
+  }
+  if (e == 0) {
+    const int t = pidx[j];
+    if (t >= 0) {
+      double2 v = make_double2(0.0, 0.0);
+      zfma(v, scale, red[0]);
+      grad[t] = zadd(grad[t], v);
+    }
+  }
+}
+
+void launch_grad_accumulate(hipStream_t s, const double2 *K, const int *pidx, int nk, const double2 *gam,
+                            double2 scale, double2 *grad) {
+  hipLaunchKernelGGL(grad_accumulate_kernel, dim3(nk), dim3(256), 0, s, K, pidx, gam, scale, grad);
+  (void)hipGetLastError();
+}
+
+}  // namespace lmpo

@@ -144,6 +144,20 @@ struct DimsRing {
   }
 };
 
+// Gates of one step recorded for the adjoint pass: after every two-site gate
+// the site tensors and bond dims are copied into the next snapshot slot.
+struct OpRecord {
+  int k;     // left site of the pair the gate acted on
+  int bond;  // model bond of the gate, or -1 for a SWAP
+  int slot;  // gate table slot (time fraction)
+  int asc;   // direction the centre moved
+};
+struct Recorder {
+  std::vector<OpRecord> ops;
+  char *slots = nullptr;  // device: capacity snapshots of `stride` bytes
+  size_t stride = 0, capacity = 0;
+};
+
 struct lmpo_state {
   ModelHost m;
   lmpo_options opt{};
@@ -187,6 +201,7 @@ struct lmpo_state {
   double2 *d_user = nullptr;    // caller-supplied two-site superoperator
   double2 *d_ident = nullptr;   // identity (compression sweep of the Hermitian part)
   bool herm_room = false;       // bond capacities doubled for the Hermitian part
+  Recorder *rec = nullptr;      // set while the adjoint pass replays a step
 };
 
 namespace {
@@ -484,6 +499,47 @@ int move_centre(lmpo_state *S, int to) {
   return LMPO_OK;
 }
 
+// Snapshot of the state: the site tensors (one contiguous block of the arena,
+// at capacity) followed by the bond dims.
+size_t site_region_bytes(const lmpo_state *S) {
+  return (size_t)(reinterpret_cast<const char *>(S->site[S->N - 1] + S->site_elems[S->N - 1]) -
+                  reinterpret_cast<const char *>(S->site[0]));
+}
+size_t snapshot_dims_offset(const lmpo_state *S) { return (site_region_bytes(S) + 255) & ~size_t(255); }
+size_t snapshot_bytes(const lmpo_state *S) {
+  return snapshot_dims_offset(S) + ((((size_t)S->N - 1) * sizeof(int) + 255) & ~size_t(255));
+}
+int save_snapshot(lmpo_state *S, char *dst) {
+  HIP_TRY(hipMemcpyAsync(dst, S->site[0], site_region_bytes(S), hipMemcpyDeviceToDevice, S->stream));
+  HIP_TRY(hipMemcpyAsync(dst + snapshot_dims_offset(S), S->d_dims, (S->N - 1) * sizeof(int),
+                         hipMemcpyDeviceToDevice, S->stream));
+  return LMPO_OK;
+}
+int load_snapshot(lmpo_state *S, const char *src) {
+  HIP_TRY(hipMemcpyAsync(S->site[0], src, site_region_bytes(S), hipMemcpyDeviceToDevice, S->stream));
+  HIP_TRY(hipMemcpyAsync(S->d_dims, src + snapshot_dims_offset(S), (S->N - 1) * sizeof(int),
+                         hipMemcpyDeviceToDevice, S->stream));
+  return LMPO_OK;
+}
+
+int record_gate(lmpo_state *S, int k, const double2 *G, int asc) {
+  Recorder &R = *S->rec;
+  OpRecord op{k, -1, 0, asc};
+  const size_t table = (size_t)S->m.nb * kGateSlots * 256;
+  if (G >= S->d_gates && G < S->d_gates + table) {
+    const size_t idx = (size_t)(G - S->d_gates) / 256;
+    op.bond = (int)(idx / kGateSlots);
+    op.slot = (int)(idx % kGateSlots);
+  } else if (G != S->d_swap) {
+    return fail(LMPO_EUNSUPPORTED, "only model gates and SWAP gates can be recorded");
+  }
+  if (R.ops.size() >= R.capacity) return fail(LMPO_EINVAL, "a step holds more gates than the gradient workspace");
+  int rc = save_snapshot(S, R.slots + R.ops.size() * R.stride);
+  if (rc) return rc;
+  R.ops.push_back(op);
+  return LMPO_OK;
+}
+
 // Two-site gate G (device, 16x16 Pauli basis) on sites (k, k+1).
 int apply_gate_dev(lmpo_state *S, int k, const double2 *G, int asc) {
   int rc = move_centre(S, S->centre <= k ? k : k + 1);
@@ -495,7 +551,7 @@ int apply_gate_dev(lmpo_state *S, int k, const double2 *G, int asc) {
   rc = launch_svd(S, svd_args(S, 0, k, asc), grid_for(S, std::max(r, c), std::min(r, c)));
   if (rc) return rc;
   S->centre = asc ? k + 1 : k;
-  return LMPO_OK;
+  return S->rec ? record_gate(S, k, G, asc) : LMPO_OK;
 }
 
 const double2 *gate_ptr(const lmpo_state *S, int bond, int slot) {
@@ -1644,6 +1700,450 @@ int lmpo_batch_destroy(lmpo_batch *B) {
   hipError_t e = hipStreamSynchronize(B->stream);
   delete B;
   if (e != hipSuccess) return fail(LMPO_EHIP, std::string("batch destroy: ") + hipGetErrorString(e));
+  return LMPO_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Adjoint gradient of a final-time one-qubit expectation value with respect
+// to every model parameter (lmpo_grad_*).
+//
+// F = Tr(O rho_T) / Tr(rho_T).  Every bond generator is linear in each
+// parameter theta, and a gate's derivative is dG/dtheta = K G with
+// K = (d/dtheta exp(x L)) exp(-x L).  Then
+//   dF/dtheta = sum_g s_g <mu_g, K_g rho_g>,
+// rho_g the state right after gate g, mu_g the co-state after it (mu_T =
+// (o - F 1) / Tr(rho_T), carried back through every later gate by its
+// transpose: the pairing of coefficient vectors is bilinear), s_g = 1 / the
+// product of the traces divided out at the ends of the steps from g's own
+// step on.  <mu, K rho> = tr(K Gamma) with Gamma the two-site transition
+// density of the two MPS on the gate's sites.
+//
+// Forward: the state runs the steps as lmpo_evolve_step does, with a
+// snapshot of all site tensors at the start of every step.  Backward, step by
+// step from the last: the step is replayed from its snapshot recording every
+// gate's output (bit-identical: same kernels, same inputs), then its gates
+// are walked in reverse: Gamma between the co-state and the recorded state,
+// the contributions of the gate's 14 parameters, and the co-state advanced by
+// the transposed gate (truncated like any gate, the state's chi_max and
+// cutoff).  The state ends as after the forward run.
+// ---------------------------------------------------------------------------
+struct lmpo_grad {
+  lmpo_state *S = nullptr;  // the state (the caller's)
+  lmpo_state *C = nullptr;  // co-state, in the workspace
+  int n_steps = 0, max_ops = 0, P = 0;
+  size_t snap = 0;
+  char *ckpt = nullptr;  // n_steps + 1 snapshots
+  Recorder rec;          // one step's gate snapshots
+  double2 *L = nullptr, *R = nullptr, *W = nullptr, *E = nullptr, *Fr = nullptr, *gam = nullptr;
+  double2 *K = nullptr;  // [nb][kGateSlots][kGradLocal][16][16]
+  int *pidx = nullptr;   // [nb][kGradLocal] global parameter index
+  double2 *grad = nullptr, *traces = nullptr, *one = nullptr;
+  double *disc_save = nullptr;
+  int *stats_save = nullptr;
+  std::vector<int> ckpt_centre;
+  ~lmpo_grad() { delete C; }
+};
+
+namespace {
+
+constexpr int kGradLocal = 14;  // parameters of one bond generator: 6 per site, J, Jz
+
+lmpo_model model_view(const ModelHost &m) {
+  lmpo_model v;
+  v.n_qubits = m.N;
+  v.n_bonds = m.nb;
+  v.bond_ij = m.bonds.data();
+  v.J = m.J.data();
+  v.Jz = m.Jz.data();
+  v.hx = m.hx.data();
+  v.hy = m.hy.data();
+  v.hz = m.hz.data();
+  v.g0 = m.g0.data();
+  v.g1 = m.g1.data();
+  v.g2 = m.g2.data();
+  return v;
+}
+
+// Gates (SWAPs included) one step applies, and the gate table slots it uses.
+int grad_ops_per_step(const lmpo_state *S) {
+  int n = 0;
+  if (S->chain) {
+    for (const TrotterLayer &l : trotter_layers(S->opt.trotter_order))
+      for (int b = l.parity; b < S->N - 1; b += 2) ++n;
+    return n;
+  }
+  for (int b = 0; b < S->m.nb; ++b) n += 1 + 2 * (S->m.bonds[2 * b + 1] - S->m.bonds[2 * b] - 1);
+  return 2 * n * (int)sweep_slots(S->opt.trotter_order).size();
+}
+std::vector<int> grad_slots(const lmpo_state *S) {
+  std::vector<int> out;
+  if (S->chain)
+    for (const TrotterLayer &l : trotter_layers(S->opt.trotter_order)) out.push_back(l.slot);
+  else
+    out = sweep_slots(S->opt.trotter_order);
+  std::sort(out.begin(), out.end());
+  out.erase(std::unique(out.begin(), out.end()), out.end());
+  return out;
+}
+
+size_t grad_layout(lmpo_grad *G, const lmpo_state *S, int n_steps, const lmpo_options &co_opt, char *base,
+                   size_t size, char **co, size_t co_bytes) {
+  Arena a{base, size};
+  const size_t cm = (size_t)std::max(S->cap_max, compute_sizes(S->N, co_opt.chi_max, 1).cap_max);
+  *co = a.take<char>(co_bytes);
+  G->snap = snapshot_bytes(S);
+  G->max_ops = grad_ops_per_step(S);
+  G->ckpt = a.take<char>((size_t)(n_steps + 1) * G->snap);
+  G->rec.slots = a.take<char>((size_t)G->max_ops * G->snap);
+  G->rec.stride = G->snap;
+  G->rec.capacity = (size_t)G->max_ops;
+  G->L = a.take<double2>(cm * cm);
+  G->R = a.take<double2>(cm * cm);
+  G->W = a.take<double2>(4 * cm * cm);
+  G->E = a.take<double2>(16 * cm * cm);
+  G->Fr = a.take<double2>(16 * cm * cm);
+  G->gam = a.take<double2>(256);
+  G->K = a.take<double2>((size_t)S->m.nb * kGateSlots * kGradLocal * 256);
+  G->pidx = a.take<int>((size_t)S->m.nb * kGradLocal);
+  G->P = 6 * S->N + 2 * S->m.nb;
+  G->grad = a.take<double2>(G->P);
+  G->traces = a.take<double2>(n_steps);
+  G->one = a.take<double2>(1);
+  G->disc_save = a.take<double>(1);
+  G->stats_save = a.take<int>(kStats);
+  return a.used;
+}
+
+// Controls of the co-state: the state's, with chi_max and cutoff replaced
+// where the caller gives them (chi_max > 0, cutoff >= 0).
+int grad_check(const lmpo_state *S, int n_steps, int co_chi, double co_cut, lmpo_options *co_opt) {
+  if (!S) return fail(LMPO_EINVAL, "state is null");
+  if (n_steps < 1) return fail(LMPO_EINVAL, "n_steps must be >= 1");
+  if (S->opt.force_hermitian_every > 0)
+    return fail(LMPO_EUNSUPPORTED, "the gradient does not pass through the Hermitian part");
+  if (!std::isfinite(co_cut)) return fail(LMPO_EINVAL, "costate_cutoff must be finite");
+  *co_opt = S->opt;
+  if (co_chi > 0) co_opt->chi_max = co_chi;
+  if (co_cut >= 0) co_opt->cutoff = co_cut;
+  if (co_opt->chi_max < 2) return fail(LMPO_EUNSUPPORTED, "the co-state needs chi_max >= 2 (it starts at bond 2)");
+  if (co_opt->chi_max > kMaxDim / 4) return fail(LMPO_EUNSUPPORTED, "costate_chi_max above 512 is not supported");
+  return LMPO_OK;
+}
+
+size_t costate_bytes(const lmpo_state *S, const lmpo_options &co_opt) {
+  lmpo_model mv = model_view(S->m);
+  return lmpo_arena_bytes(&mv, &co_opt);
+}
+
+// K = (d/dtheta exp(x L_b)) exp(-x L_b) for the kGradLocal parameters of bond
+// b: the Frechet derivative of the exponential in the direction x dL/dtheta
+// is the upper-right block of exp([[x L, x dL], [0, x L]]) (C. Van Loan,
+// IEEE Trans. Autom. Control 23 (1978) 395).  dL/dtheta is the generator of a
+// model with theta = 1 and every other parameter 0 (same bonds).
+int build_k_table(lmpo_grad *G, std::vector<std::complex<double>> &Kh, std::vector<int> &ph) {
+  const lmpo_state *S = G->S;
+  const ModelHost &m = S->m;
+  const int nb = m.nb, N = m.N;
+  Kh.assign((size_t)nb * kGateSlots * kGradLocal * 256, 0.0);
+  ph.assign((size_t)nb * kGradLocal, -1);
+  using cd = std::complex<double>;
+  std::vector<cd> Lb(256), dL(256), B(1024), EB(1024), X(256), Ginv(256);
+  for (int b = 0; b < nb; ++b) {
+    const int i = m.bonds[2 * b], j = m.bonds[2 * b + 1];
+    bond_generator_pauli(m, b, Lb.data());
+    std::vector<std::pair<std::vector<double> ModelHost::*, int>> par;
+    std::vector<int> gidx;
+    std::vector<double> ModelHost::*keys[6] = {&ModelHost::hx, &ModelHost::hy, &ModelHost::hz,
+                                              &ModelHost::g0, &ModelHost::g1, &ModelHost::g2};
+    for (int s : {i, j})
+      for (int q = 0; q < 6; ++q) {
+        par.push_back({keys[q], s});
+        gidx.push_back(q * N + s);
+      }
+    par.push_back({&ModelHost::J, b});
+    gidx.push_back(6 * N + b);
+    par.push_back({&ModelHost::Jz, b});
+    gidx.push_back(6 * N + nb + b);
+    for (int p = 0; p < kGradLocal; ++p) ph[(size_t)b * kGradLocal + p] = gidx[p];
+    for (int slot : grad_slots(S)) {
+      const double x = gate_fraction(slot) * S->opt.tau;
+      for (int e = 0; e < 256; ++e) X[e] = -x * Lb[e];
+      if (!expm_pade13(16, X.data(), Ginv.data())) return fail(LMPO_ENUMERIC, "matrix exponential failed");
+      for (int p = 0; p < kGradLocal; ++p) {
+        ModelHost u = m;
+        for (auto *v : {&u.J, &u.Jz, &u.hx, &u.hy, &u.hz, &u.g0, &u.g1, &u.g2}) std::fill(v->begin(), v->end(), 0.0);
+        (u.*(par[p].first))[par[p].second] = 1.0;
+        bond_generator_pauli(u, b, dL.data());
+        std::fill(B.begin(), B.end(), cd(0.0));
+        for (int r = 0; r < 16; ++r)
+          for (int c = 0; c < 16; ++c) {
+            B[r * 32 + c] = B[(r + 16) * 32 + c + 16] = x * Lb[r * 16 + c];
+            B[r * 32 + c + 16] = x * dL[r * 16 + c];
+          }
+        if (!expm_pade13(32, B.data(), EB.data())) return fail(LMPO_ENUMERIC, "matrix exponential failed");
+        cd *Kp = &Kh[(((size_t)b * kGateSlots + slot) * kGradLocal + p) * 256];
+        for (int r = 0; r < 16; ++r)
+          for (int c = 0; c < 16; ++c) {
+            cd acc = 0.0;
+            for (int t = 0; t < 16; ++t) acc += EB[r * 32 + 16 + t] * Ginv[t * 16 + c];
+            Kp[r * 16 + c] = acc;
+          }
+      }
+    }
+  }
+  return LMPO_OK;
+}
+
+// Gamma of the co-state C and the recorded state (sites at `snap`, bond dims
+// rd) on sites (k, k + 1), into G->gam.  C->dims must be current on the host.
+void transition_density(lmpo_grad *G, int k, const char *snap, const int *rd) {
+  lmpo_state *S = G->S, *C = G->C;
+  const int N = S->N;
+  hipStream_t st = S->stream;
+  auto md = [&](int b) { return (b < 0 || b >= N - 1) ? 1 : C->dims[b]; };
+  auto qd = [&](int b) { return (b < 0 || b >= N - 1) ? 1 : rd[b]; };
+  auto rs = [&](int s) {
+    return reinterpret_cast<const double2 *>(snap + (reinterpret_cast<const char *>(S->site[s]) -
+                                                     reinterpret_cast<const char *>(S->site[0])));
+  };
+  auto gemm = [&](int M, int Nn, int K, const double2 *A, long long sam, long long sak, long long sab,
+                  const double2 *B, long long sbk, long long sbn, long long sbb, double2 *Cc, long long scm,
+                  long long scn, long long scb, int batch) {
+    ZgemmArgs g{M, Nn, K, A, sam, sak, sab, B, sbk, sbn, sbb, Cc, scm, scn, scb};
+    launch_zgemm(st, g, batch);
+  };
+  // left environment L[p][q] over sites < k
+  (void)hipMemcpyAsync(G->L, G->one, sizeof(double2), hipMemcpyDeviceToDevice, st);
+  for (int s = 0; s < k; ++s) {
+    const int pl = md(s - 1), pr = md(s), ql = qd(s - 1), qr = qd(s);
+    // W[p][(a q')] = sum_q L[p][q] r_s[q][(a q')]
+    gemm(pl, 4 * qr, ql, G->L, ql, 1, 0, rs(s), 4 * qr, 1, 0, G->W, 4 * qr, 1, 0, 1);
+    // L'[p'][q'] = sum_{(p a)} mu_s[(p a)][p'] W[(p a)][q']
+    gemm(pr, qr, 4 * pl, C->site[s], 1, pr, 0, G->W, qr, 1, 0, G->L, qr, 1, 0, 1);
+  }
+  // right environment R[p][q] over sites > k + 1
+  (void)hipMemcpyAsync(G->R, G->one, sizeof(double2), hipMemcpyDeviceToDevice, st);
+  for (int s = N - 1; s > k + 1; --s) {
+    const int pl = md(s - 1), pr = md(s), ql = qd(s - 1), qr = qd(s);
+    // W[(p a)][q'] = sum_{p'} mu_s[(p a)][p'] R[p'][q']
+    gemm(4 * pl, qr, pr, C->site[s], pr, 1, 0, G->R, qr, 1, 0, G->W, qr, 1, 0, 1);
+    // R'[p][q] = sum_{(a q')} W[p][(a q')] r_s[q][(a q')]
+    gemm(pl, ql, 4 * qr, G->W, 4 * qr, 1, 0, rs(s), 1, 4 * qr, 0, G->R, ql, 1, 0, 1);
+  }
+  const int pl = md(k - 1), pm = md(k), pr = md(k + 1), ql = qd(k - 1), qm = qd(k), qr = qd(k + 1);
+  // E[a][p'][(c q')] = sum_p mu_k[p][a][p'] sum_q L[p][q] r_k[q][(c q')]
+  gemm(pl, 4 * qm, ql, G->L, ql, 1, 0, rs(k), 4 * qm, 1, 0, G->W, 4 * qm, 1, 0, 1);
+  gemm(pm, 4 * qm, pl, C->site[k], 1, 4 * pm, pm, G->W, 4 * qm, 1, 0, G->E, 4 * qm, 1, (long long)pm * 4 * qm, 4);
+  // Fr[d][(p' b)][q'] = sum_{q''} (sum_{p''} mu_{k+1}[(p' b)][p''] R[p''][q'']) r_{k+1}[q'][d][q'']
+  gemm(4 * pm, qr, pr, C->site[k + 1], pr, 1, 0, G->R, qr, 1, 0, G->W, qr, 1, 0, 1);
+  gemm(4 * pm, qm, qr, G->W, qr, 1, 0, rs(k + 1), 1, 4 * qr, qr, G->Fr, qm, 1, (long long)4 * pm * qm, 4);
+  launch_transition_reduce(st, G->E, G->Fr, pm, qm, G->gam);
+}
+
+// mu_T = (o - F 1) / tr in the Pauli basis: per site the trace covector is
+// sqrt(2) e_1 and sigma^a's is sqrt(2) e_a; bond dimension 2 (a row on the
+// first site, block-diagonal inside, a column on the last).  Then an exact QR
+// sweep makes it left-orthonormal with the centre on the last site.
+int init_costate(lmpo_grad *G, int site, int a, std::complex<double> F, std::complex<double> tr) {
+  lmpo_state *C = G->C;
+  const int N = C->N;
+  const double r2 = std::sqrt(2.0);
+  std::vector<std::vector<double2>> host(N);
+  const std::complex<double> last_o = 1.0 / tr, last_w = -F / tr;
+  for (int s = 0; s < N; ++s) {
+    const int nl = s == 0 ? 1 : 2, nr = s == N - 1 ? 1 : 2;
+    host[s].assign((size_t)nl * 4 * nr, make_double2(0.0, 0.0));
+    const int ao = s == site ? a : 0;  // local index carried by o's path
+    auto at = [&](int l, int q, int r) -> double2 & { return host[s][((size_t)l * 4 + q) * nr + r]; };
+    if (s == 0) {
+      at(0, ao, 0) = make_double2(r2, 0.0);
+      at(0, 0, 1) = make_double2(r2, 0.0);
+    } else if (s == N - 1) {
+      at(0, ao, 0) = make_double2(r2 * last_o.real(), r2 * last_o.imag());
+      at(1, 0, 0) = make_double2(r2 * last_w.real(), r2 * last_w.imag());
+    } else {
+      at(0, ao, 0) = make_double2(r2, 0.0);
+      at(1, 0, 1) = make_double2(r2, 0.0);
+    }
+  }
+  for (int s = 0; s < N; ++s)
+    HIP_TRY(hipMemcpyAsync(C->site[s], host[s].data(), host[s].size() * sizeof(double2), hipMemcpyHostToDevice,
+                           C->stream));
+  std::fill(C->dims.begin(), C->dims.end(), 2);
+  HIP_TRY(hipMemcpyAsync(C->d_dims, C->dims.data(), (N - 1) * sizeof(int), hipMemcpyHostToDevice, C->stream));
+  HIP_TRY(hipStreamSynchronize(C->stream));
+  C->centre = 0;
+  return move_centre(C, N - 1);
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t lmpo_grad_arena_bytes(lmpo_state *S, int32_t n_steps, int32_t costate_chi_max, double costate_cutoff) {
+  lmpo_options co_opt;
+  if (grad_check(S, n_steps, costate_chi_max, costate_cutoff, &co_opt)) return 0;
+  const size_t co = costate_bytes(S, co_opt);
+  if (co == 0) return 0;
+  lmpo_grad tmp;
+  tmp.S = S;
+  char *dummy = nullptr;
+  return grad_layout(&tmp, S, n_steps, co_opt, nullptr, 0, &dummy, co) + 256;
+}
+
+int lmpo_grad_create(lmpo_state *S, int32_t n_steps, int32_t costate_chi_max, double costate_cutoff,
+                     void *device_arena, size_t arena_bytes, lmpo_grad **out) {
+  if (!out) return fail(LMPO_EINVAL, "out is null");
+  *out = nullptr;
+  lmpo_options co_opt;
+  int rc = grad_check(S, n_steps, costate_chi_max, costate_cutoff, &co_opt);
+  if (rc) return rc;
+  if (!device_arena) return fail(LMPO_EINVAL, "device_arena is null");
+  if (reinterpret_cast<uintptr_t>(device_arena) % 256) return fail(LMPO_EINVAL, "device_arena must be 256-byte aligned");
+  const size_t co = costate_bytes(S, co_opt);
+  if (co == 0) return LMPO_EINVAL;
+  lmpo_grad *G = new lmpo_grad();
+  G->S = S;
+  G->n_steps = n_steps;
+  char *co_arena = nullptr;
+  const size_t need =
+      grad_layout(G, S, n_steps, co_opt, reinterpret_cast<char *>(device_arena), arena_bytes, &co_arena, co);
+  if (need > arena_bytes) {
+    delete G;
+    return fail(LMPO_ENOMEM, "gradient arena too small: need " + std::to_string(need) + " bytes");
+  }
+  G->ckpt_centre.assign(n_steps + 1, 0);
+  auto bail = [&](int code) {
+    delete G;
+    return code;
+  };
+  // co-state: same model and controls, its gate table replaced by the transposes
+  lmpo_model mv = model_view(S->m);
+  if ((rc = lmpo_create(&mv, &co_opt, "+z", co_arena, co, S->stream, &G->C))) return bail(rc);
+  std::vector<double2> gt(S->gates_host.size());
+  for (size_t g = 0; g < gt.size() / 256; ++g)
+    for (int r = 0; r < 16; ++r)
+      for (int c = 0; c < 16; ++c) {
+        const std::complex<double> v = S->gates_host[g * 256 + c * 16 + r];
+        gt[g * 256 + r * 16 + c] = make_double2(v.real(), v.imag());
+      }
+  std::vector<std::complex<double>> Kh;
+  std::vector<int> ph;
+  if ((rc = build_k_table(G, Kh, ph))) return bail(rc);
+  const double2 one = make_double2(1.0, 0.0);
+  hipError_t e = hipMemcpyAsync(G->C->d_gates, gt.data(), gt.size() * sizeof(double2), hipMemcpyHostToDevice,
+                                S->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(G->K, Kh.data(), Kh.size() * sizeof(double2), hipMemcpyHostToDevice, S->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(G->pidx, ph.data(), ph.size() * sizeof(int), hipMemcpyHostToDevice, S->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(G->one, &one, sizeof(double2), hipMemcpyHostToDevice, S->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(S->stream);
+  if (e != hipSuccess) return bail(fail(LMPO_EHIP, std::string("gradient setup: ") + hipGetErrorString(e)));
+  *out = G;
+  return LMPO_OK;
+}
+
+int lmpo_grad_run(lmpo_grad *G, int32_t site, char pauli, double F_out[2], double *grad_out) {
+  if (!G || !F_out || !grad_out) return fail(LMPO_EINVAL, "null argument");
+  lmpo_state *S = G->S, *C = G->C;
+  const int N = S->N, T = G->n_steps;
+  const int a = pauli_index(pauli);
+  if (site < 0 || site >= N) return fail(LMPO_EINVAL, "site index out of range");
+  if (a <= 0) return fail(LMPO_EINVAL, "pauli must be one of X, Y, Z");
+  hipStream_t st = S->stream;
+  const long long step0 = S->step_index;
+  int rc;
+  HIP_TRY(hipMemsetAsync(G->grad, 0, (size_t)G->P * sizeof(double2), st));
+  // forward, one snapshot per step start (and one of the final state)
+  for (int n = 0; n < T; ++n) {
+    if ((rc = save_snapshot(S, G->ckpt + (size_t)n * G->snap))) return rc;
+    G->ckpt_centre[n] = S->centre;
+    if ((rc = one_step(S, step0 + n))) return rc;
+    if (S->opt.force_trace) HIP_TRY(hipMemcpyAsync(G->traces + n, S->tr, sizeof(double2), hipMemcpyDeviceToDevice, st));
+  }
+  if ((rc = save_snapshot(S, G->ckpt + (size_t)T * G->snap))) return rc;
+  G->ckpt_centre[T] = S->centre;
+  // the replays below add to these; the forward run's values are restored at the end
+  HIP_TRY(hipMemcpyAsync(G->disc_save, S->disc, sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIP_TRY(hipMemcpyAsync(G->stats_save, S->stats, kStats * sizeof(int), hipMemcpyDeviceToDevice, st));
+  // F = <sigma^a_site> and tr(rho_T)
+  double fo[2];
+  if ((rc = run_measure(S, {site, a, -1, 0}, fo))) return rc;
+  launch_trace(st, S->d_sites, S->d_dims, N, S->tr);
+  double2 trT;
+  HIP_TRY(hipMemcpyAsync(&trT, S->tr, sizeof(double2), hipMemcpyDeviceToHost, st));
+  std::vector<double2> tr_host(T, make_double2(1.0, 0.0));
+  if (S->opt.force_trace)
+    HIP_TRY(hipMemcpyAsync(tr_host.data(), G->traces, T * sizeof(double2), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  const std::complex<double> F(fo[0], fo[1]), trc(trT.x, trT.y);
+  if (!(std::abs(trc) > 0) || !std::isfinite(std::abs(trc))) return fail(LMPO_ENUMERIC, "trace is zero or non-finite");
+  if ((rc = init_costate(G, site, a, F, trc))) return rc;
+  // backward
+  std::complex<double> scale = 1.0;
+  std::vector<int> rd;
+  for (int n = T - 1; n >= 0; --n) {
+    if ((rc = load_snapshot(S, G->ckpt + (size_t)n * G->snap))) return rc;
+    S->centre = G->ckpt_centre[n];
+    G->rec.ops.clear();
+    S->rec = &G->rec;
+    rc = one_step(S, step0 + n);
+    S->rec = nullptr;
+    if (rc) return rc;
+    const int nops = (int)G->rec.ops.size();
+    rd.assign((size_t)nops * (N - 1), 1);
+    for (int i = 0; i < nops; ++i)
+      HIP_TRY(hipMemcpyAsync(&rd[(size_t)i * (N - 1)], G->rec.slots + (size_t)i * G->rec.stride +
+                             snapshot_dims_offset(S), (N - 1) * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    scale /= std::complex<double>(tr_host[n].x, tr_host[n].y);
+    for (int i = nops - 1; i >= 0; --i) {
+      const OpRecord &op = G->rec.ops[i];
+      if (op.bond < 0) {
+        if ((rc = apply_gate_dev(C, op.k, C->d_swap, op.asc ? 0 : 1))) return rc;
+        continue;
+      }
+      if ((rc = sync_dims(C))) return rc;
+      transition_density(G, op.k, G->rec.slots + (size_t)i * G->rec.stride, &rd[(size_t)i * (N - 1)]);
+      const size_t kb = ((size_t)op.bond * kGateSlots + op.slot) * kGradLocal;
+      launch_grad_accumulate(st, G->K + kb * 256, G->pidx + (size_t)op.bond * kGradLocal, kGradLocal, G->gam,
+                             make_double2(scale.real(), scale.imag()), G->grad);
+      HIP_TRY(hipGetLastError());
+      if ((rc = apply_gate_dev(C, op.k, gate_ptr(C, op.bond, op.slot), op.asc ? 0 : 1))) return rc;
+    }
+  }
+  // the state as after the forward run
+  if ((rc = load_snapshot(S, G->ckpt + (size_t)T * G->snap))) return rc;
+  S->centre = G->ckpt_centre[T];
+  S->step_index = step0 + T;
+  HIP_TRY(hipMemcpyAsync(S->disc, G->disc_save, sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIP_TRY(hipMemcpyAsync(S->stats, G->stats_save, kStats * sizeof(int), hipMemcpyDeviceToDevice, st));
+  std::vector<double2> gh(G->P);
+  HIP_TRY(hipMemcpyAsync(gh.data(), G->grad, (size_t)G->P * sizeof(double2), hipMemcpyDeviceToHost, st));
+  HIP_TRY(hipStreamSynchronize(st));
+  if ((rc = sync_dims(S))) return rc;
+  if ((rc = check_err(S)) || (rc = check_err(C))) return rc;
+  F_out[0] = fo[0];
+  F_out[1] = fo[1];
+  for (int p = 0; p < G->P; ++p) {
+    if (!std::isfinite(gh[p].x)) return fail(LMPO_ENUMERIC, "non-finite gradient");
+    grad_out[p] = gh[p].x;
+  }
+  return LMPO_OK;
+}
+
+int lmpo_grad_costate_dims(lmpo_grad *G, int32_t *out) {
+  if (!G || !out) return fail(LMPO_EINVAL, "null argument");
+  return lmpo_bond_dims(G->C, out);
+}
+
+int lmpo_grad_destroy(lmpo_grad *G) {
+  if (!G) return LMPO_OK;
+  hipError_t e = hipStreamSynchronize(G->S->stream);
+  delete G;
+  if (e != hipSuccess) return fail(LMPO_EHIP, std::string("destroy: ") + hipGetErrorString(e));
   return LMPO_OK;
 }
 

@@ -112,4 +112,21 @@ void launch_scale_site(hipStream_t s, double2 *const *sites, const int *dims, in
 void launch_hermitian_sum_site(hipStream_t s, const double2 *src, double2 *dst, const int *dims, int N, int k);
 void launch_double_dims(hipStream_t s, int *dims, int n);
 
+// ---- adjoint gradient (grad.hip) ----
+// C(m, n) = sum_k A(m, k) B(k, n) per batch z; element (m, k) of A at
+// A[m * sam + k * sak + z * sab], likewise for B and C.
+struct ZgemmArgs {
+  int M, N, K;
+  const double2 *A;
+  long long sam, sak, sab;
+  const double2 *B;
+  long long sbk, sbn, sbb;
+  double2 *C;
+  long long scm, scn, scb;
+};
+void launch_zgemm(hipStream_t s, const ZgemmArgs &g, int batch);
+void launch_transition_reduce(hipStream_t s, const double2 *E, const double2 *Fr, int pm, int qm, double2 *gam);
+void launch_grad_accumulate(hipStream_t s, const double2 *K, const int *pidx, int nk, const double2 *gam,
+                            double2 scale, double2 *grad);
+
 }  // namespace lmpo

@@ -69,6 +69,7 @@ EXPORTS = [
     "lmpo_batch_arena_bytes", "lmpo_batch_create", "lmpo_batch_evolve_step", "lmpo_batch_sync",
     "lmpo_batch_plan", "lmpo_batch_profile_begin", "lmpo_batch_profile_end", "lmpo_batch_destroy",
     "lmpo_batch_set_autotune", "lmpo_autotune_table",
+    "lmpo_grad_arena_bytes", "lmpo_grad_create", "lmpo_grad_run", "lmpo_grad_costate_dims", "lmpo_grad_destroy",
 ]
 
 
@@ -126,6 +127,11 @@ def load_library(path: str = LIB_PATH):
         "lmpo_batch_destroy": (ctypes.c_int, [P]),
         "lmpo_batch_set_autotune": (ctypes.c_int, [P, i32]),
         "lmpo_autotune_table": (ctypes.c_int, [i32, pi32, pi32, pi32, pdbl, pi32]),
+        "lmpo_grad_arena_bytes": (ctypes.c_size_t, [P, i32, i32, dbl]),
+        "lmpo_grad_create": (ctypes.c_int, [P, i32, i32, dbl, P, ctypes.c_size_t, ctypes.POINTER(P)]),
+        "lmpo_grad_costate_dims": (ctypes.c_int, [P, pi32]),
+        "lmpo_grad_run": (ctypes.c_int, [P, i32, ctypes.c_char, pdbl, pdbl]),
+        "lmpo_grad_destroy": (ctypes.c_int, [P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -360,9 +366,74 @@ class Chain:
         _check(self._lib.lmpo_profile_end(self._h, _dptr(out)))
         return int(out[0]), float(out[1]), float(out[2])
 
+    def gradient(self, n_steps, site, pauli, costate_chi_max=0, costate_cutoff=-1.0):
+        """Advance n_steps and return (F, {key: dF/dtheta}) for F = <sigma^pauli_site>
+        at the end (lmpo_grad_run); keys hx, hy, hz, g0, g1, g2 (per qubit), J, Jz
+        (per bond).  The co-state takes the chain's chi_max / cutoff unless given."""
+        g = Gradient(self, n_steps, costate_chi_max, costate_cutoff)
+        try:
+            return g.run(site, pauli)
+        finally:
+            g.close()
+
     def close(self):
         if getattr(self, "_h", None):
             _check(self._lib.lmpo_destroy(self._h))
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+GRAD_SITE_KEYS = ("hx", "hy", "hz", "g0", "g1", "g2")
+GRAD_BOND_KEYS = ("J", "Jz")
+
+
+class Gradient:
+    """Adjoint-gradient workspace of one chain for a fixed number of steps
+    (lmpo_grad_*).  Each run() advances the chain by those steps."""
+
+    def __init__(self, chain, n_steps, costate_chi_max=0, costate_cutoff=-1.0):
+        import torch
+
+        lib = load_library()
+        self.chain, self.n_steps = chain, int(n_steps)
+        co = (int(costate_chi_max), float(costate_cutoff))
+        n = lib.lmpo_grad_arena_bytes(chain._h, self.n_steps, *co)
+        if n == 0:
+            raise LmpoError(-1, lib.lmpo_last_error().decode())
+        self.arena = torch.empty(n + 256, dtype=torch.uint8, device=chain.arena.device)
+        base = self.arena.data_ptr()
+        off = (-base) % 256
+        h = ctypes.c_void_p()
+        _check(lib.lmpo_grad_create(chain._h, self.n_steps, *co, ctypes.c_void_p(base + off), ctypes.c_size_t(n),
+                                    ctypes.byref(h)))
+        self._h = h
+        self._lib = lib
+        self.n_bonds = len(chain._m.bonds)
+
+    def run(self, site, pauli):
+        N, nb = self.chain.N, self.n_bonds
+        F = np.zeros(2)
+        g = np.zeros(6 * N + 2 * nb)
+        _check(self._lib.lmpo_grad_run(self._h, int(site), pauli.upper().encode()[:1], _dptr(F), _dptr(g)))
+        out = {k: g[q * N:(q + 1) * N].copy() for q, k in enumerate(GRAD_SITE_KEYS)}
+        out["J"] = g[6 * N:6 * N + nb].copy()
+        out["Jz"] = g[6 * N + nb:].copy()
+        return complex(F[0], F[1]), out
+
+    def costate_dims(self):
+        """Bond dims of the co-state (after run(): at time 0)."""
+        out = np.zeros(self.chain.N - 1, dtype=np.int32)
+        _check(self._lib.lmpo_grad_costate_dims(self._h, _iptr(out)))
+        return out.tolist()
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _check(self._lib.lmpo_grad_destroy(self._h))
             self._h = None
 
     def __del__(self):

@@ -61,3 +61,17 @@ def test_arena_size_and_argument_errors_on_host():
     lone["J"], lone["Jz"] = lad["J"][: len(lone["bonds"])], lad["Jz"][: len(lone["bonds"])]
     with pytest.raises(lmpo.LmpoError, match="belong to a bond"):
         lmpo.arena_bytes(lone, 0.1, 8)
+
+
+def test_gradient_entry_points_reject_bad_arguments_on_host():
+    """The gradient workspace calls validate their arguments before any GPU work."""
+    from paper_2203_05871_amd import lmpo
+
+    lib = lmpo.load_library()
+    assert lib.lmpo_grad_arena_bytes(None, 4, 0, -1.0) == 0
+    assert b"state is null" in lib.lmpo_last_error()
+    out = ctypes.c_void_p()
+    assert lib.lmpo_grad_create(None, 4, 0, -1.0, None, 0, ctypes.byref(out)) == -1
+    assert lib.lmpo_grad_costate_dims(None, None) == -1
+    assert lib.lmpo_grad_run(None, 0, b"Z", None, None) == -1
+    assert lib.lmpo_grad_destroy(None) == 0
