@@ -20,6 +20,8 @@ bonds sit at chi_max = 256 after two steps, timed over two steps once settled
 real-arithmetic Pauli-basis form (opt-in, exact because every propagator is
 real in that basis) is timed the same way and reported on its own
 (`real_steps_per_s`, with its observable difference to the complex FP64 run).
+`gradient` times the adjoint parameter gradients of one observable on the
+2 x 8 ladder against that ladder's forward run (gradient_leg).
 """
 from __future__ import annotations
 
@@ -222,6 +224,91 @@ def bench_batch(args):
     print(json.dumps(line), flush=True)
 
 
+def gradient_leg(cpu_budget, no_cpu):
+    """Adjoint parameter gradients on the 2 x 8 ladder (N=16, 22 bonds: 8 rungs
+    and 14 legs through the SWAP network), chi_max 128, cutoff 1e-12, tau 0.05,
+    40 steps from +z: F = <sigma^z_1>(T) and all 6N + 2 n_bonds = 140
+    derivatives in one lmpo_grad_run (state forward, replay, co-state
+    backward), against the forward run alone; central differences of the GPU
+    forward (h = 1e-5) on a few parameters as a check."""
+    import numpy as np
+    import torch
+
+    import workloads
+    from paper_2203_05871_amd import Chain, Gradient
+
+    m, run = workloads.ladder2x8()
+    tau, steps, chi, cut, init = run["tau"], run["steps"], run["chi_max"], run["cutoff"], run["init"]
+    site, pauli = 1, "Z"
+
+    def forward(model):
+        c = Chain(model, tau, chi, cut, "fp64", init, device="cuda:0")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c.evolve(steps)
+        c.sync()
+        dt = time.perf_counter() - t0
+        v = c.measure_1q([site], pauli)[0].real
+        c.close()
+        return v, dt
+
+    forward(m)  # warm-up (module load, first launches)
+    F0, tf = forward(m)
+    c = Chain(m, tau, chi, cut, "fp64", init, device="cuda:0")
+    G = Gradient(c, steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    F, g = G.run(site, pauli)
+    tg = time.perf_counter() - t0
+    co_dims, st_dims = G.costate_dims(), c.bond_dims()
+    G.close()
+    c.close()
+    fd = {}
+    for key, idx in (("hx", 0), ("hz", 1), ("J", 5), ("g0", 1)):
+        vals = []
+        for sgn in (1.0, -1.0):
+            mm = {k: (np.array(v, dtype=float) if k != "bonds" and isinstance(v, np.ndarray) else v)
+                  for k, v in m.items()}
+            mm[key][idx] += sgn * 1e-5
+            vals.append(forward(mm)[0])
+        fd[f"{key}[{idx}]"] = {"adjoint": float(g[key][idx]), "central_difference": (vals[0] - vals[1]) / 2e-5}
+    gmax = max(float(np.abs(v).max()) for v in g.values())
+    out = {"workload": "2x8 ladder (N=16, 8 rungs + 14 legs via SWAP gates), chi_max=128, cutoff=1e-12, tau=0.05, "
+                       "40 steps from +z; F = <sigma^z_1>(T); co-state with the same chi_max and cutoff",
+           "parameters": int(sum(len(v) for v in g.values())), "seconds": tg, "forward_seconds": tf,
+           "gradient_over_forward": tg / tf, "F": F.real, "F_forward_only": F0, "max_abs_gradient": gmax,
+           "state_bond_dims_T": st_dims, "costate_bond_dims_t0": co_dims,
+           "fd_check_h1e-5": fd,
+           "fd_max_abs_diff": max(abs(v["adjoint"] - v["central_difference"]) for v in fd.values())}
+    print(f"# gradient: {tg:.1f} s vs forward {tf:.2f} s", file=sys.stderr, flush=True)
+    if not no_cpu:
+        # oracle on a bounded sample: the whole gradient after the first n
+        # steps, n doubling while the budget lasts; the GPU runs the same n
+        from oracle import adjoint
+
+        n, dt, t_all = 0, 0.0, time.perf_counter()
+        while n < steps and time.perf_counter() - t_all < cpu_budget:
+            nn = 1 if n == 0 else min(2 * n, steps)
+            t0 = time.perf_counter()
+            adjoint.gradient(m, tau, nn, chi, cut, init, site, pauli)
+            n, dt = nn, time.perf_counter() - t0
+        c = Chain(m, tau, chi, cut, "fp64", init, device="cuda:0")
+        G = Gradient(c, n)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        G.run(site, pauli)
+        tgn = time.perf_counter() - t0
+        G.close()
+        c.close()
+        out["cpu_baseline"] = {"value": n / dt, "unit": "gradient steps/s (forward + backward)",
+                               "cores": blas_threads(), "kind": "oracle",
+                               "sample": f"the gradient after the first {n} of the 40 steps"}
+        out["gpu_same_sample"] = {"value": n / tgn, "unit": "gradient steps/s (forward + backward)",
+                                  "seconds": tgn}
+        out["gpu_steps_per_s"] = steps / tg
+    return out
+
+
 def cpu_baseline(model, run, steps, budget_s, threads=None):
     """The FP64 oracle on the host cores: as many of the same steps as fit in
     the time budget (a bounded sample of the same trajectory); `threads`
@@ -296,13 +383,14 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=25.0, help="seconds of oracle time for cpu_baseline")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--init", default="+x")
-    ap.add_argument("--workload", choices=["chain30", "chains64"], default="chain30",
+    ap.add_argument("--workload", choices=["chain30", "chains64", "ladder_grad"], default="chain30",
                     help="chain30: N=30 chain at chi_max=256 (headline); chains64: 64 uneven chains, batched form")
     ap.add_argument("--no-sequential", action="store_true", help="chains64: skip the sequential single-chain run")
     ap.add_argument("--no-saturated", action="store_true", help="chain30: skip the cutoff-0 run at chi = 256")
     ap.add_argument("--no-real", action="store_true", help="chain30: skip the real-arithmetic form")
     ap.add_argument("--no-variants", action="store_true",
                     help="chain30: skip the +z variant and the per-step chi profiles")
+    ap.add_argument("--no-gradient", action="store_true", help="chain30: skip the adjoint-gradient leg (2x8 ladder)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also run one plain device-to-device copy of MIB MiB (the calibration kernel of "
                          "the FETCH_SIZE / WRITE_SIZE counters)")
@@ -345,6 +433,15 @@ def main():
         if args.steps is None:
             args.steps = 40
         return bench_batch(args)
+    if args.workload == "ladder_grad":
+        g = gradient_leg(args.cpu_budget, args.no_cpu)
+        line = {"metric": "adjoint gradients (140 parameters) per second, 2x8 ladder", "value": 1.0 / g["seconds"],
+                "unit": "gradients/s", "n_gpus": 1, "steps": 40, "warmup": 1,
+                "ms_per_step": 1e3 * g["seconds"] / 40, "higher_is_better": True, "scaling": "weak",
+                "vs_baseline": None, "dtype": "f64", "data": "synthetic (the 2x8 ladder model, no dataset)",
+                "config": {"workload": g["workload"]}, "gradient": g}
+        print(json.dumps(line), flush=True)
+        return
     if args.steps is None:
         args.steps = 50
     model, run = workloads.chain30_jittered(args.init)
@@ -426,6 +523,8 @@ def main():
             line["obs_err_fp64_vs_oracle"] = float(np.abs(ref - obs).max())
             if "fp32" in res:
                 line["obs_err_fp32_vs_oracle"] = float(np.abs(res["fp32"]["obs"] - obs).max())
+    if not args.no_gradient:
+        line["gradient"] = gradient_leg(args.cpu_budget, args.no_cpu)
     print(json.dumps(line), flush=True)
 
 

@@ -340,7 +340,8 @@ int lmpo_batch_destroy(lmpo_batch *b);
  *
  * A workspace serves one state and a fixed number of steps.  It holds the
  * co-state (a state of the same model and controls, its gate table
- * transposed), a snapshot of the state at the start of every step, the gate
+ * transposed, in the real-arithmetic form: the co-state of a Hermitian
+ * observable is real in the Pauli basis, as every propagator is), a snapshot of the state at the start of every step, the gate
  * outputs of one step (the step is replayed from its snapshot during the
  * backward pass) and the environments; lmpo_grad_arena_bytes gives its size
  * (device memory, 256-byte aligned, caller-owned, bounded by (n_steps + 1 +

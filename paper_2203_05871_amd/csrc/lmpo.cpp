@@ -1825,6 +1825,10 @@ int grad_check(const lmpo_state *S, int n_steps, int co_chi, double co_cut, lmpo
     return fail(LMPO_EUNSUPPORTED, "the gradient does not pass through the Hermitian part");
   if (!std::isfinite(co_cut)) return fail(LMPO_EINVAL, "costate_cutoff must be finite");
   *co_opt = S->opt;
+  // The co-state of a Hermitian observable has real coefficients in the
+  // Pauli basis, where every propagator (and so its transpose) is real: it
+  // runs in the real-arithmetic form whatever the state's precision.
+  co_opt->precision = LMPO_FP64_REAL;
   if (co_chi > 0) co_opt->chi_max = co_chi;
   if (co_cut >= 0) co_opt->cutoff = co_cut;
   if (co_opt->chi_max < 2) return fail(LMPO_EUNSUPPORTED, "the co-state needs chi_max >= 2 (it starts at bond 2)");
@@ -1951,7 +1955,8 @@ int init_costate(lmpo_grad *G, int site, int a, std::complex<double> F, std::com
   const int N = C->N;
   const double r2 = std::sqrt(2.0);
   std::vector<std::vector<double2>> host(N);
-  const std::complex<double> last_o = 1.0 / tr, last_w = -F / tr;
+  // real form: F and tr are real up to round-off, which is dropped
+  const std::complex<double> last_o = 1.0 / tr.real(), last_w = -F.real() / tr.real();
   for (int s = 0; s < N; ++s) {
     const int nl = s == 0 ? 1 : 2, nr = s == N - 1 ? 1 : 2;
     host[s].assign((size_t)nl * 4 * nr, make_double2(0.0, 0.0));
@@ -2025,10 +2030,8 @@ int lmpo_grad_create(lmpo_state *S, int32_t n_steps, int32_t costate_chi_max, do
   std::vector<double2> gt(S->gates_host.size());
   for (size_t g = 0; g < gt.size() / 256; ++g)
     for (int r = 0; r < 16; ++r)
-      for (int c = 0; c < 16; ++c) {
-        const std::complex<double> v = S->gates_host[g * 256 + c * 16 + r];
-        gt[g * 256 + r * 16 + c] = make_double2(v.real(), v.imag());
-      }
+      for (int c = 0; c < 16; ++c)  // transposed; real (its imaginary parts are round-off)
+        gt[g * 256 + r * 16 + c] = make_double2(S->gates_host[g * 256 + c * 16 + r].real(), 0.0);
   std::vector<std::complex<double>> Kh;
   std::vector<int> ph;
   if ((rc = build_k_table(G, Kh, ph))) return bail(rc);

@@ -515,3 +515,52 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def _expectation_function():
+    import torch
+
+    class ExpectationFn(torch.autograd.Function):
+        """F = Re <sigma^pauli_site>(T) as a differentiable function of the model
+        parameters: the forward pass runs lmpo_grad_run (state forward, co-state
+        backward) and keeps the gradient, the backward pass scales it."""
+
+        @staticmethod
+        def forward(ctx, spec, *params):
+            model = {"N": spec["N"], "bonds": spec["bonds"]}
+            for key, t in zip(GRAD_SITE_KEYS + GRAD_BOND_KEYS, params):
+                model[key] = t.detach().to("cpu", torch.float64).numpy().reshape(-1)
+            ch = Chain(model, spec["tau"], spec["chi_max"], spec.get("cutoff", 0.0), spec.get("precision", "fp64"),
+                       spec.get("init", "+z"), force_trace=spec.get("force_trace", True),
+                       order=spec.get("order", 2), device=spec.get("device", "cuda:0"))
+            try:
+                F, g = ch.gradient(spec["steps"], spec["site"], spec["pauli"], spec.get("costate_chi_max", 0),
+                                   spec.get("costate_cutoff", -1.0))
+            finally:
+                ch.close()
+            grads = [torch.as_tensor(g[k], dtype=p.dtype, device=p.device).reshape(p.shape)
+                     for k, p in zip(GRAD_SITE_KEYS + GRAD_BOND_KEYS, params)]
+            ctx.save_for_backward(*grads)
+            return torch.tensor(F.real, dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, gout):
+            return (None,) + tuple(gout.to(g.dtype) * g for g in ctx.saved_tensors)
+
+    return ExpectationFn
+
+
+_EXPECTATION_FN = None
+
+
+def expectation(spec, params):
+    """Differentiable F = Re <sigma^pauli_site> after spec["steps"] steps.
+
+    spec: N, bonds, tau, steps, chi_max, site, pauli and optionally cutoff,
+    precision, init, force_trace, order, costate_chi_max, costate_cutoff,
+    device.  params: tensors hx, hy, hz, g0, g1, g2 (length N) and J, Jz
+    (length n_bonds); the result's backward fills their .grad."""
+    global _EXPECTATION_FN
+    if _EXPECTATION_FN is None:
+        _EXPECTATION_FN = _expectation_function()
+    return _EXPECTATION_FN.apply(spec, *[params[k] for k in GRAD_SITE_KEYS + GRAD_BOND_KEYS])
