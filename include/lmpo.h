@@ -320,14 +320,15 @@ int lmpo_batch_profile_end(lmpo_batch *b, double out[3]);
 int lmpo_batch_destroy(lmpo_batch *b);
 
 /* ---- Parameter gradients (adjoint form) ----------------------------------
- * Derivatives of a final-time expectation value F = Tr(sigma^a_i rho_T) /
- * Tr(rho_T) (Eq. mu) with respect to every model parameter, by the adjoint
+ * Derivatives of a final-time expectation value F = Tr(O rho_T) / Tr(rho_T),
+ * O a Pauli string (sigma^a_i of Eq. mu, the correlators of Eq. 2Qdef, or any
+ * longer product), with respect to every model parameter, by the adjoint
  * (co-state) method.  Every bond generator L_b is linear in each parameter
  * theta, and the derivative of the gate exp(x L_b) is K exp(x L_b) with K =
  * (d/dtheta exp(x L_b)) exp(-x L_b), so the derivative of the Trotter product
  * is sum over gates g of s_g <mu_g, K_g rho_g>: rho_g the state after gate g,
  * mu_g the co-state after it (mu_T = (o - F 1)/Tr(rho_T), o and 1 the
- * covectors of sigma^a_i and of the trace, carried back by the transposed
+ * covectors of O and of the trace, both products, carried back by the transposed
  * gates, SWAP gates included), s_g the inverse product of the traces divided
  * out at the ends of the steps from g's own step on, and <mu, K rho> the trace
  * of K with the two-site transition density of the two MPS.  The co-state is
@@ -364,11 +365,13 @@ int lmpo_grad_create(lmpo_state *s, int32_t n_steps, int32_t costate_chi_max, do
 
 /* Advances the state by the workspace's n_steps exactly as lmpo_evolve_step
  * would (same results; the discarded weight and the statistics count the
- * forward run only) and returns F = <sigma^pauli_site>(T) as (re, im) and
- * grad_out[p] = d Re F / d theta_p for the 6 n_qubits + 2 n_bonds parameters
- * in the order hx[0..N-1], hy, hz, g0, g1, g2, J[0..n_bonds-1], Jz.
- * pauli is 'X', 'Y' or 'Z'.  Synchronises (once per co-state gate). */
-int lmpo_grad_run(lmpo_grad *g, int32_t site, char pauli, double F[2], double *grad_out);
+ * forward run only) and returns F = <O>(T) as (re, im) and grad_out[p] =
+ * d Re F / d theta_p for the 6 n_qubits + 2 n_bonds parameters in the order
+ * hx[0..N-1], hy, hz, g0, g1, g2, J[0..n_bonds-1], Jz.  paulis: the string O,
+ * n_qubits characters of I, X, Y, Z (qubit 0 first), at least one not I.  F
+ * of one or two factors equals lmpo_measure_1q / _2q on the final state bit
+ * for bit.  Synchronises (once per co-state gate). */
+int lmpo_grad_run(lmpo_grad *g, const char *paulis, double F[2], double *grad_out);
 
 /* Bond dims of the co-state (n_qubits - 1 entries): after a run, those of
  * mu at time 0, the end of the backward pass.  Synchronises. */

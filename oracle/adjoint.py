@@ -3,8 +3,9 @@
 
 TEST INFRASTRUCTURE ONLY (see the package header).
 
-Objective: F = Tr(O rho_T) / Tr(rho_T) with O = sigma^a on one qubit
-(Eq. mu), after T Trotter steps from a fixed initial state.  Parameters: every
+Objective: F = Tr(O rho_T) / Tr(rho_T) with O a Pauli string (sigma^a on one
+qubit as in Eq. mu, a correlator as in Eq. 2Qdef, or a longer product), after
+T Trotter steps from a fixed initial state.  Parameters: every
 entry of hx, hy, hz, g0, g1, g2 (per qubit) and J, Jz (per bond) of the model
 of Sec. 2.1.  Each bond generator L_b is linear in every one of them (the
 Hamiltonian enters through a commutator, each rate multiplies its dissipator),
@@ -140,9 +141,15 @@ def forward_record(model, tau, steps, chi_max, cutoff, init, order=2, force_trac
 
 
 def costate(N, site, pauli, F, tr):
-    """MPS of mu_T = (o - F 1) / tr, bond dimension 2 (1 for N = 1 is not
-    needed: N >= 2), left-orthonormal with the centre on the last site."""
-    o = [tebd.covector(lm.PAULI[pauli]) if s == site else tebd.E_ID for s in range(N)]
+    """MPS of mu_T = (o - F 1) / tr for O = sigma^pauli on `site`."""
+    return costate_string(N, {site: pauli}, F, tr)
+
+
+def costate_string(N, ops, F, tr):
+    """MPS of mu_T = (o - F 1) / tr for the Pauli string O = prod_s ops[s]
+    ({site: 'X' | 'Y' | 'Z'}): bond dimension 2, left-orthonormal with the
+    centre on the last site."""
+    o = [tebd.covector(lm.PAULI[ops[s]]) if s in ops else tebd.E_ID for s in range(N)]
     w = [tebd.E_ID] * N
     A = []
     for s in range(N):
@@ -162,16 +169,21 @@ def costate(N, site, pauli, F, tr):
 
 
 def gradient(model, tau, steps, chi_max, cutoff, init, site, pauli, order=2, force_trace=True,
-             costate_chi_max=None, costate_cutoff=None):
+             costate_chi_max=None, costate_cutoff=None, paulis=None):
     """(F, {key: complex array of dF/dtheta}, final MPS) for O = sigma^pauli
-    on `site` (module header).  The co-state is truncated with chi_max and
+    on `site`, or for the Pauli string `paulis` (one of I, X, Y, Z per qubit)
+    when given (module header).  The co-state is truncated with chi_max and
     cutoff unless costate_chi_max / costate_cutoff are given."""
+    if paulis is not None:
+        ops = {s: p for s, p in enumerate(paulis.upper()) if p != "I"}
+    else:
+        ops = {site: pauli.upper()}
     chi_mu = chi_max if costate_chi_max is None else costate_chi_max
     cut_mu = cutoff if costate_cutoff is None else costate_cutoff
     N = model["N"]
     mps, records, traces = forward_record(model, tau, steps, chi_max, cutoff, init, order, force_trace)
-    F = mps.expect({site: lm.PAULI[pauli.upper()]})
-    mu = costate(N, site, pauli.upper(), F, mps.trace())
+    F = mps.expect({s: lm.PAULI[p] for s, p in ops.items()})
+    mu = costate_string(N, ops, F, mps.trace())
     gates = tebd.gate_tables(model, tau, order)
     P = lm.swap_gate()
     grads = {k: np.zeros(len(model[k]), dtype=np.complex128) for k in SITE_KEYS + BOND_KEYS}

@@ -1946,41 +1946,62 @@ void transition_density(lmpo_grad *G, int k, const char *snap, const int *rd) {
   launch_transition_reduce(st, G->E, G->Fr, pm, qm, G->gam);
 }
 
-// mu_T = (o - F 1) / tr in the Pauli basis: per site the trace covector is
-// sqrt(2) e_1 and sigma^a's is sqrt(2) e_a; bond dimension 2 (a row on the
-// first site, block-diagonal inside, a column on the last).  Then an exact QR
-// sweep makes it left-orthonormal with the centre on the last site.
-int init_costate(lmpo_grad *G, int site, int a, std::complex<double> F, std::complex<double> tr) {
+// mu_T = (o - F 1) / tr in the Pauli basis, o the covector of the Pauli
+// string a[0..N-1] (index 0 = identity): per site the trace covector is
+// sqrt(2) e_1 and sigma^a's is sqrt(2) e_a, so o and 1 are products and mu_T
+// has bond dimension 2 (a row on the first site, block-diagonal inside, a
+// column on the last).  Then an exact QR sweep makes it left-orthonormal
+// with the centre on the last site.  With `product` set, o alone (bond 1).
+int init_costate(lmpo_grad *G, const std::vector<int> &a, std::complex<double> F, std::complex<double> tr,
+                 bool product) {
   lmpo_state *C = G->C;
   const int N = C->N;
   const double r2 = std::sqrt(2.0);
   std::vector<std::vector<double2>> host(N);
   // real form: F and tr are real up to round-off, which is dropped
-  const std::complex<double> last_o = 1.0 / tr.real(), last_w = -F.real() / tr.real();
+  const double last_o = 1.0 / tr.real(), last_w = -F.real() / tr.real();
+  const int w = product ? 1 : 2;
   for (int s = 0; s < N; ++s) {
-    const int nl = s == 0 ? 1 : 2, nr = s == N - 1 ? 1 : 2;
+    const int nl = s == 0 ? 1 : w, nr = s == N - 1 ? 1 : w;
     host[s].assign((size_t)nl * 4 * nr, make_double2(0.0, 0.0));
-    const int ao = s == site ? a : 0;  // local index carried by o's path
     auto at = [&](int l, int q, int r) -> double2 & { return host[s][((size_t)l * 4 + q) * nr + r]; };
-    if (s == 0) {
-      at(0, ao, 0) = make_double2(r2, 0.0);
+    if (product) {
+      at(0, a[s], 0) = make_double2(r2, 0.0);
+    } else if (s == 0) {
+      at(0, a[s], 0) = make_double2(r2, 0.0);
       at(0, 0, 1) = make_double2(r2, 0.0);
     } else if (s == N - 1) {
-      at(0, ao, 0) = make_double2(r2 * last_o.real(), r2 * last_o.imag());
-      at(1, 0, 0) = make_double2(r2 * last_w.real(), r2 * last_w.imag());
+      at(0, a[s], 0) = make_double2(r2 * last_o, 0.0);
+      at(1, 0, 0) = make_double2(r2 * last_w, 0.0);
     } else {
-      at(0, ao, 0) = make_double2(r2, 0.0);
+      at(0, a[s], 0) = make_double2(r2, 0.0);
       at(1, 0, 1) = make_double2(r2, 0.0);
     }
   }
   for (int s = 0; s < N; ++s)
     HIP_TRY(hipMemcpyAsync(C->site[s], host[s].data(), host[s].size() * sizeof(double2), hipMemcpyHostToDevice,
                            C->stream));
-  std::fill(C->dims.begin(), C->dims.end(), 2);
+  std::fill(C->dims.begin(), C->dims.end(), w);
   HIP_TRY(hipMemcpyAsync(C->d_dims, C->dims.data(), (N - 1) * sizeof(int), hipMemcpyHostToDevice, C->stream));
   HIP_TRY(hipStreamSynchronize(C->stream));
   C->centre = 0;
-  return move_centre(C, N - 1);
+  return product ? LMPO_OK : move_centre(C, N - 1);
+}
+
+// <o, rho> for the Pauli string a on the state as it stands: o goes into the
+// co-state as a product (bond 1) and the transition density of the last bond,
+// traced with the identity, is the whole contraction.
+int string_expectation_numerator(lmpo_grad *G, const std::vector<int> &a, std::complex<double> &out) {
+  lmpo_state *S = G->S;
+  int rc = init_costate(G, a, 0.0, 1.0, true);
+  if (rc || (rc = sync_dims(S))) return rc;
+  transition_density(G, S->N - 2, reinterpret_cast<const char *>(S->site[0]), S->dims.data());
+  double2 gam[256];
+  HIP_TRY(hipMemcpyAsync(gam, G->gam, sizeof(gam), hipMemcpyDeviceToHost, S->stream));
+  HIP_TRY(hipStreamSynchronize(S->stream));
+  out = 0.0;
+  for (int x = 0; x < 16; ++x) out += std::complex<double>(gam[17 * x].x, gam[17 * x].y);
+  return LMPO_OK;
 }
 
 }  // namespace
@@ -2048,13 +2069,19 @@ int lmpo_grad_create(lmpo_state *S, int32_t n_steps, int32_t costate_chi_max, do
   return LMPO_OK;
 }
 
-int lmpo_grad_run(lmpo_grad *G, int32_t site, char pauli, double F_out[2], double *grad_out) {
-  if (!G || !F_out || !grad_out) return fail(LMPO_EINVAL, "null argument");
+int lmpo_grad_run(lmpo_grad *G, const char *paulis, double F_out[2], double *grad_out) {
+  if (!G || !paulis || !F_out || !grad_out) return fail(LMPO_EINVAL, "null argument");
   lmpo_state *S = G->S, *C = G->C;
   const int N = S->N, T = G->n_steps;
-  const int a = pauli_index(pauli);
-  if (site < 0 || site >= N) return fail(LMPO_EINVAL, "site index out of range");
-  if (a <= 0) return fail(LMPO_EINVAL, "pauli must be one of X, Y, Z");
+  if (std::strlen(paulis) != (size_t)N) return fail(LMPO_EINVAL, "paulis must hold one of I, X, Y, Z per qubit");
+  std::vector<int> a(N);
+  std::vector<int> req;  // the string as a 1Q / 2Q measurement request when it has one or two factors
+  for (int s = 0; s < N; ++s) {
+    a[s] = pauli_index(paulis[s]);
+    if (a[s] < 0) return fail(LMPO_EINVAL, "paulis must hold one of I, X, Y, Z per qubit");
+    if (a[s] > 0) req.insert(req.end(), {s, a[s]});
+  }
+  if (req.empty()) return fail(LMPO_EINVAL, "paulis must name at least one X, Y or Z");
   hipStream_t st = S->stream;
   const long long step0 = S->step_index;
   int rc;
@@ -2071,9 +2098,8 @@ int lmpo_grad_run(lmpo_grad *G, int32_t site, char pauli, double F_out[2], doubl
   // the replays below add to these; the forward run's values are restored at the end
   HIP_TRY(hipMemcpyAsync(G->disc_save, S->disc, sizeof(double), hipMemcpyDeviceToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->stats_save, S->stats, kStats * sizeof(int), hipMemcpyDeviceToDevice, st));
-  // F = <sigma^a_site> and tr(rho_T)
-  double fo[2];
-  if ((rc = run_measure(S, {site, a, -1, 0}, fo))) return rc;
+  // tr(rho_T) and F = <string> (one or two factors: the measurement kernels,
+  // as lmpo_measure_1q/2q; more: the transition density of o and rho_T)
   launch_trace(st, S->d_sites, S->d_dims, N, S->tr);
   double2 trT;
   HIP_TRY(hipMemcpyAsync(&trT, S->tr, sizeof(double2), hipMemcpyDeviceToHost, st));
@@ -2081,9 +2107,21 @@ int lmpo_grad_run(lmpo_grad *G, int32_t site, char pauli, double F_out[2], doubl
   if (S->opt.force_trace)
     HIP_TRY(hipMemcpyAsync(tr_host.data(), G->traces, T * sizeof(double2), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  const std::complex<double> F(fo[0], fo[1]), trc(trT.x, trT.y);
+  const std::complex<double> trc(trT.x, trT.y);
   if (!(std::abs(trc) > 0) || !std::isfinite(std::abs(trc))) return fail(LMPO_ENUMERIC, "trace is zero or non-finite");
-  if ((rc = init_costate(G, site, a, F, trc))) return rc;
+  double fo[2];
+  if (req.size() <= 4) {
+    if (req.size() == 2) req.insert(req.end(), {-1, 0});
+    if ((rc = run_measure(S, req, fo))) return rc;
+  } else {
+    std::complex<double> num;
+    if ((rc = string_expectation_numerator(G, a, num))) return rc;
+    const std::complex<double> f = num / trc;
+    fo[0] = f.real();
+    fo[1] = f.imag();
+  }
+  const std::complex<double> F(fo[0], fo[1]);
+  if ((rc = init_costate(G, a, F, trc, false))) return rc;
   // backward
   std::complex<double> scale = 1.0;
   std::vector<int> rd;

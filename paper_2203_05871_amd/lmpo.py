@@ -130,7 +130,7 @@ def load_library(path: str = LIB_PATH):
         "lmpo_grad_arena_bytes": (ctypes.c_size_t, [P, i32, i32, dbl]),
         "lmpo_grad_create": (ctypes.c_int, [P, i32, i32, dbl, P, ctypes.c_size_t, ctypes.POINTER(P)]),
         "lmpo_grad_costate_dims": (ctypes.c_int, [P, pi32]),
-        "lmpo_grad_run": (ctypes.c_int, [P, i32, ctypes.c_char, pdbl, pdbl]),
+        "lmpo_grad_run": (ctypes.c_int, [P, ctypes.c_char_p, pdbl, pdbl]),
         "lmpo_grad_destroy": (ctypes.c_int, [P]),
     }
     for name, (res, args) in sig.items():
@@ -366,13 +366,14 @@ class Chain:
         _check(self._lib.lmpo_profile_end(self._h, _dptr(out)))
         return int(out[0]), float(out[1]), float(out[2])
 
-    def gradient(self, n_steps, site, pauli, costate_chi_max=0, costate_cutoff=-1.0):
-        """Advance n_steps and return (F, {key: dF/dtheta}) for F = <sigma^pauli_site>
-        at the end (lmpo_grad_run); keys hx, hy, hz, g0, g1, g2 (per qubit), J, Jz
-        (per bond).  The co-state takes the chain's chi_max / cutoff unless given."""
+    def gradient(self, n_steps, site=None, pauli=None, paulis=None, costate_chi_max=0, costate_cutoff=-1.0):
+        """Advance n_steps and return (F, {key: dF/dtheta}) for F = <sigma^pauli_site>,
+        or for the Pauli string `paulis` (one of I, X, Y, Z per qubit), at the end
+        (lmpo_grad_run); keys hx, hy, hz, g0, g1, g2 (per qubit), J, Jz (per bond).
+        The co-state takes the chain's chi_max / cutoff unless given."""
         g = Gradient(self, n_steps, costate_chi_max, costate_cutoff)
         try:
-            return g.run(site, pauli)
+            return g.run_string(paulis) if paulis is not None else g.run(site, pauli)
         finally:
             g.close()
 
@@ -416,10 +417,17 @@ class Gradient:
         self.n_bonds = len(chain._m.bonds)
 
     def run(self, site, pauli):
+        """run_string for sigma^pauli on one qubit."""
+        s = ["I"] * self.chain.N
+        s[int(site)] = pauli.upper()
+        return self.run_string("".join(s))
+
+    def run_string(self, paulis):
+        """(F, {key: dF/dtheta}) for the Pauli string (one of I, X, Y, Z per qubit)."""
         N, nb = self.chain.N, self.n_bonds
         F = np.zeros(2)
         g = np.zeros(6 * N + 2 * nb)
-        _check(self._lib.lmpo_grad_run(self._h, int(site), pauli.upper().encode()[:1], _dptr(F), _dptr(g)))
+        _check(self._lib.lmpo_grad_run(self._h, paulis.upper().encode(), _dptr(F), _dptr(g)))
         out = {k: g[q * N:(q + 1) * N].copy() for q, k in enumerate(GRAD_SITE_KEYS)}
         out["J"] = g[6 * N:6 * N + nb].copy()
         out["Jz"] = g[6 * N + nb:].copy()
@@ -534,8 +542,8 @@ def _expectation_function():
                        spec.get("init", "+z"), force_trace=spec.get("force_trace", True),
                        order=spec.get("order", 2), device=spec.get("device", "cuda:0"))
             try:
-                F, g = ch.gradient(spec["steps"], spec["site"], spec["pauli"], spec.get("costate_chi_max", 0),
-                                   spec.get("costate_cutoff", -1.0))
+                F, g = ch.gradient(spec["steps"], spec.get("site"), spec.get("pauli"), spec.get("paulis"),
+                                   spec.get("costate_chi_max", 0), spec.get("costate_cutoff", -1.0))
             finally:
                 ch.close()
             grads = [torch.as_tensor(g[k], dtype=p.dtype, device=p.device).reshape(p.shape)
@@ -556,7 +564,8 @@ _EXPECTATION_FN = None
 def expectation(spec, params):
     """Differentiable F = Re <sigma^pauli_site> after spec["steps"] steps.
 
-    spec: N, bonds, tau, steps, chi_max, site, pauli and optionally cutoff,
+    spec: N, bonds, tau, steps, chi_max, site and pauli (or a Pauli string
+    paulis) and optionally cutoff,
     precision, init, force_trace, order, costate_chi_max, costate_cutoff,
     device.  params: tensors hx, hy, hz, g0, g1, g2 (length N) and J, Jz
     (length n_bonds); the result's backward fills their .grad."""

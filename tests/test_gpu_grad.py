@@ -20,14 +20,15 @@ def _chain(m, tau, chi, cutoff, init, precision="fp64", order=2, force_trace=Tru
 
 
 def _compare(m, tau, steps, chi, cutoff, init, site, pauli, precision="fp64", order=2, force_trace=True,
-             co_chi=None, co_cut=None):
+             co_chi=None, co_cut=None, paulis=None):
     print(f"gradient case: N={m['N']} bonds={len(m['bonds'])} chi={chi} cutoff={cutoff} steps={steps} "
-          f"order={order} {precision} <{pauli}_{site}> co-state {co_chi} {co_cut}", flush=True)
+          f"order={order} {precision} <{paulis or f'{pauli}_{site}'}> co-state {co_chi} {co_cut}", flush=True)
     ch = _chain(m, tau, chi, cutoff, init, precision, order, force_trace)
-    F, g = ch.gradient(steps, site, pauli, co_chi or 0, -1.0 if co_cut is None else co_cut)
+    F, g = ch.gradient(steps, site, pauli, paulis, co_chi or 0, -1.0 if co_cut is None else co_cut)
     ch.close()
     Fo, go, _ = adjoint.gradient(m, tau, steps, chi, cutoff, init, site, pauli, order=order,
-                                 force_trace=force_trace, costate_chi_max=co_chi, costate_cutoff=co_cut)
+                                 force_trace=force_trace, costate_chi_max=co_chi, costate_cutoff=co_cut,
+                                 paulis=paulis)
     got = np.concatenate([g[k] for k in adjoint.SITE_KEYS + adjoint.BOND_KEYS])
     ref = adjoint.flatten(m, go).real
     assert abs(F - Fo) < 1e-11
@@ -63,6 +64,18 @@ def test_ladder_gradient_with_own_costate_truncation():
     lad = workloads.ladder_model(4)
     m = workloads.random_model(8, 6, bonds=lad["bonds"])
     _compare(m, 0.1, 3, 16, 1e-12, "+x", 3, "Z", co_chi=6, co_cut=1e-6)
+
+
+def test_correlator_gradient():
+    """<Z_2 Z_5> (Eq. 2Qdef's correlator): F through the two-site measurement."""
+    _compare(workloads.random_model(8, 14), 0.1, 4, 8, 1e-10, "+x", None, None, paulis="IIZIIZII")
+
+
+def test_pauli_string_gradient_on_a_ladder():
+    """A three-factor string: F through the transition density of o and rho_T."""
+    lad = workloads.ladder_model(3)
+    m = workloads.random_model(6, 15, bonds=lad["bonds"])
+    _compare(m, 0.1, 3, 16, 1e-12, "+z", None, None, paulis="XIZIIY")
 
 
 def test_fourth_order_gradient():
