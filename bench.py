@@ -256,10 +256,12 @@ def gradient_leg(cpu_budget, no_cpu):
     F0, tf = forward(m)
     c = Chain(m, tau, chi, cut, "fp64", init, device="cuda:0")
     G = Gradient(c, steps)
+    G.costate_profile_begin(40000)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     F, g = G.run(site, pauli)
     tg = time.perf_counter() - t0
+    launches, co_ms, co_flops = G.costate_profile_end()
     co_dims, st_dims = G.costate_dims(), c.bond_dims()
     G.close()
     c.close()
@@ -278,6 +280,12 @@ def gradient_leg(cpu_budget, no_cpu):
            "parameters": int(sum(len(v) for v in g.values())), "seconds": tg, "forward_seconds": tf,
            "gradient_over_forward": tg / tf, "F": F.real, "F_forward_only": F0, "max_abs_gradient": gmax,
            "state_bond_dims_T": st_dims, "costate_bond_dims_t0": co_dims,
+           "roofline": {"bound": "mfma", "kernel": "svd_persistent_kernel (co-state, real form)",
+                        "achieved": co_flops / (co_ms * 1e-3) / 1e12, "peak": FP64_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": co_flops / (co_ms * 1e-3) / 1e12 / FP64_PEAK_TFLOPS,
+                        "traffic": None, "launches": launches, "avg_launch_ms": co_ms / max(1, launches),
+                        "flops_per_launch": co_flops / max(1, launches), "kernel_share_of_gradient":
+                            co_ms * 1e-3 / tg},
            "fd_check_h1e-5": fd,
            "fd_max_abs_diff": max(abs(v["adjoint"] - v["central_difference"]) for v in fd.values())}
     print(f"# gradient: {tg:.1f} s vs forward {tf:.2f} s", file=sys.stderr, flush=True)

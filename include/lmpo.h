@@ -377,6 +377,12 @@ int lmpo_grad_run(lmpo_grad *g, const char *paulis, double F[2], double *grad_ou
  * mu at time 0, the end of the backward pass.  Synchronises. */
 int lmpo_grad_costate_dims(lmpo_grad *g, int32_t *out);
 
+/* The co-state as a state handle (owned by the workspace; NULL for a NULL
+ * workspace), for inspection only: lmpo_bond_dims, lmpo_svd_stats and the
+ * profiling window lmpo_profile_begin / lmpo_profile_end around a run.
+ * Evolving or modifying it changes the next run's result. */
+lmpo_state *lmpo_grad_costate(lmpo_grad *g);
+
 int lmpo_grad_destroy(lmpo_grad *g);
 
 #ifdef __cplusplus

@@ -2175,6 +2175,8 @@ int lmpo_grad_run(lmpo_grad *G, const char *paulis, double F_out[2], double *gra
   return LMPO_OK;
 }
 
+lmpo_state *lmpo_grad_costate(lmpo_grad *G) { return G ? G->C : nullptr; }
+
 int lmpo_grad_costate_dims(lmpo_grad *G, int32_t *out) {
   if (!G || !out) return fail(LMPO_EINVAL, "null argument");
   return lmpo_bond_dims(G->C, out);

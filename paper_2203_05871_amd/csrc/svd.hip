@@ -805,9 +805,10 @@ __device__ __forceinline__ void svd_body(const SvdLaunch &a, Barrier &bar, Share
     int *dslot = (a.mode == 2) ? a.dims + (site - 1) : a.dims + site;
     if (rank == 0 && threadIdx.x == 0) {
       if (a.alg_flops) {
-        // declared cost of a thin complex QR with Q formed: 4 (4 R n^2 - 4 n^3 / 3), n = min(R, C)
+        // declared cost of a thin QR with Q formed: 4 R n^2 - 4 n^3 / 3 real flops, n = min(R, C),
+        // four times that for complex operands
         const double rr = R, cc = k;
-        *a.alg_flops += 4.0 * (4.0 * rr * cc * cc - 4.0 / 3.0 * cc * cc * cc);
+        *a.alg_flops += (a.real ? 1.0 : 4.0) * (4.0 * rr * cc * cc - 4.0 / 3.0 * cc * cc * cc);
       }
       if (a.stats) {
         a.stats[0] = 0;
@@ -1030,10 +1031,11 @@ __device__ __forceinline__ void svd_body(const SvdLaunch &a, Barrier &bar, Share
   int *dslot = a.dims + site;
   if (rank == 0) {
     if (threadIdx.x == 0 && a.alg_flops) {
-      // declared cost of a thin complex SVD of an R x C block (R >= C):
-      // 4 (14 R C^2 + 8 C^3) real flops (Golub & Van Loan, Golub-Reinsch count)
+      // declared cost of a thin SVD of an R x C block (R >= C): 14 R C^2 + 8 C^3
+      // real flops (Golub & Van Loan, Golub-Reinsch count), four times that for
+      // complex operands
       const double rr = R, cc = C;
-      *a.alg_flops += 4.0 * (14.0 * rr * cc * cc + 8.0 * cc * cc * cc);
+      *a.alg_flops += (a.real ? 1.0 : 4.0) * (14.0 * rr * cc * cc + 8.0 * cc * cc * cc);
     }
     if (threadIdx.x == 0 && a.stats) {
       a.stats[0] = sweeps;

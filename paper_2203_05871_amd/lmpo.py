@@ -69,7 +69,8 @@ EXPORTS = [
     "lmpo_batch_arena_bytes", "lmpo_batch_create", "lmpo_batch_evolve_step", "lmpo_batch_sync",
     "lmpo_batch_plan", "lmpo_batch_profile_begin", "lmpo_batch_profile_end", "lmpo_batch_destroy",
     "lmpo_batch_set_autotune", "lmpo_autotune_table",
-    "lmpo_grad_arena_bytes", "lmpo_grad_create", "lmpo_grad_run", "lmpo_grad_costate_dims", "lmpo_grad_destroy",
+    "lmpo_grad_arena_bytes", "lmpo_grad_create", "lmpo_grad_run", "lmpo_grad_costate_dims", "lmpo_grad_costate",
+    "lmpo_grad_destroy",
 ]
 
 
@@ -130,6 +131,7 @@ def load_library(path: str = LIB_PATH):
         "lmpo_grad_arena_bytes": (ctypes.c_size_t, [P, i32, i32, dbl]),
         "lmpo_grad_create": (ctypes.c_int, [P, i32, i32, dbl, P, ctypes.c_size_t, ctypes.POINTER(P)]),
         "lmpo_grad_costate_dims": (ctypes.c_int, [P, pi32]),
+        "lmpo_grad_costate": (P, [P]),
         "lmpo_grad_run": (ctypes.c_int, [P, ctypes.c_char_p, pdbl, pdbl]),
         "lmpo_grad_destroy": (ctypes.c_int, [P]),
     }
@@ -432,6 +434,16 @@ class Gradient:
         out["J"] = g[6 * N:6 * N + nb].copy()
         out["Jz"] = g[6 * N + nb:].copy()
         return complex(F[0], F[1]), out
+
+    def costate_profile_begin(self, max_launches=20000):
+        """HIP events around every co-state SVD launch of the next run()."""
+        _check(self._lib.lmpo_profile_begin(self._lib.lmpo_grad_costate(self._h), int(max_launches)))
+
+    def costate_profile_end(self):
+        """(co-state SVD launches, summed kernel ms, summed declared flops)."""
+        out = np.zeros(3)
+        _check(self._lib.lmpo_profile_end(self._lib.lmpo_grad_costate(self._h), _dptr(out)))
+        return int(out[0]), float(out[1]), float(out[2])
 
     def costate_dims(self):
         """Bond dims of the co-state (after run(): at time 0)."""

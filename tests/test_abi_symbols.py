@@ -73,5 +73,6 @@ def test_gradient_entry_points_reject_bad_arguments_on_host():
     out = ctypes.c_void_p()
     assert lib.lmpo_grad_create(None, 4, 0, -1.0, None, 0, ctypes.byref(out)) == -1
     assert lib.lmpo_grad_costate_dims(None, None) == -1
+    assert lib.lmpo_grad_costate(None) is None
     assert lib.lmpo_grad_run(None, b"IZ", None, None) == -1
     assert lib.lmpo_grad_destroy(None) == 0
