@@ -224,13 +224,15 @@ def bench_batch(args):
     print(json.dumps(line), flush=True)
 
 
-def gradient_leg(cpu_budget, no_cpu):
+def gradient_leg(cpu_budget, no_cpu, connected=False):
     """Adjoint parameter gradients on the 2 x 8 ladder (N=16, 22 bonds: 8 rungs
     and 14 legs through the SWAP network), chi_max 128, cutoff 1e-12, tau 0.05,
-    40 steps from +z: F = <sigma^z_1>(T) and all 6N + 2 n_bonds = 140
-    derivatives in one lmpo_grad_run (state forward, replay, co-state
-    backward), against the forward run alone; central differences of the GPU
-    forward (h = 1e-5) on a few parameters as a check."""
+    40 steps from +z: F = <sigma^z_15>(T), the far corner from the drive, and
+    all 6N + 2 n_bonds = 140 derivatives in one lmpo_grad_run (state forward,
+    replay, co-state backward), against the forward run alone; central
+    differences of the GPU forward (h = 1e-5) on a few parameters as a check.
+    With `connected`, also the connected correlator <Z_0 Z_15> - <Z_0><Z_15>
+    (one more backward pass from its four-term co-state)."""
     import numpy as np
     import torch
 
@@ -239,7 +241,7 @@ def gradient_leg(cpu_budget, no_cpu):
 
     m, run = workloads.ladder2x8()
     tau, steps, chi, cut, init = run["tau"], run["steps"], run["chi_max"], run["cutoff"], run["init"]
-    site, pauli = 1, "Z"
+    site, pauli = 15, "Z"
 
     def forward(model):
         c = Chain(model, tau, chi, cut, "fp64", init, device="cuda:0")
@@ -266,7 +268,10 @@ def gradient_leg(cpu_budget, no_cpu):
     G.close()
     c.close()
     fd = {}
-    for key, idx in (("hx", 0), ("hz", 1), ("J", 5), ("g0", 1)):
+    # the drive and parameters acting on the observed qubit (far ones give derivatives
+    # near 1e-7 at T = 2, below what differences of the truncated forward resolve)
+    near = [b for b, (i, j) in enumerate(np.asarray(m["bonds"])) if site in (i, j)]
+    for key, idx in (("hx", 0), ("hz", site), ("g0", site), ("J", near[0])):
         vals = []
         for sgn in (1.0, -1.0):
             mm = {k: (np.array(v, dtype=float) if k != "bonds" and isinstance(v, np.ndarray) else v)
@@ -276,7 +281,7 @@ def gradient_leg(cpu_budget, no_cpu):
         fd[f"{key}[{idx}]"] = {"adjoint": float(g[key][idx]), "central_difference": (vals[0] - vals[1]) / 2e-5}
     gmax = max(float(np.abs(v).max()) for v in g.values())
     out = {"workload": "2x8 ladder (N=16, 8 rungs + 14 legs via SWAP gates), chi_max=128, cutoff=1e-12, tau=0.05, "
-                       "40 steps from +z; F = <sigma^z_1>(T); co-state with the same chi_max and cutoff",
+                       "40 steps from +z; F = <sigma^z_15>(T); co-state with the same chi_max and cutoff",
            "parameters": int(sum(len(v) for v in g.values())), "seconds": tg, "forward_seconds": tf,
            "gradient_over_forward": tg / tf, "F": F.real, "F_forward_only": F0, "max_abs_gradient": gmax,
            "state_bond_dims_T": st_dims, "costate_bond_dims_t0": co_dims,
@@ -289,6 +294,17 @@ def gradient_leg(cpu_budget, no_cpu):
            "fd_check_h1e-5": fd,
            "fd_max_abs_diff": max(abs(v["adjoint"] - v["central_difference"]) for v in fd.values())}
     print(f"# gradient: {tg:.1f} s vs forward {tf:.2f} s", file=sys.stderr, flush=True)
+    if connected:
+        c = Chain(m, tau, chi, cut, "fp64", init, device="cuda:0")
+        G = Gradient(c, steps)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        C, gc = G.run_connected(0, 15, "ZZ")
+        out["connected_zz_0_15"] = {"C": C.real, "seconds": time.perf_counter() - t0,
+                                    "max_abs_gradient": max(float(np.abs(v).max()) for v in gc.values()),
+                                    "costate_bond_dims_t0": G.costate_dims()}
+        G.close()
+        c.close()
     if not no_cpu:
         # oracle on a bounded sample: the whole gradient after the first n
         # steps, n doubling while the budget lasts; the GPU runs the same n
@@ -442,7 +458,7 @@ def main():
             args.steps = 40
         return bench_batch(args)
     if args.workload == "ladder_grad":
-        g = gradient_leg(args.cpu_budget, args.no_cpu)
+        g = gradient_leg(args.cpu_budget, args.no_cpu, connected=True)
         line = {"metric": "adjoint gradients (140 parameters) per second, 2x8 ladder", "value": 1.0 / g["seconds"],
                 "unit": "gradients/s", "n_gpus": 1, "steps": 40, "warmup": 1,
                 "ms_per_step": 1e3 * g["seconds"] / 40, "higher_is_better": True, "scaling": "weak",

@@ -373,6 +373,15 @@ int lmpo_grad_create(lmpo_state *s, int32_t n_steps, int32_t costate_chi_max, do
  * for bit.  Synchronises (once per co-state gate). */
 int lmpo_grad_run(lmpo_grad *g, const char *paulis, double F[2], double *grad_out);
 
+/* As lmpo_grad_run for the connected correlator C = <a_i b_j> - <a_i><b_j>
+ * (the paper's connected two-qubit function) with paulis = "ab" (two of X,
+ * Y, Z) on qubits i != j: one backward pass whose co-state is the gradient
+ * of C at T, mu_T = (o_ij - F_j o_i - F_i o_j + (2 F_i F_j - F_ij) 1) / tr
+ * (F_x the three expectations at T).  F = C as (re, im).  That co-state
+ * starts at bond 4: a co-state chi_max below 4 is LMPO_EUNSUPPORTED, checked
+ * before the state moves. */
+int lmpo_grad_run_connected(lmpo_grad *g, int32_t i, int32_t j, const char *paulis, double F[2], double *grad_out);
+
 /* Bond dims of the co-state (n_qubits - 1 entries): after a run, those of
  * mu at time 0, the end of the backward pass.  Synchronises. */
 int lmpo_grad_costate_dims(lmpo_grad *g, int32_t *out);

@@ -4,8 +4,9 @@
 TEST INFRASTRUCTURE ONLY (see the package header).
 
 Objective: F = Tr(O rho_T) / Tr(rho_T) with O a Pauli string (sigma^a on one
-qubit as in Eq. mu, a correlator as in Eq. 2Qdef, or a longer product), after
-T Trotter steps from a fixed initial state.  Parameters: every
+qubit as in Eq. mu, a correlator as in Eq. 2Qdef, or a longer product), or the
+connected correlator <a_i b_j> - <a_i><b_j>, after T Trotter steps from a
+fixed initial state.  Parameters: every
 entry of hx, hy, hz, g0, g1, g2 (per qubit) and J, Jz (per bond) of the model
 of Sec. 2.1.  Each bond generator L_b is linear in every one of them (the
 Hamiltonian enters through a commutator, each rate multiplies its dissipator),
@@ -147,25 +148,52 @@ def costate(N, site, pauli, F, tr):
 
 def costate_string(N, ops, F, tr):
     """MPS of mu_T = (o - F 1) / tr for the Pauli string O = prod_s ops[s]
-    ({site: 'X' | 'Y' | 'Z'}): bond dimension 2, left-orthonormal with the
-    centre on the last site."""
-    o = [tebd.covector(lm.PAULI[ops[s]]) if s in ops else tebd.E_ID for s in range(N)]
-    w = [tebd.E_ID] * N
+    ({site: 'X' | 'Y' | 'Z'})."""
+    return costate_terms(N, [(1.0 / tr, ops), (-F / tr, {})])
+
+
+def costate_terms(N, terms):
+    """MPS of sum_k c_k prod_s o_{k,s} for terms [(c_k, {site: pauli})] (the
+    trace covector on every site not named): bond dimension K (a row on the
+    first site, block-diagonal inside, a column carrying the c_k on the last),
+    then left-orthonormal by QR with the centre on the last site."""
+    K = len(terms)
+    cov = [[tebd.covector(lm.PAULI[ops[s]]) if s in ops else tebd.E_ID for s in range(N)] for _, ops in terms]
     A = []
     for s in range(N):
-        if s == 0:
-            t = np.zeros((1, 4, 2), dtype=np.complex128)
-            t[0, :, 0], t[0, :, 1] = o[s], w[s]
-        elif s == N - 1:
-            t = np.zeros((2, 4, 1), dtype=np.complex128)
-            t[0, :, 0], t[1, :, 0] = o[s] / tr, -F * w[s] / tr
-        else:
-            t = np.zeros((2, 4, 2), dtype=np.complex128)
-            t[0, :, 0], t[1, :, 1] = o[s], w[s]
+        nl, nr = (1 if s == 0 else K), (1 if s == N - 1 else K)
+        t = np.zeros((nl, 4, nr), dtype=np.complex128)
+        for k, (c, _) in enumerate(terms):
+            t[0 if s == 0 else k, :, 0 if s == N - 1 else k] += (c if s == N - 1 else 1.0) * cov[k][s]
         A.append(t)
     mu = tebd.MPS(A, 0)
     mu.move_centre(N - 1)
     return mu
+
+
+def backward(model, tau, records, traces, mu, chi_mu, cut_mu, order=2):
+    """The co-state pass: {key: complex array of dF/dtheta} for the co-state
+    mu = mu_T (module header), which it advances back to time 0."""
+    gates = tebd.gate_tables(model, tau, order)
+    P = lm.swap_gate()
+    grads = {k: np.zeros(len(model[k]), dtype=np.complex128) for k in SITE_KEYS + BOND_KEYS}
+    kcache = {}
+    scale = 1.0
+    for n in reversed(range(len(records))):
+        scale = scale / traces[n]
+        for k, b, frac, asc, snap in reversed(records[n]):
+            if b is None:
+                mu.apply_gate(k, P.T, chi_mu, cut_mu, not asc)
+                continue
+            Gam = transition_density(mu.A, snap, k)
+            for key, idx in bond_parameters(model, b):
+                ck = (b, frac, key, idx)
+                if ck not in kcache:
+                    kcache[ck] = k_matrix(lm.bond_generator(model, b), generator_derivative(model, b, key, idx),
+                                          frac * tau)
+                grads[key][idx] += scale * np.sum(kcache[ck] * Gam.T)
+            mu.apply_gate(k, gates[(b, frac)].T, chi_mu, cut_mu, not asc)
+    return grads
 
 
 def gradient(model, tau, steps, chi_max, cutoff, init, site, pauli, order=2, force_trace=True,
@@ -180,30 +208,27 @@ def gradient(model, tau, steps, chi_max, cutoff, init, site, pauli, order=2, for
         ops = {site: pauli.upper()}
     chi_mu = chi_max if costate_chi_max is None else costate_chi_max
     cut_mu = cutoff if costate_cutoff is None else costate_cutoff
-    N = model["N"]
     mps, records, traces = forward_record(model, tau, steps, chi_max, cutoff, init, order, force_trace)
     F = mps.expect({s: lm.PAULI[p] for s, p in ops.items()})
-    mu = costate_string(N, ops, F, mps.trace())
-    gates = tebd.gate_tables(model, tau, order)
-    P = lm.swap_gate()
-    grads = {k: np.zeros(len(model[k]), dtype=np.complex128) for k in SITE_KEYS + BOND_KEYS}
-    kcache = {}
-    scale = 1.0
-    for n in reversed(range(steps)):
-        scale = scale / traces[n]
-        for k, b, frac, asc, snap in reversed(records[n]):
-            if b is None:
-                mu.apply_gate(k, P.T, chi_mu, cut_mu, not asc)
-                continue
-            Gam = transition_density(mu.A, snap, k)
-            for key, idx in bond_parameters(model, b):
-                ck = (b, frac, key, idx)
-                if ck not in kcache:
-                    kcache[ck] = k_matrix(lm.bond_generator(model, b), generator_derivative(model, b, key, idx),
-                                          frac * tau)
-                grads[key][idx] += scale * np.sum(kcache[ck] * Gam.T)
-            mu.apply_gate(k, gates[(b, frac)].T, chi_mu, cut_mu, not asc)
-    return F, grads, mps
+    mu = costate_string(model["N"], ops, F, mps.trace())
+    return F, backward(model, tau, records, traces, mu, chi_mu, cut_mu, order), mps
+
+
+def gradient_connected(model, tau, steps, chi_max, cutoff, init, i, j, paulis="ZZ", order=2, force_trace=True,
+                       costate_chi_max=None, costate_cutoff=None):
+    """(C, {key: dC/dtheta}, final MPS) for the connected correlator
+    C = <a_i b_j> - <a_i><b_j>: its gradient at T is
+    (o_ij - F_j o_i - F_i o_j + (2 F_i F_j - F_ij) 1) / tr, the co-state."""
+    a, b = paulis.upper()
+    chi_mu = chi_max if costate_chi_max is None else costate_chi_max
+    cut_mu = cutoff if costate_cutoff is None else costate_cutoff
+    mps, records, traces = forward_record(model, tau, steps, chi_max, cutoff, init, order, force_trace)
+    Fij = mps.expect({i: lm.PAULI[a], j: lm.PAULI[b]})
+    Fi, Fj = mps.expect({i: lm.PAULI[a]}), mps.expect({j: lm.PAULI[b]})
+    tr = mps.trace()
+    mu = costate_terms(model["N"], [(1.0 / tr, {i: a, j: b}), (-Fj / tr, {i: a}), (-Fi / tr, {j: b}),
+                                    ((2.0 * Fi * Fj - Fij) / tr, {})])
+    return Fij - Fi * Fj, backward(model, tau, records, traces, mu, chi_mu, cut_mu, order), mps
 
 
 def flatten(model, grads):

@@ -1946,46 +1946,45 @@ void transition_density(lmpo_grad *G, int k, const char *snap, const int *rd) {
   launch_transition_reduce(st, G->E, G->Fr, pm, qm, G->gam);
 }
 
-// mu_T = (o - F 1) / tr in the Pauli basis, o the covector of the Pauli
-// string a[0..N-1] (index 0 = identity): per site the trace covector is
-// sqrt(2) e_1 and sigma^a's is sqrt(2) e_a, so o and 1 are products and mu_T
-// has bond dimension 2 (a row on the first site, block-diagonal inside, a
-// column on the last).  Then an exact QR sweep makes it left-orthonormal
-// with the centre on the last site.  With `product` set, o alone (bond 1).
-int init_costate(lmpo_grad *G, const std::vector<int> &a, std::complex<double> F, std::complex<double> tr,
-                 bool product) {
+// A sum of product covectors sum_k c_k prod_s v_{k,s} as an MPS in the co-state:
+// v_{k,s} = sqrt(2) e_{a_k[s]} in the Pauli basis (the covector of the Pauli
+// factor a_k[s], index 0 the trace), bond dimension K (a row on the first
+// site, block-diagonal inside, a column carrying the c_k on the last; K <= 4
+// fits every bond capacity).  With `canonical` set, an exact QR sweep then
+// makes it left-orthonormal with the centre on the last site (bonds fall to
+// their rank).
+struct CostateTerm {
+  double c;
+  std::vector<int> a;
+};
+int init_costate(lmpo_grad *G, const std::vector<CostateTerm> &terms, bool canonical) {
   lmpo_state *C = G->C;
-  const int N = C->N;
+  const int N = C->N, K = (int)terms.size();
+  if (K < 1 || K > 4) return fail(LMPO_EINVAL, "internal: co-state of 1 to 4 product terms");
+  for (int b = 0; b < N - 1; ++b)
+    if (C->cap[b] < K)
+      return fail(LMPO_EUNSUPPORTED, "this objective's co-state starts at bond " + std::to_string(K) +
+                                         ": the co-state's chi_max must be at least that");
   const double r2 = std::sqrt(2.0);
   std::vector<std::vector<double2>> host(N);
-  // real form: F and tr are real up to round-off, which is dropped
-  const double last_o = 1.0 / tr.real(), last_w = -F.real() / tr.real();
-  const int w = product ? 1 : 2;
   for (int s = 0; s < N; ++s) {
-    const int nl = s == 0 ? 1 : w, nr = s == N - 1 ? 1 : w;
+    const int nl = s == 0 ? 1 : K, nr = s == N - 1 ? 1 : K;
     host[s].assign((size_t)nl * 4 * nr, make_double2(0.0, 0.0));
-    auto at = [&](int l, int q, int r) -> double2 & { return host[s][((size_t)l * 4 + q) * nr + r]; };
-    if (product) {
-      at(0, a[s], 0) = make_double2(r2, 0.0);
-    } else if (s == 0) {
-      at(0, a[s], 0) = make_double2(r2, 0.0);
-      at(0, 0, 1) = make_double2(r2, 0.0);
-    } else if (s == N - 1) {
-      at(0, a[s], 0) = make_double2(r2 * last_o, 0.0);
-      at(1, 0, 0) = make_double2(r2 * last_w, 0.0);
-    } else {
-      at(0, a[s], 0) = make_double2(r2, 0.0);
-      at(1, 0, 1) = make_double2(r2, 0.0);
+    for (int k = 0; k < K; ++k) {
+      const int l = s == 0 ? 0 : k, r = s == N - 1 ? 0 : k;
+      const double v = s == N - 1 ? r2 * terms[k].c : r2;
+      double2 &e = host[s][((size_t)l * 4 + terms[k].a[s]) * nr + r];
+      e.x += v;
     }
   }
   for (int s = 0; s < N; ++s)
     HIP_TRY(hipMemcpyAsync(C->site[s], host[s].data(), host[s].size() * sizeof(double2), hipMemcpyHostToDevice,
                            C->stream));
-  std::fill(C->dims.begin(), C->dims.end(), w);
+  std::fill(C->dims.begin(), C->dims.end(), K);
   HIP_TRY(hipMemcpyAsync(C->d_dims, C->dims.data(), (N - 1) * sizeof(int), hipMemcpyHostToDevice, C->stream));
   HIP_TRY(hipStreamSynchronize(C->stream));
   C->centre = 0;
-  return product ? LMPO_OK : move_centre(C, N - 1);
+  return canonical ? move_centre(C, N - 1) : LMPO_OK;
 }
 
 // <o, rho> for the Pauli string a on the state as it stands: o goes into the
@@ -1993,7 +1992,7 @@ int init_costate(lmpo_grad *G, const std::vector<int> &a, std::complex<double> F
 // traced with the identity, is the whole contraction.
 int string_expectation_numerator(lmpo_grad *G, const std::vector<int> &a, std::complex<double> &out) {
   lmpo_state *S = G->S;
-  int rc = init_costate(G, a, 0.0, 1.0, true);
+  int rc = init_costate(G, {{1.0, a}}, false);
   if (rc || (rc = sync_dims(S))) return rc;
   transition_density(G, S->N - 2, reinterpret_cast<const char *>(S->site[0]), S->dims.data());
   double2 gam[256];
@@ -2069,24 +2068,20 @@ int lmpo_grad_create(lmpo_state *S, int32_t n_steps, int32_t costate_chi_max, do
   return LMPO_OK;
 }
 
-int lmpo_grad_run(lmpo_grad *G, const char *paulis, double F_out[2], double *grad_out) {
-  if (!G || !paulis || !F_out || !grad_out) return fail(LMPO_EINVAL, "null argument");
-  lmpo_state *S = G->S, *C = G->C;
+}  // extern "C"
+
+namespace {
+
+// Forward run of the gradient: the state advances by the workspace's steps
+// with a snapshot at every step start and one of the final state; the traces
+// divided out per step and tr(rho_T) come back to the host.
+int grad_forward(lmpo_grad *G, long long &step0, std::complex<double> &trT, std::vector<double2> &tr_host) {
+  lmpo_state *S = G->S;
   const int N = S->N, T = G->n_steps;
-  if (std::strlen(paulis) != (size_t)N) return fail(LMPO_EINVAL, "paulis must hold one of I, X, Y, Z per qubit");
-  std::vector<int> a(N);
-  std::vector<int> req;  // the string as a 1Q / 2Q measurement request when it has one or two factors
-  for (int s = 0; s < N; ++s) {
-    a[s] = pauli_index(paulis[s]);
-    if (a[s] < 0) return fail(LMPO_EINVAL, "paulis must hold one of I, X, Y, Z per qubit");
-    if (a[s] > 0) req.insert(req.end(), {s, a[s]});
-  }
-  if (req.empty()) return fail(LMPO_EINVAL, "paulis must name at least one X, Y or Z");
   hipStream_t st = S->stream;
-  const long long step0 = S->step_index;
+  step0 = S->step_index;
   int rc;
   HIP_TRY(hipMemsetAsync(G->grad, 0, (size_t)G->P * sizeof(double2), st));
-  // forward, one snapshot per step start (and one of the final state)
   for (int n = 0; n < T; ++n) {
     if ((rc = save_snapshot(S, G->ckpt + (size_t)n * G->snap))) return rc;
     G->ckpt_centre[n] = S->centre;
@@ -2095,34 +2090,30 @@ int lmpo_grad_run(lmpo_grad *G, const char *paulis, double F_out[2], double *gra
   }
   if ((rc = save_snapshot(S, G->ckpt + (size_t)T * G->snap))) return rc;
   G->ckpt_centre[T] = S->centre;
-  // the replays below add to these; the forward run's values are restored at the end
+  // the replays of the backward pass add to these; the forward run's values are restored at the end
   HIP_TRY(hipMemcpyAsync(G->disc_save, S->disc, sizeof(double), hipMemcpyDeviceToDevice, st));
   HIP_TRY(hipMemcpyAsync(G->stats_save, S->stats, kStats * sizeof(int), hipMemcpyDeviceToDevice, st));
-  // tr(rho_T) and F = <string> (one or two factors: the measurement kernels,
-  // as lmpo_measure_1q/2q; more: the transition density of o and rho_T)
   launch_trace(st, S->d_sites, S->d_dims, N, S->tr);
-  double2 trT;
-  HIP_TRY(hipMemcpyAsync(&trT, S->tr, sizeof(double2), hipMemcpyDeviceToHost, st));
-  std::vector<double2> tr_host(T, make_double2(1.0, 0.0));
+  double2 t;
+  HIP_TRY(hipMemcpyAsync(&t, S->tr, sizeof(double2), hipMemcpyDeviceToHost, st));
+  tr_host.assign(T, make_double2(1.0, 0.0));
   if (S->opt.force_trace)
     HIP_TRY(hipMemcpyAsync(tr_host.data(), G->traces, T * sizeof(double2), hipMemcpyDeviceToHost, st));
   HIP_TRY(hipStreamSynchronize(st));
-  const std::complex<double> trc(trT.x, trT.y);
-  if (!(std::abs(trc) > 0) || !std::isfinite(std::abs(trc))) return fail(LMPO_ENUMERIC, "trace is zero or non-finite");
-  double fo[2];
-  if (req.size() <= 4) {
-    if (req.size() == 2) req.insert(req.end(), {-1, 0});
-    if ((rc = run_measure(S, req, fo))) return rc;
-  } else {
-    std::complex<double> num;
-    if ((rc = string_expectation_numerator(G, a, num))) return rc;
-    const std::complex<double> f = num / trc;
-    fo[0] = f.real();
-    fo[1] = f.imag();
-  }
-  const std::complex<double> F(fo[0], fo[1]);
-  if ((rc = init_costate(G, a, F, trc, false))) return rc;
-  // backward
+  trT = std::complex<double>(t.x, t.y);
+  if (!(std::abs(trT) > 0) || !std::isfinite(std::abs(trT))) return fail(LMPO_ENUMERIC, "trace is zero or non-finite");
+  return LMPO_OK;
+}
+
+// Backward pass from the co-state mu_T already in G->C: per step from the
+// last, replay with gate snapshots, then the gates in reverse (transition
+// density, contributions, transposed gate).  Leaves the state as after the
+// forward run and writes the real parts of the gradient.
+int grad_backward(lmpo_grad *G, long long step0, const std::vector<double2> &tr_host, double *grad_out) {
+  lmpo_state *S = G->S, *C = G->C;
+  const int N = S->N, T = G->n_steps;
+  hipStream_t st = S->stream;
+  int rc;
   std::complex<double> scale = 1.0;
   std::vector<int> rd;
   for (int n = T - 1; n >= 0; --n) {
@@ -2155,7 +2146,6 @@ int lmpo_grad_run(lmpo_grad *G, const char *paulis, double F_out[2], double *gra
       if ((rc = apply_gate_dev(C, op.k, gate_ptr(C, op.bond, op.slot), op.asc ? 0 : 1))) return rc;
     }
   }
-  // the state as after the forward run
   if ((rc = load_snapshot(S, G->ckpt + (size_t)T * G->snap))) return rc;
   S->centre = G->ckpt_centre[T];
   S->step_index = step0 + T;
@@ -2166,12 +2156,93 @@ int lmpo_grad_run(lmpo_grad *G, const char *paulis, double F_out[2], double *gra
   HIP_TRY(hipStreamSynchronize(st));
   if ((rc = sync_dims(S))) return rc;
   if ((rc = check_err(S)) || (rc = check_err(C))) return rc;
-  F_out[0] = fo[0];
-  F_out[1] = fo[1];
   for (int p = 0; p < G->P; ++p) {
     if (!std::isfinite(gh[p].x)) return fail(LMPO_ENUMERIC, "non-finite gradient");
     grad_out[p] = gh[p].x;
   }
+  return LMPO_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int lmpo_grad_run(lmpo_grad *G, const char *paulis, double F_out[2], double *grad_out) {
+  if (!G || !paulis || !F_out || !grad_out) return fail(LMPO_EINVAL, "null argument");
+  lmpo_state *S = G->S;
+  const int N = S->N;
+  if (std::strlen(paulis) != (size_t)N) return fail(LMPO_EINVAL, "paulis must hold one of I, X, Y, Z per qubit");
+  std::vector<int> a(N);
+  std::vector<int> req;  // the string as a 1Q / 2Q measurement request when it has one or two factors
+  for (int s = 0; s < N; ++s) {
+    a[s] = pauli_index(paulis[s]);
+    if (a[s] < 0) return fail(LMPO_EINVAL, "paulis must hold one of I, X, Y, Z per qubit");
+    if (a[s] > 0) req.insert(req.end(), {s, a[s]});
+  }
+  if (req.empty()) return fail(LMPO_EINVAL, "paulis must name at least one X, Y or Z");
+  long long step0;
+  std::complex<double> trT;
+  std::vector<double2> tr_host;
+  int rc = grad_forward(G, step0, trT, tr_host);
+  if (rc) return rc;
+  // F = <string>: one or two factors through the measurement kernels (as
+  // lmpo_measure_1q / _2q), more through the transition density of o and rho_T
+  double fo[2];
+  if (req.size() <= 4) {
+    if (req.size() == 2) req.insert(req.end(), {-1, 0});
+    if ((rc = run_measure(S, req, fo))) return rc;
+  } else {
+    std::complex<double> num;
+    if ((rc = string_expectation_numerator(G, a, num))) return rc;
+    const std::complex<double> f = num / trT;
+    fo[0] = f.real();
+    fo[1] = f.imag();
+  }
+  // mu_T = (o - F 1) / tr; F and tr are real up to round-off, which is dropped
+  const double tr = trT.real();
+  if ((rc = init_costate(G, {{1.0 / tr, a}, {-fo[0] / tr, std::vector<int>(N, 0)}}, true))) return rc;
+  if ((rc = grad_backward(G, step0, tr_host, grad_out))) return rc;
+  F_out[0] = fo[0];
+  F_out[1] = fo[1];
+  return LMPO_OK;
+}
+
+int lmpo_grad_run_connected(lmpo_grad *G, int32_t i, int32_t j, const char *paulis, double F_out[2],
+                            double *grad_out) {
+  if (!G || !paulis || !F_out || !grad_out) return fail(LMPO_EINVAL, "null argument");
+  lmpo_state *S = G->S;
+  const int N = S->N;
+  if (i < 0 || j < 0 || i >= N || j >= N || i == j) return fail(LMPO_EINVAL, "a correlator needs two distinct qubits");
+  if (std::strlen(paulis) != 2) return fail(LMPO_EINVAL, "paulis must hold two of X, Y, Z");
+  int ai = pauli_index(paulis[0]), aj = pauli_index(paulis[1]);
+  if (ai <= 0 || aj <= 0) return fail(LMPO_EINVAL, "paulis must hold two of X, Y, Z");
+  if (i > j) {
+    std::swap(i, j);
+    std::swap(ai, aj);
+  }
+  for (int b = 0; b < N - 1; ++b)  // before the state moves: the four-term co-state must fit
+    if (G->C->cap[b] < 4)
+      return fail(LMPO_EUNSUPPORTED, "the connected correlator's co-state starts at bond 4: the co-state's "
+                                     "chi_max must be at least 4");
+  long long step0;
+  std::complex<double> trT;
+  std::vector<double2> tr_host;
+  int rc = grad_forward(G, step0, trT, tr_host);
+  if (rc) return rc;
+  double f[6];  // <a_i b_j>, <a_i>, <b_j> as (re, im)
+  if ((rc = run_measure(S, {i, ai, j, aj, i, ai, -1, 0, j, aj, -1, 0}, f))) return rc;
+  const double Fij = f[0], Fi = f[2], Fj = f[4], tr = trT.real();
+  // C = F_ij - F_i F_j, dC = dF_ij - F_j dF_i - F_i dF_j with dF_x = (o_x - F_x 1) / tr:
+  // mu_T = (o_ij - F_j o_i - F_i o_j + (2 F_i F_j - F_ij) 1) / tr
+  std::vector<int> oij(N, 0), oi(N, 0), oj(N, 0), one(N, 0);
+  oij[i] = oi[i] = ai;
+  oij[j] = oj[j] = aj;
+  if ((rc = init_costate(G, {{1.0 / tr, oij}, {-Fj / tr, oi}, {-Fi / tr, oj}, {(2.0 * Fi * Fj - Fij) / tr, one}},
+                         true)))
+    return rc;
+  if ((rc = grad_backward(G, step0, tr_host, grad_out))) return rc;
+  F_out[0] = Fij - Fi * Fj;
+  F_out[1] = f[1] - (f[3] * Fj + Fi * f[5]);
   return LMPO_OK;
 }
 

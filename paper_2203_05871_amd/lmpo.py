@@ -69,7 +69,7 @@ EXPORTS = [
     "lmpo_batch_arena_bytes", "lmpo_batch_create", "lmpo_batch_evolve_step", "lmpo_batch_sync",
     "lmpo_batch_plan", "lmpo_batch_profile_begin", "lmpo_batch_profile_end", "lmpo_batch_destroy",
     "lmpo_batch_set_autotune", "lmpo_autotune_table",
-    "lmpo_grad_arena_bytes", "lmpo_grad_create", "lmpo_grad_run", "lmpo_grad_costate_dims", "lmpo_grad_costate",
+    "lmpo_grad_arena_bytes", "lmpo_grad_create", "lmpo_grad_run", "lmpo_grad_costate_dims", "lmpo_grad_costate", "lmpo_grad_run_connected",
     "lmpo_grad_destroy",
 ]
 
@@ -132,6 +132,7 @@ def load_library(path: str = LIB_PATH):
         "lmpo_grad_create": (ctypes.c_int, [P, i32, i32, dbl, P, ctypes.c_size_t, ctypes.POINTER(P)]),
         "lmpo_grad_costate_dims": (ctypes.c_int, [P, pi32]),
         "lmpo_grad_costate": (P, [P]),
+        "lmpo_grad_run_connected": (ctypes.c_int, [P, i32, i32, ctypes.c_char_p, pdbl, pdbl]),
         "lmpo_grad_run": (ctypes.c_int, [P, ctypes.c_char_p, pdbl, pdbl]),
         "lmpo_grad_destroy": (ctypes.c_int, [P]),
     }
@@ -426,10 +427,21 @@ class Gradient:
 
     def run_string(self, paulis):
         """(F, {key: dF/dtheta}) for the Pauli string (one of I, X, Y, Z per qubit)."""
-        N, nb = self.chain.N, self.n_bonds
         F = np.zeros(2)
-        g = np.zeros(6 * N + 2 * nb)
+        g = np.zeros(6 * self.chain.N + 2 * self.n_bonds)
         _check(self._lib.lmpo_grad_run(self._h, paulis.upper().encode(), _dptr(F), _dptr(g)))
+        return self._unpack(F, g)
+
+    def run_connected(self, i, j, paulis="ZZ"):
+        """(C, {key: dC/dtheta}) for the connected correlator <a_i b_j> - <a_i><b_j>."""
+        F = np.zeros(2)
+        g = np.zeros(6 * self.chain.N + 2 * self.n_bonds)
+        _check(self._lib.lmpo_grad_run_connected(self._h, int(i), int(j), paulis.upper().encode(), _dptr(F),
+                                                 _dptr(g)))
+        return self._unpack(F, g)
+
+    def _unpack(self, F, g):
+        N, nb = self.chain.N, self.n_bonds
         out = {k: g[q * N:(q + 1) * N].copy() for q, k in enumerate(GRAD_SITE_KEYS)}
         out["J"] = g[6 * N:6 * N + nb].copy()
         out["Jz"] = g[6 * N + nb:].copy()

@@ -13,6 +13,12 @@ from oracle import adjoint
 pytestmark = pytest.mark.gpu
 
 
+def Gradient(chain, n_steps, co_chi=0, co_cut=-1.0):
+    from paper_2203_05871_amd import Gradient as G
+
+    return G(chain, n_steps, co_chi, co_cut)
+
+
 def _chain(m, tau, chi, cutoff, init, precision="fp64", order=2, force_trace=True):
     from paper_2203_05871_amd import Chain
 
@@ -76,6 +82,47 @@ def test_pauli_string_gradient_on_a_ladder():
     lad = workloads.ladder_model(3)
     m = workloads.random_model(6, 15, bonds=lad["bonds"])
     _compare(m, 0.1, 3, 16, 1e-12, "+z", None, None, paulis="XIZIIY")
+
+
+@pytest.mark.parametrize("ladder", [False, True])
+def test_connected_correlator_gradient(ladder):
+    """<Z_0 Z_j> - <Z_0><Z_j> (the paper's connected function): one backward pass
+    from the four-term co-state, against the oracle's."""
+    if ladder:
+        m = workloads.random_model(8, 18, bonds=workloads.ladder_model(4)["bonds"])
+        args = (0.1, 3, 16, 1e-12, "+z")
+    else:
+        m = workloads.random_model(8, 19)
+        args = (0.1, 4, 8, 1e-10, "+x")
+    print(f"gradient case: connected <Z_0 Z_7>, N=8, ladder={ladder}", flush=True)
+    tau, steps, chi, cut, init = args
+    ch = _chain(m, tau, chi, cut, init)
+    G = Gradient(ch, steps)
+    C, g = G.run_connected(0, 7, "ZZ")
+    G.close()
+    ch.close()
+    Co, go, _ = adjoint.gradient_connected(m, tau, steps, chi, cut, init, 0, 7, "ZZ")
+    got = np.concatenate([g[k] for k in adjoint.SITE_KEYS + adjoint.BOND_KEYS])
+    ref = adjoint.flatten(m, go).real
+    err = np.abs(got - ref).max() / max(1.0, np.abs(ref).max())
+    print(f"  C = {C.real:.12f}, max |grad - oracle| / scale = {err:.2e}", flush=True)
+    assert abs(C - Co) < 1e-11
+    assert err < 1e-9
+
+
+def test_connected_correlator_needs_room_for_its_costate():
+    """Four product terms start the co-state at bond 4: a co-state chi_max of 3
+    is refused before any GPU work on it."""
+    from paper_2203_05871_amd import LmpoError
+
+    ch = _chain(workloads.random_model(5, 20), 0.1, 8, 1e-10, "+x")
+    before = [ch.get_site(k) for k in range(5)]
+    G = Gradient(ch, 1, 3, -1.0)
+    with pytest.raises(LmpoError, match="co-state"):
+        G.run_connected(0, 4, "ZZ")
+    G.close()
+    assert all(np.array_equal(a, ch.get_site(k)) for k, a in enumerate(before))  # the state did not move
+    ch.close()
 
 
 def test_fourth_order_gradient():
