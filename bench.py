@@ -280,6 +280,12 @@ def gradient_leg(cpu_budget, no_cpu, connected=False):
             vals.append(forward(mm)[0])
         fd[f"{key}[{idx}]"] = {"adjoint": float(g[key][idx]), "central_difference": (vals[0] - vals[1]) / 2e-5}
     gmax = max(float(np.abs(v).max()) for v in g.values())
+
+    def forty(gr):
+        # the 40 numbers of the ladder case: 16 h_z, 22 J, Omega = h_x[0], one g0 shared by all qubits
+        return {"hz": [float(x) for x in gr["hz"]], "J": [float(x) for x in gr["J"]], "Omega": float(gr["hx"][0]),
+                "g0_uniform": float(np.sum(gr["g0"]))}
+
     out = {"workload": "2x8 ladder (N=16, 8 rungs + 14 legs via SWAP gates), chi_max=128, cutoff=1e-12, tau=0.05, "
                        "40 steps from +z; F = <sigma^z_15>(T); co-state with the same chi_max and cutoff",
            "parameters": int(sum(len(v) for v in g.values())), "seconds": tg, "forward_seconds": tf,
@@ -291,7 +297,7 @@ def gradient_leg(cpu_budget, no_cpu, connected=False):
                         "traffic": None, "launches": launches, "avg_launch_ms": co_ms / max(1, launches),
                         "flops_per_launch": co_flops / max(1, launches), "kernel_share_of_gradient":
                             co_ms * 1e-3 / tg},
-           "fd_check_h1e-5": fd,
+           "fd_check_h1e-5": fd, "derivatives": forty(g),
            "fd_max_abs_diff": max(abs(v["adjoint"] - v["central_difference"]) for v in fd.values())}
     print(f"# gradient: {tg:.1f} s vs forward {tf:.2f} s", file=sys.stderr, flush=True)
     if connected:
@@ -302,7 +308,7 @@ def gradient_leg(cpu_budget, no_cpu, connected=False):
         C, gc = G.run_connected(0, 15, "ZZ")
         out["connected_zz_0_15"] = {"C": C.real, "seconds": time.perf_counter() - t0,
                                     "max_abs_gradient": max(float(np.abs(v).max()) for v in gc.values()),
-                                    "costate_bond_dims_t0": G.costate_dims()}
+                                    "costate_bond_dims_t0": G.costate_dims(), "derivatives": forty(gc)}
         G.close()
         c.close()
     if not no_cpu:
@@ -453,6 +459,10 @@ def main():
         torch.cuda.synchronize()
         copy_gbps = 5 * 2 * (1 << 30) / (time.perf_counter() - t0) / 1e9
         del src, dst
+    # and of the FP64 matrix-core peak: the library's MFMA throughput probe
+    from paper_2203_05871_amd.lmpo import measured_fp64_mfma_peak
+
+    mfma_tflops = measured_fp64_mfma_peak() if args.copy_probe == 0 else None
     if args.workload == "chains64":
         if args.steps is None:
             args.steps = 40
@@ -491,7 +501,7 @@ def main():
                 "avg_launch_ms": h["svd_ms"] / max(1, h["launches"]),
                 "flops_per_launch": h["svd_flops"] / max(1, h["launches"]),
                 "kernel_share_of_step": h["svd_ms"] * 1e-3 / h["seconds"],
-                "measured_copy_GBps": copy_gbps}
+                "measured_copy_GBps": copy_gbps, "measured_fp64_mfma_TFLOPs": mfma_tflops}
     line = {
         "metric": METRIC, "value": value, "unit": "steps/s", "n_gpus": 1, "steps": K, "warmup": W,
         "ms_per_step": 1e3 * h["seconds"] / K, "higher_is_better": True, "scaling": "weak",

@@ -394,6 +394,17 @@ lmpo_state *lmpo_grad_costate(lmpo_grad *g);
 
 int lmpo_grad_destroy(lmpo_grad *g);
 
+/* ---- Measured peak ---------------------------------------------------------
+ * FP64 matrix-core throughput of the device, the measured counterpart of the
+ * datasheet peak the rooflines use: 2048 workgroups of four wavefronts, each
+ * issuing 8 x 4096 independent v_mfma_f64_16x16x4f64 (2048 flops each) on
+ * register operands; the second of two launches is timed with HIP events on
+ * hip_stream.  device_buffer (caller-owned, at least
+ * lmpo_probe_fp64_mfma_bytes() bytes) receives one value per thread.
+ * Synchronises. */
+size_t lmpo_probe_fp64_mfma_bytes(void);
+int lmpo_probe_fp64_mfma(void *hip_stream, void *device_buffer, size_t buffer_bytes, double *tflops);
+
 #ifdef __cplusplus
 }
 #endif

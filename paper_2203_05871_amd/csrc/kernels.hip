@@ -255,4 +255,31 @@ void launch_double_dims(hipStream_t s, int *dims, int n) {
   check_launch();
 }
 
+// ---------------------------------------------------------------------------
+// FP64 matrix-core throughput probe (the measured counterpart of the FP64
+// peak the rooflines are quoted against): every wavefront issues `iters`
+// rounds of eight independent v_mfma_f64_16x16x4f64 (16 x 16 x 4 multiply-adds,
+// 2048 flops each) on register operands, enough chains to cover the
+// instruction latency; one store per lane keeps the results live.
+// ---------------------------------------------------------------------------
+typedef double probe_f64x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void mfma_f64_probe_kernel(int iters, double seed, double *out) {
+  const double a = seed + 1e-3 * threadIdx.x, b = seed - 1e-3 * threadIdx.x;
+  probe_f64x4 acc[8];
+  for (int i = 0; i < 8; ++i) acc[i] = probe_f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int it = 0; it < iters; ++it) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[i] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[i], 0, 0, 0);
+  }
+  double sum = 0.0;
+  for (int i = 0; i < 8; ++i) sum += acc[i][0] + acc[i][1] + acc[i][2] + acc[i][3];
+  out[(size_t)blockIdx.x * blockDim.x + threadIdx.x] = sum;
+}
+
+void launch_mfma_f64_probe(hipStream_t s, int blocks, int iters, double *out) {
+  hipLaunchKernelGGL(mfma_f64_probe_kernel, dim3(blocks), dim3(256), 0, s, iters, 0.5, out);
+  check_launch();
+}
+
 }  // namespace lmpo

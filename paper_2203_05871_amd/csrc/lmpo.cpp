@@ -2248,6 +2248,37 @@ int lmpo_grad_run_connected(lmpo_grad *G, int32_t i, int32_t j, const char *paul
 
 lmpo_state *lmpo_grad_costate(lmpo_grad *G) { return G ? G->C : nullptr; }
 
+size_t lmpo_probe_fp64_mfma_bytes(void) { return (size_t)2048 * 256 * sizeof(double); }
+
+int lmpo_probe_fp64_mfma(void *hip_stream, void *device_buffer, size_t buffer_bytes, double *tflops) {
+  if (!device_buffer || !tflops) return fail(LMPO_EINVAL, "null argument");
+  const int blocks = 2048, iters = 4096;  // 8 workgroups per compute unit, about 7 ms at the datasheet peak
+  if (buffer_bytes < (size_t)blocks * 256 * sizeof(double)) return fail(LMPO_EINVAL, "probe buffer too small");
+  hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+  double *out = reinterpret_cast<double *>(device_buffer);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIP_TRY(hipEventCreate(&e0));
+  hipError_t e = hipEventCreate(&e1);
+  float ms = 0.0f;
+  if (e == hipSuccess) {
+    launch_mfma_f64_probe(st, blocks, iters, out);  // warm-up
+    e = hipEventRecord(e0, st);
+  }
+  if (e == hipSuccess) {
+    launch_mfma_f64_probe(st, blocks, iters, out);
+    e = hipGetLastError();
+  }
+  if (e == hipSuccess) e = hipEventRecord(e1, st);
+  if (e == hipSuccess) e = hipEventSynchronize(e1);
+  if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+  (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  if (e != hipSuccess) return fail(LMPO_EHIP, std::string("probe: ") + hipGetErrorString(e));
+  const double flops = (double)blocks * 4 * iters * 8 * 2048.0;  // 4 wavefronts per workgroup
+  *tflops = flops / (ms * 1e-3) / 1e12;
+  return LMPO_OK;
+}
+
 int lmpo_grad_costate_dims(lmpo_grad *G, int32_t *out) {
   if (!G || !out) return fail(LMPO_EINVAL, "null argument");
   return lmpo_bond_dims(G->C, out);

@@ -112,6 +112,10 @@ void launch_scale_site(hipStream_t s, double2 *const *sites, const int *dims, in
 void launch_hermitian_sum_site(hipStream_t s, const double2 *src, double2 *dst, const int *dims, int N, int k);
 void launch_double_dims(hipStream_t s, int *dims, int n);
 
+// FP64 matrix-core probe: blocks x 256 threads, each wavefront 8 x iters MFMAs
+// of 2048 flops; out holds blocks * 256 doubles.
+void launch_mfma_f64_probe(hipStream_t s, int blocks, int iters, double *out);
+
 // ---- adjoint gradient (grad.hip) ----
 // C(m, n) = sum_k A(m, k) B(k, n) per batch z; element (m, k) of A at
 // A[m * sam + k * sak + z * sab], likewise for B and C.

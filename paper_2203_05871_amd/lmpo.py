@@ -70,6 +70,7 @@ EXPORTS = [
     "lmpo_batch_plan", "lmpo_batch_profile_begin", "lmpo_batch_profile_end", "lmpo_batch_destroy",
     "lmpo_batch_set_autotune", "lmpo_autotune_table",
     "lmpo_grad_arena_bytes", "lmpo_grad_create", "lmpo_grad_run", "lmpo_grad_costate_dims", "lmpo_grad_costate", "lmpo_grad_run_connected",
+    "lmpo_probe_fp64_mfma_bytes", "lmpo_probe_fp64_mfma",
     "lmpo_grad_destroy",
 ]
 
@@ -133,6 +134,8 @@ def load_library(path: str = LIB_PATH):
         "lmpo_grad_costate_dims": (ctypes.c_int, [P, pi32]),
         "lmpo_grad_costate": (P, [P]),
         "lmpo_grad_run_connected": (ctypes.c_int, [P, i32, i32, ctypes.c_char_p, pdbl, pdbl]),
+        "lmpo_probe_fp64_mfma_bytes": (ctypes.c_size_t, []),
+        "lmpo_probe_fp64_mfma": (ctypes.c_int, [P, P, ctypes.c_size_t, pdbl]),
         "lmpo_grad_run": (ctypes.c_int, [P, ctypes.c_char_p, pdbl, pdbl]),
         "lmpo_grad_destroy": (ctypes.c_int, [P]),
     }
@@ -390,6 +393,19 @@ class Chain:
             self.close()
         except Exception:
             pass
+
+
+def measured_fp64_mfma_peak(device="cuda:0"):
+    """FP64 matrix-core TFLOP/s measured by lmpo_probe_fp64_mfma on the current stream."""
+    import torch
+
+    lib = load_library()
+    n = lib.lmpo_probe_fp64_mfma_bytes()
+    buf = torch.empty(n, dtype=torch.uint8, device=device)
+    out = np.zeros(1)
+    _check(lib.lmpo_probe_fp64_mfma(ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream),
+                                    ctypes.c_void_p(buf.data_ptr()), ctypes.c_size_t(n), _dptr(out)))
+    return float(out[0])
 
 
 GRAD_SITE_KEYS = ("hx", "hy", "hz", "g0", "g1", "g2")
