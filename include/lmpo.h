@@ -370,7 +370,9 @@ int lmpo_grad_create(lmpo_state *s, int32_t n_steps, int32_t costate_chi_max, do
  * hx[0..N-1], hy, hz, g0, g1, g2, J[0..n_bonds-1], Jz.  paulis: the string O,
  * n_qubits characters of I, X, Y, Z (qubit 0 first), at least one not I.  F
  * of one or two factors equals lmpo_measure_1q / _2q on the final state bit
- * for bit.  Synchronises (once per co-state gate). */
+ * for bit.  Synchronises (once per co-state gate).  Arguments are checked
+ * before the state moves; after an error met later (LMPO_EHIP, LMPO_ENUMERIC)
+ * the state's tensors are unspecified. */
 int lmpo_grad_run(lmpo_grad *g, const char *paulis, double F[2], double *grad_out);
 
 /* As lmpo_grad_run for the connected correlator C = <a_i b_j> - <a_i><b_j>

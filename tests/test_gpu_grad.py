@@ -249,3 +249,32 @@ def test_ladder2x3_exact_gradient_against_dense_trotter():
     err = np.abs(got - np.array(ref)).max()
     print(f"  max |grad - dense central difference| = {err:.2e}", flush=True)
     assert err < 1e-8
+
+
+def test_gradient_error_paths():
+    """Refused before any work: Hermitisation, a co-state chi below 2, zero steps,
+    malformed strings (the state is left where it was)."""
+    from paper_2203_05871_amd import LmpoError
+
+    m = workloads.random_model(4, 21)
+    from paper_2203_05871_amd import Chain
+
+    h = Chain(m, 0.1, 8, 1e-10, "fp64", "+x", hermitian_every=2, device="cuda:0")
+    with pytest.raises(LmpoError, match="Hermitian"):
+        Gradient(h, 2)
+    h.close()
+    ch = _chain(m, 0.1, 8, 1e-10, "+x")
+    with pytest.raises(LmpoError, match="chi_max"):
+        Gradient(ch, 2, 1, -1.0)
+    with pytest.raises(LmpoError, match="n_steps"):
+        Gradient(ch, 0)
+    G = Gradient(ch, 2)
+    before = [ch.get_site(k) for k in range(4)]
+    for bad in ("IZ", "IIII", "IZQI"):
+        with pytest.raises(LmpoError, match="paulis"):
+            G.run_string(bad)
+    with pytest.raises(LmpoError, match="distinct"):
+        G.run_connected(1, 1, "ZZ")
+    assert all(np.array_equal(a, ch.get_site(k)) for k, a in enumerate(before))
+    G.close()
+    ch.close()
