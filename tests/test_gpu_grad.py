@@ -129,6 +129,23 @@ def test_fourth_order_gradient():
     _compare(workloads.random_model(5, 8), 0.1, 2, 16, 1e-12, "+x", 0, "Z", order=4)
 
 
+def test_fp32_contraction_form_gradient():
+    """The state in the FP32-contraction form (the co-state stays real FP64): the
+    derivatives follow the oracle's to the FP32 form's tolerance."""
+    m = workloads.random_model(8, 22)
+    print("gradient case: N=8 chi=8 fp32 contraction, <Z_4>", flush=True)
+    ch = _chain(m, 0.1, 8, 1e-10, "+x", precision="fp32")
+    F, g = ch.gradient(4, 4, "Z")
+    ch.close()
+    Fo, go, _ = adjoint.gradient(m, 0.1, 4, 8, 1e-10, "+x", 4, "Z")
+    got = np.concatenate([g[k] for k in adjoint.SITE_KEYS + adjoint.BOND_KEYS])
+    ref = adjoint.flatten(m, go).real
+    err = np.abs(got - ref).max() / max(1.0, np.abs(ref).max())
+    print(f"  F error {abs(F - Fo):.2e}, max |grad - oracle| / scale = {err:.2e}", flush=True)
+    assert abs(F - Fo) < 1e-5
+    assert err < 1e-5
+
+
 def test_real_form_gradient():
     _compare(workloads.random_model(8, 9), 0.1, 4, 8, 1e-10, "+x", 4, "Z", precision="real")
 
