@@ -6,7 +6,11 @@ TEST INFRASTRUCTURE ONLY (see the package header).
 Objective: F = Tr(O rho_T) / Tr(rho_T) with O a Pauli string (sigma^a on one
 qubit as in Eq. mu, a correlator as in Eq. 2Qdef, or a longer product), or the
 connected correlator <a_i b_j> - <a_i><b_j>, after T Trotter steps from a
-fixed initial state.  Parameters: every
+fixed initial state; or a weighted sum of a string's expectations at several
+output steps (each output's gradient enters the co-state as a source when the
+backward pass reaches its step, added to the co-state MPS by a direct sum
+compressed like the Hermitian part: QR from the left, truncated identity gates
+from the right).  Parameters: every
 entry of hx, hy, hz, g0, g1, g2 (per qubit) and J, Jz (per bond) of the model
 of Sec. 2.1.  Each bond generator L_b is linear in every one of them (the
 Hamiltonian enters through a commutator, each rate multiplies its dissipator),
@@ -103,41 +107,49 @@ def transition_density(mu, rho, k):
     return g.reshape(16, 16)
 
 
+def _record_one(model, tau, n, chi_max, cutoff, order, force_trace, mps, gates=None):
+    """Step n of tebd.evolve on mps, recording every two-site gate: returns
+    (mps, [(site k, bond or None for a SWAP, fraction of tau, ascending?, copy
+    of all site tensors)], trace divided out at the step's end)."""
+    N = model["N"]
+    gates = gates if gates is not None else tebd.gate_tables(model, tau, order)
+    P = lm.swap_gate()
+    bonds = np.asarray(model["bonds"])
+    ops = []
+
+    def gate(k, G, asc, b, frac):
+        mps.apply_gate(k, G, chi_max, cutoff, asc)
+        ops.append((k, b, frac, asc, [a.copy() for a in mps.A]))
+
+    if tebd.is_chain(model):
+        for k, frac, asc in tebd.step_schedule(N, n, order):
+            gate(k, gates[(k, frac)], asc, k, frac)
+    else:
+        for b, frac, fwd in tebd.sweep_schedule(model, order):
+            i, j = int(bonds[b, 0]), int(bonds[b, 1])
+            if j == i + 1:
+                gate(i, gates[(b, frac)], fwd, b, frac)
+                continue
+            for k in range(j - 1, i, -1):
+                gate(k, P, False, None, None)
+            gate(i, gates[(b, frac)], True, b, frac)
+            for k in range(i + 1, j):
+                gate(k, P, True, None, None)
+    return mps, ops, (mps.renormalize() if force_trace else 1.0)
+
+
 def forward_record(model, tau, steps, chi_max, cutoff, init, order=2, force_trace=True):
     """The TEBD run of tebd.evolve, keeping after every two-site gate the
     record (site k, bond or None for a SWAP, fraction of tau, ascending?,
     copy of all site tensors), and the trace divided out at each step's end.
     Returns (final MPS, [records of step n], [trace of step n])."""
-    N = model["N"]
-    mps = tebd.MPS.product(init, N)
+    mps = tebd.MPS.product(init, model["N"])
     gates = tebd.gate_tables(model, tau, order)
-    P = lm.swap_gate()
-    bonds = np.asarray(model["bonds"])
-    chain = tebd.is_chain(model)
     records, traces = [], []
     for n in range(steps):
-        ops = []
-
-        def gate(k, G, asc, b, frac):
-            mps.apply_gate(k, G, chi_max, cutoff, asc)
-            ops.append((k, b, frac, asc, [a.copy() for a in mps.A]))
-
-        if chain:
-            for k, frac, asc in tebd.step_schedule(N, n, order):
-                gate(k, gates[(k, frac)], asc, k, frac)
-        else:
-            for b, frac, fwd in tebd.sweep_schedule(model, order):
-                i, j = int(bonds[b, 0]), int(bonds[b, 1])
-                if j == i + 1:
-                    gate(i, gates[(b, frac)], fwd, b, frac)
-                    continue
-                for k in range(j - 1, i, -1):
-                    gate(k, P, False, None, None)
-                gate(i, gates[(b, frac)], True, b, frac)
-                for k in range(i + 1, j):
-                    gate(k, P, True, None, None)
-        traces.append(mps.renormalize() if force_trace else 1.0)
+        _, ops, t = _record_one(model, tau, n, chi_max, cutoff, order, force_trace, mps, gates)
         records.append(ops)
+        traces.append(t)
     return mps, records, traces
 
 
@@ -171,16 +183,51 @@ def costate_terms(N, terms):
     return mu
 
 
-def backward(model, tau, records, traces, mu, chi_mu, cut_mu, order=2):
+def add_compress(mu, src, chi_mu, cut_mu):
+    """mu + src as an MPS: the direct sum of the two (bonds added, a row on the
+    first site, block-diagonal inside, a column on the last), made
+    left-orthonormal by QR from the left, then compressed from the right by the
+    truncated two-site SVD of every bond (the identity gate, usual rule).  The
+    centre ends on site 0."""
+    N = mu.N
+    A = []
+    for k, (a, b) in enumerate(zip(mu.A, src.A)):
+        if k == 0:
+            t = np.concatenate([a, b], axis=2)
+        elif k == N - 1:
+            t = np.concatenate([a, b], axis=0)
+        else:
+            t = np.zeros((a.shape[0] + b.shape[0], 4, a.shape[2] + b.shape[2]), dtype=np.complex128)
+            t[:a.shape[0], :, :a.shape[2]] = a
+            t[a.shape[0]:, :, a.shape[2]:] = b
+        A.append(t)
+    out = tebd.MPS(A, 0)
+    out.move_centre(N - 1)
+    ident = np.eye(16, dtype=np.complex128)
+    for k in range(N - 2, -1, -1):
+        out.apply_gate(k, ident, chi_mu, cut_mu, False)
+    return out
+
+
+def backward(model, tau, records, traces, mu, chi_mu, cut_mu, order=2, sources=None):
     """The co-state pass: {key: complex array of dF/dtheta} for the co-state
-    mu = mu_T (module header), which it advances back to time 0."""
+    mu = mu_T (module header), which it advances back to time 0.  sources:
+    {step n: source MPS} added when the pass reaches the end of step n (0-based),
+    each weighted by the traces divided out after that step; mu may then be
+    None (zero) until the first source."""
     gates = tebd.gate_tables(model, tau, order)
     P = lm.swap_gate()
     grads = {k: np.zeros(len(model[k]), dtype=np.complex128) for k in SITE_KEYS + BOND_KEYS}
     kcache = {}
     scale = 1.0
     for n in reversed(range(len(records))):
+        if sources and n in sources:
+            src = sources[n]
+            src.A[-1] = src.A[-1] / scale  # the traces divided out after step n
+            mu = src if mu is None else add_compress(mu, src, chi_mu, cut_mu)
         scale = scale / traces[n]
+        if mu is None:
+            continue
         for k, b, frac, asc, snap in reversed(records[n]):
             if b is None:
                 mu.apply_gate(k, P.T, chi_mu, cut_mu, not asc)
@@ -212,6 +259,40 @@ def gradient(model, tau, steps, chi_max, cutoff, init, site, pauli, order=2, for
     F = mps.expect({s: lm.PAULI[p] for s, p in ops.items()})
     mu = costate_string(model["N"], ops, F, mps.trace())
     return F, backward(model, tau, records, traces, mu, chi_mu, cut_mu, order), mps
+
+
+def gradient_series(model, tau, steps, chi_max, cutoff, init, paulis, out_steps, weights, order=2,
+                    force_trace=True, costate_chi_max=None, costate_cutoff=None):
+    """(F_k array, {key: dJ/dtheta}, final MPS) for J = sum_k w_k F_k, F_k the
+    Pauli string's expectation after out_steps[k] steps (1 <= out_steps[k] <=
+    steps, increasing).  The gradient of F_k is carried back from the end of
+    its step: the co-state gains the source w_k (o - F_k 1) / tr_k there."""
+    ops = {s: p for s, p in enumerate(paulis.upper()) if p != "I"}
+    chi_mu = chi_max if costate_chi_max is None else costate_chi_max
+    cut_mu = cutoff if costate_cutoff is None else costate_cutoff
+    N = model["N"]
+    Fk, trk = {}, {}
+    want = set(int(s) for s in out_steps)
+
+    def observe(n_done, mps):
+        if n_done in want:
+            Fk[n_done] = mps.expect({s: lm.PAULI[p] for s, p in ops.items()})
+            trk[n_done] = mps.trace()
+
+    mps = tebd.MPS.product(init, N)
+    gates = tebd.gate_tables(model, tau, order)
+    records, traces = [], []
+    # the recording forward pass, one step at a time so that the outputs can be read
+    for n in range(steps):
+        _, r1, t1 = _record_one(model, tau, n, chi_max, cutoff, order, force_trace, mps, gates)
+        records.append(r1)
+        traces.append(t1)
+        observe(n + 1, mps)
+    sources = {s - 1: costate_string(N, ops, Fk[s], trk[s]) for s in want}
+    for s, w in zip(out_steps, weights):
+        sources[int(s) - 1].A[-1] = sources[int(s) - 1].A[-1] * w
+    grads = backward(model, tau, records, traces, None, chi_mu, cut_mu, order, sources)
+    return np.array([Fk[int(s)] for s in out_steps]), grads, mps
 
 
 def gradient_connected(model, tau, steps, chi_max, cutoff, init, i, j, paulis="ZZ", order=2, force_trace=True,

@@ -250,3 +250,53 @@ def test_costate_terms_brute_force():
         ref += c * dense.contract(v, [tebd.covector(lm.PAULI[ops[k]]) if k in ops else tebd.E_ID
                                       for k in range(N)])
     assert abs(np.dot(dense.mps_to_vector(mu.A), v) - ref) <= 1e-12 * abs(ref)
+
+
+def test_series_gradient_equals_dense_trotter_derivative():
+    """J = sum_k w_k <X_1 Z_2>(t_k) over three output steps: the co-state gains a
+    source at each; every derivative against dense central differences of J."""
+    m = rich_chain(4, 23)
+    tau, steps, h = 0.1, 4, 1e-6
+    outs, ws = [1, 3, 4], [0.5, -1.2, 2.0]
+
+    def dense_J(model):
+        N = model["N"]
+        v = dense.product_vector("+x", N)
+        J = 0.0
+        for n in range(steps):
+            v = dense.trotter_evolve(v, model, tau, 1, first_step=n)
+            if n + 1 in outs:
+                J += ws[outs.index(n + 1)] * dense.expect(v, N, {1: lm.SX, 2: lm.SZ})
+        return J
+
+    F, g, _ = adjoint.gradient_series(m, tau, steps, 16, 0.0, "+x", "IXZI", outs, ws)
+    assert abs(np.dot(ws, F) - dense_J(m)) < 1e-12
+    ref = []
+    for key, idx in adjoint.parameter_list(m):
+        vals = []
+        for sgn in (1.0, -1.0):
+            mm = {k: (np.array(v, dtype=float) if k in adjoint.SITE_KEYS + adjoint.BOND_KEYS else v)
+                  for k, v in m.items()}
+            mm[key][idx] += sgn * h
+            vals.append(dense_J(mm))
+        ref.append((vals[0] - vals[1]) / (2 * h))
+    assert np.abs(adjoint.flatten(m, g) - np.array(ref)).max() < 1e-8
+
+
+def test_series_with_one_final_output_is_the_plain_gradient():
+    m = rich_chain(5, 24)
+    F1, g1, _ = adjoint.gradient(m, 0.1, 3, 8, 1e-10, "+x", None, None, paulis="IZIII")
+    F2, g2, _ = adjoint.gradient_series(m, 0.1, 3, 8, 1e-10, "+x", "IZIII", [3], [1.0])
+    assert F2[0] == F1
+    assert np.array_equal(adjoint.flatten(m, g1), adjoint.flatten(m, g2))
+
+
+def test_add_compress_is_the_sum_without_truncation():
+    rng = np.random.default_rng(25)
+    N = 5
+    mk = lambda d: tebd.MPS([rng.standard_normal((d[s], 4, d[s + 1])) + 1j * rng.standard_normal((d[s], 4, d[s + 1]))
+                             for s in range(N)], 0)
+    a, b = mk([1, 3, 4, 5, 2, 1]), mk([1, 2, 2, 2, 2, 1])
+    ref = dense.mps_to_vector(a.A) + dense.mps_to_vector(b.A)
+    out = adjoint.add_compress(a, b, 64, 0.0)
+    assert np.abs(dense.mps_to_vector(out.A) - ref).max() < 1e-12 * np.abs(ref).max()
