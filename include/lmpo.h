@@ -350,17 +350,24 @@ int lmpo_batch_destroy(lmpo_batch *b);
  * force_hermitian_every > 0, chi_max < 2. */
 typedef struct lmpo_grad lmpo_grad;
 
+/* Workspace flags.  LMPO_GRAD_SERIES: room for lmpo_grad_run_series, whose
+ * outputs enter the co-state as sources (its bond capacities doubled, arena
+ * about 4x, co-state chi_max <= 256). */
+enum { LMPO_GRAD_SERIES = 1 };
+
 /* Device bytes of the workspace for n_steps >= 1 steps of s (0 on invalid
  * input).  costate_chi_max <= 0 and costate_cutoff < 0 take the state's
- * values; the co-state's chi_max must be 2..512. */
-size_t lmpo_grad_arena_bytes(lmpo_state *s, int32_t n_steps, int32_t costate_chi_max, double costate_cutoff);
+ * values; the co-state's chi_max must be 2..512.  flags: 0 or
+ * LMPO_GRAD_SERIES. */
+size_t lmpo_grad_arena_bytes(lmpo_state *s, int32_t n_steps, int32_t costate_chi_max, double costate_cutoff,
+                             int32_t flags);
 
 /* Builds the workspace: creates the co-state in it, transposes its gate table,
  * and tabulates K for every bond, used time fraction and parameter on the host
  * (the Frechet derivative of the exponential as the upper-right block of the
  * exponential of [[x L, x dL], [0, x L]]).  Synchronises.  The state must
  * outlive the workspace. */
-int lmpo_grad_create(lmpo_state *s, int32_t n_steps, int32_t costate_chi_max, double costate_cutoff,
+int lmpo_grad_create(lmpo_state *s, int32_t n_steps, int32_t costate_chi_max, double costate_cutoff, int32_t flags,
                      void *device_arena, size_t arena_bytes, lmpo_grad **out);
 
 /* Advances the state by the workspace's n_steps exactly as lmpo_evolve_step
@@ -374,6 +381,21 @@ int lmpo_grad_create(lmpo_state *s, int32_t n_steps, int32_t costate_chi_max, do
  * before the state moves; after an error met later (LMPO_EHIP, LMPO_ENUMERIC)
  * the state's tensors are unspecified. */
 int lmpo_grad_run(lmpo_grad *g, const char *paulis, double F[2], double *grad_out);
+
+/* As lmpo_grad_run for J = sum_k weights[k] Re <O>(t_k), t_k the state after
+ * out_steps[k] steps (n_out >= 1 entries, strictly increasing within
+ * 1..n_steps): the time series the paper's observables are.  F_out[k] =
+ * <O>(t_k) as (re, im) ([n_out][2]), grad_out = dJ/dtheta.  When the backward
+ * pass reaches the end of step out_steps[k], the co-state gains that output's
+ * source w_k (o - F_k 1) / tr_k (times the traces divided out after it): the
+ * direct sum of the co-state and the bond-2 source, compressed like the
+ * Hermitian part (exact QR from the left, truncated identity gates from the
+ * right, the co-state's chi_max and cutoff).  Before the last output the
+ * co-state is zero and the steps after it are skipped.  Needs a workspace
+ * created with LMPO_GRAD_SERIES (LMPO_EUNSUPPORTED otherwise).  A single output
+ * at n_steps with weight 1 gives lmpo_grad_run's result bit for bit. */
+int lmpo_grad_run_series(lmpo_grad *g, const char *paulis, int32_t n_out, const int32_t *out_steps,
+                         const double *weights, double *F_out, double *grad_out);
 
 /* As lmpo_grad_run for the connected correlator C = <a_i b_j> - <a_i><b_j>
  * (the paper's connected two-qubit function) with paulis = "ab" (two of X,

@@ -140,4 +140,48 @@ void launch_grad_accumulate(hipStream_t s, const double2 *K, const int *pidx, in
   (void)hipGetLastError();
 }
 
+// Site k of the MPS sum A + B (the co-state plus an output's source): A from a
+// copy of the site (bond dims `dims`, before the sum), B with bond kb; the
+// sum's site is a row [A B] on the first site, a column [A; B] on the last,
+// block-diagonal inside.  Grid-stride over the summed site.
+__global__ void mps_sum_site_kernel(const double2 *__restrict__ A, const double2 *__restrict__ B,
+                                    double2 *__restrict__ dst, const int *dims, int N, int k, int kb) {
+  const int cl = k == 0 ? 1 : dims[k - 1], cr = k == N - 1 ? 1 : dims[k];
+  const bool first = k == 0, last = k == N - 1;
+  const int bl = first ? 1 : kb, br = last ? 1 : kb;
+  const int nl = first ? 1 : cl + kb, nr = last ? 1 : cr + kb;
+  const size_t n = (size_t)nl * 4 * nr;
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    const int r = (int)(e % nr), a = (int)((e / nr) % 4), l = (int)(e / ((size_t)4 * nr));
+    double2 v = make_double2(0.0, 0.0);
+    const bool la = first || l < cl, ra = last || r < cr;  // index inside A's block
+    if (la && ra) {
+      v = A[((size_t)l * 4 + a) * cr + r];
+    } else if (!la && !ra) {
+      v = B[((size_t)(l - cl) * 4 + a) * br + (r - cr)];
+    } else if (first && !ra) {
+      v = B[((size_t)a) * br + (r - cr)];
+    } else if (last && !la) {
+      v = B[((size_t)(l - cl) * 4 + a) * br];
+    }
+    (void)bl;
+    dst[e] = v;
+  }
+}
+
+__global__ void add_dims_kernel(int *dims, int n, int add) {
+  for (int b = threadIdx.x; b < n; b += blockDim.x) dims[b] += add;
+}
+
+void launch_mps_sum_site(hipStream_t s, const double2 *A, const double2 *B, double2 *dst, const int *dims, int N,
+                         int k, int kb) {
+  hipLaunchKernelGGL(mps_sum_site_kernel, dim3(256), dim3(256), 0, s, A, B, dst, dims, N, k, kb);
+  (void)hipGetLastError();
+}
+
+void launch_add_dims(hipStream_t s, int *dims, int n, int add) {
+  hipLaunchKernelGGL(add_dims_kernel, dim3(1), dim3(64), 0, s, dims, n, add);
+  (void)hipGetLastError();
+}
+
 }  // namespace lmpo

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <mutex>
 #include <string>
@@ -1740,6 +1741,8 @@ struct lmpo_grad {
   double2 *K = nullptr;  // [nb][kGateSlots][kGradLocal][16][16]
   int *pidx = nullptr;   // [nb][kGradLocal] global parameter index
   double2 *grad = nullptr, *traces = nullptr, *one = nullptr;
+  double2 *src = nullptr;  // an output's source MPS (bond 2), [N][16]
+  bool series = false;     // co-state capacities doubled for sources
   double *disc_save = nullptr;
   int *stats_save = nullptr;
   std::vector<int> ckpt_centre;
@@ -1791,7 +1794,8 @@ std::vector<int> grad_slots(const lmpo_state *S) {
 size_t grad_layout(lmpo_grad *G, const lmpo_state *S, int n_steps, const lmpo_options &co_opt, char *base,
                    size_t size, char **co, size_t co_bytes) {
   Arena a{base, size};
-  const size_t cm = (size_t)std::max(S->cap_max, compute_sizes(S->N, co_opt.chi_max, 1).cap_max);
+  const int co_mult = co_opt.force_hermitian_every > 0 ? 2 : 1;
+  const size_t cm = (size_t)std::max(S->cap_max, compute_sizes(S->N, co_opt.chi_max, co_mult).cap_max);
   *co = a.take<char>(co_bytes);
   G->snap = snapshot_bytes(S);
   G->max_ops = grad_ops_per_step(S);
@@ -1811,6 +1815,7 @@ size_t grad_layout(lmpo_grad *G, const lmpo_state *S, int n_steps, const lmpo_op
   G->grad = a.take<double2>(G->P);
   G->traces = a.take<double2>(n_steps);
   G->one = a.take<double2>(1);
+  G->src = a.take<double2>((size_t)S->N * 16);
   G->disc_save = a.take<double>(1);
   G->stats_save = a.take<int>(kStats);
   return a.used;
@@ -1818,7 +1823,7 @@ size_t grad_layout(lmpo_grad *G, const lmpo_state *S, int n_steps, const lmpo_op
 
 // Controls of the co-state: the state's, with chi_max and cutoff replaced
 // where the caller gives them (chi_max > 0, cutoff >= 0).
-int grad_check(const lmpo_state *S, int n_steps, int co_chi, double co_cut, lmpo_options *co_opt) {
+int grad_check(const lmpo_state *S, int n_steps, int co_chi, double co_cut, int flags, lmpo_options *co_opt) {
   if (!S) return fail(LMPO_EINVAL, "state is null");
   if (n_steps < 1) return fail(LMPO_EINVAL, "n_steps must be >= 1");
   if (S->opt.force_hermitian_every > 0)
@@ -1833,6 +1838,14 @@ int grad_check(const lmpo_state *S, int n_steps, int co_chi, double co_cut, lmpo
   if (co_cut >= 0) co_opt->cutoff = co_cut;
   if (co_opt->chi_max < 2) return fail(LMPO_EUNSUPPORTED, "the co-state needs chi_max >= 2 (it starts at bond 2)");
   if (co_opt->chi_max > kMaxDim / 4) return fail(LMPO_EUNSUPPORTED, "costate_chi_max above 512 is not supported");
+  if (flags & ~LMPO_GRAD_SERIES) return fail(LMPO_EINVAL, "unknown gradient flags");
+  if (flags & LMPO_GRAD_SERIES) {
+    // room for an output's source beside the co-state: the bond capacities
+    // doubled (the co-state never takes a step, so no Hermitian part is formed)
+    if (co_opt->chi_max > kMaxDim / 8)
+      return fail(LMPO_EUNSUPPORTED, "LMPO_GRAD_SERIES needs a co-state chi_max <= 256");
+    co_opt->force_hermitian_every = 1;
+  }
   return LMPO_OK;
 }
 
@@ -1957,16 +1970,10 @@ struct CostateTerm {
   double c;
   std::vector<int> a;
 };
-int init_costate(lmpo_grad *G, const std::vector<CostateTerm> &terms, bool canonical) {
-  lmpo_state *C = G->C;
-  const int N = C->N, K = (int)terms.size();
-  if (K < 1 || K > 4) return fail(LMPO_EINVAL, "internal: co-state of 1 to 4 product terms");
-  for (int b = 0; b < N - 1; ++b)
-    if (C->cap[b] < K)
-      return fail(LMPO_EUNSUPPORTED, "this objective's co-state starts at bond " + std::to_string(K) +
-                                         ": the co-state's chi_max must be at least that");
+void terms_host(int N, const std::vector<CostateTerm> &terms, std::vector<std::vector<double2>> &host) {
+  const int K = (int)terms.size();
   const double r2 = std::sqrt(2.0);
-  std::vector<std::vector<double2>> host(N);
+  host.assign(N, {});
   for (int s = 0; s < N; ++s) {
     const int nl = s == 0 ? 1 : K, nr = s == N - 1 ? 1 : K;
     host[s].assign((size_t)nl * 4 * nr, make_double2(0.0, 0.0));
@@ -1977,6 +1984,18 @@ int init_costate(lmpo_grad *G, const std::vector<CostateTerm> &terms, bool canon
       e.x += v;
     }
   }
+}
+
+int init_costate(lmpo_grad *G, const std::vector<CostateTerm> &terms, bool canonical) {
+  lmpo_state *C = G->C;
+  const int N = C->N, K = (int)terms.size();
+  if (K < 1 || K > 4) return fail(LMPO_EINVAL, "internal: co-state of 1 to 4 product terms");
+  for (int b = 0; b < N - 1; ++b)
+    if (C->cap[b] < K)
+      return fail(LMPO_EUNSUPPORTED, "this objective's co-state starts at bond " + std::to_string(K) +
+                                         ": the co-state's chi_max must be at least that");
+  std::vector<std::vector<double2>> host;
+  terms_host(N, terms, host);
   for (int s = 0; s < N; ++s)
     HIP_TRY(hipMemcpyAsync(C->site[s], host[s].data(), host[s].size() * sizeof(double2), hipMemcpyHostToDevice,
                            C->stream));
@@ -1985,6 +2004,35 @@ int init_costate(lmpo_grad *G, const std::vector<CostateTerm> &terms, bool canon
   HIP_TRY(hipStreamSynchronize(C->stream));
   C->centre = 0;
   return canonical ? move_centre(C, N - 1) : LMPO_OK;
+}
+
+// mu <- mu + sum_k c_k prod_s v_{k,s} (two terms: an output's source): the
+// direct sum of the co-state and the source (bonds + 2, in the capacity the
+// series flag doubled), an exact QR sweep from the left, then the truncated
+// two-site SVD of every bond from the right (the identity gate, the
+// co-state's chi_max and cutoff).  The centre ends on site 0.
+int add_costate_source(lmpo_grad *G, const std::vector<CostateTerm> &terms) {
+  lmpo_state *C = G->C;
+  const int N = C->N;
+  if (terms.size() != 2) return fail(LMPO_EINVAL, "internal: a source has two product terms");
+  std::vector<std::vector<double2>> host;
+  terms_host(N, terms, host);
+  for (int s = 0; s < N; ++s)
+    HIP_TRY(hipMemcpyAsync(G->src + (size_t)s * 16, host[s].data(), host[s].size() * sizeof(double2),
+                           hipMemcpyHostToDevice, C->stream));
+  for (int k = 0; k < N; ++k) {
+    HIP_TRY(hipMemcpyAsync(C->T, C->site[k], C->site_elems[k] * sizeof(double2), hipMemcpyDeviceToDevice,
+                           C->stream));
+    launch_mps_sum_site(C->stream, C->T, G->src + (size_t)k * 16, C->site[k], C->d_dims, N, k, 2);
+    HIP_TRY(hipGetLastError());
+  }
+  launch_add_dims(C->stream, C->d_dims, N - 1, 2);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(C->stream));  // the host copies of the source outlive their upload
+  C->centre = 0;
+  int rc = move_centre(C, N - 1);
+  for (int k = N - 2; k >= 0 && !rc; --k) rc = apply_gate_dev(C, k, C->d_ident, 0);
+  return rc;
 }
 
 // <o, rho> for the Pauli string a on the state as it stands: o goes into the
@@ -2007,9 +2055,10 @@ int string_expectation_numerator(lmpo_grad *G, const std::vector<int> &a, std::c
 
 extern "C" {
 
-size_t lmpo_grad_arena_bytes(lmpo_state *S, int32_t n_steps, int32_t costate_chi_max, double costate_cutoff) {
+size_t lmpo_grad_arena_bytes(lmpo_state *S, int32_t n_steps, int32_t costate_chi_max, double costate_cutoff,
+                             int32_t flags) {
   lmpo_options co_opt;
-  if (grad_check(S, n_steps, costate_chi_max, costate_cutoff, &co_opt)) return 0;
+  if (grad_check(S, n_steps, costate_chi_max, costate_cutoff, flags, &co_opt)) return 0;
   const size_t co = costate_bytes(S, co_opt);
   if (co == 0) return 0;
   lmpo_grad tmp;
@@ -2018,12 +2067,12 @@ size_t lmpo_grad_arena_bytes(lmpo_state *S, int32_t n_steps, int32_t costate_chi
   return grad_layout(&tmp, S, n_steps, co_opt, nullptr, 0, &dummy, co) + 256;
 }
 
-int lmpo_grad_create(lmpo_state *S, int32_t n_steps, int32_t costate_chi_max, double costate_cutoff,
+int lmpo_grad_create(lmpo_state *S, int32_t n_steps, int32_t costate_chi_max, double costate_cutoff, int32_t flags,
                      void *device_arena, size_t arena_bytes, lmpo_grad **out) {
   if (!out) return fail(LMPO_EINVAL, "out is null");
   *out = nullptr;
   lmpo_options co_opt;
-  int rc = grad_check(S, n_steps, costate_chi_max, costate_cutoff, &co_opt);
+  int rc = grad_check(S, n_steps, costate_chi_max, costate_cutoff, flags, &co_opt);
   if (rc) return rc;
   if (!device_arena) return fail(LMPO_EINVAL, "device_arena is null");
   if (reinterpret_cast<uintptr_t>(device_arena) % 256) return fail(LMPO_EINVAL, "device_arena must be 256-byte aligned");
@@ -2032,6 +2081,7 @@ int lmpo_grad_create(lmpo_state *S, int32_t n_steps, int32_t costate_chi_max, do
   lmpo_grad *G = new lmpo_grad();
   G->S = S;
   G->n_steps = n_steps;
+  G->series = (flags & LMPO_GRAD_SERIES) != 0;
   char *co_arena = nullptr;
   const size_t need =
       grad_layout(G, S, n_steps, co_opt, reinterpret_cast<char *>(device_arena), arena_bytes, &co_arena, co);
@@ -2075,7 +2125,8 @@ namespace {
 // Forward run of the gradient: the state advances by the workspace's steps
 // with a snapshot at every step start and one of the final state; the traces
 // divided out per step and tr(rho_T) come back to the host.
-int grad_forward(lmpo_grad *G, long long &step0, std::complex<double> &trT, std::vector<double2> &tr_host) {
+int grad_forward(lmpo_grad *G, long long &step0, std::complex<double> &trT, std::vector<double2> &tr_host,
+                 const std::function<int(int)> &observe = nullptr) {
   lmpo_state *S = G->S;
   const int N = S->N, T = G->n_steps;
   hipStream_t st = S->stream;
@@ -2087,6 +2138,7 @@ int grad_forward(lmpo_grad *G, long long &step0, std::complex<double> &trT, std:
     G->ckpt_centre[n] = S->centre;
     if ((rc = one_step(S, step0 + n))) return rc;
     if (S->opt.force_trace) HIP_TRY(hipMemcpyAsync(G->traces + n, S->tr, sizeof(double2), hipMemcpyDeviceToDevice, st));
+    if (observe && (rc = observe(n + 1))) return rc;  // after n + 1 steps
   }
   if ((rc = save_snapshot(S, G->ckpt + (size_t)T * G->snap))) return rc;
   G->ckpt_centre[T] = S->centre;
@@ -2109,7 +2161,12 @@ int grad_forward(lmpo_grad *G, long long &step0, std::complex<double> &trT, std:
 // last, replay with gate snapshots, then the gates in reverse (transition
 // density, contributions, transposed gate).  Leaves the state as after the
 // forward run and writes the real parts of the gradient.
-int grad_backward(lmpo_grad *G, long long step0, const std::vector<double2> &tr_host, double *grad_out) {
+// sources[n] (when given and not empty): two product terms added to the
+// co-state when the pass reaches the end of step n, scaled by the traces
+// divided out after step n; the co-state is zero (and the steps skipped)
+// until the first of them unless `live`.
+int grad_backward(lmpo_grad *G, long long step0, const std::vector<double2> &tr_host, double *grad_out,
+                  const std::vector<std::vector<CostateTerm>> *sources = nullptr, bool live = true) {
   lmpo_state *S = G->S, *C = G->C;
   const int N = S->N, T = G->n_steps;
   hipStream_t st = S->stream;
@@ -2117,6 +2174,15 @@ int grad_backward(lmpo_grad *G, long long step0, const std::vector<double2> &tr_
   std::complex<double> scale = 1.0;
   std::vector<int> rd;
   for (int n = T - 1; n >= 0; --n) {
+    if (sources && !(*sources)[n].empty()) {
+      std::vector<CostateTerm> terms = (*sources)[n];
+      for (CostateTerm &t : terms) t.c /= scale.real();  // times the traces divided out after step n
+      rc = live ? add_costate_source(G, terms) : init_costate(G, terms, true);
+      if (rc) return rc;
+      live = true;
+    }
+    scale /= std::complex<double>(tr_host[n].x, tr_host[n].y);
+    if (!live) continue;  // zero co-state: nothing to carry back yet
     if ((rc = load_snapshot(S, G->ckpt + (size_t)n * G->snap))) return rc;
     S->centre = G->ckpt_centre[n];
     G->rec.ops.clear();
@@ -2130,7 +2196,6 @@ int grad_backward(lmpo_grad *G, long long step0, const std::vector<double2> &tr_
       HIP_TRY(hipMemcpyAsync(&rd[(size_t)i * (N - 1)], G->rec.slots + (size_t)i * G->rec.stride +
                              snapshot_dims_offset(S), (N - 1) * sizeof(int), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    scale /= std::complex<double>(tr_host[n].x, tr_host[n].y);
     for (int i = nops - 1; i >= 0; --i) {
       const OpRecord &op = G->rec.ops[i];
       if (op.bond < 0) {
@@ -2204,6 +2269,63 @@ int lmpo_grad_run(lmpo_grad *G, const char *paulis, double F_out[2], double *gra
   if ((rc = grad_backward(G, step0, tr_host, grad_out))) return rc;
   F_out[0] = fo[0];
   F_out[1] = fo[1];
+  return LMPO_OK;
+}
+
+int lmpo_grad_run_series(lmpo_grad *G, const char *paulis, int32_t n_out, const int32_t *out_steps,
+                         const double *weights, double *F_out, double *grad_out) {
+  if (!G || !paulis || !out_steps || !weights || !F_out || !grad_out) return fail(LMPO_EINVAL, "null argument");
+  if (!G->series) return fail(LMPO_EUNSUPPORTED, "create the workspace with LMPO_GRAD_SERIES for output sources");
+  lmpo_state *S = G->S;
+  const int N = S->N, T = G->n_steps;
+  if (std::strlen(paulis) != (size_t)N) return fail(LMPO_EINVAL, "paulis must hold one of I, X, Y, Z per qubit");
+  std::vector<int> a(N);
+  std::vector<int> req;
+  for (int s = 0; s < N; ++s) {
+    a[s] = pauli_index(paulis[s]);
+    if (a[s] < 0) return fail(LMPO_EINVAL, "paulis must hold one of I, X, Y, Z per qubit");
+    if (a[s] > 0) req.insert(req.end(), {s, a[s]});
+  }
+  if (req.empty()) return fail(LMPO_EINVAL, "paulis must name at least one X, Y or Z");
+  if (n_out < 1) return fail(LMPO_EINVAL, "n_out must be >= 1");
+  std::vector<int> slot(T + 1, -1);  // output index of the state after n steps
+  for (int k = 0; k < n_out; ++k) {
+    if (out_steps[k] < 1 || out_steps[k] > T || (k > 0 && out_steps[k] <= out_steps[k - 1]))
+      return fail(LMPO_EINVAL, "out_steps must increase strictly within 1..n_steps");
+    if (!std::isfinite(weights[k])) return fail(LMPO_EINVAL, "non-finite weight");
+    slot[out_steps[k]] = k;
+  }
+  if (req.size() == 2) req.insert(req.end(), {-1, 0});
+  std::vector<double> F(2 * (size_t)n_out), trk(n_out);
+  auto observe = [&](int done) -> int {
+    const int k = slot[done];
+    if (k < 0) return LMPO_OK;
+    launch_trace(S->stream, S->d_sites, S->d_dims, N, S->tr);
+    double2 t;
+    HIP_TRY(hipMemcpyAsync(&t, S->tr, sizeof(double2), hipMemcpyDeviceToHost, S->stream));
+    HIP_TRY(hipStreamSynchronize(S->stream));
+    trk[k] = t.x;
+    if (req.size() <= 4) return run_measure(S, req, &F[2 * (size_t)k]);
+    std::complex<double> num;
+    int rc = string_expectation_numerator(G, a, num);
+    const std::complex<double> f = num / std::complex<double>(t.x, t.y);
+    F[2 * (size_t)k] = f.real();
+    F[2 * (size_t)k + 1] = f.imag();
+    return rc;
+  };
+  long long step0;
+  std::complex<double> trT;
+  std::vector<double2> tr_host;
+  int rc = grad_forward(G, step0, trT, tr_host, observe);
+  if (rc) return rc;
+  // the source of output k: w_k (o - F_k 1) / tr_k at the end of its step
+  std::vector<std::vector<CostateTerm>> sources(T);
+  for (int k = 0; k < n_out; ++k) {
+    const double w = weights[k];
+    sources[out_steps[k] - 1] = {{w / trk[k], a}, {-(w * F[2 * (size_t)k]) / trk[k], std::vector<int>(N, 0)}};
+  }
+  if ((rc = grad_backward(G, step0, tr_host, grad_out, &sources, false))) return rc;
+  std::copy(F.begin(), F.end(), F_out);
   return LMPO_OK;
 }
 

@@ -132,5 +132,10 @@ void launch_zgemm(hipStream_t s, const ZgemmArgs &g, int batch);
 void launch_transition_reduce(hipStream_t s, const double2 *E, const double2 *Fr, int pm, int qm, double2 *gam);
 void launch_grad_accumulate(hipStream_t s, const double2 *K, const int *pidx, int nk, const double2 *gam,
                             double2 scale, double2 *grad);
+// Site k of A + B (A: a copy of the site before the sum, bond dims `dims`;
+// B: bond kb) into dst; then add_dims raises every bond by kb.
+void launch_mps_sum_site(hipStream_t s, const double2 *A, const double2 *B, double2 *dst, const int *dims, int N,
+                         int k, int kb);
+void launch_add_dims(hipStream_t s, int *dims, int n, int add);
 
 }  // namespace lmpo

@@ -69,7 +69,7 @@ EXPORTS = [
     "lmpo_batch_arena_bytes", "lmpo_batch_create", "lmpo_batch_evolve_step", "lmpo_batch_sync",
     "lmpo_batch_plan", "lmpo_batch_profile_begin", "lmpo_batch_profile_end", "lmpo_batch_destroy",
     "lmpo_batch_set_autotune", "lmpo_autotune_table",
-    "lmpo_grad_arena_bytes", "lmpo_grad_create", "lmpo_grad_run", "lmpo_grad_costate_dims", "lmpo_grad_costate", "lmpo_grad_run_connected",
+    "lmpo_grad_arena_bytes", "lmpo_grad_create", "lmpo_grad_run", "lmpo_grad_costate_dims", "lmpo_grad_costate", "lmpo_grad_run_connected", "lmpo_grad_run_series",
     "lmpo_probe_fp64_mfma_bytes", "lmpo_probe_fp64_mfma",
     "lmpo_grad_destroy",
 ]
@@ -129,8 +129,9 @@ def load_library(path: str = LIB_PATH):
         "lmpo_batch_destroy": (ctypes.c_int, [P]),
         "lmpo_batch_set_autotune": (ctypes.c_int, [P, i32]),
         "lmpo_autotune_table": (ctypes.c_int, [i32, pi32, pi32, pi32, pdbl, pi32]),
-        "lmpo_grad_arena_bytes": (ctypes.c_size_t, [P, i32, i32, dbl]),
-        "lmpo_grad_create": (ctypes.c_int, [P, i32, i32, dbl, P, ctypes.c_size_t, ctypes.POINTER(P)]),
+        "lmpo_grad_arena_bytes": (ctypes.c_size_t, [P, i32, i32, dbl, i32]),
+        "lmpo_grad_create": (ctypes.c_int, [P, i32, i32, dbl, i32, P, ctypes.c_size_t, ctypes.POINTER(P)]),
+        "lmpo_grad_run_series": (ctypes.c_int, [P, ctypes.c_char_p, i32, pi32, pdbl, pdbl, pdbl]),
         "lmpo_grad_costate_dims": (ctypes.c_int, [P, pi32]),
         "lmpo_grad_costate": (P, [P]),
         "lmpo_grad_run_connected": (ctypes.c_int, [P, i32, i32, ctypes.c_char_p, pdbl, pdbl]),
@@ -416,12 +417,12 @@ class Gradient:
     """Adjoint-gradient workspace of one chain for a fixed number of steps
     (lmpo_grad_*).  Each run() advances the chain by those steps."""
 
-    def __init__(self, chain, n_steps, costate_chi_max=0, costate_cutoff=-1.0):
+    def __init__(self, chain, n_steps, costate_chi_max=0, costate_cutoff=-1.0, series=False):
         import torch
 
         lib = load_library()
         self.chain, self.n_steps = chain, int(n_steps)
-        co = (int(costate_chi_max), float(costate_cutoff))
+        co = (int(costate_chi_max), float(costate_cutoff), 1 if series else 0)
         n = lib.lmpo_grad_arena_bytes(chain._h, self.n_steps, *co)
         if n == 0:
             raise LmpoError(-1, lib.lmpo_last_error().decode())
@@ -447,6 +448,20 @@ class Gradient:
         g = np.zeros(6 * self.chain.N + 2 * self.n_bonds)
         _check(self._lib.lmpo_grad_run(self._h, paulis.upper().encode(), _dptr(F), _dptr(g)))
         return self._unpack(F, g)
+
+    def run_series(self, paulis, out_steps, weights):
+        """(F_k array, {key: dJ/dtheta}) for J = sum_k w_k Re <paulis> after out_steps[k]
+        steps (needs series=True at creation)."""
+        outs = np.ascontiguousarray(out_steps, dtype=np.int32)
+        w = np.ascontiguousarray(weights, dtype=np.float64)
+        if len(w) != len(outs):
+            raise ValueError("one weight per output step")
+        F = np.zeros((len(outs), 2))
+        g = np.zeros(6 * self.chain.N + 2 * self.n_bonds)
+        _check(self._lib.lmpo_grad_run_series(self._h, paulis.upper().encode(), len(outs), _iptr(outs), _dptr(w),
+                                              _dptr(F), _dptr(g)))
+        _, out = self._unpack(np.zeros(2), g)
+        return F[:, 0] + 1j * F[:, 1], out
 
     def run_connected(self, i, j, paulis="ZZ"):
         """(C, {key: dC/dtheta}) for the connected correlator <a_i b_j> - <a_i><b_j>."""

@@ -68,10 +68,11 @@ def test_gradient_entry_points_reject_bad_arguments_on_host():
     from paper_2203_05871_amd import lmpo
 
     lib = lmpo.load_library()
-    assert lib.lmpo_grad_arena_bytes(None, 4, 0, -1.0) == 0
+    assert lib.lmpo_grad_arena_bytes(None, 4, 0, -1.0, 0) == 0
     assert b"state is null" in lib.lmpo_last_error()
     out = ctypes.c_void_p()
-    assert lib.lmpo_grad_create(None, 4, 0, -1.0, None, 0, ctypes.byref(out)) == -1
+    assert lib.lmpo_grad_create(None, 4, 0, -1.0, 0, None, 0, ctypes.byref(out)) == -1
+    assert lib.lmpo_grad_run_series(None, b"IZ", 1, None, None, None, None) == -1
     assert lib.lmpo_grad_costate_dims(None, None) == -1
     assert lib.lmpo_grad_costate(None) is None
     assert lib.lmpo_grad_run_connected(None, 0, 1, b"ZZ", None, None) == -1

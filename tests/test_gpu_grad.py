@@ -13,10 +13,10 @@ from oracle import adjoint
 pytestmark = pytest.mark.gpu
 
 
-def Gradient(chain, n_steps, co_chi=0, co_cut=-1.0):
+def Gradient(chain, n_steps, co_chi=0, co_cut=-1.0, series=False):
     from paper_2203_05871_amd import Gradient as G
 
-    return G(chain, n_steps, co_chi, co_cut)
+    return G(chain, n_steps, co_chi, co_cut, series)
 
 
 def _chain(m, tau, chi, cutoff, init, precision="fp64", order=2, force_trace=True):
@@ -293,5 +293,65 @@ def test_gradient_error_paths():
     with pytest.raises(LmpoError, match="distinct"):
         G.run_connected(1, 1, "ZZ")
     assert all(np.array_equal(a, ch.get_site(k)) for k, a in enumerate(before))
+    G.close()
+    ch.close()
+
+
+@pytest.mark.parametrize("ladder", [False, True])
+def test_series_gradient(ladder):
+    """J = sum_k w_k <O>(t_k) over several output steps: each output's source
+    enters the co-state (MPS sum + compression) when the backward pass reaches
+    it; against the oracle's series gradient."""
+    if ladder:
+        m = workloads.random_model(6, 26, bonds=workloads.ladder_model(3)["bonds"])
+        tau, steps, chi, cut, init, paulis, outs, ws = 0.1, 4, 16, 1e-12, "+z", "XIZIIY", [2, 3], [1.5, -0.4]
+    else:
+        m = workloads.random_model(8, 27)
+        tau, steps, chi, cut, init, paulis, outs, ws = 0.1, 5, 8, 1e-10, "+x", "IIZIIIII", [1, 2, 4], [0.3, -1.0, 0.7]
+    print(f"gradient case: series {paulis} at {outs}, ladder={ladder}", flush=True)
+    ch = _chain(m, tau, chi, cut, init)
+    G = Gradient(ch, steps, series=True)
+    F, g = G.run_series(paulis, outs, ws)
+    G.close()
+    ch.close()
+    Fo, go, _ = adjoint.gradient_series(m, tau, steps, chi, cut, init, paulis, outs, ws)
+    got = np.concatenate([g[k] for k in adjoint.SITE_KEYS + adjoint.BOND_KEYS])
+    ref = adjoint.flatten(m, go).real
+    err = np.abs(got - ref).max() / max(1.0, np.abs(ref).max())
+    print(f"  F_k error {np.abs(F - Fo).max():.2e}, max |grad - oracle| / scale = {err:.2e}", flush=True)
+    assert np.abs(F - Fo).max() < 1e-11
+    assert err < 1e-9
+
+
+def test_series_with_one_final_output_is_the_plain_gradient():
+    m = workloads.random_model(6, 28)
+    a = _chain(m, 0.1, 8, 1e-10, "+x")
+    b = _chain(m, 0.1, 8, 1e-10, "+x")
+    Ga, Gb = Gradient(a, 3, series=True), Gradient(b, 3)
+    Fa, ga = Ga.run_series("IIZIII", [3], [1.0])
+    Fb, gb = Gb.run_string("IIZIII")
+    assert Fa[0] == Fb
+    for k in ga:
+        assert np.array_equal(ga[k], gb[k])
+    Ga.close()
+    Gb.close()
+    a.close()
+    b.close()
+
+
+def test_series_argument_checks():
+    from paper_2203_05871_amd import LmpoError
+
+    ch = _chain(workloads.random_model(4, 29), 0.1, 8, 1e-10, "+x")
+    G = Gradient(ch, 3)
+    with pytest.raises(LmpoError, match="LMPO_GRAD_SERIES"):
+        G.run_series("IZII", [3], [1.0])
+    G.close()
+    G = Gradient(ch, 3, series=True)
+    before = [ch.get_site(k) for k in range(4)]
+    for outs in ([0], [4], [2, 2], [3, 1]):
+        with pytest.raises(LmpoError, match="out_steps"):
+            G.run_series("IZII", outs, [1.0] * len(outs))
+    assert all(np.array_equal(x, ch.get_site(k)) for k, x in enumerate(before))
     G.close()
     ch.close()
