@@ -391,7 +391,8 @@ int lmpo_grad_run(lmpo_grad *g, const char *paulis, double F[2], double *grad_ou
  * direct sum of the co-state and the bond-2 source, compressed like the
  * Hermitian part (exact QR from the left, truncated identity gates from the
  * right, the co-state's chi_max and cutoff).  Before the last output the
- * co-state is zero and the steps after it are skipped.  Needs a workspace
+ * co-state is zero and the steps after it are skipped; outputs of weight 0
+ * add nothing (all weights 0: the values alone, a zero gradient).  Needs a workspace
  * created with LMPO_GRAD_SERIES (LMPO_EUNSUPPORTED otherwise).  A single output
  * at n_steps with weight 1 gives lmpo_grad_run's result bit for bit. */
 int lmpo_grad_run_series(lmpo_grad *g, const char *paulis, int32_t n_out, const int32_t *out_steps,

@@ -2322,9 +2322,10 @@ int lmpo_grad_run_series(lmpo_grad *G, const char *paulis, int32_t n_out, const 
   std::vector<std::vector<CostateTerm>> sources(T);
   for (int k = 0; k < n_out; ++k) {
     const double w = weights[k];
+    if (w == 0.0) continue;  // no source (a zero co-state is never formed: all-zero weights give a zero gradient)
     sources[out_steps[k] - 1] = {{w / trk[k], a}, {-(w * F[2 * (size_t)k]) / trk[k], std::vector<int>(N, 0)}};
   }
-  if ((rc = grad_backward(G, step0, tr_host, grad_out, &sources, false))) return rc;
+  if ((rc = grad_backward(G, step0, tr_host, grad_out, &sources, false))) return rc;  // restores the state
   std::copy(F.begin(), F.end(), F_out);
   return LMPO_OK;
 }

@@ -613,7 +613,60 @@ def _expectation_function():
     return ExpectationFn
 
 
+def _series_function():
+    import torch
+
+    def run(spec, params, weights):
+        model = {"N": spec["N"], "bonds": spec["bonds"]}
+        for key, t in zip(GRAD_SITE_KEYS + GRAD_BOND_KEYS, params):
+            model[key] = t.detach().to("cpu", torch.float64).numpy().reshape(-1)
+        ch = Chain(model, spec["tau"], spec["chi_max"], spec.get("cutoff", 0.0), spec.get("precision", "fp64"),
+                   spec.get("init", "+z"), force_trace=spec.get("force_trace", True), order=spec.get("order", 2),
+                   device=spec.get("device", "cuda:0"))
+        try:
+            G = Gradient(ch, spec["steps"], spec.get("costate_chi_max", 0), spec.get("costate_cutoff", -1.0), True)
+            try:
+                return G.run_series(spec["paulis"], spec["out_steps"], weights)
+            finally:
+                G.close()
+        finally:
+            ch.close()
+
+    class ExpectationSeriesFn(torch.autograd.Function):
+        """F_k = Re <paulis> after spec["out_steps"][k] steps, as a vector-valued
+        differentiable function of the model parameters: the forward pass is a
+        series run with zero weights (values only), the backward pass one series
+        gradient whose weights are the incoming gradients."""
+
+        @staticmethod
+        def forward(ctx, spec, *params):
+            F, _ = run(spec, params, np.zeros(len(spec["out_steps"])))
+            ctx.spec = spec
+            ctx.save_for_backward(*params)
+            return torch.as_tensor(F.real, dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, gout):
+            params = ctx.saved_tensors
+            _, g = run(ctx.spec, params, gout.detach().to("cpu", torch.float64).numpy())
+            return (None,) + tuple(torch.as_tensor(g[k], dtype=p.dtype, device=p.device).reshape(p.shape)
+                                   for k, p in zip(GRAD_SITE_KEYS + GRAD_BOND_KEYS, params))
+
+    return ExpectationSeriesFn
+
+
 _EXPECTATION_FN = None
+_SERIES_FN = None
+
+
+def expectation_series(spec, params):
+    """Differentiable vector F_k = Re <spec["paulis"]> after spec["out_steps"][k]
+    steps (strictly increasing, at most spec["steps"]); otherwise as
+    expectation().  The backward pass costs one series gradient."""
+    global _SERIES_FN
+    if _SERIES_FN is None:
+        _SERIES_FN = _series_function()
+    return _SERIES_FN.apply(spec, *[params[k] for k in GRAD_SITE_KEYS + GRAD_BOND_KEYS])
 
 
 def expectation(spec, params):

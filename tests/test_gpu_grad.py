@@ -355,3 +355,31 @@ def test_series_argument_checks():
     assert all(np.array_equal(x, ch.get_site(k)) for k, x in enumerate(before))
     G.close()
     ch.close()
+
+
+def test_autograd_time_series_least_squares():
+    """loss = sum_k (F_k - d_k)^2 over a time series through
+    paulis-valued expectation_series: .grad equals the oracle's series gradient
+    with weights 2 (F_k - d_k)."""
+    import torch
+
+    from paper_2203_05871_amd import expectation_series
+
+    m = workloads.random_model(6, 30)
+    outs, d = [1, 2, 4], np.array([0.1, -0.2, 0.3])
+    spec = {"N": 6, "bonds": m["bonds"], "tau": 0.1, "steps": 4, "chi_max": 8, "cutoff": 1e-10, "init": "+x",
+            "paulis": "IIZIII", "out_steps": outs}
+    params = {k: torch.tensor(m[k], dtype=torch.float64, requires_grad=True)
+              for k in adjoint.SITE_KEYS + adjoint.BOND_KEYS}
+    F = expectation_series(spec, params)
+    loss = ((F - torch.tensor(d)) ** 2).sum()
+    loss.backward()
+    Fo, _, _ = adjoint.gradient_series(m, 0.1, 4, 8, 1e-10, "+x", "IIZIII", outs, [1.0, 1.0, 1.0])
+    assert np.abs(F.detach().numpy() - Fo.real).max() < 1e-11
+    w = 2.0 * (F.detach().numpy() - d)
+    _, go, _ = adjoint.gradient_series(m, 0.1, 4, 8, 1e-10, "+x", "IIZIII", outs, w)
+    ref = adjoint.flatten(m, go).real
+    got = np.concatenate([params[k].grad.numpy() for k in adjoint.SITE_KEYS + adjoint.BOND_KEYS])
+    err = np.abs(got - ref).max() / max(1.0, np.abs(ref).max())
+    print(f"autograd series: max |grad - oracle| / scale = {err:.2e}", flush=True)
+    assert err < 1e-9
