@@ -1915,7 +1915,7 @@ int build_k_table(lmpo_grad *G, std::vector<std::complex<double>> &Kh, std::vect
 
 // Gamma of the co-state C and the recorded state (sites at `snap`, bond dims
 // rd) on sites (k, k + 1), into G->gam.  C->dims must be current on the host.
-void transition_density(lmpo_grad *G, int k, const char *snap, const int *rd) {
+int transition_density(lmpo_grad *G, int k, const char *snap, const int *rd) {
   lmpo_state *S = G->S, *C = G->C;
   const int N = S->N;
   hipStream_t st = S->stream;
@@ -1932,7 +1932,7 @@ void transition_density(lmpo_grad *G, int k, const char *snap, const int *rd) {
     launch_zgemm(st, g, batch);
   };
   // left environment L[p][q] over sites < k
-  (void)hipMemcpyAsync(G->L, G->one, sizeof(double2), hipMemcpyDeviceToDevice, st);
+  HIP_TRY(hipMemcpyAsync(G->L, G->one, sizeof(double2), hipMemcpyDeviceToDevice, st));
   for (int s = 0; s < k; ++s) {
     const int pl = md(s - 1), pr = md(s), ql = qd(s - 1), qr = qd(s);
     // W[p][(a q')] = sum_q L[p][q] r_s[q][(a q')]
@@ -1941,7 +1941,7 @@ void transition_density(lmpo_grad *G, int k, const char *snap, const int *rd) {
     gemm(pr, qr, 4 * pl, C->site[s], 1, pr, 0, G->W, qr, 1, 0, G->L, qr, 1, 0, 1);
   }
   // right environment R[p][q] over sites > k + 1
-  (void)hipMemcpyAsync(G->R, G->one, sizeof(double2), hipMemcpyDeviceToDevice, st);
+  HIP_TRY(hipMemcpyAsync(G->R, G->one, sizeof(double2), hipMemcpyDeviceToDevice, st));
   for (int s = N - 1; s > k + 1; --s) {
     const int pl = md(s - 1), pr = md(s), ql = qd(s - 1), qr = qd(s);
     // W[(p a)][q'] = sum_{p'} mu_s[(p a)][p'] R[p'][q']
@@ -1957,6 +1957,8 @@ void transition_density(lmpo_grad *G, int k, const char *snap, const int *rd) {
   gemm(4 * pm, qr, pr, C->site[k + 1], pr, 1, 0, G->R, qr, 1, 0, G->W, qr, 1, 0, 1);
   gemm(4 * pm, qm, qr, G->W, qr, 1, 0, rs(k + 1), 1, 4 * qr, qr, G->Fr, qm, 1, (long long)4 * pm * qm, 4);
   launch_transition_reduce(st, G->E, G->Fr, pm, qm, G->gam);
+  HIP_TRY(hipGetLastError());
+  return LMPO_OK;
 }
 
 // A sum of product covectors sum_k c_k prod_s v_{k,s} as an MPS in the co-state:
@@ -2042,7 +2044,7 @@ int string_expectation_numerator(lmpo_grad *G, const std::vector<int> &a, std::c
   lmpo_state *S = G->S;
   int rc = init_costate(G, {{1.0, a}}, false);
   if (rc || (rc = sync_dims(S))) return rc;
-  transition_density(G, S->N - 2, reinterpret_cast<const char *>(S->site[0]), S->dims.data());
+  if ((rc = transition_density(G, S->N - 2, reinterpret_cast<const char *>(S->site[0]), S->dims.data()))) return rc;
   double2 gam[256];
   HIP_TRY(hipMemcpyAsync(gam, G->gam, sizeof(gam), hipMemcpyDeviceToHost, S->stream));
   HIP_TRY(hipStreamSynchronize(S->stream));
@@ -2203,7 +2205,8 @@ int grad_backward(lmpo_grad *G, long long step0, const std::vector<double2> &tr_
         continue;
       }
       if ((rc = sync_dims(C))) return rc;
-      transition_density(G, op.k, G->rec.slots + (size_t)i * G->rec.stride, &rd[(size_t)i * (N - 1)]);
+      if ((rc = transition_density(G, op.k, G->rec.slots + (size_t)i * G->rec.stride, &rd[(size_t)i * (N - 1)])))
+        return rc;
       const size_t kb = ((size_t)op.bond * kGateSlots + op.slot) * kGradLocal;
       launch_grad_accumulate(st, G->K + kb * 256, G->pidx + (size_t)op.bond * kGradLocal, kGradLocal, G->gam,
                              make_double2(scale.real(), scale.imag()), G->grad);
@@ -2305,6 +2308,7 @@ int lmpo_grad_run_series(lmpo_grad *G, const char *paulis, int32_t n_out, const 
     HIP_TRY(hipMemcpyAsync(&t, S->tr, sizeof(double2), hipMemcpyDeviceToHost, S->stream));
     HIP_TRY(hipStreamSynchronize(S->stream));
     trk[k] = t.x;
+    if (!(std::abs(t.x) > 0) || !std::isfinite(t.x)) return fail(LMPO_ENUMERIC, "trace is zero or non-finite");
     if (req.size() <= 4) return run_measure(S, req, &F[2 * (size_t)k]);
     std::complex<double> num;
     int rc = string_expectation_numerator(G, a, num);
