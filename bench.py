@@ -473,7 +473,9 @@ def main():
                 "unit": "gradients/s", "n_gpus": 1, "steps": 40, "warmup": 1,
                 "ms_per_step": 1e3 * g["seconds"] / 40, "higher_is_better": True, "scaling": "weak",
                 "vs_baseline": None, "dtype": "f64", "data": "synthetic (the 2x8 ladder model, no dataset)",
-                "config": {"workload": g["workload"]}, "gradient": g}
+                "config": {"workload": g["workload"]}, "roofline": g["roofline"], "gradient": g}
+        if "cpu_baseline" in g:
+            line["cpu_baseline"] = g["cpu_baseline"]
         print(json.dumps(line), flush=True)
         return
     if args.steps is None:
