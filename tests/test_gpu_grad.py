@@ -125,6 +125,17 @@ def test_connected_correlator_needs_room_for_its_costate():
     ch.close()
 
 
+@pytest.mark.parametrize("steps", [1, 3])
+def test_two_qubit_gradient(steps):
+    """N = 2: one bond, empty environments; one step and several."""
+    _compare(workloads.random_model(2, 32), 0.2, steps, 4, 0.0, "+y", 1, "X")
+
+
+def test_gradient_at_the_smallest_chi():
+    """chi_max = 2 for the state and the co-state (the co-state starts at bond 2)."""
+    _compare(workloads.random_model(5, 33), 0.1, 3, 2, 1e-12, "+x", 2, "Z")
+
+
 def test_fourth_order_gradient():
     _compare(workloads.random_model(5, 8), 0.1, 2, 16, 1e-12, "+x", 0, "Z", order=4)
 

@@ -300,3 +300,13 @@ def test_add_compress_is_the_sum_without_truncation():
     ref = dense.mps_to_vector(a.A) + dense.mps_to_vector(b.A)
     out = adjoint.add_compress(a, b, 64, 0.0)
     assert np.abs(dense.mps_to_vector(out.A) - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("steps", [1, 3])
+def test_two_qubit_gradient_equals_dense_trotter_derivative(steps):
+    """The smallest system: one bond, no environments on either side."""
+    m = rich_chain(2, 31)
+    F, g, _ = adjoint.gradient(m, 0.2, steps, 4, 0.0, "+y", 1, "X")
+    got = adjoint.flatten(m, g)
+    ref = dense_fd_gradient(m, 0.2, steps, "+y", 1, "X")
+    assert np.abs(got - ref).max() < 1e-8
