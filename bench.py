@@ -301,6 +301,17 @@ def gradient_leg(cpu_budget, no_cpu, connected=False):
            "fd_max_abs_diff": max(abs(v["adjoint"] - v["central_difference"]) for v in fd.values())}
     print(f"# gradient: {tg:.1f} s vs forward {tf:.2f} s", file=sys.stderr, flush=True)
     if connected:
+        # the same gradient with every step's gate snapshots kept from the forward run (no replay)
+        c = Chain(m, tau, chi, cut, "fp64", init, device="cuda:0")
+        G = Gradient(c, steps, keep_gates=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Fk, gk = G.run(site, pauli)
+        out["keep_gates"] = {"seconds": time.perf_counter() - t0,
+                             "arena_GB": G.arena.numel() / 1e9,
+                             "same_result": bool(Fk == F and all(np.array_equal(gk[k], g[k]) for k in g))}
+        G.close()
+        c.close()
         c = Chain(m, tau, chi, cut, "fp64", init, device="cuda:0")
         G = Gradient(c, steps)
         torch.cuda.synchronize()

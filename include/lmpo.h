@@ -352,13 +352,16 @@ typedef struct lmpo_grad lmpo_grad;
 
 /* Workspace flags.  LMPO_GRAD_SERIES: room for lmpo_grad_run_series, whose
  * outputs enter the co-state as sources (its bond capacities doubled, arena
- * about 4x, co-state chi_max <= 256). */
-enum { LMPO_GRAD_SERIES = 1 };
+ * about 4x, co-state chi_max <= 256).  LMPO_GRAD_KEEP_GATES: the forward run
+ * keeps every step's gate snapshots (n_steps times the gate slots of one step:
+ * tens of GB at chi 128 over 40 steps), so the backward pass replays nothing
+ * (one forward run less; same results). */
+enum { LMPO_GRAD_SERIES = 1, LMPO_GRAD_KEEP_GATES = 2 };
 
 /* Device bytes of the workspace for n_steps >= 1 steps of s (0 on invalid
  * input).  costate_chi_max <= 0 and costate_cutoff < 0 take the state's
- * values; the co-state's chi_max must be 2..512.  flags: 0 or
- * LMPO_GRAD_SERIES. */
+ * values; the co-state's chi_max must be 2..512.  flags: 0 or a combination
+ * of LMPO_GRAD_SERIES and LMPO_GRAD_KEEP_GATES. */
 size_t lmpo_grad_arena_bytes(lmpo_state *s, int32_t n_steps, int32_t costate_chi_max, double costate_cutoff,
                              int32_t flags);
 

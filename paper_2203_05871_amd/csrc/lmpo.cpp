@@ -1743,6 +1743,9 @@ struct lmpo_grad {
   double2 *grad = nullptr, *traces = nullptr, *one = nullptr;
   double2 *src = nullptr;  // an output's source MPS (bond 2), [N][16]
   bool series = false;     // co-state capacities doubled for sources
+  bool keep = false;       // every step's gate snapshots kept from the forward run (no replay)
+  char *rec_base = nullptr;                   // gate snapshot slots: one step's, or all steps' when keep
+  std::vector<std::vector<OpRecord>> kept;    // the forward run's gate records per step when keep
   double *disc_save = nullptr;
   int *stats_save = nullptr;
   std::vector<int> ckpt_centre;
@@ -1791,8 +1794,8 @@ std::vector<int> grad_slots(const lmpo_state *S) {
   return out;
 }
 
-size_t grad_layout(lmpo_grad *G, const lmpo_state *S, int n_steps, const lmpo_options &co_opt, char *base,
-                   size_t size, char **co, size_t co_bytes) {
+size_t grad_layout(lmpo_grad *G, const lmpo_state *S, int n_steps, const lmpo_options &co_opt, bool keep,
+                   char *base, size_t size, char **co, size_t co_bytes) {
   Arena a{base, size};
   const int co_mult = co_opt.force_hermitian_every > 0 ? 2 : 1;
   const size_t cm = (size_t)std::max(S->cap_max, compute_sizes(S->N, co_opt.chi_max, co_mult).cap_max);
@@ -1800,7 +1803,8 @@ size_t grad_layout(lmpo_grad *G, const lmpo_state *S, int n_steps, const lmpo_op
   G->snap = snapshot_bytes(S);
   G->max_ops = grad_ops_per_step(S);
   G->ckpt = a.take<char>((size_t)(n_steps + 1) * G->snap);
-  G->rec.slots = a.take<char>((size_t)G->max_ops * G->snap);
+  G->rec_base = a.take<char>((keep ? (size_t)n_steps : 1) * G->max_ops * G->snap);
+  G->rec.slots = G->rec_base;
   G->rec.stride = G->snap;
   G->rec.capacity = (size_t)G->max_ops;
   G->L = a.take<double2>(cm * cm);
@@ -1838,7 +1842,7 @@ int grad_check(const lmpo_state *S, int n_steps, int co_chi, double co_cut, int 
   if (co_cut >= 0) co_opt->cutoff = co_cut;
   if (co_opt->chi_max < 2) return fail(LMPO_EUNSUPPORTED, "the co-state needs chi_max >= 2 (it starts at bond 2)");
   if (co_opt->chi_max > kMaxDim / 4) return fail(LMPO_EUNSUPPORTED, "costate_chi_max above 512 is not supported");
-  if (flags & ~LMPO_GRAD_SERIES) return fail(LMPO_EINVAL, "unknown gradient flags");
+  if (flags & ~(LMPO_GRAD_SERIES | LMPO_GRAD_KEEP_GATES)) return fail(LMPO_EINVAL, "unknown gradient flags");
   if (flags & LMPO_GRAD_SERIES) {
     // room for an output's source beside the co-state: the bond capacities
     // doubled (the co-state never takes a step, so no Hermitian part is formed)
@@ -2066,7 +2070,7 @@ size_t lmpo_grad_arena_bytes(lmpo_state *S, int32_t n_steps, int32_t costate_chi
   lmpo_grad tmp;
   tmp.S = S;
   char *dummy = nullptr;
-  return grad_layout(&tmp, S, n_steps, co_opt, nullptr, 0, &dummy, co) + 256;
+  return grad_layout(&tmp, S, n_steps, co_opt, (flags & LMPO_GRAD_KEEP_GATES) != 0, nullptr, 0, &dummy, co) + 256;
 }
 
 int lmpo_grad_create(lmpo_state *S, int32_t n_steps, int32_t costate_chi_max, double costate_cutoff, int32_t flags,
@@ -2085,8 +2089,9 @@ int lmpo_grad_create(lmpo_state *S, int32_t n_steps, int32_t costate_chi_max, do
   G->n_steps = n_steps;
   G->series = (flags & LMPO_GRAD_SERIES) != 0;
   char *co_arena = nullptr;
-  const size_t need =
-      grad_layout(G, S, n_steps, co_opt, reinterpret_cast<char *>(device_arena), arena_bytes, &co_arena, co);
+  G->keep = (flags & LMPO_GRAD_KEEP_GATES) != 0;
+  const size_t need = grad_layout(G, S, n_steps, co_opt, G->keep, reinterpret_cast<char *>(device_arena), arena_bytes,
+                                  &co_arena, co);
   if (need > arena_bytes) {
     delete G;
     return fail(LMPO_ENOMEM, "gradient arena too small: need " + std::to_string(need) + " bytes");
@@ -2135,10 +2140,19 @@ int grad_forward(lmpo_grad *G, long long &step0, std::complex<double> &trT, std:
   step0 = S->step_index;
   int rc;
   HIP_TRY(hipMemsetAsync(G->grad, 0, (size_t)G->P * sizeof(double2), st));
+  if (G->keep) G->kept.assign(T, {});
   for (int n = 0; n < T; ++n) {
     if ((rc = save_snapshot(S, G->ckpt + (size_t)n * G->snap))) return rc;
     G->ckpt_centre[n] = S->centre;
-    if ((rc = one_step(S, step0 + n))) return rc;
+    if (G->keep) {  // record this step's gates into its own slots
+      G->rec.ops.clear();
+      G->rec.slots = G->rec_base + (size_t)n * G->max_ops * G->snap;
+      S->rec = &G->rec;
+    }
+    rc = one_step(S, step0 + n);
+    S->rec = nullptr;
+    if (rc) return rc;
+    if (G->keep) G->kept[n] = G->rec.ops;
     if (S->opt.force_trace) HIP_TRY(hipMemcpyAsync(G->traces + n, S->tr, sizeof(double2), hipMemcpyDeviceToDevice, st));
     if (observe && (rc = observe(n + 1))) return rc;  // after n + 1 steps
   }
@@ -2185,13 +2199,19 @@ int grad_backward(lmpo_grad *G, long long step0, const std::vector<double2> &tr_
     }
     scale /= std::complex<double>(tr_host[n].x, tr_host[n].y);
     if (!live) continue;  // zero co-state: nothing to carry back yet
-    if ((rc = load_snapshot(S, G->ckpt + (size_t)n * G->snap))) return rc;
-    S->centre = G->ckpt_centre[n];
-    G->rec.ops.clear();
-    S->rec = &G->rec;
-    rc = one_step(S, step0 + n);
-    S->rec = nullptr;
-    if (rc) return rc;
+    if (G->keep) {  // the forward run's records of this step
+      G->rec.slots = G->rec_base + (size_t)n * G->max_ops * G->snap;
+      G->rec.ops = G->kept[n];
+    } else {  // replay the step from its snapshot, recording every gate
+      if ((rc = load_snapshot(S, G->ckpt + (size_t)n * G->snap))) return rc;
+      S->centre = G->ckpt_centre[n];
+      G->rec.ops.clear();
+      G->rec.slots = G->rec_base;
+      S->rec = &G->rec;
+      rc = one_step(S, step0 + n);
+      S->rec = nullptr;
+      if (rc) return rc;
+    }
     const int nops = (int)G->rec.ops.size();
     rd.assign((size_t)nops * (N - 1), 1);
     for (int i = 0; i < nops; ++i)

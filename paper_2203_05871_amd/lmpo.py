@@ -415,14 +415,16 @@ GRAD_BOND_KEYS = ("J", "Jz")
 
 class Gradient:
     """Adjoint-gradient workspace of one chain for a fixed number of steps
-    (lmpo_grad_*).  Each run() advances the chain by those steps."""
+    (lmpo_grad_*).  Each run() advances the chain by those steps.  series:
+    room for run_series; keep_gates: every step's gate snapshots kept from the
+    forward run (no replay in the backward pass, much more device memory)."""
 
-    def __init__(self, chain, n_steps, costate_chi_max=0, costate_cutoff=-1.0, series=False):
+    def __init__(self, chain, n_steps, costate_chi_max=0, costate_cutoff=-1.0, series=False, keep_gates=False):
         import torch
 
         lib = load_library()
         self.chain, self.n_steps = chain, int(n_steps)
-        co = (int(costate_chi_max), float(costate_cutoff), 1 if series else 0)
+        co = (int(costate_chi_max), float(costate_cutoff), (1 if series else 0) | (2 if keep_gates else 0))
         n = lib.lmpo_grad_arena_bytes(chain._h, self.n_steps, *co)
         if n == 0:
             raise LmpoError(-1, lib.lmpo_last_error().decode())

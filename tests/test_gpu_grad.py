@@ -13,10 +13,10 @@ from oracle import adjoint
 pytestmark = pytest.mark.gpu
 
 
-def Gradient(chain, n_steps, co_chi=0, co_cut=-1.0, series=False):
+def Gradient(chain, n_steps, co_chi=0, co_cut=-1.0, series=False, keep_gates=False):
     from paper_2203_05871_amd import Gradient as G
 
-    return G(chain, n_steps, co_chi, co_cut, series)
+    return G(chain, n_steps, co_chi, co_cut, series, keep_gates)
 
 
 def _chain(m, tau, chi, cutoff, init, precision="fp64", order=2, force_trace=True):
@@ -394,3 +394,24 @@ def test_autograd_time_series_least_squares():
     err = np.abs(got - ref).max() / max(1.0, np.abs(ref).max())
     print(f"autograd series: max |grad - oracle| / scale = {err:.2e}", flush=True)
     assert err < 1e-9
+
+
+@pytest.mark.parametrize("series", [False, True])
+def test_kept_gate_snapshots_give_the_replayed_result(series):
+    """LMPO_GRAD_KEEP_GATES (no replay in the backward pass) gives the replayed
+    workspace's results bit for bit, on a ladder through the SWAP network."""
+    m = workloads.random_model(6, 34, bonds=workloads.ladder_model(3)["bonds"])
+    out = []
+    for keep in (False, True):
+        ch = _chain(m, 0.1, 16, 1e-12, "+x")
+        G = Gradient(ch, 3, series=series, keep_gates=keep)
+        F, g = G.run_series("IZIIXI", [1, 3], [0.5, 1.0]) if series else G.run_string("IZIIXI")
+        G.close()
+        sites = [ch.get_site(k) for k in range(6)]
+        ch.close()
+        out.append((F, g, sites))
+    (Fa, ga, sa), (Fb, gb, sb) = out
+    assert np.array_equal(np.atleast_1d(Fa), np.atleast_1d(Fb))
+    for k in ga:
+        assert np.array_equal(ga[k], gb[k])
+    assert all(np.array_equal(x, y) for x, y in zip(sa, sb))
