@@ -140,6 +140,10 @@ def test_fourth_order_gradient():
     _compare(workloads.random_model(5, 8), 0.1, 2, 16, 1e-12, "+x", 0, "Z", order=4)
 
 
+def test_third_order_gradient():
+    _compare(workloads.random_model(6, 36), 0.1, 3, 8, 1e-10, "+x", 3, "Y", order=3)
+
+
 def test_fp32_contraction_form_gradient():
     """The state in the FP32-contraction form (the co-state stays real FP64): the
     derivatives follow the oracle's to the FP32 form's tolerance."""

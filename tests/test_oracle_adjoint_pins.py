@@ -310,3 +310,12 @@ def test_two_qubit_gradient_equals_dense_trotter_derivative(steps):
     got = adjoint.flatten(m, g)
     ref = dense_fd_gradient(m, 0.2, steps, "+y", 1, "X")
     assert np.abs(got - ref).max() < 1e-8
+
+
+def test_exact_third_order_gradient_equals_dense_trotter_derivative():
+    """Order 3 (negative time fractions: gates that run the dissipators backwards)."""
+    m = rich_chain(4, 35)
+    F, g, _ = adjoint.gradient(m, 0.1, 2, 16, 0.0, "+x", 2, "Y", order=3)
+    got = adjoint.flatten(m, g)
+    ref = dense_fd_gradient(m, 0.1, 2, "+x", 2, "Y", order=3)
+    assert np.abs(got - ref).max() < 1e-8, np.abs(got - ref).max()
