@@ -168,7 +168,7 @@ def timed_batch(models, run, steps, warmup, sequential):
 
 def bench_batch(args):
     """Batched form on the 64-chain workload (a separate line from the
-    headline; not the driver's default)."""
+    headline, printed with --workload chains64)."""
     import numpy as np
 
     import workloads
