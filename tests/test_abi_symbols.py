@@ -80,3 +80,13 @@ def test_gradient_entry_points_reject_bad_arguments_on_host():
     assert lib.lmpo_probe_fp64_mfma(None, None, 0, None) == -1
     assert lib.lmpo_grad_run(None, b"IZ", None, None) == -1
     assert lib.lmpo_grad_destroy(None) == 0
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus above 1 exits with a message before any GPU work."""
+    import subprocess
+    import sys
+
+    out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                         text=True, timeout=120, cwd=ROOT)
+    assert out.returncode != 0 and "one GPU" in out.stderr
