@@ -235,6 +235,14 @@ int lmpo_last_spectrum(lmpo_state *s, int32_t n_out, double *sv, int32_t *n_sv, 
  * Results do not depend on it; it exists for tuning and for tests of that. */
 int lmpo_set_workgroups(lmpo_state *s, int32_t max_workgroups);
 
+/* Stopping threshold of this state's block Jacobi SVDs: a column pair counts
+ * as orthogonal when |g_pq| <= factor sqrt(C) eps sqrt(g_pp g_qq) (C columns,
+ * eps the FP64 unit round-off); default 32, factor >= 1.  A larger factor ends
+ * the sweeps earlier at the price of singular vectors accurate to about that
+ * threshold: meant for the gradient's co-state (lmpo_grad_costate), whose
+ * truncation is usually far coarser than the round-off. */
+int lmpo_set_svd_tolerance(lmpo_state *s, double factor);
+
 /* Jacobi statistics: out = (sweeps of the last SVD, its column count,
  * total sweeps so far, total SVDs so far, hops included); synchronises. */
 int lmpo_svd_stats(lmpo_state *s, int32_t out[4]);

@@ -190,6 +190,7 @@ struct lmpo_state {
   bool ev_overflow = false;
   int grid = 1;                 // largest co-resident grid of the persistent SVD
   int wg_cap = 0;               // caller's cap on workgroups per SVD launch (0: none)
+  double tol_factor = 32.0;     // Jacobi stopping threshold, in units of sqrt(C) eps
   ~lmpo_state() {
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
   }
@@ -411,7 +412,7 @@ SvdLaunch svd_args(lmpo_state *S, int mode, int k, int asc) {
   L.max_sweeps = kMaxSweeps;
   L.real = S->opt.precision == LMPO_FP64_REAL ? 1 : 0;
   L.cutoff = S->opt.cutoff;
-  L.tol_factor = 32.0;
+  L.tol_factor = S->tol_factor;
   L.sites = S->d_sites;
   L.dims = S->d_dims;
   L.X = S->X;
@@ -1158,6 +1159,13 @@ int lmpo_osee(lmpo_state *S, int32_t bond, double *out) {
   HIP_TRY(hipStreamSynchronize(S->stream));
   if ((rc = check_err(S))) return rc;
   *out = h[0];
+  return LMPO_OK;
+}
+
+int lmpo_set_svd_tolerance(lmpo_state *S, double factor) {
+  if (!S) return fail(LMPO_EINVAL, "state is null");
+  if (!(factor >= 1.0) || !std::isfinite(factor)) return fail(LMPO_EINVAL, "the tolerance factor must be >= 1");
+  S->tol_factor = factor;
   return LMPO_OK;
 }
 

@@ -63,7 +63,7 @@ EXPORTS = [
     "lmpo_measure_1q", "lmpo_measure_2q", "lmpo_bond_dims", "lmpo_discarded_weight", "lmpo_sync",
     "lmpo_destroy", "lmpo_last_error", "lmpo_get_site", "lmpo_set_site", "lmpo_set_centre",
     "lmpo_get_centre", "lmpo_get_gate", "lmpo_apply_gate", "lmpo_last_spectrum", "lmpo_svd_stats",
-    "lmpo_svd_profile", "lmpo_profile_begin", "lmpo_profile_end", "lmpo_set_workgroups",
+    "lmpo_svd_profile", "lmpo_profile_begin", "lmpo_profile_end", "lmpo_set_workgroups", "lmpo_set_svd_tolerance",
     "lmpo_renyi2", "lmpo_osee", "lmpo_apply_superop", "lmpo_apply_unitary", "lmpo_init_graph_state",
     "lmpo_hermitize",
     "lmpo_batch_arena_bytes", "lmpo_batch_create", "lmpo_batch_evolve_step", "lmpo_batch_sync",
@@ -113,6 +113,7 @@ def load_library(path: str = LIB_PATH):
         "lmpo_profile_begin": (ctypes.c_int, [P, i32]),
         "lmpo_profile_end": (ctypes.c_int, [P, pdbl]),
         "lmpo_set_workgroups": (ctypes.c_int, [P, i32]),
+        "lmpo_set_svd_tolerance": (ctypes.c_int, [P, dbl]),
         "lmpo_renyi2": (ctypes.c_int, [P, pdbl]),
         "lmpo_osee": (ctypes.c_int, [P, i32, pdbl]),
         "lmpo_apply_superop": (ctypes.c_int, [P, i32, i32, pdbl]),
@@ -367,6 +368,10 @@ class Chain:
         """Cap the workgroups per SVD launch (0: automatic); results do not depend on it."""
         _check(self._lib.lmpo_set_workgroups(self._h, int(max_workgroups)))
 
+    def set_svd_tolerance(self, factor):
+        """Jacobi stopping threshold in units of sqrt(C) eps (default 32)."""
+        _check(self._lib.lmpo_set_svd_tolerance(self._h, float(factor)))
+
     def profile_end(self):
         """(SVD launches, summed kernel ms from HIP events, summed declared flops)."""
         out = np.zeros(3)
@@ -489,6 +494,10 @@ class Gradient:
         out = np.zeros(3)
         _check(self._lib.lmpo_profile_end(self._lib.lmpo_grad_costate(self._h), _dptr(out)))
         return int(out[0]), float(out[1]), float(out[2])
+
+    def set_costate_svd_tolerance(self, factor):
+        """The co-state's Jacobi stopping threshold (lmpo_set_svd_tolerance on it)."""
+        _check(self._lib.lmpo_set_svd_tolerance(self._lib.lmpo_grad_costate(self._h), float(factor)))
 
     def costate_dims(self):
         """Bond dims of the co-state (after run(): at time 0)."""

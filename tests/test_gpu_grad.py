@@ -419,3 +419,25 @@ def test_kept_gate_snapshots_give_the_replayed_result(series):
     for k in ga:
         assert np.array_equal(ga[k], gb[k])
     assert all(np.array_equal(x, y) for x, y in zip(sa, sb))
+
+
+def test_costate_svd_tolerance_knob():
+    """A looser Jacobi threshold on the co-state changes the derivatives only at
+    about that threshold; factors below 1 are refused."""
+    from paper_2203_05871_amd import LmpoError
+
+    m = workloads.random_model(8, 37)
+    out = []
+    for fac in (32.0, 1e4):
+        ch = _chain(m, 0.1, 8, 1e-10, "+x")
+        G = Gradient(ch, 3)
+        G.set_costate_svd_tolerance(fac)
+        out.append(G.run(3, "Z")[1])
+        if fac == 32.0:
+            with pytest.raises(LmpoError, match="tolerance"):
+                G.set_costate_svd_tolerance(0.5)
+        G.close()
+        ch.close()
+    a = np.concatenate([out[0][k] for k in adjoint.SITE_KEYS + adjoint.BOND_KEYS])
+    b = np.concatenate([out[1][k] for k in adjoint.SITE_KEYS + adjoint.BOND_KEYS])
+    assert np.abs(a - b).max() < 1e-8 * max(1.0, np.abs(a).max())
