@@ -288,7 +288,11 @@ def gradient_leg(cpu_budget, no_cpu, connected=False):
 
     out = {"workload": "2x8 ladder (N=16, 8 rungs + 14 legs via SWAP gates), chi_max=128, cutoff=1e-12, tau=0.05, "
                        "40 steps from +z; F = <sigma^z_15>(T); co-state with the same chi_max and cutoff",
-           "parameters": int(sum(len(v) for v in g.values())), "seconds": tg, "forward_seconds": tf,
+           "parameters": int(sum(len(v) for k, v in g.items() if k != "tau")), "dF_dtau": float(g["tau"][0]),
+           "scaling_identity": {"sum_theta_dF": float(sum(np.dot(np.asarray(m[k], dtype=float), g[k])
+                                                          for k in g if k != "tau")),
+                                "tau_dF_dtau": float(tau * g["tau"][0])},
+           "seconds": tg, "forward_seconds": tf,
            "gradient_over_forward": tg / tf, "F": F.real, "F_forward_only": F0, "max_abs_gradient": gmax,
            "state_bond_dims_T": st_dims, "costate_bond_dims_t0": co_dims,
            "roofline": {"bound": "mfma", "kernel": "svd_persistent_kernel (co-state, real form)",

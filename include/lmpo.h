@@ -385,7 +385,10 @@ int lmpo_grad_create(lmpo_state *s, int32_t n_steps, int32_t costate_chi_max, do
  * would (same results; the discarded weight and the statistics count the
  * forward run only) and returns F = <O>(T) as (re, im) and grad_out[p] =
  * d Re F / d theta_p for the 6 n_qubits + 2 n_bonds parameters in the order
- * hx[0..N-1], hy, hz, g0, g1, g2, J[0..n_bonds-1], Jz.  paulis: the string O,
+ * hx[0..N-1], hy, hz, g0, g1, g2, J[0..n_bonds-1], Jz, followed by d Re F /
+ * d tau (6 n_qubits + 2 n_bonds + 1 entries; the gate exp(f tau L) has
+ * derivative f L exp(f tau L), and sum_theta theta dF/dtheta = tau dF/dtau
+ * since F depends on the parameters only through tau theta).  paulis: the string O,
  * n_qubits characters of I, X, Y, Z (qubit 0 first), at least one not I.  F
  * of one or two factors equals lmpo_measure_1q / _2q on the final state bit
  * for bit.  Synchronises (once per co-state gate).  Arguments are checked

@@ -3,6 +3,11 @@
 
 TEST INFRASTRUCTURE ONLY (see the package header).
 
+Also d/dtau of the same objectives: a gate exp(f tau L) has derivative
+f L exp(f tau L), so its K is f L (no Frechet derivative needed); since F
+depends on the parameters only through tau theta, sum_theta theta dF/dtheta =
+tau dF/dtau exactly.
+
 Objective: F = Tr(O rho_T) / Tr(rho_T) with O a Pauli string (sigma^a on one
 qubit as in Eq. mu, a correlator as in Eq. 2Qdef, or a longer product), or the
 connected correlator <a_i b_j> - <a_i><b_j>, after T Trotter steps from a
@@ -218,6 +223,7 @@ def backward(model, tau, records, traces, mu, chi_mu, cut_mu, order=2, sources=N
     gates = tebd.gate_tables(model, tau, order)
     P = lm.swap_gate()
     grads = {k: np.zeros(len(model[k]), dtype=np.complex128) for k in SITE_KEYS + BOND_KEYS}
+    grads["tau"] = np.zeros(1, dtype=np.complex128)  # the gate exp(f tau L) has d/dtau = f L exp(f tau L)
     kcache = {}
     scale = 1.0
     for n in reversed(range(len(records))):
@@ -239,6 +245,7 @@ def backward(model, tau, records, traces, mu, chi_mu, cut_mu, order=2, sources=N
                     kcache[ck] = k_matrix(lm.bond_generator(model, b), generator_derivative(model, b, key, idx),
                                           frac * tau)
                 grads[key][idx] += scale * np.sum(kcache[ck] * Gam.T)
+            grads["tau"][0] += scale * frac * np.sum(lm.bond_generator(model, b) * Gam.T)
             mu.apply_gate(k, gates[(b, frac)].T, chi_mu, cut_mu, not asc)
     return grads
 

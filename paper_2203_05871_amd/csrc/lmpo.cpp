@@ -1762,7 +1762,7 @@ struct lmpo_grad {
 
 namespace {
 
-constexpr int kGradLocal = 14;  // parameters of one bond generator: 6 per site, J, Jz
+constexpr int kGradLocal = 15;  // parameters of one gate: 6 per site, J, Jz of its generator, and tau
 
 lmpo_model model_view(const ModelHost &m) {
   lmpo_model v;
@@ -1823,7 +1823,7 @@ size_t grad_layout(lmpo_grad *G, const lmpo_state *S, int n_steps, const lmpo_op
   G->gam = a.take<double2>(256);
   G->K = a.take<double2>((size_t)S->m.nb * kGateSlots * kGradLocal * 256);
   G->pidx = a.take<int>((size_t)S->m.nb * kGradLocal);
-  G->P = 6 * S->N + 2 * S->m.nb;
+  G->P = 6 * S->N + 2 * S->m.nb + 1;  // the model's parameters, then tau
   G->grad = a.take<double2>(G->P);
   G->traces = a.take<double2>(n_steps);
   G->one = a.take<double2>(1);
@@ -1895,12 +1895,17 @@ int build_k_table(lmpo_grad *G, std::vector<std::complex<double>> &Kh, std::vect
     gidx.push_back(6 * N + b);
     par.push_back({&ModelHost::Jz, b});
     gidx.push_back(6 * N + nb + b);
+    gidx.push_back(6 * N + 2 * nb);  // tau: d/dtau exp(f tau L) = f L exp(f tau L), so K = f L
     for (int p = 0; p < kGradLocal; ++p) ph[(size_t)b * kGradLocal + p] = gidx[p];
     for (int slot : grad_slots(S)) {
       const double x = gate_fraction(slot) * S->opt.tau;
       for (int e = 0; e < 256; ++e) X[e] = -x * Lb[e];
       if (!expm_pade13(16, X.data(), Ginv.data())) return fail(LMPO_ENUMERIC, "matrix exponential failed");
-      for (int p = 0; p < kGradLocal; ++p) {
+      {
+        std::complex<double> *Kt = &Kh[(((size_t)b * kGateSlots + slot) * kGradLocal + (kGradLocal - 1)) * 256];
+        for (int e = 0; e < 256; ++e) Kt[e] = gate_fraction(slot) * Lb[e];
+      }
+      for (int p = 0; p < kGradLocal - 1; ++p) {
         ModelHost u = m;
         for (auto *v : {&u.J, &u.Jz, &u.hx, &u.hy, &u.hz, &u.g0, &u.g1, &u.g2}) std::fill(v->begin(), v->end(), 0.0);
         (u.*(par[p].first))[par[p].second] = 1.0;

@@ -381,7 +381,8 @@ class Chain:
     def gradient(self, n_steps, site=None, pauli=None, paulis=None, costate_chi_max=0, costate_cutoff=-1.0):
         """Advance n_steps and return (F, {key: dF/dtheta}) for F = <sigma^pauli_site>,
         or for the Pauli string `paulis` (one of I, X, Y, Z per qubit), at the end
-        (lmpo_grad_run); keys hx, hy, hz, g0, g1, g2 (per qubit), J, Jz (per bond).
+        (lmpo_grad_run); keys hx, hy, hz, g0, g1, g2 (per qubit), J, Jz (per bond) and
+        tau (one entry).
         The co-state takes the chain's chi_max / cutoff unless given."""
         g = Gradient(self, n_steps, costate_chi_max, costate_cutoff)
         try:
@@ -452,7 +453,7 @@ class Gradient:
     def run_string(self, paulis):
         """(F, {key: dF/dtheta}) for the Pauli string (one of I, X, Y, Z per qubit)."""
         F = np.zeros(2)
-        g = np.zeros(6 * self.chain.N + 2 * self.n_bonds)
+        g = np.zeros(6 * self.chain.N + 2 * self.n_bonds + 1)
         _check(self._lib.lmpo_grad_run(self._h, paulis.upper().encode(), _dptr(F), _dptr(g)))
         return self._unpack(F, g)
 
@@ -464,7 +465,7 @@ class Gradient:
         if len(w) != len(outs):
             raise ValueError("one weight per output step")
         F = np.zeros((len(outs), 2))
-        g = np.zeros(6 * self.chain.N + 2 * self.n_bonds)
+        g = np.zeros(6 * self.chain.N + 2 * self.n_bonds + 1)
         _check(self._lib.lmpo_grad_run_series(self._h, paulis.upper().encode(), len(outs), _iptr(outs), _dptr(w),
                                               _dptr(F), _dptr(g)))
         _, out = self._unpack(np.zeros(2), g)
@@ -473,7 +474,7 @@ class Gradient:
     def run_connected(self, i, j, paulis="ZZ"):
         """(C, {key: dC/dtheta}) for the connected correlator <a_i b_j> - <a_i><b_j>."""
         F = np.zeros(2)
-        g = np.zeros(6 * self.chain.N + 2 * self.n_bonds)
+        g = np.zeros(6 * self.chain.N + 2 * self.n_bonds + 1)
         _check(self._lib.lmpo_grad_run_connected(self._h, int(i), int(j), paulis.upper().encode(), _dptr(F),
                                                  _dptr(g)))
         return self._unpack(F, g)
@@ -482,7 +483,8 @@ class Gradient:
         N, nb = self.chain.N, self.n_bonds
         out = {k: g[q * N:(q + 1) * N].copy() for q, k in enumerate(GRAD_SITE_KEYS)}
         out["J"] = g[6 * N:6 * N + nb].copy()
-        out["Jz"] = g[6 * N + nb:].copy()
+        out["Jz"] = g[6 * N + nb:6 * N + 2 * nb].copy()
+        out["tau"] = g[6 * N + 2 * nb:].copy()
         return complex(F[0], F[1]), out
 
     def costate_profile_begin(self, max_launches=20000):

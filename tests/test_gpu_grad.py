@@ -35,8 +35,8 @@ def _compare(m, tau, steps, chi, cutoff, init, site, pauli, precision="fp64", or
     Fo, go, _ = adjoint.gradient(m, tau, steps, chi, cutoff, init, site, pauli, order=order,
                                  force_trace=force_trace, costate_chi_max=co_chi, costate_cutoff=co_cut,
                                  paulis=paulis)
-    got = np.concatenate([g[k] for k in adjoint.SITE_KEYS + adjoint.BOND_KEYS])
-    ref = adjoint.flatten(m, go).real
+    got = np.concatenate([g[k] for k in adjoint.SITE_KEYS + adjoint.BOND_KEYS + ("tau",)])
+    ref = np.concatenate([adjoint.flatten(m, go).real, go["tau"].real])
     assert abs(F - Fo) < 1e-11
     scale = max(1.0, np.abs(ref).max())
     err = np.abs(got - ref).max() / scale
@@ -236,6 +236,10 @@ def test_ladder2x8_full_size_gradient():
     ch.close()
     assert F == forward(m)
     gmax = max(np.abs(v).max() for v in g.values())
+    # F depends on the parameters only through tau theta: sum theta dF/dtheta = tau dF/dtau
+    lhs = sum(float(np.dot(np.asarray(m[k], dtype=float), g[k])) for k in adjoint.SITE_KEYS + adjoint.BOND_KEYS)
+    print(f"  sum theta dF/dtheta = {lhs:.12e}, tau dF/dtau = {tau * g['tau'][0]:.12e}", flush=True)
+    assert abs(lhs - tau * g["tau"][0]) < 1e-9 * max(1.0, abs(lhs))
     for key, idx in (("hx", 0), ("J", 5)):
         vals = []
         for sgn in (1.0, -1.0):

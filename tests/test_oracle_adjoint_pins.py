@@ -319,3 +319,15 @@ def test_exact_third_order_gradient_equals_dense_trotter_derivative():
     got = adjoint.flatten(m, g)
     ref = dense_fd_gradient(m, 0.1, 2, "+x", 2, "Y", order=3)
     assert np.abs(got - ref).max() < 1e-8, np.abs(got - ref).max()
+
+
+def test_tau_derivative_and_scaling_identity():
+    """d F / d tau against central differences of the dense Trotter product in
+    tau, and sum_theta theta dF/dtheta = tau dF/dtau (F depends on tau theta)."""
+    m = rich_chain(4, 38)
+    tau, steps, h = 0.1, 3, 1e-6
+    F, g, _ = adjoint.gradient(m, tau, steps, 16, 0.0, "+x", 1, "Z")
+    fd = (dense_expectation(m, tau + h, steps, "+x", 1, "Z") - dense_expectation(m, tau - h, steps, "+x", 1, "Z")) / (2 * h)
+    assert abs(g["tau"][0] - fd) < 1e-8
+    lhs = sum(m[k][i] * g[k][i] for k, i in adjoint.parameter_list(m))
+    assert abs(lhs - tau * g["tau"][0]) < 1e-12 * max(1.0, abs(lhs))
