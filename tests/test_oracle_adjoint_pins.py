@@ -331,3 +331,27 @@ def test_tau_derivative_and_scaling_identity():
     assert abs(g["tau"][0] - fd) < 1e-8
     lhs = sum(m[k][i] * g[k][i] for k, i in adjoint.parameter_list(m))
     assert abs(lhs - tau * g["tau"][0]) < 1e-12 * max(1.0, abs(lhs))
+
+
+def test_renyi2_gradient_equals_dense_trotter_derivative():
+    """dS_2/dtheta (Eq. S_2): co-state from rho itself; against dense differences of
+    S_2 computed from the density matrix."""
+    m = rich_chain(4, 39)
+    tau, steps, h = 0.1, 3, 1e-6
+
+    def dense_S2(model):
+        v = dense.trotter_evolve(dense.product_vector("+x", 4), model, tau, steps)
+        return dense.renyi2(v, 4)
+
+    S2, g, _ = adjoint.gradient_renyi2(m, tau, steps, 16, 0.0, "+x")
+    assert abs(S2 - dense_S2(m)) < 1e-12
+    ref = []
+    for key, idx in adjoint.parameter_list(m):
+        vals = []
+        for sgn in (1.0, -1.0):
+            mm = {k: (np.array(v, dtype=float) if k in adjoint.SITE_KEYS + adjoint.BOND_KEYS else v)
+                  for k, v in m.items()}
+            mm[key][idx] += sgn * h
+            vals.append(dense_S2(mm))
+        ref.append((vals[0] - vals[1]) / (2 * h))
+    assert np.abs(adjoint.flatten(m, g) - np.array(ref)).max() < 1e-8
