@@ -421,6 +421,17 @@ int lmpo_grad_run_series(lmpo_grad *g, const char *paulis, int32_t n_out, const 
  * before the state moves. */
 int lmpo_grad_run_connected(lmpo_grad *g, int32_t i, int32_t j, const char *paulis, double F[2], double *grad_out);
 
+/* As lmpo_grad_run for the second Renyi entropy S_2 = -ln(tr rho^2 / (tr rho)^2)
+ * at T (Eq. S_2, Sec. 2.4; the value lmpo_renyi2 reports): S2[0] = S_2,
+ * grad_out = dS_2/dtheta.  In the Pauli basis tr rho^2 = <rho, rho> = P, so the
+ * co-state is mu_T = (-2 / P)(rho_T - (P / tr) 1): the state's own tensors
+ * plus one product term (bonds + 1), compressed as an output's source is
+ * (the co-state's chi_max and cutoff), the factor applied to the gradient.
+ * Needs the state in the real-arithmetic form (LMPO_FP64_REAL), a workspace
+ * created with LMPO_GRAD_SERIES, and a co-state chi_max at least the state's:
+ * LMPO_EUNSUPPORTED otherwise, checked before the state moves. */
+int lmpo_grad_run_renyi2(lmpo_grad *g, double S2[1], double *grad_out);
+
 /* Bond dims of the co-state (n_qubits - 1 entries): after a run, those of
  * mu at time 0, the end of the backward pass.  Synchronises. */
 int lmpo_grad_costate_dims(lmpo_grad *g, int32_t *out);

@@ -713,6 +713,25 @@ int one_step(lmpo_state *S, long long step) {
   return finish_step(S, step);
 }
 
+// <<rho|rho>> = tr(rho^dagger rho) = sum |c|^2 in the orthonormal Pauli basis,
+// the squared norm of the orthogonality centre (every other site is an
+// isometry), and |tr rho|^2; tr rho itself into *tr when asked.  Synchronises.
+int purity_and_trace(lmpo_state *S, double &n2, double &t2, double2 *tr_out) {
+  launch_trace(S->stream, S->d_sites, S->d_dims, S->N, S->tr);
+  launch_norm2_site(S->stream, S->d_sites, S->d_dims, S->N, S->centre, S->aux + 2);
+  double2 tr;
+  n2 = 0.0;
+  HIP_TRY(hipMemcpyAsync(&tr, S->tr, sizeof(double2), hipMemcpyDeviceToHost, S->stream));
+  HIP_TRY(hipMemcpyAsync(&n2, S->aux + 2, sizeof(double), hipMemcpyDeviceToHost, S->stream));
+  HIP_TRY(hipStreamSynchronize(S->stream));
+  int rc = check_err(S);
+  if (rc) return rc;
+  t2 = tr.x * tr.x + tr.y * tr.y;
+  if (!(t2 > 0) || !(n2 > 0) || !std::isfinite(n2)) return fail(LMPO_ENUMERIC, "trace or purity is zero or non-finite");
+  if (tr_out) *tr_out = tr;
+  return LMPO_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1130,19 +1149,9 @@ int lmpo_profile_end(lmpo_state *S, double out[3]) {
 
 int lmpo_renyi2(lmpo_state *S, double *out) {
   if (!S || !out) return fail(LMPO_EINVAL, "null argument");
-  // tr(rho^dagger rho) = sum |c|^2 in the orthonormal Pauli basis = the squared
-  // norm of the orthogonality centre (every other site is an isometry)
-  launch_trace(S->stream, S->d_sites, S->d_dims, S->N, S->tr);
-  launch_norm2_site(S->stream, S->d_sites, S->d_dims, S->N, S->centre, S->aux + 2);
-  double2 tr;
-  double n2 = 0.0;
-  HIP_TRY(hipMemcpyAsync(&tr, S->tr, sizeof(double2), hipMemcpyDeviceToHost, S->stream));
-  HIP_TRY(hipMemcpyAsync(&n2, S->aux + 2, sizeof(double), hipMemcpyDeviceToHost, S->stream));
-  HIP_TRY(hipStreamSynchronize(S->stream));
-  int rc = check_err(S);
+  double n2, t2;
+  int rc = purity_and_trace(S, n2, t2, nullptr);
   if (rc) return rc;
-  const double t2 = tr.x * tr.x + tr.y * tr.y;
-  if (!(t2 > 0) || !(n2 > 0) || !std::isfinite(n2)) return fail(LMPO_ENUMERIC, "trace or purity is zero or non-finite");
   *out = -std::log(n2 / t2);
   return LMPO_OK;
 }
@@ -2025,15 +2034,15 @@ int init_costate(lmpo_grad *G, const std::vector<CostateTerm> &terms, bool canon
   return canonical ? move_centre(C, N - 1) : LMPO_OK;
 }
 
-// mu <- mu + sum_k c_k prod_s v_{k,s} (two terms: an output's source): the
-// direct sum of the co-state and the source (bonds + 2, in the capacity the
-// series flag doubled), an exact QR sweep from the left, then the truncated
-// two-site SVD of every bond from the right (the identity gate, the
-// co-state's chi_max and cutoff).  The centre ends on site 0.
+// mu <- mu + sum_k c_k prod_s v_{k,s} (one or two terms: an output's source
+// has two): the direct sum of the co-state and the source (bonds + the term
+// count, in the capacity the series flag doubled), an exact QR sweep from the
+// left, then the truncated two-site SVD of every bond from the right (the
+// identity gate, the co-state's chi_max and cutoff).  The centre ends on site 0.
 int add_costate_source(lmpo_grad *G, const std::vector<CostateTerm> &terms) {
   lmpo_state *C = G->C;
-  const int N = C->N;
-  if (terms.size() != 2) return fail(LMPO_EINVAL, "internal: a source has two product terms");
+  const int N = C->N, kb = (int)terms.size();
+  if (kb < 1 || kb > 2) return fail(LMPO_EINVAL, "internal: a source has one or two product terms");
   std::vector<std::vector<double2>> host;
   terms_host(N, terms, host);
   for (int s = 0; s < N; ++s)
@@ -2042,10 +2051,10 @@ int add_costate_source(lmpo_grad *G, const std::vector<CostateTerm> &terms) {
   for (int k = 0; k < N; ++k) {
     HIP_TRY(hipMemcpyAsync(C->T, C->site[k], C->site_elems[k] * sizeof(double2), hipMemcpyDeviceToDevice,
                            C->stream));
-    launch_mps_sum_site(C->stream, C->T, G->src + (size_t)k * 16, C->site[k], C->d_dims, N, k, 2);
+    launch_mps_sum_site(C->stream, C->T, G->src + (size_t)k * 16, C->site[k], C->d_dims, N, k, kb);
     HIP_TRY(hipGetLastError());
   }
-  launch_add_dims(C->stream, C->d_dims, N - 1, 2);
+  launch_add_dims(C->stream, C->d_dims, N - 1, kb);
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipStreamSynchronize(C->stream));  // the host copies of the source outlive their upload
   C->centre = 0;
@@ -2403,6 +2412,47 @@ int lmpo_grad_run_connected(lmpo_grad *G, int32_t i, int32_t j, const char *paul
   if ((rc = grad_backward(G, step0, tr_host, grad_out))) return rc;
   F_out[0] = Fij - Fi * Fj;
   F_out[1] = f[1] - (f[3] * Fj + Fi * f[5]);
+  return LMPO_OK;
+}
+
+int lmpo_grad_run_renyi2(lmpo_grad *G, double *S2_out, double *grad_out) {
+  if (!G || !S2_out || !grad_out) return fail(LMPO_EINVAL, "null argument");
+  lmpo_state *S = G->S, *C = G->C;
+  const int N = S->N;
+  if (S->opt.precision != LMPO_FP64_REAL)
+    return fail(LMPO_EUNSUPPORTED, "the Renyi-2 gradient needs the state in the real-arithmetic form "
+                                   "(LMPO_FP64_REAL): its co-state starts as a copy of the state's tensors");
+  if (!G->series)
+    return fail(LMPO_EUNSUPPORTED, "create the workspace with LMPO_GRAD_SERIES for the Renyi-2 gradient (its "
+                                   "co-state holds the state plus one bond)");
+  for (int b = 0; b < N - 1; ++b)  // before the state moves
+    if (C->cap[b] < S->cap[b] + 1)
+      return fail(LMPO_EUNSUPPORTED, "the Renyi-2 co-state holds the state plus one bond: its chi_max must be at "
+                                     "least the state's");
+  long long step0;
+  std::complex<double> trT;
+  std::vector<double2> tr_host;
+  int rc = grad_forward(G, step0, trT, tr_host);
+  if (rc) return rc;
+  double P, t2;
+  double2 tr;
+  if ((rc = purity_and_trace(S, P, t2, &tr)) || (rc = sync_dims(S))) return rc;
+  // S_2 = -ln(P / tr^2) with P = <rho, rho> (real coefficients, so the
+  // bilinear pairing is the norm): dS_2 = -2 <rho, drho> / P + 2 <1, drho> / tr,
+  // mu_T = (-2 / P) (rho - (P / tr) 1).  The co-state is the bracket (the
+  // state's own tensors plus one product term, compressed), and the factor
+  // -2 / P scales the gradient at the end.
+  for (int k = 0; k < N; ++k) {
+    const size_t n = (size_t)(k == 0 ? 1 : S->dims[k - 1]) * 4 * (k == N - 1 ? 1 : S->dims[k]);
+    HIP_TRY(hipMemcpyAsync(C->site[k], S->site[k], n * sizeof(double2), hipMemcpyDeviceToDevice, C->stream));
+  }
+  C->dims = S->dims;
+  HIP_TRY(hipMemcpyAsync(C->d_dims, C->dims.data(), (N - 1) * sizeof(int), hipMemcpyHostToDevice, C->stream));
+  HIP_TRY(hipStreamSynchronize(C->stream));
+  if ((rc = add_costate_source(G, {{-P / tr.x, std::vector<int>(N, 0)}}))) return rc;
+  if ((rc = grad_backward(G, step0, tr_host, grad_out))) return rc;
+  for (int p = 0; p < G->P; ++p) grad_out[p] *= -2.0 / P;
+  S2_out[0] = -std::log(P / t2);
   return LMPO_OK;
 }
 

@@ -445,3 +445,61 @@ def test_costate_svd_tolerance_knob():
     a = np.concatenate([out[0][k] for k in adjoint.SITE_KEYS + adjoint.BOND_KEYS])
     b = np.concatenate([out[1][k] for k in adjoint.SITE_KEYS + adjoint.BOND_KEYS])
     assert np.abs(a - b).max() < 1e-8 * max(1.0, np.abs(a).max())
+
+
+@pytest.mark.parametrize("case", ["exact_chain", "truncated_ladder", "costate_truncated"])
+def test_renyi2_gradient(case):
+    """dS_2/dtheta for S_2 = -ln(tr rho^2 / (tr rho)^2) (Eq. S_2): the co-state
+    starts from the state itself; against the oracle (which forms it from the
+    density matrix's transpose) and, all parameters and tau together, the
+    scaling identity sum theta dS_2/dtheta = tau dS_2/dtau."""
+    co_chi = co_cut = None
+    if case == "exact_chain":
+        m, tau, steps, chi, cut, init = workloads.random_model(5, 41), 0.1, 3, 32, 0.0, "+x"
+    else:
+        lad = workloads.ladder_model(4)
+        m = workloads.random_model(8, 42, bonds=lad["bonds"])
+        tau, steps, chi, cut, init = 0.1, 4, 8, 1e-10, "+z"
+        if case == "costate_truncated":
+            co_chi, co_cut = 8, 1e-6
+    print(f"gradient case: renyi2 {case} N={m['N']} chi={chi} co-state {co_chi} {co_cut}", flush=True)
+    ch = _chain(m, tau, chi, cut, init, precision="real")
+    G = Gradient(ch, steps, co_chi or 0, -1.0 if co_cut is None else co_cut, series=True)
+    S2, g = G.run_renyi2()
+    G.close()
+    assert abs(ch.renyi2() - S2) < 1e-13  # the state is left at T
+    ch.close()
+    So, go, _ = adjoint.gradient_renyi2(m, tau, steps, chi, cut, init, costate_chi_max=co_chi,
+                                        costate_cutoff=co_cut)
+    got = np.concatenate([g[k] for k in adjoint.SITE_KEYS + adjoint.BOND_KEYS + ("tau",)])
+    ref = np.concatenate([adjoint.flatten(m, go).real, go["tau"].real])
+    err = np.abs(got - ref).max() / max(1.0, np.abs(ref).max())
+    print(f"  S_2 = {S2:.12f} (oracle {So:.12f}), max |grad - oracle| / scale = {err:.2e}", flush=True)
+    assert abs(S2 - So) < 1e-11
+    assert err < 1e-9
+    theta = np.concatenate([np.asarray(m[k], dtype=float) for k in adjoint.SITE_KEYS + adjoint.BOND_KEYS])
+    lhs, rhs = float(theta @ got[:-1]), tau * got[-1]
+    assert abs(lhs - rhs) < 1e-9 * max(1.0, abs(rhs)), (lhs, rhs)
+
+
+def test_renyi2_gradient_checks():
+    """Refused before the state moves: the complex forms, a workspace without
+    the series headroom, a co-state chi_max below the state's."""
+    from paper_2203_05871_amd import LmpoError
+
+    m = workloads.random_model(4, 43)
+    ch = _chain(m, 0.1, 8, 1e-10, "+x")
+    G = Gradient(ch, 2, series=True)
+    with pytest.raises(LmpoError, match="real-arithmetic"):
+        G.run_renyi2()
+    G.close()
+    ch.close()
+    ch = _chain(m, 0.1, 8, 1e-10, "+x", precision="real")
+    before = [ch.get_site(k) for k in range(4)]
+    for kw, msg in (({}, "LMPO_GRAD_SERIES"), ({"co_chi": 2, "series": True}, "at least the state's")):
+        G = Gradient(ch, 2, **kw)
+        with pytest.raises(LmpoError, match=msg):
+            G.run_renyi2()
+        G.close()
+    assert all(np.array_equal(x, ch.get_site(k)) for k, x in enumerate(before))
+    ch.close()
