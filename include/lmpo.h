@@ -363,8 +363,11 @@ typedef struct lmpo_grad lmpo_grad;
  * about 4x, co-state chi_max <= 256).  LMPO_GRAD_KEEP_GATES: the forward run
  * keeps every step's gate snapshots (n_steps times the gate slots of one step:
  * tens of GB at chi 128 over 40 steps), so the backward pass replays nothing
- * (one forward run less; same results). */
-enum { LMPO_GRAD_SERIES = 1, LMPO_GRAD_KEEP_GATES = 2 };
+ * (one forward run less; same results).  LMPO_GRAD_COMPLEX_COSTATE: the co-state
+ * in the complex FP64 form instead of the real-arithmetic one (about four
+ * times the co-state's SVD flops; the same gradient to round-off), which the
+ * Renyi-2 gradient of a state in a complex form needs. */
+enum { LMPO_GRAD_SERIES = 1, LMPO_GRAD_KEEP_GATES = 2, LMPO_GRAD_COMPLEX_COSTATE = 4 };
 
 /* Device bytes of the workspace for n_steps >= 1 steps of s (0 on invalid
  * input).  costate_chi_max <= 0 and costate_cutoff < 0 take the state's
@@ -427,9 +430,11 @@ int lmpo_grad_run_connected(lmpo_grad *g, int32_t i, int32_t j, const char *paul
  * co-state is mu_T = (-2 / P)(rho_T - (P / tr) 1): the state's own tensors
  * plus one product term (bonds + 1), compressed as an output's source is
  * (the co-state's chi_max and cutoff), the factor applied to the gradient.
- * Needs the state in the real-arithmetic form (LMPO_FP64_REAL), a workspace
- * created with LMPO_GRAD_SERIES, and a co-state chi_max at least the state's:
- * LMPO_EUNSUPPORTED otherwise, checked before the state moves. */
+ * The copy is exact when state and co-state share a number format: needs the
+ * state in the real-arithmetic form (LMPO_FP64_REAL) or a workspace created
+ * with LMPO_GRAD_COMPLEX_COSTATE, and LMPO_GRAD_SERIES, and a co-state chi_max
+ * at least the state's: LMPO_EUNSUPPORTED otherwise, checked before the state
+ * moves. */
 int lmpo_grad_run_renyi2(lmpo_grad *g, double S2[1], double *grad_out);
 
 /* Bond dims of the co-state (n_qubits - 1 entries): after a run, those of

@@ -1853,13 +1853,15 @@ int grad_check(const lmpo_state *S, int n_steps, int co_chi, double co_cut, int 
   *co_opt = S->opt;
   // The co-state of a Hermitian observable has real coefficients in the
   // Pauli basis, where every propagator (and so its transpose) is real: it
-  // runs in the real-arithmetic form whatever the state's precision.
-  co_opt->precision = LMPO_FP64_REAL;
+  // runs in the real-arithmetic form whatever the state's precision, unless
+  // the complex form is asked for (a co-state copied from a complex state).
+  co_opt->precision = (flags & LMPO_GRAD_COMPLEX_COSTATE) ? LMPO_FP64 : LMPO_FP64_REAL;
   if (co_chi > 0) co_opt->chi_max = co_chi;
   if (co_cut >= 0) co_opt->cutoff = co_cut;
   if (co_opt->chi_max < 2) return fail(LMPO_EUNSUPPORTED, "the co-state needs chi_max >= 2 (it starts at bond 2)");
   if (co_opt->chi_max > kMaxDim / 4) return fail(LMPO_EUNSUPPORTED, "costate_chi_max above 512 is not supported");
-  if (flags & ~(LMPO_GRAD_SERIES | LMPO_GRAD_KEEP_GATES)) return fail(LMPO_EINVAL, "unknown gradient flags");
+  if (flags & ~(LMPO_GRAD_SERIES | LMPO_GRAD_KEEP_GATES | LMPO_GRAD_COMPLEX_COSTATE))
+    return fail(LMPO_EINVAL, "unknown gradient flags");
   if (flags & LMPO_GRAD_SERIES) {
     // room for an output's source beside the co-state: the bond capacities
     // doubled (the co-state never takes a step, so no Hermitian part is formed)
@@ -2419,9 +2421,10 @@ int lmpo_grad_run_renyi2(lmpo_grad *G, double *S2_out, double *grad_out) {
   if (!G || !S2_out || !grad_out) return fail(LMPO_EINVAL, "null argument");
   lmpo_state *S = G->S, *C = G->C;
   const int N = S->N;
-  if (S->opt.precision != LMPO_FP64_REAL)
-    return fail(LMPO_EUNSUPPORTED, "the Renyi-2 gradient needs the state in the real-arithmetic form "
-                                   "(LMPO_FP64_REAL): its co-state starts as a copy of the state's tensors");
+  if (S->opt.precision != LMPO_FP64_REAL && C->opt.precision == LMPO_FP64_REAL)
+    return fail(LMPO_EUNSUPPORTED, "the Renyi-2 gradient of a state in a complex form needs a workspace created "
+                                   "with LMPO_GRAD_COMPLEX_COSTATE: its co-state starts as a copy of the state's "
+                                   "tensors (the real-arithmetic form is the other way)");
   if (!G->series)
     return fail(LMPO_EUNSUPPORTED, "create the workspace with LMPO_GRAD_SERIES for the Renyi-2 gradient (its "
                                    "co-state holds the state plus one bond)");

@@ -425,14 +425,18 @@ class Gradient:
     """Adjoint-gradient workspace of one chain for a fixed number of steps
     (lmpo_grad_*).  Each run() advances the chain by those steps.  series:
     room for run_series; keep_gates: every step's gate snapshots kept from the
-    forward run (no replay in the backward pass, much more device memory)."""
+    forward run (no replay in the backward pass, much more device memory);
+    complex_costate: the co-state in the complex FP64 form (run_renyi2 of a
+    complex-form chain needs it)."""
 
-    def __init__(self, chain, n_steps, costate_chi_max=0, costate_cutoff=-1.0, series=False, keep_gates=False):
+    def __init__(self, chain, n_steps, costate_chi_max=0, costate_cutoff=-1.0, series=False, keep_gates=False,
+                 complex_costate=False):
         import torch
 
         lib = load_library()
         self.chain, self.n_steps = chain, int(n_steps)
-        co = (int(costate_chi_max), float(costate_cutoff), (1 if series else 0) | (2 if keep_gates else 0))
+        co = (int(costate_chi_max), float(costate_cutoff), (1 if series else 0) | (2 if keep_gates else 0)
+              | (4 if complex_costate else 0))
         n = lib.lmpo_grad_arena_bytes(chain._h, self.n_steps, *co)
         if n == 0:
             raise LmpoError(-1, lib.lmpo_last_error().decode())
@@ -483,7 +487,7 @@ class Gradient:
 
     def run_renyi2(self):
         """(S_2, {key: dS_2/dtheta}) for the second Renyi entropy at T (needs
-        series=True at creation and the real-arithmetic form)."""
+        series=True at creation, and the real-arithmetic form or complex_costate=True)."""
         S2 = np.zeros(1)
         g = np.zeros(6 * self.chain.N + 2 * self.n_bonds + 1)
         _check(self._lib.lmpo_grad_run_renyi2(self._h, _dptr(S2), _dptr(g)))
