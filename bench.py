@@ -232,7 +232,8 @@ def gradient_leg(cpu_budget, no_cpu, connected=False):
     replay, co-state backward), against the forward run alone; central
     differences of the GPU forward (h = 1e-5) on a few parameters as a check.
     With `connected`, also the connected correlator <Z_0 Z_15> - <Z_0><Z_15>
-    (one more backward pass from its four-term co-state)."""
+    (one more backward pass from its four-term co-state) and the second Renyi
+    entropy S_2(T) (real-arithmetic form; its co-state starts from the state)."""
     import numpy as np
     import torch
 
@@ -326,6 +327,41 @@ def gradient_leg(cpu_budget, no_cpu, connected=False):
                                     "costate_bond_dims_t0": G.costate_dims(), "derivatives": forty(gc)}
         G.close()
         c.close()
+        # the second Renyi entropy S_2(T): its co-state starts as the state itself
+        # (real-arithmetic form, so the copy is exact), checked against central
+        # differences of the real-form forward on the drive and one decay rate
+        def renyi_forward(model):
+            cr = Chain(model, tau, chi, cut, "real", init, device="cuda:0")
+            cr.evolve(steps)
+            v = cr.renyi2()
+            cr.close()
+            return v
+
+        c = Chain(m, tau, chi, cut, "real", init, device="cuda:0")
+        G = Gradient(c, steps, series=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S2, gs = G.run_renyi2()
+        ts = time.perf_counter() - t0
+        fd2 = {}
+        for key, idx in (("hx", 0), ("g0", 0)):
+            vals = []
+            for sgn in (1.0, -1.0):
+                mm = {k: (np.array(v, dtype=float) if k != "bonds" and isinstance(v, np.ndarray) else v)
+                      for k, v in m.items()}
+                mm[key][idx] += sgn * 1e-5
+                vals.append(renyi_forward(mm))
+            fd2[f"{key}[{idx}]"] = {"adjoint": float(gs[key][idx]), "central_difference": (vals[0] - vals[1]) / 2e-5}
+        out["renyi2"] = {"S2": S2, "seconds": ts, "arena_GB": G.arena.numel() / 1e9,
+                         "state_bond_dims_T": c.bond_dims(), "costate_bond_dims_t0": G.costate_dims(),
+                         "max_abs_gradient": max(float(np.abs(v).max()) for v in gs.values()),
+                         "scaling_identity": {"sum_theta_dS2": float(sum(np.dot(np.asarray(m[k], dtype=float), gs[k])
+                                                                        for k in gs if k != "tau")),
+                                              "tau_dS2_dtau": float(tau * gs["tau"][0])},
+                         "fd_check_h1e-5": fd2, "derivatives": forty(gs)}
+        G.close()
+        c.close()
+        print(f"# Renyi-2 gradient: {ts:.1f} s", file=sys.stderr, flush=True)
     if not no_cpu:
         # oracle on a bounded sample: the whole gradient after the first n
         # steps, n doubling while the budget lasts; the GPU runs the same n
