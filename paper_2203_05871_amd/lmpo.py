@@ -683,8 +683,58 @@ def _series_function():
     return ExpectationSeriesFn
 
 
+def _renyi2_function():
+    import torch
+
+    class Renyi2Fn(torch.autograd.Function):
+        """S_2(T) = -ln(tr rho^2 / (tr rho)^2) as a differentiable function of the
+        model parameters: the forward pass runs lmpo_grad_run_renyi2 (the
+        complex co-state for a complex-form chain) and keeps the gradient, the
+        backward pass scales it."""
+
+        @staticmethod
+        def forward(ctx, spec, *params):
+            model = {"N": spec["N"], "bonds": spec["bonds"]}
+            for key, t in zip(GRAD_SITE_KEYS + GRAD_BOND_KEYS, params):
+                model[key] = t.detach().to("cpu", torch.float64).numpy().reshape(-1)
+            prec = spec.get("precision", "real")
+            ch = Chain(model, spec["tau"], spec["chi_max"], spec.get("cutoff", 0.0), prec, spec.get("init", "+z"),
+                       force_trace=spec.get("force_trace", True), order=spec.get("order", 2),
+                       device=spec.get("device", "cuda:0"))
+            try:
+                G = Gradient(ch, spec["steps"], spec.get("costate_chi_max", 0), spec.get("costate_cutoff", -1.0),
+                             series=True, complex_costate=prec != "real")
+                try:
+                    S2, g = G.run_renyi2()
+                finally:
+                    G.close()
+            finally:
+                ch.close()
+            grads = [torch.as_tensor(g[k], dtype=p.dtype, device=p.device).reshape(p.shape)
+                     for k, p in zip(GRAD_SITE_KEYS + GRAD_BOND_KEYS, params)]
+            ctx.save_for_backward(*grads)
+            return torch.tensor(S2, dtype=torch.float64)
+
+        @staticmethod
+        def backward(ctx, gout):
+            return (None,) + tuple(gout.to(g.dtype) * g for g in ctx.saved_tensors)
+
+    return Renyi2Fn
+
+
 _EXPECTATION_FN = None
 _SERIES_FN = None
+_RENYI2_FN = None
+
+
+def renyi2(spec, params):
+    """Differentiable S_2 = -ln(tr rho^2 / (tr rho)^2) after spec["steps"] steps
+    (Eq. S_2); spec as for expectation() without the observable (precision
+    "real" by default), params likewise."""
+    global _RENYI2_FN
+    if _RENYI2_FN is None:
+        _RENYI2_FN = _renyi2_function()
+    return _RENYI2_FN.apply(spec, *[params[k] for k in GRAD_SITE_KEYS + GRAD_BOND_KEYS])
 
 
 def expectation_series(spec, params):

@@ -211,6 +211,33 @@ def test_autograd_function_matches_the_c_abi_and_the_oracle():
         assert np.abs(params[k].grad.numpy() - 2.0 * go[k].real).max() < 1e-9
 
 
+@pytest.mark.parametrize("precision", ["real", "fp64"])
+def test_autograd_renyi2(precision):
+    """torch.autograd through paper_2203_05871_amd.renyi2: S_2 and .grad equal
+    the workspace's run_renyi2 bit for bit and the oracle's gradient."""
+    import torch
+
+    from paper_2203_05871_amd import renyi2
+
+    m = workloads.random_model(6, 45)
+    spec = {"N": 6, "bonds": m["bonds"], "tau": 0.1, "steps": 3, "chi_max": 8, "cutoff": 1e-10, "init": "+x",
+            "precision": precision}
+    params = {k: torch.tensor(m[k], dtype=torch.float64, requires_grad=True)
+              for k in adjoint.SITE_KEYS + adjoint.BOND_KEYS}
+    S2 = renyi2(spec, params)
+    (-3.0 * S2).backward()
+    ch = _chain(m, 0.1, 8, 1e-10, "+x", precision=precision)
+    G = Gradient(ch, 3, series=True, complex_costate=precision != "real")
+    Sc, gc = G.run_renyi2()
+    G.close()
+    ch.close()
+    assert S2.item() == Sc
+    _, go, _ = adjoint.gradient_renyi2(m, 0.1, 3, 8, 1e-10, "+x")
+    for k in adjoint.SITE_KEYS + adjoint.BOND_KEYS:
+        assert np.array_equal(params[k].grad.numpy(), -3.0 * gc[k])
+        assert np.abs(params[k].grad.numpy() + 3.0 * go[k].real).max() < 1e-9
+
+
 @pytest.mark.timeout(300)
 def test_ladder2x8_full_size_gradient():
     """The 2 x 8 ladder at full size (N=16, chi_max 128, 40 steps): the oracle
