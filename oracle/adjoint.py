@@ -302,23 +302,29 @@ def gradient_series(model, tau, steps, chi_max, cutoff, init, paulis, out_steps,
     return np.array([Fk[int(s)] for s in out_steps]), grads, mps
 
 
-def gradient_renyi2(model, tau, steps, chi_max, cutoff, init, order=2, force_trace=True, costate_chi_max=None,
-                    costate_cutoff=None):
-    """(S_2, {key: dS_2/dtheta}, final MPS) for S_2 = -ln(tr rho^2 / (tr rho)^2)
-    (Eq. S_2).  tr rho^2 = sum rho[k, b] rho[b, k]: its covector is the MPS of
-    rho with every site's (ket, bra) pair exchanged, so the co-state is
-    mu_T = -2 rho^swap / tr rho^2 + 2 . 1 / tr rho, an MPS sum (rho's bonds + 1)
+def costate_renyi2(mps, chi_mu, cut_mu):
+    """The gradient of S_2 = -ln(tr rho^2 / (tr rho)^2) (Eq. S_2) at the MPS rho as
+    a covector: tr rho^2 = sum rho[k, b] rho[b, k], so the covector of its
+    derivative is 2 rho with every site's (ket, bra) pair exchanged, and
+    mu = -2 rho^swap / tr rho^2 + 2 . 1 / tr rho, an MPS sum (rho's bonds + 1)
     compressed like any source."""
-    chi_mu = chi_max if costate_chi_max is None else costate_chi_max
-    cut_mu = cutoff if costate_cutoff is None else costate_cutoff
-    N = model["N"]
-    mps, records, traces = forward_record(model, tau, steps, chi_max, cutoff, init, order, force_trace)
+    N = mps.N
     t2, tr = mps.tr_rho2(), mps.trace()
     swap = np.array([0, 2, 1, 3])
     rho_sw = tebd.MPS([a[:, swap, :].copy() for a in mps.A], 0)
     rho_sw.A[-1] = rho_sw.A[-1] * (-2.0 / t2)
-    mu = add_compress(rho_sw, costate_terms(N, [(2.0 / tr, {})]), chi_mu, cut_mu)
-    S2 = -np.log(t2 / tr ** 2)
+    return add_compress(rho_sw, costate_terms(N, [(2.0 / tr, {})]), chi_mu, cut_mu)
+
+
+def gradient_renyi2(model, tau, steps, chi_max, cutoff, init, order=2, force_trace=True, costate_chi_max=None,
+                    costate_cutoff=None):
+    """(S_2, {key: dS_2/dtheta}, final MPS) for S_2 at T (Eq. S_2): the co-state
+    pass from costate_renyi2 of the final state."""
+    chi_mu = chi_max if costate_chi_max is None else costate_chi_max
+    cut_mu = cutoff if costate_cutoff is None else costate_cutoff
+    mps, records, traces = forward_record(model, tau, steps, chi_max, cutoff, init, order, force_trace)
+    S2 = -np.log(mps.tr_rho2() / mps.trace() ** 2)
+    mu = costate_renyi2(mps, chi_mu, cut_mu)
     return S2, backward(model, tau, records, traces, mu, chi_mu, cut_mu, order), mps
 
 

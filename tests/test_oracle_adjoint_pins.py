@@ -355,3 +355,22 @@ def test_renyi2_gradient_equals_dense_trotter_derivative():
             vals.append(dense_S2(mm))
         ref.append((vals[0] - vals[1]) / (2 * h))
     assert np.abs(adjoint.flatten(m, g) - np.array(ref)).max() < 1e-8
+
+
+def test_renyi2_costate_brute_force():
+    """<mu, v> = the derivative of S_2 at rho along v (central differences of the
+    dense S_2 of rho + eps v), v Hermitian with nonzero trace: the trace term,
+    which exact trace-preserving dynamics never sees, is pinned here."""
+    m = rich_chain(3, 46)
+    mps, _, _ = adjoint.forward_record(m, 0.1, 2, 64, 0.0, "+x")
+    mu = adjoint.costate_renyi2(mps, 64, 0.0)
+    r = dense.mps_to_vector(mps.A)
+    rng = np.random.default_rng(46)
+    v = rng.standard_normal(64) + 1j * rng.standard_normal(64)
+    v = 0.5 * (v + dense.adjoint(v, 3))
+    assert abs(dense.trace(v, 3)) > 0.1
+    eps = 1e-6
+    ref = (dense.renyi2(r + eps * v, 3) - dense.renyi2(r - eps * v, 3)) / (2 * eps)
+    got = np.dot(dense.mps_to_vector(mu.A), v)
+    assert abs(got.imag) < 1e-10
+    assert abs(got.real - ref) < 1e-7 * max(1.0, abs(ref))
