@@ -328,6 +328,40 @@ def gradient_renyi2(model, tau, steps, chi_max, cutoff, init, order=2, force_tra
     return S2, backward(model, tau, records, traces, mu, chi_mu, cut_mu, order), mps
 
 
+def costate_osee(mps, bond):
+    """(OSEE, mu): the operator-space entanglement entropy across (bond, bond + 1)
+    (Eq. OSEE) at the MPS rho and its gradient as a covector.  With the centre
+    on site `bond`, the site's matrix is M = U diag(s) V^dagger, p = s^2 / W with
+    W = sum s^2, S = -sum p ln p, and dS/ds_i = (2 s_i / W)(-ln p_i - S).  Along
+    a Hermitian direction ds_i = Re <u_i v_i^dagger, dM> (Frobenius): for
+    Hermitian rho this is the bilinear pairing with the complex conjugate, so mu
+    is the conjugate of the MPS with M replaced by U diag(dS/ds) V^dagger.
+    Nothing is truncated."""
+    c = tebd.MPS([a.copy() for a in mps.A], mps.centre)
+    c.move_centre(bond)
+    l, _, r = c.A[bond].shape
+    U, s, Vh = np.linalg.svd(c.A[bond].reshape(l * 4, r), full_matrices=False)
+    W = np.sum(s ** 2)
+    p = s ** 2 / W
+    nz = p > 0
+    S = float(-np.sum(p[nz] * np.log(p[nz])))
+    g = np.zeros_like(s)
+    g[nz] = 2.0 * s[nz] / W * (-np.log(p[nz]) - S)
+    c.A[bond] = ((U * g) @ Vh).reshape(l, 4, r)
+    return S, tebd.MPS([np.conj(a) for a in c.A], bond)
+
+
+def gradient_osee(model, tau, steps, chi_max, cutoff, init, bond, order=2, force_trace=True, costate_chi_max=None,
+                  costate_cutoff=None):
+    """(OSEE, {key: dOSEE/dtheta}, final MPS) across (bond, bond + 1) at T: the
+    co-state pass from costate_osee of the final state."""
+    chi_mu = chi_max if costate_chi_max is None else costate_chi_max
+    cut_mu = cutoff if costate_cutoff is None else costate_cutoff
+    mps, records, traces = forward_record(model, tau, steps, chi_max, cutoff, init, order, force_trace)
+    S, mu = costate_osee(mps, bond)
+    return S, backward(model, tau, records, traces, mu, chi_mu, cut_mu, order), mps
+
+
 def gradient_connected(model, tau, steps, chi_max, cutoff, init, i, j, paulis="ZZ", order=2, force_trace=True,
                        costate_chi_max=None, costate_cutoff=None):
     """(C, {key: dC/dtheta}, final MPS) for the connected correlator

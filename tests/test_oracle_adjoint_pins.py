@@ -374,3 +374,48 @@ def test_renyi2_costate_brute_force():
     got = np.dot(dense.mps_to_vector(mu.A), v)
     assert abs(got.imag) < 1e-10
     assert abs(got.real - ref) < 1e-7 * max(1.0, abs(ref))
+
+
+@pytest.mark.parametrize("bond", [0, 1, 2])
+def test_osee_costate_brute_force(bond):
+    """<mu, v> = the derivative of the OSEE (Eq. OSEE) at rho along a Hermitian v:
+    central differences of the dense OSEE (the SVD of the full vector)."""
+    m = rich_chain(4, 47)
+    mps, _, _ = adjoint.forward_record(m, 0.1, 3, 64, 0.0, "+x")
+    S, mu = adjoint.costate_osee(mps, bond)
+    r = dense.mps_to_vector(mps.A)
+    assert abs(S - dense.osee(r, 4, bond)) < 1e-12
+    rng = np.random.default_rng(bond)
+    v = rng.standard_normal(256) + 1j * rng.standard_normal(256)
+    v = 0.5 * (v + dense.adjoint(v, 4))
+    v = v / np.linalg.norm(v) * np.linalg.norm(r)
+    f = lambda e: dense.osee(r + e * v, 4, bond)  # noqa: E731
+    eps = 1e-4  # fourth-order central stencil: the smallest weights (p ~ 1e-8) bend S fast
+    ref = (8.0 * (f(eps) - f(-eps)) - (f(2 * eps) - f(-2 * eps))) / (12 * eps)
+    got = np.dot(dense.mps_to_vector(mu.A), v)
+    assert abs(got.imag) < 1e-9
+    assert abs(got.real - ref) < 1e-8 * max(1.0, abs(ref))
+
+
+def test_osee_gradient_equals_dense_trotter_derivative():
+    """dOSEE/dtheta across the middle bond against dense differences of the OSEE of
+    the dense Trotter evolution."""
+    m = rich_chain(4, 48)
+    tau, steps, h = 0.1, 3, 1e-6
+
+    def dense_osee(model):
+        v = dense.trotter_evolve(dense.product_vector("+x", 4), model, tau, steps)
+        return dense.osee(v, 4, 1)
+
+    S, g, _ = adjoint.gradient_osee(m, tau, steps, 16, 0.0, "+x", 1)
+    assert abs(S - dense_osee(m)) < 1e-12
+    ref = []
+    for key, idx in adjoint.parameter_list(m):
+        vals = []
+        for sgn in (1.0, -1.0):
+            mm = {k: (np.array(v, dtype=float) if k in adjoint.SITE_KEYS + adjoint.BOND_KEYS else v)
+                  for k, v in m.items()}
+            mm[key][idx] += sgn * h
+            vals.append(dense_osee(mm))
+        ref.append((vals[0] - vals[1]) / (2 * h))
+    assert np.abs(adjoint.flatten(m, g) - np.array(ref)).max() < 1e-7
