@@ -437,6 +437,19 @@ int lmpo_grad_run_connected(lmpo_grad *g, int32_t i, int32_t j, const char *paul
  * moves. */
 int lmpo_grad_run_renyi2(lmpo_grad *g, double S2[1], double *grad_out);
 
+/* As lmpo_grad_run for the operator-space entanglement entropy across bond
+ * (bond, bond + 1) at T (Eq. OSEE; the value lmpo_osee reports): value[0] =
+ * S = -sum p ln p with p = s^2 / sum s^2 over the bond's singular values s,
+ * grad_out = dS/dtheta.  With dS/ds_i = (2 s_i / W)(-ln p_i - S), W = sum s^2,
+ * the co-state is the state with the bond's matrix U diag(s) V^T replaced by
+ * U diag(dS/ds) V^T: the state's tensors copied at T, an identity gate on the
+ * bond with cutoff 0 (every nonzero singular value kept), and its right factor
+ * rescaled row by row.  Needs the state in the real-arithmetic form
+ * (LMPO_FP64_REAL) and a co-state chi_max at least the state's:
+ * LMPO_EUNSUPPORTED otherwise, checked before the state moves; a bond outside
+ * 0..n_qubits-2 is LMPO_EINVAL. */
+int lmpo_grad_run_osee(lmpo_grad *g, int32_t bond, double value[1], double *grad_out);
+
 /* Bond dims of the co-state (n_qubits - 1 entries): after a run, those of
  * mu at time 0, the end of the backward pass.  Synchronises. */
 int lmpo_grad_costate_dims(lmpo_grad *g, int32_t *out);

@@ -169,6 +169,63 @@ __global__ void mps_sum_site_kernel(const double2 *__restrict__ A, const double2
   }
 }
 
+// Site k right after an identity gate on bond (k - 1, k) swept left to right
+// holds diag(s) V^dagger: rows are the bond index, each of length 4 chr, and
+// with every site to its right right-orthonormal row i has norm s_i.  With
+// p_i = s_i^2 / W, W = sum s^2 and S = -sum p ln p (the OSEE across the bond,
+// into *out), dS/ds_i = (2 s_i / W)(-ln p_i - S): scaling row i by that over
+// s_i, (2 / W)(-ln p_i - S), makes the site the right factor of
+// U diag(dS/ds) V^dagger.  Rows of zero weight are left zero.  One workgroup;
+// rows <= kOseeRows (checked on the host).
+__global__ __launch_bounds__(256) void osee_costate_kernel(double2 *const *sites, const int *dims, int N, int k,
+                                                           double *out) {
+  __shared__ double nrm[kOseeRows];
+  __shared__ double red[256];
+  const int rows = dims[k - 1], len = 4 * (k == N - 1 ? 1 : dims[k]);
+  double2 *A = sites[k];
+  auto reduce = [&](double v) {
+    red[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 128; off > 0; off >>= 1) {
+      if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+      __syncthreads();
+    }
+    const double r = red[0];
+    __syncthreads();
+    return r;
+  };
+  for (int i = 0; i < rows; ++i) {
+    double acc = 0.0;
+    for (int e = threadIdx.x; e < len; e += 256) {
+      const double2 v = A[(size_t)i * len + e];
+      acc = fma(v.x, v.x, fma(v.y, v.y, acc));
+    }
+    const double r = reduce(acc);
+    if (threadIdx.x == 0) nrm[i] = r;
+  }
+  __syncthreads();
+  double w = 0.0;
+  for (int i = threadIdx.x; i < rows; i += 256) w += nrm[i];
+  const double W = reduce(w);
+  double h = 0.0;
+  for (int i = threadIdx.x; i < rows; i += 256) {
+    const double p = nrm[i] / W;
+    if (p > 0.0) h -= p * log(p);
+  }
+  const double S = reduce(h);
+  for (size_t e = threadIdx.x; e < (size_t)rows * len; e += 256) {
+    const double p = nrm[e / len] / W;
+    const double f = p > 0.0 ? (2.0 / W) * (-log(p) - S) : 0.0;
+    A[e] = make_double2(A[e].x * f, A[e].y * f);
+  }
+  if (threadIdx.x == 0) out[0] = S;
+}
+
+void launch_osee_costate(hipStream_t s, double2 *const *sites, const int *dims, int N, int k, double *out) {
+  hipLaunchKernelGGL(osee_costate_kernel, dim3(1), dim3(256), 0, s, sites, dims, N, k, out);
+  (void)hipGetLastError();
+}
+
 __global__ void add_dims_kernel(int *dims, int n, int add) {
   for (int b = threadIdx.x; b < n; b += blockDim.x) dims[b] += add;
 }

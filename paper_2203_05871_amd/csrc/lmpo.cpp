@@ -2459,6 +2459,53 @@ int lmpo_grad_run_renyi2(lmpo_grad *G, double *S2_out, double *grad_out) {
   return LMPO_OK;
 }
 
+int lmpo_grad_run_osee(lmpo_grad *G, int32_t bond, double *value, double *grad_out) {
+  if (!G || !value || !grad_out) return fail(LMPO_EINVAL, "null argument");
+  lmpo_state *S = G->S, *C = G->C;
+  const int N = S->N;
+  if (bond < 0 || bond >= N - 1) return fail(LMPO_EINVAL, "bond out of range");
+  if (S->opt.precision != LMPO_FP64_REAL || C->opt.precision != LMPO_FP64_REAL)
+    return fail(LMPO_EUNSUPPORTED, "the OSEE gradient needs the state and the co-state in the real-arithmetic form "
+                                   "(LMPO_FP64_REAL): its co-state is the state with the bond's singular values "
+                                   "replaced");
+  for (int b = 0; b < N - 1; ++b)  // before the state moves
+    if (C->cap[b] < S->cap[b] || S->cap[b] > kOseeRows)
+      return fail(LMPO_EUNSUPPORTED, "the OSEE co-state starts as a copy of the state: its chi_max must be at least "
+                                     "the state's");
+  long long step0;
+  std::complex<double> trT;
+  std::vector<double2> tr_host;
+  int rc = grad_forward(G, step0, trT, tr_host);
+  if (rc || (rc = sync_dims(S))) return rc;
+  for (int k = 0; k < N; ++k) {
+    const size_t n = (size_t)(k == 0 ? 1 : S->dims[k - 1]) * 4 * (k == N - 1 ? 1 : S->dims[k]);
+    HIP_TRY(hipMemcpyAsync(C->site[k], S->site[k], n * sizeof(double2), hipMemcpyDeviceToDevice, C->stream));
+  }
+  C->dims = S->dims;
+  HIP_TRY(hipMemcpyAsync(C->d_dims, C->dims.data(), (N - 1) * sizeof(int), hipMemcpyHostToDevice, C->stream));
+  HIP_TRY(hipStreamSynchronize(C->stream));
+  C->centre = S->centre;
+  // the bond's SVD through an identity gate swept left to right, nothing
+  // truncated but exact zeros (the bond cannot grow): site bond + 1 becomes
+  // diag(s) V^T with right-orthonormal sites after it; the kernel rescales its
+  // rows to dS/ds_i and reports S
+  const double cut = C->opt.cutoff;
+  C->opt.cutoff = 0.0;
+  rc = apply_gate_dev(C, bond, C->d_ident, 1);
+  C->opt.cutoff = cut;
+  if (rc) return rc;
+  launch_osee_costate(C->stream, C->d_sites, C->d_dims, N, bond + 1, C->aux + 3);
+  HIP_TRY(hipGetLastError());
+  double h = 0.0;
+  HIP_TRY(hipMemcpyAsync(&h, C->aux + 3, sizeof(double), hipMemcpyDeviceToHost, C->stream));
+  HIP_TRY(hipStreamSynchronize(C->stream));
+  if ((rc = check_err(C))) return rc;
+  if (!std::isfinite(h)) return fail(LMPO_ENUMERIC, "non-finite entropy");
+  if ((rc = grad_backward(G, step0, tr_host, grad_out))) return rc;
+  *value = h;
+  return LMPO_OK;
+}
+
 lmpo_state *lmpo_grad_costate(lmpo_grad *G) { return G ? G->C : nullptr; }
 
 size_t lmpo_probe_fp64_mfma_bytes(void) { return (size_t)2048 * 256 * sizeof(double); }

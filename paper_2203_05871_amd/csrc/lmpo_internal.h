@@ -32,6 +32,7 @@ void swap_pauli(std::complex<double> *G);
 constexpr int JB = 8;
 constexpr int JP = 2 * JB;
 constexpr int kMaxDim = 2048;  // largest block side (4 chi) the sort handles
+constexpr int kOseeRows = kMaxDim / 4;  // largest bond the OSEE co-state kernel takes
 constexpr int kGateSlots = 12;  // gates per bond: the time fractions of orders 2, 3 and 4
 
 // Workgroups that serve one persistent SVD or hop whose Jacobi/QR works on C
@@ -137,5 +138,6 @@ void launch_grad_accumulate(hipStream_t s, const double2 *K, const int *pidx, in
 void launch_mps_sum_site(hipStream_t s, const double2 *A, const double2 *B, double2 *dst, const int *dims, int N,
                          int k, int kb);
 void launch_add_dims(hipStream_t s, int *dims, int n, int add);
+void launch_osee_costate(hipStream_t s, double2 *const *sites, const int *dims, int N, int k, double *out);
 
 }  // namespace lmpo

@@ -70,7 +70,7 @@ EXPORTS = [
     "lmpo_batch_plan", "lmpo_batch_profile_begin", "lmpo_batch_profile_end", "lmpo_batch_destroy",
     "lmpo_batch_set_autotune", "lmpo_autotune_table",
     "lmpo_grad_arena_bytes", "lmpo_grad_create", "lmpo_grad_run", "lmpo_grad_costate_dims", "lmpo_grad_costate", "lmpo_grad_run_connected", "lmpo_grad_run_series",
-    "lmpo_grad_run_renyi2",
+    "lmpo_grad_run_renyi2", "lmpo_grad_run_osee",
     "lmpo_probe_fp64_mfma_bytes", "lmpo_probe_fp64_mfma",
     "lmpo_grad_destroy",
 ]
@@ -137,6 +137,7 @@ def load_library(path: str = LIB_PATH):
         "lmpo_grad_costate_dims": (ctypes.c_int, [P, pi32]),
         "lmpo_grad_costate": (P, [P]),
         "lmpo_grad_run_renyi2": (ctypes.c_int, [P, pdbl, pdbl]),
+        "lmpo_grad_run_osee": (ctypes.c_int, [P, i32, pdbl, pdbl]),
         "lmpo_grad_run_connected": (ctypes.c_int, [P, i32, i32, ctypes.c_char_p, pdbl, pdbl]),
         "lmpo_probe_fp64_mfma_bytes": (ctypes.c_size_t, []),
         "lmpo_probe_fp64_mfma": (ctypes.c_int, [P, P, ctypes.c_size_t, pdbl]),
@@ -493,6 +494,15 @@ class Gradient:
         _check(self._lib.lmpo_grad_run_renyi2(self._h, _dptr(S2), _dptr(g)))
         _, out = self._unpack(np.zeros(2), g)
         return float(S2[0]), out
+
+    def run_osee(self, bond):
+        """(OSEE, {key: dOSEE/dtheta}) across bond (bond, bond + 1) at T (needs
+        the real-arithmetic form)."""
+        h = np.zeros(1)
+        g = np.zeros(6 * self.chain.N + 2 * self.n_bonds + 1)
+        _check(self._lib.lmpo_grad_run_osee(self._h, int(bond), _dptr(h), _dptr(g)))
+        _, out = self._unpack(np.zeros(2), g)
+        return float(h[0]), out
 
     def _unpack(self, F, g):
         N, nb = self.chain.N, self.n_bonds

@@ -77,6 +77,7 @@ def test_gradient_entry_points_reject_bad_arguments_on_host():
     assert lib.lmpo_grad_costate(None) is None
     assert lib.lmpo_grad_run_connected(None, 0, 1, b"ZZ", None, None) == -1
     assert lib.lmpo_grad_run_renyi2(None, None, None) == -1
+    assert lib.lmpo_grad_run_osee(None, 0, None, None) == -1
     assert lib.lmpo_probe_fp64_mfma_bytes() == 2048 * 256 * 8
     assert lib.lmpo_probe_fp64_mfma(None, None, 0, None) == -1
     assert lib.lmpo_set_svd_tolerance(None, 32.0) == -1

@@ -557,3 +557,66 @@ def test_renyi2_gradient_checks():
         G.close()
     assert all(np.array_equal(x, ch.get_site(k)) for k, x in enumerate(before))
     ch.close()
+
+
+@pytest.mark.parametrize("case", ["exact_chain_mid", "exact_chain_edge", "truncated_ladder", "costate_truncated"])
+def test_osee_gradient(case):
+    """dOSEE/dtheta across a bond (Eq. OSEE): the co-state is the state with the
+    bond's singular values replaced by dS/ds; against the oracle (which takes
+    the SVD of the centre site in its own basis and conjugates), the value
+    against lmpo_osee on the state left at T, and the scaling identity."""
+    co_chi = co_cut = None
+    if case.startswith("exact_chain"):
+        m, tau, steps, chi, cut, init = workloads.random_model(5, 49), 0.1, 3, 32, 0.0, "+x"
+        bond = 2 if case.endswith("mid") else 0
+    else:
+        lad = workloads.ladder_model(4)
+        m = workloads.random_model(8, 50, bonds=lad["bonds"])
+        tau, steps, chi, cut, init, bond = 0.1, 4, 8, 1e-10, "+z", 3
+        if case == "costate_truncated":
+            co_chi, co_cut = 8, 1e-6
+    print(f"gradient case: osee {case} N={m['N']} bond={bond} chi={chi} co-state {co_chi} {co_cut}", flush=True)
+    ch = _chain(m, tau, chi, cut, init, precision="real")
+    G = Gradient(ch, steps, co_chi or 0, -1.0 if co_cut is None else co_cut)
+    S, g = G.run_osee(bond)
+    G.close()
+    assert abs(ch.osee(bond) - S) < 1e-12
+    ch.close()
+    So, go, _ = adjoint.gradient_osee(m, tau, steps, chi, cut, init, bond, costate_chi_max=co_chi,
+                                      costate_cutoff=co_cut)
+    got = np.concatenate([g[k] for k in adjoint.SITE_KEYS + adjoint.BOND_KEYS + ("tau",)])
+    ref = np.concatenate([adjoint.flatten(m, go).real, go["tau"].real])
+    err = np.abs(got - ref).max() / max(1.0, np.abs(ref).max())
+    print(f"  OSEE = {S:.12f} (oracle {So:.12f}), max |grad - oracle| / scale = {err:.2e}", flush=True)
+    assert abs(S - So) < 1e-11
+    assert err < 1e-9
+    theta = np.concatenate([np.asarray(m[k], dtype=float) for k in adjoint.SITE_KEYS + adjoint.BOND_KEYS])
+    lhs, rhs = float(theta @ got[:-1]), tau * got[-1]
+    assert abs(lhs - rhs) < 1e-9 * max(1.0, abs(rhs)), (lhs, rhs)
+
+
+def test_osee_gradient_checks():
+    """Refused before the state moves: a complex-form state, a bond out of
+    range, a co-state chi_max below the state's."""
+    from paper_2203_05871_amd import LmpoError
+
+    m = workloads.random_model(4, 51)
+    ch = _chain(m, 0.1, 8, 1e-10, "+x")
+    G = Gradient(ch, 2)
+    with pytest.raises(LmpoError, match="real-arithmetic"):
+        G.run_osee(1)
+    G.close()
+    ch.close()
+    ch = _chain(m, 0.1, 8, 1e-10, "+x", precision="real")
+    before = [ch.get_site(k) for k in range(4)]
+    G = Gradient(ch, 2)
+    for b in (-1, 3):
+        with pytest.raises(LmpoError, match="bond out of range"):
+            G.run_osee(b)
+    G.close()
+    G = Gradient(ch, 2, co_chi=2)
+    with pytest.raises(LmpoError, match="at least the state's"):
+        G.run_osee(1)
+    G.close()
+    assert all(np.array_equal(x, ch.get_site(k)) for k, x in enumerate(before))
+    ch.close()
