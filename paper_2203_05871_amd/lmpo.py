@@ -693,14 +693,15 @@ def _series_function():
     return ExpectationSeriesFn
 
 
-def _renyi2_function():
+def _entropy_function(kind):
     import torch
 
-    class Renyi2Fn(torch.autograd.Function):
-        """S_2(T) = -ln(tr rho^2 / (tr rho)^2) as a differentiable function of the
-        model parameters: the forward pass runs lmpo_grad_run_renyi2 (the
-        complex co-state for a complex-form chain) and keeps the gradient, the
-        backward pass scales it."""
+    class EntropyFn(torch.autograd.Function):
+        """S_2(T) = -ln(tr rho^2 / (tr rho)^2) (kind "renyi2") or the OSEE across
+        spec["bond"] (kind "osee") as a differentiable function of the model
+        parameters: the forward pass runs lmpo_grad_run_renyi2 (the complex
+        co-state for a complex-form chain) or lmpo_grad_run_osee and keeps the
+        gradient, the backward pass scales it."""
 
         @staticmethod
         def forward(ctx, spec, *params):
@@ -713,9 +714,9 @@ def _renyi2_function():
                        device=spec.get("device", "cuda:0"))
             try:
                 G = Gradient(ch, spec["steps"], spec.get("costate_chi_max", 0), spec.get("costate_cutoff", -1.0),
-                             series=True, complex_costate=prec != "real")
+                             series=kind == "renyi2", complex_costate=kind == "renyi2" and prec != "real")
                 try:
-                    S2, g = G.run_renyi2()
+                    S2, g = G.run_renyi2() if kind == "renyi2" else G.run_osee(spec["bond"])
                 finally:
                     G.close()
             finally:
@@ -729,22 +730,30 @@ def _renyi2_function():
         def backward(ctx, gout):
             return (None,) + tuple(gout.to(g.dtype) * g for g in ctx.saved_tensors)
 
-    return Renyi2Fn
+    return EntropyFn
 
 
 _EXPECTATION_FN = None
 _SERIES_FN = None
-_RENYI2_FN = None
+_ENTROPY_FN = {}
 
 
 def renyi2(spec, params):
     """Differentiable S_2 = -ln(tr rho^2 / (tr rho)^2) after spec["steps"] steps
     (Eq. S_2); spec as for expectation() without the observable (precision
     "real" by default), params likewise."""
-    global _RENYI2_FN
-    if _RENYI2_FN is None:
-        _RENYI2_FN = _renyi2_function()
-    return _RENYI2_FN.apply(spec, *[params[k] for k in GRAD_SITE_KEYS + GRAD_BOND_KEYS])
+    if "renyi2" not in _ENTROPY_FN:
+        _ENTROPY_FN["renyi2"] = _entropy_function("renyi2")
+    return _ENTROPY_FN["renyi2"].apply(spec, *[params[k] for k in GRAD_SITE_KEYS + GRAD_BOND_KEYS])
+
+
+def osee(spec, params):
+    """Differentiable OSEE across bond spec["bond"] (bond, bond + 1) after
+    spec["steps"] steps (Eq. OSEE); spec as for renyi2() (the real-arithmetic
+    form, the default, is required), params likewise."""
+    if "osee" not in _ENTROPY_FN:
+        _ENTROPY_FN["osee"] = _entropy_function("osee")
+    return _ENTROPY_FN["osee"].apply(spec, *[params[k] for k in GRAD_SITE_KEYS + GRAD_BOND_KEYS])
 
 
 def expectation_series(spec, params):

@@ -238,6 +238,32 @@ def test_autograd_renyi2(precision):
         assert np.abs(params[k].grad.numpy() + 3.0 * go[k].real).max() < 1e-9
 
 
+def test_autograd_osee():
+    """torch.autograd through paper_2203_05871_amd.osee: the value and .grad equal
+    the workspace's run_osee bit for bit and the oracle's gradient."""
+    import torch
+
+    from paper_2203_05871_amd import osee
+
+    m = workloads.random_model(6, 52)
+    spec = {"N": 6, "bonds": m["bonds"], "tau": 0.1, "steps": 3, "chi_max": 8, "cutoff": 1e-10, "init": "+x",
+            "bond": 2}
+    params = {k: torch.tensor(m[k], dtype=torch.float64, requires_grad=True)
+              for k in adjoint.SITE_KEYS + adjoint.BOND_KEYS}
+    S = osee(spec, params)
+    (0.5 * S).backward()
+    ch = _chain(m, 0.1, 8, 1e-10, "+x", precision="real")
+    G = Gradient(ch, 3)
+    Sc, gc = G.run_osee(2)
+    G.close()
+    ch.close()
+    assert S.item() == Sc
+    _, go, _ = adjoint.gradient_osee(m, 0.1, 3, 8, 1e-10, "+x", 2)
+    for k in adjoint.SITE_KEYS + adjoint.BOND_KEYS:
+        assert np.array_equal(params[k].grad.numpy(), 0.5 * gc[k])
+        assert np.abs(params[k].grad.numpy() - 0.5 * go[k].real).max() < 1e-9
+
+
 @pytest.mark.timeout(300)
 def test_ladder2x8_full_size_gradient():
     """The 2 x 8 ladder at full size (N=16, chi_max 128, 40 steps): the oracle
