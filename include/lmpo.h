@@ -444,8 +444,10 @@ int lmpo_grad_run_renyi2(lmpo_grad *g, double S2[1], double *grad_out);
  * the co-state is the state with the bond's matrix U diag(s) V^T replaced by
  * U diag(dS/ds) V^T: the state's tensors copied at T, an identity gate on the
  * bond with cutoff 0 (every nonzero singular value kept), and its right factor
- * rescaled row by row.  Needs the state in the real-arithmetic form
- * (LMPO_FP64_REAL) and a co-state chi_max at least the state's:
+ * rescaled row by row (with complex tensors the row norms are still the s_i and
+ * the co-state's coefficients stay real).  Needs the state in the
+ * real-arithmetic form (LMPO_FP64_REAL) or a workspace created with
+ * LMPO_GRAD_COMPLEX_COSTATE, and a co-state chi_max at least the state's:
  * LMPO_EUNSUPPORTED otherwise, checked before the state moves; a bond outside
  * 0..n_qubits-2 is LMPO_EINVAL. */
 int lmpo_grad_run_osee(lmpo_grad *g, int32_t bond, double value[1], double *grad_out);

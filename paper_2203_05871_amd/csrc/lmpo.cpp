@@ -2464,10 +2464,13 @@ int lmpo_grad_run_osee(lmpo_grad *G, int32_t bond, double *value, double *grad_o
   lmpo_state *S = G->S, *C = G->C;
   const int N = S->N;
   if (bond < 0 || bond >= N - 1) return fail(LMPO_EINVAL, "bond out of range");
-  if (S->opt.precision != LMPO_FP64_REAL || C->opt.precision != LMPO_FP64_REAL)
-    return fail(LMPO_EUNSUPPORTED, "the OSEE gradient needs the state and the co-state in the real-arithmetic form "
-                                   "(LMPO_FP64_REAL): its co-state is the state with the bond's singular values "
-                                   "replaced");
+  // the Pauli-basis coefficients of rho, and so those of the co-state, are
+  // real whatever the gauge of the tensors: a complex-form state only needs a
+  // co-state that holds its tensors exactly
+  if (S->opt.precision != LMPO_FP64_REAL && C->opt.precision == LMPO_FP64_REAL)
+    return fail(LMPO_EUNSUPPORTED, "the OSEE gradient of a state in a complex form needs a workspace created with "
+                                   "LMPO_GRAD_COMPLEX_COSTATE: its co-state starts as a copy of the state's tensors "
+                                   "(the real-arithmetic form is the other way)");
   for (int b = 0; b < N - 1; ++b)  // before the state moves
     if (C->cap[b] < S->cap[b] || S->cap[b] > kOseeRows)
       return fail(LMPO_EUNSUPPORTED, "the OSEE co-state starts as a copy of the state: its chi_max must be at least "

@@ -497,7 +497,7 @@ class Gradient:
 
     def run_osee(self, bond):
         """(OSEE, {key: dOSEE/dtheta}) across bond (bond, bond + 1) at T (needs
-        the real-arithmetic form)."""
+        the real-arithmetic form or complex_costate=True)."""
         h = np.zeros(1)
         g = np.zeros(6 * self.chain.N + 2 * self.n_bonds + 1)
         _check(self._lib.lmpo_grad_run_osee(self._h, int(bond), _dptr(h), _dptr(g)))
@@ -714,7 +714,7 @@ def _entropy_function(kind):
                        device=spec.get("device", "cuda:0"))
             try:
                 G = Gradient(ch, spec["steps"], spec.get("costate_chi_max", 0), spec.get("costate_cutoff", -1.0),
-                             series=kind == "renyi2", complex_costate=kind == "renyi2" and prec != "real")
+                             series=kind == "renyi2", complex_costate=prec != "real")
                 try:
                     S2, g = G.run_renyi2() if kind == "renyi2" else G.run_osee(spec["bond"])
                 finally:
@@ -749,8 +749,7 @@ def renyi2(spec, params):
 
 def osee(spec, params):
     """Differentiable OSEE across bond spec["bond"] (bond, bond + 1) after
-    spec["steps"] steps (Eq. OSEE); spec as for renyi2() (the real-arithmetic
-    form, the default, is required), params likewise."""
+    spec["steps"] steps (Eq. OSEE); spec as for renyi2(), params likewise."""
     if "osee" not in _ENTROPY_FN:
         _ENTROPY_FN["osee"] = _entropy_function("osee")
     return _ENTROPY_FN["osee"].apply(spec, *[params[k] for k in GRAD_SITE_KEYS + GRAD_BOND_KEYS])
