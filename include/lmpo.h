@@ -366,7 +366,7 @@ typedef struct lmpo_grad lmpo_grad;
  * (one forward run less; same results).  LMPO_GRAD_COMPLEX_COSTATE: the co-state
  * in the complex FP64 form instead of the real-arithmetic one (about four
  * times the co-state's SVD flops; the same gradient to round-off), which the
- * Renyi-2 gradient of a state in a complex form needs. */
+ * Renyi-2 and OSEE gradients of a state in a complex form need. */
 enum { LMPO_GRAD_SERIES = 1, LMPO_GRAD_KEEP_GATES = 2, LMPO_GRAD_COMPLEX_COSTATE = 4 };
 
 /* Device bytes of the workspace for n_steps >= 1 steps of s (0 on invalid

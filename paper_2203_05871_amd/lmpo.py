@@ -427,8 +427,8 @@ class Gradient:
     (lmpo_grad_*).  Each run() advances the chain by those steps.  series:
     room for run_series; keep_gates: every step's gate snapshots kept from the
     forward run (no replay in the backward pass, much more device memory);
-    complex_costate: the co-state in the complex FP64 form (run_renyi2 of a
-    complex-form chain needs it)."""
+    complex_costate: the co-state in the complex FP64 form (run_renyi2 and
+    run_osee of a complex-form chain need it)."""
 
     def __init__(self, chain, n_steps, costate_chi_max=0, costate_cutoff=-1.0, series=False, keep_gates=False,
                  complex_costate=False):
