@@ -15,7 +15,12 @@ fixed initial state; or a weighted sum of a string's expectations at several
 output steps (each output's gradient enters the co-state as a source when the
 backward pass reaches its step, added to the co-state MPS by a direct sum
 compressed like the Hermitian part: QR from the left, truncated identity gates
-from the right).  Parameters: every
+from the right); or the second Renyi entropy S_2 (Eq. S_2) or the
+operator-space entanglement entropy across a bond (Eq. OSEE) at T, whose
+co-states are built from rho_T itself (costate_renyi2, costate_osee: each
+pinned against central differences of the dense entropy along a Hermitian
+direction).  Every objective is unchanged when rho_T is scaled, which is
+what lets the traces divided out enter only through s_g below.  Parameters: every
 entry of hx, hy, hz, g0, g1, g2 (per qubit) and J, Jz (per bond) of the model
 of Sec. 2.1.  Each bond generator L_b is linear in every one of them (the
 Hamiltonian enters through a commutator, each rate multiplies its dissipator),
