@@ -445,7 +445,9 @@ int lmpo_grad_run_renyi2(lmpo_grad *g, double S2[1], double *grad_out);
  * U diag(dS/ds) V^T: the state's tensors copied at T, an identity gate on the
  * bond with cutoff 0 (every nonzero singular value kept), and its right factor
  * rescaled row by row (with complex tensors the row norms are still the s_i and
- * the co-state's coefficients stay real).  Needs the state in the
+ * the co-state's coefficients stay real).  When every dS/ds_i is zero (a single
+ * nonzero weight, or equal weights) the gradient is zero and no backward pass
+ * runs.  Needs the state in the
  * real-arithmetic form (LMPO_FP64_REAL) or a workspace created with
  * LMPO_GRAD_COMPLEX_COSTATE, and a co-state chi_max at least the state's:
  * LMPO_EUNSUPPORTED otherwise, checked before the state moves; a bond outside

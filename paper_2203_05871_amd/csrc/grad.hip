@@ -175,8 +175,9 @@ __global__ void mps_sum_site_kernel(const double2 *__restrict__ A, const double2
 // p_i = s_i^2 / W, W = sum s^2 and S = -sum p ln p (the OSEE across the bond,
 // into *out), dS/ds_i = (2 s_i / W)(-ln p_i - S): scaling row i by that over
 // s_i, (2 / W)(-ln p_i - S), makes the site the right factor of
-// U diag(dS/ds) V^dagger.  Rows of zero weight are left zero.  One workgroup;
-// rows <= kOseeRows (checked on the host).
+// U diag(dS/ds) V^dagger.  Rows of zero weight are left zero.  out[1] =
+// sum_i (dS/ds_i)^2: zero when the co-state is (a single weight, or equal
+// weights).  One workgroup; rows <= kOseeRows (checked on the host).
 __global__ __launch_bounds__(256) void osee_costate_kernel(double2 *const *sites, const int *dims, int N, int k,
                                                            double *out) {
   __shared__ double nrm[kOseeRows];
@@ -213,12 +214,22 @@ __global__ __launch_bounds__(256) void osee_costate_kernel(double2 *const *sites
     if (p > 0.0) h -= p * log(p);
   }
   const double S = reduce(h);
+  double q = 0.0;
+  for (int i = threadIdx.x; i < rows; i += 256) {
+    const double p = nrm[i] / W;
+    const double f = p > 0.0 ? (2.0 / W) * (-log(p) - S) : 0.0;
+    q = fma(nrm[i] * f, f, q);
+  }
+  const double G2 = reduce(q);
   for (size_t e = threadIdx.x; e < (size_t)rows * len; e += 256) {
     const double p = nrm[e / len] / W;
     const double f = p > 0.0 ? (2.0 / W) * (-log(p) - S) : 0.0;
     A[e] = make_double2(A[e].x * f, A[e].y * f);
   }
-  if (threadIdx.x == 0) out[0] = S;
+  if (threadIdx.x == 0) {
+    out[0] = S;
+    out[1] = G2;
+  }
 }
 
 void launch_osee_costate(hipStream_t s, double2 *const *sites, const int *dims, int N, int k, double *out) {

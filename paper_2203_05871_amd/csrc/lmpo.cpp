@@ -2497,15 +2497,22 @@ int lmpo_grad_run_osee(lmpo_grad *G, int32_t bond, double *value, double *grad_o
   rc = apply_gate_dev(C, bond, C->d_ident, 1);
   C->opt.cutoff = cut;
   if (rc) return rc;
-  launch_osee_costate(C->stream, C->d_sites, C->d_dims, N, bond + 1, C->aux + 3);
+  double *res = reinterpret_cast<double *>(G->gam);  // free until the backward pass
+  launch_osee_costate(C->stream, C->d_sites, C->d_dims, N, bond + 1, res);
   HIP_TRY(hipGetLastError());
-  double h = 0.0;
-  HIP_TRY(hipMemcpyAsync(&h, C->aux + 3, sizeof(double), hipMemcpyDeviceToHost, C->stream));
+  double h[2] = {0.0, 0.0};
+  HIP_TRY(hipMemcpyAsync(h, res, sizeof(h), hipMemcpyDeviceToHost, C->stream));
   HIP_TRY(hipStreamSynchronize(C->stream));
   if ((rc = check_err(C))) return rc;
-  if (!std::isfinite(h)) return fail(LMPO_ENUMERIC, "non-finite entropy");
-  if ((rc = grad_backward(G, step0, tr_host, grad_out))) return rc;
-  *value = h;
+  if (!std::isfinite(h[0]) || !std::isfinite(h[1])) return fail(LMPO_ENUMERIC, "non-finite entropy");
+  if (h[1] > 0.0) {
+    rc = grad_backward(G, step0, tr_host, grad_out);
+  } else {  // a zero co-state (one weight, or all equal): a zero gradient, the state restored as usual
+    const std::vector<std::vector<CostateTerm>> none(G->n_steps);
+    rc = grad_backward(G, step0, tr_host, grad_out, &none, false);
+  }
+  if (rc) return rc;
+  *value = h[0];
   return LMPO_OK;
 }
 

@@ -694,3 +694,43 @@ def test_osee_gradient_checks():
     G.close()
     assert all(np.array_equal(x, ch.get_site(k)) for k, x in enumerate(before))
     ch.close()
+
+
+def test_entropy_gradient_edge_cases():
+    """N = 2 (S_2 and the OSEE of its one bond, one step) against the oracle; a
+    bond with no coupling across it (the state a product there at every time):
+    OSEE 0 and a zero gradient, the oracle's too."""
+    m2 = workloads.random_model(2, 54)
+    ch = _chain(m2, 0.1, 8, 1e-12, "+x", precision="real")
+    G = Gradient(ch, 1, series=True)
+    S2, g2 = G.run_renyi2()
+    Sb, gb = G.run_osee(0)  # continues from the state after the first run: two steps in all
+    G.close()
+    ch.close()
+    So, go, _ = adjoint.gradient_renyi2(m2, 0.1, 1, 8, 1e-12, "+x")
+    assert abs(S2 - So) < 1e-12
+    assert np.abs(np.concatenate([g2[k] for k in adjoint.SITE_KEYS + adjoint.BOND_KEYS])
+                  - adjoint.flatten(m2, go).real).max() < 1e-9
+    ch = _chain(m2, 0.1, 8, 1e-12, "+x", precision="real")
+    ch.evolve(1)
+    G = Gradient(ch, 1)
+    Sb2, gb2 = G.run_osee(0)
+    G.close()
+    ch.close()
+    assert Sb == Sb2 and all(np.array_equal(gb[k], gb2[k]) for k in gb)
+    m = workloads.random_model(3, 53)
+    m["J"] = np.array(m["J"], dtype=float)
+    m["Jz"] = np.array(m["Jz"], dtype=float)
+    m["J"][0] = m["Jz"][0] = 0.0
+    print("gradient case: osee across an uncoupled bond, N=3", flush=True)
+    ch = _chain(m, 0.1, 8, 1e-12, "+x", precision="real")
+    G = Gradient(ch, 2)
+    S, g = G.run_osee(0)
+    G.close()
+    ch.close()
+    _, go, _ = adjoint.gradient_osee(m, 0.1, 2, 8, 1e-12, "+x", 0)
+    got = np.concatenate([g[k] for k in adjoint.SITE_KEYS + adjoint.BOND_KEYS + ("tau",)])
+    print(f"  OSEE = {S:.3e}, max |grad| = {np.abs(got).max():.3e}", flush=True)
+    assert abs(S) < 1e-14
+    assert np.abs(got).max() < 1e-10
+    assert np.abs(adjoint.flatten(m, go)).max() == 0.0
