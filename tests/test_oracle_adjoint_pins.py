@@ -397,17 +397,18 @@ def test_osee_costate_brute_force(bond):
     assert abs(got.real - ref) < 1e-8 * max(1.0, abs(ref))
 
 
-def test_osee_gradient_equals_dense_trotter_derivative():
-    """dOSEE/dtheta across the middle bond against dense differences of the OSEE of
-    the dense Trotter evolution."""
+@pytest.mark.parametrize("bond", [0, 1, 2])
+def test_osee_gradient_equals_dense_trotter_derivative(bond):
+    """dOSEE/dtheta across each bond of a 4-qubit chain against dense
+    differences of the OSEE of the dense Trotter evolution."""
     m = rich_chain(4, 48)
     tau, steps, h = 0.1, 3, 1e-6
 
     def dense_osee(model):
         v = dense.trotter_evolve(dense.product_vector("+x", 4), model, tau, steps)
-        return dense.osee(v, 4, 1)
+        return dense.osee(v, 4, bond)
 
-    S, g, _ = adjoint.gradient_osee(m, tau, steps, 16, 0.0, "+x", 1)
+    S, g, _ = adjoint.gradient_osee(m, tau, steps, 16, 0.0, "+x", bond)
     assert abs(S - dense_osee(m)) < 1e-12
     ref = []
     for key, idx in adjoint.parameter_list(m):
