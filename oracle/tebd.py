@@ -24,7 +24,8 @@ two-site block theta = G (A_k A_{k+1}) as a (4 chi_l) x (4 chi_r) matrix;
 full SVD (LAPACK); keep k' = min(chi_max, k_c) singular triplets, where k_c is
 the smallest k' >= 1 whose discarded squared weight sum_{j > k'} s_j^2 is at
 most cutoff * sum_j s_j^2 (App. B: the more severe of cut_off_rho and
-max_dim_rho).  An ascending gate leaves A_k = U, A_{k+1} = S V^+ (centre moves
+max_dim_rho), except that a multiplet of (near-)equal singular values is never
+split by the cut (see truncation_rank).  An ascending gate leaves A_k = U, A_{k+1} = S V^+ (centre moves
 right), a descending one A_k = U S, A_{k+1} = V^+.  Singular values are not
 rescaled.  After each step, when trace forcing is on, rho -> rho / tr(rho)
 with the complex trace (App. B, b_force_rho_trace).
@@ -136,11 +137,30 @@ def sweep_schedule(model, order=2):
     return out
 
 
+TIE = 1e-4  # neighbouring singular values closer than TIE times the larger form one multiplet
+
+
 def truncation_rank(s, chi_max, cutoff):
-    """k' = min(chi_max, k_c); s sorted descending (App. B).
+    """k' = min(chi_max, k_c); s sorted descending (App. B), adjusted so that
+    the cut does not split a multiplet.
+
+    App. B and Sec. 6 bound the discarded weight (cut_off_rho) and the bond
+    dimension (max_dim_rho) but do not say which singular vectors of a
+    degenerate multiplet straddling the cut are kept; any basis of the
+    multiplet is a valid SVD, so splitting it leaves the truncated state
+    undetermined (two backward-stable SVDs then disagree by about the
+    multiplet's singular value).  Reading: neighbours with s_q - s_{q+1} <=
+    TIE * s_q tie (a split of a pair that close moves the kept subspace by
+    about eps s_1 / (s_q - s_{q+1}) under round-off, i.e. the truncated state
+    by eps s_1 s_q / (s_q - s_{q+1})); when the cutoff set the cut, it moves
+    past the multiplet
+    while chi_max allows (discarding less than the cutoff permits), otherwise
+    it moves in front of the multiplet (keeping fewer than chi_max).  Exact
+    zeros never join a multiplet and are always discarded; k' >= 1.
 
     Returns (k', discarded squared weight, total squared weight)."""
-    w = s.astype(np.float64) ** 2
+    s = np.asarray(s, dtype=np.float64)
+    w = s ** 2
     W = float(np.sum(w))
     r = len(s)
     # tail[k] = sum_{j >= k} w_j  (weight discarded when k values are kept)
@@ -151,7 +171,17 @@ def truncation_rank(s, chi_max, cutoff):
         if tail[k] <= cutoff * W:
             kc = k
             break
-    k = max(1, min(int(chi_max), kc))
+    nz = int(np.count_nonzero(s > 0))
+    k = max(1, min(int(chi_max), kc, nz))
+
+    def tie(q):  # the q-th and (q+1)-th values (1-based) tie; both nonzero
+        return q < nz and s[q - 1] - s[q] <= TIE * s[q - 1]
+
+    if k == kc:
+        while k < min(int(chi_max), nz) and tie(k):
+            k += 1
+    while k > 1 and tie(k):
+        k -= 1
     return k, float(tail[k]), W
 
 

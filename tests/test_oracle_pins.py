@@ -271,6 +271,7 @@ def test_trace_and_hermiticity_invariants():
     ([1.0, 0.5], 9, 0.19, 2),                     # tail 0.25 >  0.19 * 1.25
 ])
 def test_truncation_rule_brute_force(s, chi, cut, k):
+    """Spectra without ties: the plain rule of App. B."""
     s = np.array(s)
     got, disc, W = tebd.truncation_rank(s, chi, cut)
     # brute force: smallest kk >= 1 whose discarded weight is within the cutoff
@@ -280,6 +281,41 @@ def test_truncation_rule_brute_force(s, chi, cut, k):
     assert disc == pytest.approx(w[got:].sum())
     assert W == pytest.approx(w.sum())
     assert got == k
+
+
+@pytest.mark.parametrize("s,chi,cut,k", [
+    ([1.0, 0.5, 0.5, 0.1], 2, 0.0, 1),            # chi_max cuts the pair 0.5, 0.5: drop it whole
+    ([1.0, 0.5, 0.5, 0.1], 3, 0.0, 3),            # the pair fits under chi_max: no change
+    ([1.0, 0.5, 0.5, 0.5, 0.1], 2, 0.0, 1),       # a triplet
+    ([1.0, 0.5, 0.5, 0.5, 0.1], 3, 0.0, 1),
+    ([1.0, 0.3, 0.3, 1e-4], 9, 0.05, 3),          # the cutoff alone keeps one of the pair: keep both
+    ([1.0, 0.3, 0.3, 1e-4], 2, 0.05, 1),          # ... unless chi_max forbids: drop both
+    ([1.0, 0.3, 0.3 - 2e-5, 1e-4], 2, 0.05, 1),   # within 1e-4 of 0.3: a multiplet, dropped whole
+    ([1.0, 0.3, 0.3 - 5e-5, 1e-4], 2, 0.05, 2),   # 5e-5 / 0.3 > 1e-4 apart: two values, the plain rule
+    ([1.0, 1e-12, 5e-13, 0.0], 2, 0.0, 2),        # values far below s_1 tie only relative to themselves
+    ([1.0, 1.0, 0.2], 1, 0.0, 1),                 # the multiplet holds s_1: k stays >= 1
+    ([1e-20, 1e-20, 0.0], 1, 0.0, 1),
+    ([2.0, 1e-12, 0.0, 0.0], 9, 0.0, 2),          # tiny nonzero vs exact zero: no tie, zeros dropped
+])
+def test_truncation_rule_never_splits_a_multiplet(s, chi, cut, k):
+    """Spectra with ties at the cut, against a brute force over every k:
+    among the ks that do not split a multiplet (the k-th and (k+1)-th values
+    not within 1e-4 of the k-th, exact zeros excluded) and keep at most chi_max, the
+    smallest whose discarded weight is within the cutoff if one exists, else
+    the largest (chi_max decides)."""
+    s = np.array(s)
+    got, disc, W = tebd.truncation_rank(s, chi, cut)
+    w = s ** 2
+    nz = int(np.count_nonzero(s))
+
+    def splits(kk):
+        return kk < nz and s[kk - 1] - s[kk] <= 1e-4 * s[kk - 1]
+
+    ok = [kk for kk in range(1, nz + 1) if kk <= chi and not splits(kk)]
+    within = [kk for kk in ok if w[kk:].sum() <= cut * w.sum()]
+    want = min(within) if within else (max(ok) if ok else 1)
+    assert got == want == k
+    assert disc == pytest.approx(w[got:].sum(), abs=1e-300)
 
 
 def test_truncated_converges_to_dense_as_chi_grows():
