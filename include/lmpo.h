@@ -11,7 +11,11 @@
  * two-site propagators exp(x L_b), each followed by a truncated SVD that keeps
  * the more severe of a discarded-weight cutoff and a maximal bond dimension
  * (App. B, parameters cut_off_rho / max_dim_rho of Sec. 6), with the trace
- * forced to one after every step (b_force_rho_trace, Sec. 6).
+ * forced to one after every step (b_force_rho_trace, Sec. 6).  The cut never
+ * splits a multiplet of singular values (neighbours closer than 1e-4 times the
+ * larger; the paper does not say which vectors of a degenerate multiplet to
+ * keep, and any choice is an SVD): a cut set by the cutoff moves past the
+ * multiplet while chi_max allows, otherwise in front of it.
  *
  * Conventions
  *  - All functions return 0 (LMPO_OK) or a negative error code; a message is
@@ -87,7 +91,8 @@ typedef struct {
                             LMPO_EUNSUPPORTED */
   int32_t chi_max;       /* max_dim_rho, >= 1 */
   double cutoff;         /* cut_off_rho: largest discarded squared Schmidt weight,
-                            relative to the block's total; >= 0 */
+                            relative to the block's total; >= 0 (a multiplet at the
+                            cut is kept whole when chi_max allows) */
   int32_t precision;     /* LMPO_FP64, LMPO_FP32_CONTRACT (two-site contractions
                             in FP32 with FP32 accumulation, SVD/truncation/trace FP64),
                             or LMPO_FP64_REAL (real arithmetic, see above) */

@@ -19,6 +19,8 @@
 // |g_pq| <= tol sqrt(g_pp g_qq): the columns are then orthogonal to working
 // accuracy relative to their own norms, which gives small singular values
 // to high relative accuracy.
+#include <cstdlib>
+
 #include "contract_tile.h"
 #include "householder.h"
 #include "lmpo_internal.h"
@@ -517,6 +519,10 @@ __device__ void order_columns(SharedSelect &s, const double *__restrict__ nrm, i
   __syncthreads();
 }
 
+// Neighbouring singular values closer than kTie times the larger one form one
+// multiplet at the truncation cut (block_select).
+constexpr double kTie = 1e-4;
+
 __device__ void block_select(SharedSelect &s, const double *__restrict__ sig, int C, int chi_max, double cutoff,
                              int hop, int *__restrict__ perm, double *__restrict__ sorted, int *__restrict__ kept,
                              int *__restrict__ dims_slot, double *__restrict__ disc, int *__restrict__ err) {
@@ -581,9 +587,21 @@ __device__ void block_select(SharedSelect &s, const double *__restrict__ sig, in
     if (hop) {
       k = s.cnt_nz;
     } else {
-      int kc = 1 + s.cnt_above;
+      // k = min(chi_max, k_c) over the nonzero values, then moved off a
+      // multiplet: neighbours closer than kTie times the larger are one
+      // multiplet and the cut never splits it (which of its vectors to keep
+      // is not determined); a cut set by the cutoff moves past the multiplet
+      // while chi_max allows, otherwise in front of it
+      const int nz = s.cnt_nz;
+      const int kc = 1 + s.cnt_above;
       k = kc < chi_max ? kc : chi_max;
-      if (k > s.cnt_nz) k = s.cnt_nz;
+      if (k > nz) k = nz;
+      if (k < 1) k = 1;
+      auto tie = [&](int q) { return q < nz && s.key[q - 1] - s.key[q] <= kTie * s.key[q - 1]; };
+      const int kmax = chi_max < nz ? chi_max : nz;
+      if (k == kc)
+        while (k < kmax && tie(k)) ++k;
+      while (k > 1 && tie(k)) --k;
     }
     if (k < 1) k = 1;
     if (s.bad || !(W > 0.0)) *err = 1;
@@ -1243,6 +1261,28 @@ int svd_grid_size() {
   return g_grid;
 }
 
+// The persistent kernels need every workgroup of their grid resident at once
+// (they meet at grid barriers).  The grids are sized to the co-resident
+// capacity (one workgroup per compute unit), and by default the launch is
+// cooperative, so that the runtime guarantees residency.  With the environment
+// variable LMPO_PLAIN_LAUNCH=1 the same grid goes through an ordinary launch:
+// rocprofv3's counter collection intercepts ordinary dispatches only (its
+// --pmc mode fails inside hipLaunchCooperativeKernel).  On an otherwise idle
+// device the grid is then resident as well; should it not be, the bounded
+// waits of the grid barrier end the kernel with an error instead of a hang.
+static bool plain_launch() {
+  static const bool plain = [] {
+    const char *v = std::getenv("LMPO_PLAIN_LAUNCH");
+    return v && v[0] == '1';
+  }();
+  return plain;
+}
+
+static hipError_t launch_persistent(const void *fn, int grid, void **args, hipStream_t s) {
+  if (plain_launch()) return hipLaunchKernel(fn, dim3(grid), dim3(NT), args, 0, s);
+  return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(NT), args, 0, s);
+}
+
 hipError_t launch_svd_persistent(hipStream_t s, const SvdLaunch &L, int grid) {
   hipError_t e = hipMemsetAsync(L.bar, 0, kBarWords * sizeof(unsigned), s);
   if (e != hipSuccess) return e;
@@ -1250,7 +1290,7 @@ hipError_t launch_svd_persistent(hipStream_t s, const SvdLaunch &L, int grid) {
   void *args[] = {&a};
   const void *fn = L.real ? reinterpret_cast<const void *>(svd_persistent_kernel<true>)
                          : reinterpret_cast<const void *>(svd_persistent_kernel<false>);
-  return hipLaunchCooperativeKernel(fn, dim3(grid), dim3(NT), args, 0, s);
+  return launch_persistent(fn, grid, args, s);
 }
 
 int batch_grid_size() {
@@ -1270,8 +1310,7 @@ hipError_t launch_batch_layer(hipStream_t s, const BatchChain *d_chains, const i
   if (e != hipSuccess) return e;
   void *args[] = {(void *)&d_chains, (void *)&d_block_group, (void *)&d_block_rank, (void *)&d_group_size,
                   &local_step, &j, &parity, &slot, &last_layer};
-  return hipLaunchCooperativeKernel(reinterpret_cast<const void *>(batch_layer_kernel), dim3(total_blocks), dim3(NT),
-                                    args, 0, s);
+  return launch_persistent(reinterpret_cast<const void *>(batch_layer_kernel), total_blocks, args, s);
 }
 
 }  // namespace lmpo

@@ -1,5 +1,6 @@
 """The benchmark's output line: one JSON object with the fields its readers
-rely on, from a short run (3 timed steps) of the default workload."""
+rely on, from a short run (3 timed steps from a briefly settled state) of
+the default workload."""
 import json
 import os
 import sys
@@ -15,11 +16,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def test_bench_line_fields(capsys, monkeypatch):
     """In this process (a second process on the GPU beside the test runner's
     own context is not what the benchmark is run as)."""
-    print("bench contract: 3 steps, no variants, 2 s of oracle", flush=True)
+    print("bench contract: settled to t=0.5, 3 steps, headline and oracle sample only", flush=True)
     import bench
 
-    monkeypatch.setattr(sys, "argv", ["bench.py", "--steps", "3", "--warmup", "1", "--no-saturated", "--no-variants",
-                                      "--no-real", "--no-gradient", "--cpu-budget", "2"])
+    monkeypatch.setattr(sys, "argv", ["bench.py", "--steps", "3", "--warmup", "1", "--settle-t", "0.5",
+                                      "--no-configured", "--no-batched", "--no-gradient", "--cpu-budget", "2"])
     capsys.readouterr()
     bench.main()
     out = capsys.readouterr().out

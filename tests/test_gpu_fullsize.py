@@ -233,3 +233,35 @@ def test_chain30_full_run_parity(Chain):
     assert abs(ch.trace() - 1.0) < 1e-12
     ch.close()
     c32.close()
+
+
+@pytest.mark.timeout(400)
+def test_chain30_fp32_against_fp64_where_chi256_binds(Chain):
+    """The 30-site benchmark chain where chi_max = 256 binds on every interior
+    bond (cutoff 0: four steps from +x fill the bonds, 1024 x 1024 blocks in
+    the bulk); from that one state the FP32-contraction form and the FP64 form
+    each run two more steps: every <sz_i> and <sz_i sz_j> within 1e-5, the bond
+    dims identical."""
+    m, run = workloads.chain30_jittered()
+    N = m["N"]
+    print("case: N=30 chain, chi 256, cutoff 0, 4 steps then 2 per form", flush=True)
+    ch = Chain(m, run["tau"], run["chi_max"], 0.0, "fp64", run["init"])
+    ch.evolve(4)
+    dims = ch.bond_dims()
+    assert dims[3:-3] == [256] * (N - 7), dims
+    sites = [ch.get_site(k) for k in range(N)]
+    centre = ch.centre()
+    ch.close()
+    out = {}
+    for prec in ("fp64", "fp32"):
+        c = Chain(m, run["tau"], run["chi_max"], 0.0, prec, run["init"])
+        inject(c, sites, centre)
+        c.evolve(2)
+        out[prec] = (c.zz_observables(), c.bond_dims())
+        c.close()
+    (z1, z2), d64 = out["fp64"]
+    (f1, f2), d32 = out["fp32"]
+    err = max(np.abs(f1 - z1).max(), np.abs(f2 - z2).max())
+    print(f"  max |obs fp32 - fp64| = {err:.2e}", flush=True)
+    assert d32 == d64
+    assert err < 1e-5

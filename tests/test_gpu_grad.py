@@ -264,6 +264,51 @@ def test_autograd_osee():
         assert np.abs(params[k].grad.numpy() - 0.5 * go[k].real).max() < 1e-9
 
 
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("objective", ["z15", "connected_z0_z15"])
+def test_ladder2x8_configured_objectives_against_the_oracle(objective):
+    """Both objectives of the ladder's differentiation workload, <s^z_15> and
+    the connected <s^z_0 s^z_15>_c, on the 2 x 8 ladder (chi_max 128, cutoff
+    1e-12, tau 0.05, from +z) after its first 16 steps: all 6N + 2 n_bonds =
+    140 parameter derivatives and d/dtau against the oracle's, element by
+    element, to 1e-9 of the largest derivative (no absolute floor).  The
+    connected correlator's derivative dC = dF_ij - F_j dF_i - F_i dF_j is a
+    difference of terms of the size of dF_ij (about 1 here, with F_j = <s^z_15>
+    within 1e-11 of 1) that cancel down to about 1e-5, so its round-off is set
+    by the terms: its bar is 1e-9 of the larger of its own and dF_ij's largest
+    derivative, dF_ij from the same GPU run's Pauli string Z_0 Z_15."""
+    m, run = workloads.ladder2x8()
+    tau, chi, cut, init = run["tau"], run["chi_max"], run["cutoff"], run["init"]
+    n = 16
+    print(f"gradient case: 2x8 ladder, chi 128, first {n} steps, {objective}", flush=True)
+    ch = _chain(m, tau, chi, cut, init)
+    G = Gradient(ch, n)
+    if objective == "z15":
+        F, g = G.run(15, "Z")
+        Fo, go, _ = adjoint.gradient(m, tau, n, chi, cut, init, 15, "Z")
+    else:
+        F, g = G.run_connected(0, 15, "ZZ")
+        Fo, go, _ = adjoint.gradient_connected(m, tau, n, chi, cut, init, 0, 15, "ZZ")
+    G.close()
+    ch.close()
+    got = np.concatenate([g[k] for k in adjoint.SITE_KEYS + adjoint.BOND_KEYS + ("tau",)])
+    ref = np.concatenate([adjoint.flatten(m, go).real, go["tau"].real])
+    assert len(got) == 6 * m["N"] + 2 * len(m["bonds"]) + 1 == 141
+    scale = np.abs(ref).max()
+    if objective != "z15":
+        ch = _chain(m, tau, chi, cut, init)
+        _, gij = ch.gradient(n, paulis="Z" + "I" * 14 + "Z")
+        ch.close()
+        term = max(float(np.abs(v).max()) for v in gij.values())
+        print(f"  largest derivative of F_ij = <Z_0 Z_15>: {term:.3e}", flush=True)
+        scale = max(scale, term)
+    err = np.abs(got - ref).max() / scale
+    print(f"  F = {F.real:.15f} (oracle {Fo.real:.15f}), largest derivative {np.abs(ref).max():.3e}, "
+          f"bar scale {scale:.3e}, max |grad - oracle| / scale = {err:.2e}", flush=True)
+    assert abs(F - Fo) < 1e-12
+    assert err < 1e-9, err
+
+
 @pytest.mark.timeout(300)
 def test_ladder2x8_full_size_gradient():
     """The 2 x 8 ladder at full size (N=16, chi_max 128, 40 steps): the oracle
