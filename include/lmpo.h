@@ -146,6 +146,22 @@ int lmpo_measure_1q(lmpo_state *s, int32_t n, const int32_t *site, const char *p
 int lmpo_measure_2q(lmpo_state *s, int32_t n, const int32_t *i, const int32_t *j,
                     const char *paulis, double *out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): lmpo_measure_2q with
+ * the same arguments, results and kernels, but whose working memory (the
+ * trace, the two identity environments of (N + 1) x chi_cap complex entries
+ * each, the request rows and the numerators) lives in a fixed 2 MiB device
+ * array of the library (one per GPU, held until the process ends) instead of
+ * the state's arena.  It calls no hipMalloc / hipFree.  A state needing more
+ * than 2 MiB, i.e. 2 (N + 1) chi_cap * 16 bytes + 128 KiB (chi_cap the largest
+ * bond capacity), gives LMPO_EUNSUPPORTED before anything runs.  Every call on
+ * one GPU shares that array and leaves its contents behind: calls that overlap
+ * in time on one GPU (several host threads or streams) race and must be
+ * serialised by the caller.  The state's device must be current.
+ * Synchronises. */
+int lmpo_measure_2q_noalloc(lmpo_state *s, int32_t n, const int32_t *i, const int32_t *j,
+                            const char *paulis, double *out);
+
 /* Second Renyi entropy S_2 = -ln tr(rho^2) (Eq. S_2, Sec. 2.4), evaluated as
  * -ln( <<rho|rho>> / |tr rho|^2 ): <<rho|rho>> = tr(rho^dagger rho) is the squared
  * norm of the orthogonality centre (the state is kept in mixed-canonical form)

@@ -197,6 +197,7 @@ struct lmpo_state {
   double *sig = nullptr, *sorted = nullptr, *disc = nullptr, *aux = nullptr;
   double2 *tr = nullptr, *envL = nullptr, *envR = nullptr, *mout = nullptr;
   long long step_index = 0;  // global Trotter step count (fixes the layer order)
+  int device = 0;            // the GPU current at creation
   std::vector<std::complex<double>> gates_host;  // [nb][kGateSlots][256]
   bool chain = true;            // bond list is the open chain (b, b+1) in order
   double2 *d_swap = nullptr;    // exchange of two sites (Pauli basis)
@@ -745,6 +746,10 @@ size_t lmpo_arena_bytes(const lmpo_model *model, const lmpo_options *opt) {
   return layout(&tmp, z, model->n_qubits, model->n_bonds, nullptr, 0) + 256;
 }
 
+namespace {
+int scratch_setup(int device);
+}  // namespace
+
 int lmpo_create(const lmpo_model *model, const lmpo_options *opt, const char *init_pauli, void *device_arena,
                 size_t arena_bytes, void *hip_stream, lmpo_state **out) {
   if (!out) return fail(LMPO_EINVAL, "out is null");
@@ -764,6 +769,10 @@ int lmpo_create(const lmpo_model *model, const lmpo_options *opt, const char *in
   S->herm_room = opt->force_hermitian_every > 0;
   S->N = model->n_qubits;
   S->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  if (hipGetDevice(&S->device) != hipSuccess || (rc = scratch_setup(S->device)) != LMPO_OK) {
+    delete S;
+    return rc ? rc : fail(LMPO_EHIP, "hipGetDevice failed");
+  }
   size_t need = layout(S, z, S->N, S->m.nb, reinterpret_cast<char *>(device_arena), arena_bytes);
   if (need > arena_bytes) {
     delete S;
@@ -910,6 +919,104 @@ int run_measure(lmpo_state *S, const std::vector<int> &req, double *out) {
   return check_err(S);
 }
 }  // namespace
+
+// ---- allocation-free measurement (lmpo_measure_2q_noalloc) ----
+// A fixed device array serves as the measurement's working memory instead of
+// the state's arena: the trace, the left and right identity environments, the
+// request rows and the numerators.  Each GPU that the library runs on holds
+// its own copy until the process ends.  In host code `scratch` names a
+// host-side stand-in, not a device address: the address is resolved once per
+// device with hipGetSymbolAddress (at state creation, with the state's device
+// current) and only that address is handed to kernels and copies.
+namespace {
+constexpr size_t kScratchBytes = size_t(2) << 20;  // 2 MiB per device
+constexpr size_t kScratchHead = 256;               // the trace (one double2), padded
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+char *g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return fail(LMPO_EUNSUPPORTED, "device index above 63");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return LMPO_OK;
+  void *p = nullptr;
+  hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p)
+    return fail(LMPO_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+  g_scratch_ptr[device] = static_cast<char *>(p);
+  return LMPO_OK;
+}
+
+// Bytes of scratch a state's measurement needs: the trace, both environments
+// ((N + 1) x chi capacity each), kMaxReq request rows and numerators.
+size_t scratch_need(const lmpo_state *S) {
+  return kScratchHead + 2 * ((size_t)(S->N + 1) * S->cap_max * sizeof(double2)) + 4 * (size_t)kMaxReq * sizeof(int) +
+         (size_t)kMaxReq * sizeof(double2);
+}
+}  // namespace
+
+int lmpo_measure_2q_noalloc(lmpo_state *S, int32_t n, const int32_t *i, const int32_t *j, const char *paulis,
+                            double *out) {
+  if (!S || n < 0 || (n > 0 && (!i || !j || !paulis || !out))) return fail(LMPO_EINVAL, "null argument or n < 0");
+  const size_t need = scratch_need(S);
+  if (need > kScratchBytes)
+    return fail(LMPO_EUNSUPPORTED, "lmpo_measure_2q_noalloc: the state needs " + std::to_string(need) +
+                                       " bytes of measurement scratch, above the fixed " +
+                                       std::to_string(kScratchBytes) + " (2 (N + 1) chi_cap 16 + 128 KiB)");
+  for (int q = 0; q < n; ++q) {
+    const int a = pauli_index(paulis[2 * q]), b = pauli_index(paulis[2 * q + 1]);
+    if (i[q] < 0 || i[q] >= S->N || j[q] < 0 || j[q] >= S->N) return fail(LMPO_EINVAL, "site index out of range");
+    if (i[q] == j[q]) return fail(LMPO_EINVAL, "2Q observable needs i != j");
+    if (a <= 0 || b <= 0) return fail(LMPO_EINVAL, "paulis must be X, Y or Z");
+  }
+  if (n == 0) return LMPO_OK;
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != S->device) return fail(LMPO_EINVAL, "the state's device is not the current device");
+  int rc = scratch_setup(dev);  // resolved at creation already; a no-op here
+  if (rc) return rc;
+  char *base = g_scratch_ptr[dev];
+  double2 *tr_d = reinterpret_cast<double2 *>(base);
+  double2 *envL = reinterpret_cast<double2 *>(base + kScratchHead);
+  double2 *envR = envL + (size_t)(S->N + 1) * S->cap_max;
+  int *req_d = reinterpret_cast<int *>(envR + (size_t)(S->N + 1) * S->cap_max);
+  double2 *num_d = reinterpret_cast<double2 *>(req_d + 4 * (size_t)kMaxReq);
+  // host staging of fixed size per thread (no allocation per call)
+  static thread_local int req_h[4 * kMaxReq];
+  static thread_local double2 num_h[kMaxReq];
+  launch_env_all(S->stream, S->d_sites, S->d_dims, S->N, S->cap_max, envL, envR);
+  launch_trace(S->stream, S->d_sites, S->d_dims, S->N, tr_d);
+  double2 tr;
+  HIP_TRY(hipMemcpyAsync(&tr, tr_d, sizeof(double2), hipMemcpyDeviceToHost, S->stream));
+  for (int q0 = 0; q0 < n; q0 += kMaxReq) {
+    const int m = std::min(kMaxReq, n - q0);
+    for (int q = 0; q < m; ++q) {
+      int ii = i[q0 + q], jj = j[q0 + q];
+      int a = pauli_index(paulis[2 * (q0 + q)]), b = pauli_index(paulis[2 * (q0 + q) + 1]);
+      if (ii > jj) {
+        std::swap(ii, jj);
+        std::swap(a, b);
+      }
+      req_h[4 * q] = ii;
+      req_h[4 * q + 1] = a;
+      req_h[4 * q + 2] = jj;
+      req_h[4 * q + 3] = b;
+    }
+    HIP_TRY(hipMemcpyAsync(req_d, req_h, 4 * (size_t)m * sizeof(int), hipMemcpyHostToDevice, S->stream));
+    launch_measure(S->stream, S->d_sites, S->d_dims, S->N, S->cap_max, envL, envR, m, req_d, num_d);
+    HIP_TRY(hipMemcpyAsync(num_h, num_d, (size_t)m * sizeof(double2), hipMemcpyDeviceToHost, S->stream));
+    HIP_TRY(hipStreamSynchronize(S->stream));
+    const double d = tr.x * tr.x + tr.y * tr.y;
+    if (!(d > 0) || !std::isfinite(d)) return fail(LMPO_ENUMERIC, "trace is zero or non-finite");
+    for (int q = 0; q < m; ++q) {
+      const double2 v = num_h[q];
+      out[2 * (q0 + q)] = (v.x * tr.x + v.y * tr.y) / d;
+      out[2 * (q0 + q) + 1] = (v.y * tr.x - v.x * tr.y) / d;
+    }
+  }
+  return check_err(S);
+}
 
 int lmpo_measure_1q(lmpo_state *S, int32_t n, const int32_t *site, const char *pauli, double *out) {
   if (!S || n < 0 || (n > 0 && (!site || !pauli || !out))) return fail(LMPO_EINVAL, "null argument or n < 0");

@@ -60,7 +60,7 @@ _lib = None
 
 EXPORTS = [
     "lmpo_arena_bytes", "lmpo_create", "lmpo_evolve_step", "lmpo_trace", "lmpo_renormalize",
-    "lmpo_measure_1q", "lmpo_measure_2q", "lmpo_bond_dims", "lmpo_discarded_weight", "lmpo_sync",
+    "lmpo_measure_1q", "lmpo_measure_2q", "lmpo_measure_2q_noalloc", "lmpo_bond_dims", "lmpo_discarded_weight", "lmpo_sync",
     "lmpo_destroy", "lmpo_last_error", "lmpo_get_site", "lmpo_set_site", "lmpo_set_centre",
     "lmpo_get_centre", "lmpo_get_gate", "lmpo_apply_gate", "lmpo_last_spectrum", "lmpo_svd_stats",
     "lmpo_svd_profile", "lmpo_profile_begin", "lmpo_profile_end", "lmpo_set_workgroups", "lmpo_set_svd_tolerance",
@@ -97,6 +97,7 @@ def load_library(path: str = LIB_PATH):
         "lmpo_renormalize": (ctypes.c_int, [P]),
         "lmpo_measure_1q": (ctypes.c_int, [P, i32, pi32, ctypes.c_char_p, pdbl]),
         "lmpo_measure_2q": (ctypes.c_int, [P, i32, pi32, pi32, ctypes.c_char_p, pdbl]),
+        "lmpo_measure_2q_noalloc": (ctypes.c_int, [P, i32, pi32, pi32, ctypes.c_char_p, pdbl]),
         "lmpo_bond_dims": (ctypes.c_int, [P, pi32]),
         "lmpo_discarded_weight": (ctypes.c_int, [P, pdbl]),
         "lmpo_sync": (ctypes.c_int, [P]),
@@ -286,6 +287,18 @@ class Chain:
         p = "".join(paulis).encode()
         out = np.zeros((len(i), 2))
         _check(self._lib.lmpo_measure_2q(self._h, len(i), _iptr(i), _iptr(j), p, _dptr(out)))
+        return out[:, 0] + 1j * out[:, 1]
+
+    def measure_2q_noalloc(self, i, j, paulis):
+        """measure_2q through lmpo_measure_2q_noalloc (working memory in the
+        library's fixed device array instead of the arena)."""
+        i = np.ascontiguousarray(i, dtype=np.int32)
+        j = np.ascontiguousarray(j, dtype=np.int32)
+        if isinstance(paulis, str) and len(paulis) == 2:
+            paulis = [paulis] * len(i)
+        p = "".join(paulis).encode()
+        out = np.zeros((len(i), 2))
+        _check(self._lib.lmpo_measure_2q_noalloc(self._h, len(i), _iptr(i), _iptr(j), p, _dptr(out)))
         return out[:, 0] + 1j * out[:, 1]
 
     def zz_observables(self):
