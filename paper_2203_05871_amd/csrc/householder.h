@@ -316,4 +316,89 @@ __device__ __noinline__ void qr_apply_panel(SharedQR &s, int m, int nb, bool adj
   }
 }
 
+// Q Y for columns [0, ncol) of Y (R <= 64 kQyRows rows, column-major, ld R),
+// Q = H_1 ... H_nq from the factored panels (reflectors below the diagonal of
+// X at physical columns qmap[.], T of panel p at Tq + p * kQrNbMax^2).  The
+// workgroup takes four columns at a time (columns 4 rank + w, + 4 G, ...), one
+// per wavefront; lane l keeps rows l, l + 64, ... of its column in registers
+// through every panel (applied in reverse order, Y <- (I - V T V^H) Y), while
+// the workgroup stages each panel's reflectors and T in LDS once for its four
+// columns.  Each column's arithmetic is the same whatever the number of
+// workgroups.
+constexpr int kQyRows = 16;
+__device__ __noinline__ void qr_form_qy_waves(SharedQR &s, const double2 *__restrict__ X, int ldx,
+                                              const int *__restrict__ qmap, int R, int nq, int nbw,
+                                              const double2 *__restrict__ Tq, double2 *__restrict__ Y, int ncol,
+                                              int rank, int G) {
+  using namespace qr;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int npan = (nq + nbw - 1) / nbw;
+  for (int c0 = 4 * rank; c0 < ncol; c0 += 4 * G) {
+    const int c = c0 + wave;
+    const bool active = c < ncol;
+    double2 y[kQyRows];
+    double2 *yc = Y + (size_t)(active ? c : 0) * R;
+#pragma unroll
+    for (int r = 0; r < kQyRows; ++r) {
+      const int i = lane + 64 * r;
+      y[r] = (active && i < R) ? yc[i] : make_double2(0, 0);
+    }
+    for (int p = npan - 1; p >= 0; --p) {
+      const int j0 = p * nbw, nb = min(nbw, nq - j0), m = R - j0;
+      qr_load_panel(s, X, ldx, qmap, R, j0, nb, Tq + (size_t)p * kQrNbMax * kQrNbMax);
+      if (active) {
+        // w = V^H y over rows >= j0 (the staged panel holds the unit diagonal and zeros above it)
+        double2 w[kQrNbMax];
+#pragma unroll
+        for (int q = 0; q < kQrNbMax; ++q) w[q] = make_double2(0, 0);
+#pragma unroll
+        for (int r = 0; r < kQyRows; ++r) {
+          const int i = lane + 64 * r - j0;
+          if (i >= 0 && i < m) {
+#pragma unroll
+            for (int q = 0; q < kQrNbMax; ++q)
+              if (q < nb) cfmac(w[q], s.P[q * m + i], y[r]);
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < kQrNbMax; ++q) {
+          w[q].x = wave_sum(w[q].x);
+          w[q].y = wave_sum(w[q].y);
+        }
+        double2 u[kQrNbMax];
+#pragma unroll
+        for (int rr = 0; rr < kQrNbMax; ++rr) {
+          double2 a = make_double2(0, 0);
+#pragma unroll
+          for (int q = 0; q < kQrNbMax; ++q)
+            if (rr < nb && q < nb && q >= rr) cfma(a, s.T[rr][q], w[q]);
+          u[rr] = a;
+        }
+#pragma unroll
+        for (int r = 0; r < kQyRows; ++r) {
+          const int i = lane + 64 * r - j0;
+          if (i >= 0 && i < m) {
+#pragma unroll
+            for (int q = 0; q < kQrNbMax; ++q) {
+              if (q < nb) {
+                const double2 t = cmul(s.P[q * m + i], u[q]);
+                y[r].x -= t.x;
+                y[r].y -= t.y;
+              }
+            }
+          }
+        }
+      }
+    }
+    if (active) {
+#pragma unroll
+      for (int r = 0; r < kQyRows; ++r) {
+        const int i = lane + 64 * r;
+        if (i < R) yc[i] = y[r];
+      }
+    }
+  }
+  __syncthreads();
+}
+
 }  // namespace lmpo

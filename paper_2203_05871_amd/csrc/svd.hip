@@ -777,7 +777,10 @@ __device__ __forceinline__ void svd_body(const SvdLaunch &a, Barrier &bar, Share
   // are read and written per panel.
   auto apply_q = [&](int ncol) {
     constexpr int kTileCols = 8;
-    if (R * kQrNbMax <= kQrPanelElems / 2) {
+    if (R <= 64 * kQyRows) {
+      // up to 1024 rows: one wavefront per column, rows in registers
+      qr_form_qy_waves(sh.qr, a.X, ldx, a.qmap, R, nq, nbw, a.Tq, a.Lb, ncol, (int)rank, G);
+    } else if (R * kQrNbMax <= kQrPanelElems / 2) {
       double2 *tile = sh.qr.P + kQrPanelElems / 2;  // R x kTileCols, column-major
       const int ntask = (ncol + kTileCols - 1) / kTileCols;
       for (int task = rank; task < ntask; task += G) {
