@@ -128,13 +128,16 @@ int lmpo_create(const lmpo_model *model, const lmpo_options *opt, const char *in
  * on (i, i + 1), and SWAP gates carrying it back.  Each gate (SWAPs included)
  * moves the orthogonality centre onto its two sites (exact), applies the
  * 16 x 16 superoperator to the two-site block, truncates by SVD and restores
- * canonical form; then rho -> rho / tr(rho) if force_trace. */
+ * canonical form; then rho -> rho / tr(rho) if force_trace.  The step is the
+ * gate-by-gate (TEBD) form of the Trotter product of App. B; the truncation
+ * rule is the more severe of cut_off_rho and max_dim_rho (App. B, Sec. 6). */
 int lmpo_evolve_step(lmpo_state *s, int32_t n_steps);
 
 /* tr(rho) (Sec. 2.4) as (re, im); synchronises. */
 int lmpo_trace(lmpo_state *s, double out_re_im[2]);
 
-/* rho -> rho / tr(rho) (complex division); asynchronous. */
+/* rho -> rho / tr(rho) (complex division; the trace forcing of Sec. 6,
+ * b_force_rho_trace); asynchronous. */
 int lmpo_renormalize(lmpo_state *s);
 
 /* <sigma^a_i> = Tr(rho sigma^a_i) / Tr(rho) (Eq. mu) for n requests:
@@ -264,6 +267,30 @@ int lmpo_set_workgroups(lmpo_state *s, int32_t max_workgroups);
  * truncation is usually far coarser than the round-off. */
 int lmpo_set_svd_tolerance(lmpo_state *s, double factor);
 
+/* Truncated SVD of wide two-site blocks on a subspace (App. B, Sec. 6: only
+ * the kept singular triplets, at most max_dim_rho of them, and the discarded
+ * weight enter the step).  A gate block with at least min_cols columns is
+ * decomposed by subspace iteration: p = min(chi_max, chi + grow) + margin
+ * vectors (chi the bond's dimension before the gate, p rounded up to 16 and
+ * at most 3/4 of the columns), `iterations` multiplications by the block and
+ * its adjoint with Cholesky-QR orthonormalisation, then the exact SVD of the
+ * block restricted to the subspace (Rayleigh-Ritz, block Jacobi on a p x p
+ * factor).  The kept triplets are accepted when each residual
+ * ||theta^H u_j - s_j v_j|| is at most tol * s_1 and at least 16 vectors lie
+ * beyond the cut; else two more iterations are run, and if that still fails
+ * the full SVD of the block is taken instead.  The squared weight outside
+ * the subspace, ||theta||_F^2 - sum_j s_j^2, counts as discarded.  Defaults:
+ * min_cols 512, margin 64, grow 32, iterations 4, tol 2e-14; min_cols <= 0
+ * turns it off (every block then takes the full SVD).  margin must lie in
+ * [16, 128], iterations in [1, 64], tol in (0, 1). */
+int lmpo_set_svd_subspace(lmpo_state *s, int32_t min_cols, int32_t margin, int32_t grow, int32_t iterations,
+                          double tol);
+
+/* Counters of the subspace SVD since creation: out = (blocks accepted, blocks
+ * handed to the full SVD, subspace iterations of the accepted blocks);
+ * synchronises. */
+int lmpo_svd_subspace_stats(lmpo_state *s, int32_t out[3]);
+
 /* Jacobi statistics: out = (sweeps of the last SVD, its column count,
  * total sweeps so far, total SVDs so far, hops included); synchronises. */
 int lmpo_svd_stats(lmpo_state *s, int32_t out[4]);
@@ -272,10 +299,14 @@ int lmpo_svd_stats(lmpo_state *s, int32_t out[4]);
  * microseconds: [0] setup, [1] Jacobi pair work, [2] barrier wait, [5] norms +
  * select, [6] epilogue; inside the pair work [8] Gram, [9] eigen sweep, [10] X
  * update, [11] V update; [16] column order, [17] QR panels, [18] QR trailing
- * updates, [19] forming Q Y.  Counts: [3] shader clock cycles, [4] pair
- * tasks, [7] launches, [12] pair tasks that rotated.  out_us has 24 entries.
- * Synchronises. */
-int lmpo_svd_profile(lmpo_state *s, double out_us[24]);
+ * updates, [19] forming Q Y; subspace SVD: [20] set-up, [21] iterations,
+ * [22] final Cholesky QR, [24] vectors and residual check, [25] hops by
+ * Cholesky QR, and inside every Cholesky-QR pass [26] Gram matrix, [27]
+ * Cholesky factorisation (inside it [29] updates, [30] diagonal blocks, [31]
+ * rows below), [28] inverse factor and product.  Counts: [3] shader clock
+ * cycles, [4] pair tasks, [7] launches, [12] pair tasks that rotated, [23]
+ * Cholesky-QR passes.  out_us has 32 entries.  Synchronises. */
+int lmpo_svd_profile(lmpo_state *s, double out_us[32]);
 
 /* Profiling window for the persistent SVD kernel (one launch per truncated
  * SVD or centre hop).  Between begin and end, HIP events bracket every such

@@ -50,7 +50,13 @@ struct Arena {
 
 constexpr int kMaxReq = 4096;
 constexpr int kMaxSweeps = 80;
-constexpr int kStats = 8;  // [last sweeps, last C, last R, -, total sweeps, total SVDs, -, -]
+// [last sweeps, last C, last R, subspace SVDs accepted, total sweeps, total SVDs,
+//  subspace SVDs handed to the full SVD, subspace iterations]
+constexpr int kStats = 8;
+constexpr int kRsiMarginMax = 128;  // largest margin the subspace buffers allow
+constexpr double kFp32TolFactor = 1e5;  // Jacobi threshold of the FP32-contraction form, units of sqrt(C) eps
+constexpr size_t kGramSplitHost = 8;  // partial Gram matrices (rsi::kGramSplit)
+constexpr int kRsiMaxWidth = 384;   // largest subspace (the triangular solve keeps 16 x p in LDS)
 
 // Gate table slots: exp(x L_b) with x = fraction * tau.  Slots 0, 1 serve the
 // second-order step A(tau/2) B(tau) A(tau/2); slots 2..5 the fourth-order
@@ -191,6 +197,14 @@ struct lmpo_state {
   int grid = 1;                 // largest co-resident grid of the persistent SVD
   int wg_cap = 0;               // caller's cap on workgroups per SVD launch (0: none)
   double tol_factor = 32.0;     // Jacobi stopping threshold, in units of sqrt(C) eps
+  // subspace-iteration truncated SVD of wide gate blocks (see SvdLaunch)
+  int rsi_pmax = 0;             // allocated subspace width (0: not available)
+  int rsi_min_cols = 512, rsi_margin = 64, rsi_grow = 32, rsi_iters = 4;
+  double rsi_tol = 2e-14;
+  double2 *Vr = nullptr, *Zr = nullptr, *Wk = nullptr, *Gr = nullptr, *L1 = nullptr, *L2 = nullptr, *Li = nullptr, *Ldi = nullptr;
+  double2 *Rb = nullptr, *Res = nullptr;
+  double *rsi_scal = nullptr;
+  int *rsi_flag = nullptr;
   ~lmpo_state() {
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
   }
@@ -214,6 +228,7 @@ struct Sizes {
   std::vector<size_t> site_elems;
   size_t x_elems = 0, v_elems = 0, t_elems = 0, z_elems = 0;
   int max_cols = 1, max_dim = 1, cap_max = 1;
+  int rsi_pmax = 0;  // subspace width the buffers of the truncated SVD allow
 };
 
 bool is_chain(const lmpo_model *m) {
@@ -299,6 +314,14 @@ Sizes compute_sizes(int N, int chi_max, int mult) {
     consider(4 * (size_t)capR(b + 1), z.cap[b]);
     z.z_elems = std::max(z.z_elems, (size_t)z.cap[b] * z.cap[b]);
   }
+  // the subspace of a gate's truncated SVD holds at most chi_max + kRsiMarginMax
+  // vectors (and is only used when that is at most 3/4 of the block's columns)
+  {
+    int pm = (chi_max * mult + kRsiMarginMax + 15) & ~15;
+    pm = std::min(pm, kRsiMaxWidth);
+    if (4 * pm > 3 * z.max_cols) pm = (3 * z.max_cols / 4) & ~15;
+    z.rsi_pmax = pm >= 32 ? pm : 0;
+  }
   return z;
 }
 
@@ -330,6 +353,22 @@ size_t layout(lmpo_state *S, const Sizes &z, int N, int nb, char *base, size_t s
   S->qinv = a.take<int>(z.max_cols);
   S->Z = a.take<double2>(z.z_elems);
   S->T = a.take<double2>(z.t_elems);
+  S->rsi_pmax = z.rsi_pmax;
+  if (z.rsi_pmax > 0) {
+    const size_t pm = (size_t)z.rsi_pmax;
+    S->Vr = a.take<double2>((size_t)z.max_dim * pm);
+    S->Zr = a.take<double2>((size_t)z.max_dim * pm);
+    S->Wk = a.take<double2>((size_t)z.max_dim * pm);
+    S->Gr = a.take<double2>(kGramSplitHost * pm * pm);
+    S->L1 = a.take<double2>(pm * pm);
+    S->L2 = a.take<double2>(pm * pm);
+    S->Li = a.take<double2>(pm * pm);
+    S->Ldi = a.take<double2>((pm / 16 + 1) * 256);
+    S->Rb = a.take<double2>((size_t)z.max_cols * pm);
+    S->Res = a.take<double2>((size_t)z.max_cols * pm);
+    S->rsi_scal = a.take<double>(4);
+    S->rsi_flag = a.take<int>(4);
+  }
   S->sig = a.take<double>(z.max_cols);
   S->sorted = a.take<double>(z.max_cols);
   S->perm = a.take<int>(z.max_cols);
@@ -441,6 +480,24 @@ SvdLaunch svd_args(lmpo_state *S, int mode, int k, int asc) {
   L.bar = S->bar;
   L.tprof = S->tprof;
   L.alg_flops = S->alg_flops;
+  L.rsi_pmax = S->rsi_min_cols > 0 ? S->rsi_pmax : 0;
+  L.rsi_margin = S->rsi_margin;
+  L.rsi_grow = S->rsi_grow;
+  L.rsi_iters = S->rsi_iters;
+  L.rsi_min_cols = S->rsi_min_cols;
+  L.rsi_tol = S->rsi_tol;
+  L.Vr = S->Vr;
+  L.Zr = S->Zr;
+  L.Wk = S->Wk;
+  L.Gr = S->Gr;
+  L.L1 = S->L1;
+  L.L2 = S->L2;
+  L.Li = S->Li;
+  L.Ldi = S->Ldi;
+  L.Rb = S->Rb;
+  L.Res = S->Res;
+  L.rsi_scal = S->rsi_scal;
+  L.rsi_flag = S->rsi_flag;
   return L;
 }
 
@@ -765,6 +822,15 @@ int lmpo_create(const lmpo_model *model, const lmpo_options *opt, const char *in
   lmpo_state *S = new lmpo_state();
   S->m = copy_model(model);
   S->opt = *opt;
+  if (opt->precision == LMPO_FP32_CONTRACT) {
+    // the contraction hands the SVD a block rounded to FP32 (relative error
+    // about 6e-8); the FP64 SVD resolves it to about 1e-9, two orders below
+    // that, instead of to FP64 round-off: looser Jacobi and Ritz thresholds,
+    // fewer subspace iterations
+    S->tol_factor = kFp32TolFactor;
+    S->rsi_tol = 1e-9;
+    S->rsi_iters = 2;
+  }
   S->chain = is_chain(model);
   S->herm_room = opt->force_hermitian_every > 0;
   S->N = model->n_qubits;
@@ -1203,7 +1269,7 @@ int lmpo_last_spectrum(lmpo_state *S, int32_t n_out, double *sv, int32_t *n_sv, 
   return LMPO_OK;
 }
 
-int lmpo_svd_profile(lmpo_state *S, double out_us[24]) {
+int lmpo_svd_profile(lmpo_state *S, double out_us[32]) {
   if (!S || !out_us) return fail(LMPO_EINVAL, "null argument");
   unsigned long long t[32];
   HIP_TRY(hipMemcpyAsync(t, S->tprof, sizeof(t), hipMemcpyDeviceToHost, S->stream));
@@ -1212,11 +1278,12 @@ int lmpo_svd_profile(lmpo_state *S, double out_us[24]) {
   HIP_TRY(hipGetDevice(&dev));
   HIP_TRY(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
   auto us = [&](unsigned long long v) { return khz > 0 ? (double)v * 1e3 / khz : 0.0; };
-  for (int i = 0; i < 24; ++i) out_us[i] = us(t[i]);
+  for (int i = 0; i < 32; ++i) out_us[i] = us(t[i]);
   out_us[3] = (double)t[12];   // shader clock cycles of the first workgroup (whole kernels)
   out_us[4] = (double)t[13];   // pair tasks of the first workgroup
   out_us[7] = (double)t[7];    // launches
   out_us[12] = (double)t[14];  // of which rotated
+  out_us[23] = (double)t[23];  // Cholesky-QR passes
   out_us[13] = out_us[14] = out_us[15] = 0.0;
   return LMPO_OK;
 }
@@ -1289,6 +1356,36 @@ int lmpo_set_workgroups(lmpo_state *S, int32_t max_workgroups) {
   if (!S) return fail(LMPO_EINVAL, "state is null");
   if (max_workgroups < 0) return fail(LMPO_EINVAL, "max_workgroups must be >= 0");
   S->wg_cap = max_workgroups;
+  return LMPO_OK;
+}
+
+int lmpo_set_svd_subspace(lmpo_state *S, int32_t min_cols, int32_t margin, int32_t grow, int32_t iterations,
+                          double tol) {
+  if (!S) return fail(LMPO_EINVAL, "state is null");
+  if (min_cols > 0) {
+    if (margin < 16 || margin > kRsiMarginMax) return fail(LMPO_EINVAL, "margin must be in [16, 128]");
+    if (grow < 0) return fail(LMPO_EINVAL, "grow must be >= 0");
+    if (iterations < 1 || iterations > 64) return fail(LMPO_EINVAL, "iterations must be in [1, 64]");
+    if (!(tol > 0.0) || !(tol < 1.0)) return fail(LMPO_EINVAL, "tol must be in (0, 1)");
+  }
+  S->rsi_min_cols = min_cols > 0 ? min_cols : 0;
+  if (min_cols > 0) {
+    S->rsi_margin = margin;
+    S->rsi_grow = grow;
+    S->rsi_iters = iterations;
+    S->rsi_tol = tol;
+  }
+  return LMPO_OK;
+}
+
+int lmpo_svd_subspace_stats(lmpo_state *S, int32_t out[3]) {
+  if (!S || !out) return fail(LMPO_EINVAL, "null argument");
+  int st[kStats];
+  HIP_TRY(hipMemcpyAsync(st, S->stats, sizeof(st), hipMemcpyDeviceToHost, S->stream));
+  HIP_TRY(hipStreamSynchronize(S->stream));
+  out[0] = st[3];
+  out[1] = st[6];
+  out[2] = st[7];
   return LMPO_OK;
 }
 

@@ -77,6 +77,23 @@ struct SvdLaunch {
   unsigned *bar;
   unsigned long long *tprof;
   double *alg_flops;
+  // Subspace-iteration truncated SVD of wide gate blocks (mode 0): used when
+  // the block has at least rsi_min_cols columns and the subspace (the bond's
+  // present dimension plus rsi_grow, at most chi_max, plus rsi_margin; at most
+  // rsi_pmax) is at most 3/4 of them; rsi_pmax = 0 switches it off.
+  int rsi_pmax, rsi_margin, rsi_grow, rsi_iters, rsi_min_cols;
+  double rsi_tol;    // accepted Ritz residual, relative to the largest singular value
+  double2 *Vr;       // max(R) x pmax: basis of the right subspace
+  double2 *Zr;       // max(R) x pmax: its image, then the orthonormal left factor Q
+  double2 *Wk;       // max(R) x pmax: scratch (the three rotate)
+  double2 *Gr;       // kGramSplit partial pmax x pmax Gram matrices
+  double2 *L1, *L2;  // pmax x pmax Cholesky factors
+  double2 *Li;       // pmax x pmax inverse of a Cholesky factor
+  double2 *Ldi;      // inverses of its 16 x 16 diagonal blocks (pmax / 16 of them)
+  double2 *Rb;       // C x pmax: right singular vectors (kept columns)
+  double2 *Res;      // C x pmax: residual scratch
+  double *rsi_scal;  // [0] squared Frobenius norm of the block, [1] pending discarded fraction, [2] residual
+  int *rsi_flag;     // [0] Cholesky breakdown, [1] result rejected
 };
 int svd_grid_size();
 hipError_t launch_svd_persistent(hipStream_t s, const SvdLaunch &L, int grid);

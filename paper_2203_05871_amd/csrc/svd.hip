@@ -24,6 +24,7 @@
 #include "contract_tile.h"
 #include "householder.h"
 #include "lmpo_internal.h"
+#include "rsi.h"
 
 namespace lmpo {
 
@@ -49,6 +50,8 @@ __device__ __forceinline__ void zfma_cj(double2 &acc, double2 a, double2 b) {  /
 
 constexpr int NT = 256;  // threads per workgroup
 constexpr int kInnerSweeps = 1;
+constexpr int kHopCholMin = 64;  // smallest bond a centre hop moves by Cholesky QR
+constexpr int kRsiMaxIters = 40;  // subspace iterations before the full SVD takes over
 
 // Hierarchical grid barrier: 8 group counters (one per workgroup residue mod 8,
 // i.e. per XCD under the default round-robin dispatch) and a top counter; all
@@ -194,6 +197,8 @@ union SharedAll {
   SharedSelect sel;
   SharedGemm gemm;
   SharedQR qr;
+  rsi::SharedGemm rg;
+  rsi::SharedChol rc;
   double red[NT];
 };
 static_assert(NT == NT_QR, "the Householder helpers assume the SVD workgroup size");
@@ -209,7 +214,7 @@ __device__ __forceinline__ void stage_rows(SharedPair &s, const double2 *__restr
 #pragma unroll
     for (int k = 0; k < kRows; ++k) {
       const int i = threadIdx.x + k * NT;
-      buf[c][k] = (i < n && s.col[c] >= 0) ? M[(size_t)(r0 + i) + (size_t)s.col[c] * ld] : make_double2(0, 0);
+      buf[c][k] = (i < n && s.col[c] >= 0) ? rsi::gld(M, (size_t)(r0 + i) + (size_t)s.col[c] * ld) : make_double2(0, 0);
     }
 #pragma unroll
   for (int c = 0; c < JP; ++c)
@@ -260,7 +265,7 @@ __device__ __forceinline__ void rotate_staged(SharedPair &s, const double2 (*W)[
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int row = i0 + lk + 4 * r;
-        if (row < n) M[(size_t)(r0 + row) + (size_t)cj * ld] = make_double2(yr[r], yi[r]);
+        if (row < n) rsi::gst(M, (size_t)(r0 + row) + (size_t)cj * ld, make_double2(yr[r], yi[r]));
       }
     }
   }
@@ -412,7 +417,7 @@ __device__ __forceinline__ bool pair_work(SharedPair &s, double2 *__restrict__ X
     rotate_staged<kReal>(s, W, X, ldx, r0, kChunk);
   }
   // record W for the row-parallel update of V after the sweep
-  Wout[t] = W[t / JP][t % JP];
+  rsi::gst(Wout, t, W[t / JP][t % JP]);
   __syncthreads();
   mark(10);
   return true;
@@ -436,7 +441,7 @@ __device__ __forceinline__ void sweep_update_v(SharedPair &s, double2 *__restric
     __syncthreads();
     for (int e = threadIdx.x; e < h * C; e += NT) {
       const int i = e / C, c = e - i * C;
-      vs[e] = (i < nr) ? V[(size_t)(r0 + i) + (size_t)c * ldv] : make_double2(0, 0);
+      vs[e] = (i < nr) ? rsi::gld(V, (size_t)(r0 + i) + (size_t)c * ldv) : make_double2(0, 0);
     }
     __syncthreads();
     for (int round = 0; round < nbp - 1; ++round) {
@@ -452,7 +457,7 @@ __device__ __forceinline__ void sweep_update_v(SharedPair &s, double2 *__restric
           const int q = 4 * kk + lk;
           const int c = (q < JB) ? bi * JB + q : bj * JB + (q - JB);
           cq[kk] = c < C ? cmap[c] : -1;
-          w[kk] = W[q * JP + lr];
+          w[kk] = rsi::gld(W, q * JP + lr);
         }
         const int cj0 = (lr < JB) ? bi * JB + lr : bj * JB + (lr - JB);
         const int cj = cj0 < C ? cmap[cj0] : -1;
@@ -479,7 +484,7 @@ __device__ __forceinline__ void sweep_update_v(SharedPair &s, double2 *__restric
     }
     for (int e = threadIdx.x; e < nr * C; e += NT) {
       const int i = e / C, c = e - i * C;
-      V[(size_t)(r0 + i) + (size_t)c * ldv] = vs[e];
+      rsi::gst(V, (size_t)(r0 + i) + (size_t)c * ldv, vs[e]);
     }
   }
 }
@@ -523,9 +528,15 @@ __device__ void order_columns(SharedSelect &s, const double *__restrict__ nrm, i
 // multiplet at the truncation cut (block_select).
 constexpr double kTie = 1e-4;
 
+// Sort the C values sig (descending, ties by index) into sorted / perm and
+// choose the kept count (a5).  extra: squared weight of singular values not
+// listed (those beyond a subspace), added to every tail sum.  With
+// disc_pending set, the discarded fraction goes there and neither *disc nor
+// *dims_slot is touched (the caller commits them once the result is accepted).
 __device__ void block_select(SharedSelect &s, const double *__restrict__ sig, int C, int chi_max, double cutoff,
                              int hop, int *__restrict__ perm, double *__restrict__ sorted, int *__restrict__ kept,
-                             int *__restrict__ dims_slot, double *__restrict__ disc, int *__restrict__ err) {
+                             int *__restrict__ dims_slot, double *__restrict__ disc, int *__restrict__ err,
+                             double extra = 0.0, double *__restrict__ disc_pending = nullptr) {
   const int t = threadIdx.x;
   int n2 = 2;
   while (n2 < C) n2 <<= 1;
@@ -574,6 +585,10 @@ __device__ void block_select(SharedSelect &s, const double *__restrict__ sig, in
     for (int e = t; e < n2; e += NT, ++q) s.tail[e] += v[q];
     __syncthreads();
   }
+  if (extra != 0.0) {
+    for (int e = t; e <= n2; e += NT) s.tail[e] += extra;
+    __syncthreads();
+  }
   const double W = s.tail[0];
   for (int e = t; e < C; e += NT) {
     if (e >= 1 && s.tail[e] > cutoff * W) atomicAdd(&s.cnt_above, 1);
@@ -606,15 +621,420 @@ __device__ void block_select(SharedSelect &s, const double *__restrict__ sig, in
     if (k < 1) k = 1;
     if (s.bad || !(W > 0.0)) *err = 1;
     *kept = k;
-    *dims_slot = k;
-    if (!hop && W > 0.0) *disc += s.tail[k] / W;
+    if (disc_pending) {
+      *disc_pending = W > 0.0 ? s.tail[k] / W : 0.0;
+    } else {
+      *dims_slot = k;
+      if (!hop && W > 0.0) *disc += s.tail[k] / W;
+    }
   }
   __syncthreads();
 }
 
+// Phase timers of the first workgroup (thread 0 only; null when not profiling).
+struct Laps {
+  unsigned long long *tp;
+  unsigned long long tmark;
+  __device__ void lap(int slot) {
+    if (tp) {
+      const unsigned long long now = wall_clock64();
+      tp[slot] += now - tmark;
+      tmark = now;
+    }
+  }
+};
+
 }  // namespace
 
 
+
+// Column norms (root) or squared norms of the rows x C matrix M (ld), one
+// column per workgroup at a time, with a fixed-order reduction.
+__device__ void col_norms(SharedAll &sh, const double2 *M, int ld, int rows, int C, double *out, bool root, int rank,
+                          int G) {
+  for (int j = rank; j < C; j += G) {
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < rows; i += NT) {
+      double2 v = rsi::gld(M, (size_t)i + (size_t)j * ld);
+      acc = fma(v.x, v.x, fma(v.y, v.y, acc));
+    }
+    sh.red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int off = NT / 2; off > 0; off >>= 1) {
+      if (threadIdx.x < off) sh.red[threadIdx.x] += sh.red[threadIdx.x + off];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[j] = root ? sqrt(sh.red[0]) : sh.red[0];
+    __syncthreads();
+  }
+}
+
+// Block one-sided Jacobi on Y (C x C, ld C) until a sweep rotates no pair
+// (or the sweep limit).  On entry the caller's workgroups have written Y, the
+// identity into V (C x C, ld C) and zeros into sweep_cnt (the first grid
+// barrier inside orders those writes).  On return (behind a barrier) Y holds
+// Y W and V the accumulated W.  Returns the number of sweeps.
+template <bool kReal>
+__device__ __noinline__ int jacobi_run(const SvdLaunch &a, Barrier &bar, SharedAll &sh, Laps &laps, double2 *Y, int C) {
+  const unsigned rank = bar.rank;
+  const int G = (int)bar.G;
+  const int ldy = C, ldv = C;
+  int nbp = (C + JB - 1) / JB;
+  nbp += nbp & 1;
+  if (nbp < 2) nbp = 2;
+  const int npairs = nbp / 2;
+  // Workgroups [0, np) do the pair rounds, ordered block by block (see
+  // wait_blocks); the others (nv of them) apply the previous sweep's rotations
+  // to V meanwhile, so the V update leaves the critical path.  The block
+  // versions live in the second barrier block and are cleared here (every
+  // workgroup has left its previous use behind a full barrier).
+  const int np = G < npairs ? G : npairs, nv = G - np;
+  static_assert(kMaxDim / JB + 2 <= (int)kBarBlock, "block versions must fit the barrier block");
+  unsigned *ver = a.bar + kBarBlock;
+  if (rank == 0)
+    for (int b = threadIdx.x; b < nbp; b += NT) ver[b] = 0u;
+  bar.sync();
+  const double tol = a.tol_factor * sqrt((double)C) * 2.220446049250313e-16;
+  int sweeps = 0, pending = -1;  // pending: active sweep whose V update is outstanding
+  const size_t wsw_stride = (size_t)(nbp - 1) * npairs;  // pair slots per sweep
+  const size_t cmap_stride = (size_t)nbp * JB;
+  auto update_v = [&](int sw, int workers, int me) {
+    sweep_update_v<kReal>(sh.pair, a.V, ldv, C, nbp, a.W + (size_t)(sw & 1) * wsw_stride * JP * JP,
+                          a.act + (size_t)(sw & 1) * wsw_stride, workers, a.cmap + (sw & 1) * cmap_stride, me);
+  };
+  for (int sweep = 0; sweep < a.max_sweeps; ++sweep) {
+    double2 *Wsw = a.W + (size_t)(sweep & 1) * wsw_stride * JP * JP;
+    int *act = a.act + (size_t)(sweep & 1) * wsw_stride;
+    int *cmap = a.cmap + (sweep & 1) * cmap_stride;
+    // order the columns by decreasing norm for this sweep (blocks then hold
+    // columns of similar size, which speeds up convergence on graded spectra)
+    col_norms(sh, Y, ldy, C, C, a.cnorm, false, (int)rank, G);
+    bar.sync();
+    if (rank == 0) order_columns(sh.sel, a.cnorm, C, nbp * JB, cmap);
+    bar.sync();
+    if ((int)rank < np) {
+      const unsigned base = (unsigned)sweep * (unsigned)(nbp - 1);  // every block's version at the sweep's start
+      for (int round = 0; round < nbp - 1; ++round) {
+        for (int p = rank; p < npairs; p += np) {
+          int bi, bj;
+          pair_blocks(round, p, nbp, bi, bj);
+          if (np > 1) wait_blocks(ver + bi, ver + bj, base + round, a.err);
+          laps.lap(2);
+          const size_t slot = (size_t)round * npairs + p;
+          unsigned long long *tp = (a.tprof && rank == 0) ? a.tprof : nullptr;
+          const bool active = pair_work<kReal>(sh.pair, Y, ldy, C, Wsw + slot * JP * JP, C, bi, bj, tol, cmap, tp);
+          if (threadIdx.x == 0) {
+            act[slot] = active ? 1 : 0;
+            if (active) atomicAdd(&a.sweep_cnt[sweep], 1);
+          }
+          __syncthreads();
+          if (np > 1) publish_blocks(ver + bi, ver + bj, base + round + 1);
+          laps.lap(1);
+        }
+      }
+    } else if (pending >= 0) {
+      update_v(pending, nv, rank - np);
+    }
+    bar.sync();
+    sweeps = sweep + 1;
+    const bool converged =
+        __hip_atomic_load(&a.sweep_cnt[sweep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
+    if (nv == 0) {
+      if (converged) break;
+      update_v(sweep, G, rank);
+      laps.lap(11);
+    } else {
+      pending = converged ? -1 : sweep;
+      if (converged) break;
+    }
+  }
+  if (pending >= 0) update_v(pending, G, rank);  // the sweep limit was reached while rotating
+  bar.sync();
+  return sweeps;
+}
+
+// Width of the subspace for the truncated SVD of a gate block with C columns
+// whose bond held chm before the gate (0: run the full SVD).
+__device__ __forceinline__ int rsi_width(const SvdLaunch &a, int C, int chm) {
+  if (a.rsi_pmax <= 0 || C < a.rsi_min_cols) return 0;
+  int want = min(a.chi_max, chm + a.rsi_grow) + a.rsi_margin;
+  want = (want + 15) & ~15;
+  if (want > a.rsi_pmax) want = a.rsi_pmax;
+  if (4 * want > 3 * C) return 0;
+  return want;
+}
+
+// Mout <- M L^{-H} with L the Cholesky factor of M^H M (M, Mout: rows x p,
+// ld rows; Mout may not be M): one Cholesky QR pass.  The Gram matrix is
+// formed in kGramSplit partial sums by all workgroups, workgroup 0 factors
+// it, L^{-1} is formed by column blocks and the product with it is a GEMM.
+// near_identity > 0: the pass is a repeat, and its Gram matrix must lie
+// within that distance of the identity (max entry of the lower triangle),
+// which bounds the loss of orthogonality of the result to a few units of
+// round-off (Yamamoto, Nakatsukasa, Yanagisawa & Fukaya, ETNA 44 (2015) 306).
+// False (on every workgroup) when the factorisation broke down or the check
+// failed; a.rsi_flag[0] is then set.
+template <bool kReal>
+__device__ __noinline__ bool cholqr_pass(const SvdLaunch &a, Barrier &bar, SharedAll &sh, const double2 *M,
+                                         double2 *Mout, int rows, int p, double2 *L, int rank, int G,
+                                         double near_identity = 0.0) {
+  // phase timers of the first workgroup: [26] Gram, [27] Cholesky, [28] L^{-1} and the product
+  Laps laps{a.tprof && rank == 0 && threadIdx.x == 0 ? a.tprof : nullptr, (unsigned long long)wall_clock64()};
+  const size_t gstride = (size_t)p * p;
+  rsi::gemm<kReal>(sh.rg, p, p, rows, M, rows, 1, M, rows, 0, nullptr, nullptr, a.Gr, p, true, rank, G,
+                   rsi::kGramSplit, gstride);
+  bar.sync();
+  laps.lap(26);
+  if (laps.tp && rank == 0) laps.tp[23] += 1;  // Cholesky-QR passes
+  if (rank == 0) {
+    bool ok = true;
+    if (near_identity > 0.0) {
+      double dev = 0.0;
+      for (int e = threadIdx.x; e < p * p; e += NT) {
+        const int i = e % p, j = e / p;
+        if (i >= j) {
+          double2 g = a.Gr[e];
+          for (int sp = 1; sp < rsi::kGramSplit; ++sp) {
+            g.x += a.Gr[e + sp * gstride].x;
+            g.y += a.Gr[e + sp * gstride].y;
+          }
+          dev = fmax(dev, fabs(g.x - (i == j ? 1.0 : 0.0)) + fabs(g.y));
+        }
+      }
+      sh.red[threadIdx.x] = dev;
+      __syncthreads();
+      for (int off = NT / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh.red[threadIdx.x] = fmax(sh.red[threadIdx.x], sh.red[threadIdx.x + off]);
+        __syncthreads();
+      }
+      ok = sh.red[0] <= near_identity;
+      __syncthreads();
+    }
+    if (ok) ok = rsi::cholesky<kReal>(sh.rc, p, a.Gr, rsi::kGramSplit, gstride, L, a.Ldi, laps.tp);
+    if (threadIdx.x == 0 && !ok) a.rsi_flag[0] = 1;
+  }
+  bar.sync();
+  laps.lap(27);
+  if (__hip_atomic_load(&a.rsi_flag[0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+  rsi::tri_inverse<kReal>(sh.rc, p, L, a.Ldi, a.Li, rank, G);
+  bar.sync();
+  // Mout = M (L^{-1})^H
+  rsi::gemm<kReal>(sh.rg, rows, p, p, M, rows, 0, a.Li, p, 1, nullptr, nullptr, Mout, rows, false, rank, G);
+  bar.sync();
+  laps.lap(28);
+  return true;
+}
+
+// The subspace result is not used: count it and let the full SVD run.
+__device__ __forceinline__ bool rsi_reject(const SvdLaunch &a, int rank) {
+  if (rank == 0 && threadIdx.x == 0 && a.stats) a.stats[6] += 1;
+  return false;
+}
+
+// Truncated SVD of the gate block X (R x C, R >= C) by subspace iteration
+// with Rayleigh-Ritz (Halko, Martinsson & Tropp, SIAM Rev. 53 (2011) 217,
+// Alg. 4.4 with Cholesky-QR orthonormalisation): from a random C x p start,
+// alternate Z = orth(X V), V = orth(X^H Z); then X V = Q T (Cholesky QR
+// twice), one-sided Jacobi on T^H gives T = W S U^H, and X ~ (Q W) S (V U)^H
+// on the subspace.  The kept Ritz triplets are accepted when every residual
+// ||X^H u_j - s_j v_j|| is below rsi_tol s_1 (else two more iterations, then
+// the full SVD takes over: X is never modified here).  Squared weight outside
+// the subspace, ||X||^2 - sum_j s_j^2, joins the tail sums of the truncation
+// rule.  Returns true when the gate is complete (canonical update written).
+template <bool kReal>
+__device__ __noinline__ bool rsi_gate(const SvdLaunch &a, Barrier &bar, SharedAll &sh, Laps &laps, int R, int C, int trans,
+                         int chl, int chr, int p) {
+  const int rank = (int)bar.rank, G = (int)bar.G;
+  const size_t gtid = (size_t)rank * NT + threadIdx.x, gstride = (size_t)G * NT;
+  const double2 *X = a.X;
+  const int ldx = R;
+  // the basis, its image and a scratch matrix rotate through three buffers
+  double2 *Vc = a.Vr, *Zc = a.Zr, *Wk = a.Wk;
+  auto swap2 = [](double2 *&x, double2 *&y) {
+    double2 *t = x;
+    x = y;
+    y = t;
+  };
+  // squared column norms of X (for its Frobenius norm), random start, flags
+  col_norms(sh, X, ldx, R, C, a.cnorm, false, rank, G);
+  for (size_t e = gtid; e < (size_t)C * p; e += gstride)
+    Vc[e] = make_double2(rsi::hash_uniform((unsigned)(e % C), (unsigned)(e / C), 0u), 0.0);
+  if (gtid < 4) a.rsi_flag[gtid] = 0;
+  bar.sync();
+  if (rank == 0) {
+    // fixed-order sum of the column norms
+    double w = 0.0;
+    for (int j = threadIdx.x; j < C; j += NT) w += a.cnorm[j];
+    sh.red[threadIdx.x] = w;
+    __syncthreads();
+    for (int off = NT / 2; off > 0; off >>= 1) {
+      if (threadIdx.x < off) sh.red[threadIdx.x] += sh.red[threadIdx.x + off];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) a.rsi_scal[0] = sh.red[0];
+  }
+  laps.lap(20);
+  int iters = a.rsi_iters, done = 0;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    for (; done < iters; ++done) {
+      rsi::gemm<kReal>(sh.rg, R, p, C, X, ldx, 0, Vc, C, 0, nullptr, nullptr, Zc, R, false, rank, G);
+      bar.sync();
+      if (!cholqr_pass<kReal>(a, bar, sh, Zc, Wk, R, p, a.L1, rank, G)) return rsi_reject(a, rank);
+      swap2(Zc, Wk);
+      rsi::gemm<kReal>(sh.rg, C, p, R, X, ldx, 1, Zc, R, 0, nullptr, nullptr, Vc, C, false, rank, G);
+      bar.sync();
+      if (!cholqr_pass<kReal>(a, bar, sh, Vc, Wk, C, p, a.L1, rank, G)) return rsi_reject(a, rank);
+      swap2(Vc, Wk);
+    }
+    laps.lap(21);
+    // V orthonormal to working accuracy, then X V = Q T with T^H = L1 L2
+    if (!cholqr_pass<kReal>(a, bar, sh, Vc, Wk, C, p, a.L1, rank, G, 0.5)) return rsi_reject(a, rank);
+    swap2(Vc, Wk);
+    rsi::gemm<kReal>(sh.rg, R, p, C, X, ldx, 0, Vc, C, 0, nullptr, nullptr, Zc, R, false, rank, G);
+    bar.sync();
+    if (!cholqr_pass<kReal>(a, bar, sh, Zc, Wk, R, p, a.L1, rank, G)) return rsi_reject(a, rank);
+    if (!cholqr_pass<kReal>(a, bar, sh, Wk, Zc, R, p, a.L2, rank, G, 0.5)) return rsi_reject(a, rank);
+    laps.lap(22);
+    // Jacobi on Y = T^H = L1 L2 (p x p), V = I
+    rsi::gemm<kReal>(sh.rg, p, p, p, a.L1, p, 0, a.L2, p, 0, nullptr, nullptr, a.Y, p, false, rank, G);
+    for (size_t e = gtid; e < (size_t)p * p; e += gstride)
+      a.V[e] = make_double2((e % p) == (e / p) ? 1.0 : 0.0, 0.0);
+    if (gtid < (size_t)a.max_sweeps) a.sweep_cnt[gtid] = 0;
+    const int sweeps = jacobi_run<kReal>(a, bar, sh, laps, a.Y, p);
+    laps.lap(23);
+    col_norms(sh, a.Y, p, p, p, a.sig, true, rank, G);
+    bar.sync();
+    if (rank == 0) {
+      // weight outside the subspace joins every tail sum
+      double w = 0.0;
+      for (int j = threadIdx.x; j < p; j += NT) w += a.sig[j] * a.sig[j];
+      sh.red[threadIdx.x] = w;
+      __syncthreads();
+      for (int off = NT / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh.red[threadIdx.x] += sh.red[threadIdx.x + off];
+        __syncthreads();
+      }
+      const double extra = fmax(0.0, a.rsi_scal[0] - sh.red[0]);
+      __syncthreads();
+      if (threadIdx.x == 0 && a.stats) {
+        a.stats[0] = sweeps;
+        a.stats[1] = p;
+        a.stats[2] = R;
+      }
+      block_select(sh.sel, a.sig, p, a.chi_max, a.cutoff, 0, a.perm, a.sorted, a.kept, nullptr, a.disc,
+                   a.rsi_flag + 1, extra, a.rsi_scal + 1);
+    }
+    bar.sync();
+    const int k = __hip_atomic_load(a.kept, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // left vectors Q W(:, perm), right vectors V Y(:, perm) / s
+    rsi::gemm<kReal>(sh.rg, R, k, p, Zc, R, 0, a.V, p, 0, a.perm, nullptr, a.Lb, R, false, rank, G);
+    rsi::gemm<kReal>(sh.rg, C, k, p, Vc, C, 0, a.Y, p, 0, a.perm, nullptr, a.Rb, C, false, rank, G);
+    bar.sync();
+    for (size_t e = gtid; e < (size_t)C * k; e += gstride) {
+      const double inv = 1.0 / a.sorted[e / C];
+      a.Rb[e] = make_double2(a.Rb[e].x * inv, a.Rb[e].y * inv);
+    }
+    bar.sync();
+    // residuals X^H u_j - s_j v_j of the kept triplets
+    rsi::gemm<kReal>(sh.rg, C, k, R, X, ldx, 1, a.Lb, R, 0, nullptr, nullptr, a.Res, C, false, rank, G);
+    bar.sync();
+    for (int j = rank; j < k; j += G) {
+      const double sg = a.sorted[j];
+      double acc = 0.0;
+      for (int i = threadIdx.x; i < C; i += NT) {
+        const double2 r = a.Res[(size_t)i + (size_t)j * C], v = a.Rb[(size_t)i + (size_t)j * C];
+        const double dx = r.x - sg * v.x, dy = r.y - sg * v.y;
+        acc = fma(dx, dx, fma(dy, dy, acc));
+      }
+      sh.red[threadIdx.x] = acc;
+      __syncthreads();
+      for (int off = NT / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh.red[threadIdx.x] += sh.red[threadIdx.x + off];
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) a.cnorm[j] = sqrt(sh.red[0]);
+      __syncthreads();
+    }
+    bar.sync();
+    if (rank == 0) {
+      double r = 0.0;
+      for (int j = threadIdx.x; j < k; j += NT) r = fmax(r, a.cnorm[j]);
+      sh.red[threadIdx.x] = r;
+      __syncthreads();
+      for (int off = NT / 2; off > 0; off >>= 1) {
+        if (threadIdx.x < off) sh.red[threadIdx.x] = fmax(sh.red[threadIdx.x], sh.red[threadIdx.x + off]);
+        __syncthreads();
+      }
+      if (threadIdx.x == 0) {
+        const double res = sh.red[0], bound = a.rsi_tol * a.sorted[0];
+        a.rsi_scal[2] = res;
+        // decision of this attempt (every workgroup reads its own slot, so no
+        // slot is ever reset while another workgroup may still read it):
+        // 0 accepted (small residuals, room in the subspace beyond the cut);
+        // n > 0: run n more iterations (the residual has been falling by the
+        // factor f = res^(1/done) per iteration from about 1 at the random
+        // start: n iterations reach the bound); -1: hand over to the full SVD
+        int verdict;
+        if (a.rsi_flag[1] == 0 && res <= bound && k + 16 <= p) {
+          verdict = 0;
+        } else if (attempt == 0 && a.rsi_flag[1] == 0 && k + 16 <= p && res > 0.0 && bound > 0.0) {
+          const double f = fmin(0.95, fmax(1e-6, pow(res / a.sorted[0], 1.0 / done)));
+          const int more = (int)ceil(log(bound / res) / log(f)) + 1;
+          verdict = (more >= 1 && done + more <= kRsiMaxIters) ? more : -1;
+        } else {
+          verdict = -1;
+        }
+        a.rsi_flag[2 + attempt] = verdict;
+      }
+    }
+    bar.sync();
+    laps.lap(24);
+    const int verdict = __hip_atomic_load(&a.rsi_flag[2 + attempt], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (verdict == 0) {
+      // ---- accepted: commit the bond dimension and discarded weight, canonical update ----
+      if (rank == 0 && threadIdx.x == 0) {
+        a.dims[a.k] = k;
+        *a.disc += a.rsi_scal[1];
+        if (a.stats) {
+          a.stats[3] += 1;
+          a.stats[4] += sweeps;
+          a.stats[5] += 1;
+          a.stats[7] += done;
+        }
+        if (a.alg_flops) {
+          const double rr = R, cc = C;
+          *a.alg_flops += (a.real ? 1.0 : 4.0) * (14.0 * rr * cc * cc + 8.0 * cc * cc * cc);
+        }
+      }
+      double2 *Ak = a.sites[a.k], *Ak1 = a.sites[a.k + 1];
+      const size_t na = (size_t)4 * chl * k, nb2 = (size_t)k * 4 * chr;
+      const size_t n = na > nb2 ? na : nb2;
+      for (size_t e = gtid; e < n; e += gstride) {
+        if (e < na) {
+          const int i = e / k, al = e % k;
+          const double sg = a.sorted[al];
+          double2 u = trans == 0 ? a.Lb[(size_t)i + (size_t)al * R] : a.Rb[(size_t)i + (size_t)al * C];
+          if (!a.asc) u = make_double2(u.x * sg, u.y * sg);
+          Ak[e] = u;
+        }
+        if (e < nb2) {
+          const int al = e / (4 * chr), j = e % (4 * chr);
+          const double sg = a.sorted[al];
+          double2 v = trans == 0 ? a.Rb[(size_t)j + (size_t)al * C] : a.Lb[(size_t)j + (size_t)al * R];
+          if (a.asc) v = make_double2(v.x * sg, v.y * sg);
+          Ak1[e] = zconj(v);
+        }
+      }
+      laps.lap(6);
+      return true;
+    }
+    // rejected: more iterations from the present subspace, or give up
+    if (verdict < 0) break;
+    iters += verdict;
+  }
+  if (rank == 0 && threadIdx.x == 0 && a.stats) a.stats[6] += 1;
+  return false;
+}
 
 // The whole truncated SVD / centre hop, run by G cooperating workgroups
 // (group-local barriers only, so independent problems can share one launch).
@@ -633,16 +1053,10 @@ __device__ __forceinline__ void svd_body(const SvdLaunch &a, Barrier &bar, Share
   const unsigned rank = bar.rank, G_ = bar.G;
   // phase timers (workgroup 0, thread 0): 0 setup + QR, 1 pair Gram+eig, 2 wait
   // after a round, 5 norms+select, 6 epilogue, 7 launches, 11 V update
-  unsigned long long tmark = wall_clock64();
   const unsigned long long cyc0 = clock64();
-  const bool prof = a.tprof && rank == 0 && threadIdx.x == 0;
-  auto lap = [&](int slot) {
-    if (prof) {
-      unsigned long long now = wall_clock64();
-      a.tprof[slot] += now - tmark;
-      tmark = now;
-    }
-  };
+  Laps laps{a.tprof && rank == 0 && threadIdx.x == 0 ? a.tprof : nullptr, (unsigned long long)wall_clock64()};
+  const bool prof = laps.tp != nullptr;
+  auto lap = [&](int slot) { laps.lap(slot); };
   if (prof) a.tprof[7] += 1;
   const int G = (int)G_;
   const size_t gtid = (size_t)rank * NT + threadIdx.x, gstride = (size_t)G * NT;
@@ -653,6 +1067,7 @@ __device__ __forceinline__ void svd_body(const SvdLaunch &a, Barrier &bar, Share
   int R, C, trans = 0, chl = 1, chm = 1, chr = 1, site = a.k;
   if (a.mode == 0) {
     chl = dimL(a.k);
+    chm = ld_dim(a.dims + a.k);  // the bond's dimension before the gate
     chr = dimR(a.k + 1);
     const int r = 4 * chl, c = 4 * chr;
     trans = r >= c ? 0 : 1;
@@ -680,35 +1095,39 @@ __device__ __forceinline__ void svd_body(const SvdLaunch &a, Barrier &bar, Share
     C = chm;
   }
   const int ldx = R;
-  auto colnorms = [&](const double2 *M, int ld, int rows, double *out, bool root) {
-    for (int j = rank; j < C; j += G) {
-      double acc = 0.0;
-      for (int i = threadIdx.x; i < rows; i += NT) {
-        double2 v = M[(size_t)i + (size_t)j * ld];
-        acc = fma(v.x, v.x, fma(v.y, v.y, acc));
+  // ---- hop: load X from the site tensor; gate: order the columns ----
+  auto load_hop = [&]() {
+    const double2 *A = a.sites[site];
+    if (a.mode == 1) {
+      for (size_t e = gtid; e < (size_t)R * C; e += gstride) {
+        int i = e / C, j = e % C;
+        a.X[(size_t)i + (size_t)j * ldx] = A[e];
       }
-      sh.red[threadIdx.x] = acc;
-      __syncthreads();
-      for (int off = NT / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) sh.red[threadIdx.x] += sh.red[threadIdx.x + off];
-        __syncthreads();
+    } else {  // A: chm x (4 chr)
+      for (size_t e = gtid; e < (size_t)R * C; e += gstride) {
+        int i = e / R, j = e % R;  // A[i][j], i < chm, j < 4 chr
+        a.X[(size_t)j + (size_t)i * ldx] = zconj(A[e]);
       }
-      if (threadIdx.x == 0) out[j] = root ? sqrt(sh.red[0]) : sh.red[0];
-      __syncthreads();
     }
   };
-  // ---- hop: load X from the site tensor; gate: order the columns ----
-  if (a.mode == 1) {
-    const double2 *A = a.sites[site];
-    for (size_t e = gtid; e < (size_t)R * C; e += gstride) {
-      int i = e / C, j = e % C;
-      a.X[(size_t)i + (size_t)j * ldx] = A[e];
-    }
-  } else if (a.mode == 2) {
-    const double2 *A = a.sites[site];  // chm x (4 chr)
-    for (size_t e = gtid; e < (size_t)R * C; e += gstride) {
-      int i = e / R, j = e % R;  // A[i][j], i < chm, j < 4 chr
-      a.X[(size_t)j + (size_t)i * ldx] = zconj(A[e]);
+  // hops by Cholesky QR (twice) where it applies; false: Householder QR below
+  bool hop_chol = false;
+  if (a.mode == 1 || a.mode == 2) {
+    load_hop();
+    if (a.rsi_pmax > 0 && a.rsi_min_cols > 0 && C >= kHopCholMin && C <= a.rsi_pmax && R >= C) {
+      if (rank == 0 && threadIdx.x == 0) a.rsi_flag[0] = 0;
+      bar.sync();  // X, written by every workgroup, is read by every workgroup below
+      hop_chol = cholqr_pass<kReal>(a, bar, sh, a.X, a.Wk, R, C, a.L1, (int)rank, G) &&
+                 cholqr_pass<kReal>(a, bar, sh, a.Wk, a.X, R, C, a.L2, (int)rank, G, 0.5);
+      if (hop_chol) {
+        // X = Q (L1 L2)^H: Y = L1 L2 (its adjoint is the R factor), Lb = Q
+        rsi::gemm<kReal>(sh.rg, C, C, C, a.L1, C, 0, a.L2, C, 0, nullptr, nullptr, a.Y, C, false, (int)rank, G);
+        for (size_t e = gtid; e < (size_t)R * C; e += gstride) a.Lb[e] = a.X[e];
+      } else {
+        load_hop();
+      }
+      bar.sync();
+      lap(25);
     }
   } else if (a.mode == 3) {
     const double2 *A = a.sites[site];  // (4 chl) x chr, row-major
@@ -720,14 +1139,23 @@ __device__ __forceinline__ void svd_body(const SvdLaunch &a, Barrier &bar, Share
         a.X[(size_t)j + (size_t)i * ldx] = zconj(A[e]);
     }
   }
+  if (a.mode == 0) {
+    // wide blocks: the truncated SVD on a subspace (falls back to the full
+    // SVD below when its result is not accepted)
+    const int p = rsi_width(a, C, chm);
+    if (p > 0 && rsi_gate<kReal>(a, bar, sh, laps, R, C, trans, chl, chr, p)) {
+      if (prof) a.tprof[12] += clock64() - cyc0;
+      return;
+    }
+  }
   if (a.mode == 0 || a.mode == 3) {
-    colnorms(a.X, ldx, R, a.cnorm, false);
+    col_norms(sh, a.X, ldx, R, C, a.cnorm, false, (int)rank, G);
     bar.sync();
     if (rank == 0) order_columns(sh.sel, a.cnorm, C, C, a.qmap);
-  } else {
+  } else if (!hop_chol) {
     for (size_t e = gtid; e < (size_t)C; e += gstride) a.qmap[e] = (int)e;
   }
-  bar.sync();
+  if (!hop_chol) bar.sync();
   lap(16);
   // ---- blocked Householder QR of X P, with look-ahead: workgroup 0 applies
   // panel p to the first 16-column task (which holds panel p + 1) and factors
@@ -735,13 +1163,13 @@ __device__ __forceinline__ void svd_body(const SvdLaunch &a, Barrier &bar, Share
   // one barrier per panel ----
   const int nq = R < C ? R : C, nbw = qr_panel_width(R);
   auto Tpan = [&](int p) { return a.Tq + (size_t)p * kQrNbMax * kQrNbMax; };
-  if (nq > 0) {
+  if (nq > 0 && !hop_chol) {
     if (rank == 0) qr_panel(sh.qr, a.X, ldx, a.qmap, R, 0, min(nbw, nq), Tpan(0));
     lap(17);
     bar.sync();
     lap(2);
   }
-  for (int j0 = 0, p = 0; j0 < nq; j0 += nbw, ++p) {
+  for (int j0 = 0, p = 0; j0 < nq && !hop_chol; j0 += nbw, ++p) {
     const int nb = min(nbw, nq - j0);
     const int c0 = j0 + nb, ntail = C - c0, ntask = (ntail + 15) / 16;
     if (ntail <= 0) break;
@@ -817,12 +1245,14 @@ __device__ __forceinline__ void svd_body(const SvdLaunch &a, Barrier &bar, Share
   if (a.mode == 1 || a.mode == 2) {
     // ---- hop: explicit thin Q, then A_c <- Q (or Q^H), neighbour <- R A (or A R^H) ----
     const int k = nq;
-    for (size_t e = gtid; e < (size_t)R * k; e += gstride) {
-      const int i = e % R, jj = e / R;
-      a.Lb[e] = make_double2(i == jj ? 1.0 : 0.0, 0.0);
+    if (!hop_chol) {
+      for (size_t e = gtid; e < (size_t)R * k; e += gstride) {
+        const int i = e % R, jj = e / R;
+        a.Lb[e] = make_double2(i == jj ? 1.0 : 0.0, 0.0);
+      }
+      bar.sync();
+      apply_q(k);
     }
-    bar.sync();
-    apply_q(k);
     int *dslot = (a.mode == 2) ? a.dims + (site - 1) : a.dims + site;
     if (rank == 0 && threadIdx.x == 0) {
       if (a.alg_flops) {
@@ -868,7 +1298,10 @@ __device__ __forceinline__ void svd_body(const SvdLaunch &a, Barrier &bar, Share
             m = e / k;
             al = e % k;
           }
-          const double2 r = m >= al ? a.X[(size_t)al + (size_t)m * ldx] : make_double2(0, 0);  // R[al][m]
+          // R[al][m]: Householder R in the upper triangle of X, or conj(Y[m][al])
+          const double2 r = m < al ? make_double2(0, 0)
+                            : hop_chol ? zconj(a.Y[(size_t)m + (size_t)al * C])
+                                       : a.X[(size_t)al + (size_t)m * ldx];
           a.Z[e] = right ? r : zconj(r);
         }
       }
@@ -937,81 +1370,10 @@ __device__ __forceinline__ void svd_body(const SvdLaunch &a, Barrier &bar, Share
     a.V[e] = make_double2(i == j ? 1.0 : 0.0, 0.0);
   }
   if (gtid < (size_t)a.max_sweeps) a.sweep_cnt[gtid] = 0;
-  // ---- block Jacobi sweeps on Y ----
-  int nbp = (C + JB - 1) / JB;
-  nbp += nbp & 1;
-  if (nbp < 2) nbp = 2;
-  const int npairs = nbp / 2;
-  // Workgroups [0, np) do the pair rounds, ordered block by block (see
-  // wait_blocks); the others (nv of them) apply the previous sweep's rotations
-  // to V meanwhile, so the V update leaves the critical path.  The block
-  // versions live in the second barrier block and are cleared here (every
-  // workgroup has left its previous use behind a full barrier).
-  const int np = G < npairs ? G : npairs, nv = G - np;
-  static_assert(kMaxDim / JB + 2 <= (int)kBarBlock, "block versions must fit the barrier block");
-  unsigned *ver = a.bar + kBarBlock;
-  if (rank == 0)
-    for (int b = threadIdx.x; b < nbp; b += NT) ver[b] = 0u;
-  bar.sync();
-  const double tol = a.tol_factor * sqrt((double)C) * 2.220446049250313e-16;
-  int sweeps = 0, pending = -1;  // pending: active sweep whose V update is outstanding
-  const size_t wsw_stride = (size_t)(nbp - 1) * npairs;  // pair slots per sweep
-  const size_t cmap_stride = (size_t)nbp * JB;
-  auto update_v = [&](int sw, int workers, int me) {
-    sweep_update_v<kReal>(sh.pair, a.V, ldv, C, nbp, a.W + (size_t)(sw & 1) * wsw_stride * JP * JP,
-                          a.act + (size_t)(sw & 1) * wsw_stride, workers, a.cmap + (sw & 1) * cmap_stride, me);
-  };
-  for (int sweep = 0; sweep < a.max_sweeps; ++sweep) {
-    double2 *Wsw = a.W + (size_t)(sweep & 1) * wsw_stride * JP * JP;
-    int *act = a.act + (size_t)(sweep & 1) * wsw_stride;
-    int *cmap = a.cmap + (sweep & 1) * cmap_stride;
-    // order the columns by decreasing norm for this sweep (blocks then hold
-    // columns of similar size, which speeds up convergence on graded spectra)
-    colnorms(Y, ldy, C, a.cnorm, false);
-    bar.sync();
-    if (rank == 0) order_columns(sh.sel, a.cnorm, C, nbp * JB, cmap);
-    bar.sync();
-    if ((int)rank < np) {
-      const unsigned base = (unsigned)sweep * (unsigned)(nbp - 1);  // every block's version at the sweep's start
-      for (int round = 0; round < nbp - 1; ++round) {
-        for (int p = rank; p < npairs; p += np) {
-          int bi, bj;
-          pair_blocks(round, p, nbp, bi, bj);
-          if (np > 1) wait_blocks(ver + bi, ver + bj, base + round, a.err);
-          lap(2);
-          const size_t slot = (size_t)round * npairs + p;
-          unsigned long long *tp = (a.tprof && rank == 0) ? a.tprof : nullptr;
-          const bool active = pair_work<kReal>(sh.pair, Y, ldy, C, Wsw + slot * JP * JP, C, bi, bj, tol, cmap, tp);
-          if (threadIdx.x == 0) {
-            act[slot] = active ? 1 : 0;
-            if (active) atomicAdd(&a.sweep_cnt[sweep], 1);
-          }
-          __syncthreads();
-          if (np > 1) publish_blocks(ver + bi, ver + bj, base + round + 1);
-          lap(1);
-        }
-      }
-    } else if (pending >= 0) {
-      update_v(pending, nv, rank - np);
-    }
-    bar.sync();
-    sweeps = sweep + 1;
-    const bool converged =
-        __hip_atomic_load(&a.sweep_cnt[sweep], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0;
-    if (nv == 0) {
-      if (converged) break;
-      update_v(sweep, G, rank);
-      lap(11);
-    } else {
-      pending = converged ? -1 : sweep;
-      if (converged) break;
-    }
-  }
-  if (pending >= 0) update_v(pending, G, rank);  // the sweep limit was reached while rotating
-  bar.sync();
+  const int sweeps = jacobi_run<kReal>(a, bar, sh, laps, Y, C);
   if (a.mode == 3) {
     // ---- spectrum only: OSEE = -sum p ln p, p = sigma^2 / sum sigma^2 (no state change) ----
-    colnorms(Y, ldy, C, a.sig, false);
+    col_norms(sh, Y, ldy, C, C, a.sig, false, (int)rank, G);
     bar.sync();
     if (rank == 0) {
       double w = 0.0;
@@ -1046,7 +1408,7 @@ __device__ __forceinline__ void svd_body(const SvdLaunch &a, Barrier &bar, Share
     return;
   }
   // ---- singular values, truncation select; inverse of the QR column order ----
-  colnorms(Y, ldy, C, a.sig, true);
+  col_norms(sh, Y, ldy, C, C, a.sig, true, (int)rank, G);
   for (size_t e = gtid; e < (size_t)C; e += gstride) a.qinv[a.qmap[e]] = (int)e;
   bar.sync();
   int *dslot = a.dims + site;

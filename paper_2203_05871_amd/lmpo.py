@@ -64,6 +64,7 @@ EXPORTS = [
     "lmpo_destroy", "lmpo_last_error", "lmpo_get_site", "lmpo_set_site", "lmpo_set_centre",
     "lmpo_get_centre", "lmpo_get_gate", "lmpo_apply_gate", "lmpo_last_spectrum", "lmpo_svd_stats",
     "lmpo_svd_profile", "lmpo_profile_begin", "lmpo_profile_end", "lmpo_set_workgroups", "lmpo_set_svd_tolerance",
+    "lmpo_set_svd_subspace", "lmpo_svd_subspace_stats",
     "lmpo_renyi2", "lmpo_osee", "lmpo_apply_superop", "lmpo_apply_unitary", "lmpo_init_graph_state",
     "lmpo_hermitize",
     "lmpo_batch_arena_bytes", "lmpo_batch_create", "lmpo_batch_evolve_step", "lmpo_batch_sync",
@@ -116,6 +117,8 @@ def load_library(path: str = LIB_PATH):
         "lmpo_profile_end": (ctypes.c_int, [P, pdbl]),
         "lmpo_set_workgroups": (ctypes.c_int, [P, i32]),
         "lmpo_set_svd_tolerance": (ctypes.c_int, [P, dbl]),
+        "lmpo_set_svd_subspace": (ctypes.c_int, [P, i32, i32, i32, i32, dbl]),
+        "lmpo_svd_subspace_stats": (ctypes.c_int, [P, pi32]),
         "lmpo_renyi2": (ctypes.c_int, [P, pdbl]),
         "lmpo_osee": (ctypes.c_int, [P, i32, pdbl]),
         "lmpo_apply_superop": (ctypes.c_int, [P, i32, i32, pdbl]),
@@ -371,10 +374,12 @@ class Chain:
 
     def svd_profile(self):
         """Accumulated microseconds per persistent-SVD phase (first workgroup)."""
-        out = np.zeros(24)
+        out = np.zeros(32)
         _check(self._lib.lmpo_svd_profile(self._h, _dptr(out)))
         names = ["setup", "pairs", "wait", "cycles", "tasks", "select", "epilogue", "launches", "gram", "eig",
-                 "upd_x", "upd_v", "rotated", "-", "-", "-", "order", "qr_panel", "qr_update", "form_q"]
+                 "upd_x", "upd_v", "rotated", "-", "-", "-", "order", "qr_panel", "qr_update", "form_q",
+                 "sub_setup", "sub_iterations", "sub_final_cholqr", "cholqr_passes", "sub_vectors", "hop_cholqr",
+                 "cholqr_gram", "cholqr_cholesky", "cholqr_solve", "chol_update", "chol_diag", "chol_rows"]
         return dict(zip(names, out.tolist()))
 
     def profile_begin(self, max_launches=20000):
@@ -387,6 +392,18 @@ class Chain:
     def set_svd_tolerance(self, factor):
         """Jacobi stopping threshold in units of sqrt(C) eps (default 32)."""
         _check(self._lib.lmpo_set_svd_tolerance(self._h, float(factor)))
+
+    def set_svd_subspace(self, min_cols=512, margin=64, grow=32, iterations=4, tol=2e-14):
+        """Truncated SVD of gate blocks with at least min_cols columns on a
+        subspace (min_cols <= 0: every block takes the full SVD)."""
+        _check(self._lib.lmpo_set_svd_subspace(self._h, int(min_cols), int(margin), int(grow), int(iterations),
+                                               float(tol)))
+
+    def svd_subspace_stats(self):
+        """(subspace SVDs accepted, handed to the full SVD, iterations of the accepted ones)."""
+        out = np.zeros(3, dtype=np.int32)
+        _check(self._lib.lmpo_svd_subspace_stats(self._h, _iptr(out)))
+        return tuple(int(x) for x in out)
 
     def profile_end(self):
         """(SVD launches, summed kernel ms from HIP events, summed declared flops)."""

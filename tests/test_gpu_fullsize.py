@@ -59,11 +59,14 @@ def inject(ch, A, centre):
     ch.set_centre(centre)
 
 
-def one_gate_parity(Chain, dims, bond, chi_max, cutoff, seed, decay=0.0, asc=True, half=True, tau=0.05):
+def one_gate_parity(Chain, dims, bond, chi_max, cutoff, seed, decay=0.0, asc=True, half=True, tau=0.05,
+                    subspace=True):
     N = len(dims) + 1
     m = workloads.jittered_chain(N, seed)
     A = random_canonical_mps(dims, bond, seed, decay)
     ch = Chain(m, tau, chi_max, cutoff, "fp64", "+z")
+    if not subspace:
+        ch.set_svd_subspace(min_cols=0)
     inject(ch, A, bond)
     ch.apply_gate(bond, half, asc)
     sv, kept = ch.last_spectrum()
@@ -73,15 +76,31 @@ def one_gate_parity(Chain, dims, bond, chi_max, cutoff, seed, decay=0.0, asc=Tru
     return ch, ref, sv, kept, kk, s
 
 
+@pytest.mark.parametrize("subspace", [False, True])
 @pytest.mark.parametrize("decay", [0.0, 0.02])
-def test_full_size_gate_1024(Chain, decay):
+def test_full_size_gate_1024(Chain, decay, subspace):
+    """One gate on a 1024 x 1024 block, by the full SVD (all 1024 singular
+    values) and by the subspace SVD (the 320 Ritz values of its subspace)."""
     dims = [4, 16, 64, 256, 256, 256, 64, 16, 4]  # N = 10; bond 4 joins two chi = 256 bonds
-    ch, ref, sv, kept, kk, s = one_gate_parity(Chain, dims, 4, 256, 1e-10, 3, decay)
-    assert len(sv) == 1024 and len(s) == 1024
+    print(f"case: 1024 x 1024 gate, decay {decay}, subspace {subspace}", flush=True)
+    ch, ref, sv, kept, kk, s = one_gate_parity(Chain, dims, 4, 256, 1e-10, 3, decay, subspace=subspace)
+    assert len(s) == 1024
     assert kept == kk
-    # singular values: relative agreement where they carry weight
-    big = s > 1e-12 * s[0]
-    np.testing.assert_allclose(sv[big], s[big], rtol=1e-10, atol=1e-13 * s[0])
+    acc, fell, _ = ch.svd_subspace_stats()
+    if subspace and decay == 0.0:
+        # a Gaussian centre: the gate block has a gap at the bond's 256
+        assert (acc, fell) == (1, 0) and len(sv) == 320
+    if subspace and acc:
+        # the kept Ritz values; the first discarded one (a Ritz value from
+        # below, accurate to the residual of its unconverged vector) loosely
+        np.testing.assert_allclose(sv[:kept], s[:kept], rtol=1e-10, atol=1e-13 * s[0])
+        assert s[kept] * (1 - 1e-2) <= sv[kept] <= s[kept] * (1 + 1e-12)
+    else:
+        assert len(sv) == 1024
+        assert acc == 0
+        # singular values: relative agreement where they carry weight
+        big = s > 1e-12 * s[0]
+        np.testing.assert_allclose(sv[big], s[big], rtol=1e-10, atol=1e-13 * s[0])
     assert ch.bond_dims() == ref.bond_dims()
     for i in (0, 3, 4, 5, 9):
         g = ch.measure_1q([i], "Z")[0]

@@ -1,0 +1,177 @@
+"""GPU parity of the subspace truncated SVD (randomized subspace iteration with
+Rayleigh-Ritz, used for wide gate blocks) against the FP64 oracle's full
+LAPACK SVD and the truncation rule of App. B / Sec. 6.
+
+The subspace path is forced onto small blocks (min_cols lowered) so that the
+oracle finishes in seconds, and runs with its defaults on 1024 x 1024 blocks
+where chi_max = 256 binds.  Blocks whose subspace does not converge within
+the iteration budget (no gap in the spectrum at the cut) or whose Cholesky QR
+breaks down (fewer significant singular values than the subspace holds) are
+handed to the full SVD; the tests accept either path but require parity.  Bar: observables within 1e-10 (FP64), bond
+dimensions identical, the subspace path taken by most wide blocks.
+"""
+import numpy as np
+import pytest
+
+import workloads
+from oracle import model as lm
+from oracle import tebd
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def Chain():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2203_05871_amd import Chain, load_library
+
+    load_library()
+    return Chain
+
+
+def evolve_both(ch, m, run, steps, cutoff=None):
+    cut = run["cutoff"] if cutoff is None else cutoff
+    ref = tebd.MPS.product(run["init"], m["N"])
+    gates = tebd.gate_tables(m, run["tau"])
+    worst = 0.0
+    for n in range(steps):
+        ch.evolve(1)
+        tebd.evolve(ref, m, run["tau"], 1, run["chi_max"], cut, gates=gates, first_step=n)
+        assert ch.bond_dims() == ref.bond_dims(), (n, ch.bond_dims(), ref.bond_dims())
+    z1, z2 = ch.zz_observables()
+    r1, r2 = tebd.zz_observables(ref)
+    worst = max(np.abs(z1 - r1).max(), np.abs(z2 - r2).max())
+    return worst, ref
+
+
+@pytest.mark.parametrize("precision", ["fp64", "real"])
+def test_forced_subspace_small_chain(Chain, precision):
+    """N=10 jittered chain, chi_max 16, cutoff 1e-12, tau 0.05, 16 steps from
+    +x: the 64 x 64 blocks go through the subspace path (p = 32).  Some of
+    these small blocks have fewer than 32 singular values above 1e-8 of the
+    largest; their Cholesky QR breaks down and the full SVD takes them."""
+    m = workloads.jittered_chain(10, 2)
+    run = {"tau": 0.05, "chi_max": 16, "cutoff": 1e-12, "init": "+x"}
+    print(f"case: N=10 chi 16 forced subspace, {precision}", flush=True)
+    ch = Chain(m, run["tau"], run["chi_max"], run["cutoff"], precision, run["init"])
+    ch.set_svd_subspace(min_cols=32, margin=16, grow=8, iterations=6, tol=1e-13)
+    err, ref = evolve_both(ch, m, run, 16)
+    acc, fell, iters = ch.svd_subspace_stats()
+    print(f"  max |obs - oracle| = {err:.2e}; subspace accepted {acc}, fallbacks {fell}, iterations {iters}",
+          flush=True)
+    assert err < 1e-10
+    assert acc >= 40
+    assert abs(ch.discarded_weight() - ref.discarded) < 1e-12
+    ch.close()
+
+
+def test_forced_subspace_ragged_dims(Chain):
+    """Bond dims that are no multiple of 16 (37, 53, 29): one gate on each
+    side of the ragged bond, subspace forced, against the oracle."""
+    from test_gpu_fullsize import random_canonical_mps, inject
+
+    dims = [4, 16, 37, 53, 29, 16, 4]
+    N = len(dims) + 1
+    m = workloads.jittered_chain(N, 5)
+    A = random_canonical_mps(dims, 3, 5, 0.05)
+    print("case: ragged dims 37/53/29, forced subspace", flush=True)
+    ch = Chain(m, 0.05, 64, 1e-12, "fp64", "+z")
+    # no gap at the cut (chi_max = 64 binds inside a slowly decaying spectrum):
+    # the subspace needs many iterations
+    ch.set_svd_subspace(min_cols=32, margin=16, grow=8, iterations=24, tol=1e-13)
+    inject(ch, A, 3)
+    ref = tebd.MPS(tebd.from_pauli(A), centre=3)
+    for bond, asc in ((3, True), (5, True), (1, False)):
+        ch.apply_gate(bond, 0, asc)
+        ref.apply_gate(bond, lm.bond_gate(m, bond, 0.05), 64, 1e-12, asc)
+        assert ch.bond_dims() == ref.bond_dims(), bond
+    for i in range(N):
+        assert abs(ch.measure_1q([i], "Z")[0] - ref.expect({i: lm.SZ})) < 1e-10
+        assert abs(ch.measure_1q([i], "X")[0] - ref.expect({i: lm.SX})) < 1e-10
+    acc, fell, _ = ch.svd_subspace_stats()
+    assert acc >= 1 and fell == 0, (acc, fell)
+    ch.close()
+
+
+def test_chi256_step_against_oracle(Chain):
+    """One whole Trotter step of a 12-site chain whose interior bonds hold
+    chi = 256 (random canonical state, Gaussian centre): every gate between
+    two chi = 256 bonds is a 1024 x 1024 block for the subspace path with its
+    defaults, and the hops across chi = 256 bonds take Cholesky QR.  Bond dims
+    and every <sz_i>, <sz_i sz_j> against the oracle (chi_max 256, cutoff
+    1e-10)."""
+    from test_gpu_fullsize import random_canonical_mps, inject
+
+    dims = [4, 16, 64, 256, 256, 256, 256, 256, 64, 16, 4]
+    N = len(dims) + 1
+    m = workloads.jittered_chain(N, 7)
+    A = random_canonical_mps(dims, 0, 7)
+    print("case: N=12 random chi 256 state, one step, default subspace", flush=True)
+    ch = Chain(m, 0.05, 256, 1e-10, "fp64", "+z")
+    inject(ch, A, 0)
+    ref = tebd.MPS(tebd.from_pauli(A), centre=0)
+    ch.evolve(1)
+    tebd.evolve(ref, m, 0.05, 1, 256, 1e-10, first_step=0)
+    acc, fell, iters = ch.svd_subspace_stats()
+    z1, z2 = ch.zz_observables()
+    r1, r2 = tebd.zz_observables(ref)
+    err = max(np.abs(z1 - r1).max(), np.abs(z2 - r2).max())
+    print(f"  max |obs - oracle| = {err:.2e}; dims {ch.bond_dims()}; accepted {acc}, fallbacks {fell}, "
+          f"iterations {iters}", flush=True)
+    assert ch.bond_dims() == ref.bond_dims()
+    assert err < 1e-10
+    assert acc >= 4
+    ch.close()
+
+
+def test_rejected_subspace_falls_back_bit_identically(Chain):
+    """With an unreachable residual bound every subspace result is rejected
+    and the full SVD takes the untouched block: the run is bit-identical to
+    one with the subspace path switched off."""
+    m = workloads.jittered_chain(10, 2)
+    print("case: N=10 chi 16, rejected subspace vs off", flush=True)
+    a = Chain(m, 0.05, 16, 1e-12, "fp64", "+x")
+    a.set_svd_subspace(min_cols=32, margin=16, grow=8, iterations=2, tol=1e-300)
+    b = Chain(m, 0.05, 16, 1e-12, "fp64", "+x")
+    b.set_svd_subspace(min_cols=0)
+    a.evolve(6)
+    b.evolve(6)
+    acc, fell, _ = a.svd_subspace_stats()
+    assert acc == 0 and fell > 0
+    for k in range(m["N"]):
+        np.testing.assert_array_equal(a.get_site(k), b.get_site(k))
+    assert a.bond_dims() == b.bond_dims()
+    a.close()
+    b.close()
+
+
+def test_subspace_independent_of_workgroups(Chain):
+    """The subspace path gives the same bits with 1, 3 and all workgroups."""
+    m = workloads.jittered_chain(10, 4)
+    out = []
+    for wg in (1, 3, 0):
+        c = Chain(m, 0.05, 16, 1e-12, "fp64", "+x")
+        c.set_svd_subspace(min_cols=32, margin=16, grow=8, iterations=6, tol=1e-13)
+        c.set_workgroups(wg)
+        c.evolve(5)
+        out.append([c.get_site(k) for k in range(m["N"])])
+        assert c.svd_subspace_stats()[0] > 0
+        c.close()
+    for other in out[1:]:
+        for x, y in zip(out[0], other):
+            np.testing.assert_array_equal(x, y)
+
+
+def test_subspace_argument_errors(Chain):
+    from paper_2203_05871_amd import LmpoError
+
+    m = workloads.jittered_chain(6, 0)
+    c = Chain(m, 0.05, 16, 0.0, "fp64", "+x")
+    for kw in ({"margin": 8}, {"margin": 200}, {"iterations": 0}, {"tol": 0.0}, {"grow": -1}):
+        with pytest.raises(LmpoError):
+            c.set_svd_subspace(min_cols=32, **kw)
+    c.set_svd_subspace(min_cols=0)
+    c.close()
