@@ -300,11 +300,11 @@ int lmpo_svd_stats(lmpo_state *s, int32_t out[4]);
  * select, [6] epilogue; inside the pair work [8] Gram, [9] eigen sweep, [10] X
  * update, [11] V update; [16] column order, [17] QR panels, [18] QR trailing
  * updates, [19] forming Q Y; subspace SVD: [20] set-up, [21] iterations,
- * [22] final Cholesky QR, [24] vectors and residual check, [25] hops by
+ * [22] final Cholesky QR, [23] Rayleigh-Ritz outside its Jacobi phases, [24] vectors and residual check, [25] hops by
  * Cholesky QR, and inside every Cholesky-QR pass [26] Gram matrix, [27]
  * Cholesky factorisation (inside it [29] updates, [30] diagonal blocks, [31]
  * rows below), [28] inverse factor and product.  Counts: [3] shader clock
- * cycles, [4] pair tasks, [7] launches, [12] pair tasks that rotated, [23]
+ * cycles, [4] pair tasks, [7] launches, [12] pair tasks that rotated, [15]
  * Cholesky-QR passes.  out_us has 32 entries.  Synchronises. */
 int lmpo_svd_profile(lmpo_state *s, double out_us[32]);
 

@@ -1283,8 +1283,8 @@ int lmpo_svd_profile(lmpo_state *S, double out_us[32]) {
   out_us[4] = (double)t[13];   // pair tasks of the first workgroup
   out_us[7] = (double)t[7];    // launches
   out_us[12] = (double)t[14];  // of which rotated
-  out_us[23] = (double)t[23];  // Cholesky-QR passes
-  out_us[13] = out_us[14] = out_us[15] = 0.0;
+  out_us[13] = out_us[14] = 0.0;
+  out_us[15] = (double)t[15];  // Cholesky-QR passes
   return LMPO_OK;
 }
 

@@ -92,7 +92,8 @@ struct SvdLaunch {
   double2 *Ldi;      // inverses of its 16 x 16 diagonal blocks (pmax / 16 of them)
   double2 *Rb;       // C x pmax: right singular vectors (kept columns)
   double2 *Res;      // C x pmax: residual scratch
-  double *rsi_scal;  // [0] squared Frobenius norm of the block, [1] pending discarded fraction, [2] residual
+  double *rsi_scal;  // [0] squared Frobenius norm of the block, [1] pending discarded fraction, [2] residual,
+                     // [3] deviation of a repeat Gram matrix from the identity
   int *rsi_flag;     // [0] Cholesky breakdown, [1] result rejected
 };
 int svd_grid_size();

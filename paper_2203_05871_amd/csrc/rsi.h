@@ -213,74 +213,103 @@ __device__ __forceinline__ double rdlane(double v, int l) {
 }
 
 // Wavefront 0: Cholesky factor L_d of the nb x nb diagonal block P[c][r]
-// (r, c < nb, lower part) and its inverse, in registers (lane r holds row r;
-// column c of the inverse is built in lane c), broadcasting with readlane.
+// (r, c < nb, lower part; identity beyond nb) and its inverse.  Lane l
+// holds row r = l % 16 of the columns q, q + 4, q + 8, q + 12 (q = l / 16):
+// right-looking, each finished column broadcast through LDS; the inverse
+// by forward substitution, each finished row of it broadcast likewise.
 // L_d goes to sh.Ld, its inverse to sh.Mi and to Ldinv[j0 / 16].  Sets
 // sh.fail when a pivot is not positive and finite.
 template <bool kReal>
 __device__ __noinline__ void factor_diag_block(SharedChol &sh, int nb, int j0, int p,
-                                                  double2 *__restrict__ Ldinv) {
-  const int lane = threadIdx.x & 63;
-  double xr[kPanel], xi[kPanel];  // row `lane` of P, becoming row `lane` of L_d
+                                                     double2 *__restrict__ Ldinv) {
+  const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
+  double xr[4], xi[4];
 #pragma unroll
-  for (int c = 0; c < kPanel; ++c) {
-    const double2 v = (lane < nb && c <= lane && c < nb) ? sh.P[c][lane] : make_double2(0, 0);
-    xr[c] = v.x;
-    xi[c] = kReal ? 0.0 : v.y;
+  for (int t = 0; t < 4; ++t) {
+    const int c = q + 4 * t;
+    const double2 v = (r < nb && c <= r) ? sh.P[c][r] : make_double2(0, 0);
+    xr[t] = v.x;
+    xi[t] = kReal ? 0.0 : v.y;
   }
-  double dg[kPanel];  // the diagonal of L_d, the same in every lane
+  double2 *col = &sh.part[0][0][0];  // two 16-entry broadcast buffers
+  double dg[kPanel];
 #pragma unroll
   for (int c = 0; c < kPanel; ++c) {
-    // d = sqrt(P[c][c] - sum_{l<c} |L[c][l]|^2) in lane c
-    double dd = xr[c];
-#pragma unroll
-    for (int l = 0; l < c; ++l) dd -= xr[l] * xr[l] + xi[l] * xi[l];
-    dd = rdlane(dd, c);
+    const int cq = c & 3, ct = c >> 2;
+    const double dd = rdlane(xr[ct], c + 16 * cq);
     if (c < nb && lane == 0 && (!(dd > 0.0) || !(dd < INFINITY))) sh.fail = 1;
     const double d = (c < nb && dd > 0.0) ? sqrt(dd) : 1.0;
     dg[c] = d;
-    const double inv = 1.0 / d;
-    // L[r][c] = (P[r][c] - sum_{l<c} L[r][l] conj(L[c][l])) / d, rows r > c
-    double ar = xr[c], ai = xi[c];
-#pragma unroll
-    for (int l = 0; l < c; ++l) {
-      const double yr = rdlane(xr[l], c), yi = rdlane(xi[l], c);
-      ar -= xr[l] * yr + xi[l] * yi;
-      ai -= xi[l] * yr - xr[l] * yi;
+    double2 *buf = col + 16 * (c & 1);
+    if (q == cq) {
+      if (r > c) {
+        const double inv = 1.0 / d;
+        xr[ct] *= inv;
+        xi[ct] = kReal ? 0.0 : xi[ct] * inv;
+      } else {
+        xr[ct] = r == c ? d : 0.0;
+        xi[ct] = 0.0;
+      }
+      buf[r] = make_double2(xr[ct], xi[ct]);
     }
-    if (lane > c) {
-      xr[c] = ar * inv;
-      xi[c] = kReal ? 0.0 : ai * inv;
-    } else if (lane == c) {
-      xr[c] = d;
-      xi[c] = 0.0;
+    wave_lds_sync();
+    if (c + 1 < kPanel) {
+      const double2 lrc = buf[r];  // L[r][c]
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const int s = q + 4 * t;
+        if (s > c) {
+          const double2 y = buf[s];  // L[s][c]
+          xr[t] -= lrc.x * y.x + lrc.y * y.y;
+          if (!kReal) xi[t] -= lrc.y * y.x - lrc.x * y.y;
+        }
+      }
     }
   }
-  // column `lane` of the inverse: M[c][c] = 1 / L[c][c],
-  // M[r][c] = -(sum_{c <= l < r} L[r][l] M[l][c]) / L[r][r]
-  double mr[kPanel], mi[kPanel];
+  // L_d (zeros above the diagonal) to LDS
 #pragma unroll
-  for (int r = 0; r < kPanel; ++r) {
-    double ar = (r == lane) ? 1.0 : 0.0, ai = 0.0;
-#pragma unroll
-    for (int l = 0; l < r; ++l) {
-      const double lr_ = rdlane(xr[l], r), li_ = rdlane(xi[l], r);  // L[r][l]
-      ar -= lr_ * mr[l] - li_ * mi[l];
-      ai -= lr_ * mi[l] + li_ * mr[l];
-    }
-    const double inv = 1.0 / dg[r];
-    mr[r] = (r >= lane) ? ar * inv : 0.0;
-    mi[r] = (r >= lane && !kReal) ? ai * inv : 0.0;
+  for (int t = 0; t < 4; ++t) {
+    const int c = q + 4 * t;
+    sh.Ld[r][c] = c <= r ? make_double2(xr[t], xi[t]) : make_double2(0, 0);
   }
-  if (lane < kPanel) {
-    double2 *Dst = Ldinv + (size_t)(j0 / kPanel) * kPanel * kPanel;
+  wave_lds_sync();
+  // rows of M = L_d^{-1}: lane holds M[r][q + 4 t]
+  double mr[4], mi[4];
 #pragma unroll
-    for (int c = 0; c < kPanel; ++c) sh.Ld[lane][c] = make_double2(xr[c], xi[c]);
+  for (int t = 0; t < 4; ++t) {
+    mr[t] = (q + 4 * t == r) ? 1.0 : 0.0;
+    mi[t] = 0.0;
+  }
 #pragma unroll
-    for (int r = 0; r < kPanel; ++r) {
-      sh.Mi[r][lane] = make_double2(mr[r], mi[r]);
-      gst(Dst, r + lane * kPanel, make_double2(mr[r], mi[r]));
+  for (int k = 0; k < kPanel; ++k) {
+    double2 *buf = col + 16 * (k & 1);
+    if (r == k) {
+      const double inv = 1.0 / dg[k];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        mr[t] *= inv;
+        mi[t] *= inv;
+        buf[q + 4 * t] = make_double2(mr[t], mi[t]);
+      }
     }
+    wave_lds_sync();
+    if (r > k) {
+      const double2 l = sh.Ld[r][k];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        const double2 m = buf[q + 4 * t];  // M[k][j]
+        mr[t] -= l.x * m.x - l.y * m.y;
+        if (!kReal) mi[t] -= l.x * m.y + l.y * m.x;
+      }
+    }
+  }
+  double2 *Dst = Ldinv + (size_t)(j0 / kPanel) * kPanel * kPanel;
+#pragma unroll
+  for (int t = 0; t < 4; ++t) {
+    const int j = q + 4 * t;
+    const double2 v = make_double2(mr[t], kReal ? 0.0 : mi[t]);
+    sh.Mi[r][j] = v;
+    gst(Dst, r + j * kPanel, v);
   }
 }
 

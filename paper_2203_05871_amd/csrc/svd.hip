@@ -87,9 +87,12 @@ struct Barrier {
         if (t == target * ngrp - 1u) __hip_atomic_store(flag, target, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
       }
       // bounded wait: a co-resident grid always completes; the limit (seconds)
-      // only guarantees that every wave exits if residency were ever violated
+      // only guarantees that every wave exits if residency were ever violated.
+      // The flag is polled with relaxed loads and acquired once by the fence
+      // below: an acquiring load invalidates the XCD's L2 at every poll,
+      // which starves the workgroups still working on that XCD.
       unsigned spins = 0;
-      while (__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
         __builtin_amdgcn_s_sleep(1);
         if (++spins > (1u << 25)) {
           atomicOr(err, 2);
@@ -127,13 +130,14 @@ __device__ __forceinline__ void wave_sync() {
 // finished with block b (monotonic within a launch); a pair waits until both
 // of its blocks reach `need`, works, and publishes need + 1 for both.  The
 // fences are those of the grid barrier (agent-scope release before the
-// publishing store, acquire after the wait); the wait is bounded like the
-// barrier's and skipped once an error has been flagged.
+// publishing store; relaxed polling, then an acquire fence after the wait);
+// the wait is bounded like the barrier's and skipped once an error has been
+// flagged.
 __device__ __forceinline__ void wait_blocks(unsigned *va, unsigned *vb, unsigned need, int *err) {
   if (threadIdx.x == 0) {
     unsigned spins = 0;
-    while (__hip_atomic_load(va, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need ||
-           __hip_atomic_load(vb, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < need) {
+    while (__hip_atomic_load(va, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need ||
+           __hip_atomic_load(vb, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
       if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 2) break;
       __builtin_amdgcn_s_sleep(1);
       if (++spins > (1u << 25)) {  // the grid barrier's bound
@@ -766,8 +770,9 @@ __device__ __forceinline__ int rsi_width(const SvdLaunch &a, int C, int chm) {
 
 // Mout <- M L^{-H} with L the Cholesky factor of M^H M (M, Mout: rows x p,
 // ld rows; Mout may not be M): one Cholesky QR pass.  The Gram matrix is
-// formed in kGramSplit partial sums by all workgroups, workgroup 0 factors
-// it, L^{-1} is formed by column blocks and the product with it is a GEMM.
+// formed in kGramSplit partial sums by all workgroups and summed by all,
+// workgroup 0 factors it, L^{-1} is formed by column blocks and the product
+// with it is a GEMM.
 // near_identity > 0: the pass is a repeat, and its Gram matrix must lie
 // within that distance of the identity (max entry of the lower triangle),
 // which bounds the loss of orthogonality of the result to a few units of
@@ -781,36 +786,50 @@ __device__ __noinline__ bool cholqr_pass(const SvdLaunch &a, Barrier &bar, Share
   // phase timers of the first workgroup: [26] Gram, [27] Cholesky, [28] L^{-1} and the product
   Laps laps{a.tprof && rank == 0 && threadIdx.x == 0 ? a.tprof : nullptr, (unsigned long long)wall_clock64()};
   const size_t gstride = (size_t)p * p;
+  if (rank == 0 && threadIdx.x == 0) a.rsi_scal[3] = 0.0;
   rsi::gemm<kReal>(sh.rg, p, p, rows, M, rows, 1, M, rows, 0, nullptr, nullptr, a.Gr, p, true, rank, G,
                    rsi::kGramSplit, gstride);
   bar.sync();
   laps.lap(26);
-  if (laps.tp && rank == 0) laps.tp[23] += 1;  // Cholesky-QR passes
-  if (rank == 0) {
-    bool ok = true;
-    if (near_identity > 0.0) {
-      double dev = 0.0;
-      for (int e = threadIdx.x; e < p * p; e += NT) {
-        const int i = e % p, j = e / p;
-        if (i >= j) {
-          double2 g = a.Gr[e];
-          for (int sp = 1; sp < rsi::kGramSplit; ++sp) {
-            g.x += a.Gr[e + sp * gstride].x;
-            g.y += a.Gr[e + sp * gstride].y;
-          }
-          dev = fmax(dev, fabs(g.x - (i == j ? 1.0 : 0.0)) + fabs(g.y));
-        }
+  if (laps.tp) laps.tp[15] += 1;  // Cholesky-QR passes
+  // the partial sums, added into the first (lower triangle) by all
+  // workgroups; on a repeat pass also the largest deviation from the identity
+  // (a max over non-negative values, exact in any order: the bit patterns
+  // order like the values, NaN above all)
+  double dev = 0.0;
+  for (size_t e = (size_t)rank * NT + threadIdx.x; e < gstride; e += (size_t)G * NT) {
+    const int i = (int)(e % p), j = (int)(e / p);
+    if (i >= j) {
+      double2 g = a.Gr[e];
+      for (int sp = 1; sp < rsi::kGramSplit; ++sp) {
+        const double2 h = a.Gr[e + sp * gstride];
+        g.x += h.x;
+        g.y += h.y;
       }
-      sh.red[threadIdx.x] = dev;
-      __syncthreads();
-      for (int off = NT / 2; off > 0; off >>= 1) {
-        if (threadIdx.x < off) sh.red[threadIdx.x] = fmax(sh.red[threadIdx.x], sh.red[threadIdx.x + off]);
-        __syncthreads();
+      a.Gr[e] = g;
+      const double d = fabs(g.x - (i == j ? 1.0 : 0.0)) + fabs(g.y);
+      dev = d <= dev ? dev : d;
+    }
+  }
+  if (near_identity > 0.0) {
+    sh.red[threadIdx.x] = dev;
+    __syncthreads();
+    for (int off = NT / 2; off > 0; off >>= 1) {
+      if (threadIdx.x < off) {
+        const double o = sh.red[threadIdx.x + off];
+        sh.red[threadIdx.x] = o <= sh.red[threadIdx.x] ? sh.red[threadIdx.x] : o;
       }
-      ok = sh.red[0] <= near_identity;
       __syncthreads();
     }
-    if (ok) ok = rsi::cholesky<kReal>(sh.rc, p, a.Gr, rsi::kGramSplit, gstride, L, a.Ldi, laps.tp);
+    if (threadIdx.x == 0)
+      atomicMax((unsigned long long *)&a.rsi_scal[3], (unsigned long long)__double_as_longlong(sh.red[0]));
+    __syncthreads();
+  }
+  bar.sync();
+  if (rank == 0) {
+    bool ok = true;
+    if (near_identity > 0.0) ok = a.rsi_scal[3] <= near_identity;
+    if (ok) ok = rsi::cholesky<kReal>(sh.rc, p, a.Gr, 1, 0, L, a.Ldi, laps.tp);
     if (threadIdx.x == 0 && !ok) a.rsi_flag[0] = 1;
   }
   bar.sync();

@@ -377,8 +377,8 @@ class Chain:
         out = np.zeros(32)
         _check(self._lib.lmpo_svd_profile(self._h, _dptr(out)))
         names = ["setup", "pairs", "wait", "cycles", "tasks", "select", "epilogue", "launches", "gram", "eig",
-                 "upd_x", "upd_v", "rotated", "-", "-", "-", "order", "qr_panel", "qr_update", "form_q",
-                 "sub_setup", "sub_iterations", "sub_final_cholqr", "cholqr_passes", "sub_vectors", "hop_cholqr",
+                 "upd_x", "upd_v", "rotated", "-", "-", "cholqr_passes", "order", "qr_panel", "qr_update", "form_q",
+                 "sub_setup", "sub_iterations", "sub_final_cholqr", "sub_rr_rest", "sub_vectors", "hop_cholqr",
                  "cholqr_gram", "cholqr_cholesky", "cholqr_solve", "chol_update", "chol_diag", "chol_rows"]
         return dict(zip(names, out.tolist()))
 
