@@ -213,103 +213,89 @@ __device__ __forceinline__ double rdlane(double v, int l) {
 }
 
 // Wavefront 0: Cholesky factor L_d of the nb x nb diagonal block P[c][r]
-// (r, c < nb, lower part; identity beyond nb) and its inverse.  Lane l
-// holds row r = l % 16 of the columns q, q + 4, q + 8, q + 12 (q = l / 16):
-// right-looking, each finished column broadcast through LDS; the inverse
-// by forward substitution, each finished row of it broadcast likewise.
-// L_d goes to sh.Ld, its inverse to sh.Mi and to Ldinv[j0 / 16].  Sets
-// sh.fail when a pivot is not positive and finite.
+// (r, c < nb, lower part; identity beyond nb) and its inverse M_d.  Lane l
+// holds row r = l % 16 of the columns q, q + 4, q + 8, q + 12 (q = l / 16) of
+// both.  Step c finishes column c of L_d (right-looking, the column then
+// broadcast through LDS for the update of the columns right of it) and row
+// c of M_d (forward substitution: that row broadcast likewise for the rows
+// below it), so the two run side by side in 16 steps.  L_d goes to sh.Ld,
+// M_d to sh.Mi and to Ldinv[j0 / 16].  Sets sh.fail when a pivot is not
+// positive and finite.
 template <bool kReal>
 __device__ __noinline__ void factor_diag_block(SharedChol &sh, int nb, int j0, int p,
-                                                     double2 *__restrict__ Ldinv) {
+                                                  double2 *__restrict__ Ldinv) {
   const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
-  double xr[4], xi[4];
+  double xr[4], xi[4], mr[4], mi[4];
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
     const int c = q + 4 * t;
     const double2 v = (r < nb && c <= r) ? sh.P[c][r] : make_double2(0, 0);
     xr[t] = v.x;
     xi[t] = kReal ? 0.0 : v.y;
+    mr[t] = c == r ? 1.0 : 0.0;
+    mi[t] = 0.0;
   }
-  double2 *col = &sh.part[0][0][0];  // two 16-entry broadcast buffers
-  double dg[kPanel];
+  double2 *cbuf = &sh.part[0][0][0];  // column c of L_d (two buffers of 16)
+  double2 *rbuf = &sh.part[1][0][0];  // row c of M_d
 #pragma unroll
   for (int c = 0; c < kPanel; ++c) {
     const int cq = c & 3, ct = c >> 2;
     const double dd = rdlane(xr[ct], c + 16 * cq);
-    if (c < nb && lane == 0 && (!(dd > 0.0) || !(dd < INFINITY))) sh.fail = 1;
-    const double d = (c < nb && dd > 0.0) ? sqrt(dd) : 1.0;
-    dg[c] = d;
-    double2 *buf = col + 16 * (c & 1);
+    const bool good = dd > 0.0 && dd < INFINITY;
+    if (c < nb && lane == 0 && !good) sh.fail = 1;
+    const double d = (c < nb && good) ? sqrt(dd) : 1.0;
+    const double inv = 1.0 / d;
+    double2 *cb = cbuf + 16 * (c & 1), *rb = rbuf + 16 * (c & 1);
     if (q == cq) {
       if (r > c) {
-        const double inv = 1.0 / d;
         xr[ct] *= inv;
         xi[ct] = kReal ? 0.0 : xi[ct] * inv;
       } else {
         xr[ct] = r == c ? d : 0.0;
         xi[ct] = 0.0;
       }
-      buf[r] = make_double2(xr[ct], xi[ct]);
+      cb[r] = make_double2(xr[ct], xi[ct]);
     }
-    wave_lds_sync();
-    if (c + 1 < kPanel) {
-      const double2 lrc = buf[r];  // L[r][c]
-#pragma unroll
-      for (int t = 0; t < 4; ++t) {
-        const int s = q + 4 * t;
-        if (s > c) {
-          const double2 y = buf[s];  // L[s][c]
-          xr[t] -= lrc.x * y.x + lrc.y * y.y;
-          if (!kReal) xi[t] -= lrc.y * y.x - lrc.x * y.y;
-        }
-      }
-    }
-  }
-  // L_d (zeros above the diagonal) to LDS
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    const int c = q + 4 * t;
-    sh.Ld[r][c] = c <= r ? make_double2(xr[t], xi[t]) : make_double2(0, 0);
-  }
-  wave_lds_sync();
-  // rows of M = L_d^{-1}: lane holds M[r][q + 4 t]
-  double mr[4], mi[4];
-#pragma unroll
-  for (int t = 0; t < 4; ++t) {
-    mr[t] = (q + 4 * t == r) ? 1.0 : 0.0;
-    mi[t] = 0.0;
-  }
-#pragma unroll
-  for (int k = 0; k < kPanel; ++k) {
-    double2 *buf = col + 16 * (k & 1);
-    if (r == k) {
-      const double inv = 1.0 / dg[k];
+    if (r == c) {
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
         mr[t] *= inv;
         mi[t] *= inv;
-        buf[q + 4 * t] = make_double2(mr[t], mi[t]);
+        rb[q + 4 * t] = make_double2(mr[t], mi[t]);
       }
     }
     wave_lds_sync();
-    if (r > k) {
-      const double2 l = sh.Ld[r][k];
+    if (c + 1 < kPanel) {
+      const double2 lrc = cb[r];  // L[r][c]
 #pragma unroll
       for (int t = 0; t < 4; ++t) {
-        const double2 m = buf[q + 4 * t];  // M[k][j]
-        mr[t] -= l.x * m.x - l.y * m.y;
-        if (!kReal) mi[t] -= l.x * m.y + l.y * m.x;
+        const int s = q + 4 * t;
+        if (s > c) {
+          // L: column s -= L[r][c] conj(L[s][c])
+          const double2 y = cb[s];
+          xr[t] -= lrc.x * y.x + lrc.y * y.y;
+          if (!kReal) xi[t] -= lrc.y * y.x - lrc.x * y.y;
+        }
+      }
+      if (r > c) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+          // M: row r -= L[r][c] M[c][j]
+          const double2 m = rb[q + 4 * t];
+          mr[t] -= lrc.x * m.x - lrc.y * m.y;
+          if (!kReal) mi[t] -= lrc.x * m.y + lrc.y * m.x;
+        }
       }
     }
   }
   double2 *Dst = Ldinv + (size_t)(j0 / kPanel) * kPanel * kPanel;
 #pragma unroll
   for (int t = 0; t < 4; ++t) {
-    const int j = q + 4 * t;
+    const int c = q + 4 * t;
+    sh.Ld[r][c] = c <= r ? make_double2(xr[t], xi[t]) : make_double2(0, 0);
     const double2 v = make_double2(mr[t], kReal ? 0.0 : mi[t]);
-    sh.Mi[r][j] = v;
-    gst(Dst, r + j * kPanel, v);
+    sh.Mi[r][c] = v;
+    gst(Dst, r + c * kPanel, v);
   }
 }
 

@@ -69,7 +69,12 @@ struct Barrier {
   // thread 0 publishes them device-wide (agent-scope fence) and, after the
   // wait, acquires the other blocks' stores for the whole workgroup.
   __device__ void sync() {
-    if (G == 1u) {  // one workgroup: its own barrier orders its global traffic
+    if (G == 1u) {
+      // one workgroup: its own barrier orders its plain global traffic, and
+      // the device-scope fence orders that against the atomics, which are
+      // performed beyond the L2 that holds the plain stores
+      __syncthreads();
+      if (threadIdx.x == 0) __threadfence();
       __syncthreads();
       ++phase;
       return;
@@ -786,7 +791,8 @@ __device__ __noinline__ bool cholqr_pass(const SvdLaunch &a, Barrier &bar, Share
   // phase timers of the first workgroup: [26] Gram, [27] Cholesky, [28] L^{-1} and the product
   Laps laps{a.tprof && rank == 0 && threadIdx.x == 0 ? a.tprof : nullptr, (unsigned long long)wall_clock64()};
   const size_t gstride = (size_t)p * p;
-  if (rank == 0 && threadIdx.x == 0) a.rsi_scal[3] = 0.0;
+  if (rank == 0 && threadIdx.x == 0)
+    __hip_atomic_store((unsigned long long *)&a.rsi_scal[3], 0ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   rsi::gemm<kReal>(sh.rg, p, p, rows, M, rows, 1, M, rows, 0, nullptr, nullptr, a.Gr, p, true, rank, G,
                    rsi::kGramSplit, gstride);
   bar.sync();
@@ -828,7 +834,9 @@ __device__ __noinline__ bool cholqr_pass(const SvdLaunch &a, Barrier &bar, Share
   bar.sync();
   if (rank == 0) {
     bool ok = true;
-    if (near_identity > 0.0) ok = a.rsi_scal[3] <= near_identity;
+    if (near_identity > 0.0)
+      ok = __longlong_as_double((long long)__hip_atomic_load((unsigned long long *)&a.rsi_scal[3], __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT)) <= near_identity;
     if (ok) ok = rsi::cholesky<kReal>(sh.rc, p, a.Gr, 1, 0, L, a.Ldi, laps.tp);
     if (threadIdx.x == 0 && !ok) a.rsi_flag[0] = 1;
   }

@@ -149,16 +149,21 @@ def test_rejected_subspace_falls_back_bit_identically(Chain):
 
 
 def test_subspace_independent_of_workgroups(Chain):
-    """The subspace path gives the same bits with 1, 3 and all workgroups."""
+    """The subspace path gives the same bits with 1, 3 and all workgroups.
+    (10 steps: in the first few the blocks from the product state have fewer
+    significant singular values than the subspace holds, and nearly all of
+    them go to the full SVD.)"""
     m = workloads.jittered_chain(10, 4)
     out = []
     for wg in (1, 3, 0):
         c = Chain(m, 0.05, 16, 1e-12, "fp64", "+x")
         c.set_svd_subspace(min_cols=32, margin=16, grow=8, iterations=6, tol=1e-13)
         c.set_workgroups(wg)
-        c.evolve(5)
+        c.evolve(10)
         out.append([c.get_site(k) for k in range(m["N"])])
-        assert c.svd_subspace_stats()[0] > 0
+        stats = c.svd_subspace_stats()
+        print(f"  workgroups {wg}: subspace accepted {stats[0]}, fallbacks {stats[1]}", flush=True)
+        assert stats[0] >= 5, (wg, stats)
         c.close()
     for other in out[1:]:
         for x, y in zip(out[0], other):
