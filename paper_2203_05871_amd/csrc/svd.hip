@@ -852,6 +852,39 @@ __device__ __noinline__ bool cholqr_pass(const SvdLaunch &a, Barrier &bar, Share
   return true;
 }
 
+// C = op(A) B (M x N, inner K; C contiguous, ld M), then a grid barrier.
+// Products with few 64 x 64 output tiles and a long inner dimension (the
+// products with the gate block) cut the inner dimension into up to four
+// ranges, so that more workgroups take part: the partial products go to the
+// Gram scratch and are summed in a fixed order afterwards.  The cut depends
+// on the shape alone, never on the number of workgroups.
+template <bool kReal>
+__device__ void split_gemm(const SvdLaunch &a, Barrier &bar, SharedAll &sh, int M, int N, int K,
+                           const double2 *A, int lda, int opa, const double2 *B, double2 *C, int rank, int G) {
+  const int tiles = ((M + rsi::kTile - 1) / rsi::kTile) * ((N + rsi::kTile - 1) / rsi::kTile);
+  int ks = tiles > 0 ? min(4, max(1, 256 / tiles)) : 1;
+  if (K < 256) ks = 1;
+  const size_t mn = (size_t)M * N, cap = (size_t)rsi::kGramSplit * a.rsi_pmax * a.rsi_pmax;
+  while (ks > 1 && (size_t)ks * mn > cap) --ks;
+  if (ks == 1) {
+    rsi::gemm<kReal>(sh.rg, M, N, K, A, lda, opa, B, K, 0, nullptr, nullptr, C, M, false, rank, G);
+    bar.sync();
+    return;
+  }
+  rsi::gemm<kReal>(sh.rg, M, N, K, A, lda, opa, B, K, 0, nullptr, nullptr, a.Gr, M, false, rank, G, ks, mn);
+  bar.sync();
+  for (size_t e = (size_t)rank * NT + threadIdx.x; e < mn; e += (size_t)G * NT) {
+    double2 v = rsi::gld(a.Gr, e);
+    for (int s = 1; s < ks; ++s) {
+      const double2 w = rsi::gld(a.Gr, e + s * mn);
+      v.x += w.x;
+      v.y += w.y;
+    }
+    rsi::gst(C, e, v);
+  }
+  bar.sync();
+}
+
 // The subspace result is not used: count it and let the full SVD run.
 __device__ __forceinline__ bool rsi_reject(const SvdLaunch &a, int rank) {
   if (rank == 0 && threadIdx.x == 0 && a.stats) a.stats[6] += 1;
@@ -904,12 +937,10 @@ __device__ __noinline__ bool rsi_gate(const SvdLaunch &a, Barrier &bar, SharedAl
   int iters = a.rsi_iters, done = 0;
   for (int attempt = 0; attempt < 2; ++attempt) {
     for (; done < iters; ++done) {
-      rsi::gemm<kReal>(sh.rg, R, p, C, X, ldx, 0, Vc, C, 0, nullptr, nullptr, Zc, R, false, rank, G);
-      bar.sync();
+      split_gemm<kReal>(a, bar, sh, R, p, C, X, ldx, 0, Vc, Zc, rank, G);
       if (!cholqr_pass<kReal>(a, bar, sh, Zc, Wk, R, p, a.L1, rank, G)) return rsi_reject(a, rank);
       swap2(Zc, Wk);
-      rsi::gemm<kReal>(sh.rg, C, p, R, X, ldx, 1, Zc, R, 0, nullptr, nullptr, Vc, C, false, rank, G);
-      bar.sync();
+      split_gemm<kReal>(a, bar, sh, C, p, R, X, ldx, 1, Zc, Vc, rank, G);
       if (!cholqr_pass<kReal>(a, bar, sh, Vc, Wk, C, p, a.L1, rank, G)) return rsi_reject(a, rank);
       swap2(Vc, Wk);
     }
@@ -917,8 +948,7 @@ __device__ __noinline__ bool rsi_gate(const SvdLaunch &a, Barrier &bar, SharedAl
     // V orthonormal to working accuracy, then X V = Q T with T^H = L1 L2
     if (!cholqr_pass<kReal>(a, bar, sh, Vc, Wk, C, p, a.L1, rank, G, 0.5)) return rsi_reject(a, rank);
     swap2(Vc, Wk);
-    rsi::gemm<kReal>(sh.rg, R, p, C, X, ldx, 0, Vc, C, 0, nullptr, nullptr, Zc, R, false, rank, G);
-    bar.sync();
+    split_gemm<kReal>(a, bar, sh, R, p, C, X, ldx, 0, Vc, Zc, rank, G);
     if (!cholqr_pass<kReal>(a, bar, sh, Zc, Wk, R, p, a.L1, rank, G)) return rsi_reject(a, rank);
     if (!cholqr_pass<kReal>(a, bar, sh, Wk, Zc, R, p, a.L2, rank, G, 0.5)) return rsi_reject(a, rank);
     laps.lap(22);
@@ -963,8 +993,7 @@ __device__ __noinline__ bool rsi_gate(const SvdLaunch &a, Barrier &bar, SharedAl
     }
     bar.sync();
     // residuals X^H u_j - s_j v_j of the kept triplets
-    rsi::gemm<kReal>(sh.rg, C, k, R, X, ldx, 1, a.Lb, R, 0, nullptr, nullptr, a.Res, C, false, rank, G);
-    bar.sync();
+    split_gemm<kReal>(a, bar, sh, C, k, R, X, ldx, 1, a.Lb, a.Res, rank, G);
     for (int j = rank; j < k; j += G) {
       const double sg = a.sorted[j];
       double acc = 0.0;
