@@ -13,8 +13,11 @@ steps/s and the largest difference of all <s^z_i>, <s^z_i s^z_j> between the
 two after the K steps sit beside it.
 
 A step is one whole Trotter step of the hot path: centre hops, contraction +
-gate, truncated SVD, canonical update, trace renormalisation.  Warm-up runs W
-steps of each form from t=0 (first launches), untimed.
+gate, truncated SVD, canonical update, trace renormalisation.  Gate blocks of
+512 columns or more (the 1024 x 1024 blocks between two chi=256 bonds) take
+the subspace-iteration truncated SVD, accepted per block by its Ritz
+residuals, the rest the full Jacobi SVD; `subspace_svd` counts both.  Warm-up
+runs W steps of each form from t=0 (first launches), untimed.
 
 Also on the line: the configured 50-step run from +x (where chi stays below
 256) in the FP32, FP64 and real-arithmetic forms with the oracle's observables
@@ -83,6 +86,11 @@ def chain_from(model, run, precision, state):
     return ch
 
 
+# phase timers of the SVD kernel's first workgroup (lmpo_svd_profile), reported per step
+PHASES = ("pairs", "wait", "sub_iterations", "sub_final_cholqr", "sub_vectors", "hop_cholqr", "cholqr_gram",
+          "cholqr_cholesky", "cholqr_solve", "chol_update", "chol_diag", "chol_rows")
+
+
 def timed(ch, steps):
     """Exactly `steps` steps between stream synchronisations, HIP events around
     every SVD launch; returns time, kernel figures and the final observables."""
@@ -97,8 +105,14 @@ def timed(ch, steps):
     dt = time.perf_counter() - t0
     launches, svd_ms, svd_flops = ch.profile_end()
     stats = ch.svd_stats()
+    acc, fell, iters = ch.svd_subspace_stats()
+    prof = ch.svd_profile()
+    phases = {k: round(prof[k] / 1e3 / steps, 2) for k in PHASES}
+    phases["cholqr_passes_per_step"] = prof["cholqr_passes"] / steps
     return {"seconds": dt, "launches": launches, "svd_ms": svd_ms, "svd_flops": svd_flops, "obs": zz(ch),
-            "dims": ch.bond_dims(), "sweeps": stats[2], "svds": stats[3]}
+            "phases_ms_per_step": phases,
+            "dims": ch.bond_dims(), "sweeps": stats[2], "svds": stats[3],
+            "subspace": {"accepted": acc, "to_full_svd": fell, "iterations_per_accepted": iters / max(1, acc)}}
 
 
 def warm(model, run, precision, steps):
@@ -470,7 +484,10 @@ def main():
     tr = measured_traffic()
     roofline = roofline_of(h, tr["hbm_bytes_per_launch"] if tr else None)
     roofline.update({"traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated)",
-                     "measured_copy_GBps": copy_gbps, "measured_fp64_mfma_TFLOPs": mfma_tflops})
+                     "measured_copy_GBps": copy_gbps, "measured_fp64_mfma_TFLOPs": mfma_tflops,
+                     "counters_mfma_busy_frac": tr.get("mfma_busy_frac") if tr else None,
+                     "counters_mfma_f64_flops_executed_per_launch":
+                         tr.get("mfma_f64_flops_per_launch_executed") if tr else None})
     line = {
         "metric": METRIC, "value": K / h["seconds"], "unit": "steps/s", "n_gpus": 1, "steps": K, "warmup": W,
         "ms_per_step": 1e3 * h["seconds"] / K, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -491,6 +508,8 @@ def main():
         "obs_err_fp32_vs_fp64": float(np.abs(h["obs"] - d["obs"]).max()),
         "fp64_roofline": roofline_of(d),
         "sweeps_per_svd": {"fp32": h["sweeps"] / max(1, h["svds"]), "fp64": d["sweeps"] / max(1, d["svds"])},
+        "subspace_svd": {"fp32": h["subspace"], "fp64": d["subspace"]},
+        "svd_phases_ms_per_step": {"fp32": h["phases_ms_per_step"], "fp64": d["phases_ms_per_step"]},
     }
     if not args.no_cpu:
         # the oracle at the headline's block shapes: its own +x run with cutoff 0,

@@ -277,12 +277,15 @@ int lmpo_set_svd_tolerance(lmpo_state *s, double factor);
  * block restricted to the subspace (Rayleigh-Ritz, block Jacobi on a p x p
  * factor).  The kept triplets are accepted when each residual
  * ||theta^H u_j - s_j v_j|| is at most tol * s_1 and at least 16 vectors lie
- * beyond the cut; else two more iterations are run, and if that still fails
- * the full SVD of the block is taken instead.  The squared weight outside
- * the subspace, ||theta||_F^2 - sum_j s_j^2, counts as discarded.  Defaults:
- * min_cols 512, margin 64, grow 32, iterations 4, tol 2e-14; min_cols <= 0
- * turns it off (every block then takes the full SVD).  margin must lie in
- * [16, 128], iterations in [1, 64], tol in (0, 1). */
+ * beyond the cut; else the iteration continues once, for as many steps as
+ * the residual's observed rate of decrease needs to reach the bound (40 in
+ * all at most), and if that still fails the full SVD of the block is taken
+ * instead.  The squared weight outside the subspace, ||theta||_F^2 -
+ * sum_j s_j^2, counts as discarded.  Defaults: min_cols 512, margin 64, grow
+ * 32, iterations 4, tol 2e-14 (the FP32-contraction form: iterations 2, tol
+ * 1e-8, below the FP32 rounding of its block); min_cols <= 0 turns it off
+ * (every block then takes the full SVD).  margin must lie in [16, 128],
+ * iterations in [1, 64], tol in (0, 1). */
 int lmpo_set_svd_subspace(lmpo_state *s, int32_t min_cols, int32_t margin, int32_t grow, int32_t iterations,
                           double tol);
 
@@ -300,10 +303,11 @@ int lmpo_svd_stats(lmpo_state *s, int32_t out[4]);
  * select, [6] epilogue; inside the pair work [8] Gram, [9] eigen sweep, [10] X
  * update, [11] V update; [16] column order, [17] QR panels, [18] QR trailing
  * updates, [19] forming Q Y; subspace SVD: [20] set-up, [21] iterations,
- * [22] final Cholesky QR, [23] Rayleigh-Ritz outside its Jacobi phases, [24] vectors and residual check, [25] hops by
- * Cholesky QR, and inside every Cholesky-QR pass [26] Gram matrix, [27]
- * Cholesky factorisation (inside it [29] updates, [30] diagonal blocks, [31]
- * rows below), [28] inverse factor and product.  Counts: [3] shader clock
+ * [22] final Cholesky QR, [23] Rayleigh-Ritz outside its Jacobi phases,
+ * [24] vectors and residual check, [25] hops by Cholesky QR, and inside
+ * every Cholesky-QR pass [26] Gram matrix, [27] the sum of its parts and
+ * the Cholesky factorisation (inside it [29] updates, [30] diagonal blocks,
+ * [31] rows below), [28] inverse factor and product.  Counts: [3] shader clock
  * cycles, [4] pair tasks, [7] launches, [12] pair tasks that rotated, [15]
  * Cholesky-QR passes.  out_us has 32 entries.  Synchronises. */
 int lmpo_svd_profile(lmpo_state *s, double out_us[32]);

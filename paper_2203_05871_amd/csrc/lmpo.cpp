@@ -824,11 +824,12 @@ int lmpo_create(const lmpo_model *model, const lmpo_options *opt, const char *in
   S->opt = *opt;
   if (opt->precision == LMPO_FP32_CONTRACT) {
     // the contraction hands the SVD a block rounded to FP32 (relative error
-    // about 6e-8); the FP64 SVD resolves it to about 1e-9, two orders below
-    // that, instead of to FP64 round-off: looser Jacobi and Ritz thresholds,
-    // fewer subspace iterations
+    // about 6e-8): the FP64 SVD resolves it to just below that instead of to
+    // FP64 round-off.  Jacobi stops at about 1e-9 (relative off-diagonal
+    // size), the subspace SVD accepts Ritz residuals up to 1e-8 of the
+    // largest singular value and starts with two iterations.
     S->tol_factor = kFp32TolFactor;
-    S->rsi_tol = 1e-9;
+    S->rsi_tol = 1e-8;
     S->rsi_iters = 2;
   }
   S->chain = is_chain(model);
