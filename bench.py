@@ -278,25 +278,35 @@ def batched_leg(args):
                         "flops_per_launch": flops / max(1, launches)}}
     log(f"batched: {K} steps in {dt:.2f} s (sequential {dseq:.1f} s)")
     if not args.no_cpu:
+        from threadpoolctl import threadpool_limits
+
         from oracle import tebd
 
-        t0 = time.perf_counter()
-        done, worst = 0, 0.0
-        for c, m in enumerate(models):
-            mps = tebd.MPS.product(run["init"], m["N"])
-            gates = tebd.gate_tables(m, run["tau"])
-            tebd.evolve(mps, m, run["tau"], K, run["chi_max"], run["cutoff"], gates=gates)
-            z1, z2 = tebd.zz_observables(mps)
-            worst = max(worst, float(np.abs(np.concatenate([z1, z2]) - obs[c]).max()))
-            done += 1
-            if time.perf_counter() - t0 > args.cpu_budget / 2:
-                break
-        dto = time.perf_counter() - t0
-        frac = sum(m["N"] for m in models[:done]) / sum(m["N"] for m in models)
-        out["cpu_baseline"] = {"value": K * frac / dto, "unit": "steps/s", "cores": blas_threads(),
+        def oracle_chains(budget):
+            t0 = time.perf_counter()
+            done, worst = 0, 0.0
+            for c, m in enumerate(models):
+                mps = tebd.MPS.product(run["init"], m["N"])
+                gates = tebd.gate_tables(m, run["tau"])
+                tebd.evolve(mps, m, run["tau"], K, run["chi_max"], run["cutoff"], gates=gates)
+                z1, z2 = tebd.zz_observables(mps)
+                worst = max(worst, float(np.abs(np.concatenate([z1, z2]) - obs[c]).max()))
+                done += 1
+                if time.perf_counter() - t0 > budget:
+                    break
+            dto = time.perf_counter() - t0
+            frac = sum(m["N"] for m in models[:done]) / sum(m["N"] for m in models)
+            return done, K * frac / dto, worst
+
+        done, rate, worst = oracle_chains(args.cpu_budget / 2)
+        out["cpu_baseline"] = {"value": rate, "unit": "steps/s", "cores": blas_threads(),
                                "kind": "oracle", "sample": f"first {done} of {len(models)} chains, all {K} steps; "
                                                            f"batch rate scaled by their share of the sites"}
         out["obs_err_vs_oracle_sampled"] = worst
+        with threadpool_limits(limits=1):
+            done1, rate1, _ = oracle_chains(args.cpu_budget / 4)
+        out["cpu_baseline_1thread"] = {"value": rate1, "unit": "steps/s", "cores": 1, "kind": "oracle",
+                                       "sample": f"first {done1} chains, all {K} steps, one BLAS thread"}
     return out
 
 
@@ -400,6 +410,15 @@ def gradient_leg(args):
         out["cpu_baseline"] = {"value": n / to, "unit": "gradient steps/s (forward + backward)",
                                "cores": blas_threads(), "kind": "oracle",
                                "sample": f"the gradient of <s^z_15> after the first {n} of the 40 steps"}
+        from threadpoolctl import threadpool_limits
+
+        with threadpool_limits(limits=1):
+            t0 = time.perf_counter()
+            adjoint.gradient(m, tau, n, chi, cut, init, 15, "Z")
+            to1 = time.perf_counter() - t0
+        out["cpu_baseline_1thread"] = {"value": n / to1, "unit": "gradient steps/s (forward + backward)",
+                                       "cores": 1, "kind": "oracle",
+                                       "sample": f"the same gradient, one BLAS thread"}
         out["gpu_same_sample"] = {"value": n / tg1, "unit": "gradient steps/s (forward + backward)",
                                   "seconds": tg1}
         log(f"gradient vs oracle at {n} steps: {gp}")
@@ -518,7 +537,10 @@ def main():
         line["cpu_baseline"] = {"value": done / dt, "unit": "steps/s", "cores": blas_threads(), "kind": "oracle",
                                 "sample": "one oracle step whose interior bonds sit at chi=256 (its own +x run with "
                                           "cutoff 0: step 3 timed after 2 untimed), FP64 NumPy/LAPACK"}
-        log(f"oracle at chi=256: {done} step in {dt:.1f} s")
+        d1, t1, _, _ = oracle_steps(model, run, 3, args.cpu_budget, cutoff=0.0, first_timed=2, threads=1)
+        line["cpu_baseline_1thread"] = {"value": d1 / t1, "unit": "steps/s", "cores": 1, "kind": "oracle",
+                                        "sample": "the same oracle step, one BLAS thread"}
+        log(f"oracle at chi=256: {done} step in {dt:.1f} s ({t1:.1f} s on one thread)")
     if not args.no_configured:
         # the configured trajectory: 50 steps from +x at tau 0.05 (chi stays below 256)
         ks = run["steps"]
