@@ -90,11 +90,13 @@ __device__ void gemm(SharedGemm &sh, int M, int N, int K, const double2 *__restr
     const int i0 = (tile % tm) * kTile, j0 = (tile / tm) * kTile;
     if (lower_only && i0 + kTile <= j0) continue;
     const int kb = ks * kper, ke = min(K, kb + kper);
-    d4v cr[2][2], ci[2][2];
+    // complex products with three real MFMAs (Gauss): t1 = a.x b.x, t2 = a.y b.y,
+    // t3 = (a.x + a.y)(b.x + b.y); real part t1 - t2, imaginary t3 - t1 - t2
+    d4v t1[2][2], t2[2][2], t3[2][2];
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
-      for (int y = 0; y < 2; ++y) cr[x][y] = ci[x][y] = d4v{0, 0, 0, 0};
+      for (int y = 0; y < 2; ++y) t1[x][y] = t2[x][y] = t3[x][y] = d4v{0, 0, 0, 0};
     if (ke <= kb) {
       // an empty inner range (split beyond K): zero partial product
       double2 *Cs = C + (size_t)ks * cstride;
@@ -167,15 +169,19 @@ __device__ void gemm(SharedGemm &sh, int M, int N, int K, const double2 *__restr
         for (int x = 0; x < 2; ++x) a[x] = sh.As[buf][kk + lk][mo + 16 * x + lr];
 #pragma unroll
         for (int y = 0; y < 2; ++y) b[y] = sh.Bs[buf][kk + lk][no + 16 * y + lr];
+        double sa[2], sb[2];
+#pragma unroll
+        for (int x = 0; x < 2; ++x) sa[x] = a[x].x + a[x].y;
+#pragma unroll
+        for (int y = 0; y < 2; ++y) sb[y] = b[y].x + b[y].y;
 #pragma unroll
         for (int x = 0; x < 2; ++x)
 #pragma unroll
           for (int y = 0; y < 2; ++y) {
-            cr[x][y] = mma(a[x].x, b[y].x, cr[x][y]);
+            t1[x][y] = mma(a[x].x, b[y].x, t1[x][y]);
             if (!kReal) {
-              cr[x][y] = mma(-a[x].y, b[y].y, cr[x][y]);
-              ci[x][y] = mma(a[x].x, b[y].y, ci[x][y]);
-              ci[x][y] = mma(a[x].y, b[y].x, ci[x][y]);
+              t2[x][y] = mma(a[x].y, b[y].y, t2[x][y]);
+              t3[x][y] = mma(sa[x], sb[y], t3[x][y]);
             }
           }
       }
@@ -197,8 +203,11 @@ __device__ void gemm(SharedGemm &sh, int M, int N, int K, const double2 *__restr
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int m = i0 + mo + 16 * x + lk + 4 * r;
-            if (m < M)
-              gst(Cs, (size_t)m + (size_t)n * ldc, make_double2(cr[x][y][r] * sc, kReal ? 0.0 : ci[x][y][r] * sc));
+            if (m < M) {
+              const double re = kReal ? t1[x][y][r] : t1[x][y][r] - t2[x][y][r];
+              const double im = kReal ? 0.0 : t3[x][y][r] - t1[x][y][r] - t2[x][y][r];
+              gst(Cs, (size_t)m + (size_t)n * ldc, make_double2(re * sc, im * sc));
+            }
           }
       }
     }
@@ -330,7 +339,9 @@ __device__ bool cholesky(SharedChol &sh, int p, const double2 *__restrict__ Gm, 
     const int nb = min(kPanel, p - j0), rows = p - j0;
     for (int blk = wave; 16 * blk < rows; blk += 4) {
       const int ia = j0 + 16 * blk + lr;  // the lane's row of A (it supplies A[lr][lk])
-      d4v cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+      // a conj(b) with three real products (Gauss): t1 = a.x b.x, t2 = a.y b.y,
+      // t3 = (a.x + a.y)(b.x - b.y); real part t1 + t2, imaginary t3 - t1 + t2
+      d4v t1 = {0, 0, 0, 0}, t2 = {0, 0, 0, 0}, t3 = {0, 0, 0, 0};
       double2 a[4], b[4], an[4], bn[4];
       // (k < j0 always holds; rows are clamped into L: a clamped row or column
       // only feeds outputs that are not stored, so loads need no mask)
@@ -338,30 +349,33 @@ __device__ bool cholesky(SharedChol &sh, int p, const double2 *__restrict__ Gm, 
       auto load = [&](int k0, double2 *ax, double2 *bx) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int k = k0 + 4 * q + lk;
+          const int k = min(k0 + 4 * q + lk, p - 1);  // (clamped: a load past j0 is never used)
           ax[q] = gld(L, (size_t)iac + (size_t)k * p);
           bx[q] = gld(L, (size_t)ibc + (size_t)k * p);  // B[lk][lr] = conj(L[j0 + lr][k])
         }
       };
-      if (j0 > 0) load(0, a, b);
-      for (int k0 = 0; k0 < j0; k0 += 16) {
-        if (k0 + 16 < j0) load(k0 + 16, an, bn);
-        // a conj(b) = (a.x b.x + a.y b.y) + i (a.y b.x - a.x b.y)
+      auto step = [&](const double2 *ax, const double2 *bx) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-          cr = mma(a[q].x, b[q].x, cr);
+          t1 = mma(ax[q].x, bx[q].x, t1);
           if (!kReal) {
-            cr = mma(a[q].y, b[q].y, cr);
-            ci = mma(a[q].y, b[q].x, ci);
-            ci = mma(-a[q].x, b[q].y, ci);
+            t2 = mma(ax[q].y, bx[q].y, t2);
+            t3 = mma(ax[q].x + ax[q].y, bx[q].x - bx[q].y, t3);
           }
         }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          a[q] = an[q];
-          b[q] = bn[q];
-        }
+      };
+      // two register sets used in turn, every load issued unconditionally (no
+      // copies and no branch between them, so the wait before a step covers
+      // only that step's loads, not the next step's)
+      if (j0 > 0) load(0, a, b);
+      int k0 = 0;
+      for (; k0 + 16 < j0; k0 += 32) {
+        load(k0 + 16, an, bn);
+        step(a, b);
+        load(k0 + 32, a, b);
+        step(an, bn);
       }
+      if (k0 < j0) step(a, b);
       // P[i][c] = G[j0 + i][j0 + c] - update; lane holds D[lk + 4 r][lr]
       if (lr < nb) {
 #pragma unroll
@@ -375,7 +389,8 @@ __device__ bool cholesky(SharedChol &sh, int p, const double2 *__restrict__ Gm, 
               g.x += h.x;
               g.y += h.y;
             }
-            sh.P[lr][i] = make_double2(g.x - cr[r], kReal ? 0.0 : g.y - ci[r]);
+            sh.P[lr][i] = kReal ? make_double2(g.x - t1[r], 0.0)
+                                : make_double2(g.x - (t1[r] + t2[r]), g.y - (t3[r] - t1[r] + t2[r]));
           }
         }
       }
