@@ -80,7 +80,8 @@ def one_gate_parity(Chain, dims, bond, chi_max, cutoff, seed, decay=0.0, asc=Tru
 @pytest.mark.parametrize("decay", [0.0, 0.02])
 def test_full_size_gate_1024(Chain, decay, subspace):
     """One gate on a 1024 x 1024 block, by the full SVD (all 1024 singular
-    values) and by the subspace SVD (the 320 Ritz values of its subspace)."""
+    values) and by the subspace SVD with its defaults (the Ritz values of its
+    p = min(256, 256 + 32) + 48 = 304 vectors)."""
     dims = [4, 16, 64, 256, 256, 256, 64, 16, 4]  # N = 10; bond 4 joins two chi = 256 bonds
     print(f"case: 1024 x 1024 gate, decay {decay}, subspace {subspace}", flush=True)
     ch, ref, sv, kept, kk, s = one_gate_parity(Chain, dims, 4, 256, 1e-10, 3, decay, subspace=subspace)
@@ -89,7 +90,7 @@ def test_full_size_gate_1024(Chain, decay, subspace):
     acc, fell, _ = ch.svd_subspace_stats()
     if subspace and decay == 0.0:
         # a Gaussian centre: the gate block has a gap at the bond's 256
-        assert (acc, fell) == (1, 0) and len(sv) == 320
+        assert (acc, fell) == (1, 0) and len(sv) == 304
     if subspace and acc:
         # the kept Ritz values; the first discarded one (a Ritz value from
         # below, accurate to the residual of its unconverged vector) loosely
