@@ -320,6 +320,40 @@ def forty(m, gr):
                            [np.real(np.sum(gr["g0"]))]])
 
 
+def costate_convergence(m, run, chis=(64, 128, 256)):
+    """How far the co-state's truncation moves the gradient: both ladder
+    objectives with the co-state's chi_max at 64, 128 (the configured value)
+    and 256, the largest change of any of the 140 derivatives between
+    successive co-state chi_max, absolute and relative to the largest."""
+    import numpy as np
+
+    from paper_2203_05871_amd import Chain, Gradient
+
+    tau, steps, chi, cut, init = run["tau"], run["steps"], run["chi_max"], run["cutoff"], run["init"]
+    out, prev = {}, {}
+    for cchi in chis:
+        for name in ("z15", "connected_z0_z15"):
+            c = Chain(m, tau, chi, cut, "fp64", init)
+            G = Gradient(c, steps, costate_chi_max=cchi)
+            t0 = time.perf_counter()
+            F, g = G.run(15, "Z") if name == "z15" else G.run_connected(0, 15, "ZZ")
+            dt = time.perf_counter() - t0
+            dims = G.costate_dims()
+            G.close()
+            c.close()
+            v = np.concatenate([np.real(g[k]) for k in g if k != "tau"])
+            rec = {"seconds": dt, "max_abs_derivative": float(np.abs(v).max()),
+                   "costate_bond_dims_t0": [int(x) for x in dims]}
+            if name in prev:
+                d = float(np.abs(v - prev[name]).max())
+                rec["max_abs_change_from_previous_chi"] = d
+                rec["change_over_largest"] = d / float(np.abs(v).max())
+            prev[name] = v
+            out.setdefault(name, {})[str(cchi)] = rec
+            log(f"co-state chi {cchi}, {name}: {dt:.1f} s")
+    return out
+
+
 def gradient_leg(args):
     """Adjoint gradients on the 2 x 8 ladder (N=16, 8 rungs and 14 legs through
     the SWAP network), chi_max 128, cutoff 1e-12, tau 0.05, 40 steps from +z:
@@ -361,6 +395,7 @@ def gradient_leg(args):
     G.close()
     c.close()
     log(f"gradient: {tg:.1f} s vs forward {tf:.2f} s")
+    conv = costate_convergence(m, run) if args.costate_convergence else None
     out = {"workload": "2x8 ladder (N=16, 8 rungs + 14 legs via SWAP gates), chi_max=128, cutoff=1e-12, tau=0.05, "
                        "40 steps from +z; F = <sigma^z_15>(T); co-state with the same chi_max and cutoff",
            "parameters": int(sum(len(v) for k, v in g.items() if k != "tau")), "F": F.real,
@@ -376,6 +411,8 @@ def gradient_leg(args):
                         "traffic": None, "launches": launches, "avg_launch_ms": co_ms / max(1, launches),
                         "flops_per_launch": co_flops / max(1, launches), "kernel_share_of_gradient": co_ms * 1e-3 / tg},
            "derivatives_40": [float(x) for x in forty(m, g)]}
+    if conv is not None:
+        out["costate_chi_convergence"] = conv
     if not args.no_cpu:
         from oracle import adjoint
 
@@ -438,6 +475,9 @@ def main():
     ap.add_argument("--no-configured", action="store_true", help="skip the configured 50-step run from +x")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--no-gradient", action="store_true")
+    ap.add_argument("--costate-convergence", action="store_true",
+                    help="add to the gradient object both ladder objectives at co-state chi_max 64, 128, 256 "
+                         "(about 5 minutes)")
     ap.add_argument("--headline-only", action="store_true", help="only the settle and the timed chi=256 steps")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also run one plain device-to-device copy of MIB MiB (the calibration kernel of "
