@@ -315,9 +315,9 @@ __device__ __noinline__ void factor_diag_block(SharedChol &sh, int nb, int j0, i
 // wavefront brings its 16-row blocks of the block column up to date against
 // the factor's earlier columns on the matrix cores (operands straight from
 // the cache, the next four inner steps loaded while the present four are
-// multiplied), then wavefront 0 factors the 16 x 16 diagonal block and
-// inverts it in registers, and the rows below are that block's inverse
-// applied on the matrix cores.  Ldinv receives the inverses of the diagonal
+// multiplied; complex products as three real MFMAs), then wavefront 0
+// factors the 16 x 16 diagonal block and inverts it (factor_diag_block), and
+// the rows below are that block's inverse applied on the matrix cores.  Ldinv receives the inverses of the diagonal
 // blocks (16 x 16 each, column-major).  Returns false when a pivot is not
 // positive and finite.
 template <bool kReal>
