@@ -282,7 +282,7 @@ int lmpo_set_svd_tolerance(lmpo_state *s, double factor);
  * all at most), and if that still fails the full SVD of the block is taken
  * instead.  The squared weight outside the subspace, ||theta||_F^2 -
  * sum_j s_j^2, counts as discarded.  Defaults: min_cols 512, margin 48, grow
- * 32, iterations 4, tol 2e-14 (the FP32-contraction form: iterations 2, tol
+ * 32, iterations 4, tol 1e-12 (the FP32-contraction form: iterations 2, tol
  * 1e-8, below the FP32 rounding of its block); min_cols <= 0 turns it off
  * (every block then takes the full SVD).  margin must lie in [16, 128],
  * iterations in [1, 64], tol in (0, 1). */

@@ -200,7 +200,7 @@ struct lmpo_state {
   // subspace-iteration truncated SVD of wide gate blocks (see SvdLaunch)
   int rsi_pmax = 0;             // allocated subspace width (0: not available)
   int rsi_min_cols = 512, rsi_margin = 48, rsi_grow = 32, rsi_iters = 4;
-  double rsi_tol = 2e-14;
+  double rsi_tol = 1e-12;
   double2 *Vr = nullptr, *Zr = nullptr, *Wk = nullptr, *Gr = nullptr, *L1 = nullptr, *L2 = nullptr, *Li = nullptr, *Ldi = nullptr;
   double2 *Rb = nullptr, *Res = nullptr;
   double *rsi_scal = nullptr;

@@ -393,7 +393,7 @@ class Chain:
         """Jacobi stopping threshold in units of sqrt(C) eps (default 32)."""
         _check(self._lib.lmpo_set_svd_tolerance(self._h, float(factor)))
 
-    def set_svd_subspace(self, min_cols=512, margin=48, grow=32, iterations=4, tol=2e-14):
+    def set_svd_subspace(self, min_cols=512, margin=48, grow=32, iterations=4, tol=1e-12):
         """Truncated SVD of gate blocks with at least min_cols columns on a
         subspace (min_cols <= 0: every block takes the full SVD)."""
         _check(self._lib.lmpo_set_svd_subspace(self._h, int(min_cols), int(margin), int(grow), int(iterations),
