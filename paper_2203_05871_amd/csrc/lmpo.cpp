@@ -54,7 +54,7 @@ constexpr int kMaxSweeps = 80;
 //  subspace SVDs handed to the full SVD, subspace iterations]
 constexpr int kStats = 8;
 constexpr int kRsiMarginMax = 128;  // largest margin the subspace buffers allow
-constexpr double kFp32TolFactor = 1e5;  // Jacobi threshold of the FP32-contraction form, units of sqrt(C) eps
+constexpr double kFp32TolFactor = 1e6;  // Jacobi threshold of the FP32-contraction form, units of sqrt(C) eps
 constexpr size_t kGramSplitHost = 8;  // partial Gram matrices (rsi::kGramSplit)
 constexpr int kRsiMaxWidth = 384;   // largest subspace (the triangular solve keeps 16 x p in LDS)
 
@@ -825,9 +825,10 @@ int lmpo_create(const lmpo_model *model, const lmpo_options *opt, const char *in
   if (opt->precision == LMPO_FP32_CONTRACT) {
     // the contraction hands the SVD a block rounded to FP32 (relative error
     // about 6e-8): the FP64 SVD resolves it to just below that instead of to
-    // FP64 round-off.  Jacobi stops at about 1e-9 (relative off-diagonal
-    // size), the subspace SVD accepts Ritz residuals up to 1e-8 of the
-    // largest singular value and starts with two iterations.
+    // FP64 round-off.  Jacobi stops at a relative off-diagonal size of about
+    // 4e-9 (C = 304) to 7e-9 (C = 1024), the subspace SVD accepts Ritz
+    // residuals up to 1e-8 of the largest singular value and starts with two
+    // iterations.
     S->tol_factor = kFp32TolFactor;
     S->rsi_tol = 1e-8;
     S->rsi_iters = 2;

@@ -897,8 +897,9 @@ __device__ __forceinline__ bool rsi_reject(const SvdLaunch &a, int rank) {
 // alternate Z = orth(X V), V = orth(X^H Z); then X V = Q T (Cholesky QR
 // twice), one-sided Jacobi on T^H gives T = W S U^H, and X ~ (Q W) S (V U)^H
 // on the subspace.  The kept Ritz triplets are accepted when every residual
-// ||X^H u_j - s_j v_j|| is below rsi_tol s_1 (else two more iterations, then
-// the full SVD takes over: X is never modified here).  Squared weight outside
+// ||X^H u_j - s_j v_j|| is below rsi_tol s_1; else, once, the iteration goes
+// on for as many steps as the residual's rate of decrease needs, and if that
+// fails too the full SVD takes over (X is never modified here).  Squared weight outside
 // the subspace, ||X||^2 - sum_j s_j^2, joins the tail sums of the truncation
 // rule.  Returns true when the gate is complete (canonical update written).
 template <bool kReal>
