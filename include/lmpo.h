@@ -271,8 +271,9 @@ int lmpo_set_svd_tolerance(lmpo_state *s, double factor);
  * the kept singular triplets, at most max_dim_rho of them, and the discarded
  * weight enter the step).  A gate block with at least min_cols columns is
  * decomposed by subspace iteration: p = min(chi_max, chi + grow) + margin
- * vectors (chi the bond's dimension before the gate, p rounded up to 16 and
- * at most 3/4 of the columns), `iterations` multiplications by the block and
+ * vectors (chi the bond's dimension before the gate, p rounded up to 16, at
+ * most 3/4 of the columns and at most 384; a block whose min(chi_max, chi +
+ * grow) + 16 exceeds 384 takes the full SVD), `iterations` multiplications by the block and
  * its adjoint with Cholesky-QR orthonormalisation, then the exact SVD of the
  * block restricted to the subspace (Rayleigh-Ritz, block Jacobi on a p x p
  * factor).  The kept triplets are accepted when each residual

@@ -766,9 +766,14 @@ __device__ __noinline__ int jacobi_run(const SvdLaunch &a, Barrier &bar, SharedA
 // whose bond held chm before the gate (0: run the full SVD).
 __device__ __forceinline__ int rsi_width(const SvdLaunch &a, int C, int chm) {
   if (a.rsi_pmax <= 0 || C < a.rsi_min_cols) return 0;
-  int want = min(a.chi_max, chm + a.rsi_grow) + a.rsi_margin;
-  want = (want + 15) & ~15;
-  if (want > a.rsi_pmax) want = a.rsi_pmax;
+  const int keep = min(a.chi_max, chm + a.rsi_grow);  // the kept vectors the bond is expected to need
+  int want = (keep + a.rsi_margin + 15) & ~15;
+  if (want > a.rsi_pmax) {
+    // a capped subspace must still hold them and the 16 beyond the cut that
+    // acceptance asks for, else the attempt could only fail
+    if (a.rsi_pmax < keep + 16) return 0;
+    want = a.rsi_pmax;
+  }
   if (4 * want > 3 * C) return 0;
   return want;
 }
