@@ -127,6 +127,34 @@ def test_chi256_step_against_oracle(Chain):
     ch.close()
 
 
+def test_chi256_step_fp32_form_against_oracle(Chain):
+    """The same chi = 256 step in the FP32-contraction form (its own subspace
+    settings: two starting iterations, Ritz bound 1e-8) against the FP64
+    oracle: observables within 1e-5, the subspace path taken."""
+    from test_gpu_fullsize import random_canonical_mps, inject
+
+    dims = [4, 16, 64, 256, 256, 256, 256, 256, 64, 16, 4]
+    N = len(dims) + 1
+    m = workloads.jittered_chain(N, 7)
+    A = random_canonical_mps(dims, 0, 7)
+    print("case: N=12 random chi 256 state, one step, FP32-contraction form", flush=True)
+    ch = Chain(m, 0.05, 256, 1e-10, "fp32", "+z")
+    inject(ch, A, 0)
+    ref = tebd.MPS(tebd.from_pauli(A), centre=0)
+    ch.evolve(1)
+    tebd.evolve(ref, m, 0.05, 1, 256, 1e-10, first_step=0)
+    acc, fell, iters = ch.svd_subspace_stats()
+    z1, z2 = ch.zz_observables()
+    r1, r2 = tebd.zz_observables(ref)
+    err = max(np.abs(z1 - r1).max(), np.abs(z2 - r2).max())
+    print(f"  max |obs - oracle| = {err:.2e}; dims {ch.bond_dims()} (oracle {ref.bond_dims()}); accepted {acc}, "
+          f"fallbacks {fell}, iterations {iters}", flush=True)
+    assert err < 1e-5
+    assert acc >= 4
+    assert max(abs(a - b) for a, b in zip(ch.bond_dims(), ref.bond_dims())) <= 2
+    ch.close()
+
+
 def test_rejected_subspace_falls_back_bit_identically(Chain):
     """With an unreachable residual bound every subspace result is rejected
     and the full SVD takes the untouched block: the run is bit-identical to
