@@ -88,7 +88,7 @@ def chain_from(model, run, precision, state):
 
 # phase timers of the SVD kernel's first workgroup (lmpo_svd_profile), reported per step
 PHASES = ("pairs", "wait", "sub_iterations", "sub_final_cholqr", "sub_vectors", "hop_cholqr", "cholqr_gram",
-          "cholqr_cholesky", "cholqr_solve", "chol_update", "chol_diag", "chol_rows")
+          "cholqr_cholesky", "cholqr_solve", "chol_diag_lookahead", "chol_last_step", "chol_rows")
 
 
 def timed(ch, steps):

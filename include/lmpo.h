@@ -307,8 +307,9 @@ int lmpo_svd_stats(lmpo_state *s, int32_t out[4]);
  * [22] final Cholesky QR, [23] Rayleigh-Ritz outside its Jacobi phases,
  * [24] vectors and residual check, [25] hops by Cholesky QR, and inside
  * every Cholesky-QR pass [26] Gram matrix, [27] the sum of its parts and
- * the Cholesky factorisation (inside it [29] updates, [30] diagonal blocks,
- * [31] rows below), [28] inverse factor and product.  Counts: [3] shader clock
+ * the Cholesky factorisation (inside it [29] diagonal blocks with the next
+ * panel's update beside them, [30] the next panel's last update step, [31]
+ * rows below), [28] inverse factor and product.  Counts: [3] shader clock
  * cycles, [4] pair tasks, [7] launches, [12] pair tasks that rotated, [15]
  * Cholesky-QR passes.  out_us has 32 entries.  Synchronises. */
 int lmpo_svd_profile(lmpo_state *s, double out_us[32]);

@@ -55,6 +55,7 @@ struct SharedChol {
   double2 Ld[kPanel][kPanel + 1];    // diagonal block of the factor
   double2 Mi[kPanel][kPanel + 1];    // its inverse (or a 16 x 16 right-hand side)
   int fail;
+  int next;  // next row block of the look-ahead update
 };
 
 // Operand access: op 0 = as stored (column-major, element (i, j) at
@@ -311,22 +312,29 @@ __device__ __noinline__ void factor_diag_block(SharedChol &sh, int nb, int j0, i
 // Cholesky factorisation G = L L^H of the Hermitian p x p matrix G (the sum
 // of nsplit partial matrices G + s * gstride; lower triangle read,
 // column-major, ld p) by one workgroup: L (ld p) receives the factor with
-// zeros above the diagonal.  Left-looking in blocks of 16 columns: each
-// wavefront brings its 16-row blocks of the block column up to date against
-// the factor's earlier columns on the matrix cores (operands straight from
-// the cache, the next four inner steps loaded while the present four are
-// multiplied; complex products as three real MFMAs), then wavefront 0
-// factors the 16 x 16 diagonal block and inverts it (factor_diag_block), and
-// the rows below are that block's inverse applied on the matrix cores.  Ldinv receives the inverses of the diagonal
-// blocks (16 x 16 each, column-major).  Returns false when a pivot is not
-// positive and finite.
+// zeros above the diagonal.  Left-looking in blocks of 16 columns with one
+// block of look-ahead: while wavefront 0 factors the diagonal block of panel
+// n and inverts it (factor_diag_block), the wavefronts (wavefront 0 once done,
+// row blocks handed out through an LDS counter) bring panel n + 1 up to date
+// against every finished column but panel n's, on the matrix cores (operands
+// straight from the cache, the next four inner steps loaded while the present
+// four are multiplied; complex products as three real MFMAs), and leave
+// G - that sum in L's columns of panel n + 1; then the rows below panel n's
+// diagonal block are that block's inverse applied on the matrix cores, and
+// panel n + 1 takes panel n's columns as its last update step into LDS.
+// Ldinv receives the inverses of the diagonal blocks (16 x 16 each,
+// column-major).  Returns false when a pivot is not positive and finite.
 template <bool kReal>
 __device__ bool cholesky(SharedChol &sh, int p, const double2 *__restrict__ Gm, int nsplit, size_t gstride,
                          double2 *__restrict__ L, double2 *__restrict__ Ldinv, unsigned long long *tp = nullptr) {
   const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
   const int lr = lane & 15, lk = lane >> 4;
-  if (t == 0) sh.fail = 0;
-  // phase timers (thread 0, when tp is set): [29] updates, [30] diagonal blocks, [31] rows below
+  if (t == 0) {
+    sh.fail = 0;
+    sh.next = 0;
+  }
+  // phase timers (thread 0, when tp is set): [29] diagonal block beside the
+  // next panel's update, [30] the next panel's last update step, [31] rows below
   unsigned long long tm = tp && t == 0 ? (unsigned long long)wall_clock64() : 0ull;
   auto lap = [&](int slot) {
     if (tp && t == 0) {
@@ -335,82 +343,105 @@ __device__ bool cholesky(SharedChol &sh, int p, const double2 *__restrict__ Gm, 
       tm = now;
     }
   };
-  for (int j0 = 0; j0 < p; j0 += kPanel) {
-    const int nb = min(kPanel, p - j0), rows = p - j0;
-    for (int blk = wave; 16 * blk < rows; blk += 4) {
-      const int ia = j0 + 16 * blk + lr;  // the lane's row of A (it supplies A[lr][lk])
-      // a conj(b) with three real products (Gauss): t1 = a.x b.x, t2 = a.y b.y,
-      // t3 = (a.x + a.y)(b.x - b.y); real part t1 + t2, imaginary t3 - t1 + t2
-      d4v t1 = {0, 0, 0, 0}, t2 = {0, 0, 0, 0}, t3 = {0, 0, 0, 0};
-      double2 a[4], b[4], an[4], bn[4];
-      // (k < j0 always holds; rows are clamped into L: a clamped row or column
-      // only feeds outputs that are not stored, so loads need no mask)
-      const int iac = min(ia, p - 1), ibc = min(j0 + lr, p - 1);
-      auto load = [&](int k0, double2 *ax, double2 *bx) {
+  auto gsum = [&](size_t off) {
+    double2 g = gld(Gm, off);
+    for (int sp = 1; sp < nsplit; ++sp) {
+      const double2 h = gld(Gm, off + sp * gstride);
+      g.x += h.x;
+      g.y += h.y;
+    }
+    return g;
+  };
+  // t += L[jn + 16 blk + lr][k] conj(L[jn + lr][k]) over k in [klo, khi)
+  // (khi - klo a multiple of 16); lane ends with rows lk + 4 r, column lr
+  auto accumulate = [&](int jn, int blk, int klo, int khi, d4v &t1, d4v &t2, d4v &t3) {
+    const int iac = min(jn + 16 * blk + lr, p - 1), ibc = min(jn + lr, p - 1);
+    double2 a[4], b[4], an[4], bn[4];
+    auto load = [&](int k0, double2 *ax, double2 *bx) {
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int k = min(k0 + 4 * q + lk, p - 1);  // (clamped: a load past j0 is never used)
-          ax[q] = gld(L, (size_t)iac + (size_t)k * p);
-          bx[q] = gld(L, (size_t)ibc + (size_t)k * p);  // B[lk][lr] = conj(L[j0 + lr][k])
-        }
-      };
-      auto step = [&](const double2 *ax, const double2 *bx) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          t1 = mma(ax[q].x, bx[q].x, t1);
-          if (!kReal) {
-            t2 = mma(ax[q].y, bx[q].y, t2);
-            t3 = mma(ax[q].x + ax[q].y, bx[q].x - bx[q].y, t3);
-          }
-        }
-      };
-      // two register sets used in turn, every load issued unconditionally (no
-      // copies and no branch between them, so the wait before a step covers
-      // only that step's loads, not the next step's)
-      if (j0 > 0) load(0, a, b);
-      int k0 = 0;
-      for (; k0 + 16 < j0; k0 += 32) {
-        load(k0 + 16, an, bn);
-        step(a, b);
-        load(k0 + 32, a, b);
-        step(an, bn);
+      for (int q = 0; q < 4; ++q) {
+        const int k = min(k0 + 4 * q + lk, p - 1);
+        ax[q] = gld(L, (size_t)iac + (size_t)k * p);
+        bx[q] = gld(L, (size_t)ibc + (size_t)k * p);
       }
-      if (k0 < j0) step(a, b);
-      // P[i][c] = G[j0 + i][j0 + c] - update; lane holds D[lk + 4 r][lr]
-      if (lr < nb) {
+    };
+    auto step = [&](const double2 *ax, const double2 *bx) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        t1 = mma(ax[q].x, bx[q].x, t1);
+        if (!kReal) {
+          t2 = mma(ax[q].y, bx[q].y, t2);
+          t3 = mma(ax[q].x + ax[q].y, bx[q].x - bx[q].y, t3);
+        }
+      }
+    };
+    load(klo, a, b);
+    int k0 = klo;
+    for (; k0 + 16 < khi; k0 += 32) {
+      load(k0 + 16, an, bn);
+      step(a, b);
+      load(k0 + 32, a, b);
+      step(an, bn);
+    }
+    if (k0 < khi) step(a, b);
+  };
+  auto value = [&](const d4v &t1, const d4v &t2, const d4v &t3, int r, double2 g) {
+    return kReal ? make_double2(g.x - t1[r], 0.0)
+                 : make_double2(g.x - (t1[r] + t2[r]), g.y - (t3[r] - t1[r] + t2[r]));
+  };
+  // panel 0 is G itself
+  {
+    const int nb0 = min(kPanel, p);
+    for (int blk = wave; 16 * blk < p; blk += 4) {
+      if (lr < nb0) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int i = 16 * blk + lk + 4 * r;
-          if (i < rows) {
-            const size_t off = (size_t)(j0 + i) + (size_t)(j0 + lr) * p;
-            double2 g = gld(Gm, off);
-            for (int sp = 1; sp < nsplit; ++sp) {
-              const double2 h = gld(Gm, off + sp * gstride);
-              g.x += h.x;
-              g.y += h.y;
+          if (i < p) sh.P[lr][i] = gsum((size_t)i + (size_t)lr * p);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  for (int j0 = 0; j0 < p; j0 += kPanel) {
+    const int nb = min(kPanel, p - j0), rows = p - j0;
+    const int j1 = j0 + kPanel, rows1 = p - j1, nb1 = min(kPanel, rows1);
+    // wavefront 0 factors the diagonal block while the others (and wavefront 0
+    // once done) bring the next panel up to date with every finished column
+    // but this panel's, leaving G - that sum in L's next-panel columns
+    if (wave == 0) factor_diag_block<kReal>(sh, nb, j0, p, Ldinv);
+    if (rows1 > 0) {
+      for (;;) {
+        int bk = 0;
+        if (lane == 0) bk = atomicAdd(&sh.next, 1);
+        bk = __builtin_amdgcn_readfirstlane(bk);
+        if (16 * bk >= rows1) break;
+        d4v t1 = {0, 0, 0, 0}, t2 = {0, 0, 0, 0}, t3 = {0, 0, 0, 0};
+        if (j0 > 0) accumulate(j1, bk, 0, j0, t1, t2, t3);
+        if (lr < nb1) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = 16 * bk + lk + 4 * r;
+            if (i < rows1) {
+              const size_t off = (size_t)(j1 + i) + (size_t)(j1 + lr) * p;
+              gst(L, off, value(t1, t2, t3, r, gsum(off)));
             }
-            sh.P[lr][i] = kReal ? make_double2(g.x - t1[r], 0.0)
-                                : make_double2(g.x - (t1[r] + t2[r]), g.y - (t3[r] - t1[r] + t2[r]));
           }
         }
       }
     }
     __syncthreads();
     lap(29);
-    if (wave == 0) factor_diag_block<kReal>(sh, nb, j0, p, Ldinv);
-    __syncthreads();
-    lap(30);
     // rows below the diagonal block: L[j0 + 16 + i][j0 + c] = sum_k P[k][16 + i] conj(Mi[c][k])
-    // (the solve against the diagonal block as a product with its inverse)
     for (int blk = wave; 16 + 16 * blk < rows; blk += 4) {
       const int i0 = 16 + 16 * blk;
       d4v cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
 #pragma unroll
       for (int kk = 0; kk < kPanel; kk += 4) {
         const int k = kk + lk;
-        const double2 a = (i0 + lr < rows && k < nb) ? sh.P[k][i0 + lr] : make_double2(0, 0);  // A[lr][lk]
+        const double2 a = (i0 + lr < rows && k < nb) ? sh.P[k][i0 + lr] : make_double2(0, 0);
         const double2 m = (lr < nb && k < nb) ? sh.Mi[lr][k] : make_double2(0, 0);
-        const double2 b = make_double2(m.x, -m.y);                                             // B[lk][lr]
+        const double2 b = make_double2(m.x, -m.y);
         cr = mma(a.x, b.x, cr);
         if (!kReal) {
           cr = mma(-a.y, b.y, cr);
@@ -426,7 +457,6 @@ __device__ bool cholesky(SharedChol &sh, int p, const double2 *__restrict__ Gm, 
         }
       }
     }
-    // the diagonal block and the zeros above it
     for (int e = t; e < nb * (j0 + nb); e += kNT) {
       const int c = e / (j0 + nb), i = e % (j0 + nb);
       double2 v = make_double2(0, 0);
@@ -435,6 +465,23 @@ __device__ bool cholesky(SharedChol &sh, int p, const double2 *__restrict__ Gm, 
     }
     __syncthreads();
     lap(31);
+    // the next panel's last step: this panel's columns
+    if (rows1 > 0) {
+      for (int blk = wave; 16 * blk < rows1; blk += 4) {
+        d4v t1 = {0, 0, 0, 0}, t2 = {0, 0, 0, 0}, t3 = {0, 0, 0, 0};
+        accumulate(j1, blk, j0, j1, t1, t2, t3);
+        if (lr < nb1) {
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            const int i = 16 * blk + lk + 4 * r;
+            if (i < rows1) sh.P[lr][i] = value(t1, t2, t3, r, gld(L, (size_t)(j1 + i) + (size_t)(j1 + lr) * p));
+          }
+        }
+      }
+    }
+    if (t == 0) sh.next = 0;
+    __syncthreads();
+    lap(30);
   }
   return sh.fail == 0;
 }

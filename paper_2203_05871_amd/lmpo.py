@@ -379,7 +379,8 @@ class Chain:
         names = ["setup", "pairs", "wait", "cycles", "tasks", "select", "epilogue", "launches", "gram", "eig",
                  "upd_x", "upd_v", "rotated", "-", "-", "cholqr_passes", "order", "qr_panel", "qr_update", "form_q",
                  "sub_setup", "sub_iterations", "sub_final_cholqr", "sub_rr_rest", "sub_vectors", "hop_cholqr",
-                 "cholqr_gram", "cholqr_cholesky", "cholqr_solve", "chol_update", "chol_diag", "chol_rows"]
+                 "cholqr_gram", "cholqr_cholesky", "cholqr_solve", "chol_diag_lookahead", "chol_last_step",
+                 "chol_rows"]
         return dict(zip(names, out.tolist()))
 
     def profile_begin(self, max_launches=20000):
