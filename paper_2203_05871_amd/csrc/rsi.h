@@ -435,25 +435,26 @@ __device__ bool cholesky(SharedChol &sh, int p, const double2 *__restrict__ Gm, 
     // rows below the diagonal block: L[j0 + 16 + i][j0 + c] = sum_k P[k][16 + i] conj(Mi[c][k])
     for (int blk = wave; 16 + 16 * blk < rows; blk += 4) {
       const int i0 = 16 + 16 * blk;
-      d4v cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+      d4v t1 = {0, 0, 0, 0}, t2 = {0, 0, 0, 0}, t3 = {0, 0, 0, 0};
 #pragma unroll
       for (int kk = 0; kk < kPanel; kk += 4) {
         const int k = kk + lk;
         const double2 a = (i0 + lr < rows && k < nb) ? sh.P[k][i0 + lr] : make_double2(0, 0);
         const double2 m = (lr < nb && k < nb) ? sh.Mi[lr][k] : make_double2(0, 0);
         const double2 b = make_double2(m.x, -m.y);
-        cr = mma(a.x, b.x, cr);
+        t1 = mma(a.x, b.x, t1);
         if (!kReal) {
-          cr = mma(-a.y, b.y, cr);
-          ci = mma(a.x, b.y, ci);
-          ci = mma(a.y, b.x, ci);
+          t2 = mma(a.y, b.y, t2);
+          t3 = mma(a.x + a.y, b.x + b.y, t3);
         }
       }
       if (lr < nb) {
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const int i = i0 + lk + 4 * r;
-          if (i < rows) gst(L, (size_t)(j0 + i) + (size_t)(j0 + lr) * p, make_double2(cr[r], kReal ? 0.0 : ci[r]));
+          if (i < rows)
+            gst(L, (size_t)(j0 + i) + (size_t)(j0 + lr) * p,
+                kReal ? make_double2(t1[r], 0.0) : make_double2(t1[r] - t2[r], t3[r] - t1[r] - t2[r]));
         }
       }
     }
@@ -505,9 +506,19 @@ __device__ void tri_inverse(SharedChol &sh, int p, const double2 *__restrict__ L
     // sh.P[c][i]: M[J0 + i][J0 + c]
     for (int I = J; I < nblk; ++I) {
       const int I0 = I * kPanel, ni = min(kPanel, p - I0);
+      // wavefront 0's operand of the last product, L_II^{-1}, loaded now so
+      // that its latency overlaps the partial products
+      double2 dv[4];
+      if (wave == 0) {
+        const double2 *Di = Ldinv + (size_t)I * kPanel * kPanel;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) dv[q] = gld(Di, lr + (4 * q + lk) * kPanel);
+      }
       __syncthreads();
       if (I > J) {
-        d4v cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+        // complex products with three real MFMAs (Gauss): real t1 - t2,
+        // imaginary t3 - t1 - t2
+        d4v t1 = {0, 0, 0, 0}, t2 = {0, 0, 0, 0}, t3 = {0, 0, 0, 0};
         // wave w takes the 16-wide inner slices w, w + 4, ... (four steps of
         // four, their loads issued together)
         for (int k0 = J0 + 16 * wave; k0 < I0; k0 += 64) {
@@ -520,16 +531,17 @@ __device__ void tri_inverse(SharedChol &sh, int p, const double2 *__restrict__ L
 #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const double2 b = sh.P[lr][k0 + 4 * q + lk - J0];  // B[lk][lr] = M[k][J0 + lr]
-            cr = mma(a[q].x, b.x, cr);
+            t1 = mma(a[q].x, b.x, t1);
             if (!kReal) {
-              cr = mma(-a[q].y, b.y, cr);
-              ci = mma(a[q].x, b.y, ci);
-              ci = mma(a[q].y, b.x, ci);
+              t2 = mma(a[q].y, b.y, t2);
+              t3 = mma(a[q].x + a[q].y, b.x + b.y, t3);
             }
           }
         }
 #pragma unroll
-        for (int r = 0; r < 4; ++r) sh.part[wave][lk + 4 * r][lr] = make_double2(cr[r], ci[r]);
+        for (int r = 0; r < 4; ++r)
+          sh.part[wave][lk + 4 * r][lr] = kReal ? make_double2(t1[r], 0.0)
+                                                : make_double2(t1[r] - t2[r], t3[r] - t1[r] - t2[r]);
         __syncthreads();
       }
       {
@@ -548,26 +560,25 @@ __device__ void tri_inverse(SharedChol &sh, int p, const double2 *__restrict__ L
       __syncthreads();
       if (wave == 0) {
         // M[I][J] = L_II^{-1} rhs
-        const double2 *Di = Ldinv + (size_t)I * kPanel * kPanel;
-        d4v cr = {0, 0, 0, 0}, ci = {0, 0, 0, 0};
+        d4v t1 = {0, 0, 0, 0}, t2 = {0, 0, 0, 0}, t3 = {0, 0, 0, 0};
 #pragma unroll
-        for (int kk = 0; kk < kPanel; kk += 4) {
-          const int k = kk + lk;
-          const double2 dv = gld(Di, lr + k * kPanel);
-          const double2 a = (lr < ni && k < ni) ? dv : make_double2(0, 0);  // A[lr][lk]
-          const double2 b = sh.Ld[k][lr];                                                    // B[lk][lr]
-          cr = mma(a.x, b.x, cr);
+        for (int q = 0; q < 4; ++q) {
+          const int k = 4 * q + lk;
+          const double2 a = (lr < ni && k < ni) ? dv[q] : make_double2(0, 0);  // A[lr][lk]
+          const double2 b = sh.Ld[k][lr];                                      // B[lk][lr]
+          t1 = mma(a.x, b.x, t1);
           if (!kReal) {
-            cr = mma(-a.y, b.y, cr);
-            ci = mma(a.x, b.y, ci);
-            ci = mma(a.y, b.x, ci);
+            t2 = mma(a.y, b.y, t2);
+            t3 = mma(a.x + a.y, b.x + b.y, t3);
           }
         }
         if (lr < nj) {
 #pragma unroll
           for (int r = 0; r < 4; ++r) {
             const int row = lk + 4 * r;
-            if (row < ni) sh.P[lr][I0 - J0 + row] = make_double2(cr[r], kReal ? 0.0 : ci[r]);
+            if (row < ni)
+              sh.P[lr][I0 - J0 + row] = kReal ? make_double2(t1[r], 0.0)
+                                              : make_double2(t1[r] - t2[r], t3[r] - t1[r] - t2[r]);
           }
         }
       }
