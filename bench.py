@@ -254,29 +254,34 @@ def batched_leg(args):
     b.close()
     for c in chains:
         c.close()
-    chains = make()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for c in chains:
-        c.evolve(K)
-    for c in chains:
-        c.sync()
-    torch.cuda.synchronize()
-    dseq = time.perf_counter() - t0
-    seq_obs = [zz(c) for c in chains]
-    for c in chains:
-        c.close()
     achieved = flops / (ms * 1e-3) / 1e12
     out = {"workload": f"64 chains, N~U{{8..24}}, Omega~U[0.5,2], Delta~U[2,8], chi_max=64, cutoff=1e-12, "
                        f"tau=0.05, {K} steps from {run['init']} (FP64)",
-           "steps_per_s": K / dt, "seconds": dt, "max_chi_reached": int(max_chi), "workgroups": int(plan.sum()),
-           "sequential_single_chain_steps_per_s": K / dseq, "speedup_vs_sequential": dseq / dt,
-           "batch_vs_sequential_max_obs_diff": float(max(np.abs(x - y).max() for x, y in zip(obs, seq_obs))),
+           "steps_per_s": K / dt, "seconds": dt, "max_chi_reached": int(max_chi), "workgroups": int(plan.sum())}
+    if not getattr(args, "no_sequential", False):
+        chains = make()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for c in chains:
+            c.evolve(K)
+        for c in chains:
+            c.sync()
+        torch.cuda.synchronize()
+        dseq = time.perf_counter() - t0
+        seq_obs = [zz(c) for c in chains]
+        for c in chains:
+            c.close()
+        out.update({"sequential_single_chain_steps_per_s": K / dseq, "speedup_vs_sequential": dseq / dt,
+                    "batch_vs_sequential_max_obs_diff": float(max(np.abs(x - y).max()
+                                                                  for x, y in zip(obs, seq_obs)))})
+        log(f"batched: {K} steps in {dt:.2f} s (sequential {dseq:.1f} s)")
+    else:
+        log(f"batched: {K} steps in {dt:.2f} s")
+    out.update({
            "roofline": {"bound": "mfma", "kernel": "batch_layer_kernel", "achieved": achieved,
                         "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": achieved / FP64_PEAK_TFLOPS,
                         "traffic": None, "launches": launches, "avg_launch_ms": ms / max(1, launches),
-                        "flops_per_launch": flops / max(1, launches)}}
-    log(f"batched: {K} steps in {dt:.2f} s (sequential {dseq:.1f} s)")
+                        "flops_per_launch": flops / max(1, launches)}})
     if not args.no_cpu:
         from threadpoolctl import threadpool_limits
 
@@ -479,6 +484,11 @@ def main():
                     help="add to the gradient object both ladder objectives at co-state chi_max 64, 128, 256 "
                          "(about 5 minutes)")
     ap.add_argument("--headline-only", action="store_true", help="only the settle and the timed chi=256 steps")
+    ap.add_argument("--workload", choices=("chain30", "chains64", "ladder_grad"), default="chain30",
+                    help="chain30: the line above (default); chains64: only the batched form's object; "
+                         "ladder_grad: only the adjoint gradients' object")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="chains64: skip the same chains run one after another")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="also run one plain device-to-device copy of MIB MiB (the calibration kernel of "
                          "the FETCH_SIZE / WRITE_SIZE counters)")
@@ -490,6 +500,23 @@ def main():
         sys.exit(2)
     if args.headline_only:
         args.no_configured = args.no_batched = args.no_gradient = args.no_cpu = True
+    if args.workload != "chain30":
+        import torch
+
+        assert torch.cuda.is_available(), "bench.py needs a GPU"
+        if args.workload == "chains64":
+            b = batched_leg(args)
+            line = {"metric": "Trotter steps/s of a 64-chain batch (batched form)", "value": b["steps_per_s"],
+                    "unit": "steps/s", "n_gpus": 1, "higher_is_better": True, "dtype": "f64",
+                    "data": "synthetic (seeded chains, no dataset)", "config": {"workload": b["workload"]}, **b}
+        else:
+            g = gradient_leg(args)
+            line = {"metric": "adjoint gradients/s on the 2x8 ladder (140 derivatives each)",
+                    "value": 1.0 / g["seconds"], "unit": "gradients/s", "n_gpus": 1, "higher_is_better": True,
+                    "dtype": "f64", "data": "synthetic (seeded ladder, no dataset)",
+                    "config": {"workload": g["workload"]}, **g}
+        print(json.dumps(line), flush=True)
+        return
 
     import numpy as np
     import torch
